@@ -1,0 +1,724 @@
+/*
+ * csph_oracle.c -- plain FP64 CPU oracle of one CSPH-TVD time step for the
+ * coupled Saint-Venant (shallow water) + Exner (bed evolution) system of
+ * Khrapov & Khoperskov, "Application of GPUs for self-consistent modelling of
+ * shallow water dynamics and sediment transport", Lobachevskii J. Math. 41(8)
+ * (2020) 1475-1484.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the correctness reference that the
+ * GPU path is checked against.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load it; the product path never does.  It
+ * shares no code, header, table or constant with the HIP library.
+ *
+ * What is fixed by the paper and what is a reading
+ * ------------------------------------------------
+ * The paper prints the PDEs (Exner Eq. 1, slope-corrected bedload Eq. 2, Grass
+ * law Eq. 3, coefficient Eq. 4, Shamov critical velocity Eq. 5, the vector
+ * form Eq. 6), the time-step rule Eq. 7, and the kernel sequence K1..K8 of
+ * Section 3 (forces at t_n, dt, predictor to t_{n+1/2}, forces at t_{n+1/2},
+ * corrector, Euler-stage fluxes by piecewise-linear reconstruction + TVD
+ * limiter + HLL, update).  It does not print the discretisation itself, so
+ * the step below is one concrete reading of that sequence, with each choice
+ * named where it is made (O1..O9).  The layout of the computation is the
+ * simplest one: every stage loops over all cells (or all faces) of the grid,
+ * writes whole-grid arrays, and the next stage reads them.  Faces are computed
+ * once into face arrays and both neighbouring cells read the same value, so
+ * the scheme is exactly conservative up to rounding.
+ *
+ * Parity pins (tests/test_oracle_*.py): lake at rest over uneven bed with
+ * emerged islands, Stoker and Ritter dam breaks against the exact Riemann
+ * solutions, water and sediment volume conservation, balance with open
+ * boundaries and inflow, friction-only decay against its ODE, slope-diffusion
+ * decay of a bed mode against its closed form, a hand-stepped 3-cell grid,
+ * transpose / mirror / y-invariance symmetries, and the first time step.
+ * Parity unpinned: the authors' own CSPH-TVD program (only this reading of it
+ * exists here), the intended exponent of Eq. 4, and Eq. 7 omitting C_J.
+ *
+ * Layout: arrays are row-major [ny][nx], x fastest.  Sides are indexed
+ * W=0, E=1, S=2, N=3.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_BC_WALL 0
+#define ORC_BC_OPEN 1
+
+#define ORC_SED_NONE 0
+#define ORC_SED_GRASS 1
+#define ORC_SED_EQ4 2
+
+typedef struct {
+    int32_t nx, ny;
+    double dx;        /* cell size (uniform, dx = dy); "h" in Eq. 7 */
+    int32_t bc[4];    /* W, E, S, N: 0 = wall (mirror), 1 = open (zero gradient) */
+    double g;         /* gravity */
+    double cfl;       /* Courant number K of Eq. 7 */
+    double eps;       /* desingularisation depth */
+    double h_sed;     /* no bedload at or below this depth */
+    double dt_max, dt_min;
+    double s_rel;     /* s = rho_s / rho of Eq. 4 */
+    double C_J;       /* slope coefficient of Eq. 2 */
+    double C_Sh;      /* Shamov coefficient of Eq. 5 */
+    double A_G, m_exp;/* Grass law coefficient and exponent of Eq. 3 */
+    int32_t sed_law;  /* 0 none, 1 Grass (A_G, m_exp), 2 Eq. 4 coefficient (m = 4) */
+} orc_params;
+
+typedef struct {
+    const double *nM;   /* Manning coefficient per cell            [ny*nx] */
+    const double *d50;  /* median grain size per cell, m           [ny*nx] */
+    const double *psi;  /* bed porosity per cell                   [ny*nx] */
+    const double *qb;   /* q_b^+ - q_b^- per cell, m/s, or NULL    [ny*nx] */
+    int32_t n_inflow;            /* number of inflow cells */
+    const int32_t *inflow_idx;   /* flat cell index of each inflow cell */
+    const double *inflow_w;      /* weight of each inflow cell (sum 1) */
+    double Q_base, Q_peak, t_peak, t_sigma;  /* hydrograph, m^3/s */
+} orc_inputs;
+
+typedef struct {
+    double dt;          /* step actually taken */
+    double vp, vs, D;   /* the three maxima of Eq. 7 at t_n */
+    int32_t binding;    /* 0: h/(2 vp), 1: h/vs, 2: h^2/(2D), 3: dt_max, 4: fixed */
+    double out_w;       /* water volume leaving through the boundary this step */
+    double in_w;        /* water volume added by inflow this step */
+    double out_s;       /* sediment volume (1-psi) b dx^2 leaving this step */
+    double in_s;        /* sediment volume added by q_b this step */
+} orc_step_info;
+
+enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_NONFINITE = -3, ORC_ERR_DT = -4, ORC_ERR_CFL = -6 };
+
+/* ---------------------------------------------------------------------- */
+/* O1  Velocity from momentum.  A cell's velocity is q * w(H), with w the   */
+/* desingularised reciprocal depth of Kurganov & Petrova (2007): 1/H when   */
+/* H >= eps, else sqrt(2) H / sqrt(H^4 + eps^4), which is continuous at     */
+/* H = eps and vanishes at H = 0.                                           */
+/* ---------------------------------------------------------------------- */
+double orc_w(double H, double eps)
+{
+    if (H >= eps) return 1.0 / H;
+    return sqrt(2.0) * H / sqrt(H * H * H * H + eps * eps * eps * eps);
+}
+
+/* minmod limiter (the TVD limiter of the Euler stage, Section 3). */
+double orc_minmod(double a, double b)
+{
+    if (a * b <= 0.0) return 0.0;
+    if (a > 0.0) return a < b ? a : b;
+    return a > b ? a : b;
+}
+
+/* ---------------------------------------------------------------------- */
+/* O2  Zero-slope bedload J0 of one cell, Eqs. 3-5.  Bedload exists only    */
+/* where the depth exceeds h_sed and the speed exceeds the Shamov critical  */
+/* velocity v_k = C_Sh d50^(1/3) H^(1/6) (Eq. 5).  Then J0 = A |v|^m v with */
+/* A = A_G, m = m_exp for the Grass law (Eq. 3), or A from Eq. 4,           */
+/* A = 0.05 nM^3 / ((s-1) sqrt(g H) d50), with m = 4.                       */
+/* ---------------------------------------------------------------------- */
+void orc_j0(const orc_params *p, double H, double u, double v, double nM, double d50,
+            double *jx, double *jy)
+{
+    *jx = 0.0;
+    *jy = 0.0;
+    if (p->sed_law == ORC_SED_NONE) return;
+    if (!(H > p->h_sed)) return;
+    double speed = sqrt(u * u + v * v);
+    double vk = p->C_Sh * cbrt(d50) * pow(H, 1.0 / 6.0);
+    if (!(speed > vk)) return;
+    double A, m;
+    if (p->sed_law == ORC_SED_GRASS) {
+        A = p->A_G;
+        m = p->m_exp;
+    } else {
+        A = 0.05 * nM * nM * nM / ((p->s_rel - 1.0) * sqrt(p->g * H) * d50);
+        m = 4.0;
+    }
+    double f = A * pow(speed, m);
+    *jx = f * u;
+    *jy = f * v;
+}
+
+/* HLL flux of the remap (Euler stage, Section 3).  Side states are the     */
+/* hydrostatic face depth Hs, the Lagrangian velocity (uLn normal, uLt      */
+/* tangential) and the transport velocity un.  Conserved U = (Hs, Hs uLn,   */
+/* Hs uLt), physical flux un * U, Davis wave speeds from un +- sqrt(g Hs).  */
+/* Output f[0..2] = (mass, normal momentum, tangential momentum).           */
+void orc_hll(double g,
+             double HsL, double uLnL, double uLtL, double unL,
+             double HsR, double uLnR, double uLtR, double unR, double f[3])
+{
+    double UL[3] = {HsL, HsL * uLnL, HsL * uLtL};
+    double UR[3] = {HsR, HsR * uLnR, HsR * uLtR};
+    double FL[3], FR[3];
+    for (int k = 0; k < 3; ++k) {
+        FL[k] = unL * UL[k];
+        FR[k] = unR * UR[k];
+    }
+    double cL = sqrt(g * HsL), cR = sqrt(g * HsR);
+    double SL = fmin(unL - cL, unR - cR);
+    double SR = fmax(unL + cL, unR + cR);
+    for (int k = 0; k < 3; ++k) {
+        if (SL >= 0.0) f[k] = FL[k];
+        else if (SR <= 0.0) f[k] = FR[k];
+        else if (SR - SL <= 0.0) f[k] = 0.0;
+        else f[k] = (SR * FL[k] - SL * FR[k] + SL * SR * (UR[k] - UL[k])) / (SR - SL);
+    }
+}
+
+/* Hydrostatic face depths (Audusse et al. 2004) of a face between side     */
+/* states with free surfaces zL, zR and depths HL, HR: the face bed is the  */
+/* higher of the two side beds z - H, and each side depth is its surface    */
+/* above that bed, never negative.                                          */
+static void face_depths(double zL, double HL, double zR, double HR, double *HsL, double *HsR)
+{
+    double bL = zL - HL, bR = zR - HR;
+    double bf = bL > bR ? bL : bR;
+    *HsL = fmax(0.0, zL - bf);
+    *HsR = fmax(0.0, zR - bf);
+}
+
+/* Hydrograph of the inflow cells: Q(t) = Q_base + Q_peak exp(-(t-tp)^2 / (2 s^2)). */
+double orc_hydrograph(const orc_inputs *in, double t)
+{
+    double d = t - in->t_peak;
+    double s = in->t_sigma;
+    double pk = (s > 0.0) ? in->Q_peak * exp(-d * d / (2.0 * s * s)) : 0.0;
+    return in->Q_base + pk;
+}
+
+/* ---------------------------------------------------------------------- */
+/* O4  Lagrangian force per unit area on every cell column for a depth      */
+/* field Hd over bed b: the pressure + bed-slope row of Phi in Eq. 6,       */
+/* -g H grad(H + b), in hydrostatic-face form.  At each face the face bed   */
+/* is max(b_L, b_R); each side depth is Hs = max(0, Hd + b - b_face); the   */
+/* face pressure is P = (g/2) HsL HsR.  On cell i (x direction):            */
+/*   Sx_i = -(P_{i+1/2} - P_{i-1/2})/dx                                     */
+/*          + (g/(2 dx)) [ (HsL_{i+1/2})^2 - (HsR_{i-1/2})^2 ].             */
+/* A boundary face sees a ghost copy of its cell (face bed = the cell's own */
+/* bed), so there Hs = Hd and P = (g/2) Hd^2; it is evaluated through the   */
+/* same expression as an interior face between two equal cells, so a       */
+/* problem that is uniform along y stays exactly uniform.                   */
+/* At rest over any bed (constant Hd + b where wet, dry banks               */
+/* above it) every face has HsL = HsR and S = 0.                            */
+/* ---------------------------------------------------------------------- */
+static void forces(const orc_params *p, const double *Hd, const double *b, double *Sx, double *Sy)
+{
+    const int nx = p->nx, ny = p->ny;
+    const double g = p->g, dx = p->dx;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            size_t c = (size_t)j * nx + i;
+            double HsL, HsR, Pe, Pw, Pn, Ps, HsLe, HsRw, HsLn, HsRs;
+            /* east face: cell is the left side */
+            if (i + 1 < nx) {
+                size_t e = c + 1;
+                double bf = fmax(b[c], b[e]);
+                HsL = fmax(0.0, Hd[c] + b[c] - bf);
+                HsR = fmax(0.0, Hd[e] + b[e] - bf);
+            } else {
+                HsL = HsR = fmax(0.0, Hd[c] + b[c] - b[c]);
+            }
+            Pe = 0.5 * g * HsL * HsR;
+            HsLe = HsL;
+            /* west face: cell is the right side */
+            if (i > 0) {
+                size_t w = c - 1;
+                double bf = fmax(b[w], b[c]);
+                HsL = fmax(0.0, Hd[w] + b[w] - bf);
+                HsR = fmax(0.0, Hd[c] + b[c] - bf);
+            } else {
+                HsL = HsR = fmax(0.0, Hd[c] + b[c] - b[c]);
+            }
+            Pw = 0.5 * g * HsL * HsR;
+            HsRw = HsR;
+            Sx[c] = -(Pe - Pw) / dx + (g / (2.0 * dx)) * (HsLe * HsLe - HsRw * HsRw);
+            /* north face */
+            if (j + 1 < ny) {
+                size_t n = c + nx;
+                double bf = fmax(b[c], b[n]);
+                HsL = fmax(0.0, Hd[c] + b[c] - bf);
+                HsR = fmax(0.0, Hd[n] + b[n] - bf);
+            } else {
+                HsL = HsR = fmax(0.0, Hd[c] + b[c] - b[c]);
+            }
+            Pn = 0.5 * g * HsL * HsR;
+            HsLn = HsL;
+            /* south face */
+            if (j > 0) {
+                size_t s = c - nx;
+                double bf = fmax(b[s], b[c]);
+                HsL = fmax(0.0, Hd[s] + b[s] - bf);
+                HsR = fmax(0.0, Hd[c] + b[c] - bf);
+            } else {
+                HsL = HsR = fmax(0.0, Hd[c] + b[c] - b[c]);
+            }
+            Ps = 0.5 * g * HsL * HsR;
+            HsRs = HsR;
+            Sy[c] = -(Pn - Ps) / dx + (g / (2.0 * dx)) * (HsLn * HsLn - HsRs * HsRs);
+        }
+    }
+}
+
+/* Manning friction rate gamma = g nM^2 |v| / max(H, eps)^(4/3), applied    */
+/* semi-implicitly (the bottom-friction part of f in Eq. 6).                */
+static double friction_rate(const orc_params *p, double nM, double speed, double H)
+{
+    double Hf = H > p->eps ? H : p->eps;
+    return p->g * nM * nM * speed / pow(Hf, 4.0 / 3.0);
+}
+
+/* ---------------------------------------------------------------------- */
+/* O3  Time step of Eq. 7 on the state at t_n:                              */
+/*   tau = K min( h/(2 vp), h/vs, h^2/(2 D) ),                              */
+/*   vp = max|v|, vs = max(|v| + sqrt(g H)), D = max |J0| / (1 - psi),      */
+/* over all cells; a term with a zero denominator is infinite; the result   */
+/* is capped at dt_max.                                                     */
+/* ---------------------------------------------------------------------- */
+int orc_cfl(const orc_params *p, const orc_inputs *in, const double *H, const double *qx,
+            const double *qy, double *dt, double *vp_o, double *vs_o, double *D_o, int32_t *binding)
+{
+    const size_t n = (size_t)p->nx * p->ny;
+    double vp = 0.0, vs = 0.0, D = 0.0;
+    int bad = 0;
+    for (size_t c = 0; c < n; ++c) {
+        double w = orc_w(H[c], p->eps);
+        double u = qx[c] * w, v = qy[c] * w;
+        double sp = sqrt(u * u + v * v);
+        double cs = sqrt(p->g * (H[c] > 0.0 ? H[c] : 0.0));
+        double jx, jy;
+        orc_j0(p, H[c], u, v, in->nM[c], in->d50[c], &jx, &jy);
+        double Dc = sqrt(jx * jx + jy * jy) / (1.0 - in->psi[c]);
+        if (!isfinite(sp) || !isfinite(Dc) || !isfinite(H[c])) bad = 1;
+        if (sp > vp) vp = sp;
+        if (sp + cs > vs) vs = sp + cs;
+        if (Dc > D) D = Dc;
+    }
+    double h = p->dx;
+    double t0 = vp > 0.0 ? h / (2.0 * vp) : INFINITY;
+    double t1 = vs > 0.0 ? h / vs : INFINITY;
+    double t2 = D > 0.0 ? h * h / (2.0 * D) : INFINITY;
+    double m = t0;
+    int which = 0;
+    if (t1 < m) { m = t1; which = 1; }
+    if (t2 < m) { m = t2; which = 2; }
+    double d = p->cfl * m;
+    if (!(d < p->dt_max)) { d = p->dt_max; which = 3; }
+    *dt = d;
+    if (vp_o) *vp_o = vp;
+    if (vs_o) *vs_o = vs;
+    if (D_o) *D_o = D;
+    if (binding) *binding = which;
+    if (bad) return ORC_ERR_NONFINITE;
+    return ORC_OK;
+}
+
+/* Ghost rule: value of a per-cell field at cell (i,j) when (i,j) may sit   */
+/* one cell outside the grid.  A wall mirrors (the normal velocity          */
+/* component flips sign, everything else is copied); an open side copies.   */
+/* `normal_x` / `normal_y` say whether the field is the x / y component of  */
+/* a velocity.                                                              */
+static double ghost(const orc_params *p, const double *a, int i, int j, int normal_x, int normal_y)
+{
+    const int nx = p->nx, ny = p->ny;
+    int ci = i, cj = j;
+    double sgn = 1.0;
+    if (i < 0) { ci = 0; if (p->bc[0] == ORC_BC_WALL && normal_x) sgn = -1.0; }
+    if (i >= nx) { ci = nx - 1; if (p->bc[1] == ORC_BC_WALL && normal_x) sgn = -1.0; }
+    if (j < 0) { cj = 0; if (p->bc[2] == ORC_BC_WALL && normal_y) sgn = -1.0; }
+    if (j >= ny) { cj = ny - 1; if (p->bc[3] == ORC_BC_WALL && normal_y) sgn = -1.0; }
+    return sgn * a[(size_t)cj * nx + ci];
+}
+
+/* Limited slope of field a at cell (i,j) along x (dir 0) or y (dir 1). */
+static double slope(const orc_params *p, const double *a, int i, int j, int dir, int nxf, int nyf)
+{
+    double am, a0, ap;
+    a0 = a[(size_t)j * p->nx + i];
+    if (dir == 0) {
+        am = ghost(p, a, i - 1, j, nxf, nyf);
+        ap = ghost(p, a, i + 1, j, nxf, nyf);
+    } else {
+        am = ghost(p, a, i, j - 1, nxf, nyf);
+        ap = ghost(p, a, i, j + 1, nxf, nyf);
+    }
+    return orc_minmod(a0 - am, ap - a0);
+}
+
+/* Reconstructed face value of cell (i,j) at its face on side `side` (+1 the */
+/* east/north face, -1 the west/south face) along `dir`.                     */
+static double face_value(const orc_params *p, const double *a, int i, int j, int dir, int side,
+                         int nxf, int nyf)
+{
+    return a[(size_t)j * p->nx + i] + 0.5 * side * slope(p, a, i, j, dir, nxf, nyf);
+}
+
+/* ---------------------------------------------------------------------- */
+/* One CSPH-TVD step.  Arrays H, qx, qy, b are updated in place from t_n to */
+/* t_{n+1}.  dt_fixed <= 0 selects the Eq. 7 step; dt_fixed > 0 takes that  */
+/* step and fails with ORC_ERR_CFL if it exceeds the Eq. 7 step.            */
+/* ---------------------------------------------------------------------- */
+int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, double *qy,
+             double *b, double t, double dt_fixed, orc_step_info *info)
+{
+    const int nx = p->nx, ny = p->ny;
+    if (nx < 1 || ny < 1 || !(p->dx > 0.0)) return ORC_ERR_ARG;
+    const size_t n = (size_t)nx * ny;
+    const double g = p->g, dx = p->dx, eps = p->eps;
+
+    memset(info, 0, sizeof(*info));
+
+    /* O3 (K3): time step from the state at t_n. */
+    double dt, vp, vs, D;
+    int32_t binding;
+    int rc = orc_cfl(p, in, H, qx, qy, &dt, &vp, &vs, &D, &binding);
+    info->vp = vp;
+    info->vs = vs;
+    info->D = D;
+    if (rc != ORC_OK) return rc;
+    if (dt_fixed > 0.0) {
+        if (dt_fixed > dt) return ORC_ERR_CFL;
+        dt = dt_fixed;
+        binding = 4;
+    }
+    if (dt < p->dt_min) return ORC_ERR_DT;
+    info->dt = dt;
+    info->binding = binding;
+
+    double *u = malloc(n * sizeof(double)), *v = malloc(n * sizeof(double));
+    double *Sx = malloc(n * sizeof(double)), *Sy = malloc(n * sizeof(double));
+    double *up = malloc(n * sizeof(double)), *vpv = malloc(n * sizeof(double));
+    double *Hh = malloc(n * sizeof(double));
+    double *QLx = malloc(n * sizeof(double)), *QLy = malloc(n * sizeof(double));
+    double *uLx = malloc(n * sizeof(double)), *uLy = malloc(n * sizeof(double));
+    double *utx = malloc(n * sizeof(double)), *uty = malloc(n * sizeof(double));
+    double *zeta = malloc(n * sizeof(double));
+    double *J0x = malloc(n * sizeof(double)), *J0y = malloc(n * sizeof(double));
+    double *theta = malloc(n * sizeof(double));
+    /* x faces: (nx+1) per row, face k sits west of cell k; y faces likewise. */
+    const size_t nfx = (size_t)(nx + 1) * ny, nfy = (size_t)nx * (ny + 1);
+    double *FH = malloc(nfx * sizeof(double)), *Fqx = malloc(nfx * sizeof(double));
+    double *Fqy = malloc(nfx * sizeof(double)), *FJ = malloc(nfx * sizeof(double));
+    double *GH = malloc(nfy * sizeof(double)), *Gqx = malloc(nfy * sizeof(double));
+    double *Gqy = malloc(nfy * sizeof(double)), *GJ = malloc(nfy * sizeof(double));
+
+    /* O1 + O2 (K2): velocities and bedload at t_n. */
+#pragma omp parallel for schedule(static)
+    for (size_t c = 0; c < n; ++c) {
+        double w = orc_w(H[c], eps);
+        u[c] = qx[c] * w;
+        v[c] = qy[c] * w;
+        orc_j0(p, H[c], u[c], v[c], in->nM[c], in->d50[c], &J0x[c], &J0y[c]);
+    }
+
+    /* O4 + O5 (K2, K4): forces at t_n; predictor momentum and velocity;    */
+    /* half-step depth from the deformation of each column's area under the */
+    /* face-mean velocities at t_n over dt/2.                               */
+    forces(p, H, b, Sx, Sy);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            size_t c = (size_t)j * nx + i;
+            double sp = sqrt(u[c] * u[c] + v[c] * v[c]);
+            double gam = friction_rate(p, in->nM[c], sp, H[c]);
+            double w = orc_w(H[c], eps);
+            double qpx = (qx[c] + 0.5 * dt * Sx[c]) / (1.0 + 0.5 * dt * gam);
+            double qpy = (qy[c] + 0.5 * dt * Sy[c]) / (1.0 + 0.5 * dt * gam);
+            up[c] = qpx * w;
+            vpv[c] = qpy * w;
+            /* face-mean velocities: interior mean; wall 0; open = the cell's own */
+            double ue, uw, vn, vs_;
+            if (i + 1 < nx) ue = 0.5 * (u[c] + u[c + 1]);
+            else ue = (p->bc[1] == ORC_BC_WALL) ? 0.0 : u[c];
+            if (i > 0) uw = 0.5 * (u[c - 1] + u[c]);
+            else uw = (p->bc[0] == ORC_BC_WALL) ? 0.0 : u[c];
+            if (j + 1 < ny) vn = 0.5 * (v[c] + v[c + nx]);
+            else vn = (p->bc[3] == ORC_BC_WALL) ? 0.0 : v[c];
+            if (j > 0) vs_ = 0.5 * (v[c - nx] + v[c]);
+            else vs_ = (p->bc[2] == ORC_BC_WALL) ? 0.0 : v[c];
+            double Jx = 1.0 + (dt / (2.0 * dx)) * (ue - uw);
+            double Jy = 1.0 + (dt / (2.0 * dx)) * (vn - vs_);
+            Hh[c] = H[c] / (Jx * Jy);
+        }
+    }
+
+    /* O6 (K5, K6): forces at t_{n+1/2} on the half-step depths (bed b^n),  */
+    /* corrector momentum Q^L, Lagrangian velocity u^L and the transport    */
+    /* velocity u~ = (v^n + u^L)/2 that carries the remap.                  */
+    forces(p, Hh, b, Sx, Sy);
+#pragma omp parallel for schedule(static)
+    for (size_t c = 0; c < n; ++c) {
+        double spp = sqrt(up[c] * up[c] + vpv[c] * vpv[c]);
+        double gam = friction_rate(p, in->nM[c], spp, Hh[c]);
+        QLx[c] = (qx[c] + dt * Sx[c]) / (1.0 + dt * gam);
+        QLy[c] = (qy[c] + dt * Sy[c]) / (1.0 + dt * gam);
+        double w = orc_w(H[c], eps);
+        uLx[c] = QLx[c] * w;
+        uLy[c] = QLy[c] * w;
+        utx[c] = 0.5 * (u[c] + uLx[c]);
+        uty[c] = 0.5 * (v[c] + uLy[c]);
+        zeta[c] = H[c] + b[c];
+    }
+
+    /* O7 (K7): Euler-stage raw fluxes on every face.  Per direction, the   */
+    /* free surface zeta, the depth H, the normal transport velocity and    */
+    /* both Lagrangian velocity components are reconstructed piecewise      */
+    /* linearly with minmod slopes; face depths are hydrostatic; the water  */
+    /* flux is HLL; the bedload flux is the flux-split donor cell of J0     */
+    /* plus the slope term of Eq. 2, -C_J |J0| grad b, with |J0| averaged.  */
+    const double CJ = p->C_J;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+        for (int k = 0; k <= nx; ++k) {
+            size_t f = (size_t)j * (nx + 1) + k;
+            int iL = k - 1, iR = k;  /* cells west / east of face k */
+            double fl[3] = {0.0, 0.0, 0.0}, fj = 0.0;
+            if (iL >= 0 && iR < nx) {
+                double zL = face_value(p, zeta, iL, j, 0, +1, 0, 0);
+                double hL = face_value(p, H, iL, j, 0, +1, 0, 0);
+                double tL = face_value(p, utx, iL, j, 0, +1, 1, 0);
+                double nL = face_value(p, uLx, iL, j, 0, +1, 1, 0);
+                double sL = face_value(p, uLy, iL, j, 0, +1, 0, 1);
+                double zR = face_value(p, zeta, iR, j, 0, -1, 0, 0);
+                double hR = face_value(p, H, iR, j, 0, -1, 0, 0);
+                double tR = face_value(p, utx, iR, j, 0, -1, 1, 0);
+                double nR = face_value(p, uLx, iR, j, 0, -1, 1, 0);
+                double sR = face_value(p, uLy, iR, j, 0, -1, 0, 1);
+                double HsL, HsR;
+                face_depths(zL, hL, zR, hR, &HsL, &HsR);
+                orc_hll(g, HsL, nL, sL, tL, HsR, nR, sR, tR, fl);
+                size_t cL = (size_t)j * nx + iL, cR = cL + 1;
+                double mag = 0.5 * (sqrt(J0x[cL] * J0x[cL] + J0y[cL] * J0y[cL]) +
+                                    sqrt(J0x[cR] * J0x[cR] + J0y[cR] * J0y[cR]));
+                fj = fmax(J0x[cL], 0.0) + fmin(J0x[cR], 0.0) - CJ * mag * (b[cR] - b[cL]) / dx;
+            } else if (iR == nx) {  /* east boundary, interior cell on the left */
+                int ic = nx - 1;
+                size_t c = (size_t)j * nx + ic;
+                double zL = face_value(p, zeta, ic, j, 0, +1, 0, 0);
+                double hL = face_value(p, H, ic, j, 0, +1, 0, 0);
+                double tL = face_value(p, utx, ic, j, 0, +1, 1, 0);
+                double nL = face_value(p, uLx, ic, j, 0, +1, 1, 0);
+                double sL = face_value(p, uLy, ic, j, 0, +1, 0, 1);
+                double HsL, HsR;
+                face_depths(zL, hL, zL, hL, &HsL, &HsR);
+                if (p->bc[1] == ORC_BC_WALL) {
+                    double cL = sqrt(g * HsL);
+                    fl[1] = HsL * nL * (tL + fabs(tL) + cL);
+                } else {
+                    fl[0] = tL * HsL;
+                    fl[1] = tL * HsL * nL;
+                    fl[2] = tL * HsL * sL;
+                    fj = fmax(J0x[c], 0.0);
+                }
+            } else {  /* west boundary, interior cell on the right */
+                int ic = 0;
+                size_t c = (size_t)j * nx + ic;
+                double zR = face_value(p, zeta, ic, j, 0, -1, 0, 0);
+                double hR = face_value(p, H, ic, j, 0, -1, 0, 0);
+                double tR = face_value(p, utx, ic, j, 0, -1, 1, 0);
+                double nR = face_value(p, uLx, ic, j, 0, -1, 1, 0);
+                double sR = face_value(p, uLy, ic, j, 0, -1, 0, 1);
+                double HsL, HsR;
+                face_depths(zR, hR, zR, hR, &HsL, &HsR);
+                if (p->bc[0] == ORC_BC_WALL) {
+                    double cR = sqrt(g * HsR);
+                    fl[1] = HsR * nR * (tR - fabs(tR) - cR);
+                } else {
+                    fl[0] = tR * HsR;
+                    fl[1] = tR * HsR * nR;
+                    fl[2] = tR * HsR * sR;
+                    fj = fmin(J0x[c], 0.0);
+                }
+            }
+            FH[f] = fl[0];
+            Fqx[f] = fl[1];  /* normal = x */
+            Fqy[f] = fl[2];  /* tangential = y */
+            FJ[f] = fj;
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k <= ny; ++k) {
+        for (int i = 0; i < nx; ++i) {
+            size_t f = (size_t)k * nx + i;
+            int jL = k - 1, jR = k;  /* cells south / north of face k */
+            double fl[3] = {0.0, 0.0, 0.0}, fj = 0.0;
+            if (jL >= 0 && jR < ny) {
+                double zL = face_value(p, zeta, i, jL, 1, +1, 0, 0);
+                double hL = face_value(p, H, i, jL, 1, +1, 0, 0);
+                double tL = face_value(p, uty, i, jL, 1, +1, 0, 1);
+                double nL = face_value(p, uLy, i, jL, 1, +1, 0, 1);
+                double sL = face_value(p, uLx, i, jL, 1, +1, 1, 0);
+                double zR = face_value(p, zeta, i, jR, 1, -1, 0, 0);
+                double hR = face_value(p, H, i, jR, 1, -1, 0, 0);
+                double tR = face_value(p, uty, i, jR, 1, -1, 0, 1);
+                double nR = face_value(p, uLy, i, jR, 1, -1, 0, 1);
+                double sR = face_value(p, uLx, i, jR, 1, -1, 1, 0);
+                double HsL, HsR;
+                face_depths(zL, hL, zR, hR, &HsL, &HsR);
+                orc_hll(g, HsL, nL, sL, tL, HsR, nR, sR, tR, fl);
+                size_t cL = (size_t)jL * nx + i, cR = cL + nx;
+                double mag = 0.5 * (sqrt(J0x[cL] * J0x[cL] + J0y[cL] * J0y[cL]) +
+                                    sqrt(J0x[cR] * J0x[cR] + J0y[cR] * J0y[cR]));
+                fj = fmax(J0y[cL], 0.0) + fmin(J0y[cR], 0.0) - CJ * mag * (b[cR] - b[cL]) / dx;
+            } else if (jR == ny) {  /* north boundary */
+                int jc = ny - 1;
+                size_t c = (size_t)jc * nx + i;
+                double zL = face_value(p, zeta, i, jc, 1, +1, 0, 0);
+                double hL = face_value(p, H, i, jc, 1, +1, 0, 0);
+                double tL = face_value(p, uty, i, jc, 1, +1, 0, 1);
+                double nL = face_value(p, uLy, i, jc, 1, +1, 0, 1);
+                double sL = face_value(p, uLx, i, jc, 1, +1, 1, 0);
+                double HsL, HsR;
+                face_depths(zL, hL, zL, hL, &HsL, &HsR);
+                if (p->bc[3] == ORC_BC_WALL) {
+                    double cL = sqrt(g * HsL);
+                    fl[1] = HsL * nL * (tL + fabs(tL) + cL);
+                } else {
+                    fl[0] = tL * HsL;
+                    fl[1] = tL * HsL * nL;
+                    fl[2] = tL * HsL * sL;
+                    fj = fmax(J0y[c], 0.0);
+                }
+            } else {  /* south boundary */
+                int jc = 0;
+                size_t c = (size_t)jc * nx + i;
+                double zR = face_value(p, zeta, i, jc, 1, -1, 0, 0);
+                double hR = face_value(p, H, i, jc, 1, -1, 0, 0);
+                double tR = face_value(p, uty, i, jc, 1, -1, 0, 1);
+                double nR = face_value(p, uLy, i, jc, 1, -1, 0, 1);
+                double sR = face_value(p, uLx, i, jc, 1, -1, 1, 0);
+                double HsL, HsR;
+                face_depths(zR, hR, zR, hR, &HsL, &HsR);
+                if (p->bc[2] == ORC_BC_WALL) {
+                    double cR = sqrt(g * HsR);
+                    fl[1] = HsR * nR * (tR - fabs(tR) - cR);
+                } else {
+                    fl[0] = tR * HsR;
+                    fl[1] = tR * HsR * nR;
+                    fl[2] = tR * HsR * sR;
+                    fj = fmin(J0y[c], 0.0);
+                }
+            }
+            GH[f] = fl[0];
+            Gqy[f] = fl[1];  /* normal = y */
+            Gqx[f] = fl[2];  /* tangential = x */
+            GJ[f] = fj;
+        }
+    }
+
+    /* Positivity: the draining limiter.  theta_i scales every flux that    */
+    /* drains cell i so that its outflow over the step cannot exceed its    */
+    /* water H_i dx^2.                                                      */
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            size_t c = (size_t)j * nx + i;
+            double fe = FH[(size_t)j * (nx + 1) + i + 1], fw = FH[(size_t)j * (nx + 1) + i];
+            double gn = GH[(size_t)(j + 1) * nx + i], gs = GH[(size_t)j * nx + i];
+            double out = fmax(0.0, fe) + fmax(0.0, -fw) + fmax(0.0, gn) + fmax(0.0, -gs);
+            theta[c] = out > 0.0 ? fmin(1.0, H[c] * dx / (dt * out)) : 1.0;
+        }
+    }
+    /* Each face's water fluxes take the theta of their donor cell (the     */
+    /* cell the mass leaves); a ghost donor has theta = 1.                  */
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+        for (int k = 0; k <= nx; ++k) {
+            size_t f = (size_t)j * (nx + 1) + k;
+            double th = 1.0;
+            if (FH[f] > 0.0 && k - 1 >= 0) th = theta[(size_t)j * nx + k - 1];
+            if (FH[f] < 0.0 && k < nx) th = theta[(size_t)j * nx + k];
+            FH[f] *= th;
+            Fqx[f] *= th;
+            Fqy[f] *= th;
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k <= ny; ++k) {
+        for (int i = 0; i < nx; ++i) {
+            size_t f = (size_t)k * nx + i;
+            double th = 1.0;
+            if (GH[f] > 0.0 && k - 1 >= 0) th = theta[(size_t)(k - 1) * nx + i];
+            if (GH[f] < 0.0 && k < ny) th = theta[(size_t)k * nx + i];
+            GH[f] *= th;
+            Gqx[f] *= th;
+            Gqy[f] *= th;
+        }
+    }
+
+    /* O8 (K8): conservative update from the face fluxes, the inflow source */
+    /* at t_n + dt/2 (mass only) and the Exner update (Eq. 1) with the      */
+    /* cell's porosity.  A tiny negative depth left by rounding is set to   */
+    /* zero; a thin film's momentum is re-desingularised, q <- H w(H) q.    */
+    double Qmid = orc_hydrograph(in, t + 0.5 * dt);
+    double *src = calloc(n, sizeof(double));
+    for (int k = 0; k < in->n_inflow; ++k)
+        src[in->inflow_idx[k]] += Qmid * in->inflow_w[k] / (dx * dx);
+    int nonfinite = 0;
+#pragma omp parallel for schedule(static) reduction(| : nonfinite)
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            size_t c = (size_t)j * nx + i;
+            size_t fw = (size_t)j * (nx + 1) + i, fe = fw + 1;
+            size_t gs = (size_t)j * nx + i, gn = gs + nx;
+            double r = dt / dx;
+            double Hn = H[c] - r * ((FH[fe] - FH[fw]) + (GH[gn] - GH[gs])) + dt * src[c];
+            double qxn = QLx[c] - r * ((Fqx[fe] - Fqx[fw]) + (Gqx[gn] - Gqx[gs]));
+            double qyn = QLy[c] - r * ((Fqy[fe] - Fqy[fw]) + (Gqy[gn] - Gqy[gs]));
+            double om = 1.0 - in->psi[c];
+            double bn = b[c] - dt / (om * dx) * ((FJ[fe] - FJ[fw]) + (GJ[gn] - GJ[gs]));
+            if (in->qb) bn += dt * in->qb[c] / om;
+            if (Hn < 0.0) Hn = 0.0;
+            if (Hn < eps) {
+                double s = Hn * orc_w(Hn, eps);
+                qxn *= s;
+                qyn *= s;
+            }
+            if (!isfinite(Hn) || !isfinite(qxn) || !isfinite(qyn) || !isfinite(bn)) nonfinite = 1;
+            H[c] = Hn;
+            qx[c] = qxn;
+            qy[c] = qyn;
+            b[c] = bn;
+        }
+    }
+
+    /* O9: boundary outflow and source volumes of this step. */
+    double ow = 0.0, os = 0.0;
+    for (int j = 0; j < ny; ++j) {
+        ow += -FH[(size_t)j * (nx + 1)] + FH[(size_t)j * (nx + 1) + nx];
+        os += -FJ[(size_t)j * (nx + 1)] + FJ[(size_t)j * (nx + 1) + nx];
+    }
+    for (int i = 0; i < nx; ++i) {
+        ow += -GH[i] + GH[(size_t)ny * nx + i];
+        os += -GJ[i] + GJ[(size_t)ny * nx + i];
+    }
+    info->out_w = dt * dx * ow;
+    info->out_s = dt * dx * os;
+    info->in_w = in->n_inflow > 0 ? dt * Qmid : 0.0;
+    double qbs = 0.0;
+    if (in->qb)
+        for (size_t c = 0; c < n; ++c) qbs += in->qb[c];
+    info->in_s = dt * qbs * dx * dx;
+
+    free(u); free(v); free(Sx); free(Sy); free(up); free(vpv); free(Hh);
+    free(QLx); free(QLy); free(uLx); free(uLy); free(utx); free(uty); free(zeta);
+    free(J0x); free(J0y); free(theta);
+    free(FH); free(Fqx); free(Fqy); free(FJ); free(GH); free(Gqx); free(Gqy); free(GJ);
+    free(src);
+    return nonfinite ? ORC_ERR_NONFINITE : ORC_OK;
+}
+
+/* O9: water volume sum H dx^2 and sediment volume sum (1 - psi) b dx^2,    */
+/* summed in cell order.                                                    */
+void orc_volumes(const orc_params *p, const orc_inputs *in, const double *H, const double *b,
+                 double *Vw, double *Vs)
+{
+    const size_t n = (size_t)p->nx * p->ny;
+    double sw = 0.0, ss = 0.0;
+    for (size_t c = 0; c < n; ++c) {
+        sw += H[c];
+        ss += (1.0 - in->psi[c]) * b[c];
+    }
+    *Vw = sw * p->dx * p->dx;
+    *Vs = ss * p->dx * p->dx;
+}

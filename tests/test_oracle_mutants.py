@@ -1,0 +1,78 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each mutant below plants one typical error (a dropped term, a flipped sign, a
+wrong neighbour, an x/y mix-up, a wrong donor) into a temporary copy of the
+oracle's C source, compiles it on the CPU, and runs the pin suite
+(test_oracle_pins.py) against it in a subprocess.  Every mutant must make at
+least one pin fail; the unmodified source must pass.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "csph_oracle.c")
+
+MUTANTS = {
+    "w_drops_sqrt2": ("return sqrt(2.0) * H / sqrt(", "return H / sqrt("),
+    "minmod_is_maxmod": ("if (a > 0.0) return a < b ? a : b;", "if (a > 0.0) return a > b ? a : b;"),
+    "hll_diffusion_sign": ("+ SL * SR * (UR[k] - UL[k])", "- SL * SR * (UR[k] - UL[k])"),
+    "hll_davis_speed": ("fmin(unL - cL, unR - cR)", "fmin(unL - cL, unR + cR)"),
+    "pressure_sign_x": ("Sx[c] = -(Pe - Pw) / dx", "Sx[c] = (Pe - Pw) / dx"),
+    "bed_slope_term_dropped_x": ("Sx[c] = -(Pe - Pw) / dx + (g / (2.0 * dx)) * (HsLe * HsLe - HsRw * HsRw);",
+                                 "Sx[c] = -(Pe - Pw) / dx;"),
+    "force_y_uses_x_terms": ("(g / (2.0 * dx)) * (HsLn * HsLn - HsRs * HsRs)",
+                             "(g / (2.0 * dx)) * (HsLe * HsLe - HsRw * HsRw)"),
+    "force_y_wrong_neighbour": ("size_t n = c + nx;", "size_t n = c + 1;"),
+    "manning_exponent": ("pow(Hf, 4.0 / 3.0)", "pow(Hf, 3.0 / 4.0)"),
+    "predictor_full_step": ("(qx[c] + 0.5 * dt * Sx[c])", "(qx[c] + dt * Sx[c])"),
+    "half_depth_multiplies": ("Hh[c] = H[c] / (Jx * Jy);", "Hh[c] = H[c] * (Jx * Jy);"),
+    "transport_velocity_drops_vn": ("utx[c] = 0.5 * (u[c] + uLx[c]);", "utx[c] = uLx[c];"),
+    "y_face_transposed_operand": ("double tL = face_value(p, uty, i, jL, 1, +1, 0, 1);",
+                                  "double tL = face_value(p, utx, i, jL, 1, +1, 1, 0);"),
+    "wall_flux_sign_east": ("fl[1] = HsL * nL * (tL + fabs(tL) + cL);",
+                            "fl[1] = HsL * nL * (tL - fabs(tL) + cL);"),
+    "open_boundary_blocks_mass": ("fl[0] = tL * HsL;\n                    fl[1] = tL * HsL * nL;\n                    fl[2] = tL * HsL * sL;\n                    fj = fmax(J0x[c], 0.0);",
+                                  "fl[1] = tL * HsL * nL;\n                    fl[2] = tL * HsL * sL;\n                    fj = fmax(J0x[c], 0.0);"),
+    "theta_wrong_donor": ("if (FH[f] > 0.0 && k - 1 >= 0) th = theta[(size_t)j * nx + k - 1];",
+                          "if (FH[f] > 0.0 && k < nx) th = theta[(size_t)j * nx + k];"),
+    "inflow_source_dropped": ("+ dt * src[c];", ";"),
+    "exner_drops_porosity": ("double bn = b[c] - dt / (om * dx) *", "double bn = b[c] - dt / dx *"),
+    "bed_slope_diffusion_sign": ("fj = fmax(J0x[cL], 0.0) + fmin(J0x[cR], 0.0) - CJ * mag",
+                                 "fj = fmax(J0x[cL], 0.0) + fmin(J0x[cR], 0.0) + CJ * mag"),
+    "bedload_downwind": ("fj = fmax(J0x[cL], 0.0) + fmin(J0x[cR], 0.0)",
+                         "fj = fmax(J0x[cR], 0.0) + fmin(J0x[cL], 0.0)"),
+    "eq4_drops_s_minus_one": ("((p->s_rel - 1.0) * sqrt(p->g * H) * d50)", "(p->s_rel * sqrt(p->g * H) * d50)"),
+    "eq7_vp_term": ("h / (2.0 * vp)", "h / vp"),
+    "eq7_D_term": ("h * h / (2.0 * D)", "h * h / D"),
+    "shamov_exponent": ("pow(H, 1.0 / 6.0)", "pow(H, 1.0 / 3.0)"),
+}
+
+
+def _run_pins(lib):
+    env = dict(os.environ, CSPH_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return r.returncode, r.stdout[-2000:]
+
+
+@pytest.mark.slow
+def test_every_mutant_is_caught(oracle_mod):
+    src = open(SRC).read()
+    with tempfile.TemporaryDirectory() as d:
+        jobs = {}
+        for name, (old, new) in MUTANTS.items():
+            assert src.count(old) >= 1, f"mutant {name}: pattern not found"
+            msrc = os.path.join(d, f"{name}.c")
+            with open(msrc, "w") as f:
+                f.write(src.replace(old, new, 1))
+            jobs[name] = oracle_mod.compile_source(msrc, os.path.join(d, f"{name}.so"))
+        with ThreadPoolExecutor(max_workers=4) as ex:
+            results = dict(zip(jobs, ex.map(_run_pins, jobs.values())))
+    survivors = [n for n, (rc, _) in results.items() if rc == 0]
+    assert not survivors, f"mutants not caught by any pin: {survivors}"
