@@ -1,0 +1,171 @@
+/*
+ * csph.h -- C ABI of the MI355X (gfx950) CSPH-TVD solver for the coupled
+ * Saint-Venant shallow-water and Exner bed-evolution equations of Khrapov &
+ * Khoperskov, "Application of GPUs for self-consistent modelling of shallow
+ * water dynamics and sediment transport", Lobachevskii J. Math. 41(8) (2020).
+ *
+ * The library mirrors the paper's Section 3 software layout: the caller is the
+ * control block (Main: loads the bed, soil and friction fields and the initial
+ * state), the library is the computing block (Solver: the step kernels on the
+ * GPU), and field/sum readback replaces the Save/Screen blocks, so the host
+ * and the device exchange data only when the caller asks.
+ *
+ * Conventions (every function):
+ *  - Return value: 0 (SW_OK) or a negative SW_ERR_* code; sw_last_error(ctx)
+ *    gives a text for the last failure on that context.  No C++ exception
+ *    crosses this boundary.
+ *  - Fields are row-major [ny][nx] float32 arrays, x fastest, SI units
+ *    (depth h in m, unit discharges hu, hv in m^2/s, bed elevation b in m).
+ *  - ptr_kind SW_PTR_HOST: the pointer is host memory, copied synchronously.
+ *    SW_PTR_DEVICE: the pointer is device memory on the context's GPU (for
+ *    instance a torch tensor's data_ptr()); the copy is ordered on the
+ *    context's stream.  The caller keeps ownership of its buffers; the library
+ *    owns every device allocation it makes and frees them in sw_destroy.
+ *  - Work is ordered on the context's HIP stream (the stream passed to
+ *    sw_create, or one the library creates).  sw_get_fields and sw_get_sums
+ *    synchronise that stream.
+ *  - A context is used by one host thread at a time.
+ *  - Sides are indexed W=0 (x = 0), E=1 (x = max), S=2 (y = 0), N=3 (y = max).
+ */
+#ifndef CSPH_H
+#define CSPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SW_OK 0
+#define SW_ERR_ARG (-1)          /* bad argument (size, pointer, range) */
+#define SW_ERR_HIP (-2)          /* a HIP runtime call failed */
+#define SW_ERR_NONFINITE (-3)    /* a NaN/Inf appeared in the state */
+#define SW_ERR_DT_UNDERFLOW (-4) /* the Eq. 7 step fell below dt_min */
+#define SW_ERR_STATE (-5)        /* call out of order (advance before set_state, ...) */
+#define SW_ERR_CFL (-6)          /* a fixed dt exceeds the Eq. 7 step */
+
+#define SW_BC_WALL 0 /* reflective wall: ghost cell mirrors the normal velocity */
+#define SW_BC_OPEN 1 /* zero-gradient: ghost cell copies the boundary cell */
+
+#define SW_SED_NONE 0  /* no bed evolution */
+#define SW_SED_GRASS 1 /* Grass law J0 = A_G |v|^m_exp v (Eq. 3) */
+#define SW_SED_EQ4 2   /* J0 = A |v|^4 v with A = 0.05 nM^3 / ((s-1) sqrt(g h) d50) (Eqs. 3-4) */
+
+#define SW_PTR_HOST 0
+#define SW_PTR_DEVICE 1
+
+/* sw_params.flags */
+#define SW_FLAG_HGS 1u        /* skip dry tiles (the hierarchical grid system, Section 3) */
+#define SW_FLAG_UNFUSED 2u    /* run the unfused kernel sequence (faces, then update) */
+#define SW_FLAG_NO_GRAPH 4u   /* launch kernels one by one instead of replaying a HIP graph */
+
+typedef struct sw_ctx sw_ctx;
+
+/* Uniform grid: nx * ny square cells of side dx (the cell size h of Eq. 7). */
+typedef struct {
+    int32_t nx, ny;
+    double dx;
+    int32_t bc[4]; /* SW_BC_* per side W, E, S, N */
+} sw_grid;
+
+/* Model constants; sw_default_params fills the defaults named here. */
+typedef struct {
+    double g;       /* gravity, 9.81 m/s^2 */
+    double cfl;     /* Courant number K of Eq. 7, 0.3 */
+    double eps_dry; /* desingularisation depth of the velocity, 1e-5 m */
+    double h_sed;   /* no bedload at or below this depth, 1e-2 m */
+    double dt_max;  /* cap on the Eq. 7 step, 1 s */
+    double dt_min;  /* smaller Eq. 7 steps are an error, 1e-9 s */
+    double s_rel;   /* s = rho_s / rho of Eq. 4, 2.65 */
+    double C_J;     /* bed-slope coefficient of Eq. 2, 2.0 */
+    double C_Sh;    /* Shamov coefficient of Eq. 5, 5.0 */
+    double A_G;     /* Grass coefficient of Eq. 3, 1e-3 */
+    double m_exp;   /* Grass exponent of Eq. 3, 2 */
+    int32_t sed_law;/* SW_SED_*, default SW_SED_EQ4 */
+    uint32_t flags; /* SW_FLAG_*, default SW_FLAG_HGS */
+} sw_params;
+
+/* Global diagnostics, all accumulated in FP64 on the device. */
+typedef struct {
+    double t;                  /* model time */
+    double last_dt;            /* the last step taken */
+    double water_volume;       /* sum h dx^2 */
+    double sediment_volume;    /* sum (1 - psi) b dx^2 (the quantity Eq. 1 conserves) */
+    double water_boundary_out; /* accumulated outward boundary water volume */
+    double water_source_in;    /* accumulated inflow volume */
+    double sed_boundary_out;   /* accumulated outward boundary sediment volume */
+    double sed_source_in;      /* accumulated (q_b^+ - q_b^-) dx^2 dt */
+    double vp, vs, D;          /* Eq. 7 maxima of the current state */
+    int64_t step;              /* step counter */
+    int64_t wet_cells;         /* cells with h > 0 */
+    int64_t active_tiles;      /* tiles the next step will not skip */
+    int32_t binding_term;      /* Eq. 7 term that set last_dt: 0 h/(2vp), 1 h/vs, 2 h^2/(2D), 3 dt_max, 4 fixed */
+    int32_t error;             /* sticky device error (SW_ERR_*), 0 if none */
+} sw_sums;
+
+/* Fill *p with the defaults listed in sw_params. */
+void sw_default_params(sw_params *p);
+
+/* Create a solver for `grid`.  hip_stream: a hipStream_t to order all work on
+ * (for instance torch.cuda.current_stream().cuda_stream), or NULL to let the
+ * library create its own.  The state is all zero until set. */
+int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw_ctx **out);
+int sw_destroy(sw_ctx *ctx);
+
+/* Bed elevation b(x, y) (the digital elevation model of Main, Section 3). */
+int sw_set_bed(sw_ctx *ctx, const float *b, int ptr_kind);
+
+/* Soil: Manning coefficient nM, median grain size d50 (m) and porosity psi
+ * (Eqs. 1, 4, 5, friction in f of Eq. 6).  Each is a per-cell array, or NULL
+ * to use the scalar that follows it.  Porosity must lie in [0, 1). */
+int sw_set_soil(sw_ctx *ctx, const float *manning, float manning_scalar, const float *d50,
+                float d50_scalar, const float *psi, float psi_scalar, int ptr_kind);
+
+/* Initial water depth and unit discharges.  Negative depth is SW_ERR_ARG;
+ * the discharge of a cell with zero depth is set to zero.  Resets the step
+ * counter, the accumulated balances and any sticky error. */
+int sw_set_state(sw_ctx *ctx, const float *h, const float *hu, const float *hv, int ptr_kind);
+
+/* Volumetric inflow (the water source sigma of Eq. 6): n cells (flat
+ * indices j*nx+i, host array) with weights (host array, normalised to sum 1
+ * by the library) receive Q(t) = q_base + q_peak exp(-(t - t_peak)^2 /
+ * (2 t_sigma^2)) m^3/s, evaluated at mid-step; no momentum is added.  n = 0
+ * removes the inflow. */
+int sw_set_inflow(sw_ctx *ctx, const int32_t *cell_idx, const float *weight, int32_t n,
+                  double q_base, double q_peak, double t_peak, double t_sigma);
+
+/* Bed sources q_b^+ (deposition) and q_b^- (erosion drain) of Eq. 1, m/s,
+ * per cell; either may be NULL (zero). */
+int sw_set_sed_sources(sw_ctx *ctx, const float *qb_plus, const float *qb_minus, int ptr_kind);
+
+/* Model time and step counter reported by sw_get_sums (does not touch fields). */
+int sw_set_time(sw_ctx *ctx, double t, int64_t step);
+
+/* Advance nsteps CSPH-TVD steps (Section 3 kernels K1..K8) with the Eq. 7
+ * time step.  Asynchronous: errors raised on the device (SW_ERR_NONFINITE,
+ * SW_ERR_DT_UNDERFLOW) stop all later steps and are returned by the next
+ * sw_get_fields / sw_get_sums / sw_sync; the fields then hold the state at the
+ * start of the failing step. */
+int sw_advance(sw_ctx *ctx, int32_t nsteps);
+
+/* Same with a fixed step dt; a step whose Eq. 7 bound is below dt raises
+ * SW_ERR_CFL on the device (as above). */
+int sw_advance_fixed_dt(sw_ctx *ctx, int32_t nsteps, double dt);
+
+/* Wait for queued work; returns the sticky device error, if any. */
+int sw_sync(sw_ctx *ctx);
+
+/* Read the current fields (any pointer may be NULL to skip that field). */
+int sw_get_fields(sw_ctx *ctx, float *h, float *hu, float *hv, float *b, int ptr_kind);
+
+/* FP64 global sums of the current state and the accumulated balances. */
+int sw_get_sums(sw_ctx *ctx, sw_sums *out);
+
+/* Text of the last error on ctx (never NULL; "" if none). */
+const char *sw_last_error(const sw_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSPH_H */

@@ -123,7 +123,7 @@ void orc_j0(const orc_params *p, double H, double u, double v, double nM, double
     if (p->sed_law == ORC_SED_NONE) return;
     if (!(H > p->h_sed)) return;
     double speed = sqrt(u * u + v * v);
-    double vk = p->C_Sh * cbrt(d50) * pow(H, 1.0 / 6.0);
+    double vk = p->C_Sh * cbrt(d50) * sqrt(cbrt(H));  /* d50^(1/3) H^(1/6) */
     if (!(speed > vk)) return;
     double A, m;
     if (p->sed_law == ORC_SED_GRASS) {
@@ -133,7 +133,7 @@ void orc_j0(const orc_params *p, double H, double u, double v, double nM, double
         A = 0.05 * nM * nM * nM / ((p->s_rel - 1.0) * sqrt(p->g * H) * d50);
         m = 4.0;
     }
-    double f = A * pow(speed, m);
+    double f = (m == 4.0) ? A * (speed * speed) * (speed * speed) : A * pow(speed, m);
     *jx = f * u;
     *jy = f * v;
 }
@@ -265,7 +265,7 @@ static void forces(const orc_params *p, const double *Hd, const double *b, doubl
 static double friction_rate(const orc_params *p, double nM, double speed, double H)
 {
     double Hf = H > p->eps ? H : p->eps;
-    return p->g * nM * nM * speed / pow(Hf, 4.0 / 3.0);
+    return p->g * nM * nM * speed / (Hf * cbrt(Hf));  /* Hf^(4/3) */
 }
 
 /* ---------------------------------------------------------------------- */
@@ -281,6 +281,8 @@ int orc_cfl(const orc_params *p, const orc_inputs *in, const double *H, const do
     const size_t n = (size_t)p->nx * p->ny;
     double vp = 0.0, vs = 0.0, D = 0.0;
     int bad = 0;
+    /* maxima are independent of the order they are taken in */
+#pragma omp parallel for schedule(static) reduction(max : vp, vs, D) reduction(| : bad)
     for (size_t c = 0; c < n; ++c) {
         double w = orc_w(H[c], p->eps);
         double u = qx[c] * w, v = qy[c] * w;
@@ -343,14 +345,6 @@ static double slope(const orc_params *p, const double *a, int i, int j, int dir,
         ap = ghost(p, a, i, j + 1, nxf, nyf);
     }
     return orc_minmod(a0 - am, ap - a0);
-}
-
-/* Reconstructed face value of cell (i,j) at its face on side `side` (+1 the */
-/* east/north face, -1 the west/south face) along `dir`.                     */
-static double face_value(const orc_params *p, const double *a, int i, int j, int dir, int side,
-                         int nxf, int nyf)
-{
-    return a[(size_t)j * p->nx + i] + 0.5 * side * slope(p, a, i, j, dir, nxf, nyf);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -466,7 +460,31 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
     /* linearly with minmod slopes; face depths are hydrostatic; the water  */
     /* flux is HLL; the bedload flux is the flux-split donor cell of J0     */
     /* plus the slope term of Eq. 2, -C_J |J0| grad b, with |J0| averaged.  */
+    /* Slopes first: sx[k] / sy[k] hold the limited slope of field k of     */
+    /* each cell along x / y (fields: zeta, H, normal transport velocity,   */
+    /* normal and tangential Lagrangian velocity; ghosts per the BC).       */
     const double CJ = p->C_J;
+    double *sx[5], *sy[5];
+    for (int k = 0; k < 5; ++k) {
+        sx[k] = malloc(n * sizeof(double));
+        sy[k] = malloc(n * sizeof(double));
+    }
+    const double *fx[5] = {zeta, H, utx, uLx, uLy};  /* along x: normal = x */
+    const int fx_nx[5] = {0, 0, 1, 1, 0}, fx_ny[5] = {0, 0, 0, 0, 1};
+    const double *fy[5] = {zeta, H, uty, uLy, uLx};  /* along y: normal = y */
+    const int fy_nx[5] = {0, 0, 0, 0, 1}, fy_ny[5] = {0, 0, 1, 1, 0};
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            size_t c = (size_t)j * nx + i;
+            for (int k = 0; k < 5; ++k) {
+                sx[k][c] = slope(p, fx[k], i, j, 0, fx_nx[k], fx_ny[k]);
+                sy[k][c] = slope(p, fy[k], i, j, 1, fy_nx[k], fy_ny[k]);
+            }
+        }
+    }
+    /* face values of cell c on its plus (+0.5 slope) or minus (-0.5) side */
+#define FACEV(arr, sl, c, side) ((arr)[c] + 0.5 * (side) * (sl)[c])
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j) {
         for (int k = 0; k <= nx; ++k) {
@@ -474,31 +492,23 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
             int iL = k - 1, iR = k;  /* cells west / east of face k */
             double fl[3] = {0.0, 0.0, 0.0}, fj = 0.0;
             if (iL >= 0 && iR < nx) {
-                double zL = face_value(p, zeta, iL, j, 0, +1, 0, 0);
-                double hL = face_value(p, H, iL, j, 0, +1, 0, 0);
-                double tL = face_value(p, utx, iL, j, 0, +1, 1, 0);
-                double nL = face_value(p, uLx, iL, j, 0, +1, 1, 0);
-                double sL = face_value(p, uLy, iL, j, 0, +1, 0, 1);
-                double zR = face_value(p, zeta, iR, j, 0, -1, 0, 0);
-                double hR = face_value(p, H, iR, j, 0, -1, 0, 0);
-                double tR = face_value(p, utx, iR, j, 0, -1, 1, 0);
-                double nR = face_value(p, uLx, iR, j, 0, -1, 1, 0);
-                double sR = face_value(p, uLy, iR, j, 0, -1, 0, 1);
+                size_t cL = (size_t)j * nx + iL, cR = cL + 1;
+                double zL = FACEV(zeta, sx[0], cL, +1), zR = FACEV(zeta, sx[0], cR, -1);
+                double hL = FACEV(H, sx[1], cL, +1), hR = FACEV(H, sx[1], cR, -1);
+                double tL = FACEV(utx, sx[2], cL, +1), tR = FACEV(utx, sx[2], cR, -1);
+                double nL = FACEV(uLx, sx[3], cL, +1), nR = FACEV(uLx, sx[3], cR, -1);
+                double sL = FACEV(uLy, sx[4], cL, +1), sR = FACEV(uLy, sx[4], cR, -1);
                 double HsL, HsR;
                 face_depths(zL, hL, zR, hR, &HsL, &HsR);
                 orc_hll(g, HsL, nL, sL, tL, HsR, nR, sR, tR, fl);
-                size_t cL = (size_t)j * nx + iL, cR = cL + 1;
                 double mag = 0.5 * (sqrt(J0x[cL] * J0x[cL] + J0y[cL] * J0y[cL]) +
                                     sqrt(J0x[cR] * J0x[cR] + J0y[cR] * J0y[cR]));
                 fj = fmax(J0x[cL], 0.0) + fmin(J0x[cR], 0.0) - CJ * mag * (b[cR] - b[cL]) / dx;
             } else if (iR == nx) {  /* east boundary, interior cell on the left */
-                int ic = nx - 1;
-                size_t c = (size_t)j * nx + ic;
-                double zL = face_value(p, zeta, ic, j, 0, +1, 0, 0);
-                double hL = face_value(p, H, ic, j, 0, +1, 0, 0);
-                double tL = face_value(p, utx, ic, j, 0, +1, 1, 0);
-                double nL = face_value(p, uLx, ic, j, 0, +1, 1, 0);
-                double sL = face_value(p, uLy, ic, j, 0, +1, 0, 1);
+                size_t c = (size_t)j * nx + nx - 1;
+                double zL = FACEV(zeta, sx[0], c, +1), hL = FACEV(H, sx[1], c, +1);
+                double tL = FACEV(utx, sx[2], c, +1), nL = FACEV(uLx, sx[3], c, +1);
+                double sL = FACEV(uLy, sx[4], c, +1);
                 double HsL, HsR;
                 face_depths(zL, hL, zL, hL, &HsL, &HsR);
                 if (p->bc[1] == ORC_BC_WALL) {
@@ -511,13 +521,10 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
                     fj = fmax(J0x[c], 0.0);
                 }
             } else {  /* west boundary, interior cell on the right */
-                int ic = 0;
-                size_t c = (size_t)j * nx + ic;
-                double zR = face_value(p, zeta, ic, j, 0, -1, 0, 0);
-                double hR = face_value(p, H, ic, j, 0, -1, 0, 0);
-                double tR = face_value(p, utx, ic, j, 0, -1, 1, 0);
-                double nR = face_value(p, uLx, ic, j, 0, -1, 1, 0);
-                double sR = face_value(p, uLy, ic, j, 0, -1, 0, 1);
+                size_t c = (size_t)j * nx;
+                double zR = FACEV(zeta, sx[0], c, -1), hR = FACEV(H, sx[1], c, -1);
+                double tR = FACEV(utx, sx[2], c, -1), nR = FACEV(uLx, sx[3], c, -1);
+                double sR = FACEV(uLy, sx[4], c, -1);
                 double HsL, HsR;
                 face_depths(zR, hR, zR, hR, &HsL, &HsR);
                 if (p->bc[0] == ORC_BC_WALL) {
@@ -543,31 +550,23 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
             int jL = k - 1, jR = k;  /* cells south / north of face k */
             double fl[3] = {0.0, 0.0, 0.0}, fj = 0.0;
             if (jL >= 0 && jR < ny) {
-                double zL = face_value(p, zeta, i, jL, 1, +1, 0, 0);
-                double hL = face_value(p, H, i, jL, 1, +1, 0, 0);
-                double tL = face_value(p, uty, i, jL, 1, +1, 0, 1);
-                double nL = face_value(p, uLy, i, jL, 1, +1, 0, 1);
-                double sL = face_value(p, uLx, i, jL, 1, +1, 1, 0);
-                double zR = face_value(p, zeta, i, jR, 1, -1, 0, 0);
-                double hR = face_value(p, H, i, jR, 1, -1, 0, 0);
-                double tR = face_value(p, uty, i, jR, 1, -1, 0, 1);
-                double nR = face_value(p, uLy, i, jR, 1, -1, 0, 1);
-                double sR = face_value(p, uLx, i, jR, 1, -1, 1, 0);
+                size_t cL = (size_t)jL * nx + i, cR = cL + nx;
+                double zL = FACEV(zeta, sy[0], cL, +1), zR = FACEV(zeta, sy[0], cR, -1);
+                double hL = FACEV(H, sy[1], cL, +1), hR = FACEV(H, sy[1], cR, -1);
+                double tL = FACEV(uty, sy[2], cL, +1), tR = FACEV(uty, sy[2], cR, -1);
+                double nL = FACEV(uLy, sy[3], cL, +1), nR = FACEV(uLy, sy[3], cR, -1);
+                double sL = FACEV(uLx, sy[4], cL, +1), sR = FACEV(uLx, sy[4], cR, -1);
                 double HsL, HsR;
                 face_depths(zL, hL, zR, hR, &HsL, &HsR);
                 orc_hll(g, HsL, nL, sL, tL, HsR, nR, sR, tR, fl);
-                size_t cL = (size_t)jL * nx + i, cR = cL + nx;
                 double mag = 0.5 * (sqrt(J0x[cL] * J0x[cL] + J0y[cL] * J0y[cL]) +
                                     sqrt(J0x[cR] * J0x[cR] + J0y[cR] * J0y[cR]));
                 fj = fmax(J0y[cL], 0.0) + fmin(J0y[cR], 0.0) - CJ * mag * (b[cR] - b[cL]) / dx;
             } else if (jR == ny) {  /* north boundary */
-                int jc = ny - 1;
-                size_t c = (size_t)jc * nx + i;
-                double zL = face_value(p, zeta, i, jc, 1, +1, 0, 0);
-                double hL = face_value(p, H, i, jc, 1, +1, 0, 0);
-                double tL = face_value(p, uty, i, jc, 1, +1, 0, 1);
-                double nL = face_value(p, uLy, i, jc, 1, +1, 0, 1);
-                double sL = face_value(p, uLx, i, jc, 1, +1, 1, 0);
+                size_t c = (size_t)(ny - 1) * nx + i;
+                double zL = FACEV(zeta, sy[0], c, +1), hL = FACEV(H, sy[1], c, +1);
+                double tL = FACEV(uty, sy[2], c, +1), nL = FACEV(uLy, sy[3], c, +1);
+                double sL = FACEV(uLx, sy[4], c, +1);
                 double HsL, HsR;
                 face_depths(zL, hL, zL, hL, &HsL, &HsR);
                 if (p->bc[3] == ORC_BC_WALL) {
@@ -580,13 +579,10 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
                     fj = fmax(J0y[c], 0.0);
                 }
             } else {  /* south boundary */
-                int jc = 0;
-                size_t c = (size_t)jc * nx + i;
-                double zR = face_value(p, zeta, i, jc, 1, -1, 0, 0);
-                double hR = face_value(p, H, i, jc, 1, -1, 0, 0);
-                double tR = face_value(p, uty, i, jc, 1, -1, 0, 1);
-                double nR = face_value(p, uLy, i, jc, 1, -1, 0, 1);
-                double sR = face_value(p, uLx, i, jc, 1, -1, 1, 0);
+                size_t c = (size_t)i;
+                double zR = FACEV(zeta, sy[0], c, -1), hR = FACEV(H, sy[1], c, -1);
+                double tR = FACEV(uty, sy[2], c, -1), nR = FACEV(uLy, sy[3], c, -1);
+                double sR = FACEV(uLx, sy[4], c, -1);
                 double HsL, HsR;
                 face_depths(zR, hR, zR, hR, &HsL, &HsR);
                 if (p->bc[2] == ORC_BC_WALL) {
@@ -604,6 +600,11 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
             Gqx[f] = fl[2];  /* tangential = x */
             GJ[f] = fj;
         }
+    }
+#undef FACEV
+    for (int k = 0; k < 5; ++k) {
+        free(sx[k]);
+        free(sy[k]);
     }
 
     /* Positivity: the draining limiter.  theta_i scales every flux that    */

@@ -1,0 +1,260 @@
+"""Thin ctypes binding of the C ABI in include/csph.h (libcsph.so).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  The functions carry the C names; ``Solver`` is a small convenience
+wrapper over them.  Arrays may be numpy arrays (host) or torch tensors on the
+GPU (device pointers, ordered on the solver's stream).  If the library is not
+built this module raises at import time: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+# torch ships its own HIP runtime (same soname as the system one).  Loading
+# torch first makes the dynamic loader bind this library to that runtime, so
+# the process holds one HIP runtime and torch streams/pointers are valid here.
+try:
+    import torch  # noqa: F401
+except ImportError:  # a plain C/numpy user gets the system runtime
+    torch = None
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcsph.so")
+
+SW_OK = 0
+SW_ERR_ARG, SW_ERR_HIP, SW_ERR_NONFINITE, SW_ERR_DT_UNDERFLOW, SW_ERR_STATE, SW_ERR_CFL = (
+    -1, -2, -3, -4, -5, -6)
+ERROR_NAMES = {-1: "SW_ERR_ARG", -2: "SW_ERR_HIP", -3: "SW_ERR_NONFINITE",
+               -4: "SW_ERR_DT_UNDERFLOW", -5: "SW_ERR_STATE", -6: "SW_ERR_CFL"}
+SW_BC_WALL, SW_BC_OPEN = 0, 1
+SW_SED_NONE, SW_SED_GRASS, SW_SED_EQ4 = 0, 1, 2
+SW_PTR_HOST, SW_PTR_DEVICE = 0, 1
+SW_FLAG_HGS, SW_FLAG_UNFUSED, SW_FLAG_NO_GRAPH = 1, 2, 4
+
+
+class sw_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("dx", C.c_double), ("bc", C.c_int32 * 4)]
+
+
+class sw_params(C.Structure):
+    _fields_ = [("g", C.c_double), ("cfl", C.c_double), ("eps_dry", C.c_double),
+                ("h_sed", C.c_double), ("dt_max", C.c_double), ("dt_min", C.c_double),
+                ("s_rel", C.c_double), ("C_J", C.c_double), ("C_Sh", C.c_double),
+                ("A_G", C.c_double), ("m_exp", C.c_double), ("sed_law", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class sw_sums(C.Structure):
+    _fields_ = [("t", C.c_double), ("last_dt", C.c_double), ("water_volume", C.c_double),
+                ("sediment_volume", C.c_double), ("water_boundary_out", C.c_double),
+                ("water_source_in", C.c_double), ("sed_boundary_out", C.c_double),
+                ("sed_source_in", C.c_double), ("vp", C.c_double), ("vs", C.c_double),
+                ("D", C.c_double), ("step", C.c_int64), ("wet_cells", C.c_int64),
+                ("active_tiles", C.c_int64), ("binding_term", C.c_int32), ("error", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_fp = C.POINTER(C.c_float)
+_ctxp = C.c_void_p
+
+# (name, restype, argtypes) of every exported entry point
+SIGNATURES = [
+    ("sw_default_params", None, [C.POINTER(sw_params)]),
+    ("sw_create", C.c_int, [C.POINTER(sw_grid), C.POINTER(sw_params), C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("sw_destroy", C.c_int, [_ctxp]),
+    ("sw_set_bed", C.c_int, [_ctxp, C.c_void_p, C.c_int]),
+    ("sw_set_soil", C.c_int, [_ctxp, C.c_void_p, C.c_float, C.c_void_p, C.c_float, C.c_void_p,
+                              C.c_float, C.c_int]),
+    ("sw_set_state", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    ("sw_set_inflow", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double,
+                                C.c_double, C.c_double]),
+    ("sw_set_sed_sources", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_int]),
+    ("sw_set_time", C.c_int, [_ctxp, C.c_double, C.c_int64]),
+    ("sw_advance", C.c_int, [_ctxp, C.c_int32]),
+    ("sw_advance_fixed_dt", C.c_int, [_ctxp, C.c_int32, C.c_double]),
+    ("sw_sync", C.c_int, [_ctxp]),
+    ("sw_get_fields", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    ("sw_get_sums", C.c_int, [_ctxp, C.POINTER(sw_sums)]),
+    ("sw_last_error", C.c_char_p, [_ctxp]),
+]
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is not built (run __graft_entry__.build())")
+    lib = C.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = load_library()
+
+
+class SwError(RuntimeError):
+    def __init__(self, code, msg=""):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(ctx, rc):
+    if rc != SW_OK:
+        msg = lib.sw_last_error(ctx).decode() if ctx else ""
+        raise SwError(rc, msg)
+
+
+def default_params(**over) -> sw_params:
+    p = sw_params()
+    lib.sw_default_params(C.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def make_grid(nx, ny, dx, bc=(0, 0, 0, 0)) -> sw_grid:
+    g = sw_grid()
+    g.nx, g.ny, g.dx = int(nx), int(ny), float(dx)
+    for k in range(4):
+        g.bc[k] = int(bc[k])
+    return g
+
+
+def _ptr(a, n):
+    """(pointer, ptr_kind, keep-alive) of a host numpy array or a CUDA torch tensor."""
+    if a is None:
+        return None, SW_PTR_HOST, None
+    if hasattr(a, "data_ptr") and hasattr(a, "is_cuda"):
+        if a.is_cuda:
+            import torch
+            assert a.dtype == torch.float32 and a.is_contiguous() and a.numel() == n
+            return C.c_void_p(a.data_ptr()), SW_PTR_DEVICE, a
+        a = a.numpy()
+    arr = np.ascontiguousarray(a, dtype=np.float32).reshape(-1)
+    assert arr.size == n, (arr.size, n)
+    return arr.ctypes.data_as(C.c_void_p), SW_PTR_HOST, arr
+
+
+class Solver:
+    """Owns one sw_ctx; methods map one-to-one onto the C entry points."""
+
+    def __init__(self, nx, ny, dx, bc=(0, 0, 0, 0), stream=None, **params):
+        self.nx, self.ny = int(nx), int(ny)
+        self.grid = make_grid(nx, ny, dx, bc)
+        self.params = default_params(**params)
+        h = C.c_void_p()
+        s = C.c_void_p(stream) if stream is not None else None
+        _check(None, lib.sw_create(C.byref(self.grid), C.byref(self.params), s, C.byref(h)))
+        self.ctx = h
+
+    def close(self):
+        if self.ctx:
+            lib.sw_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def n(self):
+        return self.nx * self.ny
+
+    def set_bed(self, b):
+        p, kind, keep = _ptr(b, self.n)
+        _check(self.ctx, lib.sw_set_bed(self.ctx, p, kind))
+
+    def set_soil(self, manning=0.0, d50=5e-4, psi=0.4):
+        args, kinds, keep = [], set(), []
+        for v in (manning, d50, psi):
+            if np.isscalar(v):
+                args += [None, float(v)]
+            else:
+                p, kind, k = _ptr(v, self.n)
+                args += [p, 0.0]
+                kinds.add(kind)
+                keep.append(k)
+        assert len(kinds) <= 1, "mix of host and device soil arrays"
+        kind = kinds.pop() if kinds else SW_PTR_HOST
+        _check(self.ctx, lib.sw_set_soil(self.ctx, *args, kind))
+
+    def set_state(self, h, hu, hv):
+        (ph, kind, k1), (pu, _, k2), (pv, _, k3) = (_ptr(x, self.n) for x in (h, hu, hv))
+        _check(self.ctx, lib.sw_set_state(self.ctx, ph, pu, pv, kind))
+
+    def set_inflow(self, cells, weights, q_base, q_peak, t_peak, t_sigma):
+        if cells is None or len(cells) == 0:
+            _check(self.ctx, lib.sw_set_inflow(self.ctx, None, None, 0, 0.0, 0.0, 0.0, 1.0))
+            return
+        idx = np.ascontiguousarray(cells, dtype=np.int32)
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        _check(self.ctx, lib.sw_set_inflow(self.ctx, idx.ctypes.data_as(C.c_void_p),
+                                           w.ctypes.data_as(C.c_void_p), int(idx.size),
+                                           float(q_base), float(q_peak), float(t_peak),
+                                           float(t_sigma)))
+
+    def set_sed_sources(self, qb_plus=None, qb_minus=None):
+        (pp, k1, a), (pm, k2, b) = _ptr(qb_plus, self.n), _ptr(qb_minus, self.n)
+        kind = k1 if qb_plus is not None else k2
+        _check(self.ctx, lib.sw_set_sed_sources(self.ctx, pp, pm, kind))
+
+    def set_time(self, t, step=0):
+        _check(self.ctx, lib.sw_set_time(self.ctx, float(t), int(step)))
+
+    def advance(self, nsteps, dt=None):
+        if dt is None:
+            _check(self.ctx, lib.sw_advance(self.ctx, int(nsteps)))
+        else:
+            _check(self.ctx, lib.sw_advance_fixed_dt(self.ctx, int(nsteps), float(dt)))
+
+    def sync(self):
+        _check(self.ctx, lib.sw_sync(self.ctx))
+
+    def get_fields(self, out=None):
+        """Return (h, hu, hv, b) as float32 numpy arrays [ny, nx] (or fill torch tensors)."""
+        if out is not None:
+            ptrs = [_ptr(t, self.n) for t in out]
+            _check(self.ctx, lib.sw_get_fields(self.ctx, *[p for p, _, _ in ptrs], SW_PTR_DEVICE))
+            return out
+        arrs = [np.empty((self.ny, self.nx), dtype=np.float32) for _ in range(4)]
+        _check(self.ctx, lib.sw_get_fields(self.ctx, *[a.ctypes.data_as(C.c_void_p) for a in arrs],
+                                           SW_PTR_HOST))
+        return tuple(arrs)
+
+    def get_sums(self) -> dict:
+        s = sw_sums()
+        _check(self.ctx, lib.sw_get_sums(self.ctx, C.byref(s)))
+        return s.as_dict()
+
+    def load_workload(self, w):
+        """Upload a paper_2103_15196_amd.workloads.Workload (bed, soil, state, sources)."""
+        self.set_bed(w.b)
+        self.set_soil(w.nM, w.d50, w.psi)
+        if w.qb is not None:
+            self.set_sed_sources(np.maximum(w.qb, 0), np.maximum(-np.asarray(w.qb), 0))
+        if w.inflow_idx is not None:
+            self.set_inflow(w.inflow_idx, w.inflow_w, w.Q_base, w.Q_peak, w.t_peak, w.t_sigma)
+        self.set_state(w.H, w.qx, w.qy)
+
+
+def solver_for(w, stream=None, **params) -> Solver:
+    """A Solver loaded with workload ``w`` (its grid, boundary kinds, CFL and law)."""
+    kw = dict(cfl=w.cfl, sed_law=w.sed_law)
+    kw.update(params)
+    s = Solver(w.nx, w.ny, w.dx, w.bc, stream=stream, **kw)
+    s.load_workload(w)
+    return s

@@ -1,0 +1,1496 @@
+// csph.hip -- HIP (gfx950) kernels and C ABI of the CSPH-TVD shallow-water +
+// Exner solver (Khrapov & Khoperskov 2020, Section 3 kernels K1..K8).
+//
+// Layout in HBM: structure of arrays, one float32 plane per field (h, hu, hv,
+// b; Lagrangian momentum QLx, QLy; optional per-cell soil), rows padded to a
+// multiple of 64 floats so that every wavefront row load is one aligned
+// 256-byte line.  The state is double-buffered: step k reads buffer k&1 and
+// writes buffer (k+1)&1.  Global reductions (Eq. 7 maxima, volumes, boundary
+// balances) run in FP64 or as exact FP32 maxima; see the kernels below.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "csph.h"
+#include "csph_device.h"
+
+using namespace csph;
+
+namespace {
+
+constexpr int BX = 64;  // threads per block along x (one wavefront row)
+constexpr int BY = 4;   // rows per block in the one-cell-per-thread kernels
+constexpr int NSLOT = 16;  // spread of the per-step maxima over atomic slots
+
+// Device control block: per-step maxima slots, time ring, balances, error.
+struct Ctrl {
+    unsigned slot[2][NSLOT][4];  // float bits of max |v|, max |v|+c, max |J0|/(1-psi); [3]: nonfinite
+    double t[2];                 // model time at the start of step k (ring k&1)
+    double dt[2];                // step size of step k
+    double qmid[2];              // inflow discharge at t_k + dt_k/2
+    double in_w, in_s;           // accumulated source volumes
+    double vp, vs, D;            // Eq. 7 maxima at the start of the last step
+    double last_dt;
+    int err, err_k, binding, kdev;  // kdev: steps taken since the state was set
+};
+
+struct StepArgs {
+    int mode_fixed;              // 1: fixed dt
+    double dt_fixed;
+    double dx, cfl, dt_max, dt_min;
+    int has_inflow;
+    double q_base, q_peak, t_peak, t_sigma;
+    double qb_total;             // sum over cells of (q_b^+ - q_b^-) dx^2
+};
+
+__device__ __forceinline__ unsigned fbits_nonneg(float x) { return __float_as_uint(x + 0.0f); }
+
+// Wave64 + block max of three non-negative floats (as bits) and a flag,
+// then one atomicMax per value into this block's slot.
+__device__ __forceinline__ void block_maxima(unsigned a, unsigned b, unsigned c, unsigned bad,
+                                             unsigned (*slot)[4])
+{
+    __shared__ unsigned red[4][16];
+    for (int off = 32; off > 0; off >>= 1) {
+        a = max(a, (unsigned)__shfl_xor((int)a, off));
+        b = max(b, (unsigned)__shfl_xor((int)b, off));
+        c = max(c, (unsigned)__shfl_xor((int)c, off));
+        bad = max(bad, (unsigned)__shfl_xor((int)bad, off));
+    }
+    int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    int nw = (blockDim.x * blockDim.y + 63) >> 6;
+    int wv = tid >> 6;
+    if ((tid & 63) == 0) {
+        red[0][wv] = a; red[1][wv] = b; red[2][wv] = c; red[3][wv] = bad;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < nw; ++w) {
+            a = max(a, red[0][w]); b = max(b, red[1][w]); c = max(c, red[2][w]);
+            bad = max(bad, red[3][w]);
+        }
+        int s = (blockIdx.x + blockIdx.y * gridDim.x) % NSLOT;
+        if (a) atomicMax(&slot[s][0], a);
+        if (b) atomicMax(&slot[s][1], b);
+        if (c) atomicMax(&slot[s][2], c);
+        if (bad) atomicMax(&slot[s][3], bad);
+    }
+}
+
+// Eq. 7 maxima contributions of one cell of a state.
+__device__ __forceinline__ void cell_maxima(const KPar &P, float H, float qx, float qy, float b,
+                                            int c, unsigned &mv, unsigned &ms, unsigned &mD,
+                                            unsigned &bad)
+{
+    float w = wdes(H, P);
+    float u = qx * w, v = qy * w;
+    float sp = sqrtf(u * u + v * v);
+    float cs = sqrtf(P.g * (H > 0.0f ? H : 0.0f));
+    float jx, jy;
+    bedload(P, H, u, v, soil(P.nM, P.nM_s, c), soil(P.d50, P.d50_s, c), jx, jy);
+    float Dc = sqrtf(jx * jx + jy * jy) / (1.0f - soil(P.psi, P.psi_s, c));
+    bool fin = isfinite(H) && isfinite(qx) && isfinite(qy) && isfinite(b) && isfinite(sp) &&
+               isfinite(Dc);
+    if (!fin) {
+        bad = 1u;
+        return;
+    }
+    mv = max(mv, fbits_nonneg(sp));
+    ms = max(ms, fbits_nonneg(sp + cs));
+    mD = max(mD, fbits_nonneg(Dc));
+}
+
+// Maxima of the initial (or externally modified) state into slot ring k&1.
+__global__ void k_prepare(KPar P, Ctrl *ctrl, int k, const float *__restrict__ H,
+                          const float *__restrict__ qx, const float *__restrict__ qy,
+                          const float *__restrict__ b)
+{
+    int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    unsigned mv = 0, ms = 0, mD = 0, bad = 0;
+    if (i < P.nx && j < P.ny) {
+        int c = j * P.pitch + i;
+        cell_maxima(P, H[c], qx[c], qy[c], b[c], c, mv, ms, mD, bad);
+    }
+    block_maxima(mv, ms, mD, bad, ctrl->slot[k & 1]);
+}
+
+// K3: time step of Eq. 7 from the maxima of step k's state; clears the slots
+// that step k's update fills for step k+1; advances the time ring.
+__global__ void k_dt(Ctrl *ctrl, int k, StepArgs A)
+{
+    int t = threadIdx.x;
+    const int kd = ctrl->kdev;
+    unsigned(*cur)[4] = ctrl->slot[k & 1];
+    unsigned(*nxt)[4] = ctrl->slot[(k + 1) & 1];
+    unsigned a = 0, b = 0, c = 0, bad = 0;
+    if (t < NSLOT) {
+        a = cur[t][0]; b = cur[t][1]; c = cur[t][2]; bad = cur[t][3];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a = max(a, (unsigned)__shfl_xor((int)a, off));
+        b = max(b, (unsigned)__shfl_xor((int)b, off));
+        c = max(c, (unsigned)__shfl_xor((int)c, off));
+        bad = max(bad, (unsigned)__shfl_xor((int)bad, off));
+    }
+    if (ctrl->err) return;
+    if (t < NSLOT) {
+        nxt[t][0] = 0u; nxt[t][1] = 0u; nxt[t][2] = 0u; nxt[t][3] = 0u;
+    }
+    if (t != 0) return;
+    double vp = __uint_as_float(a), vs = __uint_as_float(b), D = __uint_as_float(c);
+    ctrl->vp = vp; ctrl->vs = vs; ctrl->D = D;
+    if (bad) {
+        ctrl->err = SW_ERR_NONFINITE;
+        ctrl->err_k = kd;
+        return;
+    }
+    double h = A.dx;
+    double t0 = vp > 0.0 ? h / (2.0 * vp) : INFINITY;
+    double t1 = vs > 0.0 ? h / vs : INFINITY;
+    double t2 = D > 0.0 ? h * h / (2.0 * D) : INFINITY;
+    double m = t0;
+    int which = 0;
+    if (t1 < m) { m = t1; which = 1; }
+    if (t2 < m) { m = t2; which = 2; }
+    double dt = A.cfl * m;
+    if (!(dt < A.dt_max)) { dt = A.dt_max; which = 3; }
+    if (A.mode_fixed) {
+        if (A.dt_fixed > dt) {
+            ctrl->err = SW_ERR_CFL;
+            ctrl->err_k = kd;
+            return;
+        }
+        dt = A.dt_fixed;
+        which = 4;
+    }
+    if (dt < A.dt_min) {
+        ctrl->err = SW_ERR_DT_UNDERFLOW;
+        ctrl->err_k = kd;
+        return;
+    }
+    double tn = ctrl->t[k & 1];
+    double q = 0.0;
+    if (A.has_inflow) {
+        double d = tn + 0.5 * dt - A.t_peak;
+        double pk = A.t_sigma > 0.0 ? A.q_peak * exp(-d * d / (2.0 * A.t_sigma * A.t_sigma)) : 0.0;
+        q = A.q_base + pk;
+        ctrl->in_w += dt * q;
+    }
+    ctrl->in_s += dt * A.qb_total;
+    ctrl->qmid[k & 1] = q;
+    ctrl->dt[k & 1] = dt;
+    ctrl->t[(k + 1) & 1] = tn + dt;
+    ctrl->last_dt = dt;
+    ctrl->binding = which;
+    ctrl->kdev = kd + 1;
+}
+
+// ---------------------------------------------------------------------------
+// Lagrangian stage (K2, K4, K5, K6), one thread per cell.
+// ---------------------------------------------------------------------------
+
+struct StateView {
+    const float *__restrict__ H, *__restrict__ qx, *__restrict__ qy, *__restrict__ b;
+};
+
+__device__ __forceinline__ void vel(const KPar &P, const StateView &S, int c, float &u, float &v)
+{
+    float w = wdes(S.H[c], P);
+    u = S.qx[c] * w;
+    v = S.qy[c] * w;
+}
+
+// Half-step depth of cell (i, j): H / J with J the area ratio of the column
+// after dt/2 under the face-mean velocities at t_n (wall face: 0, open face:
+// the cell's own velocity).
+__device__ float half_depth(const KPar &P, const StateView &S, int i, int j, float hdt_dx)
+{
+    int c = j * P.pitch + i;
+    float uc, vc;
+    vel(P, S, c, uc, vc);
+    float ue, uw, vn, vs, t0, t1;
+    if (i + 1 < P.nx) { vel(P, S, c + 1, t0, t1); ue = 0.5f * (uc + t0); }
+    else ue = (P.bcE == kWall) ? 0.0f : uc;
+    if (i > 0) { vel(P, S, c - 1, t0, t1); uw = 0.5f * (t0 + uc); }
+    else uw = (P.bcW == kWall) ? 0.0f : uc;
+    if (j + 1 < P.ny) { vel(P, S, c + P.pitch, t0, t1); vn = 0.5f * (vc + t1); }
+    else vn = (P.bcN == kWall) ? 0.0f : vc;
+    if (j > 0) { vel(P, S, c - P.pitch, t0, t1); vs = 0.5f * (t1 + vc); }
+    else vs = (P.bcS == kWall) ? 0.0f : vc;
+    float Jx = 1.0f + hdt_dx * (ue - uw);
+    float Jy = 1.0f + hdt_dx * (vn - vs);
+    return S.H[c] / (Jx * Jy);
+}
+
+__global__ void __launch_bounds__(BX * BY) k_lagrange(KPar P, const Ctrl *__restrict__ ctrl, int k,
+                                                      StateView S, float *__restrict__ QLx,
+                                                      float *__restrict__ QLy)
+{
+    if (ctrl->err) return;
+    int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (i >= P.nx || j >= P.ny) return;
+    float dt = (float)ctrl->dt[k & 1];
+    int c = j * P.pitch + i;
+    bool hasW = i > 0, hasE = i + 1 < P.nx, hasS = j > 0, hasN = j + 1 < P.ny;
+    int cW = hasW ? c - 1 : c, cE = hasE ? c + 1 : c;
+    int cS = hasS ? c - P.pitch : c, cN = hasN ? c + P.pitch : c;
+    float Hc = S.H[c], bc = S.b[c];
+    float bW = S.b[cW], bE = S.b[cE], bS = S.b[cS], bN = S.b[cN];
+    // K2: forces at t_n
+    float Snx = face_force(P, S.H[cW], bW, Hc, bc, S.H[cE], bE, hasW, hasE);
+    float Sny = face_force(P, S.H[cS], bS, Hc, bc, S.H[cN], bN, hasS, hasN);
+    float wc = wdes(Hc, P);
+    float qxc = S.qx[c], qyc = S.qy[c];
+    float uc = qxc * wc, vc = qyc * wc;
+    float nM = soil(P.nM, P.nM_s, c);
+    float gam = friction_rate(P, nM, sqrtf(uc * uc + vc * vc), Hc);
+    // K4: predictor momentum and half-step depths
+    float hdt = 0.5f * dt;
+    float qpx = (qxc + hdt * Snx) / (1.0f + hdt * gam);
+    float qpy = (qyc + hdt * Sny) / (1.0f + hdt * gam);
+    float upx = qpx * wc, upy = qpy * wc;
+    float hdt_dx = dt / (2.0f * P.dx);
+    float Hh = half_depth(P, S, i, j, hdt_dx);
+    float HhW = hasW ? half_depth(P, S, i - 1, j, hdt_dx) : Hh;
+    float HhE = hasE ? half_depth(P, S, i + 1, j, hdt_dx) : Hh;
+    float HhS = hasS ? half_depth(P, S, i, j - 1, hdt_dx) : Hh;
+    float HhN = hasN ? half_depth(P, S, i, j + 1, hdt_dx) : Hh;
+    // K5: forces at t_{n+1/2}
+    float Shx = face_force(P, HhW, bW, Hh, bc, HhE, bE, hasW, hasE);
+    float Shy = face_force(P, HhS, bS, Hh, bc, HhN, bN, hasS, hasN);
+    float gamh = friction_rate(P, nM, sqrtf(upx * upx + upy * upy), Hh);
+    // K6: corrector (Lagrangian momentum)
+    QLx[c] = (qxc + dt * Shx) / (1.0f + dt * gamh);
+    QLy[c] = (qyc + dt * Shy) / (1.0f + dt * gamh);
+}
+
+// ---------------------------------------------------------------------------
+// Euler stage, unfused: K7 raw face fluxes, then K8 limiter + update.
+// ---------------------------------------------------------------------------
+
+struct LagView {
+    const float *__restrict__ QLx, *__restrict__ QLy;
+};
+
+// Cell quantities along x (dir 0) or y (dir 1) for the remap.
+__device__ __forceinline__ CellQ cell_q(const KPar &P, const StateView &S, const LagView &L, int c,
+                                        int dir)
+{
+    return along(cell_vals(P, S.H[c], S.qx[c], S.qy[c], S.b[c], L.QLx[c], L.QLy[c]), dir);
+}
+
+__device__ __forceinline__ void cell_j0(const KPar &P, const StateView &S, int c, float &jx,
+                                        float &jy)
+{
+    float H = S.H[c];
+    float w = wdes(H, P);
+    bedload(P, H, S.qx[c] * w, S.qy[c] * w, soil(P.nM, P.nM_s, c), soil(P.d50, P.d50_s, c), jx, jy);
+}
+
+struct FaceView {
+    float *__restrict__ xH, *__restrict__ xn, *__restrict__ xt, *__restrict__ xJ;  // [ny][nx+1]
+    float *__restrict__ yH, *__restrict__ yn, *__restrict__ yt, *__restrict__ yJ;  // [ny+1][nx]
+};
+
+// Raw flux of x-face k in row j (between cells k-1 and k) or y-face k in
+// column i (between cells k-1 and k along y).
+__device__ void raw_face(const KPar &P, const StateView &S, const LagView &L, int dir, int k,
+                         int line, float &fH, float &fn, float &ft, float &fJ)
+{
+    const int n = dir == 0 ? P.nx : P.ny;
+    const int stride = dir == 0 ? 1 : P.pitch;
+    const int base = dir == 0 ? line * P.pitch : line;
+    const bool wallLo = (dir == 0 ? P.bcW : P.bcS) == kWall;
+    const bool wallHi = (dir == 0 ? P.bcE : P.bcN) == kWall;
+    auto q = [&](int m) -> CellQ {
+        if (m < 0) return ghost_of(cell_q(P, S, L, base, dir), wallLo);
+        if (m >= n) return ghost_of(cell_q(P, S, L, base + (n - 1) * stride, dir), wallHi);
+        return cell_q(P, S, L, base + m * stride, dir);
+    };
+    water_flux(P, k, n, wallLo, wallHi, q(k - 2), q(k - 1), q(k), q(k + 1), fH, fn, ft);
+    float jxL = 0.0f, jyL = 0.0f, bL = 0.0f, jxR = 0.0f, jyR = 0.0f, bR = 0.0f;
+    if (k > 0) {
+        int cL = base + (k - 1) * stride;
+        cell_j0(P, S, cL, jxL, jyL);
+        bL = S.b[cL];
+    }
+    if (k < n) {
+        int cR = base + k * stride;
+        cell_j0(P, S, cR, jxR, jyR);
+        bR = S.b[cR];
+    }
+    fJ = sed_flux(P, k, n, wallLo, wallHi, dir, jxL, jyL, bL, jxR, jyR, bR);
+}
+
+__global__ void __launch_bounds__(BX * BY) k_faces(KPar P, const Ctrl *__restrict__ ctrl, StateView S,
+                                                   LagView L, FaceView F)
+{
+    if (ctrl->err) return;
+    int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (j < P.ny && i <= P.nx) {
+        float fH, fn, ft, fJ;
+        raw_face(P, S, L, 0, i, j, fH, fn, ft, fJ);
+        int f = j * (P.nx + 1) + i;
+        F.xH[f] = fH; F.xn[f] = fn; F.xt[f] = ft; F.xJ[f] = fJ;
+    }
+    if (i < P.nx && j <= P.ny) {
+        float fH, fn, ft, fJ;
+        raw_face(P, S, L, 1, j, i, fH, fn, ft, fJ);
+        int f = j * P.nx + i;
+        F.yH[f] = fH; F.yn[f] = fn; F.yt[f] = ft; F.yJ[f] = fJ;
+    }
+}
+
+struct OutView {
+    float *__restrict__ H, *__restrict__ qx, *__restrict__ qy, *__restrict__ b;
+};
+
+// Draining limiter of cell (i, j): theta = min(1, H dx / (dt * outflow)).
+__device__ __forceinline__ float theta_of(const KPar &P, const StateView &S, const FaceView &F,
+                                          int i, int j, float dt)
+{
+    if (i < 0 || j < 0 || i >= P.nx || j >= P.ny) return 1.0f;  // ghost donor
+    float fe = F.xH[j * (P.nx + 1) + i + 1], fw = F.xH[j * (P.nx + 1) + i];
+    float gn = F.yH[(j + 1) * P.nx + i], gs = F.yH[j * P.nx + i];
+    float out = fmaxf(0.0f, fe) + fmaxf(0.0f, -fw) + fmaxf(0.0f, gn) + fmaxf(0.0f, -gs);
+    return out > 0.0f ? fminf(1.0f, S.H[j * P.pitch + i] * P.dx / (dt * out)) : 1.0f;
+}
+
+__global__ void __launch_bounds__(BX * BY) k_update(KPar P, Ctrl *__restrict__ ctrl, int k,
+                                                    StateView S, LagView L, FaceView F, OutView O,
+                                                    double *__restrict__ bnd)
+{
+    unsigned mv = 0, ms = 0, mD = 0, bad = 0;
+    bool live = !ctrl->err;
+    int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (live && i < P.nx && j < P.ny) {
+        double dtd = ctrl->dt[k & 1];
+        float dt = (float)dtd;
+        int c = j * P.pitch + i;
+        float th = theta_of(P, S, F, i, j, dt);
+        float thW = theta_of(P, S, F, i - 1, j, dt), thE = theta_of(P, S, F, i + 1, j, dt);
+        float thS = theta_of(P, S, F, i, j - 1, dt), thN = theta_of(P, S, F, i, j + 1, dt);
+        int fw = j * (P.nx + 1) + i, fe = fw + 1;
+        int gs = j * P.nx + i, gn = gs + P.nx;
+        // each face's water fluxes take the theta of the cell the mass leaves
+        float sw = F.xH[fw] > 0.0f ? thW : (F.xH[fw] < 0.0f ? th : 1.0f);
+        float se = F.xH[fe] > 0.0f ? th : (F.xH[fe] < 0.0f ? thE : 1.0f);
+        float ss = F.yH[gs] > 0.0f ? thS : (F.yH[gs] < 0.0f ? th : 1.0f);
+        float sn = F.yH[gn] > 0.0f ? th : (F.yH[gn] < 0.0f ? thN : 1.0f);
+        float FHw = F.xH[fw] * sw, FHe = F.xH[fe] * se, GHs = F.yH[gs] * ss, GHn = F.yH[gn] * sn;
+        float Fxw = F.xn[fw] * sw, Fxe = F.xn[fe] * se, Gxs = F.yt[gs] * ss, Gxn = F.yt[gn] * sn;
+        float Fyw = F.xt[fw] * sw, Fye = F.xt[fe] * se, Gys = F.yn[gs] * ss, Gyn = F.yn[gn] * sn;
+        float H = S.H[c], qx = S.qx[c], qy = S.qy[c], b = S.b[c];
+        float QLx = H > 0.0f ? L.QLx[c] : qx;
+        float QLy = H > 0.0f ? L.QLy[c] : qy;
+        float r = dt * P.inv_dx;
+        float src = P.srcw ? P.srcw[c] * (float)ctrl->qmid[k & 1] : 0.0f;
+        float Hn = H - r * ((FHe - FHw) + (GHn - GHs)) + dt * src;
+        float qxn = QLx - r * ((Fxe - Fxw) + (Gxn - Gxs));
+        float qyn = QLy - r * ((Fye - Fyw) + (Gyn - Gys));
+        float om = 1.0f - soil(P.psi, P.psi_s, c);
+        float bn = b - dt / (om * P.dx) * ((F.xJ[fe] - F.xJ[fw]) + (F.yJ[gn] - F.yJ[gs]));
+        if (P.qb) bn += dt * P.qb[c] / om;
+        if (Hn < 0.0f) Hn = 0.0f;
+        if (Hn < P.eps) {
+            float s = Hn * wdes(Hn, P);
+            qxn *= s;
+            qyn *= s;
+        }
+        O.H[c] = Hn; O.qx[c] = qxn; O.qy[c] = qyn; O.b[c] = bn;
+        // boundary balances (FP64, one accumulator per boundary face)
+        double wdx = dtd * (double)P.dx;
+        if (i == 0) { bnd[j] += wdx * (double)(-FHw); bnd[2 * (P.nx + P.ny) + j] += wdx * (double)(-F.xJ[fw]); }
+        if (i == P.nx - 1) { bnd[P.ny + j] += wdx * (double)FHe; bnd[2 * (P.nx + P.ny) + P.ny + j] += wdx * (double)F.xJ[fe]; }
+        if (j == 0) { bnd[2 * P.ny + i] += wdx * (double)(-GHs); bnd[2 * (P.nx + P.ny) + 2 * P.ny + i] += wdx * (double)(-F.yJ[gs]); }
+        if (j == P.ny - 1) { bnd[2 * P.ny + P.nx + i] += wdx * (double)GHn; bnd[2 * (P.nx + P.ny) + 2 * P.ny + P.nx + i] += wdx * (double)F.yJ[gn]; }
+        cell_maxima(P, Hn, qxn, qyn, bn, c, mv, ms, mD, bad);
+    }
+    block_maxima(mv, ms, mD, bad, ctrl->slot[(k + 1) & 1]);
+}
+
+
+// ---------------------------------------------------------------------------
+// Tiled path: one 256-thread workgroup per TX x TY tile of cells, LDS halo
+// tiles, and the hierarchical grid system of Section 3 (HGS): a dry tile skips
+// the Lagrangian stage; a tile whose own and four neighbour tiles are all dry
+// skips the Euler stage.  A tile is dry when every cell has h = 0 and it holds
+// no inflow or bed-source cell; such a tile provably stays unchanged, so the
+// skip is exact.  The arithmetic per cell and per face is the one of the
+// unfused kernels above (same device functions, same order).
+// ---------------------------------------------------------------------------
+
+constexpr int TX = 64, TY = 8, NT = 256;
+
+// Eq. 7 step from ring `par` of the maxima slots.  Every block computes the
+// same value; block (0,0) publishes it (time ring, balances, error, step
+// counter) and clears the slots the Euler stage of this step fills.
+__device__ bool block_dt(Ctrl *ctrl, int par, const StepArgs &A, double &dt_out)
+{
+    __shared__ double s_dt;
+    __shared__ int s_ok;
+    const int tid = threadIdx.x;
+    const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
+    if (tid < 64) {
+        unsigned a = 0, b = 0, c = 0, bad = 0;
+        if (tid < NSLOT) {
+            a = ctrl->slot[par][tid][0]; b = ctrl->slot[par][tid][1];
+            c = ctrl->slot[par][tid][2]; bad = ctrl->slot[par][tid][3];
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            a = max(a, (unsigned)__shfl_xor((int)a, off));
+            b = max(b, (unsigned)__shfl_xor((int)b, off));
+            c = max(c, (unsigned)__shfl_xor((int)c, off));
+            bad = max(bad, (unsigned)__shfl_xor((int)bad, off));
+        }
+        if (tid == 0) {
+            int ok = ctrl->err == 0;
+            int err = 0;
+            double vp = __uint_as_float(a), vs = __uint_as_float(b), D = __uint_as_float(c);
+            double h = A.dx;
+            double t0 = vp > 0.0 ? h / (2.0 * vp) : INFINITY;
+            double t1 = vs > 0.0 ? h / vs : INFINITY;
+            double t2 = D > 0.0 ? h * h / (2.0 * D) : INFINITY;
+            double m = t0;
+            int which = 0;
+            if (t1 < m) { m = t1; which = 1; }
+            if (t2 < m) { m = t2; which = 2; }
+            double dt = A.cfl * m;
+            if (!(dt < A.dt_max)) { dt = A.dt_max; which = 3; }
+            if (bad) err = SW_ERR_NONFINITE;
+            else if (A.mode_fixed && A.dt_fixed > dt) err = SW_ERR_CFL;
+            if (A.mode_fixed) { dt = A.dt_fixed; which = 4; }
+            if (!err && dt < A.dt_min) err = SW_ERR_DT_UNDERFLOW;
+            if (err) ok = 0;
+            s_ok = ok;
+            s_dt = dt;
+            if (lead && ctrl->err == 0) {
+                const int kd = ctrl->kdev;
+                ctrl->vp = vp; ctrl->vs = vs; ctrl->D = D;
+                if (err) {
+                    ctrl->err = err;
+                    ctrl->err_k = kd;
+                } else {
+                    double tn = ctrl->t[par];
+                    double q = 0.0;
+                    if (A.has_inflow) {
+                        double d = tn + 0.5 * dt - A.t_peak;
+                        double pk = A.t_sigma > 0.0
+                                        ? A.q_peak * exp(-d * d / (2.0 * A.t_sigma * A.t_sigma))
+                                        : 0.0;
+                        q = A.q_base + pk;
+                        ctrl->in_w += dt * q;
+                    }
+                    ctrl->in_s += dt * A.qb_total;
+                    ctrl->qmid[par] = q;
+                    ctrl->dt[par] = dt;
+                    ctrl->t[par ^ 1] = tn + dt;
+                    ctrl->last_dt = dt;
+                    ctrl->binding = which;
+                    ctrl->kdev = kd + 1;
+                }
+            }
+        }
+        if (lead && tid < NSLOT * 4) (&ctrl->slot[par ^ 1][0][0])[tid] = 0u;
+    }
+    __syncthreads();
+    dt_out = s_dt;
+    return s_ok != 0;
+}
+
+// Initial maxima (ring par) and wet-tile flags of a state set from the host.
+__global__ void __launch_bounds__(NT) k_prepare_t(KPar P, Ctrl *ctrl, int par, StateView S,
+                                                  uint8_t *__restrict__ act,
+                                                  const uint8_t *__restrict__ force)
+{
+    __shared__ int s_any;
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    if (tid == 0) s_any = 0;
+    __syncthreads();
+    unsigned mv = 0, ms = 0, mD = 0, bad = 0;
+    for (int q = tid; q < TX * TY; q += NT) {
+        int i = x0 + q % TX, j = y0 + q / TX;
+        if (i >= P.nx || j >= P.ny) continue;
+        int c = j * P.pitch + i;
+        float H = S.H[c];
+        cell_maxima(P, H, S.qx[c], S.qy[c], S.b[c], c, mv, ms, mD, bad);
+        if (H > 0.0f) s_any = 1;
+    }
+    block_maxima(mv, ms, mD, bad, ctrl->slot[par]);
+    int tile = blockIdx.x + blockIdx.y * gridDim.x;
+    if (tid == 0) act[tile] = (s_any || force[tile]) ? 1 : 0;
+}
+
+// Lagrangian stage on a tile (K2, K4, K5, K6) with the Eq. 7 step (K3).
+constexpr int LW = TX + 4, LHh = TY + 4;  // state tile with a 2-cell halo
+
+__global__ void __launch_bounds__(NT) k_lagrange_t(KPar P, Ctrl *ctrl, int par, StepArgs A,
+                                                   StateView S, float *__restrict__ QLx,
+                                                   float *__restrict__ QLy,
+                                                   const uint8_t *__restrict__ act, int hgs)
+{
+    __shared__ float sH[LHh][LW], sb[LHh][LW], sqx[LHh][LW], sqy[LHh][LW], su[LHh][LW],
+        sv[LHh][LW];
+    __shared__ float sHh[TY + 2][TX + 2];
+    double dtd;
+    if (!block_dt(ctrl, par, A, dtd)) return;
+    const int tile = blockIdx.x + blockIdx.y * gridDim.x;
+    if (hgs && !act[tile]) return;
+    const float dt = (float)dtd;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, tid = threadIdx.x;
+    for (int q = tid; q < LW * LHh; q += NT) {
+        int rx = q % LW, ry = q / LW;
+        int i = x0 - 2 + rx, j = y0 - 2 + ry;
+        float H = 0.0f, qx = 0.0f, qy = 0.0f, b = 0.0f, u = 0.0f, v = 0.0f;
+        if ((unsigned)i < (unsigned)P.nx && (unsigned)j < (unsigned)P.ny) {
+            int c = j * P.pitch + i;
+            H = S.H[c]; qx = S.qx[c]; qy = S.qy[c]; b = S.b[c];
+            float w = wdes(H, P);
+            u = qx * w;
+            v = qy * w;
+        }
+        sH[ry][rx] = H; sb[ry][rx] = b; sqx[ry][rx] = qx; sqy[ry][rx] = qy; su[ry][rx] = u;
+        sv[ry][rx] = v;
+    }
+    __syncthreads();
+    const float hdt_dx = dt / (2.0f * P.dx);
+    for (int q = tid; q < (TX + 2) * (TY + 2); q += NT) {
+        int cx = q % (TX + 2), cy = q / (TX + 2);
+        int i = x0 - 1 + cx, j = y0 - 1 + cy;
+        float Hh = 0.0f;
+        if ((unsigned)i < (unsigned)P.nx && (unsigned)j < (unsigned)P.ny) {
+            int rx = cx + 1, ry = cy + 1;
+            float uc = su[ry][rx], vc = sv[ry][rx];
+            float ue, uw, vn, vs;
+            if (i + 1 < P.nx) ue = 0.5f * (uc + su[ry][rx + 1]);
+            else ue = (P.bcE == kWall) ? 0.0f : uc;
+            if (i > 0) uw = 0.5f * (su[ry][rx - 1] + uc);
+            else uw = (P.bcW == kWall) ? 0.0f : uc;
+            if (j + 1 < P.ny) vn = 0.5f * (vc + sv[ry + 1][rx]);
+            else vn = (P.bcN == kWall) ? 0.0f : vc;
+            if (j > 0) vs = 0.5f * (sv[ry - 1][rx] + vc);
+            else vs = (P.bcS == kWall) ? 0.0f : vc;
+            float Jx = 1.0f + hdt_dx * (ue - uw);
+            float Jy = 1.0f + hdt_dx * (vn - vs);
+            Hh = sH[ry][rx] / (Jx * Jy);
+        }
+        sHh[cy][cx] = Hh;
+    }
+    __syncthreads();
+    for (int q = tid; q < TX * TY; q += NT) {
+        int lx = q % TX, ly = q / TX;
+        int i = x0 + lx, j = y0 + ly;
+        if (i >= P.nx || j >= P.ny) continue;
+        int rx = lx + 2, ry = ly + 2, cx = lx + 1, cy = ly + 1;
+        bool hasW = i > 0, hasE = i + 1 < P.nx, hasS = j > 0, hasN = j + 1 < P.ny;
+        float Hc = sH[ry][rx], bc = sb[ry][rx];
+        float bW = sb[ry][rx - 1], bE = sb[ry][rx + 1], bS = sb[ry - 1][rx], bN = sb[ry + 1][rx];
+        float Snx = face_force(P, sH[ry][rx - 1], bW, Hc, bc, sH[ry][rx + 1], bE, hasW, hasE);
+        float Sny = face_force(P, sH[ry - 1][rx], bS, Hc, bc, sH[ry + 1][rx], bN, hasS, hasN);
+        float wc = wdes(Hc, P);
+        float qxc = sqx[ry][rx], qyc = sqy[ry][rx];
+        float uc = qxc * wc, vc = qyc * wc;
+        int c = j * P.pitch + i;
+        float nM = soil(P.nM, P.nM_s, c);
+        float gam = friction_rate(P, nM, sqrtf(uc * uc + vc * vc), Hc);
+        float hdt = 0.5f * dt;
+        float qpx = (qxc + hdt * Snx) / (1.0f + hdt * gam);
+        float qpy = (qyc + hdt * Sny) / (1.0f + hdt * gam);
+        float upx = qpx * wc, upy = qpy * wc;
+        float Hh = sHh[cy][cx];
+        float HhW = hasW ? sHh[cy][cx - 1] : Hh, HhE = hasE ? sHh[cy][cx + 1] : Hh;
+        float HhS = hasS ? sHh[cy - 1][cx] : Hh, HhN = hasN ? sHh[cy + 1][cx] : Hh;
+        float Shx = face_force(P, HhW, bW, Hh, bc, HhE, bE, hasW, hasE);
+        float Shy = face_force(P, HhS, bS, Hh, bc, HhN, bN, hasS, hasN);
+        float gamh = friction_rate(P, nM, sqrtf(upx * upx + upy * upy), Hh);
+        QLx[c] = (qxc + dt * Shx) / (1.0f + dt * gamh);
+        QLy[c] = (qyc + dt * Shy) / (1.0f + dt * gamh);
+    }
+}
+
+// Euler stage on a tile (K7 + limiter + K8) with the epilogue reductions
+// (Eq. 7 maxima and wet flags of the new state, FP64 boundary balances).
+constexpr int EW = TX + 6, EHt = TY + 6;  // remap inputs with a 3-cell halo
+constexpr int RW = TX + 2, RH = TY + 2;   // the tile plus a 1-cell ring
+
+__global__ void __launch_bounds__(NT) k_euler_t(KPar P, Ctrl *ctrl, int par, StateView S,
+                                                LagView L, OutView O, double *__restrict__ bnd,
+                                                const uint8_t *__restrict__ act_in,
+                                                uint8_t *__restrict__ act_out,
+                                                uint8_t *__restrict__ synced,
+                                                const uint8_t *__restrict__ force, int hgs)
+{
+    __shared__ float cz[EHt][EW], ch[EHt][EW], cux[EHt][EW], cuy[EHt][EW], cLx[EHt][EW],
+        cLy[EHt][EW];
+    __shared__ float rjx[RH][RW], rjy[RH][RW], rb[RH][RW], rth[RH][RW];
+    __shared__ float fxH[RH][TX + 3], fxn[RH][TX + 3], fxt[RH][TX + 3];
+    __shared__ float fyH[TY + 3][RW], fyn[TY + 3][RW], fyt[TY + 3][RW];
+    __shared__ int s_flag;
+    if (ctrl->err) return;
+    const int ntx = gridDim.x, nty = gridDim.y;
+    const int bx = blockIdx.x, by = blockIdx.y, tile = bx + by * ntx, tid = threadIdx.x;
+    const int x0 = bx * TX, y0 = by * TY;
+    const int nx = P.nx, ny = P.ny;
+    if (hgs) {
+        bool run = act_in[tile] || (bx > 0 && act_in[tile - 1]) ||
+                   (bx + 1 < ntx && act_in[tile + 1]) || (by > 0 && act_in[tile - ntx]) ||
+                   (by + 1 < nty && act_in[tile + ntx]);
+        if (!run) {
+            if (tid == 0) s_flag = synced[tile];
+            __syncthreads();
+            if (!s_flag) {  // first skip since the tile last changed: bring the other buffer level
+                for (int q = tid; q < TX * TY; q += NT) {
+                    int i = x0 + q % TX, j = y0 + q / TX;
+                    if (i >= nx || j >= ny) continue;
+                    int c = j * P.pitch + i;
+                    O.H[c] = S.H[c]; O.qx[c] = S.qx[c]; O.qy[c] = S.qy[c]; O.b[c] = S.b[c];
+                }
+            }
+            if (tid == 0) {
+                synced[tile] = 1;
+                act_out[tile] = 0;
+            }
+            return;
+        }
+        if (tid == 0) synced[tile] = 0;
+    }
+    const float dt = (float)ctrl->dt[par];
+    const double dtd = ctrl->dt[par];
+    const bool wW = P.bcW == kWall, wE = P.bcE == kWall, wS = P.bcS == kWall, wN = P.bcN == kWall;
+
+    // remap inputs of every cell within 3 of the tile (ghost cells beyond the domain edge)
+    for (int q = tid; q < EW * EHt; q += NT) {
+        int rx = q % EW, ry = q / EW;
+        int i = x0 - 3 + rx, j = y0 - 3 + ry;
+        bool inx = (unsigned)i < (unsigned)nx, iny = (unsigned)j < (unsigned)ny;
+        CellVals v{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (inx && iny) {
+            int c = j * P.pitch + i;
+            float H = S.H[c], qx = S.qx[c], qy = S.qy[c], b = S.b[c];
+            v = cell_vals(P, H, qx, qy, b, L.QLx[c], L.QLy[c]);
+            int cx = rx - 2, cy = ry - 2;
+            if ((unsigned)cx < (unsigned)RW && (unsigned)cy < (unsigned)RH) {
+                float w = wdes(H, P);
+                float jx, jy;
+                bedload(P, H, qx * w, qy * w, soil(P.nM, P.nM_s, c), soil(P.d50, P.d50_s, c), jx,
+                        jy);
+                rjx[cy][cx] = jx;
+                rjy[cy][cx] = jy;
+                rb[cy][cx] = b;
+            }
+        } else if (iny && (i == -1 || i == nx)) {
+            int c = j * P.pitch + (i < 0 ? 0 : nx - 1);
+            v = mirror(cell_vals(P, S.H[c], S.qx[c], S.qy[c], S.b[c], L.QLx[c], L.QLy[c]), 0,
+                       i < 0 ? wW : wE);
+        } else if (inx && (j == -1 || j == ny)) {
+            int c = (j < 0 ? 0 : ny - 1) * P.pitch + i;
+            v = mirror(cell_vals(P, S.H[c], S.qx[c], S.qy[c], S.b[c], L.QLx[c], L.QLy[c]), 1,
+                       j < 0 ? wS : wN);
+        }
+        cz[ry][rx] = v.z; ch[ry][rx] = v.h; cux[ry][rx] = v.utx; cuy[ry][rx] = v.uty;
+        cLx[ry][rx] = v.uLx; cLy[ry][rx] = v.uLy;
+    }
+    __syncthreads();
+
+    // raw water fluxes of every face of the tile and its ring
+    auto cq = [&](int ry, int rx, int dir) -> CellQ {
+        CellVals v{cz[ry][rx], ch[ry][rx], cux[ry][rx], cuy[ry][rx], cLx[ry][rx], cLy[ry][rx]};
+        return along(v, dir);
+    };
+    for (int q = tid; q < RH * (TX + 3); q += NT) {
+        int kk = q % (TX + 3), fr = q / (TX + 3);
+        int k = x0 - 1 + kk, j = y0 - 1 + fr;
+        float fH = 0.0f, fn = 0.0f, ft = 0.0f;
+        if ((unsigned)j < (unsigned)ny && k >= 0 && k <= nx) {
+            int ry = fr + 2;
+            water_flux(P, k, nx, wW, wE, cq(ry, kk, 0), cq(ry, kk + 1, 0), cq(ry, kk + 2, 0),
+                       cq(ry, kk + 3, 0), fH, fn, ft);
+        }
+        fxH[fr][kk] = fH; fxn[fr][kk] = fn; fxt[fr][kk] = ft;
+    }
+    for (int q = tid; q < (TY + 3) * RW; q += NT) {
+        int cxk = q % RW, kk = q / RW;
+        int i = x0 - 1 + cxk, k = y0 - 1 + kk;
+        float fH = 0.0f, fn = 0.0f, ft = 0.0f;
+        if ((unsigned)i < (unsigned)nx && k >= 0 && k <= ny) {
+            int rx = cxk + 2;
+            water_flux(P, k, ny, wS, wN, cq(kk, rx, 1), cq(kk + 1, rx, 1), cq(kk + 2, rx, 1),
+                       cq(kk + 3, rx, 1), fH, fn, ft);
+        }
+        fyH[kk][cxk] = fH; fyn[kk][cxk] = fn; fyt[kk][cxk] = ft;
+    }
+    __syncthreads();
+
+    // draining limiter of the tile and its ring (ghost donors: 1)
+    for (int q = tid; q < RW * RH; q += NT) {
+        int cx = q % RW, cy = q / RW;
+        int i = x0 - 1 + cx, j = y0 - 1 + cy;
+        float th = 1.0f;
+        if ((unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny) {
+            float fe = fxH[cy][cx + 1], fw = fxH[cy][cx], gn = fyH[cy + 1][cx], gs = fyH[cy][cx];
+            float out = fmaxf(0.0f, fe) + fmaxf(0.0f, -fw) + fmaxf(0.0f, gn) + fmaxf(0.0f, -gs);
+            th = out > 0.0f ? fminf(1.0f, ch[cy + 2][cx + 2] * P.dx / (dt * out)) : 1.0f;
+        }
+        rth[cy][cx] = th;
+    }
+    if (tid == 0) s_flag = 0;
+    __syncthreads();
+
+    // update of the tile's own cells
+    unsigned mv = 0, ms = 0, mD = 0, bad = 0;
+    for (int q = tid; q < TX * TY; q += NT) {
+        int lx = q % TX, ly = q / TX;
+        int i = x0 + lx, j = y0 + ly;
+        if (i >= nx || j >= ny) continue;
+        int cx = lx + 1, cy = ly + 1, c = j * P.pitch + i;
+        float th = rth[cy][cx];
+        float thW = rth[cy][cx - 1], thE = rth[cy][cx + 1], thS = rth[cy - 1][cx], thN = rth[cy + 1][cx];
+        float rFw = fxH[cy][cx], rFe = fxH[cy][cx + 1], rGs = fyH[cy][cx], rGn = fyH[cy + 1][cx];
+        float sw = rFw > 0.0f ? thW : (rFw < 0.0f ? th : 1.0f);
+        float se = rFe > 0.0f ? th : (rFe < 0.0f ? thE : 1.0f);
+        float ss = rGs > 0.0f ? thS : (rGs < 0.0f ? th : 1.0f);
+        float sn = rGn > 0.0f ? th : (rGn < 0.0f ? thN : 1.0f);
+        float FHw = rFw * sw, FHe = rFe * se, GHs = rGs * ss, GHn = rGn * sn;
+        float Fxw = fxn[cy][cx] * sw, Fxe = fxn[cy][cx + 1] * se;
+        float Gxs = fyt[cy][cx] * ss, Gxn = fyt[cy + 1][cx] * sn;
+        float Fyw = fxt[cy][cx] * sw, Fye = fxt[cy][cx + 1] * se;
+        float Gys = fyn[cy][cx] * ss, Gyn = fyn[cy + 1][cx] * sn;
+        float Jw = sed_flux(P, i, nx, wW, wE, 0, rjx[cy][cx - 1], rjy[cy][cx - 1], rb[cy][cx - 1],
+                            rjx[cy][cx], rjy[cy][cx], rb[cy][cx]);
+        float Je = sed_flux(P, i + 1, nx, wW, wE, 0, rjx[cy][cx], rjy[cy][cx], rb[cy][cx],
+                            rjx[cy][cx + 1], rjy[cy][cx + 1], rb[cy][cx + 1]);
+        float Js = sed_flux(P, j, ny, wS, wN, 1, rjx[cy - 1][cx], rjy[cy - 1][cx], rb[cy - 1][cx],
+                            rjx[cy][cx], rjy[cy][cx], rb[cy][cx]);
+        float Jn = sed_flux(P, j + 1, ny, wS, wN, 1, rjx[cy][cx], rjy[cy][cx], rb[cy][cx],
+                            rjx[cy + 1][cx], rjy[cy + 1][cx], rb[cy + 1][cx]);
+        float H = S.H[c], qx = S.qx[c], qy = S.qy[c], b = S.b[c];
+        float QLxc = H > 0.0f ? L.QLx[c] : qx;
+        float QLyc = H > 0.0f ? L.QLy[c] : qy;
+        float r = dt * P.inv_dx;
+        float src = P.srcw ? P.srcw[c] * (float)ctrl->qmid[par] : 0.0f;
+        float Hn = H - r * ((FHe - FHw) + (GHn - GHs)) + dt * src;
+        float qxn = QLxc - r * ((Fxe - Fxw) + (Gxn - Gxs));
+        float qyn = QLyc - r * ((Fye - Fyw) + (Gyn - Gys));
+        float om = 1.0f - soil(P.psi, P.psi_s, c);
+        float bn = b - dt / (om * P.dx) * ((Je - Jw) + (Jn - Js));
+        if (P.qb) bn += dt * P.qb[c] / om;
+        if (Hn < 0.0f) Hn = 0.0f;
+        if (Hn < P.eps) {
+            float sc = Hn * wdes(Hn, P);
+            qxn *= sc;
+            qyn *= sc;
+        }
+        O.H[c] = Hn; O.qx[c] = qxn; O.qy[c] = qyn; O.b[c] = bn;
+        double wdx = dtd * (double)P.dx;
+        const int nb = 2 * (nx + ny);
+        if (i == 0) { bnd[j] += wdx * (double)(-FHw); bnd[nb + j] += wdx * (double)(-Jw); }
+        if (i == nx - 1) { bnd[ny + j] += wdx * (double)FHe; bnd[nb + ny + j] += wdx * (double)Je; }
+        if (j == 0) { bnd[2 * ny + i] += wdx * (double)(-GHs); bnd[nb + 2 * ny + i] += wdx * (double)(-Js); }
+        if (j == ny - 1) { bnd[2 * ny + nx + i] += wdx * (double)GHn; bnd[nb + 2 * ny + nx + i] += wdx * (double)Jn; }
+        cell_maxima(P, Hn, qxn, qyn, bn, c, mv, ms, mD, bad);
+        if (Hn > 0.0f) s_flag = 1;
+    }
+    block_maxima(mv, ms, mD, bad, ctrl->slot[par ^ 1]);
+    if (tid == 0) act_out[tile] = (s_flag || force[tile]) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 sums: water volume, sediment volume, wet cells (two fixed-order passes).
+// ---------------------------------------------------------------------------
+
+constexpr int SUM_THREADS = 256;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+    return v;
+}
+
+__global__ void __launch_bounds__(SUM_THREADS) k_sums1(KPar P, const float *__restrict__ H,
+                                                       const float *__restrict__ b,
+                                                       double *__restrict__ part, int rows_per_block)
+{
+    __shared__ double sh[3][SUM_THREADS / 64];
+    double sw = 0.0, ss = 0.0, wet = 0.0;
+    int j0 = blockIdx.x * rows_per_block, j1 = min(P.ny, j0 + rows_per_block);
+    for (int j = j0; j < j1; ++j)
+        for (int i = threadIdx.x; i < P.nx; i += SUM_THREADS) {
+            int c = j * P.pitch + i;
+            float h = H[c];
+            sw += (double)h;
+            ss += (1.0 - (double)soil(P.psi, P.psi_s, c)) * (double)b[c];
+            wet += h > 0.0f ? 1.0 : 0.0;
+        }
+    sw = wave_sum(sw); ss = wave_sum(ss); wet = wave_sum(wet);
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { sh[0][w] = sw; sh[1][w] = ss; sh[2][w] = wet; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < SUM_THREADS / 64; ++k) { sw += sh[0][k]; ss += sh[1][k]; wet += sh[2][k]; }
+        part[3 * blockIdx.x + 0] = sw;
+        part[3 * blockIdx.x + 1] = ss;
+        part[3 * blockIdx.x + 2] = wet;
+    }
+}
+
+// Sum of npart partial triples and of the boundary accumulators, in a fixed order.
+__global__ void __launch_bounds__(SUM_THREADS) k_sums2(const double *__restrict__ part, int npart,
+                                                       const double *__restrict__ bnd, int nb,
+                                                       double *__restrict__ out)
+{
+    __shared__ double sh[5][SUM_THREADS / 64];
+    double a = 0, b = 0, c = 0, d = 0, e = 0;
+    for (int k = threadIdx.x; k < npart; k += SUM_THREADS) {
+        a += part[3 * k]; b += part[3 * k + 1]; c += part[3 * k + 2];
+    }
+    for (int k = threadIdx.x; k < nb; k += SUM_THREADS) { d += bnd[k]; e += bnd[nb + k]; }
+    a = wave_sum(a); b = wave_sum(b); c = wave_sum(c); d = wave_sum(d); e = wave_sum(e);
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { sh[0][w] = a; sh[1][w] = b; sh[2][w] = c; sh[3][w] = d; sh[4][w] = e; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < SUM_THREADS / 64; ++k) { a += sh[0][k]; b += sh[1][k]; c += sh[2][k]; d += sh[3][k]; e += sh[4][k]; }
+        out[0] = a; out[1] = b; out[2] = c; out[3] = d; out[4] = e;
+    }
+}
+
+// Copy a row-major [ny][nx] plane into a pitched plane (or back).
+__global__ void k_pitch(const float *__restrict__ src, int sp, float *__restrict__ dst, int dp,
+                        int nx, int ny, int zero_mode)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i < nx && j < ny) dst[j * dp + i] = src ? src[j * sp + i] : 0.0f;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+
+struct sw_ctx {
+    sw_grid grid{};
+    sw_params par{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int nx = 0, ny = 0, pitch = 0;
+    size_t plane = 0;                // floats per pitched plane
+    float *buf = nullptr;            // all pitched planes in one allocation
+    float *H[2]{}, *qx[2]{}, *qy[2]{}, *b[2]{};
+    float *QLx = nullptr, *QLy = nullptr;
+    float *nM = nullptr, *d50 = nullptr, *psi = nullptr, *qb = nullptr, *srcw = nullptr;
+    float nM_s = 0.0f, d50_s = 5e-4f, psi_s = 0.4f;
+    float *faces = nullptr;          // unfused face arrays
+    double *bnd = nullptr;           // boundary accumulators: water [2(nx+ny)], sediment [2(nx+ny)]
+    double *part = nullptr;          // sum partials
+    double *sums = nullptr;          // sum results (device)
+    Ctrl *ctrl = nullptr;
+    int64_t k = 0;                   // steps since the state was set
+    int64_t step0 = 0;               // step counter offset (sw_set_time)
+    double t0 = 0.0;                 // time at k = 0
+    bool have_state = false, dirty = true;
+    int has_inflow = 0;
+    double q_base = 0, q_peak = 0, t_peak = 0, t_sigma = 1;
+    double qb_total = 0.0;
+    int nsum_blocks = 0, sum_rows = 1;
+    int ntx = 0, nty = 0;            // tile grid of the tiled kernels
+    uint8_t *tflags = nullptr;       // act[2][ntiles], synced[ntiles], force[ntiles]
+    hipStream_t cap = nullptr;       // private stream used only to capture graphs
+    hipGraphExec_t gexec = nullptr;  // two tiled steps (even k, then odd k)
+    bool graph_ok = false;
+    std::vector<uint8_t> force_in, force_qb;  // tiles holding inflow / bed-source cells
+    int graph_fixed = 0;
+    double graph_dt = 0.0;
+    std::string err;
+};
+
+namespace {
+
+int fail(sw_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                              \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail((ctx), SW_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+KPar make_kpar(const sw_ctx *c)
+{
+    KPar P{};
+    P.nx = c->nx; P.ny = c->ny; P.pitch = c->pitch;
+    P.bcW = c->grid.bc[0]; P.bcE = c->grid.bc[1]; P.bcS = c->grid.bc[2]; P.bcN = c->grid.bc[3];
+    P.dx = (float)c->grid.dx;
+    P.inv_dx = (float)(1.0 / c->grid.dx);
+    P.g = (float)c->par.g;
+    P.eps = (float)c->par.eps_dry;
+    P.eps4 = (float)(c->par.eps_dry * c->par.eps_dry * c->par.eps_dry * c->par.eps_dry);
+    P.h_sed = (float)c->par.h_sed;
+    P.s_rel_m1 = (float)(c->par.s_rel - 1.0);
+    P.C_J = (float)c->par.C_J; P.C_Sh = (float)c->par.C_Sh;
+    P.A_G = (float)c->par.A_G; P.m_exp = (float)c->par.m_exp;
+    P.half_g_inv_dx = (float)(c->par.g / (2.0 * c->grid.dx));
+    P.sed_law = c->par.sed_law;
+    P.nM = c->nM; P.nM_s = c->nM_s;
+    P.d50 = c->d50; P.d50_s = c->d50_s;
+    P.psi = c->psi; P.psi_s = c->psi_s;
+    P.qb = c->qb;
+    P.srcw = c->has_inflow ? c->srcw : nullptr;
+    return P;
+}
+
+StepArgs make_step_args(const sw_ctx *c, int fixed, double dt)
+{
+    StepArgs A{};
+    A.mode_fixed = fixed;
+    A.dt_fixed = dt;
+    A.dx = c->grid.dx; A.cfl = c->par.cfl; A.dt_max = c->par.dt_max; A.dt_min = c->par.dt_min;
+    A.has_inflow = c->has_inflow;
+    A.q_base = c->q_base; A.q_peak = c->q_peak; A.t_peak = c->t_peak; A.t_sigma = c->t_sigma;
+    A.qb_total = c->qb_total;
+    return A;
+}
+
+// Copy a user [ny][nx] array (host or device) into a pitched device plane.
+int upload_plane(sw_ctx *c, float *dst, const float *src, int ptr_kind)
+{
+    if (ptr_kind == SW_PTR_HOST) {
+        HIPCHK(c, hipMemcpy2DAsync(dst, c->pitch * sizeof(float), src, c->nx * sizeof(float),
+                                   c->nx * sizeof(float), c->ny, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else if (ptr_kind == SW_PTR_DEVICE) {
+        HIPCHK(c, hipMemcpy2DAsync(dst, c->pitch * sizeof(float), src, c->nx * sizeof(float),
+                                   c->nx * sizeof(float), c->ny, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        return fail(c, SW_ERR_ARG, "ptr_kind must be SW_PTR_HOST or SW_PTR_DEVICE");
+    }
+    return SW_OK;
+}
+
+int download_plane(sw_ctx *c, float *dst, const float *src, int ptr_kind)
+{
+    hipMemcpyKind kind = ptr_kind == SW_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (ptr_kind != SW_PTR_HOST && ptr_kind != SW_PTR_DEVICE)
+        return fail(c, SW_ERR_ARG, "ptr_kind must be SW_PTR_HOST or SW_PTR_DEVICE");
+    HIPCHK(c, hipMemcpy2DAsync(dst, c->nx * sizeof(float), src, c->pitch * sizeof(float),
+                               c->nx * sizeof(float), c->ny, kind, c->stream));
+    return SW_OK;
+}
+
+dim3 cell_grid(const sw_ctx *c) { return dim3((c->nx + BX - 1) / BX, (c->ny + BY - 1) / BY); }
+
+size_t ntiles(const sw_ctx *c) { return (size_t)c->ntx * c->nty; }
+uint8_t *act_flags(const sw_ctx *c, int par) { return c->tflags + par * ntiles(c); }
+uint8_t *synced_flags(const sw_ctx *c) { return c->tflags + 2 * ntiles(c); }
+uint8_t *force_flags(const sw_ctx *c) { return c->tflags + 3 * ntiles(c); }
+
+// Tiles that must never be skipped: they hold inflow or bed-source cells.
+int upload_force(sw_ctx *c)
+{
+    size_t nt = ntiles(c);
+    std::vector<uint8_t> f(nt, 0);
+    for (size_t t = 0; t < nt; ++t)
+        f[t] = (uint8_t)((c->force_in.size() == nt && c->force_in[t]) ||
+                         (c->force_qb.size() == nt && c->force_qb[t]));
+    HIPCHK(c, hipMemcpy(force_flags(c), f.data(), nt, hipMemcpyHostToDevice));
+    return SW_OK;
+}
+
+size_t tile_of(const sw_ctx *c, int i, int j) { return (size_t)(j / TY) * c->ntx + (size_t)(i / TX); }
+
+// Recompute the Eq. 7 maxima and the wet-tile flags of the current state
+// (after any set_*), and mark every tile's two buffers as possibly different.
+int prepare(sw_ctx *c)
+{
+    int cur = (int)(c->k & 1);
+    HIPCHK(c, hipMemsetAsync(c->ctrl->slot[cur], 0, sizeof(c->ctrl->slot[0]), c->stream));
+    HIPCHK(c, hipMemsetAsync(synced_flags(c), 0, ntiles(c), c->stream));
+    KPar P = make_kpar(c);
+    StateView S{c->H[cur], c->qx[cur], c->qy[cur], c->b[cur]};
+    hipLaunchKernelGGL(k_prepare_t, dim3(c->ntx, c->nty), dim3(NT), 0, c->stream, P, c->ctrl, cur,
+                       S, act_flags(c, cur), (const uint8_t *)force_flags(c));
+    HIPCHK(c, hipGetLastError());
+    c->dirty = false;
+    c->graph_ok = false;
+    return SW_OK;
+}
+
+int read_ctrl(sw_ctx *c, Ctrl *h)
+{
+    HIPCHK(c, hipMemcpyAsync(h, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SW_OK;
+}
+
+// Index of the buffer holding the current state (the start of the failing
+// step if the device raised an error).
+int current_buffer(sw_ctx *c, const Ctrl &h) { return h.err ? (h.err_k & 1) : (int)(c->k & 1); }
+
+void enqueue_tiled_step(sw_ctx *c, hipStream_t st, int par, const KPar &P, const StepArgs &A)
+{
+    const int hgs = (c->par.flags & SW_FLAG_HGS) ? 1 : 0;
+    StateView S{c->H[par], c->qx[par], c->qy[par], c->b[par]};
+    LagView L{c->QLx, c->QLy};
+    OutView O{c->H[par ^ 1], c->qx[par ^ 1], c->qy[par ^ 1], c->b[par ^ 1]};
+    dim3 grid(c->ntx, c->nty), blk(NT);
+    hipLaunchKernelGGL(k_lagrange_t, grid, blk, 0, st, P, c->ctrl, par, A, S, c->QLx, c->QLy,
+                       (const uint8_t *)act_flags(c, par), hgs);
+    hipLaunchKernelGGL(k_euler_t, grid, blk, 0, st, P, c->ctrl, par, S, L, O, c->bnd,
+                       (const uint8_t *)act_flags(c, par), act_flags(c, par ^ 1), synced_flags(c),
+                       (const uint8_t *)force_flags(c), hgs);
+}
+
+void enqueue_unfused_step(sw_ctx *c, int par, const KPar &P, const StepArgs &A)
+{
+    dim3 g = cell_grid(c), blk(BX, BY);
+    dim3 gf((c->nx + 1 + BX - 1) / BX, (c->ny + 1 + BY - 1) / BY);
+    size_t nfx = (size_t)(c->nx + 1) * c->ny, nfy = (size_t)c->nx * (c->ny + 1);
+    FaceView F;
+    F.xH = c->faces; F.xn = F.xH + nfx; F.xt = F.xn + nfx; F.xJ = F.xt + nfx;
+    F.yH = F.xJ + nfx; F.yn = F.yH + nfy; F.yt = F.yn + nfy; F.yJ = F.yt + nfy;
+    StateView S{c->H[par], c->qx[par], c->qy[par], c->b[par]};
+    LagView L{c->QLx, c->QLy};
+    OutView O{c->H[par ^ 1], c->qx[par ^ 1], c->qy[par ^ 1], c->b[par ^ 1]};
+    hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, c->stream, c->ctrl, par, A);
+    hipLaunchKernelGGL(k_lagrange, g, blk, 0, c->stream, P, c->ctrl, par, S, c->QLx, c->QLy);
+    hipLaunchKernelGGL(k_faces, gf, blk, 0, c->stream, P, c->ctrl, S, L, F);
+    hipLaunchKernelGGL(k_update, g, blk, 0, c->stream, P, c->ctrl, par, S, L, F, O, c->bnd);
+}
+
+// Capture the two-step graph (even step, then odd step) for the current inputs.
+int ensure_graph(sw_ctx *c, const KPar &P, const StepArgs &A)
+{
+    if (c->graph_ok && c->graph_fixed == A.mode_fixed && c->graph_dt == A.dt_fixed) return SW_OK;
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    enqueue_tiled_step(c, c->cap, 0, P, A);
+    enqueue_tiled_step(c, c->cap, 1, P, A);
+    HIPCHK(c, hipStreamEndCapture(c->cap, &g));
+    hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(c, SW_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    c->graph_ok = true;
+    c->graph_fixed = A.mode_fixed;
+    c->graph_dt = A.dt_fixed;
+    return SW_OK;
+}
+
+int launch_steps(sw_ctx *c, int32_t nsteps, int fixed, double dt)
+{
+    if (!c) return SW_ERR_ARG;
+    if (nsteps < 0) return fail(c, SW_ERR_ARG, "nsteps must be >= 0");
+    if (!c->have_state) return fail(c, SW_ERR_STATE, "advance before sw_set_state");
+    if (fixed && !(dt > 0.0)) return fail(c, SW_ERR_ARG, "fixed dt must be > 0");
+    if (c->dirty) {
+        int rc = prepare(c);
+        if (rc) return rc;
+    }
+    KPar P = make_kpar(c);
+    StepArgs A = make_step_args(c, fixed, dt);
+    if (c->par.flags & SW_FLAG_UNFUSED) {
+        for (int32_t s = 0; s < nsteps; ++s) {
+            enqueue_unfused_step(c, (int)(c->k & 1), P, A);
+            HIPCHK(c, hipGetLastError());
+            c->k++;
+        }
+        return SW_OK;
+    }
+    const bool use_graph = !(c->par.flags & SW_FLAG_NO_GRAPH);
+    int32_t left = nsteps;
+    if (left > 0 && (c->k & 1)) {  // align to an even step for the two-step graph
+        enqueue_tiled_step(c, c->stream, 1, P, A);
+        HIPCHK(c, hipGetLastError());
+        c->k++;
+        left--;
+    }
+    if (use_graph && left >= 2) {
+        int rc = ensure_graph(c, P, A);
+        if (rc) return rc;
+        for (; left >= 2; left -= 2) {
+            HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+            c->k += 2;
+        }
+    }
+    for (; left > 0; --left) {
+        enqueue_tiled_step(c, c->stream, (int)(c->k & 1), P, A);
+        HIPCHK(c, hipGetLastError());
+        c->k++;
+    }
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sw_default_params(sw_params *p)
+{
+    if (!p) return;
+    p->g = 9.81;
+    p->cfl = 0.3;
+    p->eps_dry = 1e-5;
+    p->h_sed = 1e-2;
+    p->dt_max = 1.0;
+    p->dt_min = 1e-9;
+    p->s_rel = 2.65;
+    p->C_J = 2.0;
+    p->C_Sh = 5.0;
+    p->A_G = 1e-3;
+    p->m_exp = 2.0;
+    p->sed_law = SW_SED_EQ4;
+    p->flags = SW_FLAG_HGS;
+}
+
+int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw_ctx **out)
+{
+    if (!grid || !params || !out) return SW_ERR_ARG;
+    *out = nullptr;
+    if (grid->nx < 1 || grid->ny < 1 || !(grid->dx > 0.0)) return SW_ERR_ARG;
+    if ((int64_t)grid->nx * grid->ny > (int64_t)1 << 31) return SW_ERR_ARG;
+    for (int s = 0; s < 4; ++s)
+        if (grid->bc[s] != SW_BC_WALL && grid->bc[s] != SW_BC_OPEN) return SW_ERR_ARG;
+    if (params->sed_law < SW_SED_NONE || params->sed_law > SW_SED_EQ4) return SW_ERR_ARG;
+    if (!(params->cfl > 0.0) || !(params->g > 0.0) || !(params->eps_dry > 0.0)) return SW_ERR_ARG;
+    sw_ctx *c = new sw_ctx();
+    c->grid = *grid;
+    c->par = *params;
+    c->nx = grid->nx;
+    c->ny = grid->ny;
+    c->pitch = (grid->nx + 63) / 64 * 64;
+    c->plane = (size_t)c->pitch * c->ny;
+    auto bail = [&](hipError_t e, const char *what) {
+        std::string m = std::string(what) + ": " + hipGetErrorString(e);
+        sw_destroy(c);
+        fprintf(stderr, "sw_create: %s\n", m.c_str());
+        return SW_ERR_HIP;
+    };
+    hipError_t e;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess)
+            return bail(e, "hipStreamCreate");
+        c->own_stream = true;
+    }
+    // planes: 2 x (H, qx, qy, b), QLx, QLy
+    const int nplanes = 10;
+    if ((e = hipMalloc(&c->buf, nplanes * c->plane * sizeof(float))) != hipSuccess)
+        return bail(e, "hipMalloc(state)");
+    if ((e = hipMemset(c->buf, 0, nplanes * c->plane * sizeof(float))) != hipSuccess)
+        return bail(e, "hipMemset(state)");
+    for (int s = 0; s < 2; ++s) {
+        c->H[s] = c->buf + (4 * s + 0) * c->plane;
+        c->qx[s] = c->buf + (4 * s + 1) * c->plane;
+        c->qy[s] = c->buf + (4 * s + 2) * c->plane;
+        c->b[s] = c->buf + (4 * s + 3) * c->plane;
+    }
+    c->QLx = c->buf + 8 * c->plane;
+    c->QLy = c->buf + 9 * c->plane;
+    size_t nf = 4 * ((size_t)(c->nx + 1) * c->ny + (size_t)c->nx * (c->ny + 1));
+    if ((e = hipMalloc(&c->faces, nf * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc(faces)");
+    if ((e = hipMemset(c->faces, 0, nf * sizeof(float))) != hipSuccess) return bail(e, "hipMemset(faces)");
+    size_t nb = 4 * (size_t)(c->nx + c->ny);
+    if ((e = hipMalloc(&c->bnd, nb * sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(bnd)");
+    if ((e = hipMemset(c->bnd, 0, nb * sizeof(double))) != hipSuccess) return bail(e, "hipMemset(bnd)");
+    c->sum_rows = std::max(1, (int)((c->ny + 1023) / 1024));
+    c->nsum_blocks = (c->ny + c->sum_rows - 1) / c->sum_rows;
+    if ((e = hipMalloc(&c->part, (3 * (size_t)c->nsum_blocks + 8) * sizeof(double))) != hipSuccess)
+        return bail(e, "hipMalloc(part)");
+    c->sums = c->part + 3 * (size_t)c->nsum_blocks;
+    c->ntx = (c->nx + TX - 1) / TX;
+    c->nty = (c->ny + TY - 1) / TY;
+    if ((e = hipMalloc(&c->tflags, 4 * ntiles(c))) != hipSuccess) return bail(e, "hipMalloc(tiles)");
+    if ((e = hipMemset(c->tflags, 0, 4 * ntiles(c))) != hipSuccess) return bail(e, "hipMemset(tiles)");
+    if ((e = hipMalloc(&c->ctrl, sizeof(Ctrl))) != hipSuccess) return bail(e, "hipMalloc(ctrl)");
+    if ((e = hipMemset(c->ctrl, 0, sizeof(Ctrl))) != hipSuccess) return bail(e, "hipMemset(ctrl)");
+    *out = c;
+    return SW_OK;
+}
+
+int sw_destroy(sw_ctx *c)
+{
+    if (!c) return SW_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->buf);
+    (void)hipFree(c->faces);
+    (void)hipFree(c->bnd);
+    (void)hipFree(c->part);
+    (void)hipFree(c->ctrl);
+    (void)hipFree(c->nM);
+    (void)hipFree(c->d50);
+    (void)hipFree(c->psi);
+    (void)hipFree(c->qb);
+    (void)hipFree(c->srcw);
+    (void)hipFree(c->tflags);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return SW_OK;
+}
+
+int sw_set_bed(sw_ctx *c, const float *b, int ptr_kind)
+{
+    if (!c) return SW_ERR_ARG;
+    if (!b) return fail(c, SW_ERR_ARG, "bed pointer is NULL");
+    int cur = (int)(c->k & 1);
+    int rc = upload_plane(c, c->b[cur], b, ptr_kind);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->b[cur ^ 1], c->b[cur], c->plane * sizeof(float),
+                             hipMemcpyDeviceToDevice, c->stream));
+    c->dirty = true;
+    return SW_OK;
+}
+
+static int set_soil_field(sw_ctx *c, float **dst, const float *src, int ptr_kind)
+{
+    if (!src) {
+        (void)hipFree(*dst);
+        *dst = nullptr;
+        return SW_OK;
+    }
+    if (!*dst) {
+        HIPCHK(c, hipMalloc(dst, c->plane * sizeof(float)));
+        HIPCHK(c, hipMemsetAsync(*dst, 0, c->plane * sizeof(float), c->stream));
+    }
+    return upload_plane(c, *dst, src, ptr_kind);
+}
+
+int sw_set_soil(sw_ctx *c, const float *manning, float manning_scalar, const float *d50,
+                float d50_scalar, const float *psi, float psi_scalar, int ptr_kind)
+{
+    if (!c) return SW_ERR_ARG;
+    if (!psi && !(psi_scalar >= 0.0f && psi_scalar < 1.0f))
+        return fail(c, SW_ERR_ARG, "porosity must lie in [0, 1)");
+    if (!d50 && !(d50_scalar > 0.0f)) return fail(c, SW_ERR_ARG, "d50 must be > 0");
+    if (!manning && !(manning_scalar >= 0.0f)) return fail(c, SW_ERR_ARG, "Manning n must be >= 0");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int rc;
+    if ((rc = set_soil_field(c, &c->nM, manning, ptr_kind))) return rc;
+    if ((rc = set_soil_field(c, &c->d50, d50, ptr_kind))) return rc;
+    if ((rc = set_soil_field(c, &c->psi, psi, ptr_kind))) return rc;
+    c->nM_s = manning_scalar;
+    c->d50_s = d50_scalar;
+    c->psi_s = psi_scalar;
+    c->dirty = true;
+    return SW_OK;
+}
+
+int sw_set_state(sw_ctx *c, const float *h, const float *hu, const float *hv, int ptr_kind)
+{
+    if (!c) return SW_ERR_ARG;
+    if (!h || !hu || !hv) return fail(c, SW_ERR_ARG, "state pointer is NULL");
+    // host-side check and clean-up of the initial state
+    size_t n = (size_t)c->nx * c->ny;
+    std::vector<float> H(n), U(n), V(n);
+    hipMemcpyKind kind = ptr_kind == SW_PTR_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+    if (ptr_kind != SW_PTR_HOST && ptr_kind != SW_PTR_DEVICE)
+        return fail(c, SW_ERR_ARG, "ptr_kind must be SW_PTR_HOST or SW_PTR_DEVICE");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(H.data(), h, n * sizeof(float), kind));
+    HIPCHK(c, hipMemcpy(U.data(), hu, n * sizeof(float), kind));
+    HIPCHK(c, hipMemcpy(V.data(), hv, n * sizeof(float), kind));
+    for (size_t q = 0; q < n; ++q) {
+        if (!(H[q] >= 0.0f) || !std::isfinite(H[q]) || !std::isfinite(U[q]) || !std::isfinite(V[q]))
+            return fail(c, SW_ERR_ARG, "initial depth must be finite and >= 0, discharges finite");
+        if (H[q] == 0.0f) { H[q] = 0.0f; U[q] = 0.0f; V[q] = 0.0f; }
+    }
+    // keep the bed, restart the step ring at k = 0
+    int cur = (int)(c->k & 1);
+    if (cur != 0)
+        HIPCHK(c, hipMemcpyAsync(c->b[0], c->b[cur], c->plane * sizeof(float),
+                                 hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->b[1], c->b[0], c->plane * sizeof(float), hipMemcpyDeviceToDevice,
+                             c->stream));
+    c->k = 0;
+    int rc;
+    if ((rc = upload_plane(c, c->H[0], H.data(), SW_PTR_HOST))) return rc;
+    if ((rc = upload_plane(c, c->qx[0], U.data(), SW_PTR_HOST))) return rc;
+    if ((rc = upload_plane(c, c->qy[0], V.data(), SW_PTR_HOST))) return rc;
+    HIPCHK(c, hipMemsetAsync(c->QLx, 0, 2 * c->plane * sizeof(float), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->bnd, 0, 4 * (size_t)(c->nx + c->ny) * sizeof(double), c->stream));
+    Ctrl h0{};
+    h0.t[0] = c->t0;
+    HIPCHK(c, hipMemcpyAsync(c->ctrl, &h0, sizeof(Ctrl), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->have_state = true;
+    c->dirty = true;
+    return SW_OK;
+}
+
+int sw_set_inflow(sw_ctx *c, const int32_t *cell_idx, const float *weight, int32_t n,
+                  double q_base, double q_peak, double t_peak, double t_sigma)
+{
+    if (!c) return SW_ERR_ARG;
+    if (n < 0) return fail(c, SW_ERR_ARG, "n must be >= 0");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (n == 0) {
+        c->has_inflow = 0;
+        c->force_in.clear();
+        c->dirty = true;
+        return upload_force(c);
+    }
+    if (!cell_idx || !weight) return fail(c, SW_ERR_ARG, "inflow arrays are NULL");
+    double wsum = 0.0;
+    for (int32_t q = 0; q < n; ++q) {
+        if (cell_idx[q] < 0 || cell_idx[q] >= c->nx * c->ny)
+            return fail(c, SW_ERR_ARG, "inflow cell index out of range");
+        if (!(weight[q] >= 0.0f)) return fail(c, SW_ERR_ARG, "inflow weights must be >= 0");
+        wsum += weight[q];
+    }
+    if (!(wsum > 0.0)) return fail(c, SW_ERR_ARG, "inflow weights sum to zero");
+    std::vector<float> w((size_t)c->plane, 0.0f);
+    std::vector<double> acc((size_t)c->nx * c->ny, 0.0);
+    for (int32_t q = 0; q < n; ++q) acc[cell_idx[q]] += (double)weight[q] / wsum;
+    double dx2 = c->grid.dx * c->grid.dx;
+    for (int j = 0; j < c->ny; ++j)
+        for (int i = 0; i < c->nx; ++i) w[(size_t)j * c->pitch + i] = (float)(acc[(size_t)j * c->nx + i] / dx2);
+    if (!c->srcw) HIPCHK(c, hipMalloc(&c->srcw, c->plane * sizeof(float)));
+    HIPCHK(c, hipMemcpy(c->srcw, w.data(), c->plane * sizeof(float), hipMemcpyHostToDevice));
+    c->has_inflow = 1;
+    c->q_base = q_base; c->q_peak = q_peak; c->t_peak = t_peak; c->t_sigma = t_sigma;
+    c->force_in.assign(ntiles(c), 0);
+    for (int32_t q = 0; q < n; ++q) c->force_in[tile_of(c, cell_idx[q] % c->nx, cell_idx[q] / c->nx)] = 1;
+    c->dirty = true;
+    return upload_force(c);
+}
+
+int sw_set_sed_sources(sw_ctx *c, const float *qb_plus, const float *qb_minus, int ptr_kind)
+{
+    if (!c) return SW_ERR_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!qb_plus && !qb_minus) {
+        (void)hipFree(c->qb);
+        c->qb = nullptr;
+        c->qb_total = 0.0;
+        c->force_qb.clear();
+        c->dirty = true;
+        return upload_force(c);
+    }
+    size_t n = (size_t)c->nx * c->ny;
+    std::vector<float> p(n, 0.0f), m(n, 0.0f), d((size_t)c->plane, 0.0f);
+    hipMemcpyKind kind = ptr_kind == SW_PTR_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+    if (qb_plus) HIPCHK(c, hipMemcpy(p.data(), qb_plus, n * sizeof(float), kind));
+    if (qb_minus) HIPCHK(c, hipMemcpy(m.data(), qb_minus, n * sizeof(float), kind));
+    double tot = 0.0;
+    c->force_qb.assign(ntiles(c), 0);
+    for (int j = 0; j < c->ny; ++j)
+        for (int i = 0; i < c->nx; ++i) {
+            float v = p[(size_t)j * c->nx + i] - m[(size_t)j * c->nx + i];
+            if (!std::isfinite(v)) return fail(c, SW_ERR_ARG, "bed sources must be finite");
+            d[(size_t)j * c->pitch + i] = v;
+            tot += (double)v;
+            if (v != 0.0f) c->force_qb[tile_of(c, i, j)] = 1;
+        }
+    if (!c->qb) HIPCHK(c, hipMalloc(&c->qb, c->plane * sizeof(float)));
+    HIPCHK(c, hipMemcpy(c->qb, d.data(), c->plane * sizeof(float), hipMemcpyHostToDevice));
+    c->qb_total = tot * c->grid.dx * c->grid.dx;
+    c->dirty = true;
+    return upload_force(c);
+}
+
+int sw_set_time(sw_ctx *c, double t, int64_t step)
+{
+    if (!c) return SW_ERR_ARG;
+    Ctrl h;
+    int rc = read_ctrl(c, &h);
+    if (rc) return rc;
+    h.t[c->k & 1] = t;
+    HIPCHK(c, hipMemcpyAsync(c->ctrl, &h, sizeof(Ctrl), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->t0 = t;
+    c->step0 = step - c->k;
+    return SW_OK;
+}
+
+int sw_advance(sw_ctx *c, int32_t nsteps) { return launch_steps(c, nsteps, 0, 0.0); }
+
+int sw_advance_fixed_dt(sw_ctx *c, int32_t nsteps, double dt) { return launch_steps(c, nsteps, 1, dt); }
+
+int sw_sync(sw_ctx *c)
+{
+    if (!c) return SW_ERR_ARG;
+    Ctrl h;
+    int rc = read_ctrl(c, &h);
+    if (rc) return rc;
+    if (h.err) return fail(c, h.err, "device error raised at step " + std::to_string(h.err_k));
+    return SW_OK;
+}
+
+int sw_get_fields(sw_ctx *c, float *h, float *hu, float *hv, float *b, int ptr_kind)
+{
+    if (!c) return SW_ERR_ARG;
+    Ctrl hc;
+    int rc = read_ctrl(c, &hc);
+    if (rc) return rc;
+    int cur = current_buffer(c, hc);
+    if (h && (rc = download_plane(c, h, c->H[cur], ptr_kind))) return rc;
+    if (hu && (rc = download_plane(c, hu, c->qx[cur], ptr_kind))) return rc;
+    if (hv && (rc = download_plane(c, hv, c->qy[cur], ptr_kind))) return rc;
+    if (b && (rc = download_plane(c, b, c->b[cur], ptr_kind))) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (hc.err) return fail(c, hc.err, "device error raised at step " + std::to_string(hc.err_k));
+    return SW_OK;
+}
+
+int sw_get_sums(sw_ctx *c, sw_sums *out)
+{
+    if (!c || !out) return SW_ERR_ARG;
+    Ctrl hc;
+    int rc = read_ctrl(c, &hc);
+    if (rc) return rc;
+    int cur = current_buffer(c, hc);
+    KPar P = make_kpar(c);
+    hipLaunchKernelGGL(k_sums1, dim3(c->nsum_blocks), dim3(SUM_THREADS), 0, c->stream, P,
+                       c->H[cur], c->b[cur], c->part, c->sum_rows);
+    int nb = 2 * (c->nx + c->ny);
+    hipLaunchKernelGGL(k_sums2, dim3(1), dim3(SUM_THREADS), 0, c->stream, c->part, c->nsum_blocks,
+                       c->bnd, nb, c->sums);
+    HIPCHK(c, hipGetLastError());
+    double s[5];
+    std::vector<uint8_t> act(ntiles(c));
+    HIPCHK(c, hipMemcpyAsync(s, c->sums, sizeof(s), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(act.data(), act_flags(c, cur), act.size(), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int64_t nact = 0;
+    for (size_t t = 0; t < act.size(); ++t) nact += act[t] ? 1 : 0;
+    double dx2 = c->grid.dx * c->grid.dx;
+    int64_t kk = hc.err ? hc.err_k : c->k;
+    memset(out, 0, sizeof(*out));
+    out->t = hc.t[kk & 1];
+    out->last_dt = hc.last_dt;
+    out->water_volume = s[0] * dx2;
+    out->sediment_volume = s[1] * dx2;
+    out->wet_cells = (int64_t)s[2];
+    out->water_boundary_out = s[3];
+    out->sed_boundary_out = s[4];
+    out->water_source_in = hc.in_w;
+    out->sed_source_in = hc.in_s;
+    out->vp = hc.vp; out->vs = hc.vs; out->D = hc.D;
+    out->step = c->step0 + kk;
+    out->active_tiles = (c->par.flags & SW_FLAG_UNFUSED) ? -1 : nact;
+    out->binding_term = hc.binding;
+    out->error = hc.err;
+    return SW_OK;
+}
+
+const char *sw_last_error(const sw_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,323 @@
+// csph_device.h -- FP32 device arithmetic of one CSPH-TVD step on gfx950.
+//
+// Every kernel of the library computes a cell, a face or a force through the
+// functions below, so a face flux evaluated by two different tiles (or two
+// different kernel variants) uses the same operations in the same order and
+// gives the same bits.  The step follows Section 3 of Khrapov & Khoperskov
+// (2020): forces at t_n, predictor to t_{n+1/2}, forces at t_{n+1/2},
+// corrector (K2..K6), Euler-stage fluxes by piecewise-linear reconstruction,
+// TVD (minmod) limiting and HLL (K7), update (K8), with the bedload of
+// Eqs. 2-5, the Exner update of Eq. 1 and the time step of Eq. 7.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace csph {
+
+constexpr int kWall = 0;
+constexpr int kOpen = 1;
+
+// Constants and per-run inputs passed by value to every kernel.
+struct KPar {
+    int nx, ny, pitch;      // pitch: floats per stored row (>= nx, multiple of 64)
+    int bcW, bcE, bcS, bcN; // 0 wall, 1 open
+    float dx, inv_dx;
+    float g, eps, eps4;     // gravity, desingularisation depth and its 4th power
+    float h_sed;            // no bedload at or below this depth
+    float s_rel_m1;         // s - 1 of Eq. 4
+    float C_J, C_Sh, A_G, m_exp;
+    float half_g_inv_dx;    // g / (2 dx)
+    int sed_law;            // 0 none, 1 Grass, 2 Eq. 4
+    const float *nM;  float nM_s;   // Manning: per cell (pitched) or scalar
+    const float *d50; float d50_s;  // grain size
+    const float *psi; float psi_s;  // porosity
+    const float *qb;                // q_b^+ - q_b^- per cell, or null
+    const float *srcw;              // inflow weight / dx^2 per cell, or null
+};
+
+__device__ __forceinline__ float soil(const float *a, float s, int c) { return a ? a[c] : s; }
+
+// Desingularised reciprocal depth (Kurganov & Petrova): 1/H for H >= eps,
+// sqrt(2) H / sqrt(H^4 + eps^4) below, zero at H = 0.
+__device__ __forceinline__ float wdes(float H, const KPar &P)
+{
+    if (H >= P.eps) return 1.0f / H;
+    float H2 = H * H;
+    return 1.41421356237f * H / sqrtf(H2 * H2 + P.eps4);
+}
+
+__device__ __forceinline__ float minmod(float a, float b)
+{
+    if (a * b <= 0.0f) return 0.0f;
+    return a > 0.0f ? fminf(a, b) : fmaxf(a, b);
+}
+
+// x^(4/3) for x > 0.
+__device__ __forceinline__ float pow43(float x) { return x * cbrtf(x); }
+
+// Manning friction rate g nM^2 |v| / max(H, eps)^(4/3) (semi-implicit).
+__device__ __forceinline__ float friction_rate(const KPar &P, float nM, float speed, float H)
+{
+    float Hf = H > P.eps ? H : P.eps;
+    return P.g * nM * nM * speed / pow43(Hf);
+}
+
+// Zero-slope bedload J0 (Eqs. 3-5): zero at or below h_sed or at or below the
+// Shamov critical speed C_Sh d50^(1/3) H^(1/6); else A |v|^m v.
+__device__ __forceinline__ void bedload(const KPar &P, float H, float u, float v, float nM,
+                                        float d50, float &jx, float &jy)
+{
+    jx = 0.0f;
+    jy = 0.0f;
+    if (P.sed_law == 0 || !(H > P.h_sed)) return;
+    float speed = sqrtf(u * u + v * v);
+    float vk = P.C_Sh * cbrtf(d50) * sqrtf(cbrtf(H));
+    if (!(speed > vk)) return;
+    float f;
+    if (P.sed_law == 1) {
+        f = P.A_G * powf(speed, P.m_exp);
+    } else {
+        float A = 0.05f * nM * nM * nM / (P.s_rel_m1 * sqrtf(P.g * H) * d50);
+        float s2 = speed * speed;
+        f = A * (s2 * s2);
+    }
+    jx = f * u;
+    jy = f * v;
+}
+
+// Hydrostatic-face force along one direction on cell C from its neighbours
+// M (minus side) and Q (plus side), for a depth field Hd over bed b:
+//   g/(2dx) [ HsL_+ (HsL_+ - HsR_+) - HsR_- (HsR_- - HsL_-) ],
+// which is -(P_+ - P_-)/dx + g/(2dx) (HsL_+^2 - HsR_-^2) with face pressure
+// P = g/2 HsL HsR, face bed max(b_L, b_R), side depth max(0, Hd + b - b_face).
+// A missing neighbour (domain boundary) is a ghost copy of C.
+__device__ __forceinline__ float face_force(const KPar &P, float HdM, float bM, float HdC,
+                                            float bC, float HdQ, float bQ, bool hasM, bool hasQ)
+{
+    float HsLp, HsRp, HsLm, HsRm;
+    if (hasQ) {
+        float bf = fmaxf(bC, bQ);
+        HsLp = fmaxf(0.0f, HdC + bC - bf);
+        HsRp = fmaxf(0.0f, HdQ + bQ - bf);
+    } else {
+        HsLp = HsRp = fmaxf(0.0f, HdC + bC - bC);
+    }
+    if (hasM) {
+        float bf = fmaxf(bM, bC);
+        HsLm = fmaxf(0.0f, HdM + bM - bf);
+        HsRm = fmaxf(0.0f, HdC + bC - bf);
+    } else {
+        HsLm = HsRm = fmaxf(0.0f, HdC + bC - bC);
+    }
+    return P.half_g_inv_dx * (HsLp * (HsLp - HsRp) - HsRm * (HsRm - HsLm));
+}
+
+// Per-cell quantities the remap reconstructs along one direction:
+// free surface z = H + b, depth H, normal transport velocity ut, normal and
+// tangential Lagrangian velocities uLn, uLt.
+struct CellQ {
+    float z, h, ut, uLn, uLt;
+};
+
+// Direction-free per-cell remap inputs: surface, depth, transport velocity
+// u~ = (v^n + u^L)/2 and Lagrangian velocity u^L = Q^L w(H), both components.
+// A cell with zero depth has zero velocities: its Q^L is replaced by its
+// (zero) momentum, so a Q^L buffer the Lagrangian stage skipped is never used.
+struct CellVals {
+    float z, h, utx, uty, uLx, uLy;
+};
+
+__device__ __forceinline__ CellVals cell_vals(const KPar &P, float H, float qx, float qy, float b,
+                                              float QLx, float QLy)
+{
+    float w = wdes(H, P);
+    float Lx = H > 0.0f ? QLx : qx;
+    float Ly = H > 0.0f ? QLy : qy;
+    float ux = qx * w, uy = qy * w;
+    float uLx = Lx * w, uLy = Ly * w;
+    CellVals v;
+    v.z = H + b;
+    v.h = H;
+    v.utx = 0.5f * (ux + uLx);
+    v.uty = 0.5f * (uy + uLy);
+    v.uLx = uLx;
+    v.uLy = uLy;
+    return v;
+}
+
+// The same cell seen along x (dir 0) or y (dir 1).
+__device__ __forceinline__ CellQ along(const CellVals &v, int dir)
+{
+    CellQ q;
+    q.z = v.z;
+    q.h = v.h;
+    if (dir == 0) {
+        q.ut = v.utx; q.uLn = v.uLx; q.uLt = v.uLy;
+    } else {
+        q.ut = v.uty; q.uLn = v.uLy; q.uLt = v.uLx;
+    }
+    return q;
+}
+
+// Ghost cell beyond a boundary normal to `dir`: a wall mirrors the normal
+// velocity components, an open side copies.
+__device__ __forceinline__ CellVals mirror(CellVals v, int dir, bool wall)
+{
+    if (wall) {
+        if (dir == 0) { v.utx = -v.utx; v.uLx = -v.uLx; }
+        else { v.uty = -v.uty; v.uLy = -v.uLy; }
+    }
+    return v;
+}
+
+__device__ __forceinline__ CellQ ghost_of(CellQ c, bool wall)
+{
+    if (wall) {
+        c.ut = -c.ut;
+        c.uLn = -c.uLn;
+    }
+    return c;
+}
+
+struct FaceState {
+    float Hs, uLn, uLt, ut;
+};
+
+// Reconstructed face states on both sides of the face between cells L and R,
+// given the outer neighbours A (beyond L) and B (beyond R): minmod slopes,
+// side values L + slope/2 and R - slope/2, hydrostatic face depths.
+__device__ __forceinline__ void face_states(const CellQ &A, const CellQ &L, const CellQ &R,
+                                            const CellQ &B, FaceState &fl, FaceState &fr)
+{
+    float zL = L.z + 0.5f * minmod(L.z - A.z, R.z - L.z);
+    float hL = L.h + 0.5f * minmod(L.h - A.h, R.h - L.h);
+    float tL = L.ut + 0.5f * minmod(L.ut - A.ut, R.ut - L.ut);
+    float nL = L.uLn + 0.5f * minmod(L.uLn - A.uLn, R.uLn - L.uLn);
+    float sL = L.uLt + 0.5f * minmod(L.uLt - A.uLt, R.uLt - L.uLt);
+    float zR = R.z - 0.5f * minmod(R.z - L.z, B.z - R.z);
+    float hR = R.h - 0.5f * minmod(R.h - L.h, B.h - R.h);
+    float tR = R.ut - 0.5f * minmod(R.ut - L.ut, B.ut - R.ut);
+    float nR = R.uLn - 0.5f * minmod(R.uLn - L.uLn, B.uLn - R.uLn);
+    float sR = R.uLt - 0.5f * minmod(R.uLt - L.uLt, B.uLt - R.uLt);
+    float bL = zL - hL, bR = zR - hR;
+    float bf = fmaxf(bL, bR);
+    fl.Hs = fmaxf(0.0f, zL - bf);
+    fr.Hs = fmaxf(0.0f, zR - bf);
+    fl.uLn = nL; fl.uLt = sL; fl.ut = tL;
+    fr.uLn = nR; fr.uLt = sR; fr.ut = tR;
+}
+
+// One-sided face state of a boundary cell: its neighbour inside (A) and its
+// ghost outside (G); side = +1 for the E/N face, -1 for the W/S face.
+__device__ __forceinline__ FaceState boundary_state(const CellQ &A, const CellQ &C,
+                                                    const CellQ &G, float side)
+{
+    // slope of C from its two neighbours in increasing coordinate order
+    const CellQ &lo = side > 0.0f ? A : G;
+    const CellQ &hi = side > 0.0f ? G : A;
+    float z = C.z + side * 0.5f * minmod(C.z - lo.z, hi.z - C.z);
+    float h = C.h + side * 0.5f * minmod(C.h - lo.h, hi.h - C.h);
+    FaceState s;
+    s.ut = C.ut + side * 0.5f * minmod(C.ut - lo.ut, hi.ut - C.ut);
+    s.uLn = C.uLn + side * 0.5f * minmod(C.uLn - lo.uLn, hi.uLn - C.uLn);
+    s.uLt = C.uLt + side * 0.5f * minmod(C.uLt - lo.uLt, hi.uLt - C.uLt);
+    float bb = z - h;
+    s.Hs = fmaxf(0.0f, z - bb);
+    return s;
+}
+
+// HLL flux of the remap: U = (Hs, Hs uLn, Hs uLt), F = ut U, Davis speeds.
+__device__ __forceinline__ void hll(float g, const FaceState &l, const FaceState &r, float &fH,
+                                    float &fn, float &ft)
+{
+    float UL0 = l.Hs, UL1 = l.Hs * l.uLn, UL2 = l.Hs * l.uLt;
+    float UR0 = r.Hs, UR1 = r.Hs * r.uLn, UR2 = r.Hs * r.uLt;
+    float FL0 = l.ut * UL0, FL1 = l.ut * UL1, FL2 = l.ut * UL2;
+    float FR0 = r.ut * UR0, FR1 = r.ut * UR1, FR2 = r.ut * UR2;
+    float cL = sqrtf(g * l.Hs), cR = sqrtf(g * r.Hs);
+    float SL = fminf(l.ut - cL, r.ut - cR);
+    float SR = fmaxf(l.ut + cL, r.ut + cR);
+    if (SL >= 0.0f) {
+        fH = FL0; fn = FL1; ft = FL2;
+    } else if (SR <= 0.0f) {
+        fH = FR0; fn = FR1; ft = FR2;
+    } else if (SR - SL <= 0.0f) {
+        fH = 0.0f; fn = 0.0f; ft = 0.0f;
+    } else {
+        float inv = 1.0f / (SR - SL);
+        float SLR = SL * SR;
+        fH = (SR * FL0 - SL * FR0 + SLR * (UR0 - UL0)) * inv;
+        fn = (SR * FL1 - SL * FR1 + SLR * (UR1 - UL1)) * inv;
+        ft = (SR * FL2 - SL * FR2 + SLR * (UR2 - UL2)) * inv;
+    }
+}
+
+// Wall face fluxes (HLL against the mirrored ghost): no mass, no tangential
+// momentum; normal momentum Hs uLn (ut +- |ut| +- c) with the upper signs for
+// the interior cell on the minus side (E/N wall).
+__device__ __forceinline__ float wall_flux_n(float g, const FaceState &s, float side)
+{
+    float c = sqrtf(g * s.Hs);
+    return s.Hs * s.uLn * (s.ut + side * (fabsf(s.ut) + c));
+}
+
+// Bedload face flux: donor split of J0 plus the slope term of Eq. 2 with the
+// mean |J0| of the two cells.
+__device__ __forceinline__ float bed_face_flux(const KPar &P, float JnL, float JmagL, float bL,
+                                               float JnR, float JmagR, float bR)
+{
+    float mag = 0.5f * (JmagL + JmagR);
+    return fmaxf(JnL, 0.0f) + fminf(JnR, 0.0f) - P.C_J * mag * (bR - bL) * P.inv_dx;
+}
+
+// Raw water fluxes (mass, normal momentum, tangential momentum) of face k
+// along one direction, k in [0, n] (face k lies between cells k-1 and k),
+// from cells c0..c3 = k-2..k+1 (ghost cells at -1 and n).  Interior faces:
+// reconstruction + HLL.  Boundary faces: the wall flux against the mirrored
+// ghost, or the physical flux of the interior face state on an open side.
+__device__ __forceinline__ void water_flux(const KPar &P, int k, int n, bool wallLo, bool wallHi,
+                                           const CellQ &c0, const CellQ &c1, const CellQ &c2,
+                                           const CellQ &c3, float &fH, float &fn, float &ft)
+{
+    fH = fn = ft = 0.0f;
+    if (k > 0 && k < n) {
+        FaceState fl, fr;
+        face_states(c0, c1, c2, c3, fl, fr);
+        hll(P.g, fl, fr, fH, fn, ft);
+    } else if (k == n) {  // high boundary: interior cell c1, its inner neighbour c0, ghost c2
+        FaceState s = boundary_state(c0, c1, c2, 1.0f);
+        if (wallHi) {
+            fn = wall_flux_n(P.g, s, 1.0f);
+        } else {
+            fH = s.ut * s.Hs;
+            fn = s.ut * s.Hs * s.uLn;
+            ft = s.ut * s.Hs * s.uLt;
+        }
+    } else {  // k == 0: interior cell c2, its inner neighbour c3, ghost c1
+        FaceState s = boundary_state(c3, c2, c1, -1.0f);
+        if (wallLo) {
+            fn = wall_flux_n(P.g, s, -1.0f);
+        } else {
+            fH = s.ut * s.Hs;
+            fn = s.ut * s.Hs * s.uLn;
+            ft = s.ut * s.Hs * s.uLt;
+        }
+    }
+}
+
+// Bedload flux of face k along direction dir from the J0 vectors and beds of
+// the cells on its two sides; walls pass nothing, an open side passes only
+// the outward part of the interior cell's J0.
+__device__ __forceinline__ float sed_flux(const KPar &P, int k, int n, bool wallLo, bool wallHi,
+                                          int dir, float jxL, float jyL, float bL, float jxR,
+                                          float jyR, float bR)
+{
+    if (k > 0 && k < n)
+        return bed_face_flux(P, dir == 0 ? jxL : jyL, sqrtf(jxL * jxL + jyL * jyL), bL,
+                             dir == 0 ? jxR : jyR, sqrtf(jxR * jxR + jyR * jyR), bR);
+    if (k == n) return wallHi ? 0.0f : fmaxf(dir == 0 ? jxL : jyL, 0.0f);
+    return wallLo ? 0.0f : fminf(dir == 0 ? jxR : jyR, 0.0f);
+}
+
+}  // namespace csph

@@ -2,7 +2,7 @@
 
 This module only draws inputs: terrains, initial water, soil fields, inflow
 cells and hydrographs.  It holds none of the method's arithmetic, and both the
-HIP path and the CPU oracle take their inputs from it.  Every generator is
+HIP path and the CPU reference take their inputs from it.  Every generator is
 deterministic in its seed (numpy PCG64).
 
 The paper's own workload, the Volga-Akhtuba floodplain (Section 3: 1024^2 to

@@ -1,0 +1,221 @@
+"""Parity of the HIP path (FP32 state, FP64 sums and dt) with the FP64 CPU oracle.
+
+Every case starts both sides from the same float32-rounded seeded inputs and
+calls the library through its C ABI.  Tolerances are the ones the precision
+policy fixes: L-inf depth <= 1e-4 m, relative mass drift <= 1e-6, wet/dry mask
+disagreement <= 0.1 % of cells (wet <=> h > 1e-4 m).
+"""
+import numpy as np
+import pytest
+
+from paper_2103_15196_amd import workloads as W
+from tests.gpu_common import compare, run_gpu, run_oracle, say
+from tests.helpers import read_golden
+
+pytestmark = pytest.mark.gpu
+
+LINF_H = 1e-4
+MASS = 1e-6
+MASK = 1e-3
+
+
+def _check(res, linf_h=LINF_H):
+    say(f"  {res}")
+    assert res["linf_h"] <= linf_h
+    assert res["mass_drift_gpu"] <= MASS
+    assert res["mask_disagree"] <= MASK
+    assert abs(res["t_gpu"] - res["t_oracle"]) <= 1e-5 * max(res["t_oracle"], 1e-9)
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle as O
+    O.build(force=False)
+    return O
+
+
+def test_gpu_dam_break_256x64_cfl(O):
+    """The 256 x 64 dam break (2 m | 0.5 m, erodible bed, Eq. 4 bedload,
+    Manning 0.02, walls, K = 0.3), 200 steps with the Eq. 7 step."""
+    w = W.dam_break_1d().as_float32()
+    say("case dam_break 256x64 cfl 200")
+    res = compare(O, w, run_gpu(w, 200), run_oracle(O, w, 200))
+    _check(res)
+    assert res["linf_b"] <= 1e-5
+
+
+def test_gpu_dam_break_256x64_fixed_dt(O):
+    w = W.dam_break_1d().as_float32()
+    say("case dam_break 256x64 fixed dt 0.05, 200")
+    res = compare(O, w, run_gpu(w, 200, dt=0.05), run_oracle(O, w, 200, dt=0.05))
+    _check(res)
+    assert res["t_gpu"] == pytest.approx(10.0, rel=1e-12)
+
+
+def test_gpu_fractal_dam_break_ragged_1000_steps(O):
+    """2-D dam break over a fractal bed with open boundaries, wet/dry fronts
+    and a ragged grid (not a multiple of the tile size), 1000 steps."""
+    w = W.dam_break_fractal(n=300, ny=236, dx=2.0, seed=7, relief=10.0, depth=8.0,
+                            steps=1000).as_float32()
+    say("case fractal dam break 300x236 1000 steps")
+    res = compare(O, w, run_gpu(w, 1000), run_oracle(O, w, 1000))
+    _check(res)
+
+
+def test_gpu_river_valley_inflow_per_cell_soil(O):
+    """Inflow hydrograph, per-cell d50 and psi, walls + one open side, bed sources."""
+    w = W.river_valley(n=200, ny=136, dx=5.0, amplitude=60.0, wavelength=500.0, width=40.0,
+                       Q_base=20.0, Q_peak=200.0, t_peak=40.0, t_sigma=15.0)
+    w.qb = np.zeros((w.ny, w.nx))
+    w.qb[60:70, 100:110] = 2e-6
+    w = w.as_float32()
+    say("case river valley 200x136 600 steps")
+    gpu = run_gpu(w, 600)
+    orc = run_oracle(O, w, 600)
+    res = compare(O, w, gpu, orc)
+    _check(res)
+    sums = gpu[1]
+    assert abs(sums["water_source_in"] - orc[2].in_w) <= 1e-6 * orc[2].in_w
+    assert sums["wet_cells"] > 100
+
+
+@pytest.mark.parametrize("name,steps,dt", [("hand_step_3x1_wall.txt", 1, 0.1)])
+def test_gpu_hand_step_3x1(name, steps, dt):
+    exp = read_golden(name)
+    w = W.Workload(name="h", nx=3, ny=1, dx=1.0, bc=(0, 0, 0, 0), H=np.array([[1.0, 0, 0]]),
+                   qx=np.zeros((1, 3)), qy=np.zeros((1, 3)), b=np.zeros((1, 3)), nM=0.0,
+                   d50=5e-4, psi=0.4, steps=1, cfl=0.9, sed_law=0)
+    (h, hu, hv, b), _ = run_gpu(w, 1, dt=0.1)
+    for i in range(3):
+        assert h[0, i] == pytest.approx(exp[f"H{i}"], abs=2e-6)
+        assert hu[0, i] == pytest.approx(exp[f"qx{i}"], abs=2e-6)
+
+
+def test_gpu_hand_steps_3x3():
+    for name, dt in (("hand_step_3x3_column.txt", 0.1), ("hand_step_3x3_drained.txt", 0.25)):
+        exp = read_golden(name)
+        H = np.zeros((3, 3))
+        H[1, 1] = 1.0
+        z = np.zeros((3, 3))
+        w = W.Workload(name="h", nx=3, ny=3, dx=1.0, bc=(0, 0, 0, 0), H=H, qx=z, qy=z, b=z,
+                       nM=0.0, d50=5e-4, psi=0.4, steps=1, cfl=0.9, sed_law=0)
+        (h, hu, hv, b), _ = run_gpu(w, 1, dt=dt)
+        assert h[1, 1] == pytest.approx(exp["H_centre"], abs=2e-6)
+        for (j, i) in ((0, 1), (2, 1), (1, 0), (1, 2)):
+            assert h[j, i] == pytest.approx(exp["H_edge"], abs=2e-6)
+        assert h[0, 0] == 0.0 and h[2, 2] == 0.0
+
+
+def test_gpu_hand_step_momentum_and_exner():
+    exp = read_golden("hand_step_2x1_momentum.txt")
+    H = np.ones((1, 2))
+    w = W.Workload(name="h", nx=2, ny=1, dx=1.0, bc=(0, 0, 0, 0), H=H, qx=np.array([[1.0, 0.0]]),
+                   qy=np.zeros((1, 2)), b=np.zeros((1, 2)), nM=0.0, d50=5e-4, psi=0.4, steps=1,
+                   cfl=0.9, sed_law=0)
+    (h, hu, hv, b), _ = run_gpu(w, 1, dt=0.1)
+    assert float(hu.sum()) == pytest.approx(exp["sum_q"], abs=5e-6)
+    exp = read_golden("hand_step_exner_3x1.txt")
+    H = np.ones((1, 3))
+    w = W.Workload(name="e", nx=3, ny=1, dx=1.0, bc=(1, 1, 0, 0), H=H,
+                   qx=np.array([[1.0, 1.5, 1.0]]), qy=np.zeros((1, 3)),
+                   b=np.array([[0.0, 0.1, 0.0]]), nM=0.0, d50=5e-4, psi=0.4, steps=1, cfl=0.3,
+                   sed_law=1)
+    (h, hu, hv, b), _ = run_gpu(w, 1, dt=0.05, A_G=1e-3, m_exp=2.0)
+    for i in range(3):
+        assert b[0, i] == pytest.approx(exp[f"b{i}"], abs=1e-8)
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0, 0), (1, 1, 1, 1)])
+def test_gpu_lake_at_rest_is_exact(bc):
+    """Still water over a fractal bed with dry islands stays bit-for-bit still."""
+    w = W.lake_at_rest(200, 130, dx=1.0, relief=3.0, level=2.0, bc=bc).as_float32()
+    (h, hu, hv, b), sums = run_gpu(w, 500)
+    assert np.array_equal(h, w.H.astype(np.float32))
+    assert np.all(hu == 0) and np.all(hv == 0)
+    assert np.array_equal(b, w.b.astype(np.float32))
+
+
+def test_gpu_y_uniform_and_transpose_bitwise():
+    w = W.dam_break_1d(nx=160, ny=70, x_dam=80).as_float32()
+    (h, hu, hv, b), _ = run_gpu(w, 150)
+    assert np.all(hv == 0)
+    for f in (h, hu, b):
+        assert np.array_equal(f, np.broadcast_to(f[:1], f.shape))
+    f = W.dam_break_fractal(n=130, ny=98, dx=2.0, seed=9, relief=5.0, depth=4.0).as_float32()
+    f.bc = (0, 1, 1, 0)
+    (h1, u1, v1, b1), s1 = run_gpu(f, 120)
+    t = W.Workload(**{k: getattr(f, k) for k in f.__dataclass_fields__})
+    t.nx, t.ny = f.ny, f.nx
+    t.H, t.b, t.qx, t.qy = f.H.T.copy(), f.b.T.copy(), f.qy.T.copy(), f.qx.T.copy()
+    t.bc = (f.bc[2], f.bc[3], f.bc[0], f.bc[1])
+    (h2, u2, v2, b2), s2 = run_gpu(t, 120)
+    assert np.array_equal(h2, h1.T) and np.array_equal(b2, b1.T)
+    assert np.array_equal(u2, v1.T) and np.array_equal(v2, u1.T)
+
+
+def test_gpu_device_pointers_and_torch_stream(O):
+    """Inputs and outputs as torch device tensors (ptr_kind = device)."""
+    import torch
+    from paper_2103_15196_amd import csph
+    w = W.dam_break_1d(nx=128, ny=48, x_dam=64).as_float32()
+    dev = torch.device("cuda:0")
+    t = {k: torch.tensor(getattr(w, k), dtype=torch.float32, device=dev).contiguous()
+         for k in ("H", "qx", "qy", "b")}
+    s = csph.Solver(w.nx, w.ny, w.dx, w.bc, stream=torch.cuda.current_stream().cuda_stream,
+                    cfl=w.cfl, sed_law=w.sed_law)
+    s.set_bed(t["b"])
+    s.set_soil(w.nM, w.d50, w.psi)
+    s.set_state(t["H"], t["qx"], t["qy"])
+    s.advance(100)
+    out = [torch.empty_like(t["H"]) for _ in range(4)]
+    s.get_fields(out)
+    torch.cuda.synchronize()
+    h_host = s.get_fields()[0]
+    s.close()
+    assert np.array_equal(out[0].cpu().numpy(), h_host)
+    p, inp, st = run_oracle(O, w, 100)
+    assert np.abs(h_host - st.H).max() <= LINF_H
+
+
+def test_gpu_errors_are_reported_and_state_kept():
+    from paper_2103_15196_amd import csph
+    w = W.dam_break_1d(nx=64, ny=16, x_dam=32).as_float32()
+    s = csph.solver_for(w, stream=None)
+    s.advance(5)
+    h5 = s.get_fields()[0]
+    s.advance(3, dt=10.0)          # far above the Eq. 7 step
+    with pytest.raises(csph.SwError) as e:
+        s.sync()
+    assert e.value.code == csph.SW_ERR_CFL
+    with pytest.raises(csph.SwError):
+        s.get_fields()
+    s.set_state(w.H, w.qx, w.qy)   # a new state clears the error
+    s.advance(5)
+    assert np.array_equal(s.get_fields()[0], h5)
+    bad = w.H.copy()
+    bad[3, 3] = np.nan
+    with pytest.raises(csph.SwError) as e:
+        s.set_state(bad, w.qx, w.qy)
+    assert e.value.code == csph.SW_ERR_ARG
+    s.close()
+
+
+def test_gpu_variants_are_bitwise_identical():
+    """Tiled vs unfused kernels, HGS on vs off, graph replay vs eager launches:
+    identical bits (same per-cell and per-face arithmetic, exact dry-tile skip)."""
+    from paper_2103_15196_amd import csph
+    w = W.dam_break_fractal(n=400, ny=200, dx=2.0, seed=11, relief=10.0, depth=6.0).as_float32()
+    w.bc = (0, 1, 1, 0)
+    F = csph
+    runs = {}
+    for name, flags in (("tiled_hgs_graph", F.SW_FLAG_HGS), ("tiled_nohgs", 0),
+                        ("tiled_hgs_eager", F.SW_FLAG_HGS | F.SW_FLAG_NO_GRAPH),
+                        ("unfused", F.SW_FLAG_UNFUSED)):
+        say(f"variant {name}")
+        runs[name] = run_gpu(w, 301, flags=flags)
+    ref = runs["unfused"]
+    for name, (f, sums) in runs.items():
+        for a, b in zip(f, ref[0]):
+            assert np.array_equal(a, b), name
+        assert sums["t"] == ref[1]["t"], name
+    assert 0 < runs["tiled_hgs_graph"][1]["active_tiles"] < (400 // 64 + 1) * (200 // 8)

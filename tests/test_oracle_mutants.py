@@ -28,12 +28,13 @@ MUTANTS = {
     "force_y_uses_x_terms": ("(g / (2.0 * dx)) * (HsLn * HsLn - HsRs * HsRs)",
                              "(g / (2.0 * dx)) * (HsLe * HsLe - HsRw * HsRw)"),
     "force_y_wrong_neighbour": ("size_t n = c + nx;", "size_t n = c + 1;"),
-    "manning_exponent": ("pow(Hf, 4.0 / 3.0)", "pow(Hf, 3.0 / 4.0)"),
+    "manning_exponent": ("(Hf * cbrt(Hf))", "(Hf * sqrt(Hf))"),
     "predictor_full_step": ("(qx[c] + 0.5 * dt * Sx[c])", "(qx[c] + dt * Sx[c])"),
     "half_depth_multiplies": ("Hh[c] = H[c] / (Jx * Jy);", "Hh[c] = H[c] * (Jx * Jy);"),
     "transport_velocity_drops_vn": ("utx[c] = 0.5 * (u[c] + uLx[c]);", "utx[c] = uLx[c];"),
-    "y_face_transposed_operand": ("double tL = face_value(p, uty, i, jL, 1, +1, 0, 1);",
-                                  "double tL = face_value(p, utx, i, jL, 1, +1, 1, 0);"),
+    "y_face_transposed_operand": ("double tL = FACEV(uty, sy[2], cL, +1), tR = FACEV(uty, sy[2], cR, -1);",
+                                  "double tL = FACEV(utx, sy[2], cL, +1), tR = FACEV(uty, sy[2], cR, -1);"),
+    "slope_ghost_normal_flag": ("const int fx_nx[5] = {0, 0, 1, 1, 0}", "const int fx_nx[5] = {0, 0, 1, 0, 0}"),
     "wall_flux_sign_east": ("fl[1] = HsL * nL * (tL + fabs(tL) + cL);",
                             "fl[1] = HsL * nL * (tL - fabs(tL) + cL);"),
     "open_boundary_blocks_mass": ("fl[0] = tL * HsL;\n                    fl[1] = tL * HsL * nL;\n                    fl[2] = tL * HsL * sL;\n                    fj = fmax(J0x[c], 0.0);",
@@ -49,7 +50,7 @@ MUTANTS = {
     "eq4_drops_s_minus_one": ("((p->s_rel - 1.0) * sqrt(p->g * H) * d50)", "(p->s_rel * sqrt(p->g * H) * d50)"),
     "eq7_vp_term": ("h / (2.0 * vp)", "h / vp"),
     "eq7_D_term": ("h * h / (2.0 * D)", "h * h / D"),
-    "shamov_exponent": ("pow(H, 1.0 / 6.0)", "pow(H, 1.0 / 3.0)"),
+    "shamov_exponent": ("cbrt(d50) * sqrt(cbrt(H))", "cbrt(d50) * cbrt(H)"),
 }
 
 
