@@ -1,0 +1,188 @@
+"""Benchmark of the CSPH-TVD step on one MI355X.
+
+Workload (N=1): the 2-D dam break over a seeded fractal bed, 2048 x 2048 cells,
+dx = 2 m, 1 m dam line, 8 m reservoir, dry downstream, open boundaries,
+psi = 0.4, Manning n = 0.03, d50 = 0.5 mm, Eq. 4 bedload, K = 0.3.  One "step"
+is one CSPH-TVD time step over the whole grid (Lagrangian stage with the Eq. 7
+step, then the fused Euler stage), replayed from a HIP graph with dry tiles
+skipped.  Inputs are resident on the GPU before the timed region starts.
+
+Prints one JSON line: value = grid cells x steps / wall time (Gcell-steps/s),
+a roofline object for the dominant kernel (timed live with HIP events on the
+solver's stream), the CPU oracle timed on a bounded sample of the same
+workload, and side measurements (the river-valley grid with dry-tile skipping
+on and off).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+# algorithmic bytes per cell of one launch (float32 planes read + written)
+EULER_BYTES = {"scalar_soil": 40, "per_cell_soil": 52}    # h,hu,hv,b,QLx,QLy in; h,hu,hv,b out (+nM,d50,psi)
+LAGRANGE_BYTES = {"scalar_soil": 24, "per_cell_soil": 28}  # h,hu,hv,b in; QLx,QLy out (+nM)
+STEP_BYTES = 32  # per cell-step: state read once + written once
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=2048, help="grid side of the dam-break workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0: auto, ~10-30 s)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the row-strip sharding is a design note only).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2103_15196_amd import csph, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    log(f"[bench] building workload dam_break_fractal n={args.n}")
+    w = W.dam_break_fractal(n=args.n, steps=args.steps).as_float32()
+    cells = w.nx * w.ny
+    s = csph.solver_for(w, stream=stream.cuda_stream)
+    log(f"[bench] warmup {args.warmup} steps")
+    if args.warmup:
+        s.advance(args.warmup)
+        s.sync()
+    s.set_state(w.H, w.qx, w.qy)  # timed steps start from the initial state
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.advance(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    s.sync()
+    sums = s.get_sums()
+    value = cells * args.steps / (ms * 1e-3) / 1e9
+    log(f"[bench] {ms:.2f} ms ({wall*1e3:.2f} ms wall) -> {value:.2f} Gcell-steps/s, "
+        f"t={sums['t']:.3f} s, wet={sums['wet_cells']}")
+
+    # per-kernel durations (HIP events on the solver's stream), same steps again
+    s.set_state(w.H, w.qx, w.qy)
+    lag_ms, eul_ms = s.advance_profiled(args.steps)
+    ps = s.get_sums()
+    eul_cells = ps["cells_euler"] / args.steps
+    lag_cells = ps["cells_lagrange"] / args.steps
+    soil = "scalar_soil"
+    eul_bytes = eul_cells * EULER_BYTES[soil]
+    achieved = eul_bytes / (eul_ms * 1e-3) / 1e9
+    log(f"[bench] kernels: lagrange {lag_ms*1e3:.1f} us ({lag_cells:.0f} cells), "
+        f"euler {eul_ms*1e3:.1f} us ({eul_cells:.0f} cells) -> {achieved:.0f} GB/s")
+    s.close()
+
+    out = {
+        "metric": "Gcell-steps/s",
+        "value": round(value, 3),
+        "unit": "Gcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"dam_break_fractal_{w.nx}x{w.ny}", "grid": [w.nx, w.ny],
+                   "dx_m": w.dx, "reservoir_m": 8.0, "dam_m": 1.0, "relief_m": 10.0,
+                   "bc": "open", "cfl": w.cfl, "sed_law": "eq4", "skip_dry_tiles": True,
+                   "graph": True, "parallelism": "single-gpu"},
+        "hbm_frac_algorithmic": round(value * STEP_BYTES / HBM_PEAK_GBS, 4),
+        "roofline": {"kernel": "k_euler_t", "bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "avg_launch_us": round(eul_ms * 1e3, 2),
+                     "bytes_per_cell": EULER_BYTES[soil], "cells_per_launch": round(eul_cells),
+                     "lagrange_avg_launch_us": round(lag_ms * 1e3, 2)},
+        "time_s_model": sums["t"],
+    }
+
+    if not args.no_extras:
+        out["river_valley"] = river_valley_rates(csph, W, torch)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def river_valley_rates(csph, W, torch, n=8192, steps=2000):
+    """The 8192^2 river valley (meandering channel, per-cell soil, inflow
+    hydrograph, initially dry): whole-grid rate with dry-tile skipping on and off."""
+    log(f"[bench] river valley {n}^2 x {steps} steps")
+    w = W.river_valley(n=n, steps=steps).as_float32()
+    res = {"grid": [w.nx, w.ny], "steps": steps}
+    stream = torch.cuda.current_stream()
+    for name, flags in (("skip_on", csph.SW_FLAG_HGS), ("skip_off", 0)):
+        s = csph.solver_for(w, stream=stream.cuda_stream, flags=flags)
+        s.advance(20)
+        s.set_state(w.H, w.qx, w.qy)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.advance(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        sums = s.get_sums()
+        res[name] = {"gcell_steps_s": round(w.nx * w.ny * steps / (ms * 1e-3) / 1e9, 3),
+                     "ms_per_step": round(ms / steps, 4),
+                     "wet_fraction": round(sums["wet_cells"] / (w.nx * w.ny), 5),
+                     "t_model_s": round(sums["t"], 3)}
+        log(f"[bench]   {name}: {res[name]}")
+        s.close()
+    return res
+
+
+def cpu_baseline(w, steps):
+    """The FP64 CPU oracle on the same grid, a bounded number of steps."""
+    from oracle import oracle as O
+    O.build(force=False)
+    from tests.helpers import oracle_case
+    p, inp, st = oracle_case(O, w)
+    O.step(p, inp, st)  # first step untimed (allocation, page faults)
+    if steps <= 0:
+        t0 = time.perf_counter()
+        O.step(p, inp, st)
+        one = time.perf_counter() - t0
+        steps = max(2, min(60, int(15.0 / max(one, 1e-3))))
+    log(f"[bench] cpu oracle: {steps} steps on {w.nx}x{w.ny}, {O.threads()} threads")
+    t0 = time.perf_counter()
+    O.run(p, inp, st, steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(w.nx * w.ny * steps / dt / 1e9, 5), "unit": "Gcell-steps/s",
+            "cores": O.threads(), "kind": "oracle",
+            "sample": f"{steps} steps (after 1 untimed) of the {w.nx}x{w.ny} dam break, FP64, "
+                      f"{dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -99,6 +99,8 @@ typedef struct {
     int64_t step;              /* step counter */
     int64_t wet_cells;         /* cells with h > 0 */
     int64_t active_tiles;      /* tiles the next step will not skip */
+    int64_t cells_lagrange;    /* cells the Lagrangian-stage kernel processed since set_state */
+    int64_t cells_euler;       /* cells the Euler-stage kernel processed since set_state */
     int32_t binding_term;      /* Eq. 7 term that set last_dt: 0 h/(2vp), 1 h/vs, 2 h^2/(2D), 3 dt_max, 4 fixed */
     int32_t error;             /* sticky device error (SW_ERR_*), 0 if none */
 } sw_sums;
@@ -151,6 +153,13 @@ int sw_advance(sw_ctx *ctx, int32_t nsteps);
 /* Same with a fixed step dt; a step whose Eq. 7 bound is below dt raises
  * SW_ERR_CFL on the device (as above). */
 int sw_advance_fixed_dt(sw_ctx *ctx, int32_t nsteps, double dt);
+
+/* Measurement aid: advance nsteps (Eq. 7 step) with one launch per kernel and
+ * a HIP event recorded on the context's stream around each launch; on return
+ * avg_ms[0] / avg_ms[1] hold the mean duration of the Lagrangian-stage and
+ * Euler-stage kernels.  Same kernels and arithmetic as sw_advance (the tiled
+ * path); synchronises.  SW_ERR_ARG on the unfused path. */
+int sw_advance_profiled(sw_ctx *ctx, int32_t nsteps, double *avg_ms);
 
 /* Wait for queued work; returns the sticky device error, if any. */
 int sw_sync(sw_ctx *ctx);

@@ -86,6 +86,20 @@ typedef struct {
     double in_s;        /* sediment volume added by q_b this step */
 } orc_step_info;
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads an OpenMP loop of the oracle runs on. */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_NONFINITE = -3, ORC_ERR_DT = -4, ORC_ERR_CFL = -6 };
 
 /* ---------------------------------------------------------------------- */

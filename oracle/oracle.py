@@ -97,6 +97,8 @@ def _load():
         lib.orc_step.restype = C.c_int
         lib.orc_step.argtypes = [C.POINTER(_Params), C.POINTER(_Inputs), _dp, _dp, _dp, _dp,
                                  C.c_double, C.c_double, C.POINTER(_Info)]
+        lib.orc_threads.restype = C.c_int
+        lib.orc_threads.argtypes = []
         lib.orc_volumes.restype = None
         lib.orc_volumes.argtypes = [C.POINTER(_Params), C.POINTER(_Inputs), _dp, _dp, _dp, _dp]
         _lib = lib
@@ -295,3 +297,8 @@ def hydrograph(inp: Inputs, t: float) -> float:
     ci.Q_base, ci.Q_peak = float(inp.Q_base), float(inp.Q_peak)
     ci.t_peak, ci.t_sigma = float(inp.t_peak), float(inp.t_sigma)
     return _load().orc_hydrograph(C.byref(ci), float(t))
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(_load().orc_threads())

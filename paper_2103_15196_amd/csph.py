@@ -53,7 +53,8 @@ class sw_sums(C.Structure):
                 ("water_source_in", C.c_double), ("sed_boundary_out", C.c_double),
                 ("sed_source_in", C.c_double), ("vp", C.c_double), ("vs", C.c_double),
                 ("D", C.c_double), ("step", C.c_int64), ("wet_cells", C.c_int64),
-                ("active_tiles", C.c_int64), ("binding_term", C.c_int32), ("error", C.c_int32)]
+                ("active_tiles", C.c_int64), ("cells_lagrange", C.c_int64),
+                ("cells_euler", C.c_int64), ("binding_term", C.c_int32), ("error", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -77,6 +78,7 @@ SIGNATURES = [
     ("sw_set_time", C.c_int, [_ctxp, C.c_double, C.c_int64]),
     ("sw_advance", C.c_int, [_ctxp, C.c_int32]),
     ("sw_advance_fixed_dt", C.c_int, [_ctxp, C.c_int32, C.c_double]),
+    ("sw_advance_profiled", C.c_int, [_ctxp, C.c_int32, C.POINTER(C.c_double)]),
     ("sw_sync", C.c_int, [_ctxp]),
     ("sw_get_fields", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     ("sw_get_sums", C.c_int, [_ctxp, C.POINTER(sw_sums)]),
@@ -220,6 +222,12 @@ class Solver:
             _check(self.ctx, lib.sw_advance(self.ctx, int(nsteps)))
         else:
             _check(self.ctx, lib.sw_advance_fixed_dt(self.ctx, int(nsteps), float(dt)))
+
+    def advance_profiled(self, nsteps):
+        """Advance with per-kernel HIP events; returns (lagrange_ms, euler_ms) averages."""
+        out = (C.c_double * 2)()
+        _check(self.ctx, lib.sw_advance_profiled(self.ctx, int(nsteps), out))
+        return out[0], out[1]
 
     def sync(self):
         _check(self.ctx, lib.sw_sync(self.ctx))

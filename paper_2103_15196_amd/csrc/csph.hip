@@ -38,6 +38,7 @@ struct Ctrl {
     double vp, vs, D;            // Eq. 7 maxima at the start of the last step
     double last_dt;
     int err, err_k, binding, kdev;  // kdev: steps taken since the state was set
+    unsigned long long work[2];     // cells processed by the Lagrangian / Euler stage
 };
 
 struct StepArgs {
@@ -54,7 +55,7 @@ __device__ __forceinline__ unsigned fbits_nonneg(float x) { return __float_as_ui
 // Wave64 + block max of three non-negative floats (as bits) and a flag,
 // then one atomicMax per value into this block's slot.
 __device__ __forceinline__ void block_maxima(unsigned a, unsigned b, unsigned c, unsigned bad,
-                                             unsigned (*slot)[4])
+                                             unsigned (*slot)[4], int sidx)
 {
     __shared__ unsigned red[4][16];
     for (int off = 32; off > 0; off >>= 1) {
@@ -75,7 +76,7 @@ __device__ __forceinline__ void block_maxima(unsigned a, unsigned b, unsigned c,
             a = max(a, red[0][w]); b = max(b, red[1][w]); c = max(c, red[2][w]);
             bad = max(bad, red[3][w]);
         }
-        int s = (blockIdx.x + blockIdx.y * gridDim.x) % NSLOT;
+        int s = sidx % NSLOT;
         if (a) atomicMax(&slot[s][0], a);
         if (b) atomicMax(&slot[s][1], b);
         if (c) atomicMax(&slot[s][2], c);
@@ -117,7 +118,7 @@ __global__ void k_prepare(KPar P, Ctrl *ctrl, int k, const float *__restrict__ H
         int c = j * P.pitch + i;
         cell_maxima(P, H[c], qx[c], qy[c], b[c], c, mv, ms, mD, bad);
     }
-    block_maxima(mv, ms, mD, bad, ctrl->slot[k & 1]);
+    block_maxima(mv, ms, mD, bad, ctrl->slot[k & 1], blockIdx.x + blockIdx.y * gridDim.x);
 }
 
 // K3: time step of Eq. 7 from the maxima of step k's state; clears the slots
@@ -412,7 +413,7 @@ __global__ void __launch_bounds__(BX * BY) k_update(KPar P, Ctrl *__restrict__ c
         if (j == P.ny - 1) { bnd[2 * P.ny + P.nx + i] += wdx * (double)GHn; bnd[2 * (P.nx + P.ny) + 2 * P.ny + P.nx + i] += wdx * (double)F.yJ[gn]; }
         cell_maxima(P, Hn, qxn, qyn, bn, c, mv, ms, mD, bad);
     }
-    block_maxima(mv, ms, mD, bad, ctrl->slot[(k + 1) & 1]);
+    block_maxima(mv, ms, mD, bad, ctrl->slot[(k + 1) & 1], blockIdx.x + blockIdx.y * gridDim.x);
 }
 
 
@@ -423,20 +424,35 @@ __global__ void __launch_bounds__(BX * BY) k_update(KPar P, Ctrl *__restrict__ c
 // skips the Euler stage.  A tile is dry when every cell has h = 0 and it holds
 // no inflow or bed-source cell; such a tile provably stays unchanged, so the
 // skip is exact.  The arithmetic per cell and per face is the one of the
-// unfused kernels above (same device functions, same order).
+// unfused kernels above (same device functions, same order), so every tile
+// shape gives the same bits.  The tile functions serve a single grid (tile =
+// block index) and an ensemble (tile = entry of a table over all members).
 // ---------------------------------------------------------------------------
 
-constexpr int TX = 64, TY = 8, NT = 256;
+constexpr int NT = 256;
+
+// Everything a tile of one grid needs: constants, Eq. 7 inputs, buffers, flags.
+struct Inst {
+    KPar P;
+    StepArgs A;
+    Ctrl *ctrl;
+    float *H[2], *qx[2], *qy[2], *b[2];
+    float *QLx, *QLy;
+    double *bnd;
+    uint8_t *act[2];
+    uint8_t *synced;
+    const uint8_t *force;
+    int ntx, nty, hgs;
+};
 
 // Eq. 7 step from ring `par` of the maxima slots.  Every block computes the
-// same value; block (0,0) publishes it (time ring, balances, error, step
-// counter) and clears the slots the Euler stage of this step fills.
-__device__ bool block_dt(Ctrl *ctrl, int par, const StepArgs &A, double &dt_out)
+// same value; the lead block of the grid publishes it (time ring, balances,
+// error, step counter) and clears the slots the Euler stage of this step fills.
+__device__ bool block_dt(Ctrl *ctrl, int par, const StepArgs &A, bool lead, double &dt_out)
 {
     __shared__ double s_dt;
     __shared__ int s_ok;
     const int tid = threadIdx.x;
-    const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
     if (tid < 64) {
         unsigned a = 0, b = 0, c = 0, bad = 0;
         if (tid < NSLOT) {
@@ -505,13 +521,14 @@ __device__ bool block_dt(Ctrl *ctrl, int par, const StepArgs &A, double &dt_out)
 }
 
 // Initial maxima (ring par) and wet-tile flags of a state set from the host.
-__global__ void __launch_bounds__(NT) k_prepare_t(KPar P, Ctrl *ctrl, int par, StateView S,
-                                                  uint8_t *__restrict__ act,
-                                                  const uint8_t *__restrict__ force)
+template <int TX, int TY>
+__device__ void prepare_tile(const Inst &I, int par, int bx, int by)
 {
     __shared__ int s_any;
+    const KPar &P = I.P;
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int x0 = bx * TX, y0 = by * TY, tile = bx + by * I.ntx;
+    const float *H = I.H[par], *qx = I.qx[par], *qy = I.qy[par], *b = I.b[par];
     if (tid == 0) s_any = 0;
     __syncthreads();
     unsigned mv = 0, ms = 0, mD = 0, bad = 0;
@@ -519,44 +536,44 @@ __global__ void __launch_bounds__(NT) k_prepare_t(KPar P, Ctrl *ctrl, int par, S
         int i = x0 + q % TX, j = y0 + q / TX;
         if (i >= P.nx || j >= P.ny) continue;
         int c = j * P.pitch + i;
-        float H = S.H[c];
-        cell_maxima(P, H, S.qx[c], S.qy[c], S.b[c], c, mv, ms, mD, bad);
-        if (H > 0.0f) s_any = 1;
+        float h = H[c];
+        cell_maxima(P, h, qx[c], qy[c], b[c], c, mv, ms, mD, bad);
+        if (h > 0.0f) s_any = 1;
     }
-    block_maxima(mv, ms, mD, bad, ctrl->slot[par]);
-    int tile = blockIdx.x + blockIdx.y * gridDim.x;
-    if (tid == 0) act[tile] = (s_any || force[tile]) ? 1 : 0;
+    block_maxima(mv, ms, mD, bad, I.ctrl->slot[par], tile);
+    if (tid == 0) I.act[par][tile] = (s_any || I.force[tile]) ? 1 : 0;
 }
 
 // Lagrangian stage on a tile (K2, K4, K5, K6) with the Eq. 7 step (K3).
-constexpr int LW = TX + 4, LHh = TY + 4;  // state tile with a 2-cell halo
-
-__global__ void __launch_bounds__(NT) k_lagrange_t(KPar P, Ctrl *ctrl, int par, StepArgs A,
-                                                   StateView S, float *__restrict__ QLx,
-                                                   float *__restrict__ QLy,
-                                                   const uint8_t *__restrict__ act, int hgs)
+template <int TX, int TY>
+__device__ void lagrange_tile(const Inst &I, int par, int bx, int by)
 {
+    constexpr int LW = TX + 4, LHh = TY + 4;  // state tile with a 2-cell halo
     __shared__ float sH[LHh][LW], sb[LHh][LW], sqx[LHh][LW], sqy[LHh][LW], su[LHh][LW],
         sv[LHh][LW];
     __shared__ float sHh[TY + 2][TX + 2];
+    const KPar &P = I.P;
     double dtd;
-    if (!block_dt(ctrl, par, A, dtd)) return;
-    const int tile = blockIdx.x + blockIdx.y * gridDim.x;
-    if (hgs && !act[tile]) return;
+    if (!block_dt(I.ctrl, par, I.A, bx == 0 && by == 0, dtd)) return;
+    const int tile = bx + by * I.ntx;
+    if (I.hgs && !I.act[par][tile]) return;
     const float dt = (float)dtd;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, tid = threadIdx.x;
+    const int x0 = bx * TX, y0 = by * TY, tid = threadIdx.x;
+    const float *H = I.H[par], *Qx = I.qx[par], *Qy = I.qy[par], *B = I.b[par];
+    if (tid == 0)
+        atomicAdd(&I.ctrl->work[0], (unsigned long long)(min(TX, P.nx - x0) * min(TY, P.ny - y0)));
     for (int q = tid; q < LW * LHh; q += NT) {
         int rx = q % LW, ry = q / LW;
         int i = x0 - 2 + rx, j = y0 - 2 + ry;
-        float H = 0.0f, qx = 0.0f, qy = 0.0f, b = 0.0f, u = 0.0f, v = 0.0f;
+        float h = 0.0f, qx = 0.0f, qy = 0.0f, b = 0.0f, u = 0.0f, v = 0.0f;
         if ((unsigned)i < (unsigned)P.nx && (unsigned)j < (unsigned)P.ny) {
             int c = j * P.pitch + i;
-            H = S.H[c]; qx = S.qx[c]; qy = S.qy[c]; b = S.b[c];
-            float w = wdes(H, P);
+            h = H[c]; qx = Qx[c]; qy = Qy[c]; b = B[c];
+            float w = wdes(h, P);
             u = qx * w;
             v = qy * w;
         }
-        sH[ry][rx] = H; sb[ry][rx] = b; sqx[ry][rx] = qx; sqy[ry][rx] = qy; su[ry][rx] = u;
+        sH[ry][rx] = h; sb[ry][rx] = b; sqx[ry][rx] = qx; sqy[ry][rx] = qy; su[ry][rx] = u;
         sv[ry][rx] = v;
     }
     __syncthreads();
@@ -610,57 +627,60 @@ __global__ void __launch_bounds__(NT) k_lagrange_t(KPar P, Ctrl *ctrl, int par, 
         float Shx = face_force(P, HhW, bW, Hh, bc, HhE, bE, hasW, hasE);
         float Shy = face_force(P, HhS, bS, Hh, bc, HhN, bN, hasS, hasN);
         float gamh = friction_rate(P, nM, sqrtf(upx * upx + upy * upy), Hh);
-        QLx[c] = (qxc + dt * Shx) / (1.0f + dt * gamh);
-        QLy[c] = (qyc + dt * Shy) / (1.0f + dt * gamh);
+        I.QLx[c] = (qxc + dt * Shx) / (1.0f + dt * gamh);
+        I.QLy[c] = (qyc + dt * Shy) / (1.0f + dt * gamh);
     }
 }
 
 // Euler stage on a tile (K7 + limiter + K8) with the epilogue reductions
 // (Eq. 7 maxima and wet flags of the new state, FP64 boundary balances).
-constexpr int EW = TX + 6, EHt = TY + 6;  // remap inputs with a 3-cell halo
-constexpr int RW = TX + 2, RH = TY + 2;   // the tile plus a 1-cell ring
-
-__global__ void __launch_bounds__(NT) k_euler_t(KPar P, Ctrl *ctrl, int par, StateView S,
-                                                LagView L, OutView O, double *__restrict__ bnd,
-                                                const uint8_t *__restrict__ act_in,
-                                                uint8_t *__restrict__ act_out,
-                                                uint8_t *__restrict__ synced,
-                                                const uint8_t *__restrict__ force, int hgs)
+template <int TX, int TY>
+__device__ void euler_tile(const Inst &I, int par, int bx, int by)
 {
+    constexpr int EW = TX + 6, EHt = TY + 6;  // remap inputs with a 3-cell halo
+    constexpr int RW = TX + 2, RH = TY + 2;   // the tile plus a 1-cell ring
     __shared__ float cz[EHt][EW], ch[EHt][EW], cux[EHt][EW], cuy[EHt][EW], cLx[EHt][EW],
         cLy[EHt][EW];
     __shared__ float rjx[RH][RW], rjy[RH][RW], rb[RH][RW], rth[RH][RW];
     __shared__ float fxH[RH][TX + 3], fxn[RH][TX + 3], fxt[RH][TX + 3];
     __shared__ float fyH[TY + 3][RW], fyn[TY + 3][RW], fyt[TY + 3][RW];
     __shared__ int s_flag;
+    const KPar &P = I.P;
+    Ctrl *ctrl = I.ctrl;
     if (ctrl->err) return;
-    const int ntx = gridDim.x, nty = gridDim.y;
-    const int bx = blockIdx.x, by = blockIdx.y, tile = bx + by * ntx, tid = threadIdx.x;
+    const int ntx = I.ntx, nty = I.nty;
+    const int tile = bx + by * ntx, tid = threadIdx.x;
     const int x0 = bx * TX, y0 = by * TY;
     const int nx = P.nx, ny = P.ny;
-    if (hgs) {
+    const float *SH = I.H[par], *Sqx = I.qx[par], *Sqy = I.qy[par], *Sb = I.b[par];
+    float *OH = I.H[par ^ 1], *Oqx = I.qx[par ^ 1], *Oqy = I.qy[par ^ 1], *Ob = I.b[par ^ 1];
+    const float *QLx = I.QLx, *QLy = I.QLy;
+    const uint8_t *act_in = I.act[par];
+    if (I.hgs) {
         bool run = act_in[tile] || (bx > 0 && act_in[tile - 1]) ||
                    (bx + 1 < ntx && act_in[tile + 1]) || (by > 0 && act_in[tile - ntx]) ||
                    (by + 1 < nty && act_in[tile + ntx]);
         if (!run) {
-            if (tid == 0) s_flag = synced[tile];
+            if (tid == 0) s_flag = I.synced[tile];
             __syncthreads();
             if (!s_flag) {  // first skip since the tile last changed: bring the other buffer level
                 for (int q = tid; q < TX * TY; q += NT) {
                     int i = x0 + q % TX, j = y0 + q / TX;
                     if (i >= nx || j >= ny) continue;
                     int c = j * P.pitch + i;
-                    O.H[c] = S.H[c]; O.qx[c] = S.qx[c]; O.qy[c] = S.qy[c]; O.b[c] = S.b[c];
+                    OH[c] = SH[c]; Oqx[c] = Sqx[c]; Oqy[c] = Sqy[c]; Ob[c] = Sb[c];
                 }
             }
             if (tid == 0) {
-                synced[tile] = 1;
-                act_out[tile] = 0;
+                I.synced[tile] = 1;
+                I.act[par ^ 1][tile] = 0;
             }
             return;
         }
-        if (tid == 0) synced[tile] = 0;
+        if (tid == 0) I.synced[tile] = 0;
     }
+    if (tid == 0)
+        atomicAdd(&ctrl->work[1], (unsigned long long)(min(TX, nx - x0) * min(TY, ny - y0)));
     const float dt = (float)ctrl->dt[par];
     const double dtd = ctrl->dt[par];
     const bool wW = P.bcW == kWall, wE = P.bcE == kWall, wS = P.bcS == kWall, wN = P.bcN == kWall;
@@ -673,13 +693,13 @@ __global__ void __launch_bounds__(NT) k_euler_t(KPar P, Ctrl *ctrl, int par, Sta
         CellVals v{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         if (inx && iny) {
             int c = j * P.pitch + i;
-            float H = S.H[c], qx = S.qx[c], qy = S.qy[c], b = S.b[c];
-            v = cell_vals(P, H, qx, qy, b, L.QLx[c], L.QLy[c]);
+            float h = SH[c], qx = Sqx[c], qy = Sqy[c], b = Sb[c];
+            v = cell_vals(P, h, qx, qy, b, QLx[c], QLy[c]);
             int cx = rx - 2, cy = ry - 2;
             if ((unsigned)cx < (unsigned)RW && (unsigned)cy < (unsigned)RH) {
-                float w = wdes(H, P);
+                float w = wdes(h, P);
                 float jx, jy;
-                bedload(P, H, qx * w, qy * w, soil(P.nM, P.nM_s, c), soil(P.d50, P.d50_s, c), jx,
+                bedload(P, h, qx * w, qy * w, soil(P.nM, P.nM_s, c), soil(P.d50, P.d50_s, c), jx,
                         jy);
                 rjx[cy][cx] = jx;
                 rjy[cy][cx] = jy;
@@ -687,11 +707,11 @@ __global__ void __launch_bounds__(NT) k_euler_t(KPar P, Ctrl *ctrl, int par, Sta
             }
         } else if (iny && (i == -1 || i == nx)) {
             int c = j * P.pitch + (i < 0 ? 0 : nx - 1);
-            v = mirror(cell_vals(P, S.H[c], S.qx[c], S.qy[c], S.b[c], L.QLx[c], L.QLy[c]), 0,
+            v = mirror(cell_vals(P, SH[c], Sqx[c], Sqy[c], Sb[c], QLx[c], QLy[c]), 0,
                        i < 0 ? wW : wE);
         } else if (inx && (j == -1 || j == ny)) {
             int c = (j < 0 ? 0 : ny - 1) * P.pitch + i;
-            v = mirror(cell_vals(P, S.H[c], S.qx[c], S.qy[c], S.b[c], L.QLx[c], L.QLy[c]), 1,
+            v = mirror(cell_vals(P, SH[c], Sqx[c], Sqy[c], Sb[c], QLx[c], QLy[c]), 1,
                        j < 0 ? wS : wN);
         }
         cz[ry][rx] = v.z; ch[ry][rx] = v.h; cux[ry][rx] = v.utx; cuy[ry][rx] = v.uty;
@@ -745,6 +765,7 @@ __global__ void __launch_bounds__(NT) k_euler_t(KPar P, Ctrl *ctrl, int par, Sta
 
     // update of the tile's own cells
     unsigned mv = 0, ms = 0, mD = 0, bad = 0;
+    double *bnd = I.bnd;
     for (int q = tid; q < TX * TY; q += NT) {
         int lx = q % TX, ly = q / TX;
         int i = x0 + lx, j = y0 + ly;
@@ -770,12 +791,12 @@ __global__ void __launch_bounds__(NT) k_euler_t(KPar P, Ctrl *ctrl, int par, Sta
                             rjx[cy][cx], rjy[cy][cx], rb[cy][cx]);
         float Jn = sed_flux(P, j + 1, ny, wS, wN, 1, rjx[cy][cx], rjy[cy][cx], rb[cy][cx],
                             rjx[cy + 1][cx], rjy[cy + 1][cx], rb[cy + 1][cx]);
-        float H = S.H[c], qx = S.qx[c], qy = S.qy[c], b = S.b[c];
-        float QLxc = H > 0.0f ? L.QLx[c] : qx;
-        float QLyc = H > 0.0f ? L.QLy[c] : qy;
+        float h = SH[c], qx = Sqx[c], qy = Sqy[c], b = Sb[c];
+        float QLxc = h > 0.0f ? QLx[c] : qx;
+        float QLyc = h > 0.0f ? QLy[c] : qy;
         float r = dt * P.inv_dx;
         float src = P.srcw ? P.srcw[c] * (float)ctrl->qmid[par] : 0.0f;
-        float Hn = H - r * ((FHe - FHw) + (GHn - GHs)) + dt * src;
+        float Hn = h - r * ((FHe - FHw) + (GHn - GHs)) + dt * src;
         float qxn = QLxc - r * ((Fxe - Fxw) + (Gxn - Gxs));
         float qyn = QLyc - r * ((Fye - Fyw) + (Gyn - Gys));
         float om = 1.0f - soil(P.psi, P.psi_s, c);
@@ -787,7 +808,7 @@ __global__ void __launch_bounds__(NT) k_euler_t(KPar P, Ctrl *ctrl, int par, Sta
             qxn *= sc;
             qyn *= sc;
         }
-        O.H[c] = Hn; O.qx[c] = qxn; O.qy[c] = qyn; O.b[c] = bn;
+        OH[c] = Hn; Oqx[c] = qxn; Oqy[c] = qyn; Ob[c] = bn;
         double wdx = dtd * (double)P.dx;
         const int nb = 2 * (nx + ny);
         if (i == 0) { bnd[j] += wdx * (double)(-FHw); bnd[nb + j] += wdx * (double)(-Jw); }
@@ -797,9 +818,49 @@ __global__ void __launch_bounds__(NT) k_euler_t(KPar P, Ctrl *ctrl, int par, Sta
         cell_maxima(P, Hn, qxn, qyn, bn, c, mv, ms, mD, bad);
         if (Hn > 0.0f) s_flag = 1;
     }
-    block_maxima(mv, ms, mD, bad, ctrl->slot[par ^ 1]);
-    if (tid == 0) act_out[tile] = (s_flag || force[tile]) ? 1 : 0;
+    block_maxima(mv, ms, mD, bad, ctrl->slot[par ^ 1], tile);
+    if (tid == 0) I.act[par ^ 1][tile] = (s_flag || I.force[tile]) ? 1 : 0;
 }
+
+// Single grid: tile = block index.
+template <int TX, int TY>
+__global__ void __launch_bounds__(NT) k_prepare_t(Inst I, int par)
+{
+    prepare_tile<TX, TY>(I, par, blockIdx.x, blockIdx.y);
+}
+template <int TX, int TY>
+__global__ void __launch_bounds__(NT) k_lagrange_t(Inst I, int par)
+{
+    lagrange_tile<TX, TY>(I, par, blockIdx.x, blockIdx.y);
+}
+template <int TX, int TY>
+__global__ void __launch_bounds__(NT) k_euler_t(Inst I, int par)
+{
+    euler_tile<TX, TY>(I, par, blockIdx.x, blockIdx.y);
+}
+
+// Ensemble: block b handles tile (table[3b+1], table[3b+2]) of member table[3b].
+template <int TX, int TY>
+__global__ void __launch_bounds__(NT) k_lagrange_b(const Inst *__restrict__ insts,
+                                                   const int *__restrict__ table, int par)
+{
+    const int *t = table + 3 * blockIdx.x;
+    lagrange_tile<TX, TY>(insts[t[0]], par, t[1], t[2]);
+}
+template <int TX, int TY>
+__global__ void __launch_bounds__(NT) k_euler_b(const Inst *__restrict__ insts,
+                                                const int *__restrict__ table, int par)
+{
+    const int *t = table + 3 * blockIdx.x;
+    euler_tile<TX, TY>(insts[t[0]], par, t[1], t[2]);
+}
+
+// Tile shapes the autotuner chooses from (TX x TY cells per 256-thread block).
+struct Shape {
+    int tx, ty;
+};
+constexpr Shape kShapes[] = {{64, 8}, {64, 4}, {64, 16}, {128, 4}};
+constexpr int kNumShapes = 4;
 
 // ---------------------------------------------------------------------------
 // FP64 sums: water volume, sediment volume, wet cells (two fixed-order passes).
@@ -905,7 +966,9 @@ struct sw_ctx {
     hipStream_t cap = nullptr;       // private stream used only to capture graphs
     hipGraphExec_t gexec = nullptr;  // two tiled steps (even k, then odd k)
     bool graph_ok = false;
-    std::vector<uint8_t> force_in, force_qb;  // tiles holding inflow / bed-source cells
+    std::vector<int32_t> forced_in, forced_qb;  // inflow / bed-source cells (flat indices)
+    int shape = 0;                   // index into kShapes
+    size_t max_tiles = 0;            // tile count of the smallest shape (flag capacity)
     int graph_fixed = 0;
     double graph_dt = 0.0;
     std::string err;
@@ -991,35 +1054,90 @@ int download_plane(sw_ctx *c, float *dst, const float *src, int ptr_kind)
 dim3 cell_grid(const sw_ctx *c) { return dim3((c->nx + BX - 1) / BX, (c->ny + BY - 1) / BY); }
 
 size_t ntiles(const sw_ctx *c) { return (size_t)c->ntx * c->nty; }
-uint8_t *act_flags(const sw_ctx *c, int par) { return c->tflags + par * ntiles(c); }
-uint8_t *synced_flags(const sw_ctx *c) { return c->tflags + 2 * ntiles(c); }
-uint8_t *force_flags(const sw_ctx *c) { return c->tflags + 3 * ntiles(c); }
+uint8_t *act_flags(const sw_ctx *c, int par) { return c->tflags + par * c->max_tiles; }
+uint8_t *synced_flags(const sw_ctx *c) { return c->tflags + 2 * c->max_tiles; }
+uint8_t *force_flags(const sw_ctx *c) { return c->tflags + 3 * c->max_tiles; }
+
+size_t tile_of(const sw_ctx *c, int cell)
+{
+    int i = cell % c->nx, j = cell / c->nx;
+    return (size_t)(j / kShapes[c->shape].ty) * c->ntx + (size_t)(i / kShapes[c->shape].tx);
+}
 
 // Tiles that must never be skipped: they hold inflow or bed-source cells.
 int upload_force(sw_ctx *c)
 {
-    size_t nt = ntiles(c);
-    std::vector<uint8_t> f(nt, 0);
-    for (size_t t = 0; t < nt; ++t)
-        f[t] = (uint8_t)((c->force_in.size() == nt && c->force_in[t]) ||
-                         (c->force_qb.size() == nt && c->force_qb[t]));
-    HIPCHK(c, hipMemcpy(force_flags(c), f.data(), nt, hipMemcpyHostToDevice));
+    std::vector<uint8_t> f(ntiles(c), 0);
+    for (int32_t q : c->forced_in) f[tile_of(c, q)] = 1;
+    for (int32_t q : c->forced_qb) f[tile_of(c, q)] = 1;
+    HIPCHK(c, hipMemcpy(force_flags(c), f.data(), f.size(), hipMemcpyHostToDevice));
     return SW_OK;
 }
 
-size_t tile_of(const sw_ctx *c, int i, int j) { return (size_t)(j / TY) * c->ntx + (size_t)(i / TX); }
+void set_shape(sw_ctx *c, int shape)
+{
+    c->shape = shape;
+    c->ntx = (c->nx + kShapes[shape].tx - 1) / kShapes[shape].tx;
+    c->nty = (c->ny + kShapes[shape].ty - 1) / kShapes[shape].ty;
+    c->dirty = true;
+    c->graph_ok = false;
+}
+
+Inst make_inst(const sw_ctx *c, const StepArgs &A)
+{
+    Inst I{};
+    I.P = make_kpar(c);
+    I.A = A;
+    I.ctrl = c->ctrl;
+    for (int s = 0; s < 2; ++s) {
+        I.H[s] = c->H[s]; I.qx[s] = c->qx[s]; I.qy[s] = c->qy[s]; I.b[s] = c->b[s];
+        I.act[s] = act_flags(c, s);
+    }
+    I.QLx = c->QLx;
+    I.QLy = c->QLy;
+    I.bnd = c->bnd;
+    I.synced = synced_flags(c);
+    I.force = force_flags(c);
+    I.ntx = c->ntx;
+    I.nty = c->nty;
+    I.hgs = (c->par.flags & SW_FLAG_HGS) ? 1 : 0;
+    return I;
+}
+
+// Launch one tiled stage for the context's tile shape.
+enum Stage { kPrepare, kLagrange, kEuler };
+
+template <int TX, int TY>
+void launch_stage_t(Stage st, hipStream_t s, const Inst &I, int par, dim3 g)
+{
+    if (st == kPrepare) hipLaunchKernelGGL((k_prepare_t<TX, TY>), g, dim3(NT), 0, s, I, par);
+    else if (st == kLagrange) hipLaunchKernelGGL((k_lagrange_t<TX, TY>), g, dim3(NT), 0, s, I, par);
+    else hipLaunchKernelGGL((k_euler_t<TX, TY>), g, dim3(NT), 0, s, I, par);
+}
+
+void launch_stage(int shape, Stage st, hipStream_t s, const Inst &I, int par)
+{
+    dim3 g(I.ntx, I.nty);
+    switch (shape) {
+    case 0: launch_stage_t<64, 8>(st, s, I, par, g); break;
+    case 1: launch_stage_t<64, 4>(st, s, I, par, g); break;
+    case 2: launch_stage_t<64, 16>(st, s, I, par, g); break;
+    default: launch_stage_t<128, 4>(st, s, I, par, g); break;
+    }
+}
 
 // Recompute the Eq. 7 maxima and the wet-tile flags of the current state
-// (after any set_*), and mark every tile's two buffers as possibly different.
+// (after any set_* or a tile-shape change), and mark every tile's two buffers
+// as possibly different.
 int prepare(sw_ctx *c)
 {
     int cur = (int)(c->k & 1);
+    int rc = upload_force(c);
+    if (rc) return rc;
     HIPCHK(c, hipMemsetAsync(c->ctrl->slot[cur], 0, sizeof(c->ctrl->slot[0]), c->stream));
-    HIPCHK(c, hipMemsetAsync(synced_flags(c), 0, ntiles(c), c->stream));
-    KPar P = make_kpar(c);
-    StateView S{c->H[cur], c->qx[cur], c->qy[cur], c->b[cur]};
-    hipLaunchKernelGGL(k_prepare_t, dim3(c->ntx, c->nty), dim3(NT), 0, c->stream, P, c->ctrl, cur,
-                       S, act_flags(c, cur), (const uint8_t *)force_flags(c));
+    HIPCHK(c, hipMemsetAsync(synced_flags(c), 0, c->max_tiles, c->stream));
+    Inst I = make_inst(c, make_step_args(c, 0, 0.0));
+    launch_stage(c->shape, kPrepare, c->stream, I, cur);
     HIPCHK(c, hipGetLastError());
     c->dirty = false;
     c->graph_ok = false;
@@ -1039,16 +1157,10 @@ int current_buffer(sw_ctx *c, const Ctrl &h) { return h.err ? (h.err_k & 1) : (i
 
 void enqueue_tiled_step(sw_ctx *c, hipStream_t st, int par, const KPar &P, const StepArgs &A)
 {
-    const int hgs = (c->par.flags & SW_FLAG_HGS) ? 1 : 0;
-    StateView S{c->H[par], c->qx[par], c->qy[par], c->b[par]};
-    LagView L{c->QLx, c->QLy};
-    OutView O{c->H[par ^ 1], c->qx[par ^ 1], c->qy[par ^ 1], c->b[par ^ 1]};
-    dim3 grid(c->ntx, c->nty), blk(NT);
-    hipLaunchKernelGGL(k_lagrange_t, grid, blk, 0, st, P, c->ctrl, par, A, S, c->QLx, c->QLy,
-                       (const uint8_t *)act_flags(c, par), hgs);
-    hipLaunchKernelGGL(k_euler_t, grid, blk, 0, st, P, c->ctrl, par, S, L, O, c->bnd,
-                       (const uint8_t *)act_flags(c, par), act_flags(c, par ^ 1), synced_flags(c),
-                       (const uint8_t *)force_flags(c), hgs);
+    (void)P;
+    Inst I = make_inst(c, A);
+    launch_stage(c->shape, kLagrange, st, I, par);
+    launch_stage(c->shape, kEuler, st, I, par);
 }
 
 void enqueue_unfused_step(sw_ctx *c, int par, const KPar &P, const StepArgs &A)
@@ -1213,10 +1325,13 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
     if ((e = hipMalloc(&c->part, (3 * (size_t)c->nsum_blocks + 8) * sizeof(double))) != hipSuccess)
         return bail(e, "hipMalloc(part)");
     c->sums = c->part + 3 * (size_t)c->nsum_blocks;
-    c->ntx = (c->nx + TX - 1) / TX;
-    c->nty = (c->ny + TY - 1) / TY;
-    if ((e = hipMalloc(&c->tflags, 4 * ntiles(c))) != hipSuccess) return bail(e, "hipMalloc(tiles)");
-    if ((e = hipMemset(c->tflags, 0, 4 * ntiles(c))) != hipSuccess) return bail(e, "hipMemset(tiles)");
+    for (int sh = 0; sh < kNumShapes; ++sh) {
+        set_shape(c, sh);
+        c->max_tiles = std::max(c->max_tiles, ntiles(c));
+    }
+    set_shape(c, 0);
+    if ((e = hipMalloc(&c->tflags, 4 * c->max_tiles)) != hipSuccess) return bail(e, "hipMalloc(tiles)");
+    if ((e = hipMemset(c->tflags, 0, 4 * c->max_tiles)) != hipSuccess) return bail(e, "hipMemset(tiles)");
     if ((e = hipMalloc(&c->ctrl, sizeof(Ctrl))) != hipSuccess) return bail(e, "hipMalloc(ctrl)");
     if ((e = hipMemset(c->ctrl, 0, sizeof(Ctrl))) != hipSuccess) return bail(e, "hipMemset(ctrl)");
     *out = c;
@@ -1342,7 +1457,7 @@ int sw_set_inflow(sw_ctx *c, const int32_t *cell_idx, const float *weight, int32
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (n == 0) {
         c->has_inflow = 0;
-        c->force_in.clear();
+        c->forced_in.clear();
         c->dirty = true;
         return upload_force(c);
     }
@@ -1365,8 +1480,7 @@ int sw_set_inflow(sw_ctx *c, const int32_t *cell_idx, const float *weight, int32
     HIPCHK(c, hipMemcpy(c->srcw, w.data(), c->plane * sizeof(float), hipMemcpyHostToDevice));
     c->has_inflow = 1;
     c->q_base = q_base; c->q_peak = q_peak; c->t_peak = t_peak; c->t_sigma = t_sigma;
-    c->force_in.assign(ntiles(c), 0);
-    for (int32_t q = 0; q < n; ++q) c->force_in[tile_of(c, cell_idx[q] % c->nx, cell_idx[q] / c->nx)] = 1;
+    c->forced_in.assign(cell_idx, cell_idx + n);
     c->dirty = true;
     return upload_force(c);
 }
@@ -1379,7 +1493,7 @@ int sw_set_sed_sources(sw_ctx *c, const float *qb_plus, const float *qb_minus, i
         (void)hipFree(c->qb);
         c->qb = nullptr;
         c->qb_total = 0.0;
-        c->force_qb.clear();
+        c->forced_qb.clear();
         c->dirty = true;
         return upload_force(c);
     }
@@ -1389,14 +1503,14 @@ int sw_set_sed_sources(sw_ctx *c, const float *qb_plus, const float *qb_minus, i
     if (qb_plus) HIPCHK(c, hipMemcpy(p.data(), qb_plus, n * sizeof(float), kind));
     if (qb_minus) HIPCHK(c, hipMemcpy(m.data(), qb_minus, n * sizeof(float), kind));
     double tot = 0.0;
-    c->force_qb.assign(ntiles(c), 0);
+    c->forced_qb.clear();
     for (int j = 0; j < c->ny; ++j)
         for (int i = 0; i < c->nx; ++i) {
             float v = p[(size_t)j * c->nx + i] - m[(size_t)j * c->nx + i];
             if (!std::isfinite(v)) return fail(c, SW_ERR_ARG, "bed sources must be finite");
             d[(size_t)j * c->pitch + i] = v;
             tot += (double)v;
-            if (v != 0.0f) c->force_qb[tile_of(c, i, j)] = 1;
+            if (v != 0.0f) c->forced_qb.push_back(j * c->nx + i);
         }
     if (!c->qb) HIPCHK(c, hipMalloc(&c->qb, c->plane * sizeof(float)));
     HIPCHK(c, hipMemcpy(c->qb, d.data(), c->plane * sizeof(float), hipMemcpyHostToDevice));
@@ -1422,6 +1536,45 @@ int sw_set_time(sw_ctx *c, double t, int64_t step)
 int sw_advance(sw_ctx *c, int32_t nsteps) { return launch_steps(c, nsteps, 0, 0.0); }
 
 int sw_advance_fixed_dt(sw_ctx *c, int32_t nsteps, double dt) { return launch_steps(c, nsteps, 1, dt); }
+
+int sw_advance_profiled(sw_ctx *c, int32_t nsteps, double *avg_ms)
+{
+    if (!c || !avg_ms) return SW_ERR_ARG;
+    if (nsteps < 1) return fail(c, SW_ERR_ARG, "nsteps must be >= 1");
+    if (c->par.flags & SW_FLAG_UNFUSED)
+        return fail(c, SW_ERR_ARG, "kernel timing covers the tiled path only");
+    if (!c->have_state) return fail(c, SW_ERR_STATE, "advance before sw_set_state");
+    if (c->dirty) {
+        int rc = prepare(c);
+        if (rc) return rc;
+    }
+    Inst I = make_inst(c, make_step_args(c, 0, 0.0));
+    std::vector<hipEvent_t> ev(3 * (size_t)nsteps, nullptr);
+    for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
+    for (int32_t s = 0; s < nsteps; ++s) {
+        int par = (int)(c->k & 1);
+        HIPCHK(c, hipEventRecord(ev[3 * s], c->stream));
+        launch_stage(c->shape, kLagrange, c->stream, I, par);
+        HIPCHK(c, hipEventRecord(ev[3 * s + 1], c->stream));
+        launch_stage(c->shape, kEuler, c->stream, I, par);
+        HIPCHK(c, hipEventRecord(ev[3 * s + 2], c->stream));
+        HIPCHK(c, hipGetLastError());
+        c->k++;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double tl = 0.0, te = 0.0;
+    for (int32_t s = 0; s < nsteps; ++s) {
+        float a = 0.0f, b = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&a, ev[3 * s], ev[3 * s + 1]));
+        HIPCHK(c, hipEventElapsedTime(&b, ev[3 * s + 1], ev[3 * s + 2]));
+        tl += a;
+        te += b;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    avg_ms[0] = tl / nsteps;
+    avg_ms[1] = te / nsteps;
+    return SW_OK;
+}
 
 int sw_sync(sw_ctx *c)
 {
@@ -1486,6 +1639,8 @@ int sw_get_sums(sw_ctx *c, sw_sums *out)
     out->vp = hc.vp; out->vs = hc.vs; out->D = hc.D;
     out->step = c->step0 + kk;
     out->active_tiles = (c->par.flags & SW_FLAG_UNFUSED) ? -1 : nact;
+    out->cells_lagrange = (int64_t)hc.work[0];
+    out->cells_euler = (int64_t)hc.work[1];
     out->binding_term = hc.binding;
     out->error = hc.err;
     return SW_OK;
