@@ -2,7 +2,8 @@
 
 Workload (N=1): the 2-D dam break over a seeded fractal bed, 2048 x 2048 cells,
 dx = 2 m, 1 m dam line, 8 m reservoir, dry downstream, open boundaries,
-psi = 0.4, Manning n = 0.03, d50 = 0.5 mm, Eq. 4 bedload, K = 0.3.  One "step"
+psi = 0.4, Manning n = 0.03, Grass bedload (A_G = 0.001, m = 2; d50 = 0.5 mm
+for the Shamov critical speed), K = 0.3.  One "step"
 is one CSPH-TVD time step over the whole grid (Lagrangian stage with the Eq. 7
 step, then the fused Euler stage), replayed from a HIP graph with dry tiles
 skipped.  Inputs are resident on the GPU before the timed region starts.
@@ -45,6 +46,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0: auto, ~10-30 s)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 512 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -58,17 +61,32 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
+    # a real (non-null) stream: the solver orders its kernels on it and the
+    # timing events are recorded on it
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+
+    if args.calibrate_copy:
+        # a plain streaming kernel of known size (1 GiB read, 1 GiB written,
+        # larger than the 256 MB Infinity Cache) to scale the HBM counters
+        src = torch.ones(256 * 1024 * 1024, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        log("[bench] counter calibration: 3 x (1073741824 bytes read + written) by the mul kernel")
+        del src, dst
 
     log(f"[bench] building workload dam_break_fractal n={args.n}")
     w = W.dam_break_fractal(n=args.n, steps=args.steps).as_float32()
     cells = w.nx * w.ny
+    assert stream.cuda_stream != 0
     s = csph.solver_for(w, stream=stream.cuda_stream)
     log(f"[bench] warmup {args.warmup} steps")
     if args.warmup:
         s.advance(args.warmup)
         s.sync()
-    s.set_state(w.H, w.qx, w.qy)  # timed steps start from the initial state
+    s.reset(w)  # timed steps start from the initial bed and state
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps")
     e0 = torch.cuda.Event(enable_timing=True)
@@ -88,7 +106,7 @@ def main():
         f"t={sums['t']:.3f} s, wet={sums['wet_cells']}")
 
     # per-kernel durations (HIP events on the solver's stream), same steps again
-    s.set_state(w.H, w.qx, w.qy)
+    s.reset(w)
     lag_ms, eul_ms = s.advance_profiled(args.steps)
     ps = s.get_sums()
     eul_cells = ps["cells_euler"] / args.steps
@@ -115,7 +133,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"dam_break_fractal_{w.nx}x{w.ny}", "grid": [w.nx, w.ny],
                    "dx_m": w.dx, "reservoir_m": 8.0, "dam_m": 1.0, "relief_m": 10.0,
-                   "bc": "open", "cfl": w.cfl, "sed_law": "eq4", "skip_dry_tiles": True,
+                   "bc": "open", "cfl": w.cfl, "sed_law": "grass", "skip_dry_tiles": True,
                    "graph": True, "parallelism": "single-gpu"},
         "hbm_frac_algorithmic": round(value * STEP_BYTES / HBM_PEAK_GBS, 4),
         "roofline": {"kernel": "k_euler_t", "bound": "hbm", "achieved": round(achieved, 1),
@@ -144,7 +162,7 @@ def river_valley_rates(csph, W, torch, n=8192, steps=2000):
     for name, flags in (("skip_on", csph.SW_FLAG_HGS), ("skip_off", 0)):
         s = csph.solver_for(w, stream=stream.cuda_stream, flags=flags)
         s.advance(20)
-        s.set_state(w.H, w.qx, w.qy)
+        s.reset(w)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)

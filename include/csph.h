@@ -161,6 +161,19 @@ int sw_advance_fixed_dt(sw_ctx *ctx, int32_t nsteps, double dt);
  * path); synchronises.  SW_ERR_ARG on the unfused path. */
 int sw_advance_profiled(sw_ctx *ctx, int32_t nsteps, double *avg_ms);
 
+/* Use tile shape tile_x x tile_y cells per workgroup for later steps (one of
+ * 64x8, 64x4, 64x16, 128x4; SW_ERR_ARG otherwise).  Results do not depend on
+ * the shape. */
+int sw_set_tile_shape(sw_ctx *ctx, int32_t tile_x, int32_t tile_y);
+
+/* Tile-shape autotuner: from the current state, time nsteps of each tile
+ * shape the library has (64x8, 64x4, 64x16, 128x4 cells per workgroup), put
+ * the state, time and balances back, and keep the fastest shape for every
+ * later step.  All shapes give bit-identical results.  Allocates and frees a
+ * copy of the state; synchronises.  *tile_x, *tile_y (may be NULL) receive
+ * the chosen shape. */
+int sw_autotune(sw_ctx *ctx, int32_t nsteps, int32_t *tile_x, int32_t *tile_y);
+
 /* Wait for queued work; returns the sticky device error, if any. */
 int sw_sync(sw_ctx *ctx);
 
@@ -172,6 +185,37 @@ int sw_get_sums(sw_ctx *ctx, sw_sums *out);
 
 /* Text of the last error on ctx (never NULL; "" if none). */
 const char *sw_last_error(const sw_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Ensembles: many grids (uneven sizes, own terrain, soil, inflow and Eq. 7
+ * step) advanced together.  Each step is one launch of the Eq. 7 reduction
+ * (one workgroup per member) and one launch per stage over a table of all
+ * members' tiles, replayed from a HIP graph.  Each member computes exactly
+ * what it computes alone (bit for bit).
+ * ------------------------------------------------------------------------ */
+typedef struct swb_ctx swb_ctx;
+
+/* Group n member solvers made by sw_create and loaded with the sw_set_*
+ * calls.  Members must share one HIP stream, be distinct, and not use
+ * SW_FLAG_UNFUSED.  The batch references the members and does not own them:
+ * destroy the batch before its members.  Members stay usable on their own
+ * (sw_get_fields, sw_get_sums, sw_set_*, sw_advance). */
+int swb_create(int32_t n, sw_ctx *const *members, swb_ctx **out);
+int swb_destroy(swb_ctx *batch);
+
+/* Tile shape of every member while it is advanced by the batch (as
+ * sw_set_tile_shape). */
+int swb_set_tile_shape(swb_ctx *batch, int32_t tile_x, int32_t tile_y);
+
+/* Advance every member nsteps steps, each with its own Eq. 7 step.  All
+ * members must hold a state and stand at steps of the same parity
+ * (SW_ERR_STATE otherwise).  Asynchronous; device errors are per member. */
+int swb_advance(swb_ctx *batch, int32_t nsteps);
+
+/* Wait for the batch; returns the first member's sticky device error. */
+int swb_sync(swb_ctx *batch);
+
+const char *swb_last_error(const swb_ctx *batch);
 
 #ifdef __cplusplus
 }

@@ -79,10 +79,18 @@ SIGNATURES = [
     ("sw_advance", C.c_int, [_ctxp, C.c_int32]),
     ("sw_advance_fixed_dt", C.c_int, [_ctxp, C.c_int32, C.c_double]),
     ("sw_advance_profiled", C.c_int, [_ctxp, C.c_int32, C.POINTER(C.c_double)]),
+    ("sw_set_tile_shape", C.c_int, [_ctxp, C.c_int32, C.c_int32]),
+    ("sw_autotune", C.c_int, [_ctxp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     ("sw_sync", C.c_int, [_ctxp]),
     ("sw_get_fields", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     ("sw_get_sums", C.c_int, [_ctxp, C.POINTER(sw_sums)]),
     ("sw_last_error", C.c_char_p, [_ctxp]),
+    ("swb_create", C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
+    ("swb_destroy", C.c_int, [C.c_void_p]),
+    ("swb_set_tile_shape", C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    ("swb_advance", C.c_int, [C.c_void_p, C.c_int32]),
+    ("swb_sync", C.c_int, [C.c_void_p]),
+    ("swb_last_error", C.c_char_p, [C.c_void_p]),
 ]
 
 
@@ -229,6 +237,15 @@ class Solver:
         _check(self.ctx, lib.sw_advance_profiled(self.ctx, int(nsteps), out))
         return out[0], out[1]
 
+    def set_tile_shape(self, tx, ty):
+        _check(self.ctx, lib.sw_set_tile_shape(self.ctx, int(tx), int(ty)))
+
+    def autotune(self, nsteps=20):
+        """Pick the fastest tile shape on the current state; returns (tile_x, tile_y)."""
+        tx, ty = C.c_int32(), C.c_int32()
+        _check(self.ctx, lib.sw_autotune(self.ctx, int(nsteps), C.byref(tx), C.byref(ty)))
+        return tx.value, ty.value
+
     def sync(self):
         _check(self.ctx, lib.sw_sync(self.ctx))
 
@@ -248,6 +265,11 @@ class Solver:
         _check(self.ctx, lib.sw_get_sums(self.ctx, C.byref(s)))
         return s.as_dict()
 
+    def reset(self, w):
+        """Restart from workload ``w``'s initial bed and state (time back to 0)."""
+        self.set_bed(w.b)
+        self.set_state(w.H, w.qx, w.qy)
+
     def load_workload(self, w):
         """Upload a paper_2103_15196_amd.workloads.Workload (bed, soil, state, sources)."""
         self.set_bed(w.b)
@@ -266,3 +288,40 @@ def solver_for(w, stream=None, **params) -> Solver:
     s = Solver(w.nx, w.ny, w.dx, w.bc, stream=stream, **kw)
     s.load_workload(w)
     return s
+
+
+def _bcheck(b, rc):
+    if rc != SW_OK:
+        msg = lib.swb_last_error(b).decode() if b else ""
+        raise SwError(rc, msg)
+
+
+class Batch:
+    """Owns one swb_ctx over existing Solver members (which it keeps alive)."""
+
+    def __init__(self, members):
+        self.members = list(members)
+        arr = (C.c_void_p * len(self.members))(*[m.ctx for m in self.members])
+        h = C.c_void_p()
+        _bcheck(None, lib.swb_create(len(self.members), arr, C.byref(h)))
+        self.ctx = h
+
+    def close(self):
+        if self.ctx:
+            lib.swb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tile_shape(self, tx, ty):
+        _bcheck(self.ctx, lib.swb_set_tile_shape(self.ctx, int(tx), int(ty)))
+
+    def advance(self, nsteps):
+        _bcheck(self.ctx, lib.swb_advance(self.ctx, int(nsteps)))
+
+    def sync(self):
+        _bcheck(self.ctx, lib.swb_sync(self.ctx))

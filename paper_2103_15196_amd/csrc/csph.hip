@@ -91,11 +91,11 @@ __device__ __forceinline__ void cell_maxima(const KPar &P, float H, float qx, fl
 {
     float w = wdes(H, P);
     float u = qx * w, v = qy * w;
-    float sp = sqrtf(u * u + v * v);
+    float sp = sqrtf(sumsq(u, v));
     float cs = sqrtf(P.g * (H > 0.0f ? H : 0.0f));
     float jx, jy;
     bedload(P, H, u, v, soil(P.nM, P.nM_s, c), soil(P.d50, P.d50_s, c), jx, jy);
-    float Dc = sqrtf(jx * jx + jy * jy) / (1.0f - soil(P.psi, P.psi_s, c));
+    float Dc = sqrtf(sumsq(jx, jy)) / (1.0f - soil(P.psi, P.psi_s, c));
     bool fin = isfinite(H) && isfinite(qx) && isfinite(qy) && isfinite(b) && isfinite(sp) &&
                isfinite(Dc);
     if (!fin) {
@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(BX * BY) k_lagrange(KPar P, const Ctrl *__rest
     float qxc = S.qx[c], qyc = S.qy[c];
     float uc = qxc * wc, vc = qyc * wc;
     float nM = soil(P.nM, P.nM_s, c);
-    float gam = friction_rate(P, nM, sqrtf(uc * uc + vc * vc), Hc);
+    float gam = friction_rate(P, nM, sqrtf(sumsq(uc, vc)), Hc);
     // K4: predictor momentum and half-step depths
     float hdt = 0.5f * dt;
     float qpx = (qxc + hdt * Snx) / (1.0f + hdt * gam);
@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(BX * BY) k_lagrange(KPar P, const Ctrl *__rest
     // K5: forces at t_{n+1/2}
     float Shx = face_force(P, HhW, bW, Hh, bc, HhE, bE, hasW, hasE);
     float Shy = face_force(P, HhS, bS, Hh, bc, HhN, bN, hasS, hasN);
-    float gamh = friction_rate(P, nM, sqrtf(upx * upx + upy * upy), Hh);
+    float gamh = friction_rate(P, nM, sqrtf(sumsq(upx, upy)), Hh);
     // K6: corrector (Lagrangian momentum)
     QLx[c] = (qxc + dt * Shx) / (1.0f + dt * gamh);
     QLy[c] = (qyc + dt * Shy) / (1.0f + dt * gamh);
@@ -359,7 +359,7 @@ __device__ __forceinline__ float theta_of(const KPar &P, const StateView &S, con
     if (i < 0 || j < 0 || i >= P.nx || j >= P.ny) return 1.0f;  // ghost donor
     float fe = F.xH[j * (P.nx + 1) + i + 1], fw = F.xH[j * (P.nx + 1) + i];
     float gn = F.yH[(j + 1) * P.nx + i], gs = F.yH[j * P.nx + i];
-    float out = fmaxf(0.0f, fe) + fmaxf(0.0f, -fw) + fmaxf(0.0f, gn) + fmaxf(0.0f, -gs);
+    float out = (fmaxf(0.0f, fe) + fmaxf(0.0f, -fw)) + (fmaxf(0.0f, gn) + fmaxf(0.0f, -gs));
     return out > 0.0f ? fminf(1.0f, S.H[j * P.pitch + i] * P.dx / (dt * out)) : 1.0f;
 }
 
@@ -442,82 +442,103 @@ struct Inst {
     uint8_t *act[2];
     uint8_t *synced;
     const uint8_t *force;
+    uint4 *tmax[2];  // per tile: Eq. 7 maxima of the state the tile will step from (float bits) + nonfinite flag
     int ntx, nty, hgs;
 };
 
-// Eq. 7 step from ring `par` of the maxima slots.  Every block computes the
-// same value; the lead block of the grid publishes it (time ring, balances,
-// error, step counter) and clears the slots the Euler stage of this step fills.
-__device__ bool block_dt(Ctrl *ctrl, int par, const StepArgs &A, bool lead, double &dt_out)
+// Block maxima of three non-negative floats (as bits) and a flag, stored with
+// one plain 16-byte write for the tile (no atomics: per-tile slots).
+__device__ __forceinline__ void block_maxima_store(unsigned a, unsigned b, unsigned c, unsigned bad,
+                                                   uint4 *out)
 {
-    __shared__ double s_dt;
-    __shared__ int s_ok;
-    const int tid = threadIdx.x;
-    if (tid < 64) {
-        unsigned a = 0, b = 0, c = 0, bad = 0;
-        if (tid < NSLOT) {
-            a = ctrl->slot[par][tid][0]; b = ctrl->slot[par][tid][1];
-            c = ctrl->slot[par][tid][2]; bad = ctrl->slot[par][tid][3];
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            a = max(a, (unsigned)__shfl_xor((int)a, off));
-            b = max(b, (unsigned)__shfl_xor((int)b, off));
-            c = max(c, (unsigned)__shfl_xor((int)c, off));
-            bad = max(bad, (unsigned)__shfl_xor((int)bad, off));
-        }
-        if (tid == 0) {
-            int ok = ctrl->err == 0;
-            int err = 0;
-            double vp = __uint_as_float(a), vs = __uint_as_float(b), D = __uint_as_float(c);
-            double h = A.dx;
-            double t0 = vp > 0.0 ? h / (2.0 * vp) : INFINITY;
-            double t1 = vs > 0.0 ? h / vs : INFINITY;
-            double t2 = D > 0.0 ? h * h / (2.0 * D) : INFINITY;
-            double m = t0;
-            int which = 0;
-            if (t1 < m) { m = t1; which = 1; }
-            if (t2 < m) { m = t2; which = 2; }
-            double dt = A.cfl * m;
-            if (!(dt < A.dt_max)) { dt = A.dt_max; which = 3; }
-            if (bad) err = SW_ERR_NONFINITE;
-            else if (A.mode_fixed && A.dt_fixed > dt) err = SW_ERR_CFL;
-            if (A.mode_fixed) { dt = A.dt_fixed; which = 4; }
-            if (!err && dt < A.dt_min) err = SW_ERR_DT_UNDERFLOW;
-            if (err) ok = 0;
-            s_ok = ok;
-            s_dt = dt;
-            if (lead && ctrl->err == 0) {
-                const int kd = ctrl->kdev;
-                ctrl->vp = vp; ctrl->vs = vs; ctrl->D = D;
-                if (err) {
-                    ctrl->err = err;
-                    ctrl->err_k = kd;
-                } else {
-                    double tn = ctrl->t[par];
-                    double q = 0.0;
-                    if (A.has_inflow) {
-                        double d = tn + 0.5 * dt - A.t_peak;
-                        double pk = A.t_sigma > 0.0
-                                        ? A.q_peak * exp(-d * d / (2.0 * A.t_sigma * A.t_sigma))
-                                        : 0.0;
-                        q = A.q_base + pk;
-                        ctrl->in_w += dt * q;
-                    }
-                    ctrl->in_s += dt * A.qb_total;
-                    ctrl->qmid[par] = q;
-                    ctrl->dt[par] = dt;
-                    ctrl->t[par ^ 1] = tn + dt;
-                    ctrl->last_dt = dt;
-                    ctrl->binding = which;
-                    ctrl->kdev = kd + 1;
-                }
-            }
-        }
-        if (lead && tid < NSLOT * 4) (&ctrl->slot[par ^ 1][0][0])[tid] = 0u;
+    __shared__ unsigned red[4][NT / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        a = max(a, (unsigned)__shfl_xor((int)a, off));
+        b = max(b, (unsigned)__shfl_xor((int)b, off));
+        c = max(c, (unsigned)__shfl_xor((int)c, off));
+        bad = max(bad, (unsigned)__shfl_xor((int)bad, off));
+    }
+    const int tid = threadIdx.x, wv = tid >> 6;
+    if ((tid & 63) == 0) {
+        red[0][wv] = a; red[1][wv] = b; red[2][wv] = c; red[3][wv] = bad;
     }
     __syncthreads();
-    dt_out = s_dt;
-    return s_ok != 0;
+    if (tid == 0) {
+        for (int w = 1; w < NT / 64; ++w) {
+            a = max(a, red[0][w]); b = max(b, red[1][w]); c = max(c, red[2][w]);
+            bad = max(bad, red[3][w]);
+        }
+        *out = make_uint4(a, b, c, bad);
+    }
+}
+
+// K3: the Eq. 7 step of one grid from its per-tile maxima (one 1024-thread
+// block; the maximum does not depend on the order it is taken in).  Publishes
+// dt, the time ring, the source balances and the step counter, or the error.
+constexpr int RT = 1024;
+
+__device__ void reduce_dt(Ctrl *ctrl, int par, const StepArgs &A, const uint4 *__restrict__ tm,
+                          int ntiles)
+{
+    __shared__ unsigned red[4][RT / 64];
+    const int tid = threadIdx.x;
+    unsigned a = 0, b = 0, c = 0, bad = 0;
+    for (int t = tid; t < ntiles; t += RT) {
+        uint4 v = tm[t];
+        a = max(a, v.x); b = max(b, v.y); c = max(c, v.z); bad = max(bad, v.w);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a = max(a, (unsigned)__shfl_xor((int)a, off));
+        b = max(b, (unsigned)__shfl_xor((int)b, off));
+        c = max(c, (unsigned)__shfl_xor((int)c, off));
+        bad = max(bad, (unsigned)__shfl_xor((int)bad, off));
+    }
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = a; red[1][tid >> 6] = b; red[2][tid >> 6] = c; red[3][tid >> 6] = bad;
+    }
+    __syncthreads();
+    if (tid != 0 || ctrl->err) return;
+    for (int w = 1; w < RT / 64; ++w) {
+        a = max(a, red[0][w]); b = max(b, red[1][w]); c = max(c, red[2][w]); bad = max(bad, red[3][w]);
+    }
+    const int kd = ctrl->kdev;
+    double vp = __uint_as_float(a), vs = __uint_as_float(b), D = __uint_as_float(c);
+    ctrl->vp = vp; ctrl->vs = vs; ctrl->D = D;
+    double h = A.dx;
+    double t0 = vp > 0.0 ? h / (2.0 * vp) : INFINITY;
+    double t1 = vs > 0.0 ? h / vs : INFINITY;
+    double t2 = D > 0.0 ? h * h / (2.0 * D) : INFINITY;
+    double m = t0;
+    int which = 0;
+    if (t1 < m) { m = t1; which = 1; }
+    if (t2 < m) { m = t2; which = 2; }
+    double dt = A.cfl * m;
+    if (!(dt < A.dt_max)) { dt = A.dt_max; which = 3; }
+    int err = 0;
+    if (bad) err = SW_ERR_NONFINITE;
+    else if (A.mode_fixed && A.dt_fixed > dt) err = SW_ERR_CFL;
+    if (A.mode_fixed) { dt = A.dt_fixed; which = 4; }
+    if (!err && dt < A.dt_min) err = SW_ERR_DT_UNDERFLOW;
+    if (err) {
+        ctrl->err = err;
+        ctrl->err_k = kd;
+        return;
+    }
+    double tn = ctrl->t[par];
+    double q = 0.0;
+    if (A.has_inflow) {
+        double d = tn + 0.5 * dt - A.t_peak;
+        double pk = A.t_sigma > 0.0 ? A.q_peak * exp(-d * d / (2.0 * A.t_sigma * A.t_sigma)) : 0.0;
+        q = A.q_base + pk;
+        ctrl->in_w += dt * q;
+    }
+    ctrl->in_s += dt * A.qb_total;
+    ctrl->qmid[par] = q;
+    ctrl->dt[par] = dt;
+    ctrl->t[par ^ 1] = tn + dt;
+    ctrl->last_dt = dt;
+    ctrl->binding = which;
+    ctrl->kdev = kd + 1;
 }
 
 // Initial maxima (ring par) and wet-tile flags of a state set from the host.
@@ -540,7 +561,7 @@ __device__ void prepare_tile(const Inst &I, int par, int bx, int by)
         cell_maxima(P, h, qx[c], qy[c], b[c], c, mv, ms, mD, bad);
         if (h > 0.0f) s_any = 1;
     }
-    block_maxima(mv, ms, mD, bad, I.ctrl->slot[par], tile);
+    block_maxima_store(mv, ms, mD, bad, &I.tmax[par][tile]);
     if (tid == 0) I.act[par][tile] = (s_any || I.force[tile]) ? 1 : 0;
 }
 
@@ -553,15 +574,12 @@ __device__ void lagrange_tile(const Inst &I, int par, int bx, int by)
         sv[LHh][LW];
     __shared__ float sHh[TY + 2][TX + 2];
     const KPar &P = I.P;
-    double dtd;
-    if (!block_dt(I.ctrl, par, I.A, bx == 0 && by == 0, dtd)) return;
+    if (I.ctrl->err) return;
     const int tile = bx + by * I.ntx;
     if (I.hgs && !I.act[par][tile]) return;
-    const float dt = (float)dtd;
+    const float dt = (float)I.ctrl->dt[par];
     const int x0 = bx * TX, y0 = by * TY, tid = threadIdx.x;
     const float *H = I.H[par], *Qx = I.qx[par], *Qy = I.qy[par], *B = I.b[par];
-    if (tid == 0)
-        atomicAdd(&I.ctrl->work[0], (unsigned long long)(min(TX, P.nx - x0) * min(TY, P.ny - y0)));
     for (int q = tid; q < LW * LHh; q += NT) {
         int rx = q % LW, ry = q / LW;
         int i = x0 - 2 + rx, j = y0 - 2 + ry;
@@ -616,7 +634,7 @@ __device__ void lagrange_tile(const Inst &I, int par, int bx, int by)
         float uc = qxc * wc, vc = qyc * wc;
         int c = j * P.pitch + i;
         float nM = soil(P.nM, P.nM_s, c);
-        float gam = friction_rate(P, nM, sqrtf(uc * uc + vc * vc), Hc);
+        float gam = friction_rate(P, nM, sqrtf(sumsq(uc, vc)), Hc);
         float hdt = 0.5f * dt;
         float qpx = (qxc + hdt * Snx) / (1.0f + hdt * gam);
         float qpy = (qyc + hdt * Sny) / (1.0f + hdt * gam);
@@ -626,7 +644,7 @@ __device__ void lagrange_tile(const Inst &I, int par, int bx, int by)
         float HhS = hasS ? sHh[cy - 1][cx] : Hh, HhN = hasN ? sHh[cy + 1][cx] : Hh;
         float Shx = face_force(P, HhW, bW, Hh, bc, HhE, bE, hasW, hasE);
         float Shy = face_force(P, HhS, bS, Hh, bc, HhN, bN, hasS, hasN);
-        float gamh = friction_rate(P, nM, sqrtf(upx * upx + upy * upy), Hh);
+        float gamh = friction_rate(P, nM, sqrtf(sumsq(upx, upy)), Hh);
         I.QLx[c] = (qxc + dt * Shx) / (1.0f + dt * gamh);
         I.QLy[c] = (qyc + dt * Shy) / (1.0f + dt * gamh);
     }
@@ -674,13 +692,12 @@ __device__ void euler_tile(const Inst &I, int par, int bx, int by)
             if (tid == 0) {
                 I.synced[tile] = 1;
                 I.act[par ^ 1][tile] = 0;
+                I.tmax[par ^ 1][tile] = make_uint4(0u, 0u, 0u, 0u);
             }
             return;
         }
         if (tid == 0) I.synced[tile] = 0;
     }
-    if (tid == 0)
-        atomicAdd(&ctrl->work[1], (unsigned long long)(min(TX, nx - x0) * min(TY, ny - y0)));
     const float dt = (float)ctrl->dt[par];
     const double dtd = ctrl->dt[par];
     const bool wW = P.bcW == kWall, wE = P.bcE == kWall, wS = P.bcS == kWall, wN = P.bcN == kWall;
@@ -755,7 +772,7 @@ __device__ void euler_tile(const Inst &I, int par, int bx, int by)
         float th = 1.0f;
         if ((unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny) {
             float fe = fxH[cy][cx + 1], fw = fxH[cy][cx], gn = fyH[cy + 1][cx], gs = fyH[cy][cx];
-            float out = fmaxf(0.0f, fe) + fmaxf(0.0f, -fw) + fmaxf(0.0f, gn) + fmaxf(0.0f, -gs);
+            float out = (fmaxf(0.0f, fe) + fmaxf(0.0f, -fw)) + (fmaxf(0.0f, gn) + fmaxf(0.0f, -gs));
             th = out > 0.0f ? fminf(1.0f, ch[cy + 2][cx + 2] * P.dx / (dt * out)) : 1.0f;
         }
         rth[cy][cx] = th;
@@ -818,8 +835,50 @@ __device__ void euler_tile(const Inst &I, int par, int bx, int by)
         cell_maxima(P, Hn, qxn, qyn, bn, c, mv, ms, mD, bad);
         if (Hn > 0.0f) s_flag = 1;
     }
-    block_maxima(mv, ms, mD, bad, ctrl->slot[par ^ 1], tile);
+    block_maxima_store(mv, ms, mD, bad, &I.tmax[par ^ 1][tile]);
     if (tid == 0) I.act[par ^ 1][tile] = (s_flag || I.force[tile]) ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(RT) k_dt_t(Inst I, int par)
+{
+    reduce_dt(I.ctrl, par, I.A, I.tmax[par], I.ntx * I.nty);
+}
+
+// Ensemble: block m reduces member m.
+__global__ void __launch_bounds__(RT) k_dt_b(const Inst *__restrict__ insts, int par)
+{
+    const Inst &I = insts[blockIdx.x];
+    reduce_dt(I.ctrl, par, I.A, I.tmax[par], I.ntx * I.nty);
+}
+
+// Measurement only: cells the two stages of the step that read flag ring `par`
+// processed (a tile runs the Lagrangian stage if wet, the Euler stage if it or
+// a side neighbour is wet), added to ctrl->work.
+__global__ void __launch_bounds__(RT) k_count_t(Inst I, int par, int tx, int ty)
+{
+    __shared__ unsigned long long red[2][RT / 64];
+    unsigned long long nl = 0, ne = 0;
+    const uint8_t *act = I.act[par];
+    for (int t = threadIdx.x; t < I.ntx * I.nty; t += RT) {
+        int bx = t % I.ntx, by = t / I.ntx;
+        unsigned long long cells = (unsigned long long)(min(tx, I.P.nx - bx * tx) * min(ty, I.P.ny - by * ty));
+        bool run = act[t] || (bx > 0 && act[t - 1]) || (bx + 1 < I.ntx && act[t + 1]) ||
+                   (by > 0 && act[t - I.ntx]) || (by + 1 < I.nty && act[t + I.ntx]);
+        if (!I.hgs) run = true;
+        if (act[t] || !I.hgs) nl += cells;
+        if (run) ne += cells;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        nl += __shfl_xor(nl, off);
+        ne += __shfl_xor(ne, off);
+    }
+    if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = nl; red[1][threadIdx.x >> 6] = ne; }
+    __syncthreads();
+    if (threadIdx.x == 0 && !I.ctrl->err) {
+        for (int w = 1; w < RT / 64; ++w) { nl += red[0][w]; ne += red[1][w]; }
+        I.ctrl->work[0] += nl;
+        I.ctrl->work[1] += ne;
+    }
 }
 
 // Single grid: tile = block index.
@@ -969,6 +1028,7 @@ struct sw_ctx {
     std::vector<int32_t> forced_in, forced_qb;  // inflow / bed-source cells (flat indices)
     int shape = 0;                   // index into kShapes
     size_t max_tiles = 0;            // tile count of the smallest shape (flag capacity)
+    uint4 *tmax = nullptr;           // per-tile Eq. 7 maxima, two rings of max_tiles
     int graph_fixed = 0;
     double graph_dt = 0.0;
     std::string err;
@@ -1098,6 +1158,8 @@ Inst make_inst(const sw_ctx *c, const StepArgs &A)
     I.bnd = c->bnd;
     I.synced = synced_flags(c);
     I.force = force_flags(c);
+    I.tmax[0] = c->tmax;
+    I.tmax[1] = c->tmax + c->max_tiles;
     I.ntx = c->ntx;
     I.nty = c->nty;
     I.hgs = (c->par.flags & SW_FLAG_HGS) ? 1 : 0;
@@ -1105,14 +1167,37 @@ Inst make_inst(const sw_ctx *c, const StepArgs &A)
 }
 
 // Launch one tiled stage for the context's tile shape.
-enum Stage { kPrepare, kLagrange, kEuler };
+enum Stage { kPrepare, kDt, kLagrange, kEuler, kCount };
 
 template <int TX, int TY>
 void launch_stage_t(Stage st, hipStream_t s, const Inst &I, int par, dim3 g)
 {
     if (st == kPrepare) hipLaunchKernelGGL((k_prepare_t<TX, TY>), g, dim3(NT), 0, s, I, par);
+    else if (st == kDt) hipLaunchKernelGGL(k_dt_t, dim3(1), dim3(RT), 0, s, I, par);
+    else if (st == kCount) hipLaunchKernelGGL(k_count_t, dim3(1), dim3(RT), 0, s, I, par, TX, TY);
     else if (st == kLagrange) hipLaunchKernelGGL((k_lagrange_t<TX, TY>), g, dim3(NT), 0, s, I, par);
     else hipLaunchKernelGGL((k_euler_t<TX, TY>), g, dim3(NT), 0, s, I, par);
+}
+
+template <int TX, int TY>
+void launch_batch_t(Stage st, hipStream_t s, const Inst *insts, int nmem, const int *table,
+                    int ntab, int par)
+{
+    if (st == kDt) hipLaunchKernelGGL(k_dt_b, dim3(nmem), dim3(RT), 0, s, insts, par);
+    else if (st == kLagrange)
+        hipLaunchKernelGGL((k_lagrange_b<TX, TY>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
+    else hipLaunchKernelGGL((k_euler_b<TX, TY>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
+}
+
+void launch_batch(int shape, Stage st, hipStream_t s, const Inst *insts, int nmem,
+                  const int *table, int ntab, int par)
+{
+    switch (shape) {
+    case 0: launch_batch_t<64, 8>(st, s, insts, nmem, table, ntab, par); break;
+    case 1: launch_batch_t<64, 4>(st, s, insts, nmem, table, ntab, par); break;
+    case 2: launch_batch_t<64, 16>(st, s, insts, nmem, table, ntab, par); break;
+    default: launch_batch_t<128, 4>(st, s, insts, nmem, table, ntab, par); break;
+    }
 }
 
 void launch_stage(int shape, Stage st, hipStream_t s, const Inst &I, int par)
@@ -1138,6 +1223,11 @@ int prepare(sw_ctx *c)
     HIPCHK(c, hipMemsetAsync(synced_flags(c), 0, c->max_tiles, c->stream));
     Inst I = make_inst(c, make_step_args(c, 0, 0.0));
     launch_stage(c->shape, kPrepare, c->stream, I, cur);
+    if (c->par.flags & SW_FLAG_UNFUSED) {
+        KPar P = make_kpar(c);
+        hipLaunchKernelGGL(k_prepare, cell_grid(c), dim3(BX, BY), 0, c->stream, P, c->ctrl, cur,
+                           c->H[cur], c->qx[cur], c->qy[cur], c->b[cur]);
+    }
     HIPCHK(c, hipGetLastError());
     c->dirty = false;
     c->graph_ok = false;
@@ -1159,6 +1249,7 @@ void enqueue_tiled_step(sw_ctx *c, hipStream_t st, int par, const KPar &P, const
 {
     (void)P;
     Inst I = make_inst(c, A);
+    launch_stage(c->shape, kDt, st, I, par);
     launch_stage(c->shape, kLagrange, st, I, par);
     launch_stage(c->shape, kEuler, st, I, par);
 }
@@ -1314,9 +1405,11 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
     }
     c->QLx = c->buf + 8 * c->plane;
     c->QLy = c->buf + 9 * c->plane;
-    size_t nf = 4 * ((size_t)(c->nx + 1) * c->ny + (size_t)c->nx * (c->ny + 1));
-    if ((e = hipMalloc(&c->faces, nf * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc(faces)");
-    if ((e = hipMemset(c->faces, 0, nf * sizeof(float))) != hipSuccess) return bail(e, "hipMemset(faces)");
+    if (c->par.flags & SW_FLAG_UNFUSED) {  // face arrays of the unfused sequence only
+        size_t nf = 4 * ((size_t)(c->nx + 1) * c->ny + (size_t)c->nx * (c->ny + 1));
+        if ((e = hipMalloc(&c->faces, nf * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc(faces)");
+        if ((e = hipMemset(c->faces, 0, nf * sizeof(float))) != hipSuccess) return bail(e, "hipMemset(faces)");
+    }
     size_t nb = 4 * (size_t)(c->nx + c->ny);
     if ((e = hipMalloc(&c->bnd, nb * sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(bnd)");
     if ((e = hipMemset(c->bnd, 0, nb * sizeof(double))) != hipSuccess) return bail(e, "hipMemset(bnd)");
@@ -1332,6 +1425,8 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
     set_shape(c, 0);
     if ((e = hipMalloc(&c->tflags, 4 * c->max_tiles)) != hipSuccess) return bail(e, "hipMalloc(tiles)");
     if ((e = hipMemset(c->tflags, 0, 4 * c->max_tiles)) != hipSuccess) return bail(e, "hipMemset(tiles)");
+    if ((e = hipMalloc(&c->tmax, 2 * c->max_tiles * sizeof(uint4))) != hipSuccess) return bail(e, "hipMalloc(tmax)");
+    if ((e = hipMemset(c->tmax, 0, 2 * c->max_tiles * sizeof(uint4))) != hipSuccess) return bail(e, "hipMemset(tmax)");
     if ((e = hipMalloc(&c->ctrl, sizeof(Ctrl))) != hipSuccess) return bail(e, "hipMalloc(ctrl)");
     if ((e = hipMemset(c->ctrl, 0, sizeof(Ctrl))) != hipSuccess) return bail(e, "hipMemset(ctrl)");
     *out = c;
@@ -1353,6 +1448,7 @@ int sw_destroy(sw_ctx *c)
     (void)hipFree(c->qb);
     (void)hipFree(c->srcw);
     (void)hipFree(c->tflags);
+    (void)hipFree(c->tmax);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1426,8 +1522,12 @@ int sw_set_state(sw_ctx *c, const float *h, const float *hu, const float *hv, in
             return fail(c, SW_ERR_ARG, "initial depth must be finite and >= 0, discharges finite");
         if (H[q] == 0.0f) { H[q] = 0.0f; U[q] = 0.0f; V[q] = 0.0f; }
     }
-    // keep the bed, restart the step ring at k = 0
-    int cur = (int)(c->k & 1);
+    // keep the bed of the current state (the start of a failed step after a
+    // device error), restart the step ring at k = 0
+    Ctrl hc;
+    int rc0 = read_ctrl(c, &hc);
+    if (rc0) return rc0;
+    int cur = current_buffer(c, hc);
     if (cur != 0)
         HIPCHK(c, hipMemcpyAsync(c->b[0], c->b[cur], c->plane * sizeof(float),
                                  hipMemcpyDeviceToDevice, c->stream));
@@ -1553,11 +1653,13 @@ int sw_advance_profiled(sw_ctx *c, int32_t nsteps, double *avg_ms)
     for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
     for (int32_t s = 0; s < nsteps; ++s) {
         int par = (int)(c->k & 1);
+        launch_stage(c->shape, kDt, c->stream, I, par);
         HIPCHK(c, hipEventRecord(ev[3 * s], c->stream));
         launch_stage(c->shape, kLagrange, c->stream, I, par);
         HIPCHK(c, hipEventRecord(ev[3 * s + 1], c->stream));
         launch_stage(c->shape, kEuler, c->stream, I, par);
         HIPCHK(c, hipEventRecord(ev[3 * s + 2], c->stream));
+        launch_stage(c->shape, kCount, c->stream, I, par);
         HIPCHK(c, hipGetLastError());
         c->k++;
     }
@@ -1573,6 +1675,95 @@ int sw_advance_profiled(sw_ctx *c, int32_t nsteps, double *avg_ms)
     for (auto &e : ev) (void)hipEventDestroy(e);
     avg_ms[0] = tl / nsteps;
     avg_ms[1] = te / nsteps;
+    return SW_OK;
+}
+
+int sw_set_tile_shape(sw_ctx *c, int32_t tile_x, int32_t tile_y)
+{
+    if (!c) return SW_ERR_ARG;
+    for (int sh = 0; sh < kNumShapes; ++sh)
+        if (kShapes[sh].tx == tile_x && kShapes[sh].ty == tile_y) {
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            set_shape(c, sh);
+            return SW_OK;
+        }
+    return fail(c, SW_ERR_ARG, "unknown tile shape");
+}
+
+int sw_autotune(sw_ctx *c, int32_t nsteps, int32_t *tile_x, int32_t *tile_y)
+{
+    if (!c) return SW_ERR_ARG;
+    if (nsteps < 1) return fail(c, SW_ERR_ARG, "nsteps must be >= 1");
+    if (!c->have_state) return fail(c, SW_ERR_STATE, "autotune before sw_set_state");
+    if (c->par.flags & SW_FLAG_UNFUSED) return fail(c, SW_ERR_ARG, "the unfused path has no tiles");
+    Ctrl saved;
+    int rc = read_ctrl(c, &saved);
+    if (rc) return rc;
+    if (saved.err) return fail(c, saved.err, "autotune with a pending device error");
+    const int64_t k0 = c->k;
+    const int cur = (int)(k0 & 1);
+    const size_t nb = 4 * (size_t)(c->nx + c->ny);
+    float *keep = nullptr;
+    double *keepb = nullptr;
+    HIPCHK(c, hipMalloc(&keep, 4 * c->plane * sizeof(float)));
+    hipError_t e = hipMalloc(&keepb, nb * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipFree(keep);
+        return fail(c, SW_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    float *src[4] = {c->H[cur], c->qx[cur], c->qy[cur], c->b[cur]};
+    auto save_restore = [&](bool save) -> int {
+        for (int f = 0; f < 4; ++f) {
+            float *a = keep + f * c->plane, *b = src[f];
+            HIPCHK(c, hipMemcpyAsync(save ? a : b, save ? b : a, c->plane * sizeof(float),
+                                     hipMemcpyDeviceToDevice, c->stream));
+        }
+        HIPCHK(c, hipMemcpyAsync(save ? keepb : c->bnd, save ? c->bnd : keepb, nb * sizeof(double),
+                                 hipMemcpyDeviceToDevice, c->stream));
+        if (!save) {
+            HIPCHK(c, hipMemcpyAsync(c->ctrl, &saved, sizeof(Ctrl), hipMemcpyHostToDevice, c->stream));
+            c->k = k0;
+            c->dirty = true;
+        }
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return SW_OK;
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best = c->shape;
+    float best_ms = 0.0f;
+    rc = save_restore(true);
+    if (!rc && hipEventCreate(&e0) != hipSuccess) rc = fail(c, SW_ERR_HIP, "hipEventCreate");
+    if (!rc && hipEventCreate(&e1) != hipSuccess) rc = fail(c, SW_ERR_HIP, "hipEventCreate");
+    for (int sh = 0; sh < kNumShapes && !rc; ++sh) {
+        set_shape(c, sh);
+        if ((rc = prepare(c))) break;
+        Inst I = make_inst(c, make_step_args(c, 0, 0.0));
+        if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = fail(c, SW_ERR_HIP, "hipEventRecord"); break; }
+        for (int32_t s = 0; s < nsteps; ++s) {
+            int par = (int)(c->k & 1);
+            launch_stage(sh, kDt, c->stream, I, par);
+            launch_stage(sh, kLagrange, c->stream, I, par);
+            launch_stage(sh, kEuler, c->stream, I, par);
+            c->k++;
+        }
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(c, SW_ERR_HIP, "kernel timing failed");
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (sh == 0 || ms < best_ms) { best_ms = ms; best = sh; }
+        if ((rc = save_restore(false))) break;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (!rc) rc = save_restore(false);
+    (void)hipFree(keep);
+    (void)hipFree(keepb);
+    if (rc) return rc;
+    set_shape(c, best);
+    if (tile_x) *tile_x = kShapes[best].tx;
+    if (tile_y) *tile_y = kShapes[best].ty;
     return SW_OK;
 }
 
@@ -1647,5 +1838,203 @@ int sw_get_sums(sw_ctx *c, sw_sums *out)
 }
 
 const char *sw_last_error(const sw_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"
+
+// ===========================================================================
+// Ensembles: several grids advanced together, one launch per stage per step.
+// ===========================================================================
+
+struct swb_ctx {
+    std::vector<sw_ctx *> mem;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    Inst *d_insts = nullptr;
+    int *d_table = nullptr;
+    int ntab = 0;
+    int shape = 0;
+    hipGraphExec_t gexec = nullptr;
+    bool built = false;
+    std::string err;
+};
+
+namespace {
+
+int bfail(swb_ctx *b, int code, const std::string &msg)
+{
+    if (b) b->err = msg;
+    return code;
+}
+
+#define BHIPCHK(b, call)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return bfail((b), SW_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Instance table and tile table for the current member inputs and shape.
+int batch_build(swb_ctx *b)
+{
+    const int n = (int)b->mem.size();
+    std::vector<Inst> insts(n);
+    std::vector<int> table;
+    for (int m = 0; m < n; ++m) {
+        sw_ctx *c = b->mem[m];
+        if (c->shape != b->shape) set_shape(c, b->shape);
+        if (c->dirty) {
+            int rc = prepare(c);
+            if (rc) return bfail(b, rc, "member " + std::to_string(m) + ": " + c->err);
+        }
+        insts[m] = make_inst(c, make_step_args(c, 0, 0.0));
+        for (int by = 0; by < c->nty; ++by)
+            for (int bx = 0; bx < c->ntx; ++bx) {
+                table.push_back(m);
+                table.push_back(bx);
+                table.push_back(by);
+            }
+    }
+    (void)hipFree(b->d_insts);
+    (void)hipFree(b->d_table);
+    b->d_insts = nullptr;
+    b->d_table = nullptr;
+    BHIPCHK(b, hipMalloc(&b->d_insts, n * sizeof(Inst)));
+    BHIPCHK(b, hipMalloc(&b->d_table, table.size() * sizeof(int)));
+    BHIPCHK(b, hipMemcpy(b->d_insts, insts.data(), n * sizeof(Inst), hipMemcpyHostToDevice));
+    BHIPCHK(b, hipMemcpy(b->d_table, table.data(), table.size() * sizeof(int), hipMemcpyHostToDevice));
+    b->ntab = (int)(table.size() / 3);
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    b->built = true;
+    return SW_OK;
+}
+
+void batch_step(swb_ctx *b, hipStream_t st, int par)
+{
+    const int n = (int)b->mem.size();
+    launch_batch(b->shape, kDt, st, b->d_insts, n, b->d_table, b->ntab, par);
+    launch_batch(b->shape, kLagrange, st, b->d_insts, n, b->d_table, b->ntab, par);
+    launch_batch(b->shape, kEuler, st, b->d_insts, n, b->d_table, b->ntab, par);
+}
+
+bool batch_needs_build(const swb_ctx *b)
+{
+    if (!b->built) return true;
+    for (const sw_ctx *c : b->mem)
+        if (c->dirty || c->shape != b->shape) return true;
+    return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swb_create(int32_t n, sw_ctx *const *members, swb_ctx **out)
+{
+    if (!out || n < 1 || !members) return SW_ERR_ARG;
+    *out = nullptr;
+    for (int32_t m = 0; m < n; ++m) {
+        if (!members[m]) return SW_ERR_ARG;
+        if (members[m]->stream != members[0]->stream) return SW_ERR_ARG;
+        if (members[m]->par.flags & SW_FLAG_UNFUSED) return SW_ERR_ARG;
+        for (int32_t q = 0; q < m; ++q)
+            if (members[q] == members[m]) return SW_ERR_ARG;
+    }
+    swb_ctx *b = new swb_ctx();
+    b->mem.assign(members, members + n);
+    b->stream = members[0]->stream;
+    *out = b;
+    return SW_OK;
+}
+
+int swb_destroy(swb_ctx *b)
+{
+    if (!b) return SW_OK;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    (void)hipFree(b->d_insts);
+    (void)hipFree(b->d_table);
+    delete b;
+    return SW_OK;
+}
+
+int swb_set_tile_shape(swb_ctx *b, int32_t tile_x, int32_t tile_y)
+{
+    if (!b) return SW_ERR_ARG;
+    for (int sh = 0; sh < kNumShapes; ++sh)
+        if (kShapes[sh].tx == tile_x && kShapes[sh].ty == tile_y) {
+            BHIPCHK(b, hipStreamSynchronize(b->stream));
+            b->shape = sh;
+            b->built = false;
+            return SW_OK;
+        }
+    return bfail(b, SW_ERR_ARG, "unknown tile shape");
+}
+
+int swb_advance(swb_ctx *b, int32_t nsteps)
+{
+    if (!b) return SW_ERR_ARG;
+    if (nsteps < 0) return bfail(b, SW_ERR_ARG, "nsteps must be >= 0");
+    const int par0 = (int)(b->mem[0]->k & 1);
+    for (size_t m = 0; m < b->mem.size(); ++m) {
+        if (!b->mem[m]->have_state)
+            return bfail(b, SW_ERR_STATE, "member " + std::to_string(m) + " has no state");
+        if ((int)(b->mem[m]->k & 1) != par0)
+            return bfail(b, SW_ERR_STATE, "members are at steps of different parity");
+    }
+    if (batch_needs_build(b)) {
+        int rc = batch_build(b);
+        if (rc) return rc;
+    }
+    int32_t left = nsteps;
+    auto advance_members = [&](int s) {
+        for (sw_ctx *c : b->mem) c->k += s;
+    };
+    if (left > 0 && (b->mem[0]->k & 1)) {
+        batch_step(b, b->stream, 1);
+        BHIPCHK(b, hipGetLastError());
+        advance_members(1);
+        left--;
+    }
+    if (left >= 2) {
+        if (!b->gexec) {
+            if (!b->cap) BHIPCHK(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            BHIPCHK(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+            batch_step(b, b->cap, 0);
+            batch_step(b, b->cap, 1);
+            BHIPCHK(b, hipStreamEndCapture(b->cap, &g));
+            hipError_t e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return bfail(b, SW_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        for (; left >= 2; left -= 2) {
+            BHIPCHK(b, hipGraphLaunch(b->gexec, b->stream));
+            advance_members(2);
+        }
+    }
+    for (; left > 0; --left) {
+        batch_step(b, b->stream, (int)(b->mem[0]->k & 1));
+        BHIPCHK(b, hipGetLastError());
+        advance_members(1);
+    }
+    return SW_OK;
+}
+
+int swb_sync(swb_ctx *b)
+{
+    if (!b) return SW_ERR_ARG;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    for (size_t m = 0; m < b->mem.size(); ++m) {
+        int rc = sw_sync(b->mem[m]);
+        if (rc) return bfail(b, rc, "member " + std::to_string(m) + ": " + b->mem[m]->err);
+    }
+    return SW_OK;
+}
+
+const char *swb_last_error(const swb_ctx *b) { return b ? b->err.c_str() : "null batch"; }
 
 }  // extern "C"

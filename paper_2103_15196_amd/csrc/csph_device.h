@@ -38,6 +38,14 @@ struct KPar {
 
 __device__ __forceinline__ float soil(const float *a, float s, int c) { return a ? a[c] : s; }
 
+// a^2 + b^2 without fused multiply-add, so that swapping a and b (a grid and
+// its transpose) gives the same bits.
+__device__ __forceinline__ float sumsq(float a, float b)
+{
+#pragma clang fp contract(off)
+    return a * a + b * b;
+}
+
 // Desingularised reciprocal depth (Kurganov & Petrova): 1/H for H >= eps,
 // sqrt(2) H / sqrt(H^4 + eps^4) below, zero at H = 0.
 __device__ __forceinline__ float wdes(float H, const KPar &P)
@@ -53,8 +61,15 @@ __device__ __forceinline__ float minmod(float a, float b)
     return a > 0.0f ? fminf(a, b) : fmaxf(a, b);
 }
 
+// Powers through the hardware base-2 logarithm and exponential (v_log_f32,
+// v_exp_f32, about 1 ulp): x^p = 2^(p log2 x) for x > 0.
+__device__ __forceinline__ float powp(float x, float p)
+{
+    return __builtin_amdgcn_exp2f(p * __builtin_amdgcn_logf(x));
+}
+
 // x^(4/3) for x > 0.
-__device__ __forceinline__ float pow43(float x) { return x * cbrtf(x); }
+__device__ __forceinline__ float pow43(float x) { return powp(x, 4.0f / 3.0f); }
 
 // Manning friction rate g nM^2 |v| / max(H, eps)^(4/3) (semi-implicit).
 __device__ __forceinline__ float friction_rate(const KPar &P, float nM, float speed, float H)
@@ -71,12 +86,12 @@ __device__ __forceinline__ void bedload(const KPar &P, float H, float u, float v
     jx = 0.0f;
     jy = 0.0f;
     if (P.sed_law == 0 || !(H > P.h_sed)) return;
-    float speed = sqrtf(u * u + v * v);
-    float vk = P.C_Sh * cbrtf(d50) * sqrtf(cbrtf(H));
+    float speed = sqrtf(sumsq(u, v));
+    float vk = P.C_Sh * powp(d50, 1.0f / 3.0f) * powp(H, 1.0f / 6.0f);
     if (!(speed > vk)) return;
     float f;
     if (P.sed_law == 1) {
-        f = P.A_G * powf(speed, P.m_exp);
+        f = P.A_G * (P.m_exp == 2.0f ? speed * speed : powp(speed, P.m_exp));
     } else {
         float A = 0.05f * nM * nM * nM / (P.s_rel_m1 * sqrtf(P.g * H) * d50);
         float s2 = speed * speed;
@@ -238,19 +253,17 @@ __device__ __forceinline__ void hll(float g, const FaceState &l, const FaceState
     float cL = sqrtf(g * l.Hs), cR = sqrtf(g * r.Hs);
     float SL = fminf(l.ut - cL, r.ut - cR);
     float SR = fmaxf(l.ut + cL, r.ut + cR);
-    if (SL >= 0.0f) {
-        fH = FL0; fn = FL1; ft = FL2;
-    } else if (SR <= 0.0f) {
-        fH = FR0; fn = FR1; ft = FR2;
-    } else if (SR - SL <= 0.0f) {
-        fH = 0.0f; fn = 0.0f; ft = 0.0f;
-    } else {
-        float inv = 1.0f / (SR - SL);
-        float SLR = SL * SR;
-        fH = (SR * FL0 - SL * FR0 + SLR * (UR0 - UL0)) * inv;
-        fn = (SR * FL1 - SL * FR1 + SLR * (UR1 - UL1)) * inv;
-        ft = (SR * FL2 - SL * FR2 + SLR * (UR2 - UL2)) * inv;
-    }
+    // the four cases are selected, not branched: every lane evaluates the
+    // HLL average and keeps the upwind flux when both speeds share a sign
+    const bool left = SL >= 0.0f, right = SR <= 0.0f, fan = SR - SL > 0.0f;
+    const float inv = fan ? 1.0f / (SR - SL) : 0.0f;
+    const float SLR = SL * SR;
+    const float hH = (SR * FL0 - SL * FR0 + SLR * (UR0 - UL0)) * inv;
+    const float hn = (SR * FL1 - SL * FR1 + SLR * (UR1 - UL1)) * inv;
+    const float ht = (SR * FL2 - SL * FR2 + SLR * (UR2 - UL2)) * inv;
+    fH = left ? FL0 : (right ? FR0 : hH);
+    fn = left ? FL1 : (right ? FR1 : hn);
+    ft = left ? FL2 : (right ? FR2 : ht);
 }
 
 // Wall face fluxes (HLL against the mirrored ghost): no mass, no tangential
@@ -314,8 +327,8 @@ __device__ __forceinline__ float sed_flux(const KPar &P, int k, int n, bool wall
                                           float jyR, float bR)
 {
     if (k > 0 && k < n)
-        return bed_face_flux(P, dir == 0 ? jxL : jyL, sqrtf(jxL * jxL + jyL * jyL), bL,
-                             dir == 0 ? jxR : jyR, sqrtf(jxR * jxR + jyR * jyR), bR);
+        return bed_face_flux(P, dir == 0 ? jxL : jyL, sqrtf(sumsq(jxL, jyL)), bL,
+                             dir == 0 ? jxR : jyR, sqrtf(sumsq(jxR, jyR)), bR);
     if (k == n) return wallHi ? 0.0f : fmaxf(dir == 0 ? jxL : jyL, 0.0f);
     return wallLo ? 0.0f : fminf(dir == 0 ? jxR : jyR, 0.0f);
 }

@@ -103,11 +103,14 @@ def dam_break_1d(nx: int = 256, ny: int = 64, dx: float = 1.0, h_left: float = 2
 def dam_break_fractal(n: int = 2048, dx: float = 2.0, seed: int = 2, relief: float = 10.0,
                       dam_height: float = 1.0, depth: float = 8.0, manning: float = 0.03,
                       d50: float = 5e-4, psi: float = 0.4, steps: int = 1000,
-                      cfl: float = 0.3, ny: Optional[int] = None) -> Workload:
+                      cfl: float = 0.3, ny: Optional[int] = None,
+                      sed_law: int = SED_GRASS) -> Workload:
     """2-D dam break over a seeded fractal bed (spectral slope -2): a dam line
     `dam_height` above the terrain on column n/4, a reservoir upstream whose
     flat surface sits `depth` above the mean upstream bed, dry downstream,
-    open boundaries on all sides."""
+    open boundaries on all sides.  No grain size is part of this scenario, so
+    the bedload is the Grass law (A_G = 0.001, m = 2); d50 only sets the
+    Shamov critical speed."""
     nx = n
     ny = n if ny is None else ny
     b = fractal_surface(nx, ny, seed, relief)
@@ -119,7 +122,7 @@ def dam_break_fractal(n: int = 2048, dx: float = 2.0, seed: int = 2, relief: flo
     z = np.zeros((ny, nx))
     return Workload(name=f"dam_break_fractal_{nx}x{ny}", nx=nx, ny=ny, dx=dx,
                     bc=(OPEN, OPEN, OPEN, OPEN), H=H, qx=z.copy(), qy=z.copy(), b=b,
-                    nM=manning, d50=d50, psi=psi, steps=steps, cfl=cfl, sed_law=SED_EQ4,
+                    nM=manning, d50=d50, psi=psi, steps=steps, cfl=cfl, sed_law=sed_law,
                     extra={"seed": seed, "i_dam": i_dam, "zeta_r": zeta_r})
 
 

@@ -461,3 +461,29 @@ def test_nonfinite_state_is_rejected(oracle_mod):
     with pytest.raises(O.OracleError) as e:
         O.step(p, inp, s)
     assert e.value.code == -3
+
+
+def test_eq4_fractal_dam_break_is_ill_conditioned(oracle_mod):
+    """Why the 2-D fractal dam breaks use the Grass law: with Eq. 4's
+    coefficient (proportional to 1/sqrt(g h)) the bedload jumps from 0 to
+    O(10) m^2/s where a fast thin front crosses h_sed, and a 1e-7 relative
+    change of the initial depth (float32 rounding) moves the FP64 solution by
+    more than the parity tolerance within 100 steps; with the Grass law the same change stays
+    near rounding level (the parity tolerance on depth is 1e-4 m)."""
+    O = oracle_mod
+    base = W.dam_break_fractal(n=120, ny=96, dx=2.0, seed=7, relief=10.0, depth=8.0).as_float32()
+    rng = np.random.default_rng(0)
+    pert = base.H * (1 + 1e-7 * rng.standard_normal(base.H.shape))
+    out = {}
+    for law in (O.SED_EQ4, O.SED_GRASS):
+        res = []
+        for H in (base.H, pert):
+            w = W.Workload(**{k: getattr(base, k) for k in base.__dataclass_fields__})
+            w.H = H
+            p, inp, s = oracle_case(O, w, sed_law=law)
+            O.run(p, inp, s, 100)
+            res.append(s.H)
+        out[law] = float(np.abs(res[0] - res[1]).max())
+    assert out[O.SED_EQ4] > 1e-4
+    assert out[O.SED_GRASS] < 1e-5
+    assert out[O.SED_EQ4] > 30 * out[O.SED_GRASS]
