@@ -161,13 +161,15 @@ int sw_advance_fixed_dt(sw_ctx *ctx, int32_t nsteps, double dt);
  * path); synchronises.  SW_ERR_ARG on the unfused path. */
 int sw_advance_profiled(sw_ctx *ctx, int32_t nsteps, double *avg_ms);
 
-/* Use tile shape tile_x x tile_y cells per workgroup for later steps (one of
- * 64x8, 64x4, 64x16, 128x4; SW_ERR_ARG otherwise).  Results do not depend on
- * the shape. */
+/* Use tile shape tile_x x tile_y for later steps: 64x8, 64x4, 64x16 or 128x4
+ * cells per 256-thread workgroup staged through LDS, or 58x8 (the default),
+ * 58x16 or 58x32 cells per wavefront (strips: one lane per column plus a
+ * 3-column halo, rows marched in registers).  SW_ERR_ARG for any other shape.
+ * Results do not depend on the shape (bit-identical). */
 int sw_set_tile_shape(sw_ctx *ctx, int32_t tile_x, int32_t tile_y);
 
 /* Tile-shape autotuner: from the current state, time nsteps of each tile
- * shape the library has (64x8, 64x4, 64x16, 128x4 cells per workgroup), put
+ * shape the library has (the seven of sw_set_tile_shape), put
  * the state, time and balances back, and keep the fastest shape for every
  * later step.  All shapes give bit-identical results.  Allocates and frees a
  * copy of the state; synchronises.  *tile_x, *tile_y (may be NULL) receive

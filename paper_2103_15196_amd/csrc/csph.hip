@@ -84,18 +84,19 @@ __device__ __forceinline__ void block_maxima(unsigned a, unsigned b, unsigned c,
     }
 }
 
-// Eq. 7 maxima contributions of one cell of a state.
-__device__ __forceinline__ void cell_maxima(const KPar &P, float H, float qx, float qy, float b,
-                                            int c, unsigned &mv, unsigned &ms, unsigned &mD,
-                                            unsigned &bad)
+// Eq. 7 maxima contributions of one cell of a state with Manning coefficient
+// nM, grain size d50 and porosity psi.
+__device__ __forceinline__ void cell_maxima_s(const KPar &P, float H, float qx, float qy, float b,
+                                              float nM, float d50, float psi, unsigned &mv,
+                                              unsigned &ms, unsigned &mD, unsigned &bad)
 {
     float w = wdes(H, P);
     float u = qx * w, v = qy * w;
     float sp = sqrtf(sumsq(u, v));
     float cs = sqrtf(P.g * (H > 0.0f ? H : 0.0f));
     float jx, jy;
-    bedload(P, H, u, v, soil(P.nM, P.nM_s, c), soil(P.d50, P.d50_s, c), jx, jy);
-    float Dc = sqrtf(sumsq(jx, jy)) / (1.0f - soil(P.psi, P.psi_s, c));
+    bedload(P, H, u, v, nM, d50, jx, jy);
+    float Dc = sqrtf(sumsq(jx, jy)) / (1.0f - psi);
     bool fin = isfinite(H) && isfinite(qx) && isfinite(qy) && isfinite(b) && isfinite(sp) &&
                isfinite(Dc);
     if (!fin) {
@@ -105,6 +106,15 @@ __device__ __forceinline__ void cell_maxima(const KPar &P, float H, float qx, fl
     mv = max(mv, fbits_nonneg(sp));
     ms = max(ms, fbits_nonneg(sp + cs));
     mD = max(mD, fbits_nonneg(Dc));
+}
+
+// The same for cell c of the grid (soil read from its per-cell planes or scalars).
+__device__ __forceinline__ void cell_maxima(const KPar &P, float H, float qx, float qy, float b,
+                                            int c, unsigned &mv, unsigned &ms, unsigned &mD,
+                                            unsigned &bad)
+{
+    cell_maxima_s(P, H, qx, qy, b, soil(P.nM, P.nM_s, c), soil(P.d50, P.d50_s, c),
+                  soil(P.psi, P.psi_s, c), mv, ms, mD, bad);
 }
 
 // Maxima of the initial (or externally modified) state into slot ring k&1.
@@ -565,6 +575,126 @@ __device__ void prepare_tile(const Inst &I, int par, int bx, int by)
     if (tid == 0) I.act[par][tile] = (s_any || I.force[tile]) ? 1 : 0;
 }
 
+// ---------------------------------------------------------------------------
+// Per-cell arithmetic shared by the tile and strip kernels (one copy of each
+// expression, so both paths give the same bits).
+// ---------------------------------------------------------------------------
+
+// K4 half-step depth of cell (i, j) from its velocities and those of its four
+// neighbours (wall face: 0, open face: the cell's own velocity).
+__device__ __forceinline__ float half_depth_cell(const KPar &P, float H, float uc, float uW, float uE,
+                                                 float vc, float vS, float vN, int i, int j,
+                                                 float hdt_dx)
+{
+    float ue, uw, vn, vs;
+    if (i + 1 < P.nx) ue = 0.5f * (uc + uE);
+    else ue = (P.bcE == kWall) ? 0.0f : uc;
+    if (i > 0) uw = 0.5f * (uW + uc);
+    else uw = (P.bcW == kWall) ? 0.0f : uc;
+    if (j + 1 < P.ny) vn = 0.5f * (vc + vN);
+    else vn = (P.bcN == kWall) ? 0.0f : vc;
+    if (j > 0) vs = 0.5f * (vS + vc);
+    else vs = (P.bcS == kWall) ? 0.0f : vc;
+    float Jx = 1.0f + hdt_dx * (ue - uw);
+    float Jy = 1.0f + hdt_dx * (vn - vs);
+    return H / (Jx * Jy);
+}
+
+// K2 + K4 + K5 + K6 of one cell: forces at t_n from the depths and beds of the
+// cell (C) and its W/E/S/N neighbours, semi-implicit predictor, forces at
+// t_{n+1/2} from the half-step depths, corrector to the Lagrangian momentum.
+struct NbrDepths {
+    float C, W, E, S, N;
+};
+__device__ __forceinline__ void lagrange_cell(const KPar &P, float dt, const NbrDepths &Hd,
+                                              const NbrDepths &bd, const NbrDepths &Hh, bool hasW,
+                                              bool hasE, bool hasS, bool hasN, float qxc, float qyc,
+                                              float nM, float &QLx, float &QLy)
+{
+    float Snx = face_force(P, Hd.W, bd.W, Hd.C, bd.C, Hd.E, bd.E, hasW, hasE);
+    float Sny = face_force(P, Hd.S, bd.S, Hd.C, bd.C, Hd.N, bd.N, hasS, hasN);
+    float wc = wdes(Hd.C, P);
+    float uc = qxc * wc, vc = qyc * wc;
+    float gam = friction_rate(P, nM, sqrtf(sumsq(uc, vc)), Hd.C);
+    float hdt = 0.5f * dt;
+    float qpx = (qxc + hdt * Snx) / (1.0f + hdt * gam);
+    float qpy = (qyc + hdt * Sny) / (1.0f + hdt * gam);
+    float upx = qpx * wc, upy = qpy * wc;
+    float HhW = hasW ? Hh.W : Hh.C, HhE = hasE ? Hh.E : Hh.C;
+    float HhS = hasS ? Hh.S : Hh.C, HhN = hasN ? Hh.N : Hh.C;
+    float Shx = face_force(P, HhW, bd.W, Hh.C, bd.C, HhE, bd.E, hasW, hasE);
+    float Shy = face_force(P, HhS, bd.S, Hh.C, bd.C, HhN, bd.N, hasS, hasN);
+    float gamh = friction_rate(P, nM, sqrtf(sumsq(upx, upy)), Hh.C);
+    QLx = (qxc + dt * Shx) / (1.0f + dt * gamh);
+    QLy = (qyc + dt * Shy) / (1.0f + dt * gamh);
+}
+
+// Draining limiter of a cell of depth h from its four raw mass fluxes.
+__device__ __forceinline__ float drain_theta(const KPar &P, float dt, float h, float fw, float fe,
+                                             float gs, float gn)
+{
+    float out = (fmaxf(0.0f, fe) + fmaxf(0.0f, -fw)) + (fmaxf(0.0f, gn) + fmaxf(0.0f, -gs));
+    return out > 0.0f ? fminf(1.0f, h * P.dx / (dt * out)) : 1.0f;
+}
+
+// Raw fluxes and limiters around one cell, the inputs of its K8 update.
+struct CellFaces {
+    float th, thW, thE, thS, thN;        // limiters of the cell and its four neighbours
+    float xHw, xnw, xtw, xHe, xne, xte;  // raw x-face fluxes (mass, normal, tangential), W and E
+    float yHs, yns, yts, yHn, ynn, ytn;  // raw y-face fluxes, S and N
+    float Jw, Je, Js, Jn;                // bedload face fluxes
+};
+struct CellNew {
+    float H, qx, qy, b;
+    float FHw, FHe, GHs, GHn;  // limited mass fluxes (boundary balances)
+};
+
+// K8 of one cell: each face's water fluxes take the limiter of the cell the
+// mass leaves; conservative update of H and momentum from Q^L, Exner update
+// of b (Eq. 1), negative depth clamped, momentum re-desingularised below eps.
+__device__ __forceinline__ CellNew cell_update(const KPar &P, float dt, const CellFaces &F, float h,
+                                               float qx, float qy, float b, float QLx, float QLy,
+                                               float src, float psi, float qb)
+{
+    float sw = F.xHw > 0.0f ? F.thW : (F.xHw < 0.0f ? F.th : 1.0f);
+    float se = F.xHe > 0.0f ? F.th : (F.xHe < 0.0f ? F.thE : 1.0f);
+    float ss = F.yHs > 0.0f ? F.thS : (F.yHs < 0.0f ? F.th : 1.0f);
+    float sn = F.yHn > 0.0f ? F.th : (F.yHn < 0.0f ? F.thN : 1.0f);
+    CellNew o;
+    o.FHw = F.xHw * sw; o.FHe = F.xHe * se; o.GHs = F.yHs * ss; o.GHn = F.yHn * sn;
+    float Fxw = F.xnw * sw, Fxe = F.xne * se, Gxs = F.yts * ss, Gxn = F.ytn * sn;
+    float Fyw = F.xtw * sw, Fye = F.xte * se, Gys = F.yns * ss, Gyn = F.ynn * sn;
+    float QLxc = h > 0.0f ? QLx : qx;
+    float QLyc = h > 0.0f ? QLy : qy;
+    float r = dt * P.inv_dx;
+    float Hn = h - r * ((o.FHe - o.FHw) + (o.GHn - o.GHs)) + dt * src;
+    float qxn = QLxc - r * ((Fxe - Fxw) + (Gxn - Gxs));
+    float qyn = QLyc - r * ((Fye - Fyw) + (Gyn - Gys));
+    float om = 1.0f - psi;
+    float bn = b - dt / (om * P.dx) * ((F.Je - F.Jw) + (F.Jn - F.Js));
+    if (P.qb) bn += dt * qb / om;
+    if (Hn < 0.0f) Hn = 0.0f;
+    if (Hn < P.eps) {
+        float sc = Hn * wdes(Hn, P);
+        qxn *= sc;
+        qyn *= sc;
+    }
+    o.H = Hn; o.qx = qxn; o.qy = qyn; o.b = bn;
+    return o;
+}
+
+// FP64 balances of the water and sediment leaving through the boundary faces
+// of cell (i, j) (one accumulator per boundary face, owned by that cell).
+__device__ __forceinline__ void boundary_balances(const KPar &P, double *bnd, double wdx, int i,
+                                                  int j, const CellNew &o, const CellFaces &F)
+{
+    const int nx = P.nx, ny = P.ny, nb = 2 * (nx + ny);
+    if (i == 0) { bnd[j] += wdx * (double)(-o.FHw); bnd[nb + j] += wdx * (double)(-F.Jw); }
+    if (i == nx - 1) { bnd[ny + j] += wdx * (double)o.FHe; bnd[nb + ny + j] += wdx * (double)F.Je; }
+    if (j == 0) { bnd[2 * ny + i] += wdx * (double)(-o.GHs); bnd[nb + 2 * ny + i] += wdx * (double)(-F.Js); }
+    if (j == ny - 1) { bnd[2 * ny + nx + i] += wdx * (double)o.GHn; bnd[nb + 2 * ny + nx + i] += wdx * (double)F.Jn; }
+}
+
 // Lagrangian stage on a tile (K2, K4, K5, K6) with the Eq. 7 step (K3).
 template <int TX, int TY>
 __device__ void lagrange_tile(const Inst &I, int par, int bx, int by)
@@ -602,19 +732,8 @@ __device__ void lagrange_tile(const Inst &I, int par, int bx, int by)
         float Hh = 0.0f;
         if ((unsigned)i < (unsigned)P.nx && (unsigned)j < (unsigned)P.ny) {
             int rx = cx + 1, ry = cy + 1;
-            float uc = su[ry][rx], vc = sv[ry][rx];
-            float ue, uw, vn, vs;
-            if (i + 1 < P.nx) ue = 0.5f * (uc + su[ry][rx + 1]);
-            else ue = (P.bcE == kWall) ? 0.0f : uc;
-            if (i > 0) uw = 0.5f * (su[ry][rx - 1] + uc);
-            else uw = (P.bcW == kWall) ? 0.0f : uc;
-            if (j + 1 < P.ny) vn = 0.5f * (vc + sv[ry + 1][rx]);
-            else vn = (P.bcN == kWall) ? 0.0f : vc;
-            if (j > 0) vs = 0.5f * (sv[ry - 1][rx] + vc);
-            else vs = (P.bcS == kWall) ? 0.0f : vc;
-            float Jx = 1.0f + hdt_dx * (ue - uw);
-            float Jy = 1.0f + hdt_dx * (vn - vs);
-            Hh = sH[ry][rx] / (Jx * Jy);
+            Hh = half_depth_cell(P, sH[ry][rx], su[ry][rx], su[ry][rx - 1], su[ry][rx + 1],
+                                 sv[ry][rx], sv[ry - 1][rx], sv[ry + 1][rx], i, j, hdt_dx);
         }
         sHh[cy][cx] = Hh;
     }
@@ -625,28 +744,15 @@ __device__ void lagrange_tile(const Inst &I, int par, int bx, int by)
         if (i >= P.nx || j >= P.ny) continue;
         int rx = lx + 2, ry = ly + 2, cx = lx + 1, cy = ly + 1;
         bool hasW = i > 0, hasE = i + 1 < P.nx, hasS = j > 0, hasN = j + 1 < P.ny;
-        float Hc = sH[ry][rx], bc = sb[ry][rx];
-        float bW = sb[ry][rx - 1], bE = sb[ry][rx + 1], bS = sb[ry - 1][rx], bN = sb[ry + 1][rx];
-        float Snx = face_force(P, sH[ry][rx - 1], bW, Hc, bc, sH[ry][rx + 1], bE, hasW, hasE);
-        float Sny = face_force(P, sH[ry - 1][rx], bS, Hc, bc, sH[ry + 1][rx], bN, hasS, hasN);
-        float wc = wdes(Hc, P);
-        float qxc = sqx[ry][rx], qyc = sqy[ry][rx];
-        float uc = qxc * wc, vc = qyc * wc;
+        NbrDepths Hd{sH[ry][rx], sH[ry][rx - 1], sH[ry][rx + 1], sH[ry - 1][rx], sH[ry + 1][rx]};
+        NbrDepths bd{sb[ry][rx], sb[ry][rx - 1], sb[ry][rx + 1], sb[ry - 1][rx], sb[ry + 1][rx]};
+        NbrDepths Hh{sHh[cy][cx], sHh[cy][cx - 1], sHh[cy][cx + 1], sHh[cy - 1][cx], sHh[cy + 1][cx]};
         int c = j * P.pitch + i;
-        float nM = soil(P.nM, P.nM_s, c);
-        float gam = friction_rate(P, nM, sqrtf(sumsq(uc, vc)), Hc);
-        float hdt = 0.5f * dt;
-        float qpx = (qxc + hdt * Snx) / (1.0f + hdt * gam);
-        float qpy = (qyc + hdt * Sny) / (1.0f + hdt * gam);
-        float upx = qpx * wc, upy = qpy * wc;
-        float Hh = sHh[cy][cx];
-        float HhW = hasW ? sHh[cy][cx - 1] : Hh, HhE = hasE ? sHh[cy][cx + 1] : Hh;
-        float HhS = hasS ? sHh[cy - 1][cx] : Hh, HhN = hasN ? sHh[cy + 1][cx] : Hh;
-        float Shx = face_force(P, HhW, bW, Hh, bc, HhE, bE, hasW, hasE);
-        float Shy = face_force(P, HhS, bS, Hh, bc, HhN, bN, hasS, hasN);
-        float gamh = friction_rate(P, nM, sqrtf(sumsq(upx, upy)), Hh);
-        I.QLx[c] = (qxc + dt * Shx) / (1.0f + dt * gamh);
-        I.QLy[c] = (qyc + dt * Shy) / (1.0f + dt * gamh);
+        float QLx, QLy;
+        lagrange_cell(P, dt, Hd, bd, Hh, hasW, hasE, hasS, hasN, sqx[ry][rx], sqy[ry][rx],
+                      soil(P.nM, P.nM_s, c), QLx, QLy);
+        I.QLx[c] = QLx;
+        I.QLy[c] = QLy;
     }
 }
 
@@ -771,9 +877,8 @@ __device__ void euler_tile(const Inst &I, int par, int bx, int by)
         int i = x0 - 1 + cx, j = y0 - 1 + cy;
         float th = 1.0f;
         if ((unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny) {
-            float fe = fxH[cy][cx + 1], fw = fxH[cy][cx], gn = fyH[cy + 1][cx], gs = fyH[cy][cx];
-            float out = (fmaxf(0.0f, fe) + fmaxf(0.0f, -fw)) + (fmaxf(0.0f, gn) + fmaxf(0.0f, -gs));
-            th = out > 0.0f ? fminf(1.0f, ch[cy + 2][cx + 2] * P.dx / (dt * out)) : 1.0f;
+            th = drain_theta(P, dt, ch[cy + 2][cx + 2], fxH[cy][cx], fxH[cy][cx + 1], fyH[cy][cx],
+                             fyH[cy + 1][cx]);
         }
         rth[cy][cx] = th;
     }
@@ -788,55 +893,339 @@ __device__ void euler_tile(const Inst &I, int par, int bx, int by)
         int i = x0 + lx, j = y0 + ly;
         if (i >= nx || j >= ny) continue;
         int cx = lx + 1, cy = ly + 1, c = j * P.pitch + i;
-        float th = rth[cy][cx];
-        float thW = rth[cy][cx - 1], thE = rth[cy][cx + 1], thS = rth[cy - 1][cx], thN = rth[cy + 1][cx];
-        float rFw = fxH[cy][cx], rFe = fxH[cy][cx + 1], rGs = fyH[cy][cx], rGn = fyH[cy + 1][cx];
-        float sw = rFw > 0.0f ? thW : (rFw < 0.0f ? th : 1.0f);
-        float se = rFe > 0.0f ? th : (rFe < 0.0f ? thE : 1.0f);
-        float ss = rGs > 0.0f ? thS : (rGs < 0.0f ? th : 1.0f);
-        float sn = rGn > 0.0f ? th : (rGn < 0.0f ? thN : 1.0f);
-        float FHw = rFw * sw, FHe = rFe * se, GHs = rGs * ss, GHn = rGn * sn;
-        float Fxw = fxn[cy][cx] * sw, Fxe = fxn[cy][cx + 1] * se;
-        float Gxs = fyt[cy][cx] * ss, Gxn = fyt[cy + 1][cx] * sn;
-        float Fyw = fxt[cy][cx] * sw, Fye = fxt[cy][cx + 1] * se;
-        float Gys = fyn[cy][cx] * ss, Gyn = fyn[cy + 1][cx] * sn;
-        float Jw = sed_flux(P, i, nx, wW, wE, 0, rjx[cy][cx - 1], rjy[cy][cx - 1], rb[cy][cx - 1],
-                            rjx[cy][cx], rjy[cy][cx], rb[cy][cx]);
-        float Je = sed_flux(P, i + 1, nx, wW, wE, 0, rjx[cy][cx], rjy[cy][cx], rb[cy][cx],
-                            rjx[cy][cx + 1], rjy[cy][cx + 1], rb[cy][cx + 1]);
-        float Js = sed_flux(P, j, ny, wS, wN, 1, rjx[cy - 1][cx], rjy[cy - 1][cx], rb[cy - 1][cx],
-                            rjx[cy][cx], rjy[cy][cx], rb[cy][cx]);
-        float Jn = sed_flux(P, j + 1, ny, wS, wN, 1, rjx[cy][cx], rjy[cy][cx], rb[cy][cx],
-                            rjx[cy + 1][cx], rjy[cy + 1][cx], rb[cy + 1][cx]);
-        float h = SH[c], qx = Sqx[c], qy = Sqy[c], b = Sb[c];
-        float QLxc = h > 0.0f ? QLx[c] : qx;
-        float QLyc = h > 0.0f ? QLy[c] : qy;
-        float r = dt * P.inv_dx;
+        CellFaces F;
+        F.th = rth[cy][cx];
+        F.thW = rth[cy][cx - 1]; F.thE = rth[cy][cx + 1]; F.thS = rth[cy - 1][cx]; F.thN = rth[cy + 1][cx];
+        F.xHw = fxH[cy][cx]; F.xnw = fxn[cy][cx]; F.xtw = fxt[cy][cx];
+        F.xHe = fxH[cy][cx + 1]; F.xne = fxn[cy][cx + 1]; F.xte = fxt[cy][cx + 1];
+        F.yHs = fyH[cy][cx]; F.yns = fyn[cy][cx]; F.yts = fyt[cy][cx];
+        F.yHn = fyH[cy + 1][cx]; F.ynn = fyn[cy + 1][cx]; F.ytn = fyt[cy + 1][cx];
+        F.Jw = sed_flux(P, i, nx, wW, wE, 0, rjx[cy][cx - 1], rjy[cy][cx - 1], rb[cy][cx - 1],
+                        rjx[cy][cx], rjy[cy][cx], rb[cy][cx]);
+        F.Je = sed_flux(P, i + 1, nx, wW, wE, 0, rjx[cy][cx], rjy[cy][cx], rb[cy][cx],
+                        rjx[cy][cx + 1], rjy[cy][cx + 1], rb[cy][cx + 1]);
+        F.Js = sed_flux(P, j, ny, wS, wN, 1, rjx[cy - 1][cx], rjy[cy - 1][cx], rb[cy - 1][cx],
+                        rjx[cy][cx], rjy[cy][cx], rb[cy][cx]);
+        F.Jn = sed_flux(P, j + 1, ny, wS, wN, 1, rjx[cy][cx], rjy[cy][cx], rb[cy][cx],
+                        rjx[cy + 1][cx], rjy[cy + 1][cx], rb[cy + 1][cx]);
         float src = P.srcw ? P.srcw[c] * (float)ctrl->qmid[par] : 0.0f;
-        float Hn = h - r * ((FHe - FHw) + (GHn - GHs)) + dt * src;
-        float qxn = QLxc - r * ((Fxe - Fxw) + (Gxn - Gxs));
-        float qyn = QLyc - r * ((Fye - Fyw) + (Gyn - Gys));
-        float om = 1.0f - soil(P.psi, P.psi_s, c);
-        float bn = b - dt / (om * P.dx) * ((Je - Jw) + (Jn - Js));
-        if (P.qb) bn += dt * P.qb[c] / om;
-        if (Hn < 0.0f) Hn = 0.0f;
-        if (Hn < P.eps) {
-            float sc = Hn * wdes(Hn, P);
-            qxn *= sc;
-            qyn *= sc;
-        }
-        OH[c] = Hn; Oqx[c] = qxn; Oqy[c] = qyn; Ob[c] = bn;
-        double wdx = dtd * (double)P.dx;
-        const int nb = 2 * (nx + ny);
-        if (i == 0) { bnd[j] += wdx * (double)(-FHw); bnd[nb + j] += wdx * (double)(-Jw); }
-        if (i == nx - 1) { bnd[ny + j] += wdx * (double)FHe; bnd[nb + ny + j] += wdx * (double)Je; }
-        if (j == 0) { bnd[2 * ny + i] += wdx * (double)(-GHs); bnd[nb + 2 * ny + i] += wdx * (double)(-Js); }
-        if (j == ny - 1) { bnd[2 * ny + nx + i] += wdx * (double)GHn; bnd[nb + 2 * ny + nx + i] += wdx * (double)Jn; }
-        cell_maxima(P, Hn, qxn, qyn, bn, c, mv, ms, mD, bad);
-        if (Hn > 0.0f) s_flag = 1;
+        CellNew o = cell_update(P, dt, F, SH[c], Sqx[c], Sqy[c], Sb[c], QLx[c], QLy[c], src,
+                                soil(P.psi, P.psi_s, c), P.qb ? P.qb[c] : 0.0f);
+        OH[c] = o.H; Oqx[c] = o.qx; Oqy[c] = o.qy; Ob[c] = o.b;
+        boundary_balances(P, bnd, dtd * (double)P.dx, i, j, o, F);
+        cell_maxima(P, o.H, o.qx, o.qy, o.b, c, mv, ms, mD, bad);
+        if (o.H > 0.0f) s_flag = 1;
     }
     block_maxima_store(mv, ms, mD, bad, &I.tmax[par ^ 1][tile]);
     if (tid == 0) I.act[par ^ 1][tile] = (s_flag || I.force[tile]) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Strip path: one wavefront per tile of SX = 58 columns x S rows.  Lane l
+// holds column x0 - 3 + l, so the 3-column halo on each side sits in lanes
+// 0-2 and 61-63 and a cell's x neighbours are one DPP lane shift away; the
+// wave marches up its rows, keeping the rows its stencil still needs in
+// registers (the y neighbours), with the loads of the row two ahead in
+// flight.  No LDS and no barriers: the four waves of a workgroup are four
+// independent tiles stacked along y.  Every cell and face goes through the
+// same device functions as in the tile kernels, so the bits are the same.
+// ---------------------------------------------------------------------------
+
+constexpr int SX = 58;           // interior columns of a strip tile
+constexpr int SHALO = 3;         // halo columns on each side
+constexpr int SWAVES = NT / 64;  // strip tiles per workgroup (stacked along y)
+
+// The value lane l-1 (lane_prev) or l+1 (lane_next) holds; 0 in the lane that
+// has no such neighbour.  Called only where all 64 lanes are active.
+__device__ __forceinline__ float lane_prev(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_next(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ CellQ q_prev(const CellQ &q)
+{
+    return CellQ{lane_prev(q.z), lane_prev(q.h), lane_prev(q.ut), lane_prev(q.uLn), lane_prev(q.uLt)};
+}
+__device__ __forceinline__ CellQ q_next(const CellQ &q)
+{
+    return CellQ{lane_next(q.z), lane_next(q.h), lane_next(q.ut), lane_next(q.uLn), lane_next(q.uLt)};
+}
+
+// Wave-wide maxima of the Eq. 7 contributions and the wet flag of a strip
+// tile, stored with plain writes into the tile's slots.
+__device__ __forceinline__ void strip_maxima_store(const Inst &I, int par_out, int tile, unsigned a,
+                                                   unsigned b, unsigned c, unsigned bad, bool wet)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        a = max(a, (unsigned)__shfl_xor((int)a, off));
+        b = max(b, (unsigned)__shfl_xor((int)b, off));
+        c = max(c, (unsigned)__shfl_xor((int)c, off));
+        bad = max(bad, (unsigned)__shfl_xor((int)bad, off));
+    }
+    const bool any_wet = __ballot(wet) != 0;
+    if ((threadIdx.x & 63) == 0) {
+        I.tmax[par_out][tile] = make_uint4(a, b, c, bad);
+        I.act[par_out][tile] = (any_wet || I.force[tile]) ? 1 : 0;
+    }
+}
+
+// One row of a strip as loaded (clamped into the grid; the consumer zeroes
+// what lies outside): state, Lagrangian momentum, soil and sources.
+struct StripRow {
+    float h, qx, qy, b, Lx, Ly;
+    float nM, d50, psi, src, qb;
+};
+
+struct Flux3 {
+    float H, n, t;
+};
+struct BedCell {
+    float jx, jy, b;
+};
+
+// Lagrangian stage on a strip tile.
+template <int S>
+__device__ void lagrange_strip(const Inst &I, int par, int bx, int by)
+{
+    const KPar &P = I.P;
+    if (I.ctrl->err) return;
+    const int tile = bx + by * I.ntx;
+    if (I.hgs && !I.act[par][tile]) return;
+    const float dt = (float)I.ctrl->dt[par];
+    const int lane = threadIdx.x & 63;
+    const int nx = P.nx, ny = P.ny, pitch = P.pitch;
+    const int x0 = bx * SX, y0 = by * S;
+    const int i = x0 - SHALO + lane;
+    const bool inx = (unsigned)i < (unsigned)nx;
+    const bool mine = lane >= SHALO && lane < SHALO + SX && inx;
+    const int ci = min(max(i, 0), nx - 1);
+    const int jend = min(y0 + S, ny);
+    const float *H = I.H[par], *Qx = I.qx[par], *Qy = I.qy[par], *B = I.b[par];
+    const float hdt_dx = dt / (2.0f * P.dx);
+    struct LRow {
+        float h, qx, qy, b, nM;
+    };
+    auto load_row = [&](int r, LRow &w) {
+        const int c = min(max(r, 0), ny - 1) * pitch + ci;
+        w.h = H[c]; w.qx = Qx[c]; w.qy = Qy[c]; w.b = B[c];
+        w.nM = P.nM ? P.nM[c] : P.nM_s;
+    };
+    // rows r-3 .. r of depth and bed, r-2 .. r of momentum and Manning n,
+    // r-1 .. r of u, r-2 .. r of v, half-step depths of rows r-3 .. r-1
+    float H0 = 0, H1 = 0, H2 = 0, H3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+    float qx1 = 0, qx2 = 0, qx3 = 0, qy1 = 0, qy2 = 0, qy3 = 0, n1 = 0, n2 = 0, n3 = 0;
+    float u2 = 0, u3 = 0, v1 = 0, v2 = 0, v3 = 0;
+    float Hh0 = 0, Hh1 = 0, Hh2 = 0;
+    auto step = [&](int r, const LRow &in) {
+        H0 = H1; H1 = H2; H2 = H3; b0 = b1; b1 = b2; b2 = b3;
+        qx1 = qx2; qx2 = qx3; qy1 = qy2; qy2 = qy3; n1 = n2; n2 = n3;
+        u2 = u3; v1 = v2; v2 = v3;
+        const bool ok = inx && (unsigned)r < (unsigned)ny;
+        H3 = ok ? in.h : 0.0f;
+        b3 = ok ? in.b : 0.0f;
+        qx3 = ok ? in.qx : 0.0f;
+        qy3 = ok ? in.qy : 0.0f;
+        n3 = in.nM;
+        const float w = wdes(H3, P);
+        u3 = ok ? qx3 * w : 0.0f;
+        v3 = ok ? qy3 * w : 0.0f;
+        {  // K4 half-step depth of row r-1 (the tile's rows and a one-row ring)
+            const int j = r - 1;
+            const float uW = lane_prev(u2), uE = lane_next(u2);
+            float hh = 0.0f;
+            if (j >= y0 - 1 && j <= y0 + S && inx && (unsigned)j < (unsigned)ny)
+                hh = half_depth_cell(P, H2, u2, uW, uE, v2, v1, v3, i, j, hdt_dx);
+            Hh0 = Hh1; Hh1 = Hh2; Hh2 = hh;
+        }
+        const int j = r - 2;  // K2, K4, K5, K6 of row r-2
+        if (j >= y0 && j < jend) {
+            const float HW = lane_prev(H1), HE = lane_next(H1);
+            const float bW = lane_prev(b1), bE = lane_next(b1);
+            const float hW = lane_prev(Hh1), hE = lane_next(Hh1);
+            if (mine) {
+                NbrDepths Hd{H1, HW, HE, H0, H2};
+                NbrDepths bd{b1, bW, bE, b0, b2};
+                NbrDepths Hh{Hh1, hW, hE, Hh0, Hh2};
+                float QLx, QLy;
+                lagrange_cell(P, dt, Hd, bd, Hh, i > 0, i + 1 < nx, j > 0, j + 1 < ny, qx1, qy1, n1,
+                              QLx, QLy);
+                const int c = j * pitch + i;
+                I.QLx[c] = QLx;
+                I.QLy[c] = QLy;
+            }
+        }
+    };
+    const int rlo = y0 - 2, rhi = y0 + S + 1;  // S + 4 rows, an even count
+    LRow A, Bq;
+    load_row(rlo, A);
+    load_row(rlo + 1, Bq);
+    for (int r = rlo; r <= rhi; r += 2) {
+        step(r, A);
+        if (r + 2 <= rhi) load_row(r + 2, A);
+        step(r + 1, Bq);
+        if (r + 3 <= rhi) load_row(r + 3, Bq);
+    }
+}
+
+// Euler stage on a strip tile (K7 + limiter + K8) with the epilogue
+// reductions (Eq. 7 maxima and wet flag of the new state, boundary balances).
+template <int S>
+__device__ void euler_strip(const Inst &I, int par, int bx, int by)
+{
+    const KPar &P = I.P;
+    Ctrl *ctrl = I.ctrl;
+    if (ctrl->err) return;
+    const int ntx = I.ntx, nty = I.nty, tile = bx + by * ntx;
+    const int lane = threadIdx.x & 63;
+    const int nx = P.nx, ny = P.ny, pitch = P.pitch;
+    const int x0 = bx * SX, y0 = by * S;
+    const int i = x0 - SHALO + lane;
+    const bool inx = (unsigned)i < (unsigned)nx;
+    const bool mine = lane >= SHALO && lane < SHALO + SX && inx;
+    const int jend = min(y0 + S, ny);
+    const float *SH = I.H[par], *Sqx = I.qx[par], *Sqy = I.qy[par], *Sb = I.b[par];
+    float *OH = I.H[par ^ 1], *Oqx = I.qx[par ^ 1], *Oqy = I.qy[par ^ 1], *Ob = I.b[par ^ 1];
+    const float *QLx = I.QLx, *QLy = I.QLy;
+    if (I.hgs) {
+        const uint8_t *act_in = I.act[par];
+        bool run = act_in[tile] || (bx > 0 && act_in[tile - 1]) ||
+                   (bx + 1 < ntx && act_in[tile + 1]) || (by > 0 && act_in[tile - ntx]) ||
+                   (by + 1 < nty && act_in[tile + ntx]);
+        if (!run) {
+            if (!I.synced[tile] && mine)  // first skip since the tile last changed
+                for (int j = y0; j < jend; ++j) {
+                    int c = j * pitch + i;
+                    OH[c] = SH[c]; Oqx[c] = Sqx[c]; Oqy[c] = Sqy[c]; Ob[c] = Sb[c];
+                }
+            if (lane == 0) {
+                I.synced[tile] = 1;
+                I.act[par ^ 1][tile] = 0;
+                I.tmax[par ^ 1][tile] = make_uint4(0u, 0u, 0u, 0u);
+            }
+            return;
+        }
+        if (lane == 0) I.synced[tile] = 0;
+    }
+    const double dtd = ctrl->dt[par];
+    const float dt = (float)dtd;
+    const float qmid = (float)ctrl->qmid[par];
+    const double wdx = dtd * (double)P.dx;
+    const bool wW = P.bcW == kWall, wE = P.bcE == kWall, wS = P.bcS == kWall, wN = P.bcN == kWall;
+    const bool xghost = i == -1 || i == nx;
+    const bool face_x = i >= 0 && i <= nx;  // this lane's west face is a grid face
+    const int ci = min(max(i, 0), nx - 1);
+    auto load_row = [&](int r, StripRow &w) {
+        const int c = min(max(r, 0), ny - 1) * pitch + ci;
+        w.h = SH[c]; w.qx = Sqx[c]; w.qy = Sqy[c]; w.b = Sb[c]; w.Lx = QLx[c]; w.Ly = QLy[c];
+        w.nM = P.nM ? P.nM[c] : P.nM_s;
+        w.d50 = P.d50 ? P.d50[c] : P.d50_s;
+        w.psi = P.psi ? P.psi[c] : P.psi_s;
+        w.src = P.srcw ? P.srcw[c] : 0.0f;
+        w.qb = P.qb ? P.qb[c] : 0.0f;
+    };
+    // registers carried along the march, for the current row r:
+    StripRow w0{}, w1{}, w2{}, w3{};           // rows r-3 .. r as loaded
+    CellVals v0{}, v1{}, v2{}, v3{};           // remap inputs of rows r-3 .. r
+    Flux3 X3{}, X2{};                          // raw x fluxes of this lane's W face, rows r-3, r-2
+    Flux3 Y3{}, Y2{}, Y1{};                    // raw y fluxes of faces r-3, r-2, r-1
+    float th4 = 1.0f, th3 = 1.0f, th2 = 1.0f;  // limiters of rows r-4 .. r-2
+    BedCell J4{}, J3{}, J2{};                  // J0 and bed of rows r-4 .. r-2
+    unsigned mv = 0, ms = 0, mD = 0, bad = 0;
+    bool wet = false;
+    auto step = [&](int r, const StripRow &in) {
+        w0 = w1; w1 = w2; w2 = w3; w3 = in;
+        v0 = v1; v1 = v2; v2 = v3;
+        {  // remap inputs of row r (ghost cells beyond the domain edge)
+            const bool iny = (unsigned)r < (unsigned)ny;
+            const bool yghost = r == -1 || r == ny;
+            const CellVals v = cell_vals(P, in.h, in.qx, in.qy, in.b, in.Lx, in.Ly);
+            if (inx && iny) v3 = v;
+            else if (iny && xghost) v3 = mirror(v, 0, i < 0 ? wW : wE);
+            else if (inx && yghost) v3 = mirror(v, 1, r < 0 ? wS : wN);
+            else v3 = CellVals{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        }
+        Y3 = Y2; Y2 = Y1;
+        {  // y face r-1 (between rows r-2 and r-1) of this column
+            const int k = r - 1;
+            Flux3 f{0.0f, 0.0f, 0.0f};
+            if (k >= y0 - 1 && k <= y0 + S + 1 && inx && k >= 0 && k <= ny)
+                water_flux(P, k, ny, wS, wN, along(v0, 1), along(v1, 1), along(v2, 1),
+                           along(v3, 1), f.H, f.n, f.t);
+            Y1 = f;
+        }
+        const int jr = r - 2;  // ring/tile row whose x faces, J0 and limiter are due
+        const bool ring_row = jr >= y0 - 1 && jr <= y0 + S;
+        const bool row_in = (unsigned)jr < (unsigned)ny;
+        X3 = X2;
+        J4 = J3; J3 = J2;
+        th4 = th3; th3 = th2;
+        if (ring_row) {
+            {  // x faces of row r-2: this lane's W face from the cells two west .. one east
+                const CellQ c2 = along(v1, 0);
+                const CellQ c1 = q_prev(c2), c0 = q_prev(c1), c3 = q_next(c2);
+                Flux3 f{0.0f, 0.0f, 0.0f};
+                if (row_in && face_x) water_flux(P, i, nx, wW, wE, c0, c1, c2, c3, f.H, f.n, f.t);
+                X2 = f;
+            }
+            {  // zero-slope bedload J0 (Eqs. 3-5) and bed of row r-2
+                BedCell J{0.0f, 0.0f, 0.0f};
+                if (inx && row_in) {
+                    const float w = wdes(w1.h, P);
+                    bedload(P, w1.h, w1.qx * w, w1.qy * w, w1.nM, w1.d50, J.jx, J.jy);
+                    J.b = w1.b;
+                }
+                J2 = J;
+            }
+            {  // draining limiter of row r-2
+                const float fe = lane_next(X2.H);
+                th2 = (inx && row_in) ? drain_theta(P, dt, v1.h, X2.H, fe, Y2.H, Y1.H) : 1.0f;
+            }
+        } else {
+            X2 = Flux3{0.0f, 0.0f, 0.0f};
+            J2 = BedCell{0.0f, 0.0f, 0.0f};
+            th2 = 1.0f;
+        }
+        const int j = r - 3;  // K8 of row r-3
+        if (j >= y0 && j < jend) {
+            CellFaces F;
+            F.thW = lane_prev(th3); F.thE = lane_next(th3);
+            F.xHe = lane_next(X3.H); F.xne = lane_next(X3.n); F.xte = lane_next(X3.t);
+            const float jxW = lane_prev(J3.jx), jyW = lane_prev(J3.jy), bW = lane_prev(J3.b);
+            const float jxE = lane_next(J3.jx), jyE = lane_next(J3.jy), bE = lane_next(J3.b);
+            if (mine) {
+                F.th = th3; F.thS = th4; F.thN = th2;
+                F.xHw = X3.H; F.xnw = X3.n; F.xtw = X3.t;
+                F.yHs = Y3.H; F.yns = Y3.n; F.yts = Y3.t;
+                F.yHn = Y2.H; F.ynn = Y2.n; F.ytn = Y2.t;
+                F.Jw = sed_flux(P, i, nx, wW, wE, 0, jxW, jyW, bW, J3.jx, J3.jy, J3.b);
+                F.Je = sed_flux(P, i + 1, nx, wW, wE, 0, J3.jx, J3.jy, J3.b, jxE, jyE, bE);
+                F.Js = sed_flux(P, j, ny, wS, wN, 1, J4.jx, J4.jy, J4.b, J3.jx, J3.jy, J3.b);
+                F.Jn = sed_flux(P, j + 1, ny, wS, wN, 1, J3.jx, J3.jy, J3.b, J2.jx, J2.jy, J2.b);
+                const float src = P.srcw ? w0.src * qmid : 0.0f;
+                const CellNew o = cell_update(P, dt, F, w0.h, w0.qx, w0.qy, w0.b, w0.Lx, w0.Ly, src,
+                                              w0.psi, w0.qb);
+                const int c = j * pitch + i;
+                OH[c] = o.H; Oqx[c] = o.qx; Oqy[c] = o.qy; Ob[c] = o.b;
+                boundary_balances(P, I.bnd, wdx, i, j, o, F);
+                cell_maxima_s(P, o.H, o.qx, o.qy, o.b, w0.nM, w0.d50, w0.psi, mv, ms, mD, bad);
+                if (o.H > 0.0f) wet = true;
+            }
+        }
+    };
+    const int rlo = y0 - 3, rhi = y0 + S + 2;  // S + 6 rows, an even count
+    StripRow A, B;
+    load_row(rlo, A);
+    load_row(rlo + 1, B);
+    for (int r = rlo; r <= rhi; r += 2) {
+        step(r, A);
+        if (r + 2 <= rhi) load_row(r + 2, A);
+        step(r + 1, B);
+        if (r + 3 <= rhi) load_row(r + 3, B);
+    }
+    strip_maxima_store(I, par ^ 1, tile, mv, ms, mD, bad, wet);
 }
 
 __global__ void __launch_bounds__(RT) k_dt_t(Inst I, int par)
@@ -914,12 +1303,51 @@ __global__ void __launch_bounds__(NT) k_euler_b(const Inst *__restrict__ insts,
     euler_tile<TX, TY>(insts[t[0]], par, t[1], t[2]);
 }
 
-// Tile shapes the autotuner chooses from (TX x TY cells per 256-thread block).
+// Strip tiles: workgroup (bx, g) runs the SWAVES tiles (bx, SWAVES g + w),
+// one per wavefront w.
+template <int S>
+__global__ void __launch_bounds__(NT) k_lagrange_s(Inst I, int par)
+{
+    const int by = blockIdx.y * SWAVES + (threadIdx.x >> 6);
+    if (by < I.nty) lagrange_strip<S>(I, par, blockIdx.x, by);
+}
+template <int S>
+__global__ void __launch_bounds__(NT) k_euler_s(Inst I, int par)
+{
+    const int by = blockIdx.y * SWAVES + (threadIdx.x >> 6);
+    if (by < I.nty) euler_strip<S>(I, par, blockIdx.x, by);
+}
+
+// Ensemble strips: workgroup b runs tiles (table[3b+1], SWAVES table[3b+2] + w)
+// of member table[3b].
+template <int S>
+__global__ void __launch_bounds__(NT) k_lagrange_sb(const Inst *__restrict__ insts,
+                                                    const int *__restrict__ table, int par)
+{
+    const int *t = table + 3 * blockIdx.x;
+    const Inst &I = insts[t[0]];
+    const int by = t[2] * SWAVES + (threadIdx.x >> 6);
+    if (by < I.nty) lagrange_strip<S>(I, par, t[1], by);
+}
+template <int S>
+__global__ void __launch_bounds__(NT) k_euler_sb(const Inst *__restrict__ insts,
+                                                 const int *__restrict__ table, int par)
+{
+    const int *t = table + 3 * blockIdx.x;
+    const Inst &I = insts[t[0]];
+    const int by = t[2] * SWAVES + (threadIdx.x >> 6);
+    if (by < I.nty) euler_strip<S>(I, par, t[1], by);
+}
+
+// Tile shapes the autotuner chooses from: TX x TY cells per 256-thread
+// workgroup (LDS tiles), or SX x S cells per wavefront (strips, TX = SX).
 struct Shape {
     int tx, ty;
 };
-constexpr Shape kShapes[] = {{64, 8}, {64, 4}, {64, 16}, {128, 4}};
-constexpr int kNumShapes = 4;
+constexpr Shape kShapes[] = {{64, 8}, {64, 4}, {64, 16}, {128, 4}, {SX, 8}, {SX, 16}, {SX, 32}};
+constexpr int kNumShapes = 7;
+constexpr bool is_strip(int shape) { return kShapes[shape].tx == SX; }
+constexpr int kDefaultShape = 4;  // 58 x 8 strips
 
 // ---------------------------------------------------------------------------
 // FP64 sums: water volume, sediment volume, wet cells (two fixed-order passes).
@@ -1026,7 +1454,7 @@ struct sw_ctx {
     hipGraphExec_t gexec = nullptr;  // two tiled steps (even k, then odd k)
     bool graph_ok = false;
     std::vector<int32_t> forced_in, forced_qb;  // inflow / bed-source cells (flat indices)
-    int shape = 0;                   // index into kShapes
+    int shape = kDefaultShape;       // index into kShapes
     size_t max_tiles = 0;            // tile count of the smallest shape (flag capacity)
     uint4 *tmax = nullptr;           // per-tile Eq. 7 maxima, two rings of max_tiles
     int graph_fixed = 0;
@@ -1189,6 +1617,16 @@ void launch_batch_t(Stage st, hipStream_t s, const Inst *insts, int nmem, const 
     else hipLaunchKernelGGL((k_euler_b<TX, TY>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
 }
 
+template <int S>
+void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, int nmem, const int *table,
+                    int ntab, int par)
+{
+    if (st == kDt) hipLaunchKernelGGL(k_dt_b, dim3(nmem), dim3(RT), 0, s, insts, par);
+    else if (st == kLagrange)
+        hipLaunchKernelGGL((k_lagrange_sb<S>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
+    else hipLaunchKernelGGL((k_euler_sb<S>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
+}
+
 void launch_batch(int shape, Stage st, hipStream_t s, const Inst *insts, int nmem,
                   const int *table, int ntab, int par)
 {
@@ -1196,8 +1634,24 @@ void launch_batch(int shape, Stage st, hipStream_t s, const Inst *insts, int nme
     case 0: launch_batch_t<64, 8>(st, s, insts, nmem, table, ntab, par); break;
     case 1: launch_batch_t<64, 4>(st, s, insts, nmem, table, ntab, par); break;
     case 2: launch_batch_t<64, 16>(st, s, insts, nmem, table, ntab, par); break;
-    default: launch_batch_t<128, 4>(st, s, insts, nmem, table, ntab, par); break;
+    case 3: launch_batch_t<128, 4>(st, s, insts, nmem, table, ntab, par); break;
+    case 4: launch_batch_s<8>(st, s, insts, nmem, table, ntab, par); break;
+    case 5: launch_batch_s<16>(st, s, insts, nmem, table, ntab, par); break;
+    default: launch_batch_s<32>(st, s, insts, nmem, table, ntab, par); break;
     }
+}
+
+// Strip shapes: the prepare pass runs one workgroup per tile, the stage
+// kernels one wavefront per tile.
+template <int S>
+void launch_strip_t(Stage st, hipStream_t s, const Inst &I, int par)
+{
+    const dim3 gt(I.ntx, I.nty), gs(I.ntx, (I.nty + SWAVES - 1) / SWAVES);
+    if (st == kPrepare) hipLaunchKernelGGL((k_prepare_t<SX, S>), gt, dim3(NT), 0, s, I, par);
+    else if (st == kDt) hipLaunchKernelGGL(k_dt_t, dim3(1), dim3(RT), 0, s, I, par);
+    else if (st == kCount) hipLaunchKernelGGL(k_count_t, dim3(1), dim3(RT), 0, s, I, par, SX, S);
+    else if (st == kLagrange) hipLaunchKernelGGL((k_lagrange_s<S>), gs, dim3(NT), 0, s, I, par);
+    else hipLaunchKernelGGL((k_euler_s<S>), gs, dim3(NT), 0, s, I, par);
 }
 
 void launch_stage(int shape, Stage st, hipStream_t s, const Inst &I, int par)
@@ -1207,7 +1661,10 @@ void launch_stage(int shape, Stage st, hipStream_t s, const Inst &I, int par)
     case 0: launch_stage_t<64, 8>(st, s, I, par, g); break;
     case 1: launch_stage_t<64, 4>(st, s, I, par, g); break;
     case 2: launch_stage_t<64, 16>(st, s, I, par, g); break;
-    default: launch_stage_t<128, 4>(st, s, I, par, g); break;
+    case 3: launch_stage_t<128, 4>(st, s, I, par, g); break;
+    case 4: launch_strip_t<8>(st, s, I, par); break;
+    case 5: launch_strip_t<16>(st, s, I, par); break;
+    default: launch_strip_t<32>(st, s, I, par); break;
     }
 }
 
@@ -1422,7 +1879,7 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
         set_shape(c, sh);
         c->max_tiles = std::max(c->max_tiles, ntiles(c));
     }
-    set_shape(c, 0);
+    set_shape(c, kDefaultShape);
     if ((e = hipMalloc(&c->tflags, 4 * c->max_tiles)) != hipSuccess) return bail(e, "hipMalloc(tiles)");
     if ((e = hipMemset(c->tflags, 0, 4 * c->max_tiles)) != hipSuccess) return bail(e, "hipMemset(tiles)");
     if ((e = hipMalloc(&c->tmax, 2 * c->max_tiles * sizeof(uint4))) != hipSuccess) return bail(e, "hipMalloc(tmax)");
@@ -1852,7 +2309,7 @@ struct swb_ctx {
     Inst *d_insts = nullptr;
     int *d_table = nullptr;
     int ntab = 0;
-    int shape = 0;
+    int shape = kDefaultShape;
     hipGraphExec_t gexec = nullptr;
     bool built = false;
     std::string err;
@@ -1887,7 +2344,9 @@ int batch_build(swb_ctx *b)
             if (rc) return bfail(b, rc, "member " + std::to_string(m) + ": " + c->err);
         }
         insts[m] = make_inst(c, make_step_args(c, 0, 0.0));
-        for (int by = 0; by < c->nty; ++by)
+        // one entry per workgroup: a tile, or a stack of SWAVES strip tiles
+        const int rows = is_strip(b->shape) ? (c->nty + SWAVES - 1) / SWAVES : c->nty;
+        for (int by = 0; by < rows; ++by)
             for (int bx = 0; bx < c->ntx; ++bx) {
                 table.push_back(m);
                 table.push_back(bx);

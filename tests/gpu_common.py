@@ -20,13 +20,16 @@ def torch_stream():
     return torch.cuda.current_stream().cuda_stream
 
 
-def run_gpu(w, steps, dt=None, flags=None, stream=None, **params):
-    """Run workload ``w`` for ``steps`` steps on the GPU; returns (fields, sums)."""
+def run_gpu(w, steps, dt=None, flags=None, stream=None, shape=None, **params):
+    """Run workload ``w`` for ``steps`` steps on the GPU (tile shape ``shape``
+    if given); returns (fields, sums)."""
     from paper_2103_15196_amd import csph
     if flags is not None:
         params["flags"] = flags
     s = csph.solver_for(w, stream=stream if stream is not None else torch_stream(), **params)
     try:
+        if shape is not None:
+            s.set_tile_shape(*shape)
         if steps:
             s.advance(steps, dt)
         f = s.get_fields()

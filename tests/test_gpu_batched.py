@@ -30,7 +30,7 @@ def _solo(w, steps, stream):
     return f, sums
 
 
-@pytest.mark.parametrize("shape", [(64, 8), (64, 4)])
+@pytest.mark.parametrize("shape", [(64, 8), (64, 4), (58, 16)])
 def test_gpu_batch_equals_members_alone(shape):
     import torch
     from paper_2103_15196_amd import csph

@@ -226,7 +226,7 @@ def test_gpu_tile_shapes_and_autotune_give_the_same_bits():
     import torch
     w = W.dam_break_fractal(n=300, ny=236, dx=2.0, seed=7, relief=10.0, depth=8.0).as_float32()
     ref, ref_sums = run_gpu(w, 200)
-    for shape in ((64, 4), (64, 16), (128, 4)):
+    for shape in ((64, 4), (64, 16), (128, 4), (58, 8), (58, 16), (58, 32)):
         s = csph.solver_for(w, stream=torch.cuda.current_stream().cuda_stream)
         s.set_tile_shape(*shape)
         s.advance(200)

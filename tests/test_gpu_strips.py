@@ -1,0 +1,92 @@
+"""The strip kernels (one wavefront per 58-column tile, rows marched in
+registers, x neighbours by lane shifts) against the LDS tile kernels: every
+strip height gives exactly the bits of the 64 x 8 tiles on walls, open sides,
+per-cell soil, inflow and bed sources, ragged edges, grids narrower than one
+strip, graph replay and eager launches, dry-tile skipping on and off."""
+import numpy as np
+import pytest
+
+from paper_2103_15196_amd import workloads as W
+from tests.gpu_common import run_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+STRIPS = [(58, 8), (58, 16), (58, 32)]
+
+
+def _same(a, b, what):
+    (fa, sa), (fb, sb) = a, b
+    for x, y, name in zip(fa, fb, ("h", "hu", "hv", "b")):
+        assert np.array_equal(x, y), f"{what}: {name} differs"
+    assert sa["t"] == sb["t"] and sa["step"] == sb["step"], what
+    for k in ("water_volume", "water_boundary_out", "sed_boundary_out"):
+        assert sa[k] == sb[k], f"{what}: {k}"
+
+
+def _river():
+    w = W.river_valley(n=200, ny=136, dx=5.0, amplitude=60.0, wavelength=500.0, width=40.0,
+                       Q_base=20.0, Q_peak=200.0, t_peak=40.0, t_sigma=15.0)
+    w.qb = np.zeros((w.ny, w.nx))
+    w.qb[60:70, 100:110] = 2e-6
+    return w.as_float32()
+
+
+def _mixed_bc():
+    f = W.dam_break_fractal(n=130, ny=98, dx=2.0, seed=9, relief=5.0, depth=4.0).as_float32()
+    f.bc = (0, 1, 1, 0)
+    return f
+
+
+CASES = {
+    "fractal_open_300x236": (lambda: W.dam_break_fractal(n=300, ny=236, dx=2.0, seed=7, relief=10.0,
+                                                         depth=8.0).as_float32(), 200),
+    "dam_break_walls_eq4_256x64": (lambda: W.dam_break_1d().as_float32(), 200),
+    "river_inflow_soil_sources_200x136": (_river, 300),
+    "fractal_mixed_bc_130x98": (_mixed_bc, 150),
+    "narrow_40x90": (lambda: W.dam_break_fractal(n=40, ny=90, dx=1.0, seed=3, relief=2.0,
+                                                 depth=2.0).as_float32(), 120),
+    "one_row_96x1": (lambda: W.dam_break_1d(nx=96, ny=1, x_dam=40).as_float32(), 80),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_gpu_strips_equal_tiles(case):
+    make, steps = CASES[case]
+    w = make()
+    ref = run_gpu(w, steps)
+    for shape in STRIPS:
+        say(f"strip {shape} on {case} ({w.nx}x{w.ny}, {steps} steps)")
+        _same(run_gpu(w, steps, shape=shape), ref, f"{case} {shape}")
+
+
+def test_gpu_strips_variants():
+    """Dry-tile skipping off and eager launches give the same bits on strips."""
+    from paper_2103_15196_amd import csph
+    w = W.dam_break_fractal(n=400, ny=200, dx=2.0, seed=11, relief=10.0, depth=6.0).as_float32()
+    w.bc = (0, 1, 1, 0)
+    ref = run_gpu(w, 151)
+    for flags in (0, csph.SW_FLAG_HGS | csph.SW_FLAG_NO_GRAPH, csph.SW_FLAG_HGS):
+        say(f"strip (58, 16) flags {flags}")
+        _same(run_gpu(w, 151, flags=flags, shape=(58, 16)), ref, f"flags {flags}")
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0, 0), (1, 1, 1, 1)])
+def test_gpu_strips_lake_at_rest_is_exact(bc):
+    w = W.lake_at_rest(200, 130, dx=1.0, relief=3.0, level=2.0, bc=bc).as_float32()
+    (h, hu, hv, b), _ = run_gpu(w, 300, shape=(58, 16))
+    assert np.array_equal(h, w.H.astype(np.float32))
+    assert np.all(hu == 0) and np.all(hv == 0)
+    assert np.array_equal(b, w.b.astype(np.float32))
+
+
+def test_gpu_strips_tiny_grids():
+    """Grids of 1-3 cells per side (every lane but a few is halo)."""
+    for nx, ny in ((3, 1), (2, 1), (3, 3), (1, 5)):
+        H = np.zeros((ny, nx))
+        H.flat[0] = 1.0
+        z = np.zeros((ny, nx))
+        w = W.Workload(name="t", nx=nx, ny=ny, dx=1.0, bc=(0, 0, 0, 0), H=H, qx=z, qy=z, b=z,
+                       nM=0.0, d50=5e-4, psi=0.4, steps=1, cfl=0.9, sed_law=0)
+        ref = run_gpu(w, 5, dt=0.05)
+        for shape in STRIPS:
+            _same(run_gpu(w, 5, dt=0.05, shape=shape), ref, f"{nx}x{ny} {shape}")
