@@ -986,8 +986,8 @@ struct BedCell {
     float jx, jy, b;
 };
 
-// Lagrangian stage on a strip tile.
-template <int S>
+// Lagrangian stage on a strip tile (CS: per-cell Manning coefficient).
+template <int S, bool CS>
 __device__ void lagrange_strip(const Inst &I, int par, int bx, int by)
 {
     const KPar &P = I.P;
@@ -1011,7 +1011,7 @@ __device__ void lagrange_strip(const Inst &I, int par, int bx, int by)
     auto load_row = [&](int r, LRow &w) {
         const int c = min(max(r, 0), ny - 1) * pitch + ci;
         w.h = H[c]; w.qx = Qx[c]; w.qy = Qy[c]; w.b = B[c];
-        w.nM = P.nM ? P.nM[c] : P.nM_s;
+        w.nM = CS && P.nM ? P.nM[c] : P.nM_s;
     };
     // rows r-3 .. r of depth and bed, r-2 .. r of momentum and Manning n,
     // r-1 .. r of u, r-2 .. r of v, half-step depths of rows r-3 .. r-1
@@ -1072,7 +1072,8 @@ __device__ void lagrange_strip(const Inst &I, int par, int bx, int by)
 
 // Euler stage on a strip tile (K7 + limiter + K8) with the epilogue
 // reductions (Eq. 7 maxima and wet flag of the new state, boundary balances).
-template <int S>
+// CS: some soil or source field is a per-cell plane (else all are scalars).
+template <int S, bool CS>
 __device__ void euler_strip(const Inst &I, int par, int bx, int by)
 {
     const KPar &P = I.P;
@@ -1117,67 +1118,99 @@ __device__ void euler_strip(const Inst &I, int par, int bx, int by)
     const bool xghost = i == -1 || i == nx;
     const bool face_x = i >= 0 && i <= nx;  // this lane's west face is a grid face
     const int ci = min(max(i, 0), nx - 1);
-    auto load_row = [&](int r, StripRow &w) {
+    auto soil_at = [&](const float *a, float sc, int c) -> float { return CS && a ? a[c] : sc; };
+    // a row as loaded (clamped into the grid; the consumer zeroes what lies outside)
+    struct Row {
+        float h, qx, qy, b, Lx, Ly, nM, d50;
+    };
+    auto load_row = [&](int r, Row &w) {
         const int c = min(max(r, 0), ny - 1) * pitch + ci;
         w.h = SH[c]; w.qx = Sqx[c]; w.qy = Sqy[c]; w.b = Sb[c]; w.Lx = QLx[c]; w.Ly = QLy[c];
-        w.nM = P.nM ? P.nM[c] : P.nM_s;
-        w.d50 = P.d50 ? P.d50[c] : P.d50_s;
-        w.psi = P.psi ? P.psi[c] : P.psi_s;
-        w.src = P.srcw ? P.srcw[c] : 0.0f;
-        w.qb = P.qb ? P.qb[c] : 0.0f;
+        w.nM = soil_at(P.nM, P.nM_s, c);
+        w.d50 = soil_at(P.d50, P.d50_s, c);
     };
     // registers carried along the march, for the current row r:
-    StripRow w0{}, w1{}, w2{}, w3{};           // rows r-3 .. r as loaded
-    CellVals v0{}, v1{}, v2{}, v3{};           // remap inputs of rows r-3 .. r
+    CellVals v1{}, v2{}, v3{};                 // remap inputs of rows r-2 .. r
+    SideQ yp{};                                // plus (north) side of row r-2 along y
     Flux3 X3{}, X2{};                          // raw x fluxes of this lane's W face, rows r-3, r-2
     Flux3 Y3{}, Y2{}, Y1{};                    // raw y fluxes of faces r-3, r-2, r-1
     float th4 = 1.0f, th3 = 1.0f, th2 = 1.0f;  // limiters of rows r-4 .. r-2
-    BedCell J4{}, J3{}, J2{};                  // J0 and bed of rows r-4 .. r-2
+    float xs3 = 0, xs2 = 0, xs1 = 0, xs0 = 0;  // bedload flux of this lane's W face, rows r-3 .. r
+    float ys3 = 0, ys2 = 0, ys1 = 0, ys0 = 0;  // bedload flux of y faces r-3 .. r
+    float pjy = 0, pmag = 0, pb = 0;           // J0_y, |J0| and bed of row r-1
     unsigned mv = 0, ms = 0, mD = 0, bad = 0;
     bool wet = false;
-    auto step = [&](int r, const StripRow &in) {
-        w0 = w1; w1 = w2; w2 = w3; w3 = in;
-        v0 = v1; v1 = v2; v2 = v3;
+    auto step = [&](int r, const Row &in) {
+        // the cells K8 updates in this step (row r-3), loaded again (cache hits)
+        const int ju = r - 3;
+        const bool upd = ju >= y0 && ju < jend;
+        float uh = 0, uqx = 0, uqy = 0, ub = 0, uLx = 0, uLy = 0;
+        float upsi = P.psi_s, usrc = 0, uqb = 0, unM = P.nM_s, ud50 = P.d50_s;
+        if (upd) {
+            const int c = ju * pitch + ci;
+            uh = SH[c]; uqx = Sqx[c]; uqy = Sqy[c]; ub = Sb[c]; uLx = QLx[c]; uLy = QLy[c];
+            upsi = soil_at(P.psi, P.psi_s, c);
+            usrc = soil_at(P.srcw, 0.0f, c);
+            uqb = soil_at(P.qb, 0.0f, c);
+            unM = soil_at(P.nM, P.nM_s, c);
+            ud50 = soil_at(P.d50, P.d50_s, c);
+        }
+        const bool iny = (unsigned)r < (unsigned)ny;
         {  // remap inputs of row r (ghost cells beyond the domain edge)
-            const bool iny = (unsigned)r < (unsigned)ny;
             const bool yghost = r == -1 || r == ny;
             const CellVals v = cell_vals(P, in.h, in.qx, in.qy, in.b, in.Lx, in.Ly);
+            v1 = v2; v2 = v3;
             if (inx && iny) v3 = v;
             else if (iny && xghost) v3 = mirror(v, 0, i < 0 ? wW : wE);
             else if (inx && yghost) v3 = mirror(v, 1, r < 0 ? wS : wN);
             else v3 = CellVals{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         }
+        xs3 = xs2; xs2 = xs1; xs1 = xs0;
+        ys3 = ys2; ys2 = ys1; ys1 = ys0;
+        if (r >= y0 - 1 && r <= y0 + S) {  // J0 (Eqs. 3-5) of row r and its bedload faces
+            float jx = 0.0f, jy = 0.0f, b = 0.0f;
+            if (inx && iny) {
+                const float w = wdes(in.h, P);
+                bedload(P, in.h, in.qx * w, in.qy * w, in.nM, in.d50, jx, jy);
+                b = in.b;
+            }
+            const float mag = sqrtf(sumsq(jx, jy));
+            const float jxW = lane_prev(jx), magW = lane_prev(mag), bW = lane_prev(b);
+            float xs = 0.0f, ys = 0.0f;
+            if (r >= y0 && r < jend && face_x)  // W face of this lane in row r
+                xs = sed_face(P, i, nx, wW, wE, jxW, magW, bW, jx, mag, b);
+            if (r >= y0 && inx && r <= ny)  // y face r, between rows r-1 and r
+                ys = sed_face(P, r, ny, wS, wN, pjy, pmag, pb, jy, mag, b);
+            xs0 = xs; ys0 = ys;
+            pjy = jy; pmag = mag; pb = b;
+        }
         Y3 = Y2; Y2 = Y1;
-        {  // y face r-1 (between rows r-2 and r-1) of this column
+        {  // y reconstruction of row r-1 and y face r-1 (between rows r-2 and r-1)
             const int k = r - 1;
             Flux3 f{0.0f, 0.0f, 0.0f};
-            if (k >= y0 - 1 && k <= y0 + S + 1 && inx && k >= 0 && k <= ny)
-                water_flux(P, k, ny, wS, wN, along(v0, 1), along(v1, 1), along(v2, 1),
-                           along(v3, 1), f.H, f.n, f.t);
+            if (k >= y0 - 2 && k <= y0 + S + 1) {
+                SideQ ym, ypn;
+                reconstruct(along(v1, 1), along(v2, 1), along(v3, 1), ym, ypn);
+                if (k >= y0 - 1 && inx && k >= 0 && k <= ny)
+                    side_flux(P, k, ny, wS, wN, yp, ym, f.H, f.n, f.t);
+                yp = ypn;
+            }
             Y1 = f;
         }
-        const int jr = r - 2;  // ring/tile row whose x faces, J0 and limiter are due
-        const bool ring_row = jr >= y0 - 1 && jr <= y0 + S;
-        const bool row_in = (unsigned)jr < (unsigned)ny;
+        const int jr = r - 2;  // ring/tile row whose x faces and limiter are due
         X3 = X2;
-        J4 = J3; J3 = J2;
         th4 = th3; th3 = th2;
-        if (ring_row) {
-            {  // x faces of row r-2: this lane's W face from the cells two west .. one east
-                const CellQ c2 = along(v1, 0);
-                const CellQ c1 = q_prev(c2), c0 = q_prev(c1), c3 = q_next(c2);
+        if (jr >= y0 - 1 && jr <= y0 + S) {
+            const bool row_in = (unsigned)jr < (unsigned)ny;
+            {  // x reconstruction of row r-2 and this lane's W face (west lane's plus side)
+                const CellQ c = along(v1, 0);
+                SideQ xm, xp;
+                reconstruct(q_prev(c), c, q_next(c), xm, xp);
+                const SideQ xl{lane_prev(xp.z), lane_prev(xp.h), lane_prev(xp.ut),
+                               lane_prev(xp.uLn), lane_prev(xp.uLt), lane_prev(xp.b)};
                 Flux3 f{0.0f, 0.0f, 0.0f};
-                if (row_in && face_x) water_flux(P, i, nx, wW, wE, c0, c1, c2, c3, f.H, f.n, f.t);
+                if (row_in && face_x) side_flux(P, i, nx, wW, wE, xl, xm, f.H, f.n, f.t);
                 X2 = f;
-            }
-            {  // zero-slope bedload J0 (Eqs. 3-5) and bed of row r-2
-                BedCell J{0.0f, 0.0f, 0.0f};
-                if (inx && row_in) {
-                    const float w = wdes(w1.h, P);
-                    bedload(P, w1.h, w1.qx * w, w1.qy * w, w1.nM, w1.d50, J.jx, J.jy);
-                    J.b = w1.b;
-                }
-                J2 = J;
             }
             {  // draining limiter of row r-2
                 const float fe = lane_next(X2.H);
@@ -1185,38 +1218,31 @@ __device__ void euler_strip(const Inst &I, int par, int bx, int by)
             }
         } else {
             X2 = Flux3{0.0f, 0.0f, 0.0f};
-            J2 = BedCell{0.0f, 0.0f, 0.0f};
             th2 = 1.0f;
         }
-        const int j = r - 3;  // K8 of row r-3
-        if (j >= y0 && j < jend) {
+        if (upd) {  // K8 of row r-3
             CellFaces F;
             F.thW = lane_prev(th3); F.thE = lane_next(th3);
             F.xHe = lane_next(X3.H); F.xne = lane_next(X3.n); F.xte = lane_next(X3.t);
-            const float jxW = lane_prev(J3.jx), jyW = lane_prev(J3.jy), bW = lane_prev(J3.b);
-            const float jxE = lane_next(J3.jx), jyE = lane_next(J3.jy), bE = lane_next(J3.b);
+            F.Je = lane_next(xs3);
             if (mine) {
                 F.th = th3; F.thS = th4; F.thN = th2;
                 F.xHw = X3.H; F.xnw = X3.n; F.xtw = X3.t;
                 F.yHs = Y3.H; F.yns = Y3.n; F.yts = Y3.t;
                 F.yHn = Y2.H; F.ynn = Y2.n; F.ytn = Y2.t;
-                F.Jw = sed_flux(P, i, nx, wW, wE, 0, jxW, jyW, bW, J3.jx, J3.jy, J3.b);
-                F.Je = sed_flux(P, i + 1, nx, wW, wE, 0, J3.jx, J3.jy, J3.b, jxE, jyE, bE);
-                F.Js = sed_flux(P, j, ny, wS, wN, 1, J4.jx, J4.jy, J4.b, J3.jx, J3.jy, J3.b);
-                F.Jn = sed_flux(P, j + 1, ny, wS, wN, 1, J3.jx, J3.jy, J3.b, J2.jx, J2.jy, J2.b);
-                const float src = P.srcw ? w0.src * qmid : 0.0f;
-                const CellNew o = cell_update(P, dt, F, w0.h, w0.qx, w0.qy, w0.b, w0.Lx, w0.Ly, src,
-                                              w0.psi, w0.qb);
-                const int c = j * pitch + i;
+                F.Jw = xs3; F.Js = ys3; F.Jn = ys2;
+                const float src = P.srcw ? usrc * qmid : 0.0f;
+                const CellNew o = cell_update(P, dt, F, uh, uqx, uqy, ub, uLx, uLy, src, upsi, uqb);
+                const int c = ju * pitch + i;
                 OH[c] = o.H; Oqx[c] = o.qx; Oqy[c] = o.qy; Ob[c] = o.b;
-                boundary_balances(P, I.bnd, wdx, i, j, o, F);
-                cell_maxima_s(P, o.H, o.qx, o.qy, o.b, w0.nM, w0.d50, w0.psi, mv, ms, mD, bad);
+                boundary_balances(P, I.bnd, wdx, i, ju, o, F);
+                cell_maxima_s(P, o.H, o.qx, o.qy, o.b, unM, ud50, upsi, mv, ms, mD, bad);
                 if (o.H > 0.0f) wet = true;
             }
         }
     };
     const int rlo = y0 - 3, rhi = y0 + S + 2;  // S + 6 rows, an even count
-    StripRow A, B;
+    Row A, B;
     load_row(rlo, A);
     load_row(rlo + 1, B);
     for (int r = rlo; r <= rhi; r += 2) {
@@ -1305,38 +1331,38 @@ __global__ void __launch_bounds__(NT) k_euler_b(const Inst *__restrict__ insts,
 
 // Strip tiles: workgroup (bx, g) runs the SWAVES tiles (bx, SWAVES g + w),
 // one per wavefront w.
-template <int S>
+template <int S, bool CS>
 __global__ void __launch_bounds__(NT) k_lagrange_s(Inst I, int par)
 {
     const int by = blockIdx.y * SWAVES + (threadIdx.x >> 6);
-    if (by < I.nty) lagrange_strip<S>(I, par, blockIdx.x, by);
+    if (by < I.nty) lagrange_strip<S, CS>(I, par, blockIdx.x, by);
 }
-template <int S>
+template <int S, bool CS>
 __global__ void __launch_bounds__(NT) k_euler_s(Inst I, int par)
 {
     const int by = blockIdx.y * SWAVES + (threadIdx.x >> 6);
-    if (by < I.nty) euler_strip<S>(I, par, blockIdx.x, by);
+    if (by < I.nty) euler_strip<S, CS>(I, par, blockIdx.x, by);
 }
 
 // Ensemble strips: workgroup b runs tiles (table[3b+1], SWAVES table[3b+2] + w)
 // of member table[3b].
-template <int S>
+template <int S, bool CS>
 __global__ void __launch_bounds__(NT) k_lagrange_sb(const Inst *__restrict__ insts,
                                                     const int *__restrict__ table, int par)
 {
     const int *t = table + 3 * blockIdx.x;
     const Inst &I = insts[t[0]];
     const int by = t[2] * SWAVES + (threadIdx.x >> 6);
-    if (by < I.nty) lagrange_strip<S>(I, par, t[1], by);
+    if (by < I.nty) lagrange_strip<S, CS>(I, par, t[1], by);
 }
-template <int S>
+template <int S, bool CS>
 __global__ void __launch_bounds__(NT) k_euler_sb(const Inst *__restrict__ insts,
                                                  const int *__restrict__ table, int par)
 {
     const int *t = table + 3 * blockIdx.x;
     const Inst &I = insts[t[0]];
     const int by = t[2] * SWAVES + (threadIdx.x >> 6);
-    if (by < I.nty) euler_strip<S>(I, par, t[1], by);
+    if (by < I.nty) euler_strip<S, CS>(I, par, t[1], by);
 }
 
 // Tile shapes the autotuner chooses from: TX x TY cells per 256-thread
@@ -1617,29 +1643,41 @@ void launch_batch_t(Stage st, hipStream_t s, const Inst *insts, int nmem, const 
     else hipLaunchKernelGGL((k_euler_b<TX, TY>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
 }
 
-template <int S>
+template <int S, bool CS>
 void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, int nmem, const int *table,
                     int ntab, int par)
 {
     if (st == kDt) hipLaunchKernelGGL(k_dt_b, dim3(nmem), dim3(RT), 0, s, insts, par);
     else if (st == kLagrange)
-        hipLaunchKernelGGL((k_lagrange_sb<S>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
-    else hipLaunchKernelGGL((k_euler_sb<S>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
+        hipLaunchKernelGGL((k_lagrange_sb<S, CS>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
+    else hipLaunchKernelGGL((k_euler_sb<S, CS>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
 }
 
+template <int S>
+void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, int nmem, const int *table,
+                    int ntab, int par, bool cs)
+{
+    if (cs) launch_batch_s<S, true>(st, s, insts, nmem, table, ntab, par);
+    else launch_batch_s<S, false>(st, s, insts, nmem, table, ntab, par);
+}
+
+// cs: some member has a per-cell soil or source plane.
 void launch_batch(int shape, Stage st, hipStream_t s, const Inst *insts, int nmem,
-                  const int *table, int ntab, int par)
+                  const int *table, int ntab, int par, bool cs)
 {
     switch (shape) {
     case 0: launch_batch_t<64, 8>(st, s, insts, nmem, table, ntab, par); break;
     case 1: launch_batch_t<64, 4>(st, s, insts, nmem, table, ntab, par); break;
     case 2: launch_batch_t<64, 16>(st, s, insts, nmem, table, ntab, par); break;
     case 3: launch_batch_t<128, 4>(st, s, insts, nmem, table, ntab, par); break;
-    case 4: launch_batch_s<8>(st, s, insts, nmem, table, ntab, par); break;
-    case 5: launch_batch_s<16>(st, s, insts, nmem, table, ntab, par); break;
-    default: launch_batch_s<32>(st, s, insts, nmem, table, ntab, par); break;
+    case 4: launch_batch_s<8>(st, s, insts, nmem, table, ntab, par, cs); break;
+    case 5: launch_batch_s<16>(st, s, insts, nmem, table, ntab, par, cs); break;
+    default: launch_batch_s<32>(st, s, insts, nmem, table, ntab, par, cs); break;
     }
 }
+
+// Whether a grid's kernels must read per-cell soil or source planes.
+bool cell_soil(const KPar &P) { return P.nM || P.d50 || P.psi || P.srcw || P.qb; }
 
 // Strip shapes: the prepare pass runs one workgroup per tile, the stage
 // kernels one wavefront per tile.
@@ -1650,8 +1688,13 @@ void launch_strip_t(Stage st, hipStream_t s, const Inst &I, int par)
     if (st == kPrepare) hipLaunchKernelGGL((k_prepare_t<SX, S>), gt, dim3(NT), 0, s, I, par);
     else if (st == kDt) hipLaunchKernelGGL(k_dt_t, dim3(1), dim3(RT), 0, s, I, par);
     else if (st == kCount) hipLaunchKernelGGL(k_count_t, dim3(1), dim3(RT), 0, s, I, par, SX, S);
-    else if (st == kLagrange) hipLaunchKernelGGL((k_lagrange_s<S>), gs, dim3(NT), 0, s, I, par);
-    else hipLaunchKernelGGL((k_euler_s<S>), gs, dim3(NT), 0, s, I, par);
+    else if (st == kLagrange) {
+        if (cell_soil(I.P)) hipLaunchKernelGGL((k_lagrange_s<S, true>), gs, dim3(NT), 0, s, I, par);
+        else hipLaunchKernelGGL((k_lagrange_s<S, false>), gs, dim3(NT), 0, s, I, par);
+    } else {
+        if (cell_soil(I.P)) hipLaunchKernelGGL((k_euler_s<S, true>), gs, dim3(NT), 0, s, I, par);
+        else hipLaunchKernelGGL((k_euler_s<S, false>), gs, dim3(NT), 0, s, I, par);
+    }
 }
 
 void launch_stage(int shape, Stage st, hipStream_t s, const Inst &I, int par)
@@ -2310,6 +2353,7 @@ struct swb_ctx {
     int *d_table = nullptr;
     int ntab = 0;
     int shape = kDefaultShape;
+    bool cs = false;  // some member reads per-cell soil or source planes
     hipGraphExec_t gexec = nullptr;
     bool built = false;
     std::string err;
@@ -2336,6 +2380,7 @@ int batch_build(swb_ctx *b)
     const int n = (int)b->mem.size();
     std::vector<Inst> insts(n);
     std::vector<int> table;
+    b->cs = false;
     for (int m = 0; m < n; ++m) {
         sw_ctx *c = b->mem[m];
         if (c->shape != b->shape) set_shape(c, b->shape);
@@ -2344,6 +2389,7 @@ int batch_build(swb_ctx *b)
             if (rc) return bfail(b, rc, "member " + std::to_string(m) + ": " + c->err);
         }
         insts[m] = make_inst(c, make_step_args(c, 0, 0.0));
+        b->cs = b->cs || cell_soil(insts[m].P);
         // one entry per workgroup: a tile, or a stack of SWAVES strip tiles
         const int rows = is_strip(b->shape) ? (c->nty + SWAVES - 1) / SWAVES : c->nty;
         for (int by = 0; by < rows; ++by)
@@ -2373,9 +2419,9 @@ int batch_build(swb_ctx *b)
 void batch_step(swb_ctx *b, hipStream_t st, int par)
 {
     const int n = (int)b->mem.size();
-    launch_batch(b->shape, kDt, st, b->d_insts, n, b->d_table, b->ntab, par);
-    launch_batch(b->shape, kLagrange, st, b->d_insts, n, b->d_table, b->ntab, par);
-    launch_batch(b->shape, kEuler, st, b->d_insts, n, b->d_table, b->ntab, par);
+    launch_batch(b->shape, kDt, st, b->d_insts, n, b->d_table, b->ntab, par, b->cs);
+    launch_batch(b->shape, kLagrange, st, b->d_insts, n, b->d_table, b->ntab, par, b->cs);
+    launch_batch(b->shape, kEuler, st, b->d_insts, n, b->d_table, b->ntab, par, b->cs);
 }
 
 bool batch_needs_build(const swb_ctx *b)

@@ -319,18 +319,88 @@ __device__ __forceinline__ void water_flux(const KPar &P, int k, int n, bool wal
     }
 }
 
-// Bedload flux of face k along direction dir from the J0 vectors and beds of
-// the cells on its two sides; walls pass nothing, an open side passes only
-// the outward part of the interior cell's J0.
+// Reconstructed values of one cell on its two faces along a direction: the
+// minmod slope of each quantity from the neighbours M (minus side) and Q
+// (plus side), value -/+ slope/2, and the bed under each face value.  The
+// face between cells k-1 and k takes the plus side of k-1 and the minus side
+// of k; this gives the bits of face_states / boundary_state (same slopes,
+// same contractions), with each slope computed once per cell.
+struct SideQ {
+    float z, h, ut, uLn, uLt, b;
+};
+
+__device__ __forceinline__ void reconstruct(const CellQ &M, const CellQ &C, const CellQ &Q,
+                                            SideQ &minus, SideQ &plus)
+{
+    const float sz = minmod(C.z - M.z, Q.z - C.z);
+    const float sh = minmod(C.h - M.h, Q.h - C.h);
+    const float st = minmod(C.ut - M.ut, Q.ut - C.ut);
+    const float sn = minmod(C.uLn - M.uLn, Q.uLn - C.uLn);
+    const float ss = minmod(C.uLt - M.uLt, Q.uLt - C.uLt);
+    plus.z = C.z + 0.5f * sz;
+    plus.h = C.h + 0.5f * sh;
+    plus.ut = C.ut + 0.5f * st;
+    plus.uLn = C.uLn + 0.5f * sn;
+    plus.uLt = C.uLt + 0.5f * ss;
+    minus.z = C.z - 0.5f * sz;
+    minus.h = C.h - 0.5f * sh;
+    minus.ut = C.ut - 0.5f * st;
+    minus.uLn = C.uLn - 0.5f * sn;
+    minus.uLt = C.uLt - 0.5f * ss;
+    plus.b = plus.z - plus.h;
+    minus.b = minus.z - minus.h;
+}
+
+// Raw water fluxes of face k in [0, n] from the plus side L of cell k-1 and
+// the minus side R of cell k (the result of water_flux): interior faces take
+// hydrostatic face depths and HLL; a boundary face uses the interior cell's
+// side only (wall flux, or the physical flux on an open side).
+__device__ __forceinline__ void side_flux(const KPar &P, int k, int n, bool wallLo, bool wallHi,
+                                          const SideQ &L, const SideQ &R, float &fH, float &fn,
+                                          float &ft)
+{
+    fH = fn = ft = 0.0f;
+    if (k > 0 && k < n) {
+        const float bf = fmaxf(L.b, R.b);
+        FaceState fl, fr;
+        fl.Hs = fmaxf(0.0f, L.z - bf); fl.uLn = L.uLn; fl.uLt = L.uLt; fl.ut = L.ut;
+        fr.Hs = fmaxf(0.0f, R.z - bf); fr.uLn = R.uLn; fr.uLt = R.uLt; fr.ut = R.ut;
+        hll(P.g, fl, fr, fH, fn, ft);
+        return;
+    }
+    const SideQ &C = k == n ? L : R;
+    const float side = k == n ? 1.0f : -1.0f;
+    FaceState s;
+    s.Hs = fmaxf(0.0f, C.z - C.b); s.uLn = C.uLn; s.uLt = C.uLt; s.ut = C.ut;
+    if (k == n ? wallHi : wallLo) {
+        fn = wall_flux_n(P.g, s, side);
+    } else {
+        fH = s.ut * s.Hs;
+        fn = s.ut * s.Hs * s.uLn;
+        ft = s.ut * s.Hs * s.uLt;
+    }
+}
+
+// Bedload flux of face k (between cells k-1 and k, k in [0, n]) from the
+// normal J0 components, the |J0| and the beds of the cells on its two sides;
+// walls pass nothing, an open side passes only the outward part of the
+// interior cell's J0.
+__device__ __forceinline__ float sed_face(const KPar &P, int k, int n, bool wallLo, bool wallHi,
+                                          float JnL, float magL, float bL, float JnR, float magR,
+                                          float bR)
+{
+    if (k > 0 && k < n) return bed_face_flux(P, JnL, magL, bL, JnR, magR, bR);
+    if (k == n) return wallHi ? 0.0f : fmaxf(JnL, 0.0f);
+    return wallLo ? 0.0f : fminf(JnR, 0.0f);
+}
+
+// The same from the J0 vectors of the two side cells, along direction dir.
 __device__ __forceinline__ float sed_flux(const KPar &P, int k, int n, bool wallLo, bool wallHi,
                                           int dir, float jxL, float jyL, float bL, float jxR,
                                           float jyR, float bR)
 {
-    if (k > 0 && k < n)
-        return bed_face_flux(P, dir == 0 ? jxL : jyL, sqrtf(sumsq(jxL, jyL)), bL,
-                             dir == 0 ? jxR : jyR, sqrtf(sumsq(jxR, jyR)), bR);
-    if (k == n) return wallHi ? 0.0f : fmaxf(dir == 0 ? jxL : jyL, 0.0f);
-    return wallLo ? 0.0f : fminf(dir == 0 ? jxR : jyR, 0.0f);
+    return sed_face(P, k, n, wallLo, wallHi, dir == 0 ? jxL : jyL, sqrtf(sumsq(jxL, jyL)), bL,
+                    dir == 0 ? jxR : jyR, sqrtf(sumsq(jxR, jyR)), bR);
 }
 
 }  // namespace csph
