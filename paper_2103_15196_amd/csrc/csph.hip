@@ -454,6 +454,17 @@ struct Inst {
     const uint8_t *force;
     uint4 *tmax[2];  // per tile: Eq. 7 maxima of the state the tile will step from (float bits) + nonfinite flag
     int ntx, nty, hgs;
+    // work lists of one step (strip shapes, single grid), built by K3 in
+    // nchunk segments of up to `chunk` tiles: segment b of a list sits at
+    // entries [b chunk, b chunk + count) and starts at position pre[b] of the
+    // whole list; totals[0] / totals[1] are the Lagrangian / Euler lengths.
+    // An Euler entry -1-t asks for a buffer copy of dry tile t.
+    int *totals;                 // list lengths
+    int *cnt_l, *cnt_e;          // per-segment lengths
+    int *pre_l, *pre_e;          // per-segment start positions (nchunk + 1)
+    uint4 *part;                 // per-segment Eq. 7 maxima
+    int *lag, *eul;              // the segments
+    int nchunk, chunk;
 };
 
 // Block maxima of three non-negative floats (as bits) and a flag, stored with
@@ -487,15 +498,24 @@ __device__ __forceinline__ void block_maxima_store(unsigned a, unsigned b, unsig
 // dt, the time ring, the source balances and the step counter, or the error.
 constexpr int RT = 1024;
 
-__device__ void reduce_dt(Ctrl *ctrl, int par, const StepArgs &A, const uint4 *__restrict__ tm,
-                          int ntiles)
+// Block-wide maxima of the per-tile slots [t0, t1) (the result is valid in
+// thread 0), with eight independent loads in flight per thread.
+__device__ uint4 block_tile_maxima(const uint4 *__restrict__ tm, int t0, int t1)
 {
     __shared__ unsigned red[4][RT / 64];
     const int tid = threadIdx.x;
     unsigned a = 0, b = 0, c = 0, bad = 0;
-    for (int t = tid; t < ntiles; t += RT) {
-        uint4 v = tm[t];
-        a = max(a, v.x); b = max(b, v.y); c = max(c, v.z); bad = max(bad, v.w);
+    for (int s0 = t0 + tid; s0 < t1; s0 += 8 * RT) {
+        uint4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = s0 + u * RT;
+            v[u] = t < t1 ? tm[t] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a = max(a, v[u].x); b = max(b, v[u].y); c = max(c, v[u].z); bad = max(bad, v[u].w);
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
         a = max(a, (unsigned)__shfl_xor((int)a, off));
@@ -507,30 +527,51 @@ __device__ void reduce_dt(Ctrl *ctrl, int par, const StepArgs &A, const uint4 *_
         red[0][tid >> 6] = a; red[1][tid >> 6] = b; red[2][tid >> 6] = c; red[3][tid >> 6] = bad;
     }
     __syncthreads();
-    if (tid != 0 || ctrl->err) return;
-    for (int w = 1; w < RT / 64; ++w) {
-        a = max(a, red[0][w]); b = max(b, red[1][w]); c = max(c, red[2][w]); bad = max(bad, red[3][w]);
-    }
-    const int kd = ctrl->kdev;
-    double vp = __uint_as_float(a), vs = __uint_as_float(b), D = __uint_as_float(c);
-    ctrl->vp = vp; ctrl->vs = vs; ctrl->D = D;
+    if (tid == 0)
+        for (int w = 1; w < RT / 64; ++w) {
+            a = max(a, red[0][w]); b = max(b, red[1][w]); c = max(c, red[2][w]); bad = max(bad, red[3][w]);
+        }
+    return make_uint4(a, b, c, bad);
+}
+
+// K3 proper (one thread): the Eq. 7 step from the maxima (float bits) of
+// |v|, |v| + c and |J0|/(1-psi) and the nonfinite flag; publishes dt, the
+// time ring, the source balances and the step counter, or the error.
+struct Eq7 {
+    double dt;
+    int which, err;
+};
+__device__ Eq7 eq7_step(const StepArgs &A, uint4 m)
+{
+    double vp = __uint_as_float(m.x), vs = __uint_as_float(m.y), D = __uint_as_float(m.z);
     double h = A.dx;
     double t0 = vp > 0.0 ? h / (2.0 * vp) : INFINITY;
     double t1 = vs > 0.0 ? h / vs : INFINITY;
     double t2 = D > 0.0 ? h * h / (2.0 * D) : INFINITY;
-    double m = t0;
+    double mm = t0;
     int which = 0;
-    if (t1 < m) { m = t1; which = 1; }
-    if (t2 < m) { m = t2; which = 2; }
-    double dt = A.cfl * m;
+    if (t1 < mm) { mm = t1; which = 1; }
+    if (t2 < mm) { mm = t2; which = 2; }
+    double dt = A.cfl * mm;
     if (!(dt < A.dt_max)) { dt = A.dt_max; which = 3; }
     int err = 0;
-    if (bad) err = SW_ERR_NONFINITE;
+    if (m.w) err = SW_ERR_NONFINITE;
     else if (A.mode_fixed && A.dt_fixed > dt) err = SW_ERR_CFL;
     if (A.mode_fixed) { dt = A.dt_fixed; which = 4; }
     if (!err && dt < A.dt_min) err = SW_ERR_DT_UNDERFLOW;
-    if (err) {
-        ctrl->err = err;
+    return Eq7{dt, which, err};
+}
+
+__device__ void publish_dt(Ctrl *ctrl, int par, const StepArgs &A, uint4 m)
+{
+    if (ctrl->err) return;
+    const int kd = ctrl->kdev;
+    ctrl->vp = __uint_as_float(m.x); ctrl->vs = __uint_as_float(m.y); ctrl->D = __uint_as_float(m.z);
+    const Eq7 e = eq7_step(A, m);
+    const double dt = e.dt;
+    const int which = e.which;
+    if (e.err) {
+        ctrl->err = e.err;
         ctrl->err_k = kd;
         return;
     }
@@ -549,6 +590,15 @@ __device__ void reduce_dt(Ctrl *ctrl, int par, const StepArgs &A, const uint4 *_
     ctrl->last_dt = dt;
     ctrl->binding = which;
     ctrl->kdev = kd + 1;
+}
+
+// K3 of one grid in one 1024-thread workgroup (the maximum does not depend
+// on the order it is taken in).
+__device__ void reduce_dt(Ctrl *ctrl, int par, const StepArgs &A, const uint4 *__restrict__ tm,
+                          int ntiles)
+{
+    const uint4 m = block_tile_maxima(tm, 0, ntiles);
+    if (threadIdx.x == 0) publish_dt(ctrl, par, A, m);
 }
 
 // Initial maxima (ring par) and wet-tile flags of a state set from the host.
@@ -988,13 +1038,11 @@ struct BedCell {
 
 // Lagrangian stage on a strip tile (CS: per-cell Manning coefficient).
 template <int S, bool CS>
-__device__ void lagrange_strip(const Inst &I, int par, int bx, int by)
+__device__ void lagrange_strip(const Inst &I, int par, int bx, int by, float dt)
 {
     const KPar &P = I.P;
-    if (I.ctrl->err) return;
     const int tile = bx + by * I.ntx;
     if (I.hgs && !I.act[par][tile]) return;
-    const float dt = (float)I.ctrl->dt[par];
     const int lane = threadIdx.x & 63;
     const int nx = P.nx, ny = P.ny, pitch = P.pitch;
     const int x0 = bx * SX, y0 = by * S;
@@ -1074,7 +1122,7 @@ __device__ void lagrange_strip(const Inst &I, int par, int bx, int by)
 // reductions (Eq. 7 maxima and wet flag of the new state, boundary balances).
 // CS: some soil or source field is a per-cell plane (else all are scalars).
 template <int S, bool CS>
-__device__ void euler_strip(const Inst &I, int par, int bx, int by)
+__device__ void euler_strip(const Inst &I, int par, int bx, int by, bool skip_check = true)
 {
     const KPar &P = I.P;
     Ctrl *ctrl = I.ctrl;
@@ -1090,7 +1138,7 @@ __device__ void euler_strip(const Inst &I, int par, int bx, int by)
     const float *SH = I.H[par], *Sqx = I.qx[par], *Sqy = I.qy[par], *Sb = I.b[par];
     float *OH = I.H[par ^ 1], *Oqx = I.qx[par ^ 1], *Oqy = I.qy[par ^ 1], *Ob = I.b[par ^ 1];
     const float *QLx = I.QLx, *QLy = I.QLy;
-    if (I.hgs) {
+    if (I.hgs && skip_check) {
         const uint8_t *act_in = I.act[par];
         bool run = act_in[tile] || (bx > 0 && act_in[tile - 1]) ||
                    (bx + 1 < ntx && act_in[tile + 1]) || (by > 0 && act_in[tile - ntx]) ||
@@ -1329,21 +1377,6 @@ __global__ void __launch_bounds__(NT) k_euler_b(const Inst *__restrict__ insts,
     euler_tile<TX, TY>(insts[t[0]], par, t[1], t[2]);
 }
 
-// Strip tiles: workgroup (bx, g) runs the SWAVES tiles (bx, SWAVES g + w),
-// one per wavefront w.
-template <int S, bool CS>
-__global__ void __launch_bounds__(NT) k_lagrange_s(Inst I, int par)
-{
-    const int by = blockIdx.y * SWAVES + (threadIdx.x >> 6);
-    if (by < I.nty) lagrange_strip<S, CS>(I, par, blockIdx.x, by);
-}
-template <int S, bool CS>
-__global__ void __launch_bounds__(NT) k_euler_s(Inst I, int par)
-{
-    const int by = blockIdx.y * SWAVES + (threadIdx.x >> 6);
-    if (by < I.nty) euler_strip<S, CS>(I, par, blockIdx.x, by);
-}
-
 // Ensemble strips: workgroup b runs tiles (table[3b+1], SWAVES table[3b+2] + w)
 // of member table[3b].
 template <int S, bool CS>
@@ -1353,7 +1386,7 @@ __global__ void __launch_bounds__(NT) k_lagrange_sb(const Inst *__restrict__ ins
     const int *t = table + 3 * blockIdx.x;
     const Inst &I = insts[t[0]];
     const int by = t[2] * SWAVES + (threadIdx.x >> 6);
-    if (by < I.nty) lagrange_strip<S, CS>(I, par, t[1], by);
+    if (by < I.nty && !I.ctrl->err) lagrange_strip<S, CS>(I, par, t[1], by, (float)I.ctrl->dt[par]);
 }
 template <int S, bool CS>
 __global__ void __launch_bounds__(NT) k_euler_sb(const Inst *__restrict__ insts,
@@ -1363,6 +1396,221 @@ __global__ void __launch_bounds__(NT) k_euler_sb(const Inst *__restrict__ insts,
     const Inst &I = insts[t[0]];
     const int by = t[2] * SWAVES + (threadIdx.x >> 6);
     if (by < I.nty) euler_strip<S, CS>(I, par, t[1], by);
+}
+
+// ---------------------------------------------------------------------------
+// Work lists (strips on a single grid).  Launching one workgroup per tile
+// leaves the wet tiles scattered among dry ones, so some CUs get twice the
+// average work.  Instead K3 compacts, in tile order, the tiles whose
+// Lagrangian stage runs (wet or forced) and those whose Euler stage runs (wet
+// or a side neighbour wet), plus one copy entry for each newly dry tile whose
+// two buffer levels still differ; it also gives every tile left out zero
+// maxima and a dry flag for the next state.  The stage kernels then run one
+// wavefront per list entry: the listed tiles are dispatched first and
+// back-to-back, so the hardware spreads them evenly over the CUs.
+// ---------------------------------------------------------------------------
+
+// Wave64 inclusive prefix sum.
+__device__ __forceinline__ int wave_scan(int v)
+{
+    const int lane = threadIdx.x & 63;
+    for (int off = 1; off < 64; off <<= 1) {
+        int u = __shfl_up(v, off);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
+
+// Exclusive prefix sums of two per-thread counts over the 1024 threads of a
+// block, and their totals.
+__device__ __forceinline__ void block_scan2(int a, int b, int &xa, int &xb, int &ta, int &tb)
+{
+    __shared__ int wa[RT / 64], wb[RT / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ia = wave_scan(a), ib = wave_scan(b);
+    if (lane == 63) { wa[wv] = ia; wb[wv] = ib; }
+    __syncthreads();
+    int oa = 0, ob = 0;
+    ta = 0; tb = 0;
+    for (int k = 0; k < RT / 64; ++k) {
+        if (k < wv) { oa += wa[k]; ob += wb[k]; }
+        ta += wa[k]; tb += wb[k];
+    }
+    xa = oa + ia - a;
+    xb = ob + ib - b;
+}
+
+// K3 for strips (nchunk workgroups): workgroup b reduces the Eq. 7 maxima of
+// its tiles and, under dry-tile skipping, writes its segment of each list,
+// each thread classifying a contiguous run of tiles so that entries come out
+// in tile order.  The segments are combined by the Lagrangian kernel that
+// follows (the kernel boundary makes these writes visible): every wavefront
+// derives its entry and the Eq. 7 step from the segment lengths and maxima,
+// and wavefront 0 publishes the step and the Euler list's start positions.
+__global__ void __launch_bounds__(RT) k_dt_lists(Inst I, int par)
+{
+    const int nt = I.ntx * I.nty, b = blockIdx.x;
+    const int c0 = b * I.chunk, c1 = min(nt, c0 + I.chunk);
+    const uint4 m = block_tile_maxima(I.tmax[par], c0, c1);
+    if (threadIdx.x == 0) I.part[b] = m;
+    if (!I.hgs) return;
+    const int ntx = I.ntx, nty = I.nty;
+    const uint8_t *act = I.act[par];
+    uint8_t *act_next = I.act[par ^ 1];
+    uint4 *tm_next = I.tmax[par ^ 1];
+    uint8_t *synced = I.synced;
+    const int per = (c1 - c0 + RT - 1) / RT;  // at most 32 (chunk <= 32 RT)
+    const int t0 = min(c1, c0 + (int)threadIdx.x * per), t1 = min(c1, t0 + per);
+    unsigned m_act = 0u, m_run = 0u, m_copy = 0u;
+    int bx = t0 % ntx, by = t0 / ntx;
+    for (int t = t0; t < t1; ++t) {
+        // all five flags and the synced flag loaded together (no short circuit)
+        const unsigned fa = act[t], fw = act[bx > 0 ? t - 1 : t], fe = act[bx + 1 < ntx ? t + 1 : t];
+        const unsigned fs = act[by > 0 ? t - ntx : t], fn = act[by + 1 < nty ? t + ntx : t];
+        const unsigned sy = synced[t];
+        const int q = t - t0;
+        const bool r = (fa | fw | fe | fs | fn) != 0;
+        m_act |= (unsigned)(fa != 0) << q;
+        m_run |= (unsigned)r << q;
+        m_copy |= (unsigned)(!r && !sy) << q;
+        if (++bx == ntx) { bx = 0; ++by; }
+    }
+    int ol, oe, tl, te;
+    block_scan2(__popc(m_act), __popc(m_run | m_copy), ol, oe, tl, te);
+    int *lag = I.lag + c0, *eul = I.eul + c0;
+    for (int t = t0; t < t1; ++t) {
+        const unsigned bit = 1u << (t - t0);
+        if (m_act & bit) lag[ol++] = t;
+        if (m_run & bit) {
+            eul[oe++] = t;
+            synced[t] = 0;
+        } else {
+            if (m_copy & bit) {
+                eul[oe++] = -1 - t;
+                synced[t] = 1;
+            }
+            act_next[t] = 0;
+            tm_next[t] = make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
+    if (threadIdx.x == 0) {
+        I.cnt_l[b] = tl;
+        I.cnt_e[b] = te;
+    }
+}
+
+// Entry w of a list kept in segments: the segment is the last one whose
+// start position is <= w (one ballot per 64 segments).
+__device__ __forceinline__ int list_entry(const int *seg, const int *pre, int nb, int chunk, int w)
+{
+    const int lane = threadIdx.x & 63;
+    int b = -1;
+    for (int g = 0; g < nb; g += 64) {
+        const int k = g + lane;
+        const unsigned long long le = __ballot(k < nb && pre[k] <= w);
+        b += __popcll(le);
+        if (le != ~0ull) break;
+    }
+    return seg[b * chunk + (w - pre[b])];
+}
+
+// Bring the other buffer level of a dry strip tile to the current state.
+template <int S>
+__device__ void strip_copy(const Inst &I, int par, int bx, int by)
+{
+    const int lane = threadIdx.x & 63;
+    const int i = bx * SX + lane;
+    if (lane >= SX || i >= I.P.nx) return;
+    const int y0 = by * S, jend = min(y0 + S, I.P.ny);
+    for (int j = y0; j < jend; ++j) {
+        const int c = j * I.P.pitch + i;
+        I.H[par ^ 1][c] = I.H[par][c];
+        I.qx[par ^ 1][c] = I.qx[par][c];
+        I.qy[par ^ 1][c] = I.qy[par][c];
+        I.b[par ^ 1][c] = I.b[par][c];
+    }
+}
+
+// Strip stages over the step's lists: wavefront w takes entry w (tile w when
+// nothing is skipped).  The grid covers the longest possible list; the
+// listed tiles come first in dispatch order and the waves past the end of
+// the list leave at once.
+// Start position of every segment of a list from the segment lengths (one
+// wave scan per 64 segments): returns the list length; *seg / *start receive
+// the segment holding entry w and its start (when w is below the length).
+__device__ __forceinline__ int list_locate(const int *cnt, int nb, int w, int &seg, int &start,
+                                           int *pre_out)
+{
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    seg = 0;
+    start = 0;
+    for (int g = 0; g < nb; g += 64) {
+        const int k = g + lane;
+        const int c = k < nb ? cnt[k] : 0;
+        const int inc = wave_scan(c);
+        const int st = base + inc - c;
+        if (pre_out && k < nb) pre_out[k] = st;
+        const unsigned long long le = __ballot(k < nb && st <= w);
+        if (le) {
+            const int j = 63 - __clzll(le);  // the set lanes are a prefix (starts never decrease)
+            seg = g + j;
+            start = __shfl(st, j);
+        }
+        base += __shfl(inc, 63);
+    }
+    return base;
+}
+
+template <int S, bool CS>
+__global__ void __launch_bounds__(NT) k_lagrange_sl(Inst I, int par)
+{
+    Ctrl *ctrl = I.ctrl;
+    if (ctrl->err) return;
+    const int lane = threadIdx.x & 63;
+    const int w = blockIdx.x * SWAVES + (threadIdx.x >> 6);
+    const bool publisher = w == 0;
+    const int nb = I.nchunk;
+    int n = I.ntx * I.nty, seg = 0, start = 0;
+    if (I.hgs) n = list_locate(I.cnt_l, nb, w, seg, start, nullptr);
+    if (w >= n && !publisher) return;
+    // the Eq. 7 step from the segment maxima (K3 proper)
+    unsigned a = 0, b = 0, c = 0, bad = 0;
+    for (int g = 0; g < nb; g += 64) {
+        const uint4 v = g + lane < nb ? I.part[g + lane] : make_uint4(0u, 0u, 0u, 0u);
+        a = max(a, v.x); b = max(b, v.y); c = max(c, v.z); bad = max(bad, v.w);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a = max(a, (unsigned)__shfl_xor((int)a, off));
+        b = max(b, (unsigned)__shfl_xor((int)b, off));
+        c = max(c, (unsigned)__shfl_xor((int)c, off));
+        bad = max(bad, (unsigned)__shfl_xor((int)bad, off));
+    }
+    const uint4 m = make_uint4(a, b, c, bad);
+    if (publisher) {
+        if (I.hgs) {  // start positions of the Euler list for the Euler kernel
+            int s0, s1;
+            const int ne = list_locate(I.cnt_e, nb, 0, s0, s1, I.pre_e);
+            if (lane == 0) I.totals[1] = ne;
+        }
+        if (lane == 0) publish_dt(ctrl, par, I.A, m);
+    }
+    const Eq7 e = eq7_step(I.A, m);
+    if (e.err || w >= n) return;
+    const int t = I.hgs ? I.lag[seg * I.chunk + (w - start)] : w;
+    lagrange_strip<S, CS>(I, par, t % I.ntx, t / I.ntx, (float)e.dt);
+}
+template <int S, bool CS>
+__global__ void __launch_bounds__(NT) k_euler_sl(Inst I, int par)
+{
+    if (I.ctrl->err) return;
+    const int w = blockIdx.x * SWAVES + (threadIdx.x >> 6);
+    const int n = I.hgs ? I.totals[1] : I.ntx * I.nty;
+    if (w >= n) return;
+    const int e = I.hgs ? list_entry(I.eul, I.pre_e, I.nchunk, I.chunk, w) : w;
+    const int t = e < 0 ? -1 - e : e;
+    if (e < 0) strip_copy<S>(I, par, t % I.ntx, t / I.ntx);
+    else euler_strip<S, CS>(I, par, t % I.ntx, t / I.ntx, false);
 }
 
 // Tile shapes the autotuner chooses from: TX x TY cells per 256-thread
@@ -1483,6 +1731,8 @@ struct sw_ctx {
     int shape = kDefaultShape;       // index into kShapes
     size_t max_tiles = 0;            // tile count of the smallest shape (flag capacity)
     uint4 *tmax = nullptr;           // per-tile Eq. 7 maxima, two rings of max_tiles
+    int *sched = nullptr;            // work lists of the strip kernels (layout: sched_layout)
+    int max_chunks = 0;              // list segments of the largest tile grid
     int graph_fixed = 0;
     double graph_dt = 0.0;
     std::string err;
@@ -1568,6 +1818,29 @@ int download_plane(sw_ctx *c, float *dst, const float *src, int ptr_kind)
 dim3 cell_grid(const sw_ctx *c) { return dim3((c->nx + BX - 1) / BX, (c->ny + BY - 1) / BY); }
 
 size_t ntiles(const sw_ctx *c) { return (size_t)c->ntx * c->nty; }
+
+// Tiles per K3 workgroup (list segment) for nt tiles: at least RT, at most
+// 32 RT (one 32-bit mask per thread), and at most 64 segments where possible.
+int list_chunk(int nt) { return std::min(32 * RT, std::max(RT, (nt + 63) / 64)); }
+
+// Offsets (in ints) of the parts of the work-list buffer.
+struct SchedLayout {
+    size_t totals, cnt_l, cnt_e, pre_l, pre_e, part, lag, eul, total;
+};
+SchedLayout sched_layout(int nchunks, size_t tiles)
+{
+    SchedLayout L;
+    L.totals = 0;
+    L.cnt_l = 4;
+    L.cnt_e = L.cnt_l + nchunks;
+    L.pre_l = L.cnt_e + nchunks;
+    L.pre_e = L.pre_l + nchunks + 1;
+    L.part = (L.pre_e + nchunks + 1 + 3) / 4 * 4;  // uint4 aligned
+    L.lag = L.part + 4 * (size_t)nchunks;
+    L.eul = L.lag + tiles;
+    L.total = L.eul + tiles;
+    return L;
+}
 uint8_t *act_flags(const sw_ctx *c, int par) { return c->tflags + par * c->max_tiles; }
 uint8_t *synced_flags(const sw_ctx *c) { return c->tflags + 2 * c->max_tiles; }
 uint8_t *force_flags(const sw_ctx *c) { return c->tflags + 3 * c->max_tiles; }
@@ -1617,6 +1890,19 @@ Inst make_inst(const sw_ctx *c, const StepArgs &A)
     I.ntx = c->ntx;
     I.nty = c->nty;
     I.hgs = (c->par.flags & SW_FLAG_HGS) ? 1 : 0;
+    const int nt = c->ntx * c->nty;
+    I.chunk = list_chunk(nt);
+    I.nchunk = (nt + I.chunk - 1) / I.chunk;
+    SchedLayout L = sched_layout(c->max_chunks, c->max_tiles);
+    int *sb = c->sched;
+    I.totals = sb + L.totals;
+    I.cnt_l = sb + L.cnt_l;
+    I.cnt_e = sb + L.cnt_e;
+    I.pre_l = sb + L.pre_l;
+    I.pre_e = sb + L.pre_e;
+    I.part = (uint4 *)(sb + L.part);
+    I.lag = sb + L.lag;
+    I.eul = sb + L.eul;
     return I;
 }
 
@@ -1679,22 +1965,21 @@ void launch_batch(int shape, Stage st, hipStream_t s, const Inst *insts, int nme
 // Whether a grid's kernels must read per-cell soil or source planes.
 bool cell_soil(const KPar &P) { return P.nM || P.d50 || P.psi || P.srcw || P.qb; }
 
-// Strip shapes: the prepare pass runs one workgroup per tile, the stage
-// kernels one wavefront per tile.
+// Strip shapes: the prepare pass runs one workgroup per tile; K3 builds the
+// work lists; the stage kernels run one wavefront per list entry.
 template <int S>
 void launch_strip_t(Stage st, hipStream_t s, const Inst &I, int par)
 {
-    const dim3 gt(I.ntx, I.nty), gs(I.ntx, (I.nty + SWAVES - 1) / SWAVES);
+    const dim3 gt(I.ntx, I.nty);
+    const int gl = (I.ntx * I.nty + SWAVES - 1) / SWAVES;  // one wavefront per possible entry
+    const bool cs = cell_soil(I.P);
+    auto lag = cs ? k_lagrange_sl<S, true> : k_lagrange_sl<S, false>;
+    auto eul = cs ? k_euler_sl<S, true> : k_euler_sl<S, false>;
     if (st == kPrepare) hipLaunchKernelGGL((k_prepare_t<SX, S>), gt, dim3(NT), 0, s, I, par);
-    else if (st == kDt) hipLaunchKernelGGL(k_dt_t, dim3(1), dim3(RT), 0, s, I, par);
+    else if (st == kDt) hipLaunchKernelGGL(k_dt_lists, dim3(I.nchunk), dim3(RT), 0, s, I, par);
     else if (st == kCount) hipLaunchKernelGGL(k_count_t, dim3(1), dim3(RT), 0, s, I, par, SX, S);
-    else if (st == kLagrange) {
-        if (cell_soil(I.P)) hipLaunchKernelGGL((k_lagrange_s<S, true>), gs, dim3(NT), 0, s, I, par);
-        else hipLaunchKernelGGL((k_lagrange_s<S, false>), gs, dim3(NT), 0, s, I, par);
-    } else {
-        if (cell_soil(I.P)) hipLaunchKernelGGL((k_euler_s<S, true>), gs, dim3(NT), 0, s, I, par);
-        else hipLaunchKernelGGL((k_euler_s<S, false>), gs, dim3(NT), 0, s, I, par);
-    }
+    else if (st == kLagrange) hipLaunchKernelGGL(lag, dim3(gl), dim3(NT), 0, s, I, par);
+    else hipLaunchKernelGGL(eul, dim3(gl), dim3(NT), 0, s, I, par);
 }
 
 void launch_stage(int shape, Stage st, hipStream_t s, const Inst &I, int par)
@@ -1921,11 +2206,16 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
     for (int sh = 0; sh < kNumShapes; ++sh) {
         set_shape(c, sh);
         c->max_tiles = std::max(c->max_tiles, ntiles(c));
+        const int nt = (int)ntiles(c), ch = list_chunk(nt);
+        c->max_chunks = std::max(c->max_chunks, (nt + ch - 1) / ch);
     }
     set_shape(c, kDefaultShape);
     if ((e = hipMalloc(&c->tflags, 4 * c->max_tiles)) != hipSuccess) return bail(e, "hipMalloc(tiles)");
     if ((e = hipMemset(c->tflags, 0, 4 * c->max_tiles)) != hipSuccess) return bail(e, "hipMemset(tiles)");
     if ((e = hipMalloc(&c->tmax, 2 * c->max_tiles * sizeof(uint4))) != hipSuccess) return bail(e, "hipMalloc(tmax)");
+    const size_t nsched = sched_layout(c->max_chunks, c->max_tiles).total;
+    if ((e = hipMalloc(&c->sched, nsched * sizeof(int))) != hipSuccess) return bail(e, "hipMalloc(sched)");
+    if ((e = hipMemset(c->sched, 0, nsched * sizeof(int))) != hipSuccess) return bail(e, "hipMemset(sched)");
     if ((e = hipMemset(c->tmax, 0, 2 * c->max_tiles * sizeof(uint4))) != hipSuccess) return bail(e, "hipMemset(tmax)");
     if ((e = hipMalloc(&c->ctrl, sizeof(Ctrl))) != hipSuccess) return bail(e, "hipMalloc(ctrl)");
     if ((e = hipMemset(c->ctrl, 0, sizeof(Ctrl))) != hipSuccess) return bail(e, "hipMemset(ctrl)");
@@ -1949,6 +2239,7 @@ int sw_destroy(sw_ctx *c)
     (void)hipFree(c->srcw);
     (void)hipFree(c->tflags);
     (void)hipFree(c->tmax);
+    (void)hipFree(c->sched);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
