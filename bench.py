@@ -9,8 +9,10 @@ step, then the fused Euler stage), replayed from a HIP graph with dry tiles
 skipped.  Inputs are resident on the GPU before the timed region starts.
 
 Prints one JSON line: value = grid cells x steps / wall time (Gcell-steps/s),
-a roofline object for the dominant kernel (timed live with HIP events on the
-solver's stream), the CPU oracle timed on a bounded sample of the same
+a roofline object for the dominant kernel (the strip Euler kernel, timed live
+with HIP events on the solver's stream; HBM traffic and executed VALU work per
+launch from the committed rocprofv3 counter summary when it was taken on the
+current kernel sources), the CPU oracle timed on a bounded sample of the same
 workload, and side measurements (the river-valley grid with dry-tile skipping
 on and off).
 """
@@ -27,14 +29,47 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+# FP32 VALU issue peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_TLANE = 256 * 4 * 16 * 2.4e9 / 1e12
+KERNEL_SOURCES = ("paper_2103_15196_amd/csrc/csph.hip", "paper_2103_15196_amd/csrc/csph_device.h")
+PROFILE = "profiles/k_euler_sl_dam_break_2048_counters.md"
 # algorithmic bytes per cell of one launch (float32 planes read + written)
 EULER_BYTES = {"scalar_soil": 40, "per_cell_soil": 52}    # h,hu,hv,b,QLx,QLy in; h,hu,hv,b out (+nM,d50,psi)
+# (per processed cell of one Euler launch: the strip kernel reads each of these once
+# from HBM when halo rows and columns are served from cache)
 LAGRANGE_BYTES = {"scalar_soil": 24, "per_cell_soil": 28}  # h,hu,hv,b in; QLx,QLy out (+nM)
 STEP_BYTES = 32  # per cell-step: state read once + written once
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_counters():
+    """Per-launch HBM bytes and VALU instructions of the dominant kernel from
+    the committed rocprofv3 summary, if it was taken on the current kernel
+    sources (else None: the counters no longer describe this kernel)."""
+    path = os.path.join(ROOT, PROFILE)
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if line.startswith("<!-- bench:"):
+            for kv in line.strip()[len("<!-- bench:"):-3].split():
+                k, v = kv.split("=", 1)
+                rec[k] = v
+    if rec.get("src_sha256") != kernel_source_hash():
+        return None
+    return rec
 
 
 def main():
@@ -114,6 +149,7 @@ def main():
     soil = "scalar_soil"
     eul_bytes = eul_cells * EULER_BYTES[soil]
     achieved = eul_bytes / (eul_ms * 1e-3) / 1e9
+    prof = profiled_counters()
     log(f"[bench] kernels: lagrange {lag_ms*1e3:.1f} us ({lag_cells:.0f} cells), "
         f"euler {eul_ms*1e3:.1f} us ({eul_cells:.0f} cells) -> {achieved:.0f} GB/s")
     s.close()
@@ -136,13 +172,23 @@ def main():
                    "bc": "open", "cfl": w.cfl, "sed_law": "grass", "skip_dry_tiles": True,
                    "graph": True, "parallelism": "single-gpu"},
         "hbm_frac_algorithmic": round(value * STEP_BYTES / HBM_PEAK_GBS, 4),
-        "roofline": {"kernel": "k_euler_t", "bound": "hbm", "achieved": round(achieved, 1),
+        "roofline": {"kernel": "k_euler_sl<8,false>", "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "avg_launch_us": round(eul_ms * 1e3, 2),
+                     "traffic": (int(float(prof["traffic_bytes"])) if prof else None),
+                     "avg_launch_us": round(eul_ms * 1e3, 2),
                      "bytes_per_cell": EULER_BYTES[soil], "cells_per_launch": round(eul_cells),
                      "lagrange_avg_launch_us": round(lag_ms * 1e3, 2)},
         "time_s_model": sums["t"],
     }
+    if prof:
+        # executed VALU work of the same kernel (profiled on these sources):
+        # the roof this ALU-bound stencil actually runs against
+        lane_ops = float(prof["valu_insts"]) * 64
+        ach = lane_ops / (eul_ms * 1e-3) / 1e12
+        out["alu"] = {"kernel": "k_euler_sl<8,false>", "achieved": round(ach, 2),
+                      "peak": round(VALU_PEAK_TLANE, 2), "unit": "Tlane-op/s",
+                      "frac": round(ach / VALU_PEAK_TLANE, 4),
+                      "valu_lane_ops_per_launch": int(lane_ops)}
 
     if not args.no_extras:
         out["river_valley"] = river_valley_rates(csph, W, torch)
