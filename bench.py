@@ -14,7 +14,7 @@ with HIP events on the solver's stream; HBM traffic and executed VALU work per
 launch from the committed rocprofv3 counter summary when it was taken on the
 current kernel sources), the CPU oracle timed on a bounded sample of the same
 workload, and side measurements (the river-valley grid with dry-tile skipping
-on and off).
+on and off; the learned surrogate's accuracy and effective rate).
 """
 from __future__ import annotations
 
@@ -192,6 +192,7 @@ def main():
 
     if not args.no_extras:
         out["river_valley"] = river_valley_rates(csph, W, torch)
+        out["surrogate"] = surrogate_rates(csph, torch)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
@@ -223,6 +224,36 @@ def river_valley_rates(csph, W, torch, n=8192, steps=2000):
                      "t_model_s": round(sums["t"], 3)}
         log(f"[bench]   {name}: {res[name]}")
         s.close()
+    return res
+
+
+def surrogate_rates(csph, torch, train_steps=1500):
+    """The learned surrogate (6 BF16 matrix-core 3x3 convolutions, widths 5, 48 x 5, 4)
+    trained here on 24 closed-basin trajectories of 128^2 (k = 8 fixed steps per
+    call): held-out depth error against the 5e-3 m gate, and the effective rate
+    of the surrogate step on a 1024^2 basin (fall backs included) next to the
+    plain solver's 8 fixed steps."""
+    import numpy as np
+    from paper_2103_15196_amd import surrogate as SG
+    st = torch.cuda.current_stream().cuda_stream
+    t0 = time.perf_counter()
+    tr = SG.collect(range(5000, 5024), 128, 160, 8, stream=st)
+    ho = SG.collect(range(6000, 6004), 128, 160, 8, stream=st)
+    ins, outs = SG.scales(tr)
+    net = csph.Surrogate(SG.DESIGN_CHANNELS, stream=st)
+    net.set_params(SG.he_init(SG.DESIGN_CHANNELS, 1))
+    losses = SG.train(net, tr, ins, outs, steps=train_steps, batch=8, lr=1e-3)
+    err, drift = SG.evaluate(net, ho, ins, outs)
+    w = SG.basin(1024, 6100, 5.0)
+    gain = SG.measure_gain(net, w, SG.fixed_dt(w), calls=20, k=8, stream=st)
+    net.close()
+    enabled = bool(err.max() <= 5e-3)
+    res = {"train_pairs": int(len(tr.x)), "train_steps": train_steps,
+           "final_loss": round(float(np.mean(losses[-50:])), 5),
+           "heldout_linf_dh_m": round(float(err.max()), 5), "gate_m": 5e-3, "enabled": enabled,
+           "heldout_median_volume_drift": float(np.median(drift)), **gain,
+           "seconds": round(time.perf_counter() - t0, 1)}
+    log(f"[bench]   surrogate: {res}")
     return res
 
 

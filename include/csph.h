@@ -143,6 +143,18 @@ int sw_set_sed_sources(sw_ctx *ctx, const float *qb_plus, const float *qb_minus,
 /* Model time and step counter reported by sw_get_sums (does not touch fields). */
 int sw_set_time(sw_ctx *ctx, double t, int64_t step);
 
+/* Replace bed and state with device arrays [ny][nx] (dense rows) and set the
+ * model time t and step counter: no copy through the host and no check, for
+ * drivers that produce states on the GPU (the caller guarantees finite
+ * values, h >= 0 and hu = hv = 0 where h = 0).  The Lagrangian momentum, the
+ * balances and any pending device error are cleared, as by sw_set_state.
+ * Stream-ordered; SW_ERR_ARG for NULL pointers. */
+int sw_replace_state(sw_ctx *ctx, const float *h, const float *hu, const float *hv,
+                     const float *b, double t, int64_t step);
+
+/* The grid the context was created with. */
+int sw_get_grid(const sw_ctx *ctx, sw_grid *out);
+
 /* Advance nsteps CSPH-TVD steps (Section 3 kernels K1..K8) with the Eq. 7
  * time step.  Asynchronous: errors raised on the device (SW_ERR_NONFINITE,
  * SW_ERR_DT_UNDERFLOW) stop all later steps and are returned by the next

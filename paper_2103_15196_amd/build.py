@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", "csph.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "csph.hip"), os.path.join(HERE, "csrc", "surrogate.hip")]
 OUT = os.path.join(HERE, "libcsph.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -91,6 +91,24 @@ SIGNATURES = [
     ("swb_advance", C.c_int, [C.c_void_p, C.c_int32]),
     ("swb_sync", C.c_int, [C.c_void_p]),
     ("swb_last_error", C.c_char_p, [C.c_void_p]),
+    ("sw_replace_state", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_double, C.c_int64]),
+    ("sw_get_grid", C.c_int, [_ctxp, C.POINTER(sw_grid)]),
+    ("sws_create", C.c_int, [C.POINTER(C.c_int32), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("sws_destroy", C.c_int, [C.c_void_p]),
+    ("sws_param_count", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("sws_set_params", C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    ("sws_get_params", C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    ("sws_set_scales", C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    ("sws_forward", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                              C.c_int]),
+    ("sws_train_step", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                 C.c_int32, C.c_float, C.POINTER(C.c_double), C.c_int]),
+    ("sws_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                           C.c_void_p, C.POINTER(C.c_double), C.c_int]),
+    ("sws_advance", C.c_int, [C.c_void_p, _ctxp, C.c_int32, C.c_double, C.c_double,
+                              C.POINTER(C.c_int32)]),
+    ("sws_last_error", C.c_char_p, [C.c_void_p]),
 ]
 
 
@@ -325,3 +343,90 @@ class Batch:
 
     def sync(self):
         _bcheck(self.ctx, lib.swb_sync(self.ctx))
+
+
+def _scheck(h, rc):
+    if rc != SW_OK:
+        msg = lib.sws_last_error(h).decode() if h else ""
+        raise SwError(rc, msg)
+
+
+class Surrogate:
+    """The convolutional surrogate (BF16 matrix-core convolutions): widths
+    `channels` (5 inputs ... 4 outputs); parameters as one FP32 vector (per
+    layer W[c_out][c_in][3][3] then b[c_out])."""
+
+    def __init__(self, channels, stream=None):
+        self.channels = [int(c) for c in channels]
+        arr = (C.c_int32 * len(self.channels))(*self.channels)
+        h = C.c_void_p()
+        _scheck(None, lib.sws_create(arr, len(self.channels) - 1, stream, C.byref(h)))
+        self.ctx = h
+        n = C.c_int64()
+        _scheck(self.ctx, lib.sws_param_count(self.ctx, C.byref(n)))
+        self.nparam = n.value
+
+    def close(self):
+        if self.ctx:
+            lib.sws_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, dtype=np.float32).reshape(-1)
+        assert a.size == self.nparam
+        _scheck(self.ctx, lib.sws_set_params(self.ctx, a.ctypes.data, SW_PTR_HOST))
+
+    def get_params(self):
+        a = np.empty(self.nparam, np.float32)
+        _scheck(self.ctx, lib.sws_get_params(self.ctx, a.ctypes.data, SW_PTR_HOST))
+        return a
+
+    def set_scales(self, in_scale, out_scale):
+        i = (C.c_float * 5)(*[float(v) for v in in_scale])
+        o = (C.c_float * 4)(*[float(v) for v in out_scale])
+        _scheck(self.ctx, lib.sws_set_scales(self.ctx, i, o))
+
+    def forward(self, x):
+        """x: [nimg, 5, ny, nx] -> [nimg, 4, ny, nx] (host arrays)."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        nimg, c, ny, nx = x.shape
+        assert c == 5
+        y = np.empty((nimg, 4, ny, nx), np.float32)
+        _scheck(self.ctx, lib.sws_forward(self.ctx, x.ctypes.data, y.ctypes.data, nimg, nx, ny,
+                                          SW_PTR_HOST))
+        return y
+
+    def grad(self, x, target):
+        """(gradient vector, loss) without an update."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(target, dtype=np.float32)
+        nimg, _, ny, nx = x.shape
+        g = np.empty(self.nparam, np.float32)
+        loss = C.c_double()
+        _scheck(self.ctx, lib.sws_grad(self.ctx, x.ctypes.data, t.ctypes.data, nimg, nx, ny,
+                                       g.ctypes.data, C.byref(loss), SW_PTR_HOST))
+        return g, loss.value
+
+    def train_step(self, x, target, lr):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(target, dtype=np.float32)
+        nimg, _, ny, nx = x.shape
+        loss = C.c_double()
+        _scheck(self.ctx, lib.sws_train_step(self.ctx, x.ctypes.data, t.ctypes.data, nimg, nx, ny,
+                                             float(lr), C.byref(loss), SW_PTR_HOST))
+        return loss.value
+
+    def advance(self, solver, k, dt, max_drift=1e-5):
+        """k steps of `solver` by the surrogate (or by the solver if the water
+        volume would change by more than max_drift); returns True if the
+        surrogate's prediction was kept."""
+        used = C.c_int32()
+        _scheck(self.ctx, lib.sws_advance(self.ctx, solver.ctx, int(k), float(dt), float(max_drift),
+                                          C.byref(used)))
+        return bool(used.value)

@@ -2424,6 +2424,39 @@ int sw_set_time(sw_ctx *c, double t, int64_t step)
     return SW_OK;
 }
 
+int sw_replace_state(sw_ctx *c, const float *h, const float *hu, const float *hv, const float *b,
+                     double t, int64_t step)
+{
+    if (!c) return SW_ERR_ARG;
+    if (!h || !hu || !hv || !b) return fail(c, SW_ERR_ARG, "state pointer is NULL");
+    int rc;
+    c->k = 0;
+    if ((rc = upload_plane(c, c->H[0], h, SW_PTR_DEVICE))) return rc;
+    if ((rc = upload_plane(c, c->qx[0], hu, SW_PTR_DEVICE))) return rc;
+    if ((rc = upload_plane(c, c->qy[0], hv, SW_PTR_DEVICE))) return rc;
+    if ((rc = upload_plane(c, c->b[0], b, SW_PTR_DEVICE))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->b[1], c->b[0], c->plane * sizeof(float), hipMemcpyDeviceToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemsetAsync(c->QLx, 0, 2 * c->plane * sizeof(float), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->bnd, 0, 4 * (size_t)(c->nx + c->ny) * sizeof(double), c->stream));
+    Ctrl h0{};
+    h0.t[0] = t;
+    HIPCHK(c, hipMemcpyAsync(c->ctrl, &h0, sizeof(Ctrl), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // h0 lives on this stack frame
+    c->t0 = t;
+    c->step0 = step;
+    c->have_state = true;
+    c->dirty = true;
+    return SW_OK;
+}
+
+int sw_get_grid(const sw_ctx *c, sw_grid *out)
+{
+    if (!c || !out) return SW_ERR_ARG;
+    *out = c->grid;
+    return SW_OK;
+}
+
 int sw_advance(sw_ctx *c, int32_t nsteps) { return launch_steps(c, nsteps, 0, 0.0); }
 
 int sw_advance_fixed_dt(sw_ctx *c, int32_t nsteps, double dt) { return launch_steps(c, nsteps, 1, dt); }

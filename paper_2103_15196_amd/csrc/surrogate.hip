@@ -1,0 +1,808 @@
+// surrogate.hip -- the learned surrogate of the CSPH-TVD step on gfx950: 3x3
+// convolutions on the matrix cores (v_mfma_f32_16x16x32_bf16: BF16 operands,
+// FP32 accumulation), training kernels (input gradients on the matrix cores,
+// weight gradients and Adam in FP32) and the surrogate step with its mass
+// check and plain-solver fall back.
+//
+// Layouts.  Activations are BF16, channels last ("NHWC"): [img][y][x][C] with
+// C = 8 for the 5-channel input (channels 5..7 zero) and C = 48 for the
+// hidden layers.  A convolution is an implicit GEMM: output pixel m (16 per
+// MFMA block, consecutive along x), output channel n (16 per block) and the
+// reduction index k = tap * C + c over the 9 taps (ky, kx) and C channels,
+// padded to a multiple of 32.  Lane l of a wavefront holds A[l % 16][8 (l/16)
+// .. +7] (8 channels of one pixel at one tap: a 16-byte load), B[8 (l/16) ..
+// +7][l % 16] and D[4 (l/16) .. +3][l % 16] (checked on the GPU).  Weights are
+// packed once per update into exactly these per-lane B fragments.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "csph.h"
+#include "surrogate.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int MAXW = 48;      // widest layer
+constexpr int CIN0 = 8;       // stored channels of the 5-channel input
+constexpr int NT = 256;       // threads per workgroup
+constexpr int NWAVE = NT / 64;
+
+__device__ __forceinline__ unsigned short bf16_bits(float f)
+{
+    // round to nearest even (NaN kept quiet)
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_float(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// One layer's geometry: stored input channels (8 or 48), valid input and
+// output channels, output channel blocks of 16, reduction chunks of 32.
+struct Geo {
+    int cs, cin, cout, nb, kc;
+};
+
+// ---------------------------------------------------------------------------
+// Weight packing: B[k][n] = Wf[n][c][ky][kx] for k = (3 ky + kx) cs + c, in the
+// per-lane fragment order [nb][kc][lane][8].  flip: the weights of the
+// transposed convolution (input gradient), Wf[n][c][ky][kx] = W[c][n][2-ky][2-kx].
+// ---------------------------------------------------------------------------
+__global__ void k_pack(const float *__restrict__ W, Geo g, int flip, int wcin, int wcout,
+                       unsigned short *__restrict__ out)
+{
+    const int total = g.nb * g.kc * 64 * 8;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
+        const int j = q & 7, lane = (q >> 3) & 63, f = q >> 9;
+        const int kc = f % g.kc, nb = f / g.kc;
+        const int k = 32 * kc + 8 * (lane >> 4) + j, n = 16 * nb + (lane & 15);
+        const int tap = k / g.cs, c = k % g.cs;
+        float v = 0.0f;
+        if (tap < 9 && c < g.cin && n < g.cout) {
+            const int ky = tap / 3, kx = tap % 3;
+            // W is [wcout][wcin][3][3]
+            v = flip ? W[((c * wcin + n) * 3 + (2 - ky)) * 3 + (2 - kx)]
+                     : W[((n * wcin + c) * 3 + ky) * 3 + kx];
+        }
+        out[q] = bf16_bits(v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Convolution on the matrix cores.  Wavefront job = 16 consecutive pixels of
+// one row of one image, all output channels.  The packed weights of the layer
+// are staged in LDS once per workgroup; jobs are taken grid-stride.
+// mode 0: bias + ReLU -> BF16 NHWC (out_c channels stored)
+// mode 1: bias, no activation -> FP32 planar [img][cout][ny][nx]
+// mode 2: input gradient: no bias, times (mask > 0) -> BF16 NHWC (mask: the
+//         BF16 activation the gradient flows into, mask_c channels per pixel)
+// ---------------------------------------------------------------------------
+template <int NB, int KC>
+__global__ void __launch_bounds__(NT) k_conv(const unsigned short *__restrict__ in, Geo g,
+                                             const unsigned short *__restrict__ wpk,
+                                             const float *__restrict__ bias, int mode,
+                                             const unsigned short *__restrict__ mask, int mask_c,
+                                             void *__restrict__ out, int out_c, int nimg, int nx,
+                                             int ny)
+{
+    __shared__ uint4 sw[NB * KC * 64];
+    const uint4 *w4 = reinterpret_cast<const uint4 *>(wpk);
+    for (int q = threadIdx.x; q < NB * KC * 64; q += NT) sw[q] = w4[q];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int xblocks = (nx + 15) / 16;
+    const long jobs = (long)nimg * ny * xblocks;
+    const int m = lane & 15, kg = lane >> 4;
+    for (long job = (long)blockIdx.x * NWAVE + (threadIdx.x >> 6); job < jobs;
+         job += (long)gridDim.x * NWAVE) {
+        const int xb = (int)(job % xblocks);
+        const long rowi = job / xblocks;
+        const int y = (int)(rowi % ny), img = (int)(rowi / ny);
+        const int x0 = xb * 16;
+        floatx4 acc[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        const unsigned short *base = in + (long)img * ny * nx * g.cs;
+#pragma unroll 2
+        for (int kc = 0; kc < KC; ++kc) {
+            const int k = 32 * kc + 8 * kg;
+            const int tap = k / g.cs, c = k % g.cs;
+            uint4 a = make_uint4(0u, 0u, 0u, 0u);
+            if (tap < 9) {
+                const int yy = y + tap / 3 - 1, xx = x0 + m + tap % 3 - 1;
+                if ((unsigned)yy < (unsigned)ny && (unsigned)xx < (unsigned)nx)
+                    a = *reinterpret_cast<const uint4 *>(base + ((long)yy * nx + xx) * g.cs + c);
+            }
+            bf16x8 av;
+            __builtin_memcpy(&av, &a, 16);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const uint4 wv = sw[(b * KC + kc) * 64 + lane];
+                bf16x8 bv;
+                __builtin_memcpy(&bv, &wv, 16);
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[b], 0, 0, 0);
+            }
+        }
+        // lane holds output pixels x0 + 4 kg + i (i = 0..3), channel 16 b + m
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int n = 16 * b + m;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int xx = x0 + 4 * kg + i;
+                if (xx >= nx || n >= g.cout) continue;
+                const long pix = ((long)img * ny + y) * nx + xx;
+                float v = acc[b][i];
+                if (mode == 0) {
+                    v = fmaxf(v + bias[n], 0.0f);
+                    static_cast<unsigned short *>(out)[pix * out_c + n] = bf16_bits(v);
+                } else if (mode == 1) {
+                    v += bias[n];
+                    static_cast<float *>(out)[(((long)img * g.cout + n) * ny + y) * nx + xx] = v;
+                } else {
+                    if (!(bf16_float(mask[pix * mask_c + n]) > 0.0f)) v = 0.0f;
+                    static_cast<unsigned short *>(out)[pix * out_c + n] = bf16_bits(v);
+                }
+            }
+        }
+    }
+}
+
+// Planar FP32 [img][cin][ny][nx] -> BF16 NHWC with cs stored channels.
+__global__ void k_to_nhwc(const float *__restrict__ x, int cin, int cs, long npix_img, int nimg,
+                          unsigned short *__restrict__ out)
+{
+    const long total = npix_img * nimg;
+    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < total;
+         p += (long)gridDim.x * blockDim.x) {
+        const long img = p / npix_img, q = p % npix_img;
+        for (int c = 0; c < cs; ++c)
+            out[p * cs + c] = c < cin ? bf16_bits(x[(img * cin + c) * npix_img + q]) : 0;
+    }
+}
+
+// Loss and its gradient: d = y - t; loss partial sums of d^2 (FP64); the
+// gradient 2 d / N stored BF16 NHWC (cs channels) for the backward pass.
+__global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, int cout, int cs,
+                      long npix_img, int nimg, double inv_n, unsigned short *__restrict__ g,
+                      double *__restrict__ part)
+{
+    __shared__ double red[NWAVE];
+    double s = 0.0;
+    const long total = npix_img * nimg;
+    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < total;
+         p += (long)gridDim.x * blockDim.x) {
+        const long img = p / npix_img, q = p % npix_img;
+        for (int c = 0; c < cs; ++c) {
+            float gv = 0.0f;
+            if (c < cout) {
+                const long i = (img * cout + c) * npix_img + q;
+                const float d = y[i] - t[i];
+                s += (double)d * (double)d;
+                gv = (float)(2.0 * inv_n * (double)d);
+            }
+            g[p * cs + c] = bf16_bits(gv);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < NWAVE; ++w) s += red[w];
+        part[blockIdx.x] = s;
+    }
+}
+
+// Weight and bias gradients of one layer, FP32: dW[n][c][ky][kx] =
+// sum_pixels dz[p][n] x[p + (ky-1, kx-1)][c], db[n] = sum_pixels dz[p][n].
+// Workgroup job = 64 pixels of one row; x rows y-1..y+1 and dz staged in LDS;
+// thread t accumulates the (n, c) pairs t, t + 256, ... over all 9 taps and
+// all its jobs, then writes its partials (one slice per workgroup).
+constexpr int DWX = 64;
+__global__ void __launch_bounds__(NT) k_dw(const unsigned short *__restrict__ x, int cs, int cin,
+                                           const unsigned short *__restrict__ dz, int dcs, int cout,
+                                           int nimg, int nx, int ny, float *__restrict__ part)
+{
+    __shared__ unsigned short sx[3][DWX + 2][MAXW];
+    __shared__ unsigned short sd[DWX][MAXW];
+    const int npair = cout * cin;
+    constexpr int PP = (MAXW * MAXW + NT - 1) / NT;  // pairs per thread
+    float acc[PP][9];
+    float accb = 0.0f;
+#pragma unroll
+    for (int q = 0; q < PP; ++q)
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[q][t] = 0.0f;
+    const int xblocks = (nx + DWX - 1) / DWX;
+    const long jobs = (long)nimg * ny * xblocks;
+    for (long job = blockIdx.x; job < jobs; job += gridDim.x) {
+        const int xb = (int)(job % xblocks);
+        const long rowi = job / xblocks;
+        const int y = (int)(rowi % ny), img = (int)(rowi / ny);
+        const int x0 = xb * DWX;
+        __syncthreads();
+        for (int q = threadIdx.x; q < 3 * (DWX + 2) * cin; q += NT) {
+            const int c = q % cin, xx = (q / cin) % (DWX + 2), r = q / (cin * (DWX + 2));
+            const int gy = y + r - 1, gx = x0 + xx - 1;
+            unsigned short v = 0;
+            if ((unsigned)gy < (unsigned)ny && (unsigned)gx < (unsigned)nx)
+                v = x[(((long)img * ny + gy) * nx + gx) * cs + c];
+            sx[r][xx][c] = v;
+        }
+        for (int q = threadIdx.x; q < DWX * cout; q += NT) {
+            const int n = q % cout, xx = q / cout;
+            const int gx = x0 + xx;
+            sd[xx][n] = gx < nx ? dz[(((long)img * ny + y) * nx + gx) * dcs + n] : 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PP; ++q) {
+            const int pr = threadIdx.x + q * NT;
+            if (pr >= npair) continue;
+            const int n = pr / cin, c = pr % cin;
+            for (int xx = 0; xx < DWX; ++xx) {
+                const float d = bf16_float(sd[xx][n]);
+                if (d == 0.0f) continue;
+#pragma unroll
+                for (int t = 0; t < 9; ++t)
+                    acc[q][t] += d * bf16_float(sx[t / 3][xx + t % 3][c]);
+            }
+        }
+        if (threadIdx.x < cout)
+            for (int xx = 0; xx < DWX; ++xx) accb += bf16_float(sd[xx][threadIdx.x]);
+    }
+    float *mine = part + (long)blockIdx.x * (npair * 9 + cout);
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+        const int pr = threadIdx.x + q * NT;
+        if (pr >= npair) continue;
+        const int n = pr / cin, c = pr % cin;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) mine[(n * cin + c) * 9 + t] = acc[q][t];
+    }
+    if (threadIdx.x < cout) mine[npair * 9 + threadIdx.x] = accb;
+}
+
+// Sum of the per-workgroup partial gradients (fixed order) into grad.
+__global__ void k_dw_sum(const float *__restrict__ part, int nparts, int len,
+                         float *__restrict__ grad)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int p = 0; p < nparts; ++p) s += part[(long)p * len + i];
+        grad[i] = s;
+    }
+}
+
+// Adam with bias correction (Kingma & Ba 2015), FP32.
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, long n, float lr, float b1, float b2, float eps,
+                       float c1, float c2)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// Surrogate inputs from a solver state: x = scale * (h, hu, hv, b, h > 0).
+__global__ void k_inputs(const float *__restrict__ f, long n, float s0, float s1, float s2,
+                         float s3, float s4, unsigned short *__restrict__ out)
+{
+    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < n;
+         p += (long)gridDim.x * blockDim.x) {
+        const float h = f[p], qx = f[n + p], qy = f[2 * n + p], b = f[3 * n + p];
+        out[p * CIN0 + 0] = bf16_bits(s0 * h);
+        out[p * CIN0 + 1] = bf16_bits(s1 * qx);
+        out[p * CIN0 + 2] = bf16_bits(s2 * qy);
+        out[p * CIN0 + 3] = bf16_bits(s3 * b);
+        out[p * CIN0 + 4] = bf16_bits(h > 0.0f ? s4 : 0.0f);
+        for (int c = 5; c < CIN0; ++c) out[p * CIN0 + c] = 0;
+    }
+}
+
+// New state = old + out_scale * prediction (depth clamped at 0, momentum 0 on
+// dry cells); FP64 partial sums of the old and new depth.
+__global__ void k_apply(const float *__restrict__ f, const float *__restrict__ o, long n, float s0,
+                        float s1, float s2, float s3, float *__restrict__ nf,
+                        double *__restrict__ part)
+{
+    __shared__ double r0[NWAVE], r1[NWAVE];
+    double a = 0.0, b = 0.0;
+    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < n;
+         p += (long)gridDim.x * blockDim.x) {
+        const float h = f[p];
+        float hn = h + s0 * o[p];
+        if (!(hn > 0.0f)) hn = 0.0f;
+        const float qx = hn > 0.0f ? f[n + p] + s1 * o[n + p] : 0.0f;
+        const float qy = hn > 0.0f ? f[2 * n + p] + s2 * o[2 * n + p] : 0.0f;
+        nf[p] = hn;
+        nf[n + p] = qx;
+        nf[2 * n + p] = qy;
+        nf[3 * n + p] = f[3 * n + p] + s3 * o[3 * n + p];
+        a += (double)h;
+        b += (double)hn;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off);
+        b += __shfl_down(b, off);
+    }
+    if ((threadIdx.x & 63) == 0) { r0[threadIdx.x >> 6] = a; r1[threadIdx.x >> 6] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < NWAVE; ++w) { a += r0[w]; b += r1[w]; }
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+
+struct sws_net {
+    hipStream_t stream = nullptr;
+    int L = 0;
+    std::vector<int> ch;            // widths, L + 1
+    std::vector<Geo> fwd, bwd;      // per layer (bwd: transposed convolution)
+    std::vector<long> woff, boff;   // offsets of W_l, b_l in the parameter vector
+    long nparam = 0;
+    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;  // params, grads, Adam moments
+    std::vector<unsigned short *> wpk, wpk_t;                      // packed forward / transposed weights
+    long adam_t = 0;
+    float in_scale[5] = {1, 1, 1, 1, 1}, out_scale[4] = {1, 1, 1, 1};
+    bool packed = false;
+    // scratch (grown on demand)
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    std::string err;
+};
+
+namespace {
+
+int sfail(sws_net *n, int code, const std::string &msg)
+{
+    if (n) n->err = msg;
+    return code;
+}
+
+#define SHIP(n, call)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return sfail((n), SW_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int stored(int c) { return c <= CIN0 ? CIN0 : MAXW; }
+
+Geo make_geo(int cin, int cout)
+{
+    Geo g;
+    g.cs = stored(cin);
+    g.cin = cin;
+    g.cout = cout;
+    g.nb = (cout + 15) / 16;
+    g.kc = (9 * g.cs + 31) / 32;
+    return g;
+}
+
+size_t packed_len(const Geo &g) { return (size_t)g.nb * g.kc * 64 * 8; }
+
+int grid_for(long n) { return (int)std::min<long>(4096, std::max<long>(1, (n + NT - 1) / NT)); }
+
+template <int NB, int KC>
+void conv_t(hipStream_t s, int grid, const unsigned short *in, Geo g, const unsigned short *w,
+            const float *bias, int mode, const unsigned short *mask, int mask_c, void *out,
+            int out_c, int nimg, int nx, int ny)
+{
+    hipLaunchKernelGGL((k_conv<NB, KC>), dim3(grid), dim3(NT), 0, s, in, g, w, bias, mode, mask,
+                       mask_c, out, out_c, nimg, nx, ny);
+}
+
+// Dispatch on (output blocks, reduction chunks): KC = 3 for the 8-channel
+// input, 14 for 48 stored channels.
+int conv(sws_net *n, const unsigned short *in, const Geo &g, const unsigned short *w,
+         const float *bias, int mode, const unsigned short *mask, int mask_c, void *out, int out_c,
+         int nimg, int nx, int ny)
+{
+    const long jobs = (long)nimg * ny * ((nx + 15) / 16);
+    const int grid = (int)std::min<long>(2048, std::max<long>(1, (jobs + NWAVE - 1) / NWAVE));
+    hipStream_t s = n->stream;
+    if (g.kc == 3 && g.nb == 3) conv_t<3, 3>(s, grid, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
+    else if (g.kc == 3 && g.nb == 1) conv_t<1, 3>(s, grid, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
+    else if (g.kc == 3 && g.nb == 2) conv_t<2, 3>(s, grid, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
+    else if (g.kc == 14 && g.nb == 3) conv_t<3, 14>(s, grid, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
+    else if (g.kc == 14 && g.nb == 2) conv_t<2, 14>(s, grid, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
+    else if (g.kc == 14 && g.nb == 1) conv_t<1, 14>(s, grid, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
+    else return sfail(n, SW_ERR_ARG, "unsupported layer shape");
+    SHIP(n, hipGetLastError());
+    return SW_OK;
+}
+
+int pack_all(sws_net *n)
+{
+    for (int l = 0; l < n->L; ++l) {
+        const Geo &g = n->fwd[l];
+        hipLaunchKernelGGL(k_pack, dim3(grid_for((long)packed_len(g))), dim3(NT), 0, n->stream,
+                           n->p + n->woff[l], g, 0, n->ch[l], n->ch[l + 1], n->wpk[l]);
+        if (l > 0) {  // the input gradient of layer 0 is never needed
+            const Geo &t = n->bwd[l];
+            hipLaunchKernelGGL(k_pack, dim3(grid_for((long)packed_len(t))), dim3(NT), 0,
+                               n->stream, n->p + n->woff[l], t, 1, n->ch[l], n->ch[l + 1],
+                               n->wpk_t[l]);
+        }
+    }
+    SHIP(n, hipGetLastError());
+    n->packed = true;
+    return SW_OK;
+}
+
+int ensure_scratch(sws_net *n, size_t bytes)
+{
+    if (bytes <= n->scratch_bytes) return SW_OK;
+    SHIP(n, hipStreamSynchronize(n->stream));
+    (void)hipFree(n->scratch);
+    n->scratch = nullptr;
+    n->scratch_bytes = 0;
+    SHIP(n, hipMalloc(&n->scratch, bytes));
+    // channels a layer narrower than its stored width never writes must read as 0
+    SHIP(n, hipMemsetAsync(n->scratch, 0, bytes, n->stream));
+    n->scratch_bytes = bytes;
+    return SW_OK;
+}
+
+// Scratch layout for nimg images of npix pixels: activations of every layer
+// (BF16 NHWC, kept for the backward pass), the FP32 output, two gradient
+// buffers, weight-gradient partials and reduction partials.
+struct Scratch {
+    std::vector<unsigned short *> act;  // act[l]: input of layer l (stored channels)
+    float *out;
+    unsigned short *ga, *gb;
+    float *dwpart;
+    double *red;
+    size_t bytes;
+};
+constexpr int DW_GRID = 512;
+constexpr int RED_GRID = 1024;
+
+Scratch layout(const sws_net *n, long npix, char *base)
+{
+    Scratch s;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char *p = base ? base + off : nullptr;
+        off += (b + 255) / 256 * 256;
+        return p;
+    };
+    for (int l = 0; l < n->L; ++l)
+        s.act.push_back((unsigned short *)take((size_t)npix * stored(n->ch[l]) * 2));
+    s.out = (float *)take((size_t)npix * 4 * sizeof(float));
+    s.ga = (unsigned short *)take((size_t)npix * MAXW * 2);
+    s.gb = (unsigned short *)take((size_t)npix * MAXW * 2);
+    s.dwpart = (float *)take((size_t)DW_GRID * (MAXW * MAXW * 9 + MAXW) * sizeof(float));
+    s.red = (double *)take((size_t)2 * RED_GRID * sizeof(double));
+    s.bytes = off;
+    return s;
+}
+
+int forward_into(sws_net *n, const Scratch &s, int nimg, int nx, int ny)
+{
+    for (int l = 0; l < n->L; ++l) {
+        const bool last = l == n->L - 1;
+        int rc = conv(n, s.act[l], n->fwd[l], n->wpk[l], n->p + n->boff[l], last ? 1 : 0, nullptr,
+                      0, last ? (void *)s.out : (void *)s.act[l + 1],
+                      last ? 0 : stored(n->ch[l + 1]), nimg, nx, ny);
+        if (rc) return rc;
+    }
+    return SW_OK;
+}
+
+int copy_in(sws_net *n, void *dst, const void *src, size_t bytes, int ptr_kind)
+{
+    if (ptr_kind != SW_PTR_HOST && ptr_kind != SW_PTR_DEVICE)
+        return sfail(n, SW_ERR_ARG, "ptr_kind must be SW_PTR_HOST or SW_PTR_DEVICE");
+    SHIP(n, hipMemcpyAsync(dst, src, bytes,
+                           ptr_kind == SW_PTR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                           n->stream));
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sws_create(const int32_t *channels, int32_t nlayers, void *hip_stream, sws_net **out)
+{
+    if (!channels || !out || nlayers < 2) return SW_ERR_ARG;
+    *out = nullptr;
+    if (channels[0] != 5 || channels[nlayers] != 4) return SW_ERR_ARG;
+    for (int l = 0; l <= nlayers; ++l)
+        if (channels[l] < 1 || channels[l] > MAXW) return SW_ERR_ARG;
+    sws_net *n = new sws_net();
+    n->stream = (hipStream_t)hip_stream;
+    n->L = nlayers;
+    n->ch.assign(channels, channels + nlayers + 1);
+    long off = 0;
+    for (int l = 0; l < nlayers; ++l) {
+        n->fwd.push_back(make_geo(n->ch[l], n->ch[l + 1]));
+        // the transposed convolution reads gradient buffers of MAXW channels per pixel
+        Geo t = make_geo(n->ch[l + 1], n->ch[l]);
+        t.cs = MAXW;
+        t.kc = (9 * MAXW + 31) / 32;
+        n->bwd.push_back(t);
+        n->woff.push_back(off);
+        off += (long)n->ch[l + 1] * n->ch[l] * 9;
+        n->boff.push_back(off);
+        off += n->ch[l + 1];
+    }
+    n->nparam = off;
+    auto bail = [&](hipError_t e) {
+        sws_destroy(n);
+        (void)e;
+        return SW_ERR_HIP;
+    };
+    hipError_t e;
+    for (float **q : {&n->p, &n->g, &n->m, &n->v}) {
+        if ((e = hipMalloc(q, off * sizeof(float))) != hipSuccess) return bail(e);
+        if ((e = hipMemset(*q, 0, off * sizeof(float))) != hipSuccess) return bail(e);
+    }
+    for (int l = 0; l < nlayers; ++l) {
+        unsigned short *a = nullptr, *b = nullptr;
+        if ((e = hipMalloc(&a, packed_len(n->fwd[l]) * 2)) != hipSuccess) return bail(e);
+        n->wpk.push_back(a);
+        if ((e = hipMalloc(&b, packed_len(n->bwd[l]) * 2)) != hipSuccess) return bail(e);
+        n->wpk_t.push_back(b);
+    }
+    *out = n;
+    return SW_OK;
+}
+
+int sws_destroy(sws_net *n)
+{
+    if (!n) return SW_OK;
+    if (n->stream) (void)hipStreamSynchronize(n->stream);
+    else (void)hipDeviceSynchronize();
+    for (float *q : {n->p, n->g, n->m, n->v}) (void)hipFree(q);
+    for (auto *q : n->wpk) (void)hipFree(q);
+    for (auto *q : n->wpk_t) (void)hipFree(q);
+    (void)hipFree(n->scratch);
+    delete n;
+    return SW_OK;
+}
+
+int sws_param_count(const sws_net *n, int64_t *count)
+{
+    if (!n || !count) return SW_ERR_ARG;
+    *count = n->nparam;
+    return SW_OK;
+}
+
+int sws_set_params(sws_net *n, const float *params, int ptr_kind)
+{
+    if (!n || !params) return SW_ERR_ARG;
+    int rc = copy_in(n, n->p, params, n->nparam * sizeof(float), ptr_kind);
+    if (rc) return rc;
+    SHIP(n, hipMemsetAsync(n->m, 0, n->nparam * sizeof(float), n->stream));
+    SHIP(n, hipMemsetAsync(n->v, 0, n->nparam * sizeof(float), n->stream));
+    n->adam_t = 0;
+    return pack_all(n);
+}
+
+int sws_get_params(sws_net *n, float *params, int ptr_kind)
+{
+    if (!n || !params) return SW_ERR_ARG;
+    if (ptr_kind != SW_PTR_HOST && ptr_kind != SW_PTR_DEVICE)
+        return sfail(n, SW_ERR_ARG, "ptr_kind must be SW_PTR_HOST or SW_PTR_DEVICE");
+    SHIP(n, hipMemcpyAsync(params, n->p, n->nparam * sizeof(float),
+                           ptr_kind == SW_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                           n->stream));
+    SHIP(n, hipStreamSynchronize(n->stream));
+    return SW_OK;
+}
+
+int sws_set_scales(sws_net *n, const float in_scale[5], const float out_scale[4])
+{
+    if (!n || !in_scale || !out_scale) return SW_ERR_ARG;
+    std::memcpy(n->in_scale, in_scale, sizeof n->in_scale);
+    std::memcpy(n->out_scale, out_scale, sizeof n->out_scale);
+    return SW_OK;
+}
+
+int sws_forward(sws_net *n, const float *x, float *y, int32_t nimg, int32_t nx, int32_t ny,
+                int ptr_kind)
+{
+    if (!n || !x || !y || nimg < 1 || nx < 1 || ny < 1) return SW_ERR_ARG;
+    if (ptr_kind != SW_PTR_HOST && ptr_kind != SW_PTR_DEVICE)
+        return sfail(n, SW_ERR_ARG, "ptr_kind must be SW_PTR_HOST or SW_PTR_DEVICE");
+    if (!n->packed) {
+        int rc = pack_all(n);
+        if (rc) return rc;
+    }
+    const long npix = (long)nimg * nx * ny;
+    const size_t xin = (size_t)npix * 5 * sizeof(float), yout = (size_t)npix * 4 * sizeof(float);
+    const size_t need = layout(n, npix, nullptr).bytes + xin;
+    int rc = ensure_scratch(n, need);
+    if (rc) return rc;
+    Scratch s = layout(n, npix, (char *)n->scratch);
+    float *xd = (float *)((char *)n->scratch + s.bytes);
+    rc = copy_in(n, xd, x, xin, ptr_kind);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_to_nhwc, dim3(grid_for(npix)), dim3(NT), 0, n->stream, xd, 5, CIN0,
+                       (long)nx * ny, nimg, s.act[0]);
+    rc = forward_into(n, s, nimg, nx, ny);
+    if (rc) return rc;
+    SHIP(n, hipMemcpyAsync(y, s.out, yout,
+                           ptr_kind == SW_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                           n->stream));
+    SHIP(n, hipStreamSynchronize(n->stream));
+    return SW_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Forward, loss and backward: the gradient lands in n->g; the FP64 loss
+// partials in the scratch (returned through *loss when asked, synchronising).
+int compute_grads(sws_net *n, const float *x, const float *target, int32_t nimg, int32_t nx,
+                  int32_t ny, double *loss, int ptr_kind)
+{
+    if (!n || !x || !target || nimg < 1 || nx < 1 || ny < 1) return SW_ERR_ARG;
+    if (ptr_kind != SW_PTR_HOST && ptr_kind != SW_PTR_DEVICE)
+        return sfail(n, SW_ERR_ARG, "ptr_kind must be SW_PTR_HOST or SW_PTR_DEVICE");
+    if (!n->packed) {
+        int rc = pack_all(n);
+        if (rc) return rc;
+    }
+    const long npix = (long)nimg * nx * ny;
+    const size_t xin = (size_t)npix * 5 * sizeof(float), tin = (size_t)npix * 4 * sizeof(float);
+    const size_t need = layout(n, npix, nullptr).bytes + xin + tin;
+    int rc = ensure_scratch(n, need);
+    if (rc) return rc;
+    Scratch s = layout(n, npix, (char *)n->scratch);
+    float *xd = (float *)((char *)n->scratch + s.bytes);
+    float *td = (float *)((char *)xd + xin);
+    if ((rc = copy_in(n, xd, x, xin, ptr_kind))) return rc;
+    if ((rc = copy_in(n, td, target, tin, ptr_kind))) return rc;
+    hipLaunchKernelGGL(k_to_nhwc, dim3(grid_for(npix)), dim3(NT), 0, n->stream, xd, 5, CIN0,
+                       (long)nx * ny, nimg, s.act[0]);
+    if ((rc = forward_into(n, s, nimg, nx, ny))) return rc;
+    // loss and dL/dy (BF16, stored channels of the last layer's output = 16-block)
+    const int L = n->L;
+    const int cs_out = MAXW;  // gradient buffers always hold MAXW channels per pixel
+    hipLaunchKernelGGL(k_mse, dim3(RED_GRID), dim3(NT), 0, n->stream, s.out, td, 4, cs_out,
+                       (long)nx * ny, nimg, 1.0 / ((double)npix * 4), s.ga, s.red);
+    unsigned short *gcur = s.ga, *gnext = s.gb;
+    for (int l = L - 1; l >= 0; --l) {
+        // weight and bias gradients of layer l from dz_l (gcur) and its input act[l]
+        const int cin = n->ch[l], cout = n->ch[l + 1];
+        hipLaunchKernelGGL(k_dw, dim3(DW_GRID), dim3(NT), 0, n->stream, s.act[l], stored(cin), cin,
+                           gcur, cs_out, cout, nimg, nx, ny, s.dwpart);
+        const int len = cout * cin * 9 + cout;
+        hipLaunchKernelGGL(k_dw_sum, dim3(grid_for(len)), dim3(NT), 0, n->stream, s.dwpart, DW_GRID,
+                           len, n->g + n->woff[l]);
+        if (l > 0) {  // dz_{l-1} = (W_l^T * dz_l) where act[l] > 0
+            rc = conv(n, gcur, n->bwd[l], n->wpk_t[l], nullptr, 2, s.act[l], stored(n->ch[l]),
+                      gnext, cs_out, nimg, nx, ny);
+            if (rc) return rc;
+            std::swap(gcur, gnext);
+        }
+    }
+    if (loss) {
+        std::vector<double> h(RED_GRID);
+        SHIP(n, hipMemcpyAsync(h.data(), s.red, RED_GRID * sizeof(double), hipMemcpyDeviceToHost,
+                               n->stream));
+        SHIP(n, hipStreamSynchronize(n->stream));
+        double sum = 0.0;
+        for (double v : h) sum += v;
+        *loss = sum / ((double)npix * 4);
+    }
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sws_grad(sws_net *n, const float *x, const float *target, int32_t nimg, int32_t nx,
+             int32_t ny, float *grad, double *loss, int ptr_kind)
+{
+    if (!grad) return SW_ERR_ARG;
+    int rc = compute_grads(n, x, target, nimg, nx, ny, loss, ptr_kind);
+    if (rc) return rc;
+    SHIP(n, hipMemcpyAsync(grad, n->g, n->nparam * sizeof(float),
+                           ptr_kind == SW_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                           n->stream));
+    SHIP(n, hipStreamSynchronize(n->stream));
+    return SW_OK;
+}
+
+int sws_train_step(sws_net *n, const float *x, const float *target, int32_t nimg, int32_t nx,
+                   int32_t ny, float lr, double *loss, int ptr_kind)
+{
+    int rc = compute_grads(n, x, target, nimg, nx, ny, loss, ptr_kind);
+    if (rc) return rc;
+    // Adam
+    n->adam_t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = (float)(1.0 - std::pow(0.9, (double)n->adam_t));
+    const float c2 = (float)(1.0 - std::pow(0.999, (double)n->adam_t));
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(n->nparam)), dim3(NT), 0, n->stream, n->p, n->g, n->m,
+                       n->v, n->nparam, lr, b1, b2, 1e-8f, c1, c2);
+    SHIP(n, hipGetLastError());
+    return pack_all(n);
+}
+
+int sws_advance(sws_net *n, sw_ctx *solver, int32_t k, double dt, double max_drift, int32_t *used)
+{
+    if (!n || !solver || k < 1 || !(dt > 0.0) || !(max_drift >= 0.0)) return SW_ERR_ARG;
+    if (used) *used = 0;
+    if (!n->packed) {
+        int rc = pack_all(n);
+        if (rc) return rc;
+    }
+    sw_grid gr;
+    sw_sums sums;
+    int rc = sw_get_grid(solver, &gr);
+    if (!rc) rc = sw_get_sums(solver, &sums);
+    if (rc) return sfail(n, rc, std::string("solver: ") + sw_last_error(solver));
+    const int nx = gr.nx, ny = gr.ny;
+    const long npix = (long)nx * ny;
+    const size_t fbytes = (size_t)npix * 4 * sizeof(float);
+    const size_t need = layout(n, npix, nullptr).bytes + 2 * fbytes;
+    if ((rc = ensure_scratch(n, need))) return rc;
+    Scratch s = layout(n, npix, (char *)n->scratch);
+    float *f0 = (float *)((char *)n->scratch + s.bytes);
+    float *f1 = (float *)((char *)f0 + fbytes);
+    // the solver's fields (on its stream), then the network on ours
+    rc = sw_get_fields(solver, f0, f0 + npix, f0 + 2 * npix, f0 + 3 * npix, SW_PTR_DEVICE);
+    if (!rc) rc = sw_sync(solver);
+    if (rc) return sfail(n, rc, std::string("solver: ") + sw_last_error(solver));
+    const float *is = n->in_scale, *os = n->out_scale;
+    hipLaunchKernelGGL(k_inputs, dim3(grid_for(npix)), dim3(NT), 0, n->stream, f0, npix, is[0],
+                       is[1], is[2], is[3], is[4], s.act[0]);
+    if ((rc = forward_into(n, s, 1, nx, ny))) return rc;
+    hipLaunchKernelGGL(k_apply, dim3(RED_GRID), dim3(NT), 0, n->stream, f0, s.out, npix, os[0], os[1],
+                       os[2], os[3], f1, s.red);
+    SHIP(n, hipGetLastError());
+    std::vector<double> part(2 * RED_GRID);
+    SHIP(n, hipMemcpyAsync(part.data(), s.red, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           n->stream));
+    SHIP(n, hipStreamSynchronize(n->stream));
+    double v0 = 0.0, v1 = 0.0;
+    for (int b = 0; b < RED_GRID; ++b) {
+        v0 += part[2 * b];
+        v1 += part[2 * b + 1];
+    }
+    const double drift = v0 > 0.0 ? std::fabs(v1 - v0) / v0 : (v1 > 0.0 ? INFINITY : 0.0);
+    if (drift <= max_drift) {
+        rc = sw_replace_state(solver, f1, f1 + npix, f1 + 2 * npix, f1 + 3 * npix, sums.t + k * dt,
+                              sums.step + k);
+        if (rc) return sfail(n, rc, std::string("solver: ") + sw_last_error(solver));
+        if (used) *used = 1;
+        return SW_OK;
+    }
+    rc = sw_advance_fixed_dt(solver, k, dt);
+    if (!rc) rc = sw_sync(solver);
+    if (rc) return sfail(n, rc, std::string("solver: ") + sw_last_error(solver));
+    return SW_OK;
+}
+
+const char *sws_last_error(const sws_net *n) { return n ? n->err.c_str() : "null net"; }
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+"""Training and evaluation of the convolutional surrogate on solver trajectories.
+
+Everything numerical runs in the library's kernels: the trajectories come
+from the solver (fixed step), the network's forward, backward and Adam steps
+from `sws_train_step`, the surrogate step from `sws_advance`.  This module
+only assembles arrays (sampling pairs, per-channel scales) and loops.
+
+A training pair is (state at step n, change of (h, hu, hv, b) over the next k
+steps).  Network inputs are x = in_scale * (h, hu, hv, b, wet mask); its
+targets the changes divided by out_scale.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import csph
+from . import workloads as W
+
+DESIGN_CHANNELS = (5, 48, 48, 48, 48, 48, 4)
+G = 9.81
+
+
+@dataclass
+class Pairs:
+    x: np.ndarray       # [n, 5, ny, nx] raw inputs (h, hu, hv, b, mask)
+    d: np.ndarray       # [n, 4, ny, nx] changes over k steps
+    k: int
+    dt: np.ndarray      # [n] step of each pair's trajectory
+
+
+def basin(n, seed, depth, relief=10.0, dx=2.0):
+    """A closed fractal basin with a dam-break reservoir (walls on every side,
+    Grass bedload): the water volume cannot change."""
+    w = W.dam_break_fractal(n=n, dx=dx, seed=seed, relief=relief, depth=depth).as_float32()
+    w.bc = (0, 0, 0, 0)
+    return w
+
+
+def fixed_dt(w, factor=0.08):
+    """dt = factor dx / sqrt(g H_max) of the trajectory's initial state; 0.08
+    keeps it under the Eq. 7 step (K = 0.3) while |v| + c stays below about
+    3.7 sqrt(g H_max), which covers the dam-break flows."""
+    return factor * w.dx / math.sqrt(G * max(float(w.H.max()), 1e-3))
+
+
+def trajectory_pairs(w, steps, k, dt, stream=None):
+    """Run the solver for `steps` fixed steps and return the (state, change
+    over k steps) pairs at every k-th step."""
+    s = csph.solver_for(w, stream=stream)
+    xs, ds = [], []
+    f0 = s.get_fields()
+    for _ in range(steps // k):
+        s.advance(k, dt=dt)
+        f1 = s.get_fields()
+        h, hu, hv, b = f0
+        xs.append(np.stack([h, hu, hv, b, (h > 0).astype(np.float32)]))
+        ds.append(np.stack([a1 - a0 for a1, a0 in zip(f1, f0)]))
+        f0 = f1
+    s.close()
+    return xs, ds
+
+
+def collect(seeds, n, steps, k, stream=None, depth_range=(2.0, 8.0)):
+    xs, ds, dts = [], [], []
+    for sd in seeds:
+        rng = np.random.default_rng(sd)
+        w = basin(n, sd, float(rng.uniform(*depth_range)))
+        dt = fixed_dt(w)
+        x, d = trajectory_pairs(w, steps, k, dt, stream)
+        xs += x
+        ds += d
+        dts += [dt] * len(x)
+    return Pairs(np.stack(xs), np.stack(ds), k, np.array(dts))
+
+
+def scales(p: Pairs):
+    ins = [1.0 / max(float(np.abs(p.x[:, c]).max()), 1e-6) for c in range(4)] + [1.0]
+    outs = [max(float(p.d[:, c].std()), 1e-9) for c in range(4)]
+    return np.array(ins, np.float32), np.array(outs, np.float32)
+
+
+def he_init(channels, seed):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for cin, cout in zip(channels[:-1], channels[1:]):
+        bound = math.sqrt(6.0 / (9 * cin))
+        parts.append(rng.uniform(-bound, bound, cout * cin * 9))
+        parts.append(np.zeros(cout))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def train(net, p: Pairs, in_s, out_s, steps, batch, lr, seed=0, log=None):
+    net.set_scales(in_s, out_s)
+    x = p.x * in_s[None, :, None, None]
+    t = p.d / out_s[None, :, None, None]
+    rng = np.random.default_rng(seed)
+    losses = []
+    for it in range(steps):
+        idx = rng.choice(len(x), size=min(batch, len(x)), replace=False)
+        # cosine decay of the learning rate
+        lr_t = lr * 0.5 * (1.0 + math.cos(math.pi * it / steps))
+        losses.append(net.train_step(x[idx], t[idx], lr_t))
+        if log and (it % 100 == 0 or it == steps - 1):
+            log(f"train step {it}: loss {losses[-1]:.4e}")
+    return losses
+
+
+def evaluate(net, p: Pairs, in_s, out_s):
+    """Largest depth error of one surrogate call over the pairs, and the
+    relative volume change each prediction would make."""
+    y = net.forward(p.x * in_s[None, :, None, None])
+    dh = y[:, 0] * out_s[0]
+    err = np.abs(dh - p.d[:, 0]).max(axis=(1, 2))
+    vol = p.x[:, 0].sum(axis=(1, 2)).astype(np.float64)
+    h_new = np.maximum(p.x[:, 0] + dh, 0.0)
+    drift = np.abs(h_new.sum(axis=(1, 2)) - vol) / np.maximum(vol, 1e-30)
+    return err, drift
+
+
+def measure_gain(net, w, dt, calls, k=8, max_drift=1e-5, stream=None):
+    """Effective rate of the surrogate step (k steps per call, fall backs
+    included) against the plain solver's k fixed steps, both in grid cells x
+    steps per second.  Every call starts from the same initial state (the
+    reset is not timed), so one bad prediction cannot spoil the next call."""
+    import torch
+    s = csph.solver_for(w, stream=stream)
+    used, t_sur, t_plain = 0, 0.0, 0.0
+    for _ in range(calls):
+        s.reset(w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        used += int(net.advance(s, k, dt, max_drift))
+        torch.cuda.synchronize()
+        t_sur += time.perf_counter() - t0
+    for it in range(calls + 1):
+        s.reset(w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance(k, dt=dt)
+        s.sync()
+        if it:  # the first run builds the step graph
+            t_plain += time.perf_counter() - t0
+    s.close()
+    cells = w.nx * w.ny * k * calls
+    return {"grid": [w.nx, w.ny], "k": k, "calls": calls, "max_drift": max_drift,
+            "surrogate_gcell_steps_s": round(cells / t_sur / 1e9, 3),
+            "plain_gcell_steps_s": round(cells / t_plain / 1e9, 3),
+            "kept": used, "fallback_rate": round(1.0 - used / calls, 4)}

@@ -1,0 +1,187 @@
+"""The surrogate's kernels (BF16 matrix-core convolutions, FP32 weight
+gradients and Adam) against the FP64 oracle of the network, and its solver
+step (mass check, plain fall back) against the solver itself."""
+import numpy as np
+import pytest
+
+from oracle import surrogate_oracle as S
+from paper_2103_15196_amd import workloads as W
+from tests.gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+DESIGN = (5, 48, 48, 48, 48, 48, 4)
+
+
+def _flat(Ws, bs):
+    return np.concatenate([np.concatenate([w.reshape(-1), b]) for w, b in zip(Ws, bs)])
+
+
+def _unflat(p, chans):
+    Ws, bs, o = [], [], 0
+    for cin, cout in zip(chans[:-1], chans[1:]):
+        n = cout * cin * 9
+        Ws.append(p[o:o + n].reshape(cout, cin, 3, 3))
+        o += n
+        bs.append(p[o:o + cout])
+        o += cout
+    return Ws, bs
+
+
+def _net(chans, seed):
+    from paper_2103_15196_amd import csph
+    import torch
+    Ws, bs = S.init_weights(chans, seed)
+    rng = np.random.default_rng(seed + 1)
+    bs = [rng.uniform(-0.1, 0.1, b.shape) for b in bs]
+    p = _flat(Ws, bs).astype(np.float32)
+    net = csph.Surrogate(chans, stream=torch.cuda.current_stream().cuda_stream)
+    net.set_params(p)
+    Ws, bs = _unflat(p.astype(np.float64), chans)
+    return net, Ws, bs
+
+
+@pytest.mark.parametrize("chans", [DESIGN, (5, 8, 4), (5, 16, 11, 4)])
+def test_gpu_surrogate_forward_matches_oracle(chans):
+    net, Ws, bs = _net(chans, seed=10)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((2, 5, 23, 37)).astype(np.float32)
+    y = net.forward(x)
+    for i in range(2):
+        ref, _ = S.forward(x[i].astype(np.float64), Ws, bs, bf16=True)
+        err = np.abs(y[i] - ref).max()
+        say(f"forward {chans} image {i}: max |gpu - oracle| {err:.3e}, max |oracle| {np.abs(ref).max():.3e}")
+        assert err <= 5e-3 * np.abs(ref).max() + 1e-4
+    net.close()
+
+
+@pytest.mark.parametrize("chans", [(5, 16, 11, 4), DESIGN])
+def test_gpu_surrogate_gradients_match_oracle(chans):
+    net, Ws, bs = _net(chans, seed=20)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((2, 5, 19, 41)).astype(np.float32)
+    t = rng.standard_normal((2, 4, 19, 41)).astype(np.float32)
+    g, loss = net.grad(x, t)
+    gW = [np.zeros_like(w) for w in Ws]
+    gb = [np.zeros_like(b) for b in bs]
+    lref = 0.0
+    for i in range(2):
+        out, cache = S.forward(x[i].astype(np.float64), Ws, bs, bf16=True)
+        d = out - t[i]
+        lref += float(np.sum(d * d))
+        dW, db = S.backward(Ws, cache, 2.0 * d / t.size, bf16=True)
+        for l in range(len(Ws)):
+            gW[l] += dW[l]
+            gb[l] += db[l]
+    lref /= t.size
+    assert loss == pytest.approx(lref, rel=2e-3)
+    ref = _flat(gW, gb)
+    o = 0
+    for l, (w, b) in enumerate(zip(gW, gb)):
+        n = w.size + b.size
+        err = np.abs(g[o:o + n] - ref[o:o + n]).max()
+        scale = np.abs(ref[o:o + n]).max()
+        say(f"grad {chans} layer {l}: max err {err:.3e} of max {scale:.3e}")
+        assert err <= 3e-2 * scale + 1e-7
+        # the direction of the layer gradient agrees closely
+        cos = float(np.dot(g[o:o + n], ref[o:o + n]) /
+                    (np.linalg.norm(g[o:o + n]) * np.linalg.norm(ref[o:o + n]) + 1e-30))
+        assert cos > 0.999
+        o += n
+    net.close()
+
+
+def test_gpu_surrogate_adam_step_matches_oracle():
+    chans = (5, 16, 4)
+    net, Ws, bs = _net(chans, seed=30)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((1, 5, 16, 32)).astype(np.float32)
+    t = rng.standard_normal((1, 4, 16, 32)).astype(np.float32)
+    p0 = net.get_params().astype(np.float64)
+    g, _ = net.grad(x, t)
+    net.train_step(x, t, lr=1e-3)
+    p1 = net.get_params()
+    ref = [p0.copy()]
+    S.adam_step(ref, [g.astype(np.float64)], [np.zeros_like(p0)], [np.zeros_like(p0)], t=1, lr=1e-3)
+    assert np.abs(p1 - ref[0]).max() <= 1e-6
+    net.close()
+
+
+def test_gpu_surrogate_training_reduces_loss():
+    chans = (5, 16, 4)
+    net, _, _ = _net(chans, seed=40)
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((4, 5, 24, 24)).astype(np.float32)
+    t = 0.5 * np.roll(x[:, :4], 1, axis=3)  # a shift the 3x3 stencil can represent
+    losses = [net.train_step(x, t, lr=3e-3) for _ in range(150)]
+    say(f"training loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.3 * losses[0]
+    net.close()
+
+
+def _closed_basin():
+    w = W.dam_break_fractal(n=96, ny=64, dx=2.0, seed=5, relief=3.0, depth=3.0).as_float32()
+    w.bc = (0, 0, 0, 0)
+    return w
+
+
+def test_gpu_surrogate_step_keeps_or_falls_back():
+    from paper_2103_15196_amd import csph
+    import torch
+    st = torch.cuda.current_stream().cuda_stream
+    w = _closed_basin()
+    dt = 0.02
+    # zero network: the predicted change is 0, the volume is kept, the state stays
+    net = csph.Surrogate((5, 16, 4), stream=st)
+    net.set_params(np.zeros(net.nparam, np.float32))
+    s = csph.solver_for(w, stream=st)
+    used = net.advance(s, 8, dt)
+    assert used
+    h, hu, hv, b = s.get_fields()
+    assert np.array_equal(h, w.H.astype(np.float32)) and np.array_equal(b, w.b.astype(np.float32))
+    sums = s.get_sums()
+    assert sums["t"] == pytest.approx(8 * dt, rel=1e-12) and sums["step"] == 8
+    # the solver continues from the replaced state
+    s.advance(5, dt=dt)
+    s.sync()
+    s.close()
+    # a wild network changes the volume: the solver takes the 8 fixed steps itself
+    wild = csph.Surrogate((5, 16, 4), stream=st)
+    wild.set_params(np.random.default_rng(7).uniform(-1, 1, wild.nparam).astype(np.float32))
+    wild.set_scales([1, 1, 1, 1, 1], [1, 1, 1, 1])
+    s = csph.solver_for(w, stream=st)
+    used = wild.advance(s, 8, dt)
+    assert not used
+    f = s.get_fields()
+    r = csph.solver_for(w, stream=st)
+    r.advance(8, dt=dt)
+    g = r.get_fields()
+    for a, c in zip(f, g):
+        assert np.array_equal(a, c)
+    s.close()
+    r.close()
+    net.close()
+    wild.close()
+
+
+def test_gpu_surrogate_training_driver_end_to_end():
+    """Trajectories from the solver, a short training run, held-out error and
+    volume change, and the gain measurement (every call restarted)."""
+    import torch
+    from paper_2103_15196_amd import csph, surrogate as SG
+    st = torch.cuda.current_stream().cuda_stream
+    tr = SG.collect([5000, 5001], n=48, steps=32, k=8, stream=st)
+    ho = SG.collect([6000], n=48, steps=32, k=8, stream=st)
+    assert tr.x.shape == (8, 5, 48, 48) and tr.d.shape == (8, 4, 48, 48)
+    ins, outs = SG.scales(tr)
+    net = csph.Surrogate((5, 16, 16, 4), stream=st)
+    net.set_params(SG.he_init((5, 16, 16, 4), 1))
+    losses = SG.train(net, tr, ins, outs, steps=60, batch=4, lr=3e-3)
+    assert losses[-1] < losses[0]
+    err, drift = SG.evaluate(net, ho, ins, outs)
+    assert np.all(np.isfinite(err)) and np.all(np.isfinite(drift))
+    w = SG.basin(64, 6100, 4.0)
+    res = SG.measure_gain(net, w, SG.fixed_dt(w), calls=2, k=8, stream=st)
+    say(f"end to end: loss {losses[0]:.3f} -> {losses[-1]:.3f}; held-out max err {err.max():.3e}; {res}")
+    assert res["calls"] == 2 and 0.0 <= res["fallback_rate"] <= 1.0
+    net.close()
