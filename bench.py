@@ -193,6 +193,7 @@ def main():
     if not args.no_extras:
         out["river_valley"] = river_valley_rates(csph, W, torch)
         out["surrogate"] = surrogate_rates(csph, torch)
+        out["ensemble"] = ensemble_rates(csph, W, torch)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
@@ -254,6 +255,49 @@ def surrogate_rates(csph, torch, train_steps=1500):
            "heldout_median_volume_drift": float(np.median(drift)), **gain,
            "seconds": round(time.perf_counter() - t0, 1)}
     log(f"[bench]   surrogate: {res}")
+    return res
+
+
+def ensemble_rates(csph, W, torch, count=64, steps=1000):
+    """64 dam-break members of uneven size (sides U{256..1536}, own terrain,
+    depth, Manning n and Eq. 7 step), 1000 steps each: one batch (one launch
+    per stage over all members' tiles, graph replay) against the members
+    advanced one after another; both rates are all members' cell-steps over
+    the wall time, from the same initial states."""
+    log(f"[bench] ensemble of {count} x {steps} steps")
+    ms = [m.as_float32() for m in W.ensemble(count=count, seed0=1000, n_min=256, n_max=1536,
+                                             steps=steps)]
+    cells = sum(m.nx * m.ny for m in ms)
+    stream = torch.cuda.current_stream()
+    solvers = [csph.solver_for(m, stream=stream.cuda_stream) for m in ms]
+    b = csph.Batch(solvers)
+    b.advance(2)
+    b.sync()
+    for s, m in zip(solvers, ms):
+        s.reset(m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.advance(steps)
+    b.sync()
+    t_batch = time.perf_counter() - t0
+    b.close()
+    for s, m in zip(solvers, ms):
+        s.advance(2)
+        s.reset(m)
+    torch.cuda.synchronize()
+    t_seq = 0.0
+    for s in solvers:
+        t0 = time.perf_counter()
+        s.advance(steps)
+        s.sync()
+        t_seq += time.perf_counter() - t0
+    for s in solvers:
+        s.close()
+    res = {"members": count, "cells": cells, "steps": steps,
+           "batched_gcell_steps_s": round(cells * steps / t_batch / 1e9, 3),
+           "sequential_gcell_steps_s": round(cells * steps / t_seq / 1e9, 3),
+           "speedup": round(t_seq / t_batch, 3)}
+    log(f"[bench]   ensemble: {res}")
     return res
 
 
