@@ -1122,7 +1122,7 @@ __device__ void lagrange_strip(const Inst &I, int par, int bx, int by, float dt)
 // reductions (Eq. 7 maxima and wet flag of the new state, boundary balances).
 // CS: some soil or source field is a per-cell plane (else all are scalars).
 template <int S, bool CS>
-__device__ void euler_strip(const Inst &I, int par, int bx, int by, bool skip_check = true)
+__device__ void euler_strip(const Inst &I, int par, int bx, int by)
 {
     const KPar &P = I.P;
     Ctrl *ctrl = I.ctrl;
@@ -1138,26 +1138,6 @@ __device__ void euler_strip(const Inst &I, int par, int bx, int by, bool skip_ch
     const float *SH = I.H[par], *Sqx = I.qx[par], *Sqy = I.qy[par], *Sb = I.b[par];
     float *OH = I.H[par ^ 1], *Oqx = I.qx[par ^ 1], *Oqy = I.qy[par ^ 1], *Ob = I.b[par ^ 1];
     const float *QLx = I.QLx, *QLy = I.QLy;
-    if (I.hgs && skip_check) {
-        const uint8_t *act_in = I.act[par];
-        bool run = act_in[tile] || (bx > 0 && act_in[tile - 1]) ||
-                   (bx + 1 < ntx && act_in[tile + 1]) || (by > 0 && act_in[tile - ntx]) ||
-                   (by + 1 < nty && act_in[tile + ntx]);
-        if (!run) {
-            if (!I.synced[tile] && mine)  // first skip since the tile last changed
-                for (int j = y0; j < jend; ++j) {
-                    int c = j * pitch + i;
-                    OH[c] = SH[c]; Oqx[c] = Sqx[c]; Oqy[c] = Sqy[c]; Ob[c] = Sb[c];
-                }
-            if (lane == 0) {
-                I.synced[tile] = 1;
-                I.act[par ^ 1][tile] = 0;
-                I.tmax[par ^ 1][tile] = make_uint4(0u, 0u, 0u, 0u);
-            }
-            return;
-        }
-        if (lane == 0) I.synced[tile] = 0;
-    }
     const double dtd = ctrl->dt[par];
     const float dt = (float)dtd;
     const float qmid = (float)ctrl->qmid[par];
@@ -1377,27 +1357,6 @@ __global__ void __launch_bounds__(NT) k_euler_b(const Inst *__restrict__ insts,
     euler_tile<TX, TY>(insts[t[0]], par, t[1], t[2]);
 }
 
-// Ensemble strips: workgroup b runs tiles (table[3b+1], SWAVES table[3b+2] + w)
-// of member table[3b].
-template <int S, bool CS>
-__global__ void __launch_bounds__(NT) k_lagrange_sb(const Inst *__restrict__ insts,
-                                                    const int *__restrict__ table, int par)
-{
-    const int *t = table + 3 * blockIdx.x;
-    const Inst &I = insts[t[0]];
-    const int by = t[2] * SWAVES + (threadIdx.x >> 6);
-    if (by < I.nty && !I.ctrl->err) lagrange_strip<S, CS>(I, par, t[1], by, (float)I.ctrl->dt[par]);
-}
-template <int S, bool CS>
-__global__ void __launch_bounds__(NT) k_euler_sb(const Inst *__restrict__ insts,
-                                                 const int *__restrict__ table, int par)
-{
-    const int *t = table + 3 * blockIdx.x;
-    const Inst &I = insts[t[0]];
-    const int by = t[2] * SWAVES + (threadIdx.x >> 6);
-    if (by < I.nty) euler_strip<S, CS>(I, par, t[1], by);
-}
-
 // ---------------------------------------------------------------------------
 // Work lists (strips on a single grid).  Launching one workgroup per tile
 // leaves the wet tiles scattered among dry ones, so some CUs get twice the
@@ -1447,9 +1406,9 @@ __device__ __forceinline__ void block_scan2(int a, int b, int &xa, int &xb, int 
 // follows (the kernel boundary makes these writes visible): every wavefront
 // derives its entry and the Eq. 7 step from the segment lengths and maxima,
 // and wavefront 0 publishes the step and the Euler list's start positions.
-__global__ void __launch_bounds__(RT) k_dt_lists(Inst I, int par)
+__device__ void dt_lists(const Inst &I, int par, int b)
 {
-    const int nt = I.ntx * I.nty, b = blockIdx.x;
+    const int nt = I.ntx * I.nty;
     const int c0 = b * I.chunk, c1 = min(nt, c0 + I.chunk);
     const uint4 m = block_tile_maxima(I.tmax[par], c0, c1);
     if (threadIdx.x == 0) I.part[b] = m;
@@ -1497,6 +1456,15 @@ __global__ void __launch_bounds__(RT) k_dt_lists(Inst I, int par)
         I.cnt_l[b] = tl;
         I.cnt_e[b] = te;
     }
+}
+
+__global__ void __launch_bounds__(RT) k_dt_lists(Inst I, int par) { dt_lists(I, par, blockIdx.x); }
+
+// Ensemble: workgroup b runs segment table[2b+1] of member table[2b].
+__global__ void __launch_bounds__(RT) k_dt_lists_b(const Inst *__restrict__ insts,
+                                                   const int *__restrict__ table, int par)
+{
+    dt_lists(insts[table[2 * blockIdx.x]], par, table[2 * blockIdx.x + 1]);
 }
 
 // Entry w of a list kept in segments: the segment is the last one whose
@@ -1563,12 +1531,11 @@ __device__ __forceinline__ int list_locate(const int *cnt, int nb, int w, int &s
 }
 
 template <int S, bool CS>
-__global__ void __launch_bounds__(NT) k_lagrange_sl(Inst I, int par)
+__device__ void lagrange_listed(const Inst &I, int par, int w)
 {
     Ctrl *ctrl = I.ctrl;
     if (ctrl->err) return;
     const int lane = threadIdx.x & 63;
-    const int w = blockIdx.x * SWAVES + (threadIdx.x >> 6);
     const bool publisher = w == 0;
     const int nb = I.nchunk;
     int n = I.ntx * I.nty, seg = 0, start = 0;
@@ -1601,16 +1568,42 @@ __global__ void __launch_bounds__(NT) k_lagrange_sl(Inst I, int par)
     lagrange_strip<S, CS>(I, par, t % I.ntx, t / I.ntx, (float)e.dt);
 }
 template <int S, bool CS>
-__global__ void __launch_bounds__(NT) k_euler_sl(Inst I, int par)
+__device__ void euler_listed(const Inst &I, int par, int w)
 {
     if (I.ctrl->err) return;
-    const int w = blockIdx.x * SWAVES + (threadIdx.x >> 6);
     const int n = I.hgs ? I.totals[1] : I.ntx * I.nty;
     if (w >= n) return;
     const int e = I.hgs ? list_entry(I.eul, I.pre_e, I.nchunk, I.chunk, w) : w;
     const int t = e < 0 ? -1 - e : e;
     if (e < 0) strip_copy<S>(I, par, t % I.ntx, t / I.ntx);
-    else euler_strip<S, CS>(I, par, t % I.ntx, t / I.ntx, false);
+    else euler_strip<S, CS>(I, par, t % I.ntx, t / I.ntx);
+}
+
+template <int S, bool CS>
+__global__ void __launch_bounds__(NT) k_lagrange_sl(Inst I, int par)
+{
+    lagrange_listed<S, CS>(I, par, blockIdx.x * SWAVES + (threadIdx.x >> 6));
+}
+template <int S, bool CS>
+__global__ void __launch_bounds__(NT) k_euler_sl(Inst I, int par)
+{
+    euler_listed<S, CS>(I, par, blockIdx.x * SWAVES + (threadIdx.x >> 6));
+}
+
+// Ensemble: workgroup b runs waves SWAVES table[2b+1] + w of member table[2b].
+template <int S, bool CS>
+__global__ void __launch_bounds__(NT) k_lagrange_slb(const Inst *__restrict__ insts,
+                                                     const int *__restrict__ table, int par)
+{
+    const int *t = table + 2 * blockIdx.x;
+    lagrange_listed<S, CS>(insts[t[0]], par, t[1] * SWAVES + (threadIdx.x >> 6));
+}
+template <int S, bool CS>
+__global__ void __launch_bounds__(NT) k_euler_slb(const Inst *__restrict__ insts,
+                                                  const int *__restrict__ table, int par)
+{
+    const int *t = table + 2 * blockIdx.x;
+    euler_listed<S, CS>(insts[t[0]], par, t[1] * SWAVES + (threadIdx.x >> 6));
 }
 
 // Tile shapes the autotuner chooses from: TX x TY cells per 256-thread
@@ -1929,36 +1922,39 @@ void launch_batch_t(Stage st, hipStream_t s, const Inst *insts, int nmem, const 
     else hipLaunchKernelGGL((k_euler_b<TX, TY>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
 }
 
+// Strip ensembles: K3a over the (member, segment) table dtab, the stage
+// kernels over the (member, local workgroup) table, both on work lists.
 template <int S, bool CS>
-void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, int nmem, const int *table,
-                    int ntab, int par)
+void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, const int *table, int ntab,
+                    const int *dtab, int ndtab, int par)
 {
-    if (st == kDt) hipLaunchKernelGGL(k_dt_b, dim3(nmem), dim3(RT), 0, s, insts, par);
+    if (st == kDt) hipLaunchKernelGGL(k_dt_lists_b, dim3(ndtab), dim3(RT), 0, s, insts, dtab, par);
     else if (st == kLagrange)
-        hipLaunchKernelGGL((k_lagrange_sb<S, CS>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
-    else hipLaunchKernelGGL((k_euler_sb<S, CS>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
+        hipLaunchKernelGGL((k_lagrange_slb<S, CS>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
+    else hipLaunchKernelGGL((k_euler_slb<S, CS>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
 }
 
 template <int S>
-void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, int nmem, const int *table,
-                    int ntab, int par, bool cs)
+void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, const int *table, int ntab,
+                    const int *dtab, int ndtab, int par, bool cs)
 {
-    if (cs) launch_batch_s<S, true>(st, s, insts, nmem, table, ntab, par);
-    else launch_batch_s<S, false>(st, s, insts, nmem, table, ntab, par);
+    if (cs) launch_batch_s<S, true>(st, s, insts, table, ntab, dtab, ndtab, par);
+    else launch_batch_s<S, false>(st, s, insts, table, ntab, dtab, ndtab, par);
 }
 
-// cs: some member has a per-cell soil or source plane.
+// cs: some member has a per-cell soil or source plane.  Tile shapes take the
+// (member, bx, by) table; strips the stage and K3a tables.
 void launch_batch(int shape, Stage st, hipStream_t s, const Inst *insts, int nmem,
-                  const int *table, int ntab, int par, bool cs)
+                  const int *table, int ntab, const int *dtab, int ndtab, int par, bool cs)
 {
     switch (shape) {
     case 0: launch_batch_t<64, 8>(st, s, insts, nmem, table, ntab, par); break;
     case 1: launch_batch_t<64, 4>(st, s, insts, nmem, table, ntab, par); break;
     case 2: launch_batch_t<64, 16>(st, s, insts, nmem, table, ntab, par); break;
     case 3: launch_batch_t<128, 4>(st, s, insts, nmem, table, ntab, par); break;
-    case 4: launch_batch_s<8>(st, s, insts, nmem, table, ntab, par, cs); break;
-    case 5: launch_batch_s<16>(st, s, insts, nmem, table, ntab, par, cs); break;
-    default: launch_batch_s<32>(st, s, insts, nmem, table, ntab, par, cs); break;
+    case 4: launch_batch_s<8>(st, s, insts, table, ntab, dtab, ndtab, par, cs); break;
+    case 5: launch_batch_s<16>(st, s, insts, table, ntab, dtab, ndtab, par, cs); break;
+    default: launch_batch_s<32>(st, s, insts, table, ntab, dtab, ndtab, par, cs); break;
     }
 }
 
@@ -2674,8 +2670,8 @@ struct swb_ctx {
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;
     Inst *d_insts = nullptr;
-    int *d_table = nullptr;
-    int ntab = 0;
+    int *d_table = nullptr;          // stage table, then (strips) the K3a table
+    int ntab = 0, ndtab = 0;
     int shape = kDefaultShape;
     bool cs = false;  // some member reads per-cell soil or source planes
     hipGraphExec_t gexec = nullptr;
@@ -2703,7 +2699,7 @@ int batch_build(swb_ctx *b)
 {
     const int n = (int)b->mem.size();
     std::vector<Inst> insts(n);
-    std::vector<int> table;
+    std::vector<int> table, dtable;
     b->cs = false;
     for (int m = 0; m < n; ++m) {
         sw_ctx *c = b->mem[m];
@@ -2714,15 +2710,29 @@ int batch_build(swb_ctx *b)
         }
         insts[m] = make_inst(c, make_step_args(c, 0, 0.0));
         b->cs = b->cs || cell_soil(insts[m].P);
-        // one entry per workgroup: a tile, or a stack of SWAVES strip tiles
-        const int rows = is_strip(b->shape) ? (c->nty + SWAVES - 1) / SWAVES : c->nty;
-        for (int by = 0; by < rows; ++by)
-            for (int bx = 0; bx < c->ntx; ++bx) {
+        if (is_strip(b->shape)) {  // one entry per workgroup of SWAVES list entries
+            const int blocks = (c->ntx * c->nty + SWAVES - 1) / SWAVES;
+            for (int w = 0; w < blocks; ++w) {
                 table.push_back(m);
-                table.push_back(bx);
-                table.push_back(by);
+                table.push_back(w);
             }
+            for (int k = 0; k < insts[m].nchunk; ++k) {
+                dtable.push_back(m);
+                dtable.push_back(k);
+            }
+        } else {  // one entry per tile
+            for (int by = 0; by < c->nty; ++by)
+                for (int bx = 0; bx < c->ntx; ++bx) {
+                    table.push_back(m);
+                    table.push_back(bx);
+                    table.push_back(by);
+                }
+        }
     }
+    const int per = is_strip(b->shape) ? 2 : 3;
+    b->ntab = (int)(table.size() / per);
+    b->ndtab = (int)(dtable.size() / 2);
+    table.insert(table.end(), dtable.begin(), dtable.end());
     (void)hipFree(b->d_insts);
     (void)hipFree(b->d_table);
     b->d_insts = nullptr;
@@ -2731,7 +2741,6 @@ int batch_build(swb_ctx *b)
     BHIPCHK(b, hipMalloc(&b->d_table, table.size() * sizeof(int)));
     BHIPCHK(b, hipMemcpy(b->d_insts, insts.data(), n * sizeof(Inst), hipMemcpyHostToDevice));
     BHIPCHK(b, hipMemcpy(b->d_table, table.data(), table.size() * sizeof(int), hipMemcpyHostToDevice));
-    b->ntab = (int)(table.size() / 3);
     if (b->gexec) {
         (void)hipGraphExecDestroy(b->gexec);
         b->gexec = nullptr;
@@ -2743,9 +2752,12 @@ int batch_build(swb_ctx *b)
 void batch_step(swb_ctx *b, hipStream_t st, int par)
 {
     const int n = (int)b->mem.size();
-    launch_batch(b->shape, kDt, st, b->d_insts, n, b->d_table, b->ntab, par, b->cs);
-    launch_batch(b->shape, kLagrange, st, b->d_insts, n, b->d_table, b->ntab, par, b->cs);
-    launch_batch(b->shape, kEuler, st, b->d_insts, n, b->d_table, b->ntab, par, b->cs);
+    const int *dtab = b->d_table + 2 * b->ntab;
+    launch_batch(b->shape, kDt, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, par, b->cs);
+    launch_batch(b->shape, kLagrange, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, par,
+                 b->cs);
+    launch_batch(b->shape, kEuler, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, par,
+                 b->cs);
 }
 
 bool batch_needs_build(const swb_ctx *b)
