@@ -85,18 +85,20 @@ __device__ __forceinline__ void block_maxima(unsigned a, unsigned b, unsigned c,
 }
 
 // Eq. 7 maxima contributions of one cell of a state with Manning coefficient
-// nM, grain size d50 and porosity psi.
-__device__ __forceinline__ void cell_maxima_s(const KPar &P, float H, float qx, float qy, float b,
+// nM, grain size d50 and porosity psi; jx, jy, jm receive the cell's J0 and
+// |J0| (the values the next Euler stage uses).
+__device__ __forceinline__ void cell_maxima_j(const KPar &P, float H, float qx, float qy, float b,
                                               float nM, float d50, float psi, unsigned &mv,
-                                              unsigned &ms, unsigned &mD, unsigned &bad)
+                                              unsigned &ms, unsigned &mD, unsigned &bad, float &jx,
+                                              float &jy, float &jm)
 {
     float w = wdes(H, P);
     float u = qx * w, v = qy * w;
     float sp = sqrtf(sumsq(u, v));
     float cs = sqrtf(P.g * (H > 0.0f ? H : 0.0f));
-    float jx, jy;
     bedload(P, H, u, v, nM, d50, jx, jy);
-    float Dc = sqrtf(sumsq(jx, jy)) / (1.0f - psi);
+    jm = sqrtf(sumsq(jx, jy));
+    float Dc = jm / (1.0f - psi);
     bool fin = isfinite(H) && isfinite(qx) && isfinite(qy) && isfinite(b) && isfinite(sp) &&
                isfinite(Dc);
     if (!fin) {
@@ -106,6 +108,14 @@ __device__ __forceinline__ void cell_maxima_s(const KPar &P, float H, float qx, 
     mv = max(mv, fbits_nonneg(sp));
     ms = max(ms, fbits_nonneg(sp + cs));
     mD = max(mD, fbits_nonneg(Dc));
+}
+
+__device__ __forceinline__ void cell_maxima_s(const KPar &P, float H, float qx, float qy, float b,
+                                              float nM, float d50, float psi, unsigned &mv,
+                                              unsigned &ms, unsigned &mD, unsigned &bad)
+{
+    float jx, jy, jm;
+    cell_maxima_j(P, H, qx, qy, b, nM, d50, psi, mv, ms, mD, bad, jx, jy, jm);
 }
 
 // The same for cell c of the grid (soil read from its per-cell planes or scalars).
@@ -448,6 +458,7 @@ struct Inst {
     Ctrl *ctrl;
     float *H[2], *qx[2], *qy[2], *b[2];
     float *QLx, *QLy;
+    float *jx[2], *jy[2], *jm[2];  // J0 and |J0| of each buffer level's state (strip kernels)
     double *bnd;
     uint8_t *act[2];
     uint8_t *synced;
@@ -618,7 +629,12 @@ __device__ void prepare_tile(const Inst &I, int par, int bx, int by)
         if (i >= P.nx || j >= P.ny) continue;
         int c = j * P.pitch + i;
         float h = H[c];
-        cell_maxima(P, h, qx[c], qy[c], b[c], c, mv, ms, mD, bad);
+        float jx, jy, jm;
+        cell_maxima_j(P, h, qx[c], qy[c], b[c], soil(P.nM, P.nM_s, c), soil(P.d50, P.d50_s, c),
+                      soil(P.psi, P.psi_s, c), mv, ms, mD, bad, jx, jy, jm);
+        I.jx[par][c] = jx;
+        I.jy[par][c] = jy;
+        I.jm[par][c] = jm;
         if (h > 0.0f) s_any = 1;
     }
     block_maxima_store(mv, ms, mD, bad, &I.tmax[par][tile]);
@@ -1146,16 +1162,27 @@ __device__ void euler_strip(const Inst &I, int par, int bx, int by)
     const bool xghost = i == -1 || i == nx;
     const bool face_x = i >= 0 && i <= nx;  // this lane's west face is a grid face
     const int ci = min(max(i, 0), nx - 1);
-    auto soil_at = [&](const float *a, float sc, int c) -> float { return CS && a ? a[c] : sc; };
-    // a row as loaded (clamped into the grid; the consumer zeroes what lies outside)
+    const float *Jx = I.jx[par], *Jy = I.jy[par], *Jm = I.jm[par];
+    // every plane is addressed as a uniform base plus one 32-bit byte offset
+    auto at = [](const float *base, unsigned o) -> float {
+        return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + o);
+    };
+    auto put = [](float *base, unsigned o, float v) {
+        *reinterpret_cast<float *>(reinterpret_cast<char *>(base) + o) = v;
+    };
+    auto soil_at = [&](const float *a, float sc, unsigned o) -> float {
+        return CS && a ? at(a, o) : sc;
+    };
+    // a row as loaded (clamped into the grid; the consumer zeroes what lies
+    // outside): state, Lagrangian momentum, J0 and |J0| of the state
     struct Row {
-        float h, qx, qy, b, Lx, Ly, nM, d50;
+        float h, qx, qy, b, Lx, Ly, jx, jy, jm;
     };
     auto load_row = [&](int r, Row &w) {
-        const int c = min(max(r, 0), ny - 1) * pitch + ci;
-        w.h = SH[c]; w.qx = Sqx[c]; w.qy = Sqy[c]; w.b = Sb[c]; w.Lx = QLx[c]; w.Ly = QLy[c];
-        w.nM = soil_at(P.nM, P.nM_s, c);
-        w.d50 = soil_at(P.d50, P.d50_s, c);
+        const unsigned o = (unsigned)(min(max(r, 0), ny - 1) * pitch + ci) * 4u;
+        w.h = at(SH, o); w.qx = at(Sqx, o); w.qy = at(Sqy, o); w.b = at(Sb, o);
+        w.Lx = at(QLx, o); w.Ly = at(QLy, o);
+        w.jx = at(Jx, o); w.jy = at(Jy, o); w.jm = at(Jm, o);
     };
     // registers carried along the march, for the current row r:
     CellVals v1{}, v2{}, v3{};                 // remap inputs of rows r-2 .. r
@@ -1174,14 +1201,15 @@ __device__ void euler_strip(const Inst &I, int par, int bx, int by)
         const bool upd = ju >= y0 && ju < jend;
         float uh = 0, uqx = 0, uqy = 0, ub = 0, uLx = 0, uLy = 0;
         float upsi = P.psi_s, usrc = 0, uqb = 0, unM = P.nM_s, ud50 = P.d50_s;
+        const unsigned uo = (unsigned)(ju * pitch + ci) * 4u;
         if (upd) {
-            const int c = ju * pitch + ci;
-            uh = SH[c]; uqx = Sqx[c]; uqy = Sqy[c]; ub = Sb[c]; uLx = QLx[c]; uLy = QLy[c];
-            upsi = soil_at(P.psi, P.psi_s, c);
-            usrc = soil_at(P.srcw, 0.0f, c);
-            uqb = soil_at(P.qb, 0.0f, c);
-            unM = soil_at(P.nM, P.nM_s, c);
-            ud50 = soil_at(P.d50, P.d50_s, c);
+            uh = at(SH, uo); uqx = at(Sqx, uo); uqy = at(Sqy, uo); ub = at(Sb, uo);
+            uLx = at(QLx, uo); uLy = at(QLy, uo);
+            upsi = soil_at(P.psi, P.psi_s, uo);
+            usrc = soil_at(P.srcw, 0.0f, uo);
+            uqb = soil_at(P.qb, 0.0f, uo);
+            unM = soil_at(P.nM, P.nM_s, uo);
+            ud50 = soil_at(P.d50, P.d50_s, uo);
         }
         const bool iny = (unsigned)r < (unsigned)ny;
         {  // remap inputs of row r (ghost cells beyond the domain edge)
@@ -1196,13 +1224,10 @@ __device__ void euler_strip(const Inst &I, int par, int bx, int by)
         xs3 = xs2; xs2 = xs1; xs1 = xs0;
         ys3 = ys2; ys2 = ys1; ys1 = ys0;
         if (r >= y0 - 1 && r <= y0 + S) {  // J0 (Eqs. 3-5) of row r and its bedload faces
-            float jx = 0.0f, jy = 0.0f, b = 0.0f;
-            if (inx && iny) {
-                const float w = wdes(in.h, P);
-                bedload(P, in.h, in.qx * w, in.qy * w, in.nM, in.d50, jx, jy);
-                b = in.b;
-            }
-            const float mag = sqrtf(sumsq(jx, jy));
+            // J0 and |J0| of the state were stored by the step that produced it
+            const bool in_dom = inx && iny;
+            const float jx = in_dom ? in.jx : 0.0f, jy = in_dom ? in.jy : 0.0f;
+            const float mag = in_dom ? in.jm : 0.0f, b = in_dom ? in.b : 0.0f;
             const float jxW = lane_prev(jx), magW = lane_prev(mag), bW = lane_prev(b);
             float xs = 0.0f, ys = 0.0f;
             if (r >= y0 && r < jend && face_x)  // W face of this lane in row r
@@ -1261,10 +1286,12 @@ __device__ void euler_strip(const Inst &I, int par, int bx, int by)
                 F.Jw = xs3; F.Js = ys3; F.Jn = ys2;
                 const float src = P.srcw ? usrc * qmid : 0.0f;
                 const CellNew o = cell_update(P, dt, F, uh, uqx, uqy, ub, uLx, uLy, src, upsi, uqb);
-                const int c = ju * pitch + i;
-                OH[c] = o.H; Oqx[c] = o.qx; Oqy[c] = o.qy; Ob[c] = o.b;
+                put(OH, uo, o.H); put(Oqx, uo, o.qx); put(Oqy, uo, o.qy); put(Ob, uo, o.b);
                 boundary_balances(P, I.bnd, wdx, i, ju, o, F);
-                cell_maxima_s(P, o.H, o.qx, o.qy, o.b, unM, ud50, upsi, mv, ms, mD, bad);
+                float njx, njy, njm;
+                cell_maxima_j(P, o.H, o.qx, o.qy, o.b, unM, ud50, upsi, mv, ms, mD, bad, njx, njy,
+                              njm);
+                put(I.jx[par ^ 1], uo, njx); put(I.jy[par ^ 1], uo, njy); put(I.jm[par ^ 1], uo, njm);
                 if (o.H > 0.0f) wet = true;
             }
         }
@@ -1496,6 +1523,9 @@ __device__ void strip_copy(const Inst &I, int par, int bx, int by)
         I.qx[par ^ 1][c] = I.qx[par][c];
         I.qy[par ^ 1][c] = I.qy[par][c];
         I.b[par ^ 1][c] = I.b[par][c];
+        I.jx[par ^ 1][c] = I.jx[par][c];
+        I.jy[par ^ 1][c] = I.jy[par][c];
+        I.jm[par ^ 1][c] = I.jm[par][c];
     }
 }
 
@@ -1700,6 +1730,7 @@ struct sw_ctx {
     float *buf = nullptr;            // all pitched planes in one allocation
     float *H[2]{}, *qx[2]{}, *qy[2]{}, *b[2]{};
     float *QLx = nullptr, *QLy = nullptr;
+    float *jx[2]{}, *jy[2]{}, *jm[2]{};  // J0 and |J0| per buffer level
     float *nM = nullptr, *d50 = nullptr, *psi = nullptr, *qb = nullptr, *srcw = nullptr;
     float nM_s = 0.0f, d50_s = 5e-4f, psi_s = 0.4f;
     float *faces = nullptr;          // unfused face arrays
@@ -1874,6 +1905,11 @@ Inst make_inst(const sw_ctx *c, const StepArgs &A)
         I.act[s] = act_flags(c, s);
     }
     I.QLx = c->QLx;
+    for (int s = 0; s < 2; ++s) {
+        I.jx[s] = c->jx[s];
+        I.jy[s] = c->jy[s];
+        I.jm[s] = c->jm[s];
+    }
     I.QLy = c->QLy;
     I.bnd = c->bnd;
     I.synced = synced_flags(c);
@@ -2173,7 +2209,7 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
         c->own_stream = true;
     }
     // planes: 2 x (H, qx, qy, b), QLx, QLy
-    const int nplanes = 10;
+    const int nplanes = 16;
     if ((e = hipMalloc(&c->buf, nplanes * c->plane * sizeof(float))) != hipSuccess)
         return bail(e, "hipMalloc(state)");
     if ((e = hipMemset(c->buf, 0, nplanes * c->plane * sizeof(float))) != hipSuccess)
@@ -2186,6 +2222,11 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
     }
     c->QLx = c->buf + 8 * c->plane;
     c->QLy = c->buf + 9 * c->plane;
+    for (int s = 0; s < 2; ++s) {
+        c->jx[s] = c->buf + (10 + 3 * s) * c->plane;
+        c->jy[s] = c->buf + (11 + 3 * s) * c->plane;
+        c->jm[s] = c->buf + (12 + 3 * s) * c->plane;
+    }
     if (c->par.flags & SW_FLAG_UNFUSED) {  // face arrays of the unfused sequence only
         size_t nf = 4 * ((size_t)(c->nx + 1) * c->ny + (size_t)c->nx * (c->ny + 1));
         if ((e = hipMalloc(&c->faces, nf * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc(faces)");
