@@ -312,7 +312,7 @@ def cpu_baseline(w, steps):
         t0 = time.perf_counter()
         O.step(p, inp, st)
         one = time.perf_counter() - t0
-        steps = max(2, min(60, int(15.0 / max(one, 1e-3))))
+        steps = max(2, min(600, int(15.0 / max(one, 1e-3))))
     log(f"[bench] cpu oracle: {steps} steps on {w.nx}x{w.ny}, {O.threads()} threads")
     t0 = time.perf_counter()
     O.run(p, inp, st, steps)
