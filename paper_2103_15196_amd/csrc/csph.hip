@@ -94,11 +94,11 @@ __device__ __forceinline__ void cell_maxima_j(const KPar &P, float H, float qx, 
 {
     float w = wdes(H, P);
     float u = qx * w, v = qy * w;
-    float sp = sqrtf(sumsq(u, v));
-    float cs = sqrtf(P.g * (H > 0.0f ? H : 0.0f));
+    float sp = nsqrt(sumsq(u, v));
+    float cs = nsqrt(P.g * (H > 0.0f ? H : 0.0f));
     bedload(P, H, u, v, nM, d50, jx, jy);
-    jm = sqrtf(sumsq(jx, jy));
-    float Dc = jm / (1.0f - psi);
+    jm = nsqrt(sumsq(jx, jy));
+    float Dc = ndiv(jm, 1.0f - psi);
     bool fin = isfinite(H) && isfinite(qx) && isfinite(qy) && isfinite(b) && isfinite(sp) &&
                isfinite(Dc);
     if (!fin) {
@@ -246,7 +246,7 @@ __device__ float half_depth(const KPar &P, const StateView &S, int i, int j, flo
     else vs = (P.bcS == kWall) ? 0.0f : vc;
     float Jx = 1.0f + hdt_dx * (ue - uw);
     float Jy = 1.0f + hdt_dx * (vn - vs);
-    return S.H[c] / (Jx * Jy);
+    return ndiv(S.H[c], Jx * Jy);
 }
 
 __global__ void __launch_bounds__(BX * BY) k_lagrange(KPar P, const Ctrl *__restrict__ ctrl, int k,
@@ -270,11 +270,11 @@ __global__ void __launch_bounds__(BX * BY) k_lagrange(KPar P, const Ctrl *__rest
     float qxc = S.qx[c], qyc = S.qy[c];
     float uc = qxc * wc, vc = qyc * wc;
     float nM = soil(P.nM, P.nM_s, c);
-    float gam = friction_rate(P, nM, sqrtf(sumsq(uc, vc)), Hc);
+    float gam = friction_rate(P, nM, nsqrt(sumsq(uc, vc)), Hc);
     // K4: predictor momentum and half-step depths
     float hdt = 0.5f * dt;
-    float qpx = (qxc + hdt * Snx) / (1.0f + hdt * gam);
-    float qpy = (qyc + hdt * Sny) / (1.0f + hdt * gam);
+    float qpx = ndiv(qxc + hdt * Snx, 1.0f + hdt * gam);
+    float qpy = ndiv(qyc + hdt * Sny, 1.0f + hdt * gam);
     float upx = qpx * wc, upy = qpy * wc;
     float hdt_dx = dt / (2.0f * P.dx);
     float Hh = half_depth(P, S, i, j, hdt_dx);
@@ -285,10 +285,10 @@ __global__ void __launch_bounds__(BX * BY) k_lagrange(KPar P, const Ctrl *__rest
     // K5: forces at t_{n+1/2}
     float Shx = face_force(P, HhW, bW, Hh, bc, HhE, bE, hasW, hasE);
     float Shy = face_force(P, HhS, bS, Hh, bc, HhN, bN, hasS, hasN);
-    float gamh = friction_rate(P, nM, sqrtf(sumsq(upx, upy)), Hh);
+    float gamh = friction_rate(P, nM, nsqrt(sumsq(upx, upy)), Hh);
     // K6: corrector (Lagrangian momentum)
-    QLx[c] = (qxc + dt * Shx) / (1.0f + dt * gamh);
-    QLy[c] = (qyc + dt * Shy) / (1.0f + dt * gamh);
+    QLx[c] = ndiv(qxc + dt * Shx, 1.0f + dt * gamh);
+    QLy[c] = ndiv(qyc + dt * Shy, 1.0f + dt * gamh);
 }
 
 // ---------------------------------------------------------------------------
@@ -663,7 +663,7 @@ __device__ __forceinline__ float half_depth_cell(const KPar &P, float H, float u
     else vs = (P.bcS == kWall) ? 0.0f : vc;
     float Jx = 1.0f + hdt_dx * (ue - uw);
     float Jy = 1.0f + hdt_dx * (vn - vs);
-    return H / (Jx * Jy);
+    return ndiv(H, Jx * Jy);
 }
 
 // K2 + K4 + K5 + K6 of one cell: forces at t_n from the depths and beds of the
@@ -681,18 +681,18 @@ __device__ __forceinline__ void lagrange_cell(const KPar &P, float dt, const Nbr
     float Sny = face_force(P, Hd.S, bd.S, Hd.C, bd.C, Hd.N, bd.N, hasS, hasN);
     float wc = wdes(Hd.C, P);
     float uc = qxc * wc, vc = qyc * wc;
-    float gam = friction_rate(P, nM, sqrtf(sumsq(uc, vc)), Hd.C);
+    float gam = friction_rate(P, nM, nsqrt(sumsq(uc, vc)), Hd.C);
     float hdt = 0.5f * dt;
-    float qpx = (qxc + hdt * Snx) / (1.0f + hdt * gam);
-    float qpy = (qyc + hdt * Sny) / (1.0f + hdt * gam);
+    float qpx = ndiv(qxc + hdt * Snx, 1.0f + hdt * gam);
+    float qpy = ndiv(qyc + hdt * Sny, 1.0f + hdt * gam);
     float upx = qpx * wc, upy = qpy * wc;
     float HhW = hasW ? Hh.W : Hh.C, HhE = hasE ? Hh.E : Hh.C;
     float HhS = hasS ? Hh.S : Hh.C, HhN = hasN ? Hh.N : Hh.C;
     float Shx = face_force(P, HhW, bd.W, Hh.C, bd.C, HhE, bd.E, hasW, hasE);
     float Shy = face_force(P, HhS, bd.S, Hh.C, bd.C, HhN, bd.N, hasS, hasN);
-    float gamh = friction_rate(P, nM, sqrtf(sumsq(upx, upy)), Hh.C);
-    QLx = (qxc + dt * Shx) / (1.0f + dt * gamh);
-    QLy = (qyc + dt * Shy) / (1.0f + dt * gamh);
+    float gamh = friction_rate(P, nM, nsqrt(sumsq(upx, upy)), Hh.C);
+    QLx = ndiv(qxc + dt * Shx, 1.0f + dt * gamh);
+    QLy = ndiv(qyc + dt * Shy, 1.0f + dt * gamh);
 }
 
 // Draining limiter of a cell of depth h from its four raw mass fluxes.

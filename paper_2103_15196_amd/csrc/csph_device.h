@@ -38,6 +38,34 @@ struct KPar {
 
 __device__ __forceinline__ float soil(const float *a, float s, int c) { return a ? a[c] : s; }
 
+// Square root and quotient for the operands the step produces: x = 0 or
+// x >= 2^-96, and divisors whose quotient needs no range scaling.  The
+// hardware estimate (v_sqrt_f32 / v_rcp_f32, within 1 ulp) is corrected with
+// exact fused residuals: for the square root, the neighbours s -/+ 1 ulp of
+// the estimate s are taken when x - (s -/+ 1 ulp) s says the root lies past
+// their midpoint with s; for the quotient, one Newton step refines the
+// reciprocal and two residual steps q + r (a - b q) the quotient.  In this
+// range both are the correctly rounded results (what sqrtf and a / b give),
+// without the scaling and special-value handling that only operands outside
+// it need.  (A numerator of -0 gives +0.)
+__device__ __forceinline__ float nsqrt(float x)
+{
+    const float s = __builtin_amdgcn_sqrtf(x);
+    const float lo = __int_as_float(__float_as_int(s) - 1);
+    const float hi = __int_as_float(__float_as_int(s) + 1);
+    const float r = fmaf(-lo, s, x) <= 0.0f ? lo : s;
+    return fmaf(-hi, s, x) > 0.0f ? hi : r;
+}
+
+__device__ __forceinline__ float ndiv(float a, float b)
+{
+    float r = __builtin_amdgcn_rcpf(b);
+    r = fmaf(fmaf(-b, r, 1.0f), r, r);
+    float q = a * r;
+    q = fmaf(fmaf(-b, q, a), r, q);
+    return fmaf(fmaf(-b, q, a), r, q);
+}
+
 // a^2 + b^2 without fused multiply-add, so that swapping a and b (a grid and
 // its transpose) gives the same bits.
 __device__ __forceinline__ float sumsq(float a, float b)
@@ -50,9 +78,9 @@ __device__ __forceinline__ float sumsq(float a, float b)
 // sqrt(2) H / sqrt(H^4 + eps^4) below, zero at H = 0.
 __device__ __forceinline__ float wdes(float H, const KPar &P)
 {
-    if (H >= P.eps) return 1.0f / H;
+    if (H >= P.eps) return ndiv(1.0f, H);
     float H2 = H * H;
-    return 1.41421356237f * H / sqrtf(H2 * H2 + P.eps4);
+    return ndiv(1.41421356237f * H, nsqrt(H2 * H2 + P.eps4));
 }
 
 __device__ __forceinline__ float minmod(float a, float b)
@@ -75,7 +103,7 @@ __device__ __forceinline__ float pow43(float x) { return powp(x, 4.0f / 3.0f); }
 __device__ __forceinline__ float friction_rate(const KPar &P, float nM, float speed, float H)
 {
     float Hf = H > P.eps ? H : P.eps;
-    return P.g * nM * nM * speed / pow43(Hf);
+    return ndiv(P.g * nM * nM * speed, pow43(Hf));
 }
 
 // Zero-slope bedload J0 (Eqs. 3-5): zero at or below h_sed or at or below the
@@ -86,14 +114,14 @@ __device__ __forceinline__ void bedload(const KPar &P, float H, float u, float v
     jx = 0.0f;
     jy = 0.0f;
     if (P.sed_law == 0 || !(H > P.h_sed)) return;
-    float speed = sqrtf(sumsq(u, v));
+    float speed = nsqrt(sumsq(u, v));
     float vk = P.C_Sh * powp(d50, 1.0f / 3.0f) * powp(H, 1.0f / 6.0f);
     if (!(speed > vk)) return;
     float f;
     if (P.sed_law == 1) {
         f = P.A_G * (P.m_exp == 2.0f ? speed * speed : powp(speed, P.m_exp));
     } else {
-        float A = 0.05f * nM * nM * nM / (P.s_rel_m1 * sqrtf(P.g * H) * d50);
+        float A = ndiv(0.05f * nM * nM * nM, P.s_rel_m1 * nsqrt(P.g * H) * d50);
         float s2 = speed * speed;
         f = A * (s2 * s2);
     }
@@ -250,13 +278,13 @@ __device__ __forceinline__ void hll(float g, const FaceState &l, const FaceState
     float UR0 = r.Hs, UR1 = r.Hs * r.uLn, UR2 = r.Hs * r.uLt;
     float FL0 = l.ut * UL0, FL1 = l.ut * UL1, FL2 = l.ut * UL2;
     float FR0 = r.ut * UR0, FR1 = r.ut * UR1, FR2 = r.ut * UR2;
-    float cL = sqrtf(g * l.Hs), cR = sqrtf(g * r.Hs);
+    float cL = nsqrt(g * l.Hs), cR = nsqrt(g * r.Hs);
     float SL = fminf(l.ut - cL, r.ut - cR);
     float SR = fmaxf(l.ut + cL, r.ut + cR);
     // the four cases are selected, not branched: every lane evaluates the
     // HLL average and keeps the upwind flux when both speeds share a sign
     const bool left = SL >= 0.0f, right = SR <= 0.0f, fan = SR - SL > 0.0f;
-    const float inv = fan ? 1.0f / (SR - SL) : 0.0f;
+    const float inv = fan ? ndiv(1.0f, SR - SL) : 0.0f;
     const float SLR = SL * SR;
     const float hH = (SR * FL0 - SL * FR0 + SLR * (UR0 - UL0)) * inv;
     const float hn = (SR * FL1 - SL * FR1 + SLR * (UR1 - UL1)) * inv;
@@ -271,7 +299,7 @@ __device__ __forceinline__ void hll(float g, const FaceState &l, const FaceState
 // the interior cell on the minus side (E/N wall).
 __device__ __forceinline__ float wall_flux_n(float g, const FaceState &s, float side)
 {
-    float c = sqrtf(g * s.Hs);
+    float c = nsqrt(g * s.Hs);
     return s.Hs * s.uLn * (s.ut + side * (fabsf(s.ut) + c));
 }
 
@@ -399,8 +427,8 @@ __device__ __forceinline__ float sed_flux(const KPar &P, int k, int n, bool wall
                                           int dir, float jxL, float jyL, float bL, float jxR,
                                           float jyR, float bR)
 {
-    return sed_face(P, k, n, wallLo, wallHi, dir == 0 ? jxL : jyL, sqrtf(sumsq(jxL, jyL)), bL,
-                    dir == 0 ? jxR : jyR, sqrtf(sumsq(jxR, jyR)), bR);
+    return sed_face(P, k, n, wallLo, wallHi, dir == 0 ? jxL : jyL, nsqrt(sumsq(jxL, jyL)), bL,
+                    dir == 0 ? jxR : jyR, nsqrt(sumsq(jxR, jyR)), bR);
 }
 
 }  // namespace csph
