@@ -1020,17 +1020,35 @@ __device__ __forceinline__ CellQ q_next(const CellQ &q)
     return CellQ{lane_next(q.z), lane_next(q.h), lane_next(q.ut), lane_next(q.uLn), lane_next(q.uLt)};
 }
 
+// Maximum over the 64 lanes (all active), uniform: DPP swaps within quads
+// (quad_perm [1,0,3,2] and [2,3,0,1]), half rows (row_half_mirror) and rows
+// of 16 (row_mirror) leave each row's maximum in all its lanes; the four row
+// maxima are then read as scalars.
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_max(unsigned x)
+{
+    return max(x, (unsigned)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ unsigned wave_max_u32(unsigned x)
+{
+    x = dpp_max<0xb1>(x);
+    x = dpp_max<0x4e>(x);
+    x = dpp_max<0x141>(x);
+    x = dpp_max<0x140>(x);
+    const unsigned r0 = __builtin_amdgcn_readlane((int)x, 0), r1 = __builtin_amdgcn_readlane((int)x, 16);
+    const unsigned r2 = __builtin_amdgcn_readlane((int)x, 32), r3 = __builtin_amdgcn_readlane((int)x, 48);
+    return max(max(r0, r1), max(r2, r3));
+}
+
 // Wave-wide maxima of the Eq. 7 contributions and the wet flag of a strip
 // tile, stored with plain writes into the tile's slots.
 __device__ __forceinline__ void strip_maxima_store(const Inst &I, int par_out, int tile, unsigned a,
                                                    unsigned b, unsigned c, unsigned bad, bool wet)
 {
-    for (int off = 32; off > 0; off >>= 1) {
-        a = max(a, (unsigned)__shfl_xor((int)a, off));
-        b = max(b, (unsigned)__shfl_xor((int)b, off));
-        c = max(c, (unsigned)__shfl_xor((int)c, off));
-        bad = max(bad, (unsigned)__shfl_xor((int)bad, off));
-    }
+    a = wave_max_u32(a);
+    b = wave_max_u32(b);
+    c = wave_max_u32(c);
+    bad = wave_max_u32(bad);
     const bool any_wet = __ballot(wet) != 0;
     if ((threadIdx.x & 63) == 0) {
         I.tmax[par_out][tile] = make_uint4(a, b, c, bad);
@@ -1396,15 +1414,25 @@ __global__ void __launch_bounds__(NT) k_euler_b(const Inst *__restrict__ insts,
 // back-to-back, so the hardware spreads them evenly over the CUs.
 // ---------------------------------------------------------------------------
 
-// Wave64 inclusive prefix sum.
+// Wave64 inclusive prefix sum (all lanes active): DPP row shifts by 1, 2, 4
+// and 8 (a lane without a source in its row of 16 adds 0) give the sum
+// within each row; the totals of the rows below are added from lanes 15, 31
+// and 47 as scalars.
+template <int CTRL>
+__device__ __forceinline__ int dpp_add_shifted(int x)
+{
+    return x + __builtin_amdgcn_update_dpp(0, x, CTRL, 0xf, 0xf, true);
+}
 __device__ __forceinline__ int wave_scan(int v)
 {
-    const int lane = threadIdx.x & 63;
-    for (int off = 1; off < 64; off <<= 1) {
-        int u = __shfl_up(v, off);
-        if (lane >= off) v += u;
-    }
-    return v;
+    v = dpp_add_shifted<0x111>(v);
+    v = dpp_add_shifted<0x112>(v);
+    v = dpp_add_shifted<0x114>(v);
+    v = dpp_add_shifted<0x118>(v);
+    const int row = (threadIdx.x & 63) >> 4;
+    const int t0 = __builtin_amdgcn_readlane(v, 15), t1 = __builtin_amdgcn_readlane(v, 31);
+    const int t2 = __builtin_amdgcn_readlane(v, 47);
+    return v + (row >= 1 ? t0 : 0) + (row >= 2 ? t1 : 0) + (row >= 3 ? t2 : 0);
 }
 
 // Exclusive prefix sums of two per-thread counts over the 1024 threads of a
@@ -1496,13 +1524,15 @@ __global__ void __launch_bounds__(RT) k_dt_lists_b(const Inst *__restrict__ inst
 
 // Entry w of a list kept in segments: the segment is the last one whose
 // start position is <= w (one ballot per 64 segments).
-__device__ __forceinline__ int list_entry(const int *seg, const int *pre, int nb, int chunk, int w)
+// p0: this lane's start position in the first group of 64, loaded by the caller.
+__device__ __forceinline__ int list_entry(const int *seg, const int *pre, int p0, int nb, int chunk,
+                                          int w)
 {
     const int lane = threadIdx.x & 63;
     int b = -1;
     for (int g = 0; g < nb; g += 64) {
         const int k = g + lane;
-        const unsigned long long le = __ballot(k < nb && pre[k] <= w);
+        const unsigned long long le = __ballot(k < nb && (g == 0 ? p0 : pre[k]) <= w);
         b += __popcll(le);
         if (le != ~0ull) break;
     }
@@ -1536,8 +1566,9 @@ __device__ void strip_copy(const Inst &I, int par, int bx, int by)
 // Start position of every segment of a list from the segment lengths (one
 // wave scan per 64 segments): returns the list length; *seg / *start receive
 // the segment holding entry w and its start (when w is below the length).
-__device__ __forceinline__ int list_locate(const int *cnt, int nb, int w, int &seg, int &start,
-                                           int *pre_out)
+// c0: this lane's length in the first group of 64 segments, loaded by the caller.
+__device__ __forceinline__ int list_locate(const int *cnt, int c0, int nb, int w, int &seg,
+                                           int &start, int *pre_out)
 {
     const int lane = threadIdx.x & 63;
     int base = 0;
@@ -1545,7 +1576,7 @@ __device__ __forceinline__ int list_locate(const int *cnt, int nb, int w, int &s
     start = 0;
     for (int g = 0; g < nb; g += 64) {
         const int k = g + lane;
-        const int c = k < nb ? cnt[k] : 0;
+        const int c = g == 0 ? c0 : (k < nb ? cnt[k] : 0);
         const int inc = wave_scan(c);
         const int st = base + inc - c;
         if (pre_out && k < nb) pre_out[k] = st;
@@ -1553,9 +1584,9 @@ __device__ __forceinline__ int list_locate(const int *cnt, int nb, int w, int &s
         if (le) {
             const int j = 63 - __clzll(le);  // the set lanes are a prefix (starts never decrease)
             seg = g + j;
-            start = __shfl(st, j);
+            start = __builtin_amdgcn_readlane(st, j);
         }
-        base += __shfl(inc, 63);
+        base += __builtin_amdgcn_readlane(inc, 63);
     }
     return base;
 }
@@ -1564,46 +1595,48 @@ template <int S, bool CS>
 __device__ void lagrange_listed(const Inst &I, int par, int w)
 {
     Ctrl *ctrl = I.ctrl;
-    if (ctrl->err) return;
     const int lane = threadIdx.x & 63;
     const bool publisher = w == 0;
     const int nb = I.nchunk;
+    // the error flag and the first 64 segment lengths and maxima are loaded
+    // together, before any of them is used (one round trip, not three)
+    const int err = ctrl->err;
+    const int cl0 = I.hgs && lane < nb ? I.cnt_l[lane] : 0;
+    const int ce0 = I.hgs && publisher && lane < nb ? I.cnt_e[lane] : 0;
+    uint4 v = lane < nb ? I.part[lane] : make_uint4(0u, 0u, 0u, 0u);
     int n = I.ntx * I.nty, seg = 0, start = 0;
-    if (I.hgs) n = list_locate(I.cnt_l, nb, w, seg, start, nullptr);
+    if (I.hgs) n = list_locate(I.cnt_l, cl0, nb, w, seg, start, nullptr);
     if (w >= n && !publisher) return;
     // the Eq. 7 step from the segment maxima (K3 proper)
-    unsigned a = 0, b = 0, c = 0, bad = 0;
-    for (int g = 0; g < nb; g += 64) {
-        const uint4 v = g + lane < nb ? I.part[g + lane] : make_uint4(0u, 0u, 0u, 0u);
+    unsigned a = v.x, b = v.y, c = v.z, bad = v.w;
+    for (int g = 64; g < nb; g += 64) {
+        v = g + lane < nb ? I.part[g + lane] : make_uint4(0u, 0u, 0u, 0u);
         a = max(a, v.x); b = max(b, v.y); c = max(c, v.z); bad = max(bad, v.w);
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        a = max(a, (unsigned)__shfl_xor((int)a, off));
-        b = max(b, (unsigned)__shfl_xor((int)b, off));
-        c = max(c, (unsigned)__shfl_xor((int)c, off));
-        bad = max(bad, (unsigned)__shfl_xor((int)bad, off));
-    }
-    const uint4 m = make_uint4(a, b, c, bad);
+    const uint4 m = make_uint4(wave_max_u32(a), wave_max_u32(b), wave_max_u32(c), wave_max_u32(bad));
     if (publisher) {
         if (I.hgs) {  // start positions of the Euler list for the Euler kernel
             int s0, s1;
-            const int ne = list_locate(I.cnt_e, nb, 0, s0, s1, I.pre_e);
+            const int ne = list_locate(I.cnt_e, ce0, nb, 0, s0, s1, I.pre_e);
             if (lane == 0) I.totals[1] = ne;
         }
         if (lane == 0) publish_dt(ctrl, par, I.A, m);
     }
     const Eq7 e = eq7_step(I.A, m);
-    if (e.err || w >= n) return;
+    if (err || e.err || w >= n) return;
     const int t = I.hgs ? I.lag[seg * I.chunk + (w - start)] : w;
     lagrange_strip<S, CS>(I, par, t % I.ntx, t / I.ntx, (float)e.dt);
 }
 template <int S, bool CS>
 __device__ void euler_listed(const Inst &I, int par, int w)
 {
-    if (I.ctrl->err) return;
+    // error flag, list length and the first 64 start positions in one round trip
+    const int lane = threadIdx.x & 63;
+    const int err = I.ctrl->err;
     const int n = I.hgs ? I.totals[1] : I.ntx * I.nty;
-    if (w >= n) return;
-    const int e = I.hgs ? list_entry(I.eul, I.pre_e, I.nchunk, I.chunk, w) : w;
+    const int p0 = I.hgs && lane < I.nchunk ? I.pre_e[lane] : 0;
+    if (err || w >= n) return;
+    const int e = I.hgs ? list_entry(I.eul, I.pre_e, p0, I.nchunk, I.chunk, w) : w;
     const int t = e < 0 ? -1 - e : e;
     if (e < 0) strip_copy<S>(I, par, t % I.ntx, t / I.ntx);
     else euler_strip<S, CS>(I, par, t % I.ntx, t / I.ntx);
