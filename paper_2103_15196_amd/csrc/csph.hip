@@ -1435,25 +1435,6 @@ __device__ __forceinline__ int wave_scan(int v)
     return v + (row >= 1 ? t0 : 0) + (row >= 2 ? t1 : 0) + (row >= 3 ? t2 : 0);
 }
 
-// Exclusive prefix sums of two per-thread counts over the 1024 threads of a
-// block, and their totals.
-__device__ __forceinline__ void block_scan2(int a, int b, int &xa, int &xb, int &ta, int &tb)
-{
-    __shared__ int wa[RT / 64], wb[RT / 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int ia = wave_scan(a), ib = wave_scan(b);
-    if (lane == 63) { wa[wv] = ia; wb[wv] = ib; }
-    __syncthreads();
-    int oa = 0, ob = 0;
-    ta = 0; tb = 0;
-    for (int k = 0; k < RT / 64; ++k) {
-        if (k < wv) { oa += wa[k]; ob += wb[k]; }
-        ta += wa[k]; tb += wb[k];
-    }
-    xa = oa + ia - a;
-    xb = ob + ib - b;
-}
-
 // K3 for strips (nchunk workgroups): workgroup b reduces the Eq. 7 maxima of
 // its tiles and, under dry-tile skipping, writes its segment of each list,
 // each thread classifying a contiguous run of tiles so that entries come out
@@ -1463,51 +1444,76 @@ __device__ __forceinline__ void block_scan2(int a, int b, int &xa, int &xb, int 
 // and wavefront 0 publishes the step and the Euler list's start positions.
 __device__ void dt_lists(const Inst &I, int par, int b)
 {
+    __shared__ unsigned red[4][RT / 64];
+    __shared__ int wl[RT / 64], we[RT / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nt = I.ntx * I.nty;
     const int c0 = b * I.chunk, c1 = min(nt, c0 + I.chunk);
-    const uint4 m = block_tile_maxima(I.tmax[par], c0, c1);
-    if (threadIdx.x == 0) I.part[b] = m;
-    if (!I.hgs) return;
     const int ntx = I.ntx, nty = I.nty;
     const uint8_t *act = I.act[par];
-    uint8_t *act_next = I.act[par ^ 1];
-    uint4 *tm_next = I.tmax[par ^ 1];
-    uint8_t *synced = I.synced;
+    const uint8_t *synced = I.synced;
+    const uint4 *tm = I.tmax[par];
     const int per = (c1 - c0 + RT - 1) / RT;  // at most 32 (chunk <= 32 RT)
-    const int t0 = min(c1, c0 + (int)threadIdx.x * per), t1 = min(c1, t0 + per);
+    const int t0 = min(c1, c0 + tid * per), t1 = min(c1, t0 + per);
+    // every load first: the tiles' maxima and (under skipping) the five wet
+    // flags and the synced flag of each tile of this thread's run
+    unsigned a = 0, bb = 0, c = 0, bad = 0;
     unsigned m_act = 0u, m_run = 0u, m_copy = 0u;
     int bx = t0 % ntx, by = t0 / ntx;
     for (int t = t0; t < t1; ++t) {
-        // all five flags and the synced flag loaded together (no short circuit)
-        const unsigned fa = act[t], fw = act[bx > 0 ? t - 1 : t], fe = act[bx + 1 < ntx ? t + 1 : t];
-        const unsigned fs = act[by > 0 ? t - ntx : t], fn = act[by + 1 < nty ? t + ntx : t];
-        const unsigned sy = synced[t];
-        const int q = t - t0;
-        const bool r = (fa | fw | fe | fs | fn) != 0;
-        m_act |= (unsigned)(fa != 0) << q;
-        m_run |= (unsigned)r << q;
-        m_copy |= (unsigned)(!r && !sy) << q;
+        const uint4 v = tm[t];
+        a = max(a, v.x); bb = max(bb, v.y); c = max(c, v.z); bad = max(bad, v.w);
+        if (I.hgs) {
+            const unsigned fa = act[t], fw = act[bx > 0 ? t - 1 : t], fe = act[bx + 1 < ntx ? t + 1 : t];
+            const unsigned fs = act[by > 0 ? t - ntx : t], fn = act[by + 1 < nty ? t + ntx : t];
+            const unsigned sy = synced[t];
+            const int q = t - t0;
+            const bool r = (fa | fw | fe | fs | fn) != 0;
+            m_act |= (unsigned)(fa != 0) << q;
+            m_run |= (unsigned)r << q;
+            m_copy |= (unsigned)(!r && !sy) << q;
+        }
         if (++bx == ntx) { bx = 0; ++by; }
     }
-    int ol, oe, tl, te;
-    block_scan2(__popc(m_act), __popc(m_run | m_copy), ol, oe, tl, te);
+    // wave maxima and wave prefix sums of the list counts, one barrier
+    const int nl = __popc(m_act), ne = __popc(m_run | m_copy);
+    const int il = wave_scan(nl), ie = wave_scan(ne);
+    a = wave_max_u32(a); bb = wave_max_u32(bb); c = wave_max_u32(c); bad = wave_max_u32(bad);
+    if (lane == 63) { wl[wv] = il; we[wv] = ie; }
+    if (lane == 0) { red[0][wv] = a; red[1][wv] = bb; red[2][wv] = c; red[3][wv] = bad; }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < RT / 64; ++w) {
+            a = max(a, red[0][w]); bb = max(bb, red[1][w]); c = max(c, red[2][w]); bad = max(bad, red[3][w]);
+        }
+        I.part[b] = make_uint4(a, bb, c, bad);
+    }
+    if (!I.hgs) return;
+    int ol = il - nl, oe = ie - ne, tl = 0, te = 0;
+    for (int k = 0; k < RT / 64; ++k) {
+        if (k < wv) { ol += wl[k]; oe += we[k]; }
+        tl += wl[k]; te += we[k];
+    }
+    uint8_t *act_next = I.act[par ^ 1];
+    uint4 *tm_next = I.tmax[par ^ 1];
+    uint8_t *synced_w = I.synced;
     int *lag = I.lag + c0, *eul = I.eul + c0;
     for (int t = t0; t < t1; ++t) {
         const unsigned bit = 1u << (t - t0);
         if (m_act & bit) lag[ol++] = t;
         if (m_run & bit) {
             eul[oe++] = t;
-            synced[t] = 0;
+            synced_w[t] = 0;
         } else {
             if (m_copy & bit) {
                 eul[oe++] = -1 - t;
-                synced[t] = 1;
+                synced_w[t] = 1;
             }
             act_next[t] = 0;
             tm_next[t] = make_uint4(0u, 0u, 0u, 0u);
         }
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         I.cnt_l[b] = tl;
         I.cnt_e[b] = te;
     }
@@ -1783,6 +1789,7 @@ struct sw_ctx {
     uint8_t *tflags = nullptr;       // act[2][ntiles], synced[ntiles], force[ntiles]
     hipStream_t cap = nullptr;       // private stream used only to capture graphs
     hipGraphExec_t gexec = nullptr;  // two tiled steps (even k, then odd k)
+    hipGraphExec_t gexec_long = nullptr;  // kLongPairs such pairs
     bool graph_ok = false;
     std::vector<int32_t> forced_in, forced_qb;  // inflow / bed-source cells (flat indices)
     int shape = kDefaultShape;       // index into kShapes
@@ -2122,22 +2129,38 @@ void enqueue_unfused_step(sw_ctx *c, int par, const KPar &P, const StepArgs &A)
 }
 
 // Capture the two-step graph (even step, then odd step) for the current inputs.
+// Step pairs in the long graph: one graph launch per 16 steps, so the gap
+// between two graph launches is paid once per 16 steps instead of every
+// second step.
+constexpr int kLongPairs = 8;
+
+int capture_pairs(sw_ctx *c, const KPar &P, const StepArgs &A, int pairs, hipGraphExec_t *out)
+{
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    for (int q = 0; q < pairs; ++q) {
+        enqueue_tiled_step(c, c->cap, 0, P, A);
+        enqueue_tiled_step(c, c->cap, 1, P, A);
+    }
+    HIPCHK(c, hipStreamEndCapture(c->cap, &g));
+    hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(c, SW_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return SW_OK;
+}
+
 int ensure_graph(sw_ctx *c, const KPar &P, const StepArgs &A)
 {
     if (c->graph_ok && c->graph_fixed == A.mode_fixed && c->graph_dt == A.dt_fixed) return SW_OK;
-    if (c->gexec) {
-        (void)hipGraphExecDestroy(c->gexec);
-        c->gexec = nullptr;
-    }
+    for (hipGraphExec_t *x : {&c->gexec, &c->gexec_long})
+        if (*x) {
+            (void)hipGraphExecDestroy(*x);
+            *x = nullptr;
+        }
     if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
-    hipGraph_t g = nullptr;
-    HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-    enqueue_tiled_step(c, c->cap, 0, P, A);
-    enqueue_tiled_step(c, c->cap, 1, P, A);
-    HIPCHK(c, hipStreamEndCapture(c->cap, &g));
-    hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return fail(c, SW_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    int rc = capture_pairs(c, P, A, 1, &c->gexec);
+    if (!rc) rc = capture_pairs(c, P, A, kLongPairs, &c->gexec_long);
+    if (rc) return rc;
     c->graph_ok = true;
     c->graph_fixed = A.mode_fixed;
     c->graph_dt = A.dt_fixed;
@@ -2175,6 +2198,10 @@ int launch_steps(sw_ctx *c, int32_t nsteps, int fixed, double dt)
     if (use_graph && left >= 2) {
         int rc = ensure_graph(c, P, A);
         if (rc) return rc;
+        for (; left >= 2 * kLongPairs; left -= 2 * kLongPairs) {
+            HIPCHK(c, hipGraphLaunch(c->gexec_long, c->stream));
+            c->k += 2 * kLongPairs;
+        }
         for (; left >= 2; left -= 2) {
             HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
             c->k += 2;
@@ -2311,6 +2338,7 @@ int sw_destroy(sw_ctx *c)
     (void)hipFree(c->tmax);
     (void)hipFree(c->sched);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->gexec_long) (void)hipGraphExecDestroy(c->gexec_long);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -2749,6 +2777,7 @@ struct swb_ctx {
     int shape = kDefaultShape;
     bool cs = false;  // some member reads per-cell soil or source planes
     hipGraphExec_t gexec = nullptr;
+    hipGraphExec_t gexec_long = nullptr;
     bool built = false;
     std::string err;
 };
@@ -2815,6 +2844,10 @@ int batch_build(swb_ctx *b)
     BHIPCHK(b, hipMalloc(&b->d_table, table.size() * sizeof(int)));
     BHIPCHK(b, hipMemcpy(b->d_insts, insts.data(), n * sizeof(Inst), hipMemcpyHostToDevice));
     BHIPCHK(b, hipMemcpy(b->d_table, table.data(), table.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (b->gexec_long) {
+        (void)hipGraphExecDestroy(b->gexec_long);
+        b->gexec_long = nullptr;
+    }
     if (b->gexec) {
         (void)hipGraphExecDestroy(b->gexec);
         b->gexec = nullptr;
@@ -2869,6 +2902,7 @@ int swb_destroy(swb_ctx *b)
     if (!b) return SW_OK;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->gexec_long) (void)hipGraphExecDestroy(b->gexec_long);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     (void)hipFree(b->d_insts);
     (void)hipFree(b->d_table);
@@ -2915,16 +2949,26 @@ int swb_advance(swb_ctx *b, int32_t nsteps)
         left--;
     }
     if (left >= 2) {
-        if (!b->gexec) {
+        if (!b->gexec) {  // graphs of one and of kLongPairs step pairs
             if (!b->cap) BHIPCHK(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
-            hipGraph_t g = nullptr;
-            BHIPCHK(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-            batch_step(b, b->cap, 0);
-            batch_step(b, b->cap, 1);
-            BHIPCHK(b, hipStreamEndCapture(b->cap, &g));
-            hipError_t e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) return bfail(b, SW_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            for (int pairs : {1, kLongPairs}) {
+                hipGraph_t g = nullptr;
+                BHIPCHK(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+                for (int q = 0; q < pairs; ++q) {
+                    batch_step(b, b->cap, 0);
+                    batch_step(b, b->cap, 1);
+                }
+                BHIPCHK(b, hipStreamEndCapture(b->cap, &g));
+                hipError_t e = hipGraphInstantiate(pairs == 1 ? &b->gexec : &b->gexec_long, g, nullptr,
+                                                   nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess)
+                    return bfail(b, SW_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+        }
+        for (; left >= 2 * kLongPairs; left -= 2 * kLongPairs) {
+            BHIPCHK(b, hipGraphLaunch(b->gexec_long, b->stream));
+            advance_members(2 * kLongPairs);
         }
         for (; left >= 2; left -= 2) {
             BHIPCHK(b, hipGraphLaunch(b->gexec, b->stream));
