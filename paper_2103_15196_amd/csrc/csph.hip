@@ -1234,10 +1234,17 @@ __device__ void euler_strip(const Inst &I, int par, int bx, int by)
             const bool yghost = r == -1 || r == ny;
             const CellVals v = cell_vals(P, in.h, in.qx, in.qy, in.b, in.Lx, in.Ly);
             v1 = v2; v2 = v3;
-            if (inx && iny) v3 = v;
-            else if (iny && xghost) v3 = mirror(v, 0, i < 0 ? wW : wE);
-            else if (inx && yghost) v3 = mirror(v, 1, r < 0 ? wS : wN);
-            else v3 = CellVals{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            // a cell inside, a ghost beyond one edge (a wall mirrors the normal
+            // components: the sign flips of `mirror`), or zero; selected per lane
+            const bool gx = iny && !inx && xghost, gy = inx && !iny && yghost;
+            const bool keep = (inx && iny) || gx || gy;
+            const bool fx = gx && (i < 0 ? wW : wE), fy = gy && (r < 0 ? wS : wN);
+            v3.z = keep ? v.z : 0.0f;
+            v3.h = keep ? v.h : 0.0f;
+            v3.utx = keep ? (fx ? -v.utx : v.utx) : 0.0f;
+            v3.uLx = keep ? (fx ? -v.uLx : v.uLx) : 0.0f;
+            v3.uty = keep ? (fy ? -v.uty : v.uty) : 0.0f;
+            v3.uLy = keep ? (fy ? -v.uLy : v.uLy) : 0.0f;
         }
         xs3 = xs2; xs2 = xs1; xs1 = xs0;
         ys3 = ys2; ys2 = ys1; ys1 = ys0;
@@ -1262,8 +1269,10 @@ __device__ void euler_strip(const Inst &I, int par, int bx, int by)
             if (k >= y0 - 2 && k <= y0 + S + 1) {
                 SideQ ym, ypn;
                 reconstruct(along(v1, 1), along(v2, 1), along(v3, 1), ym, ypn);
-                if (k >= y0 - 1 && inx && k >= 0 && k <= ny)
+                if (k >= y0 - 1 && k >= 0 && k <= ny) {  // the face row (uniform); lanes inside the grid keep it
                     side_flux(P, k, ny, wS, wN, yp, ym, f.H, f.n, f.t);
+                    if (!inx) f = Flux3{0.0f, 0.0f, 0.0f};
+                }
                 yp = ypn;
             }
             Y1 = f;
@@ -1279,9 +1288,10 @@ __device__ void euler_strip(const Inst &I, int par, int bx, int by)
                 reconstruct(q_prev(c), c, q_next(c), xm, xp);
                 const SideQ xl{lane_prev(xp.z), lane_prev(xp.h), lane_prev(xp.ut),
                                lane_prev(xp.uLn), lane_prev(xp.uLt), lane_prev(xp.b)};
-                Flux3 f{0.0f, 0.0f, 0.0f};
-                if (row_in && face_x) side_flux(P, i, nx, wW, wE, xl, xm, f.H, f.n, f.t);
-                X2 = f;
+                Flux3 f;
+                side_flux(P, i, nx, wW, wE, xl, xm, f.H, f.n, f.t);
+                const bool on = row_in && face_x;
+                X2 = Flux3{on ? f.H : 0.0f, on ? f.n : 0.0f, on ? f.t : 0.0f};
             }
             {  // draining limiter of row r-2
                 const float fe = lane_next(X2.H);
@@ -1597,9 +1607,13 @@ __device__ __forceinline__ int list_locate(const int *cnt, int c0, int nb, int w
     return base;
 }
 
+// The entry index and the tile it names are the same in every lane of the
+// wavefront; readfirstlane states that, so tile coordinates and the row
+// ranges derived from them live in scalar registers and branch as scalars.
 template <int S, bool CS>
 __device__ void lagrange_listed(const Inst &I, int par, int w)
 {
+    w = __builtin_amdgcn_readfirstlane(w);
     Ctrl *ctrl = I.ctrl;
     const int lane = threadIdx.x & 63;
     const bool publisher = w == 0;
@@ -1630,19 +1644,21 @@ __device__ void lagrange_listed(const Inst &I, int par, int w)
     }
     const Eq7 e = eq7_step(I.A, m);
     if (err || e.err || w >= n) return;
-    const int t = I.hgs ? I.lag[seg * I.chunk + (w - start)] : w;
+    const int t = __builtin_amdgcn_readfirstlane(I.hgs ? I.lag[seg * I.chunk + (w - start)] : w);
     lagrange_strip<S, CS>(I, par, t % I.ntx, t / I.ntx, (float)e.dt);
 }
 template <int S, bool CS>
 __device__ void euler_listed(const Inst &I, int par, int w)
 {
     // error flag, list length and the first 64 start positions in one round trip
+    w = __builtin_amdgcn_readfirstlane(w);
     const int lane = threadIdx.x & 63;
     const int err = I.ctrl->err;
     const int n = I.hgs ? I.totals[1] : I.ntx * I.nty;
     const int p0 = I.hgs && lane < I.nchunk ? I.pre_e[lane] : 0;
     if (err || w >= n) return;
-    const int e = I.hgs ? list_entry(I.eul, I.pre_e, p0, I.nchunk, I.chunk, w) : w;
+    const int e = __builtin_amdgcn_readfirstlane(
+        I.hgs ? list_entry(I.eul, I.pre_e, p0, I.nchunk, I.chunk, w) : w);
     const int t = e < 0 ? -1 - e : e;
     if (e < 0) strip_copy<S>(I, par, t % I.ntx, t / I.ntx);
     else euler_strip<S, CS>(I, par, t % I.ntx, t / I.ntx);

@@ -83,10 +83,13 @@ __device__ __forceinline__ float wdes(float H, const KPar &P)
     return ndiv(1.41421356237f * H, nsqrt(H2 * H2 + P.eps4));
 }
 
+// minmod(a, b): 0 unless a and b share a sign, else the one nearer zero,
+// i.e. min(|a|, |b|) with the sign of a.  Written without branches (one
+// min with absolute-value operands, one sign insert, one select).
 __device__ __forceinline__ float minmod(float a, float b)
 {
-    if (a * b <= 0.0f) return 0.0f;
-    return a > 0.0f ? fminf(a, b) : fmaxf(a, b);
+    const float m = copysignf(fminf(fabsf(a), fabsf(b)), a);
+    return a * b <= 0.0f ? 0.0f : m;
 }
 
 // Powers through the hardware base-2 logarithm and exponential (v_log_f32,
@@ -387,15 +390,15 @@ __device__ __forceinline__ void side_flux(const KPar &P, int k, int n, bool wall
                                           const SideQ &L, const SideQ &R, float &fH, float &fn,
                                           float &ft)
 {
+    // the interior flux is evaluated in every lane (no branch around it); a
+    // lane whose face is a boundary face replaces it below
+    const float bf = fmaxf(L.b, R.b);
+    FaceState fl, fr;
+    fl.Hs = fmaxf(0.0f, L.z - bf); fl.uLn = L.uLn; fl.uLt = L.uLt; fl.ut = L.ut;
+    fr.Hs = fmaxf(0.0f, R.z - bf); fr.uLn = R.uLn; fr.uLt = R.uLt; fr.ut = R.ut;
+    hll(P.g, fl, fr, fH, fn, ft);
+    if (k > 0 && k < n) return;
     fH = fn = ft = 0.0f;
-    if (k > 0 && k < n) {
-        const float bf = fmaxf(L.b, R.b);
-        FaceState fl, fr;
-        fl.Hs = fmaxf(0.0f, L.z - bf); fl.uLn = L.uLn; fl.uLt = L.uLt; fl.ut = L.ut;
-        fr.Hs = fmaxf(0.0f, R.z - bf); fr.uLn = R.uLn; fr.uLt = R.uLt; fr.ut = R.ut;
-        hll(P.g, fl, fr, fH, fn, ft);
-        return;
-    }
     const SideQ &C = k == n ? L : R;
     const float side = k == n ? 1.0f : -1.0f;
     FaceState s;
@@ -417,9 +420,11 @@ __device__ __forceinline__ float sed_face(const KPar &P, int k, int n, bool wall
                                           float JnL, float magL, float bL, float JnR, float magR,
                                           float bR)
 {
-    if (k > 0 && k < n) return bed_face_flux(P, JnL, magL, bL, JnR, magR, bR);
-    if (k == n) return wallHi ? 0.0f : fmaxf(JnL, 0.0f);
-    return wallLo ? 0.0f : fminf(JnR, 0.0f);
+    // all three forms are evaluated and the face's own is selected (no branches)
+    const float inner = bed_face_flux(P, JnL, magL, bL, JnR, magR, bR);
+    const float hi = wallHi ? 0.0f : fmaxf(JnL, 0.0f);
+    const float lo = wallLo ? 0.0f : fminf(JnR, 0.0f);
+    return (k > 0 && k < n) ? inner : (k == n ? hi : lo);
 }
 
 // The same from the J0 vectors of the two side cells, along direction dir.
