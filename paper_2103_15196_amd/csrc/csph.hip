@@ -1804,6 +1804,11 @@ struct sw_ctx {
     int ntx = 0, nty = 0;            // tile grid of the tiled kernels
     uint8_t *tflags = nullptr;       // act[2][ntiles], synced[ntiles], force[ntiles]
     hipStream_t cap = nullptr;       // private stream used only to capture graphs
+    // pinned host staging of one plane (hipHostMalloc, on first use): every
+    // transfer of a field between the host and the device goes through it,
+    // so the runtime never has to pin pageable user memory on the fly
+    float *stage = nullptr;
+    size_t stage_bytes = 0;
     hipGraphExec_t gexec = nullptr;  // two tiled steps (even k, then odd k)
     hipGraphExec_t gexec_long = nullptr;  // kLongPairs such pairs
     bool graph_ok = false;
@@ -1869,11 +1874,49 @@ StepArgs make_step_args(const sw_ctx *c, int fixed, double dt)
     return A;
 }
 
+// The staging holds at least `bytes` (and at least one plane) afterwards.
+int ensure_stage(sw_ctx *c, size_t bytes)
+{
+    bytes = std::max(bytes, c->plane * sizeof(float));
+    if (c->stage_bytes >= bytes) return SW_OK;
+    if (c->stage) (void)hipHostFree(c->stage);
+    c->stage = nullptr;
+    c->stage_bytes = 0;
+    HIPCHK(c, hipHostMalloc((void **)&c->stage, bytes, hipHostMallocDefault));
+    c->stage_bytes = bytes;
+    return SW_OK;
+}
+
+// Host bytes -> device, through the pinned staging (at most one plane).
+int stage_to_device(sw_ctx *c, void *dst, const void *src, size_t bytes)
+{
+    int rc = ensure_stage(c, bytes);
+    if (rc) return rc;
+    std::memcpy(c->stage, src, bytes);
+    HIPCHK(c, hipMemcpyAsync(dst, c->stage, bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SW_OK;
+}
+
+// Device bytes -> host (ordered after the work on the stream), through the staging.
+int stage_to_host(sw_ctx *c, void *dst, const void *src, size_t bytes)
+{
+    int rc = ensure_stage(c, bytes);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->stage, src, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::memcpy(dst, c->stage, bytes);
+    return SW_OK;
+}
+
 // Copy a user [ny][nx] array (host or device) into a pitched device plane.
 int upload_plane(sw_ctx *c, float *dst, const float *src, int ptr_kind)
 {
     if (ptr_kind == SW_PTR_HOST) {
-        HIPCHK(c, hipMemcpy2DAsync(dst, c->pitch * sizeof(float), src, c->nx * sizeof(float),
+        int rc = ensure_stage(c, 0);
+        if (rc) return rc;
+        std::memcpy(c->stage, src, (size_t)c->nx * c->ny * sizeof(float));
+        HIPCHK(c, hipMemcpy2DAsync(dst, c->pitch * sizeof(float), c->stage, c->nx * sizeof(float),
                                    c->nx * sizeof(float), c->ny, hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     } else if (ptr_kind == SW_PTR_DEVICE) {
@@ -1887,11 +1930,19 @@ int upload_plane(sw_ctx *c, float *dst, const float *src, int ptr_kind)
 
 int download_plane(sw_ctx *c, float *dst, const float *src, int ptr_kind)
 {
-    hipMemcpyKind kind = ptr_kind == SW_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     if (ptr_kind != SW_PTR_HOST && ptr_kind != SW_PTR_DEVICE)
         return fail(c, SW_ERR_ARG, "ptr_kind must be SW_PTR_HOST or SW_PTR_DEVICE");
-    HIPCHK(c, hipMemcpy2DAsync(dst, c->nx * sizeof(float), src, c->pitch * sizeof(float),
-                               c->nx * sizeof(float), c->ny, kind, c->stream));
+    if (ptr_kind == SW_PTR_DEVICE) {
+        HIPCHK(c, hipMemcpy2DAsync(dst, c->nx * sizeof(float), src, c->pitch * sizeof(float),
+                                   c->nx * sizeof(float), c->ny, hipMemcpyDeviceToDevice, c->stream));
+        return SW_OK;
+    }
+    int rc = ensure_stage(c, 0);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpy2DAsync(c->stage, c->nx * sizeof(float), src, c->pitch * sizeof(float),
+                               c->nx * sizeof(float), c->ny, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::memcpy(dst, c->stage, (size_t)c->nx * c->ny * sizeof(float));
     return SW_OK;
 }
 
@@ -1937,8 +1988,7 @@ int upload_force(sw_ctx *c)
     std::vector<uint8_t> f(ntiles(c), 0);
     for (int32_t q : c->forced_in) f[tile_of(c, q)] = 1;
     for (int32_t q : c->forced_qb) f[tile_of(c, q)] = 1;
-    HIPCHK(c, hipMemcpy(force_flags(c), f.data(), f.size(), hipMemcpyHostToDevice));
-    return SW_OK;
+    return stage_to_device(c, force_flags(c), f.data(), f.size());
 }
 
 void set_shape(sw_ctx *c, int shape)
@@ -2109,9 +2159,7 @@ int prepare(sw_ctx *c)
 
 int read_ctrl(sw_ctx *c, Ctrl *h)
 {
-    HIPCHK(c, hipMemcpyAsync(h, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    return SW_OK;
+    return stage_to_host(c, h, c->ctrl, sizeof(Ctrl));
 }
 
 // Index of the buffer holding the current state (the start of the failing
@@ -2288,7 +2336,7 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
     const int nplanes = 16;
     if ((e = hipMalloc(&c->buf, nplanes * c->plane * sizeof(float))) != hipSuccess)
         return bail(e, "hipMalloc(state)");
-    if ((e = hipMemset(c->buf, 0, nplanes * c->plane * sizeof(float))) != hipSuccess)
+    if ((e = hipMemsetAsync(c->buf, 0, nplanes * c->plane * sizeof(float), c->stream)) != hipSuccess)
         return bail(e, "hipMemset(state)");
     for (int s = 0; s < 2; ++s) {
         c->H[s] = c->buf + (4 * s + 0) * c->plane;
@@ -2306,11 +2354,11 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
     if (c->par.flags & SW_FLAG_UNFUSED) {  // face arrays of the unfused sequence only
         size_t nf = 4 * ((size_t)(c->nx + 1) * c->ny + (size_t)c->nx * (c->ny + 1));
         if ((e = hipMalloc(&c->faces, nf * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc(faces)");
-        if ((e = hipMemset(c->faces, 0, nf * sizeof(float))) != hipSuccess) return bail(e, "hipMemset(faces)");
+        if ((e = hipMemsetAsync(c->faces, 0, nf * sizeof(float), c->stream)) != hipSuccess) return bail(e, "hipMemset(faces)");
     }
     size_t nb = 4 * (size_t)(c->nx + c->ny);
     if ((e = hipMalloc(&c->bnd, nb * sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(bnd)");
-    if ((e = hipMemset(c->bnd, 0, nb * sizeof(double))) != hipSuccess) return bail(e, "hipMemset(bnd)");
+    if ((e = hipMemsetAsync(c->bnd, 0, nb * sizeof(double), c->stream)) != hipSuccess) return bail(e, "hipMemset(bnd)");
     c->sum_rows = std::max(1, (int)((c->ny + 1023) / 1024));
     c->nsum_blocks = (c->ny + c->sum_rows - 1) / c->sum_rows;
     if ((e = hipMalloc(&c->part, (3 * (size_t)c->nsum_blocks + 8) * sizeof(double))) != hipSuccess)
@@ -2324,14 +2372,18 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
     }
     set_shape(c, kDefaultShape);
     if ((e = hipMalloc(&c->tflags, 4 * c->max_tiles)) != hipSuccess) return bail(e, "hipMalloc(tiles)");
-    if ((e = hipMemset(c->tflags, 0, 4 * c->max_tiles)) != hipSuccess) return bail(e, "hipMemset(tiles)");
+    if ((e = hipMemsetAsync(c->tflags, 0, 4 * c->max_tiles, c->stream)) != hipSuccess) return bail(e, "hipMemset(tiles)");
     if ((e = hipMalloc(&c->tmax, 2 * c->max_tiles * sizeof(uint4))) != hipSuccess) return bail(e, "hipMalloc(tmax)");
     const size_t nsched = sched_layout(c->max_chunks, c->max_tiles).total;
     if ((e = hipMalloc(&c->sched, nsched * sizeof(int))) != hipSuccess) return bail(e, "hipMalloc(sched)");
-    if ((e = hipMemset(c->sched, 0, nsched * sizeof(int))) != hipSuccess) return bail(e, "hipMemset(sched)");
-    if ((e = hipMemset(c->tmax, 0, 2 * c->max_tiles * sizeof(uint4))) != hipSuccess) return bail(e, "hipMemset(tmax)");
+    if ((e = hipMemsetAsync(c->sched, 0, nsched * sizeof(int), c->stream)) != hipSuccess) return bail(e, "hipMemset(sched)");
+    if ((e = hipMemsetAsync(c->tmax, 0, 2 * c->max_tiles * sizeof(uint4), c->stream)) != hipSuccess) return bail(e, "hipMemset(tmax)");
     if ((e = hipMalloc(&c->ctrl, sizeof(Ctrl))) != hipSuccess) return bail(e, "hipMalloc(ctrl)");
-    if ((e = hipMemset(c->ctrl, 0, sizeof(Ctrl))) != hipSuccess) return bail(e, "hipMemset(ctrl)");
+    if ((e = hipMemsetAsync(c->ctrl, 0, sizeof(Ctrl), c->stream)) != hipSuccess) return bail(e, "hipMemset(ctrl)");
+    // every clear above is ordered on the context's stream (which may be a
+    // non-blocking stream that does not wait for the null stream); creation
+    // returns once they are done
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return bail(e, "hipStreamSynchronize");
     *out = c;
     return SW_OK;
 }
@@ -2353,6 +2405,7 @@ int sw_destroy(sw_ctx *c)
     (void)hipFree(c->tflags);
     (void)hipFree(c->tmax);
     (void)hipFree(c->sched);
+    if (c->stage) (void)hipHostFree(c->stage);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->gexec_long) (void)hipGraphExecDestroy(c->gexec_long);
     if (c->cap) (void)hipStreamDestroy(c->cap);
@@ -2415,13 +2468,21 @@ int sw_set_state(sw_ctx *c, const float *h, const float *hu, const float *hv, in
     // host-side check and clean-up of the initial state
     size_t n = (size_t)c->nx * c->ny;
     std::vector<float> H(n), U(n), V(n);
-    hipMemcpyKind kind = ptr_kind == SW_PTR_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
     if (ptr_kind != SW_PTR_HOST && ptr_kind != SW_PTR_DEVICE)
         return fail(c, SW_ERR_ARG, "ptr_kind must be SW_PTR_HOST or SW_PTR_DEVICE");
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(H.data(), h, n * sizeof(float), kind));
-    HIPCHK(c, hipMemcpy(U.data(), hu, n * sizeof(float), kind));
-    HIPCHK(c, hipMemcpy(V.data(), hv, n * sizeof(float), kind));
+    {
+        const float *src[3] = {h, hu, hv};
+        float *dst[3] = {H.data(), U.data(), V.data()};
+        for (int f = 0; f < 3; ++f) {
+            if (ptr_kind == SW_PTR_HOST) {
+                std::memcpy(dst[f], src[f], n * sizeof(float));
+            } else {
+                int rc = stage_to_host(c, dst[f], src[f], n * sizeof(float));
+                if (rc) return rc;
+            }
+        }
+    }
     for (size_t q = 0; q < n; ++q) {
         if (!(H[q] >= 0.0f) || !std::isfinite(H[q]) || !std::isfinite(U[q]) || !std::isfinite(V[q]))
             return fail(c, SW_ERR_ARG, "initial depth must be finite and >= 0, discharges finite");
@@ -2447,8 +2508,10 @@ int sw_set_state(sw_ctx *c, const float *h, const float *hu, const float *hv, in
     HIPCHK(c, hipMemsetAsync(c->bnd, 0, 4 * (size_t)(c->nx + c->ny) * sizeof(double), c->stream));
     Ctrl h0{};
     h0.t[0] = c->t0;
-    HIPCHK(c, hipMemcpyAsync(c->ctrl, &h0, sizeof(Ctrl), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    {
+        const int rc_ = stage_to_device(c, c->ctrl, &h0, sizeof(Ctrl));
+        if (rc_) return rc_;
+    }
     c->have_state = true;
     c->dirty = true;
     return SW_OK;
@@ -2482,7 +2545,8 @@ int sw_set_inflow(sw_ctx *c, const int32_t *cell_idx, const float *weight, int32
     for (int j = 0; j < c->ny; ++j)
         for (int i = 0; i < c->nx; ++i) w[(size_t)j * c->pitch + i] = (float)(acc[(size_t)j * c->nx + i] / dx2);
     if (!c->srcw) HIPCHK(c, hipMalloc(&c->srcw, c->plane * sizeof(float)));
-    HIPCHK(c, hipMemcpy(c->srcw, w.data(), c->plane * sizeof(float), hipMemcpyHostToDevice));
+    int rcw = stage_to_device(c, c->srcw, w.data(), c->plane * sizeof(float));
+    if (rcw) return rcw;
     c->has_inflow = 1;
     c->q_base = q_base; c->q_peak = q_peak; c->t_peak = t_peak; c->t_sigma = t_sigma;
     c->forced_in.assign(cell_idx, cell_idx + n);
@@ -2504,9 +2568,19 @@ int sw_set_sed_sources(sw_ctx *c, const float *qb_plus, const float *qb_minus, i
     }
     size_t n = (size_t)c->nx * c->ny;
     std::vector<float> p(n, 0.0f), m(n, 0.0f), d((size_t)c->plane, 0.0f);
-    hipMemcpyKind kind = ptr_kind == SW_PTR_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
-    if (qb_plus) HIPCHK(c, hipMemcpy(p.data(), qb_plus, n * sizeof(float), kind));
-    if (qb_minus) HIPCHK(c, hipMemcpy(m.data(), qb_minus, n * sizeof(float), kind));
+    if (ptr_kind != SW_PTR_HOST && ptr_kind != SW_PTR_DEVICE)
+        return fail(c, SW_ERR_ARG, "ptr_kind must be SW_PTR_HOST or SW_PTR_DEVICE");
+    for (int f = 0; f < 2; ++f) {
+        const float *src = f == 0 ? qb_plus : qb_minus;
+        float *dst = f == 0 ? p.data() : m.data();
+        if (!src) continue;
+        if (ptr_kind == SW_PTR_HOST) {
+            std::memcpy(dst, src, n * sizeof(float));
+        } else {
+            int rc = stage_to_host(c, dst, src, n * sizeof(float));
+            if (rc) return rc;
+        }
+    }
     double tot = 0.0;
     c->forced_qb.clear();
     for (int j = 0; j < c->ny; ++j)
@@ -2518,7 +2592,8 @@ int sw_set_sed_sources(sw_ctx *c, const float *qb_plus, const float *qb_minus, i
             if (v != 0.0f) c->forced_qb.push_back(j * c->nx + i);
         }
     if (!c->qb) HIPCHK(c, hipMalloc(&c->qb, c->plane * sizeof(float)));
-    HIPCHK(c, hipMemcpy(c->qb, d.data(), c->plane * sizeof(float), hipMemcpyHostToDevice));
+    int rcq = stage_to_device(c, c->qb, d.data(), c->plane * sizeof(float));
+    if (rcq) return rcq;
     c->qb_total = tot * c->grid.dx * c->grid.dx;
     c->dirty = true;
     return upload_force(c);
@@ -2531,8 +2606,10 @@ int sw_set_time(sw_ctx *c, double t, int64_t step)
     int rc = read_ctrl(c, &h);
     if (rc) return rc;
     h.t[c->k & 1] = t;
-    HIPCHK(c, hipMemcpyAsync(c->ctrl, &h, sizeof(Ctrl), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    {
+        const int rc_ = stage_to_device(c, c->ctrl, &h, sizeof(Ctrl));
+        if (rc_) return rc_;
+    }
     c->t0 = t;
     c->step0 = step - c->k;
     return SW_OK;
@@ -2555,8 +2632,10 @@ int sw_replace_state(sw_ctx *c, const float *h, const float *hu, const float *hv
     HIPCHK(c, hipMemsetAsync(c->bnd, 0, 4 * (size_t)(c->nx + c->ny) * sizeof(double), c->stream));
     Ctrl h0{};
     h0.t[0] = t;
-    HIPCHK(c, hipMemcpyAsync(c->ctrl, &h0, sizeof(Ctrl), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));  // h0 lives on this stack frame
+    {
+        const int rc_ = stage_to_device(c, c->ctrl, &h0, sizeof(Ctrl));
+        if (rc_) return rc_;
+    }
     c->t0 = t;
     c->step0 = step;
     c->have_state = true;
@@ -2659,7 +2738,10 @@ int sw_autotune(sw_ctx *c, int32_t nsteps, int32_t *tile_x, int32_t *tile_y)
         HIPCHK(c, hipMemcpyAsync(save ? keepb : c->bnd, save ? c->bnd : keepb, nb * sizeof(double),
                                  hipMemcpyDeviceToDevice, c->stream));
         if (!save) {
-            HIPCHK(c, hipMemcpyAsync(c->ctrl, &saved, sizeof(Ctrl), hipMemcpyHostToDevice, c->stream));
+            {
+                const int rc_ = stage_to_device(c, c->ctrl, &saved, sizeof(Ctrl));
+                if (rc_) return rc_;
+            }
             c->k = k0;
             c->dirty = true;
         }
@@ -2747,10 +2829,8 @@ int sw_get_sums(sw_ctx *c, sw_sums *out)
     HIPCHK(c, hipGetLastError());
     double s[5];
     std::vector<uint8_t> act(ntiles(c));
-    HIPCHK(c, hipMemcpyAsync(s, c->sums, sizeof(s), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(act.data(), act_flags(c, cur), act.size(), hipMemcpyDeviceToHost,
-                             c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if ((rc = stage_to_host(c, s, c->sums, sizeof(s)))) return rc;
+    if ((rc = stage_to_host(c, act.data(), act_flags(c, cur), act.size()))) return rc;
     int64_t nact = 0;
     for (size_t t = 0; t < act.size(); ++t) nact += act[t] ? 1 : 0;
     double dx2 = c->grid.dx * c->grid.dx;
@@ -2858,8 +2938,20 @@ int batch_build(swb_ctx *b)
     b->d_table = nullptr;
     BHIPCHK(b, hipMalloc(&b->d_insts, n * sizeof(Inst)));
     BHIPCHK(b, hipMalloc(&b->d_table, table.size() * sizeof(int)));
-    BHIPCHK(b, hipMemcpy(b->d_insts, insts.data(), n * sizeof(Inst), hipMemcpyHostToDevice));
-    BHIPCHK(b, hipMemcpy(b->d_table, table.data(), table.size() * sizeof(int), hipMemcpyHostToDevice));
+    {  // through a pinned temporary (no on-the-fly pinning of the host vectors)
+        const size_t bi = n * sizeof(Inst), bt = table.size() * sizeof(int);
+        char *tmp = nullptr;
+        BHIPCHK(b, hipHostMalloc((void **)&tmp, bi + bt, hipHostMallocDefault));
+        std::memcpy(tmp, insts.data(), bi);
+        std::memcpy(tmp + bi, table.data(), bt);
+        hipError_t e1 = hipMemcpyAsync(b->d_insts, tmp, bi, hipMemcpyHostToDevice, b->stream);
+        hipError_t e2 = hipMemcpyAsync(b->d_table, tmp + bi, bt, hipMemcpyHostToDevice, b->stream);
+        hipError_t e3 = hipStreamSynchronize(b->stream);
+        (void)hipHostFree(tmp);
+        BHIPCHK(b, e1);
+        BHIPCHK(b, e2);
+        BHIPCHK(b, e3);
+    }
     if (b->gexec_long) {
         (void)hipGraphExecDestroy(b->gexec_long);
         b->gexec_long = nullptr;

@@ -370,6 +370,10 @@ struct sws_net {
     // scratch (grown on demand)
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    // pinned host staging (hipHostMalloc, grown on demand): every transfer
+    // between user host memory and the device goes through it
+    void *hstage = nullptr;
+    size_t hstage_bytes = 0;
     std::string err;
 };
 
@@ -512,13 +516,50 @@ int forward_into(sws_net *n, const Scratch &s, int nimg, int nx, int ny)
     return SW_OK;
 }
 
+int ensure_hstage(sws_net *n, size_t bytes)
+{
+    if (n->hstage_bytes >= bytes) return SW_OK;
+    if (n->hstage) (void)hipHostFree(n->hstage);
+    n->hstage = nullptr;
+    n->hstage_bytes = 0;
+    SHIP(n, hipHostMalloc(&n->hstage, bytes, hipHostMallocDefault));
+    n->hstage_bytes = bytes;
+    return SW_OK;
+}
+
+// User memory (host or device) -> device, stream-ordered; a host source goes
+// through the pinned staging and is done when this returns.
 int copy_in(sws_net *n, void *dst, const void *src, size_t bytes, int ptr_kind)
 {
     if (ptr_kind != SW_PTR_HOST && ptr_kind != SW_PTR_DEVICE)
         return sfail(n, SW_ERR_ARG, "ptr_kind must be SW_PTR_HOST or SW_PTR_DEVICE");
-    SHIP(n, hipMemcpyAsync(dst, src, bytes,
-                           ptr_kind == SW_PTR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
-                           n->stream));
+    if (ptr_kind == SW_PTR_DEVICE) {
+        SHIP(n, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, n->stream));
+        return SW_OK;
+    }
+    int rc = ensure_hstage(n, bytes);
+    if (rc) return rc;
+    std::memcpy(n->hstage, src, bytes);
+    SHIP(n, hipMemcpyAsync(dst, n->hstage, bytes, hipMemcpyHostToDevice, n->stream));
+    SHIP(n, hipStreamSynchronize(n->stream));
+    return SW_OK;
+}
+
+// Device -> user memory (host or device), after the work on the stream; synchronises.
+int copy_out(sws_net *n, void *dst, const void *src, size_t bytes, int ptr_kind)
+{
+    if (ptr_kind != SW_PTR_HOST && ptr_kind != SW_PTR_DEVICE)
+        return sfail(n, SW_ERR_ARG, "ptr_kind must be SW_PTR_HOST or SW_PTR_DEVICE");
+    if (ptr_kind == SW_PTR_DEVICE) {
+        SHIP(n, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, n->stream));
+        SHIP(n, hipStreamSynchronize(n->stream));
+        return SW_OK;
+    }
+    int rc = ensure_hstage(n, bytes);
+    if (rc) return rc;
+    SHIP(n, hipMemcpyAsync(n->hstage, src, bytes, hipMemcpyDeviceToHost, n->stream));
+    SHIP(n, hipStreamSynchronize(n->stream));
+    std::memcpy(dst, n->hstage, bytes);
     return SW_OK;
 }
 
@@ -559,8 +600,10 @@ int sws_create(const int32_t *channels, int32_t nlayers, void *hip_stream, sws_n
     hipError_t e;
     for (float **q : {&n->p, &n->g, &n->m, &n->v}) {
         if ((e = hipMalloc(q, off * sizeof(float))) != hipSuccess) return bail(e);
-        if ((e = hipMemset(*q, 0, off * sizeof(float))) != hipSuccess) return bail(e);
+        if ((e = hipMemsetAsync(*q, 0, off * sizeof(float), n->stream)) != hipSuccess) return bail(e);
     }
+    // ordered on the net's stream (possibly non-blocking), done before returning
+    if ((e = hipStreamSynchronize(n->stream)) != hipSuccess) return bail(e);
     for (int l = 0; l < nlayers; ++l) {
         unsigned short *a = nullptr, *b = nullptr;
         if ((e = hipMalloc(&a, packed_len(n->fwd[l]) * 2)) != hipSuccess) return bail(e);
@@ -581,6 +624,7 @@ int sws_destroy(sws_net *n)
     for (auto *q : n->wpk) (void)hipFree(q);
     for (auto *q : n->wpk_t) (void)hipFree(q);
     (void)hipFree(n->scratch);
+    if (n->hstage) (void)hipHostFree(n->hstage);
     delete n;
     return SW_OK;
 }
@@ -608,11 +652,7 @@ int sws_get_params(sws_net *n, float *params, int ptr_kind)
     if (!n || !params) return SW_ERR_ARG;
     if (ptr_kind != SW_PTR_HOST && ptr_kind != SW_PTR_DEVICE)
         return sfail(n, SW_ERR_ARG, "ptr_kind must be SW_PTR_HOST or SW_PTR_DEVICE");
-    SHIP(n, hipMemcpyAsync(params, n->p, n->nparam * sizeof(float),
-                           ptr_kind == SW_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
-                           n->stream));
-    SHIP(n, hipStreamSynchronize(n->stream));
-    return SW_OK;
+    return copy_out(n, params, n->p, n->nparam * sizeof(float), ptr_kind);
 }
 
 int sws_set_scales(sws_net *n, const float in_scale[5], const float out_scale[4])
@@ -646,11 +686,7 @@ int sws_forward(sws_net *n, const float *x, float *y, int32_t nimg, int32_t nx, 
                        (long)nx * ny, nimg, s.act[0]);
     rc = forward_into(n, s, nimg, nx, ny);
     if (rc) return rc;
-    SHIP(n, hipMemcpyAsync(y, s.out, yout,
-                           ptr_kind == SW_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
-                           n->stream));
-    SHIP(n, hipStreamSynchronize(n->stream));
-    return SW_OK;
+    return copy_out(n, y, s.out, yout, ptr_kind);
 }
 
 }  // extern "C"
@@ -705,9 +741,8 @@ int compute_grads(sws_net *n, const float *x, const float *target, int32_t nimg,
     }
     if (loss) {
         std::vector<double> h(RED_GRID);
-        SHIP(n, hipMemcpyAsync(h.data(), s.red, RED_GRID * sizeof(double), hipMemcpyDeviceToHost,
-                               n->stream));
-        SHIP(n, hipStreamSynchronize(n->stream));
+        const int rc_ = copy_out(n, h.data(), s.red, RED_GRID * sizeof(double), SW_PTR_HOST);
+        if (rc_) return rc_;
         double sum = 0.0;
         for (double v : h) sum += v;
         *loss = sum / ((double)npix * 4);
@@ -725,11 +760,7 @@ int sws_grad(sws_net *n, const float *x, const float *target, int32_t nimg, int3
     if (!grad) return SW_ERR_ARG;
     int rc = compute_grads(n, x, target, nimg, nx, ny, loss, ptr_kind);
     if (rc) return rc;
-    SHIP(n, hipMemcpyAsync(grad, n->g, n->nparam * sizeof(float),
-                           ptr_kind == SW_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
-                           n->stream));
-    SHIP(n, hipStreamSynchronize(n->stream));
-    return SW_OK;
+    return copy_out(n, grad, n->g, n->nparam * sizeof(float), ptr_kind);
 }
 
 int sws_train_step(sws_net *n, const float *x, const float *target, int32_t nimg, int32_t nx,
@@ -781,9 +812,7 @@ int sws_advance(sws_net *n, sw_ctx *solver, int32_t k, double dt, double max_dri
                        os[2], os[3], f1, s.red);
     SHIP(n, hipGetLastError());
     std::vector<double> part(2 * RED_GRID);
-    SHIP(n, hipMemcpyAsync(part.data(), s.red, part.size() * sizeof(double), hipMemcpyDeviceToHost,
-                           n->stream));
-    SHIP(n, hipStreamSynchronize(n->stream));
+    if ((rc = copy_out(n, part.data(), s.red, part.size() * sizeof(double), SW_PTR_HOST))) return rc;
     double v0 = 0.0, v1 = 0.0;
     for (int b = 0; b < RED_GRID; ++b) {
         v0 += part[2 * b];
