@@ -166,11 +166,14 @@ int sw_advance(sw_ctx *ctx, int32_t nsteps);
  * SW_ERR_CFL on the device (as above). */
 int sw_advance_fixed_dt(sw_ctx *ctx, int32_t nsteps, double dt);
 
-/* Measurement aid: advance nsteps (Eq. 7 step) with one launch per kernel and
- * a HIP event recorded on the context's stream around each launch; on return
- * avg_ms[0] / avg_ms[1] hold the mean duration of the Lagrangian-stage and
- * Euler-stage kernels.  Same kernels and arithmetic as sw_advance (the tiled
- * path); synchronises.  SW_ERR_ARG on the unfused path. */
+/* Measurement aid: advance nsteps (Eq. 7 step) with one launch per kernel on
+ * the context's stream, timing the Lagrangian-stage and Euler-stage kernels;
+ * on return avg_ms[0] / avg_ms[1] hold their mean durations.  Strip shapes:
+ * each launch records its own start and end time stamps (hipExtLaunchKernel
+ * events, the kernel's execution as a kernel trace reports it); LDS tile
+ * shapes: HIP events recorded between the launches.  Same kernels and
+ * arithmetic as sw_advance (the tiled path); synchronises.  SW_ERR_ARG on the
+ * unfused path. */
 int sw_advance_profiled(sw_ctx *ctx, int32_t nsteps, double *avg_ms);
 
 /* Use tile shape tile_x x tile_y for later steps: 64x8, 64x4, 64x16 or 128x4

@@ -7,6 +7,7 @@
 // 256-byte line.  The state is double-buffered: step k reads buffer k&1 and
 // writes buffer (k+1)&1.  Global reductions (Eq. 7 maxima, volumes, boundary
 // balances) run in FP64 or as exact FP32 maxima; see the kernels below.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -2105,8 +2106,18 @@ bool cell_soil(const KPar &P) { return P.nM || P.d50 || P.psi || P.srcw || P.qb;
 
 // Strip shapes: the prepare pass runs one workgroup per tile; K3 builds the
 // work lists; the stage kernels run one wavefront per list entry.
+// A stage kernel launch; with events e0/e1 (measurement), the launch itself
+// records its start and end time stamps in them (hipExtLaunchKernelGGL).
+template <typename K>
+void launch_timed(K kern, dim3 g, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const Inst &I,
+                  int par)
+{
+    if (e0) hipExtLaunchKernelGGL(kern, g, dim3(NT), 0, s, e0, e1, 0, I, par);
+    else hipLaunchKernelGGL(kern, g, dim3(NT), 0, s, I, par);
+}
+
 template <int S>
-void launch_strip_t(Stage st, hipStream_t s, const Inst &I, int par)
+void launch_strip_t(Stage st, hipStream_t s, const Inst &I, int par, hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 gt(I.ntx, I.nty);
     const int gl = (I.ntx * I.nty + SWAVES - 1) / SWAVES;  // one wavefront per possible entry
@@ -2116,11 +2127,13 @@ void launch_strip_t(Stage st, hipStream_t s, const Inst &I, int par)
     if (st == kPrepare) hipLaunchKernelGGL((k_prepare_t<SX, S>), gt, dim3(NT), 0, s, I, par);
     else if (st == kDt) hipLaunchKernelGGL(k_dt_lists, dim3(I.nchunk), dim3(RT), 0, s, I, par);
     else if (st == kCount) hipLaunchKernelGGL(k_count_t, dim3(1), dim3(RT), 0, s, I, par, SX, S);
-    else if (st == kLagrange) hipLaunchKernelGGL(lag, dim3(gl), dim3(NT), 0, s, I, par);
-    else hipLaunchKernelGGL(eul, dim3(gl), dim3(NT), 0, s, I, par);
+    else if (st == kLagrange) launch_timed(lag, dim3(gl), s, e0, e1, I, par);
+    else launch_timed(eul, dim3(gl), s, e0, e1, I, par);
 }
 
-void launch_stage(int shape, Stage st, hipStream_t s, const Inst &I, int par)
+// e0/e1 (optional): time stamps of a Lagrangian or Euler launch on strips.
+void launch_stage(int shape, Stage st, hipStream_t s, const Inst &I, int par,
+                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     dim3 g(I.ntx, I.nty);
     switch (shape) {
@@ -2128,9 +2141,9 @@ void launch_stage(int shape, Stage st, hipStream_t s, const Inst &I, int par)
     case 1: launch_stage_t<64, 4>(st, s, I, par, g); break;
     case 2: launch_stage_t<64, 16>(st, s, I, par, g); break;
     case 3: launch_stage_t<128, 4>(st, s, I, par, g); break;
-    case 4: launch_strip_t<8>(st, s, I, par); break;
-    case 5: launch_strip_t<16>(st, s, I, par); break;
-    default: launch_strip_t<32>(st, s, I, par); break;
+    case 4: launch_strip_t<8>(st, s, I, par, e0, e1); break;
+    case 5: launch_strip_t<16>(st, s, I, par, e0, e1); break;
+    default: launch_strip_t<32>(st, s, I, par, e0, e1); break;
     }
 }
 
@@ -2666,16 +2679,26 @@ int sw_advance_profiled(sw_ctx *c, int32_t nsteps, double *avg_ms)
         if (rc) return rc;
     }
     Inst I = make_inst(c, make_step_args(c, 0, 0.0));
-    std::vector<hipEvent_t> ev(3 * (size_t)nsteps, nullptr);
+    // strips: each stage launch records its own start and end (the kernel's
+    // execution, as a kernel trace reports it); tile shapes: events between launches
+    const bool ext = is_strip(c->shape);
+    std::vector<hipEvent_t> ev(4 * (size_t)nsteps, nullptr);
     for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
     for (int32_t s = 0; s < nsteps; ++s) {
         int par = (int)(c->k & 1);
+        hipEvent_t *e = &ev[4 * (size_t)s];
         launch_stage(c->shape, kDt, c->stream, I, par);
-        HIPCHK(c, hipEventRecord(ev[3 * s], c->stream));
-        launch_stage(c->shape, kLagrange, c->stream, I, par);
-        HIPCHK(c, hipEventRecord(ev[3 * s + 1], c->stream));
-        launch_stage(c->shape, kEuler, c->stream, I, par);
-        HIPCHK(c, hipEventRecord(ev[3 * s + 2], c->stream));
+        if (ext) {
+            launch_stage(c->shape, kLagrange, c->stream, I, par, e[0], e[1]);
+            launch_stage(c->shape, kEuler, c->stream, I, par, e[2], e[3]);
+        } else {
+            HIPCHK(c, hipEventRecord(e[0], c->stream));
+            launch_stage(c->shape, kLagrange, c->stream, I, par);
+            HIPCHK(c, hipEventRecord(e[1], c->stream));
+            HIPCHK(c, hipEventRecord(e[2], c->stream));
+            launch_stage(c->shape, kEuler, c->stream, I, par);
+            HIPCHK(c, hipEventRecord(e[3], c->stream));
+        }
         launch_stage(c->shape, kCount, c->stream, I, par);
         HIPCHK(c, hipGetLastError());
         c->k++;
@@ -2684,8 +2707,8 @@ int sw_advance_profiled(sw_ctx *c, int32_t nsteps, double *avg_ms)
     double tl = 0.0, te = 0.0;
     for (int32_t s = 0; s < nsteps; ++s) {
         float a = 0.0f, b = 0.0f;
-        HIPCHK(c, hipEventElapsedTime(&a, ev[3 * s], ev[3 * s + 1]));
-        HIPCHK(c, hipEventElapsedTime(&b, ev[3 * s + 1], ev[3 * s + 2]));
+        HIPCHK(c, hipEventElapsedTime(&a, ev[4 * (size_t)s], ev[4 * (size_t)s + 1]));
+        HIPCHK(c, hipEventElapsedTime(&b, ev[4 * (size_t)s + 2], ev[4 * (size_t)s + 3]));
         tl += a;
         te += b;
     }
