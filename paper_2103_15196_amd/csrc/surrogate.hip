@@ -77,82 +77,177 @@ __global__ void k_pack(const float *__restrict__ W, Geo g, int flip, int wcin, i
 }
 
 // ---------------------------------------------------------------------------
-// Convolution on the matrix cores.  Wavefront job = 16 consecutive pixels of
-// one row of one image, all output channels.  The packed weights of the layer
-// are staged in LDS once per workgroup; jobs are taken grid-stride.
+// Convolution on the matrix cores.  A workgroup of CW = 8 wavefronts owns a
+// strip of TW = 64 output pixels of one image and marches down a segment of
+// rows, 8 output rows per step (one per wavefront, two wavefronts per SIMD).
+// Each step stages the 10 input rows they need (64 + 2 pixels, zero outside
+// the image) in LDS
+// with coalesced 16-byte loads; the layer's packed weights are staged once.
+// A wavefront computes its 64 pixels (4 M blocks of 16) x all output
+// channels (NB blocks of 16): per reduction chunk it reads 4 A fragments and
+// NB B fragments from LDS and issues 4 NB MFMAs, so every fragment read
+// feeds several MFMAs.  CS, the stored input channels, is 8 (KC = 3) for the
+// input layer and 48 (KC = 14) otherwise.
 // mode 0: bias + ReLU -> BF16 NHWC (out_c channels stored)
 // mode 1: bias, no activation -> FP32 planar [img][cout][ny][nx]
 // mode 2: input gradient: no bias, times (mask > 0) -> BF16 NHWC (mask: the
 //         BF16 activation the gradient flows into, mask_c channels per pixel)
 // ---------------------------------------------------------------------------
+constexpr int TW = 64;     // output pixels per tile row
+constexpr int CW = 8;      // wavefronts (output rows per step) of a convolution workgroup
+constexpr int CT = 64 * CW;
+constexpr int CSEG = 32;   // output rows per workgroup (a multiple of CW)
+
 template <int NB, int KC>
-__global__ void __launch_bounds__(NT) k_conv(const unsigned short *__restrict__ in, Geo g,
+__global__ void __launch_bounds__(CT) k_conv(const unsigned short *__restrict__ in, Geo g,
                                              const unsigned short *__restrict__ wpk,
                                              const float *__restrict__ bias, int mode,
                                              const unsigned short *__restrict__ mask, int mask_c,
                                              void *__restrict__ out, int out_c, int nimg, int nx,
                                              int ny)
 {
+    constexpr int CS = KC == 3 ? CIN0 : MAXW;
+    constexpr int PXU = CS * 2 / 16;            // uint4 per staged pixel
+    constexpr int ROWU = (TW + 2) * PXU;        // uint4 per staged row
+    constexpr int SROWS = CW + 2;               // staged rows per step
+    constexpr int SU = SROWS * ROWU;            // staged uint4 per step
+    constexpr int PER = (SU + CT - 1) / CT;     // staged uint4 per thread
+    constexpr int OU = TW * NB * 2;             // uint4 of one wave's BF16 output tile
+    constexpr int XU = SU > CW * OU ? SU : CW * OU;
     __shared__ uint4 sw[NB * KC * 64];
+    __shared__ uint4 sx[XU];  // staged input rows; then the waves' output tiles
     const uint4 *w4 = reinterpret_cast<const uint4 *>(wpk);
-    for (int q = threadIdx.x; q < NB * KC * 64; q += NT) sw[q] = w4[q];
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int xblocks = (nx + 15) / 16;
-    const long jobs = (long)nimg * ny * xblocks;
+    for (int q = threadIdx.x; q < NB * KC * 64; q += CT) sw[q] = w4[q];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = lane & 15, kg = lane >> 4;
-    for (long job = (long)blockIdx.x * NWAVE + (threadIdx.x >> 6); job < jobs;
-         job += (long)gridDim.x * NWAVE) {
-        const int xb = (int)(job % xblocks);
-        const long rowi = job / xblocks;
-        const int y = (int)(rowi % ny), img = (int)(rowi / ny);
-        const int x0 = xb * 16;
-        floatx4 acc[NB];
+    const int x0 = blockIdx.x * TW, img = blockIdx.z;
+    const int ys = blockIdx.y * CSEG, ye = min(ny, ys + CSEG);
+    const unsigned short *base = in + (long)img * ny * nx * CS;
+    // the input rows of the next step are loaded into registers while the
+    // current step computes
+    uint4 pre[PER];
+    auto fetch = [&](int y0) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc[b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        const unsigned short *base = in + (long)img * ny * nx * g.cs;
-#pragma unroll 2
+        for (int j = 0; j < PER; ++j) {
+            const int q = threadIdx.x + j * CT;
+            const int r = q / ROWU, rem = q - r * ROWU;
+            const int px = rem / PXU, part = rem - px * PXU;
+            const int yy = y0 - 1 + r, xx = x0 - 1 + px;
+            pre[j] = make_uint4(0u, 0u, 0u, 0u);
+            if (q < SU && (unsigned)yy < (unsigned)ny && (unsigned)xx < (unsigned)nx)
+                pre[j] = *reinterpret_cast<const uint4 *>(base + ((long)yy * nx + xx) * CS + part * 8);
+        }
+    };
+    // BF16 NHWC outputs of exactly NB * 16 channels leave through LDS as
+    // whole 16-byte pixel chunks
+    const bool tile_out = mode != 1 && out_c == NB * 16 && (mode == 0 || mask_c == out_c);
+    fetch(ys);
+    for (int y0 = ys; y0 < ye; y0 += CW) {
+        __syncthreads();  // the previous step is done with sx
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int q = threadIdx.x + j * CT;
+            if (q < SU) sx[q] = pre[j];
+        }
+        __syncthreads();
+        if (y0 + CW < ye) fetch(y0 + CW);
+        floatx4 acc[4][NB];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[mb][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
+            // the padding rows k >= 9 CS of the packed weights are zero, so a
+            // lane past the last tap may read any finite activation: it reads
+            // tap 8 (no branch around the fragment reads)
             const int k = 32 * kc + 8 * kg;
-            const int tap = k / g.cs, c = k % g.cs;
-            uint4 a = make_uint4(0u, 0u, 0u, 0u);
-            if (tap < 9) {
-                const int yy = y + tap / 3 - 1, xx = x0 + m + tap % 3 - 1;
-                if ((unsigned)yy < (unsigned)ny && (unsigned)xx < (unsigned)nx)
-                    a = *reinterpret_cast<const uint4 *>(base + ((long)yy * nx + xx) * g.cs + c);
-            }
-            bf16x8 av;
-            __builtin_memcpy(&av, &a, 16);
+            const int tap = min(k / CS, 8), c = k - (k / CS) * CS;
+            const int ty = tap / 3, tx = tap - 3 * ty;
+            bf16x8 bv[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const uint4 wv = sw[(b * KC + kc) * 64 + lane];
-                bf16x8 bv;
-                __builtin_memcpy(&bv, &wv, 16);
-                acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[b], 0, 0, 0);
+                const uint4 wv4 = sw[(b * KC + kc) * 64 + lane];
+                __builtin_memcpy(&bv[b], &wv4, 16);
+            }
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) {
+                const uint4 a = sx[(wv + ty) * ROWU + (mb * 16 + m + tx) * PXU + c / 8];
+                bf16x8 av;
+                __builtin_memcpy(&av, &a, 16);
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    acc[mb][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[b], acc[mb][b], 0, 0, 0);
             }
         }
-        // lane holds output pixels x0 + 4 kg + i (i = 0..3), channel 16 b + m
+        // lane holds, in M block mb, output pixels x0 + 16 mb + 4 kg + i
+        // (i = 0..3) of row y, channel 16 b + m
+        const int y = y0 + wv;
+        if (tile_out) {
+            __syncthreads();  // every wave is done reading the staged rows
+            unsigned short *so = reinterpret_cast<unsigned short *>(sx + wv * OU);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int n = 16 * b + m;
+            for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int xx = x0 + 4 * kg + i;
-                if (xx >= nx || n >= g.cout) continue;
-                const long pix = ((long)img * ny + y) * nx + xx;
-                float v = acc[b][i];
-                if (mode == 0) {
-                    v = fmaxf(v + bias[n], 0.0f);
-                    static_cast<unsigned short *>(out)[pix * out_c + n] = bf16_bits(v);
-                } else if (mode == 1) {
-                    v += bias[n];
-                    static_cast<float *>(out)[(((long)img * g.cout + n) * ny + y) * nx + xx] = v;
-                } else {
-                    if (!(bf16_float(mask[pix * mask_c + n]) > 0.0f)) v = 0.0f;
-                    static_cast<unsigned short *>(out)[pix * out_c + n] = bf16_bits(v);
+                for (int b = 0; b < NB; ++b) {
+                    const int n = 16 * b + m;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        float v = acc[mb][b][i];
+                        if (mode == 0) v = n < g.cout ? fmaxf(v + bias[min(n, g.cout - 1)], 0.0f) : 0.0f;
+                        so[(16 * mb + 4 * kg + i) * (NB * 16) + n] = bf16_bits(v);
+                    }
+                }
+            __syncthreads();
+            if (y < ye) {
+                unsigned short *ob = static_cast<unsigned short *>(out);
+                for (int q = lane; q < OU; q += 64) {
+                    const int px = q / (NB * 2), part = q - px * (NB * 2);
+                    const int xx = x0 + px;
+                    if (xx >= nx) continue;
+                    const long pix = ((long)img * ny + y) * nx + xx;
+                    uint4 v = sx[wv * OU + q];
+                    if (mode == 2) {  // the gradient flows only where the activation is > 0
+                        const uint4 mk = *reinterpret_cast<const uint4 *>(mask + pix * mask_c + part * 8);
+                        unsigned vv[4] = {v.x, v.y, v.z, v.w};
+                        const unsigned mm[4] = {mk.x, mk.y, mk.z, mk.w};
+#pragma unroll
+                        for (int h = 0; h < 4; ++h) {
+                            const bool lo = bf16_float((unsigned short)(mm[h] & 0xffffu)) > 0.0f;
+                            const bool hi = bf16_float((unsigned short)(mm[h] >> 16)) > 0.0f;
+                            vv[h] &= (lo ? 0x0000ffffu : 0u) | (hi ? 0xffff0000u : 0u);
+                        }
+                        v = make_uint4(vv[0], vv[1], vv[2], vv[3]);
+                    }
+                    *reinterpret_cast<uint4 *>(ob + pix * out_c + part * 8) = v;
                 }
             }
+            continue;
         }
+        if (y >= ye) continue;
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int n = 16 * b + m;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int xx = x0 + 16 * mb + 4 * kg + i;
+                    if (xx >= nx || n >= g.cout) continue;
+                    const long pix = ((long)img * ny + y) * nx + xx;
+                    float v = acc[mb][b][i];
+                    if (mode == 0) {
+                        v = fmaxf(v + bias[n], 0.0f);
+                        static_cast<unsigned short *>(out)[pix * out_c + n] = bf16_bits(v);
+                    } else if (mode == 1) {
+                        v += bias[n];
+                        static_cast<float *>(out)[(((long)img * g.cout + n) * ny + y) * nx + xx] = v;
+                    } else {
+                        if (!(bf16_float(mask[pix * mask_c + n]) > 0.0f)) v = 0.0f;
+                        static_cast<unsigned short *>(out)[pix * out_c + n] = bf16_bits(v);
+                    }
+                }
+            }
     }
 }
 
@@ -410,22 +505,23 @@ size_t packed_len(const Geo &g) { return (size_t)g.nb * g.kc * 64 * 8; }
 int grid_for(long n) { return (int)std::min<long>(4096, std::max<long>(1, (n + NT - 1) / NT)); }
 
 template <int NB, int KC>
-void conv_t(hipStream_t s, int grid, const unsigned short *in, Geo g, const unsigned short *w,
+void conv_t(hipStream_t s, dim3 grid, const unsigned short *in, Geo g, const unsigned short *w,
             const float *bias, int mode, const unsigned short *mask, int mask_c, void *out,
             int out_c, int nimg, int nx, int ny)
 {
-    hipLaunchKernelGGL((k_conv<NB, KC>), dim3(grid), dim3(NT), 0, s, in, g, w, bias, mode, mask,
+    hipLaunchKernelGGL((k_conv<NB, KC>), grid, dim3(CT), 0, s, in, g, w, bias, mode, mask,
                        mask_c, out, out_c, nimg, nx, ny);
 }
 
 // Dispatch on (output blocks, reduction chunks): KC = 3 for the 8-channel
-// input, 14 for 48 stored channels.
+// input, 14 for 48 stored channels.  One workgroup per (64-pixel strip,
+// CSEG-row segment, image).
 int conv(sws_net *n, const unsigned short *in, const Geo &g, const unsigned short *w,
          const float *bias, int mode, const unsigned short *mask, int mask_c, void *out, int out_c,
          int nimg, int nx, int ny)
 {
-    const long jobs = (long)nimg * ny * ((nx + 15) / 16);
-    const int grid = (int)std::min<long>(2048, std::max<long>(1, (jobs + NWAVE - 1) / NWAVE));
+    if (g.cs != (g.kc == 3 ? CIN0 : MAXW)) return sfail(n, SW_ERR_ARG, "unsupported layer shape");
+    const dim3 grid((nx + TW - 1) / TW, (ny + CSEG - 1) / CSEG, nimg);
     hipStream_t s = n->stream;
     if (g.kc == 3 && g.nb == 3) conv_t<3, 3>(s, grid, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
     else if (g.kc == 3 && g.nb == 1) conv_t<1, 3>(s, grid, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
