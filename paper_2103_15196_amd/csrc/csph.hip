@@ -1608,10 +1608,29 @@ __device__ __forceinline__ int list_locate(const int *cnt, int c0, int nb, int w
     return base;
 }
 
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup b to XCD b % 8).
+// Of the nwg workgroups a list needs, XCD x instead takes one contiguous run
+// of the list, so tiles that are neighbours along y (and the halo rows they
+// both read) mostly meet in the same L2.  A bijection of [0, nwg): XCD x
+// holds q + (x < r) of them (nwg = 8 q + r), starting at x q + min(x, r).
+__device__ __forceinline__ int xcd_block(int b, int nwg)
+{
+    const int q = nwg >> 3, r = nwg & 7, x = b & 7, k = b >> 3;
+    return x * q + min(x, r) + k;
+}
+// Entry of wavefront wave of workgroup b for a list of n entries.
+__device__ __forceinline__ int xcd_entry(int b, int wave, int n)
+{
+    const int nwg = (n + SWAVES - 1) / SWAVES;
+    return b < nwg ? xcd_block(b, nwg) * SWAVES + wave : b * SWAVES + wave;
+}
+
 // The entry index and the tile it names are the same in every lane of the
 // wavefront; readfirstlane states that, so tile coordinates and the row
 // ranges derived from them live in scalar registers and branch as scalars.
-template <int S, bool CS>
+// XP: w is the raw index blockIdx.x * SWAVES + wave, to be spread over the
+// XCDs once the list length is known (single grids); else the entry itself.
+template <int S, bool CS, bool XP>
 __device__ void lagrange_listed(const Inst &I, int par, int w)
 {
     w = __builtin_amdgcn_readfirstlane(w);
@@ -1626,6 +1645,10 @@ __device__ void lagrange_listed(const Inst &I, int par, int w)
     const int ce0 = I.hgs && publisher && lane < nb ? I.cnt_e[lane] : 0;
     uint4 v = lane < nb ? I.part[lane] : make_uint4(0u, 0u, 0u, 0u);
     int n = I.ntx * I.nty, seg = 0, start = 0;
+    if (XP) {  // the raw index 0 stays entry 0 (the publisher)
+        if (I.hgs) n = list_locate(I.cnt_l, cl0, nb, 0, seg, start, nullptr);
+        w = __builtin_amdgcn_readfirstlane(xcd_entry(w / SWAVES, w % SWAVES, n));
+    }
     if (I.hgs) n = list_locate(I.cnt_l, cl0, nb, w, seg, start, nullptr);
     if (w >= n && !publisher) return;
     // the Eq. 7 step from the segment maxima (K3 proper)
@@ -1648,7 +1671,7 @@ __device__ void lagrange_listed(const Inst &I, int par, int w)
     const int t = __builtin_amdgcn_readfirstlane(I.hgs ? I.lag[seg * I.chunk + (w - start)] : w);
     lagrange_strip<S, CS>(I, par, t % I.ntx, t / I.ntx, (float)e.dt);
 }
-template <int S, bool CS>
+template <int S, bool CS, bool XP>
 __device__ void euler_listed(const Inst &I, int par, int w)
 {
     // error flag, list length and the first 64 start positions in one round trip
@@ -1657,6 +1680,7 @@ __device__ void euler_listed(const Inst &I, int par, int w)
     const int err = I.ctrl->err;
     const int n = I.hgs ? I.totals[1] : I.ntx * I.nty;
     const int p0 = I.hgs && lane < I.nchunk ? I.pre_e[lane] : 0;
+    if (XP) w = __builtin_amdgcn_readfirstlane(xcd_entry(w / SWAVES, w % SWAVES, n));
     if (err || w >= n) return;
     const int e = __builtin_amdgcn_readfirstlane(
         I.hgs ? list_entry(I.eul, I.pre_e, p0, I.nchunk, I.chunk, w) : w);
@@ -1668,12 +1692,12 @@ __device__ void euler_listed(const Inst &I, int par, int w)
 template <int S, bool CS>
 __global__ void __launch_bounds__(NT) k_lagrange_sl(Inst I, int par)
 {
-    lagrange_listed<S, CS>(I, par, blockIdx.x * SWAVES + (threadIdx.x >> 6));
+    lagrange_listed<S, CS, true>(I, par, blockIdx.x * SWAVES + (threadIdx.x >> 6));
 }
 template <int S, bool CS>
 __global__ void __launch_bounds__(NT) k_euler_sl(Inst I, int par)
 {
-    euler_listed<S, CS>(I, par, blockIdx.x * SWAVES + (threadIdx.x >> 6));
+    euler_listed<S, CS, true>(I, par, blockIdx.x * SWAVES + (threadIdx.x >> 6));
 }
 
 // Ensemble: workgroup b runs waves SWAVES table[2b+1] + w of member table[2b].
@@ -1682,14 +1706,14 @@ __global__ void __launch_bounds__(NT) k_lagrange_slb(const Inst *__restrict__ in
                                                      const int *__restrict__ table, int par)
 {
     const int *t = table + 2 * blockIdx.x;
-    lagrange_listed<S, CS>(insts[t[0]], par, t[1] * SWAVES + (threadIdx.x >> 6));
+    lagrange_listed<S, CS, false>(insts[t[0]], par, t[1] * SWAVES + (threadIdx.x >> 6));
 }
 template <int S, bool CS>
 __global__ void __launch_bounds__(NT) k_euler_slb(const Inst *__restrict__ insts,
                                                   const int *__restrict__ table, int par)
 {
     const int *t = table + 2 * blockIdx.x;
-    euler_listed<S, CS>(insts[t[0]], par, t[1] * SWAVES + (threadIdx.x >> 6));
+    euler_listed<S, CS, false>(insts[t[0]], par, t[1] * SWAVES + (threadIdx.x >> 6));
 }
 
 // Tile shapes the autotuner chooses from: TX x TY cells per 256-thread
