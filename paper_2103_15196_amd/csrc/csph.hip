@@ -615,7 +615,7 @@ __device__ void reduce_dt(Ctrl *ctrl, int par, const StepArgs &A, const uint4 *_
 
 // Initial maxima (ring par) and wet-tile flags of a state set from the host.
 template <int TX, int TY>
-__device__ void prepare_tile(const Inst &I, int par, int bx, int by)
+__device__ __forceinline__ void prepare_tile(const Inst &I, int par, int bx, int by)
 {
     __shared__ int s_any;
     const KPar &P = I.P;
@@ -764,7 +764,7 @@ __device__ __forceinline__ void boundary_balances(const KPar &P, double *bnd, do
 
 // Lagrangian stage on a tile (K2, K4, K5, K6) with the Eq. 7 step (K3).
 template <int TX, int TY>
-__device__ void lagrange_tile(const Inst &I, int par, int bx, int by)
+__device__ __forceinline__ void lagrange_tile(const Inst &I, int par, int bx, int by)
 {
     constexpr int LW = TX + 4, LHh = TY + 4;  // state tile with a 2-cell halo
     __shared__ float sH[LHh][LW], sb[LHh][LW], sqx[LHh][LW], sqy[LHh][LW], su[LHh][LW],
@@ -826,7 +826,7 @@ __device__ void lagrange_tile(const Inst &I, int par, int bx, int by)
 // Euler stage on a tile (K7 + limiter + K8) with the epilogue reductions
 // (Eq. 7 maxima and wet flags of the new state, FP64 boundary balances).
 template <int TX, int TY>
-__device__ void euler_tile(const Inst &I, int par, int bx, int by)
+__device__ __forceinline__ void euler_tile(const Inst &I, int par, int bx, int by)
 {
     constexpr int EW = TX + 6, EHt = TY + 6;  // remap inputs with a 3-cell halo
     constexpr int RW = TX + 2, RH = TY + 2;   // the tile plus a 1-cell ring
@@ -1073,7 +1073,7 @@ struct BedCell {
 
 // Lagrangian stage on a strip tile (CS: per-cell Manning coefficient).
 template <int S, bool CS>
-__device__ void lagrange_strip(const Inst &I, int par, int bx, int by, float dt)
+__device__ __forceinline__ void lagrange_strip(const Inst &I, int par, int bx, int by, float dt)
 {
     const KPar &P = I.P;
     const int tile = bx + by * I.ntx;
@@ -1157,7 +1157,7 @@ __device__ void lagrange_strip(const Inst &I, int par, int bx, int by, float dt)
 // reductions (Eq. 7 maxima and wet flag of the new state, boundary balances).
 // CS: some soil or source field is a per-cell plane (else all are scalars).
 template <int S, bool CS>
-__device__ void euler_strip(const Inst &I, int par, int bx, int by)
+__device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int by)
 {
     const KPar &P = I.P;
     Ctrl *ctrl = I.ctrl;
@@ -1631,7 +1631,7 @@ __device__ __forceinline__ int xcd_entry(int b, int wave, int n)
 // XP: w is the raw index blockIdx.x * SWAVES + wave, to be spread over the
 // XCDs once the list length is known (single grids); else the entry itself.
 template <int S, bool CS, bool XP>
-__device__ void lagrange_listed(const Inst &I, int par, int w)
+__device__ __forceinline__ void lagrange_listed(const Inst &I, int par, int w)
 {
     w = __builtin_amdgcn_readfirstlane(w);
     Ctrl *ctrl = I.ctrl;
@@ -1672,7 +1672,7 @@ __device__ void lagrange_listed(const Inst &I, int par, int w)
     lagrange_strip<S, CS>(I, par, t % I.ntx, t / I.ntx, (float)e.dt);
 }
 template <int S, bool CS, bool XP>
-__device__ void euler_listed(const Inst &I, int par, int w)
+__device__ __forceinline__ void euler_listed(const Inst &I, int par, int w)
 {
     // error flag, list length and the first 64 start positions in one round trip
     w = __builtin_amdgcn_readfirstlane(w);
