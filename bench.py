@@ -91,12 +91,12 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0: auto, ~10-30 s)")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a 512 MiB device-to-device copy (counter calibration)")
+                    help="also run a 1 GiB in / 1 GiB out torch mul (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the row-strip sharding is a design note only).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the solver has no multi-GPU path "
+              "(row-strip sharding is described in the design notes only).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
