@@ -55,12 +55,27 @@ def test_gpu_surrogate_forward_matches_oracle(chans):
     net.close()
 
 
-@pytest.mark.parametrize("chans", [(5, 16, 11, 4), DESIGN])
-def test_gpu_surrogate_gradients_match_oracle(chans):
+def test_gpu_surrogate_forward_spans_several_tiles():
+    """An image wider than two 64-pixel strips and taller than two 32-row
+    segments, with ragged tails in both directions."""
+    net, Ws, bs = _net(DESIGN, seed=12)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((1, 5, 71, 150)).astype(np.float32)
+    y = net.forward(x)
+    ref, _ = S.forward(x[0].astype(np.float64), Ws, bs, bf16=True)
+    err = np.abs(y[0] - ref).max()
+    say(f"forward 71x150: max |gpu - oracle| {err:.3e}, max |oracle| {np.abs(ref).max():.3e}")
+    assert err <= 5e-3 * np.abs(ref).max() + 1e-4
+    net.close()
+
+
+@pytest.mark.parametrize("chans,hw", [((5, 16, 11, 4), (19, 41)), (DESIGN, (19, 41)),
+                                     (DESIGN, (45, 133))])
+def test_gpu_surrogate_gradients_match_oracle(chans, hw):
     net, Ws, bs = _net(chans, seed=20)
     rng = np.random.default_rng(4)
-    x = rng.standard_normal((2, 5, 19, 41)).astype(np.float32)
-    t = rng.standard_normal((2, 4, 19, 41)).astype(np.float32)
+    x = rng.standard_normal((2, 5) + hw).astype(np.float32)
+    t = rng.standard_normal((2, 4) + hw).astype(np.float32)
     g, loss = net.grad(x, t)
     gW = [np.zeros_like(w) for w in Ws]
     gb = [np.zeros_like(b) for b in bs]
@@ -81,7 +96,7 @@ def test_gpu_surrogate_gradients_match_oracle(chans):
         n = w.size + b.size
         err = np.abs(g[o:o + n] - ref[o:o + n]).max()
         scale = np.abs(ref[o:o + n]).max()
-        say(f"grad {chans} layer {l}: max err {err:.3e} of max {scale:.3e}")
+        say(f"grad {chans} {hw} layer {l}: max err {err:.3e} of max {scale:.3e}")
         assert err <= 3e-2 * scale + 1e-7
         # the direction of the layer gradient agrees closely
         cos = float(np.dot(g[o:o + n], ref[o:o + n]) /
