@@ -1004,13 +1004,15 @@ constexpr int SWAVES = NT / 64;  // strip tiles per workgroup (stacked along y)
 
 // The value lane l-1 (lane_prev) or l+1 (lane_next) holds; 0 in the lane that
 // has no such neighbour.  Called only where all 64 lanes are active.
+// bound_ctrl set: the lane without a source reads 0, so no register has to
+// be cleared before the move (lane layout checked on the GPU).
 __device__ __forceinline__ float lane_prev(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float lane_next(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ CellQ q_prev(const CellQ &q)
 {
@@ -1215,21 +1217,18 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
     unsigned mv = 0, ms = 0, mD = 0, bad = 0;
     bool wet = false;
     auto step = [&](int r, const Row &in) {
-        // the cells K8 updates in this step (row r-3), loaded again (cache hits)
+        // the cells K8 updates in this step (row r-3), loaded again (cache
+        // hits); loaded in every step from a clamped row (used only when upd)
         const int ju = r - 3;
         const bool upd = ju >= y0 && ju < jend;
-        float uh = 0, uqx = 0, uqy = 0, ub = 0, uLx = 0, uLy = 0;
-        float upsi = P.psi_s, usrc = 0, uqb = 0, unM = P.nM_s, ud50 = P.d50_s;
-        const unsigned uo = (unsigned)(ju * pitch + ci) * 4u;
-        if (upd) {
-            uh = at(SH, uo); uqx = at(Sqx, uo); uqy = at(Sqy, uo); ub = at(Sb, uo);
-            uLx = at(QLx, uo); uLy = at(QLy, uo);
-            upsi = soil_at(P.psi, P.psi_s, uo);
-            usrc = soil_at(P.srcw, 0.0f, uo);
-            uqb = soil_at(P.qb, 0.0f, uo);
-            unM = soil_at(P.nM, P.nM_s, uo);
-            ud50 = soil_at(P.d50, P.d50_s, uo);
-        }
+        const unsigned uo = (unsigned)(min(max(ju, 0), ny - 1) * pitch + ci) * 4u;
+        const float uh = at(SH, uo), uqx = at(Sqx, uo), uqy = at(Sqy, uo), ub = at(Sb, uo);
+        const float uLx = at(QLx, uo), uLy = at(QLy, uo);
+        const float upsi = soil_at(P.psi, P.psi_s, uo);
+        const float usrc = soil_at(P.srcw, 0.0f, uo);
+        const float uqb = soil_at(P.qb, 0.0f, uo);
+        const float unM = soil_at(P.nM, P.nM_s, uo);
+        const float ud50 = soil_at(P.d50, P.d50_s, uo);
         const bool iny = (unsigned)r < (unsigned)ny;
         {  // remap inputs of row r (ghost cells beyond the domain edge)
             const bool yghost = r == -1 || r == ny;
