@@ -1218,10 +1218,11 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
     bool wet = false;
     auto step = [&](int r, const Row &in) {
         // the cells K8 updates in this step (row r-3), loaded again (cache
-        // hits); loaded in every step from a clamped row (used only when upd)
+        // hits); loaded in every step, from the nearest row of the tile when
+        // r-3 lies outside it (then unused), so no row outside the march is read
         const int ju = r - 3;
         const bool upd = ju >= y0 && ju < jend;
-        const unsigned uo = (unsigned)(min(max(ju, 0), ny - 1) * pitch + ci) * 4u;
+        const unsigned uo = (unsigned)(min(max(ju, y0), jend - 1) * pitch + ci) * 4u;
         const float uh = at(SH, uo), uqx = at(Sqx, uo), uqy = at(Sqy, uo), ub = at(Sb, uo);
         const float uLx = at(QLx, uo), uLy = at(QLy, uo);
         const float upsi = soil_at(P.psi, P.psi_s, uo);
