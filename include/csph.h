@@ -16,7 +16,9 @@
  *    crosses this boundary.
  *  - Fields are row-major [ny][nx] float32 arrays, x fastest, SI units
  *    (depth h in m, unit discharges hu, hv in m^2/s, bed elevation b in m).
- *  - ptr_kind SW_PTR_HOST: the pointer is host memory, copied synchronously.
+ *  - ptr_kind SW_PTR_HOST: the pointer is host memory, copied synchronously
+ *    and in the context's stream order, through a pinned staging buffer the
+ *    library owns (pageable user memory is never handed to a device copy).
  *    SW_PTR_DEVICE: the pointer is device memory on the context's GPU (for
  *    instance a torch tensor's data_ptr()); the copy is ordered on the
  *    context's stream.  The caller keeps ownership of its buffers; the library

@@ -14,7 +14,8 @@
  * Errors: the SW_* codes of csph.h (SW_ERR_ARG for bad arguments, SW_ERR_HIP
  * for a failed HIP call); sws_last_error gives the text.  All calls are
  * stream-ordered on the stream given at creation; the ones returning values
- * to the host synchronise it.
+ * to the host synchronise it.  Host arrays (SW_PTR_HOST) pass through a
+ * pinned staging buffer the net owns and are copied synchronously.
  */
 #ifndef CSPH_SURROGATE_H
 #define CSPH_SURROGATE_H
