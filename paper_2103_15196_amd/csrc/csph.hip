@@ -1164,7 +1164,7 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
     const KPar &P = I.P;
     Ctrl *ctrl = I.ctrl;
     if (ctrl->err) return;
-    const int ntx = I.ntx, nty = I.nty, tile = bx + by * ntx;
+    const int ntx = I.ntx, tile = bx + by * ntx;
     const int lane = threadIdx.x & 63;
     const int nx = P.nx, ny = P.ny, pitch = P.pitch;
     const int x0 = bx * SX, y0 = by * S;
@@ -1784,14 +1784,6 @@ __global__ void __launch_bounds__(SUM_THREADS) k_sums2(const double *__restrict_
         for (int k = 1; k < SUM_THREADS / 64; ++k) { a += sh[0][k]; b += sh[1][k]; c += sh[2][k]; d += sh[3][k]; e += sh[4][k]; }
         out[0] = a; out[1] = b; out[2] = c; out[3] = d; out[4] = e;
     }
-}
-
-// Copy a row-major [ny][nx] plane into a pitched plane (or back).
-__global__ void k_pitch(const float *__restrict__ src, int sp, float *__restrict__ dst, int dp,
-                        int nx, int ny, int zero_mode)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
-    if (i < nx && j < ny) dst[j * dp + i] = src ? src[j * sp + i] : 0.0f;
 }
 
 }  // namespace

@@ -56,7 +56,7 @@ struct Geo {
 // per-lane fragment order [nb][kc][lane][8].  flip: the weights of the
 // transposed convolution (input gradient), Wf[n][c][ky][kx] = W[c][n][2-ky][2-kx].
 // ---------------------------------------------------------------------------
-__global__ void k_pack(const float *__restrict__ W, Geo g, int flip, int wcin, int wcout,
+__global__ void k_pack(const float *__restrict__ W, Geo g, int flip, int wcin,
                        unsigned short *__restrict__ out)
 {
     const int total = g.nb * g.kc * 64 * 8;
@@ -103,8 +103,7 @@ __global__ void __launch_bounds__(CT) k_conv(const unsigned short *__restrict__ 
                                              const unsigned short *__restrict__ wpk,
                                              const float *__restrict__ bias, int mode,
                                              const unsigned short *__restrict__ mask, int mask_c,
-                                             void *__restrict__ out, int out_c, int nimg, int nx,
-                                             int ny)
+                                             void *__restrict__ out, int out_c, int nx, int ny)
 {
     constexpr int CS = KC == 3 ? CIN0 : MAXW;
     constexpr int PXU = CS * 2 / 16;            // uint4 per staged pixel
@@ -351,7 +350,7 @@ __global__ void __launch_bounds__(NT) k_dw(const unsigned short *__restrict__ x,
                     acc[q][t] += d * bf16_float(sx[t / 3][xx + t % 3][c]);
             }
         }
-        if (threadIdx.x < cout)
+        if ((int)threadIdx.x < cout)
             for (int xx = 0; xx < DWX; ++xx) accb += bf16_float(sd[xx][threadIdx.x]);
     }
     float *mine = part + (long)blockIdx.x * (npair * 9 + cout);
@@ -363,7 +362,7 @@ __global__ void __launch_bounds__(NT) k_dw(const unsigned short *__restrict__ x,
 #pragma unroll
         for (int t = 0; t < 9; ++t) mine[(n * cin + c) * 9 + t] = acc[q][t];
     }
-    if (threadIdx.x < cout) mine[npair * 9 + threadIdx.x] = accb;
+    if ((int)threadIdx.x < cout) mine[npair * 9 + threadIdx.x] = accb;
 }
 
 // Sum of the per-workgroup partial gradients (fixed order) into grad.
@@ -509,8 +508,9 @@ void conv_t(hipStream_t s, dim3 grid, const unsigned short *in, Geo g, const uns
             const float *bias, int mode, const unsigned short *mask, int mask_c, void *out,
             int out_c, int nimg, int nx, int ny)
 {
+    (void)nimg;  // the grid's z dimension
     hipLaunchKernelGGL((k_conv<NB, KC>), grid, dim3(CT), 0, s, in, g, w, bias, mode, mask,
-                       mask_c, out, out_c, nimg, nx, ny);
+                       mask_c, out, out_c, nx, ny);
 }
 
 // Dispatch on (output blocks, reduction chunks): KC = 3 for the 8-channel
@@ -539,12 +539,11 @@ int pack_all(sws_net *n)
     for (int l = 0; l < n->L; ++l) {
         const Geo &g = n->fwd[l];
         hipLaunchKernelGGL(k_pack, dim3(grid_for((long)packed_len(g))), dim3(NT), 0, n->stream,
-                           n->p + n->woff[l], g, 0, n->ch[l], n->ch[l + 1], n->wpk[l]);
+                           n->p + n->woff[l], g, 0, n->ch[l], n->wpk[l]);
         if (l > 0) {  // the input gradient of layer 0 is never needed
             const Geo &t = n->bwd[l];
             hipLaunchKernelGGL(k_pack, dim3(grid_for((long)packed_len(t))), dim3(NT), 0,
-                               n->stream, n->p + n->woff[l], t, 1, n->ch[l], n->ch[l + 1],
-                               n->wpk_t[l]);
+                               n->stream, n->p + n->woff[l], t, 1, n->ch[l], n->wpk_t[l]);
         }
     }
     SHIP(n, hipGetLastError());
