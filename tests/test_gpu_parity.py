@@ -247,6 +247,28 @@ def test_gpu_tile_shapes_and_autotune_give_the_same_bits():
     assert sums["t"] == ref_sums["t"] and sums["step"] == 200
 
 
+def test_gpu_profiled_advance_gives_the_same_bits_and_times():
+    """The measurement path (one launch per kernel with time stamps: the strip
+    launches' own, events between LDS-tile launches) steps exactly like
+    sw_advance and reports positive mean kernel durations."""
+    from paper_2103_15196_amd import csph
+    import torch
+    w = W.dam_break_fractal(n=300, ny=236, dx=2.0, seed=7, relief=10.0, depth=8.0).as_float32()
+    ref, ref_sums = run_gpu(w, 50)
+    for shape in ((58, 8), (64, 8)):
+        s = csph.solver_for(w, stream=torch.cuda.current_stream().cuda_stream)
+        s.set_tile_shape(*shape)
+        lag_ms, eul_ms = s.advance_profiled(50)
+        f = s.get_fields()
+        sums = s.get_sums()
+        s.close()
+        say(f"profiled {shape}: lagrange {lag_ms * 1e3:.2f} us, euler {eul_ms * 1e3:.2f} us")
+        assert lag_ms > 0.0 and eul_ms > 0.0
+        for a, b in zip(f, ref):
+            assert np.array_equal(a, b), shape
+        assert sums["t"] == ref_sums["t"] and sums["step"] == 50
+
+
 def test_gpu_dam_break_2048_full_size_vs_stored_oracle():
     """The 2048 x 2048 fractal dam break, 1000 steps, in the launch configuration
     the benchmark times (graph replay, dry-tile skipping, default tile shape),
