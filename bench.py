@@ -184,7 +184,7 @@ def main():
         "hbm_frac_algorithmic": round(value * STEP_BYTES / HBM_PEAK_GBS, 4),
         # the strip Euler kernel is bound by VALU issue: its roofline is the
         # non-packed FP32 VALU rate, against the algorithmic operations it must do
-        "roofline": {"kernel": "k_euler_sl<8,false>", "bound": "alu", "achieved": round(alu_ach, 3),
+        "roofline": {"kernel": "k_euler_sl<8,false,1>", "bound": "alu", "achieved": round(alu_ach, 3),
                      "peak": round(VALU_PEAK_TLANE, 2), "unit": "Top/s",
                      "frac": round(alu_ach / VALU_PEAK_TLANE, 4),
                      "traffic": (int(float(prof["traffic_bytes"])) if prof else None),

@@ -1001,6 +1001,10 @@ __device__ __forceinline__ void euler_tile(const Inst &I, int par, int bx, int b
 constexpr int SX = 58;           // interior columns of a strip tile
 constexpr int SHALO = 3;         // halo columns on each side
 constexpr int SWAVES = NT / 64;  // strip tiles per workgroup (stacked along y)
+// Largest stage grid of a single grid's strip kernels (workgroups): dispatching
+// a workgroup that finds no entry still costs time, so a mostly dry grid does
+// not launch one per tile.
+constexpr int kMaxStageGroups = 8192;
 
 // The value lane l-1 (lane_prev) or l+1 (lane_next) holds; 0 in the lane that
 // has no such neighbour.  Called only where all 64 lanes are active.
@@ -1628,9 +1632,17 @@ __device__ __forceinline__ int xcd_entry(int b, int wave, int n)
 // The entry index and the tile it names are the same in every lane of the
 // wavefront; readfirstlane states that, so tile coordinates and the row
 // ranges derived from them live in scalar registers and branch as scalars.
-// XP: w is the raw index blockIdx.x * SWAVES + wave, to be spread over the
-// XCDs once the list length is known (single grids); else the entry itself.
-template <int S, bool CS, bool XP>
+// How a wavefront finds its list entry from w:
+//   XP = 0: w is the entry itself (ensembles: one wavefront per entry);
+//   XP = 1: w = blockIdx.x * SWAVES + wave of a single grid whose stage grid
+//           has a wavefront per possible entry; spread over the XCDs once the
+//           list length is known;
+//   XP = 2: as 1, for grids with more tiles than kMaxStageGroups workgroups
+//           hold: the grid's G4 = gridDim.x * SWAVES wavefronts take the list
+//           in passes of at most G4 entries, each pass spread over the XCDs.
+// (XP = 2 is a kernel of its own: the pass loop costs the Euler kernel
+// registers, and with them a wavefront per SIMD, that XP = 1 keeps.)
+template <int S, bool CS, int XP>
 __device__ __forceinline__ void lagrange_listed(const Inst &I, int par, int w)
 {
     w = __builtin_amdgcn_readfirstlane(w);
@@ -1645,12 +1657,13 @@ __device__ __forceinline__ void lagrange_listed(const Inst &I, int par, int w)
     const int ce0 = I.hgs && publisher && lane < nb ? I.cnt_e[lane] : 0;
     uint4 v = lane < nb ? I.part[lane] : make_uint4(0u, 0u, 0u, 0u);
     int n = I.ntx * I.nty, seg = 0, start = 0;
-    if (XP) {  // the raw index 0 stays entry 0 (the publisher)
-        if (I.hgs) n = list_locate(I.cnt_l, cl0, nb, 0, seg, start, nullptr);
-        w = __builtin_amdgcn_readfirstlane(xcd_entry(w / SWAVES, w % SWAVES, n));
-    }
-    if (I.hgs) n = list_locate(I.cnt_l, cl0, nb, w, seg, start, nullptr);
-    if (w >= n && !publisher) return;
+    const int G4 = XP == 2 ? (int)gridDim.x * SWAVES : 0;
+    if (XP && I.hgs) n = list_locate(I.cnt_l, cl0, nb, 0, seg, start, nullptr);
+    if (XP == 1) w = __builtin_amdgcn_readfirstlane(xcd_entry(w / SWAVES, w % SWAVES, n));
+    if (XP != 2 && I.hgs) n = list_locate(I.cnt_l, cl0, nb, w, seg, start, nullptr);
+    // XP = 2: workgroups past those the first (fullest) pass needs have no entry
+    const bool idle = XP == 2 ? w / SWAVES >= (min(G4, n) + SWAVES - 1) / SWAVES : w >= n;
+    if (idle && !publisher) return;
     // the Eq. 7 step from the segment maxima (K3 proper)
     unsigned a = v.x, b = v.y, c = v.z, bad = v.w;
     for (int g = 64; g < nb; g += 64) {
@@ -1667,11 +1680,33 @@ __device__ __forceinline__ void lagrange_listed(const Inst &I, int par, int w)
         if (lane == 0) publish_dt(ctrl, par, I.A, m);
     }
     const Eq7 e = eq7_step(I.A, m);
-    if (err || e.err || w >= n) return;
-    const int t = __builtin_amdgcn_readfirstlane(I.hgs ? I.lag[seg * I.chunk + (w - start)] : w);
-    lagrange_strip<S, CS>(I, par, t % I.ntx, t / I.ntx, (float)e.dt);
+    if (err || e.err) return;
+    const float dt = (float)e.dt;
+    if (XP != 2) {
+        if (w >= n) return;
+        const int t = __builtin_amdgcn_readfirstlane(I.hgs ? I.lag[seg * I.chunk + (w - start)] : w);
+        lagrange_strip<S, CS>(I, par, t % I.ntx, t / I.ntx, dt);
+        return;
+    }
+    for (int base = 0; base < n; base += G4) {
+        const int cnt = min(G4, n - base);
+        const int we = __builtin_amdgcn_readfirstlane(base + xcd_entry(w / SWAVES, w % SWAVES, cnt));
+        if (we >= base + cnt) continue;
+        if (I.hgs) list_locate(I.cnt_l, cl0, nb, we, seg, start, nullptr);
+        const int t = __builtin_amdgcn_readfirstlane(I.hgs ? I.lag[seg * I.chunk + (we - start)] : we);
+        lagrange_strip<S, CS>(I, par, t % I.ntx, t / I.ntx, dt);
+    }
 }
-template <int S, bool CS, bool XP>
+template <int S, bool CS>
+__device__ __forceinline__ void euler_entry(const Inst &I, int par, int p0, int w)
+{
+    const int e = __builtin_amdgcn_readfirstlane(
+        I.hgs ? list_entry(I.eul, I.pre_e, p0, I.nchunk, I.chunk, w) : w);
+    const int t = e < 0 ? -1 - e : e;
+    if (e < 0) strip_copy<S>(I, par, t % I.ntx, t / I.ntx);
+    else euler_strip<S, CS>(I, par, t % I.ntx, t / I.ntx);
+}
+template <int S, bool CS, int XP>
 __device__ __forceinline__ void euler_listed(const Inst &I, int par, int w)
 {
     // error flag, list length and the first 64 start positions in one round trip
@@ -1680,24 +1715,34 @@ __device__ __forceinline__ void euler_listed(const Inst &I, int par, int w)
     const int err = I.ctrl->err;
     const int n = I.hgs ? I.totals[1] : I.ntx * I.nty;
     const int p0 = I.hgs && lane < I.nchunk ? I.pre_e[lane] : 0;
-    if (XP) w = __builtin_amdgcn_readfirstlane(xcd_entry(w / SWAVES, w % SWAVES, n));
-    if (err || w >= n) return;
-    const int e = __builtin_amdgcn_readfirstlane(
-        I.hgs ? list_entry(I.eul, I.pre_e, p0, I.nchunk, I.chunk, w) : w);
-    const int t = e < 0 ? -1 - e : e;
-    if (e < 0) strip_copy<S>(I, par, t % I.ntx, t / I.ntx);
-    else euler_strip<S, CS>(I, par, t % I.ntx, t / I.ntx);
+    if (XP != 2) {
+        if (XP == 1) w = __builtin_amdgcn_readfirstlane(xcd_entry(w / SWAVES, w % SWAVES, n));
+        if (err || w >= n) return;
+        euler_entry<S, CS>(I, par, p0, w);
+        return;
+    }
+    if (err) return;
+    const int G4 = (int)gridDim.x * SWAVES;
+    for (int base = 0; base < n; base += G4) {
+        const int cnt = min(G4, n - base);
+        const int we = __builtin_amdgcn_readfirstlane(base + xcd_entry(w / SWAVES, w % SWAVES, cnt));
+        if (we >= base + cnt) {
+            if (base == 0) return;  // no entry in the first (fullest) pass: none later
+            continue;
+        }
+        euler_entry<S, CS>(I, par, p0, we);
+    }
 }
 
-template <int S, bool CS>
+template <int S, bool CS, int XP>
 __global__ void __launch_bounds__(NT) k_lagrange_sl(Inst I, int par)
 {
-    lagrange_listed<S, CS, true>(I, par, blockIdx.x * SWAVES + (threadIdx.x >> 6));
+    lagrange_listed<S, CS, XP>(I, par, blockIdx.x * SWAVES + (threadIdx.x >> 6));
 }
-template <int S, bool CS>
+template <int S, bool CS, int XP>
 __global__ void __launch_bounds__(NT) k_euler_sl(Inst I, int par)
 {
-    euler_listed<S, CS, true>(I, par, blockIdx.x * SWAVES + (threadIdx.x >> 6));
+    euler_listed<S, CS, XP>(I, par, blockIdx.x * SWAVES + (threadIdx.x >> 6));
 }
 
 // Ensemble: workgroup b runs waves SWAVES table[2b+1] + w of member table[2b].
@@ -1706,14 +1751,14 @@ __global__ void __launch_bounds__(NT) k_lagrange_slb(const Inst *__restrict__ in
                                                      const int *__restrict__ table, int par)
 {
     const int *t = table + 2 * blockIdx.x;
-    lagrange_listed<S, CS, false>(insts[t[0]], par, t[1] * SWAVES + (threadIdx.x >> 6));
+    lagrange_listed<S, CS, 0>(insts[t[0]], par, t[1] * SWAVES + (threadIdx.x >> 6));
 }
 template <int S, bool CS>
 __global__ void __launch_bounds__(NT) k_euler_slb(const Inst *__restrict__ insts,
                                                   const int *__restrict__ table, int par)
 {
     const int *t = table + 2 * blockIdx.x;
-    euler_listed<S, CS, false>(insts[t[0]], par, t[1] * SWAVES + (threadIdx.x >> 6));
+    euler_listed<S, CS, 0>(insts[t[0]], par, t[1] * SWAVES + (threadIdx.x >> 6));
 }
 
 // Tile shapes the autotuner chooses from: TX x TY cells per 256-thread
@@ -2136,10 +2181,16 @@ template <int S>
 void launch_strip_t(Stage st, hipStream_t s, const Inst &I, int par, hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 gt(I.ntx, I.nty);
-    const int gl = (I.ntx * I.nty + SWAVES - 1) / SWAVES;  // one wavefront per possible entry
+    // one wavefront per possible entry, up to kMaxStageGroups workgroups (the
+    // stage kernels then take longer lists in passes)
+    const int need = (I.ntx * I.nty + SWAVES - 1) / SWAVES;
+    const bool passes = need > kMaxStageGroups;
+    const int gl = passes ? kMaxStageGroups : need;
     const bool cs = cell_soil(I.P);
-    auto lag = cs ? k_lagrange_sl<S, true> : k_lagrange_sl<S, false>;
-    auto eul = cs ? k_euler_sl<S, true> : k_euler_sl<S, false>;
+    auto lag = passes ? (cs ? k_lagrange_sl<S, true, 2> : k_lagrange_sl<S, false, 2>)
+                      : (cs ? k_lagrange_sl<S, true, 1> : k_lagrange_sl<S, false, 1>);
+    auto eul = passes ? (cs ? k_euler_sl<S, true, 2> : k_euler_sl<S, false, 2>)
+                      : (cs ? k_euler_sl<S, true, 1> : k_euler_sl<S, false, 1>);
     if (st == kPrepare) hipLaunchKernelGGL((k_prepare_t<SX, S>), gt, dim3(NT), 0, s, I, par);
     else if (st == kDt) hipLaunchKernelGGL(k_dt_lists, dim3(I.nchunk), dim3(RT), 0, s, I, par);
     else if (st == kCount) hipLaunchKernelGGL(k_count_t, dim3(1), dim3(RT), 0, s, I, par, SX, S);

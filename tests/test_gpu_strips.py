@@ -3,6 +3,8 @@ registers, x neighbours by lane shifts) against the LDS tile kernels: every
 strip height gives exactly the bits of the 64 x 8 tiles on walls, open sides,
 per-cell soil, inflow and bed sources, ragged edges, grids narrower than one
 strip, graph replay and eager launches, dry-tile skipping on and off."""
+import copy
+
 import numpy as np
 import pytest
 
@@ -90,3 +92,20 @@ def test_gpu_strips_tiny_grids():
         ref = run_gpu(w, 5, dt=0.05)
         for shape in STRIPS:
             _same(run_gpu(w, 5, dt=0.05, shape=shape), ref, f"{nx}x{ny} {shape}")
+
+
+def test_gpu_strips_long_lists_take_several_passes():
+    """8192 x 2048 cells: 58 x 8 strips make 36352 tiles, more than the stage
+    grid's 8192 workgroups of 4 wavefronts hold, so the Lagrangian and Euler
+    kernels take their lists in two passes; 58 x 32 strips (4544 tiles) take
+    one.  Both give the bits of the 64 x 8 tiles, with every tile listed (no
+    dry-tile skipping) and with the lists of an all-wet grid."""
+    from paper_2103_15196_amd import csph
+    w = W.dam_break_fractal(n=8192, ny=2048, dx=2.0, seed=5, relief=10.0, depth=6.0).as_float32()
+    wet = copy.deepcopy(w)
+    wet.H = (w.H + 0.5).astype(np.float32).astype(np.float64)
+    for name, case, flags in (("all tiles", w, 0), ("all wet", wet, csph.SW_FLAG_HGS)):
+        ref = run_gpu(case, 30, flags=flags)
+        for shape in ((58, 8), (58, 32)):
+            say(f"strip {shape}, {name}, 8192x2048, 30 steps")
+            _same(run_gpu(case, 30, flags=flags, shape=shape), ref, f"{name} {shape}")
