@@ -96,14 +96,24 @@ __global__ void k_pack(const float *__restrict__ W, Geo g, int flip, int wcin,
 constexpr int TW = 64;     // output pixels per tile row
 constexpr int CW = 8;      // wavefronts (output rows per step) of a convolution workgroup
 constexpr int CT = 64 * CW;
-constexpr int CSEG = 32;   // output rows per workgroup (a multiple of CW)
+
+// LDS of one convolution workgroup: packed weights, then the staged input
+// rows (reused for the waves' output tiles)
+template <int NB, int KC>
+constexpr int conv_lds_bytes()
+{
+    constexpr int PXU = (KC == 3 ? CIN0 : MAXW) * 2 / 16;
+    constexpr int SU = (CW + 2) * (TW + 2) * PXU, OU = TW * NB * 2;
+    return 16 * (NB * KC * 64 + (SU > CW * OU ? SU : CW * OU));
+}
 
 template <int NB, int KC>
 __global__ void __launch_bounds__(CT) k_conv(const unsigned short *__restrict__ in, Geo g,
                                              const unsigned short *__restrict__ wpk,
                                              const float *__restrict__ bias, int mode,
                                              const unsigned short *__restrict__ mask, int mask_c,
-                                             void *__restrict__ out, int out_c, int nx, int ny)
+                                             void *__restrict__ out, int out_c, int nx, int ny,
+                                             int cseg)
 {
     constexpr int CS = KC == 3 ? CIN0 : MAXW;
     constexpr int PXU = CS * 2 / 16;            // uint4 per staged pixel
@@ -120,7 +130,7 @@ __global__ void __launch_bounds__(CT) k_conv(const unsigned short *__restrict__ 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = lane & 15, kg = lane >> 4;
     const int x0 = blockIdx.x * TW, img = blockIdx.z;
-    const int ys = blockIdx.y * CSEG, ye = min(ny, ys + CSEG);
+    const int ys = blockIdx.y * cseg, ye = min(ny, ys + cseg);
     const unsigned short *base = in + (long)img * ny * nx * CS;
     // the input rows of the next step are loaded into registers while the
     // current step computes
@@ -503,32 +513,41 @@ size_t packed_len(const Geo &g) { return (size_t)g.nb * g.kc * 64 * 8; }
 
 int grid_for(long n) { return (int)std::min<long>(4096, std::max<long>(1, (n + NT - 1) / NT)); }
 
+constexpr int kConvCUs = 256;           // compute units of the MI355X
+constexpr int kLdsPerCU = 160 * 1024;   // LDS bytes per compute unit
+
+// One workgroup per (64-pixel strip, row segment, image).  The segments are
+// as tall as leaves every workgroup the chip holds at once one of them (a
+// multiple of CW rows): each workgroup loads its weights and first input rows
+// once, so fewer, taller segments spend less time on that.
 template <int NB, int KC>
-void conv_t(hipStream_t s, dim3 grid, const unsigned short *in, Geo g, const unsigned short *w,
+void conv_t(hipStream_t s, const unsigned short *in, Geo g, const unsigned short *w,
             const float *bias, int mode, const unsigned short *mask, int mask_c, void *out,
             int out_c, int nimg, int nx, int ny)
 {
-    (void)nimg;  // the grid's z dimension
+    const long cols = (long)((nx + TW - 1) / TW) * nimg;
+    const long steps = (ny + CW - 1) / CW;
+    const long slots = (long)kConvCUs * std::max(1, kLdsPerCU / conv_lds_bytes<NB, KC>());
+    const int cseg = CW * (int)std::max<long>(1, (cols * steps + slots - 1) / slots);
+    const dim3 grid((nx + TW - 1) / TW, (ny + cseg - 1) / cseg, nimg);
     hipLaunchKernelGGL((k_conv<NB, KC>), grid, dim3(CT), 0, s, in, g, w, bias, mode, mask,
-                       mask_c, out, out_c, nx, ny);
+                       mask_c, out, out_c, nx, ny, cseg);
 }
 
 // Dispatch on (output blocks, reduction chunks): KC = 3 for the 8-channel
-// input, 14 for 48 stored channels.  One workgroup per (64-pixel strip,
-// CSEG-row segment, image).
+// input, 14 for 48 stored channels.
 int conv(sws_net *n, const unsigned short *in, const Geo &g, const unsigned short *w,
          const float *bias, int mode, const unsigned short *mask, int mask_c, void *out, int out_c,
          int nimg, int nx, int ny)
 {
     if (g.cs != (g.kc == 3 ? CIN0 : MAXW)) return sfail(n, SW_ERR_ARG, "unsupported layer shape");
-    const dim3 grid((nx + TW - 1) / TW, (ny + CSEG - 1) / CSEG, nimg);
     hipStream_t s = n->stream;
-    if (g.kc == 3 && g.nb == 3) conv_t<3, 3>(s, grid, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
-    else if (g.kc == 3 && g.nb == 1) conv_t<1, 3>(s, grid, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
-    else if (g.kc == 3 && g.nb == 2) conv_t<2, 3>(s, grid, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
-    else if (g.kc == 14 && g.nb == 3) conv_t<3, 14>(s, grid, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
-    else if (g.kc == 14 && g.nb == 2) conv_t<2, 14>(s, grid, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
-    else if (g.kc == 14 && g.nb == 1) conv_t<1, 14>(s, grid, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
+    if (g.kc == 3 && g.nb == 3) conv_t<3, 3>(s, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
+    else if (g.kc == 3 && g.nb == 1) conv_t<1, 3>(s, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
+    else if (g.kc == 3 && g.nb == 2) conv_t<2, 3>(s, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
+    else if (g.kc == 14 && g.nb == 3) conv_t<3, 14>(s, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
+    else if (g.kc == 14 && g.nb == 2) conv_t<2, 14>(s, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
+    else if (g.kc == 14 && g.nb == 1) conv_t<1, 14>(s, in, g, w, bias, mode, mask, mask_c, out, out_c, nimg, nx, ny);
     else return sfail(n, SW_ERR_ARG, "unsupported layer shape");
     SHIP(n, hipGetLastError());
     return SW_OK;
