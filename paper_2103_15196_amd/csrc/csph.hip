@@ -1077,13 +1077,13 @@ struct BedCell {
     float jx, jy, b;
 };
 
-// Lagrangian stage on a strip tile (CS: per-cell Manning coefficient).
+// Lagrangian stage on a strip tile (CS: per-cell Manning coefficient).  Its
+// callers pass listed tiles only: under skipping, the list holds exactly the
+// tiles whose wet flag is set, so the flag is not read again here.
 template <int S, bool CS>
 __device__ __forceinline__ void lagrange_strip(const Inst &I, int par, int bx, int by, float dt)
 {
     const KPar &P = I.P;
-    const int tile = bx + by * I.ntx;
-    if (I.hgs && !I.act[par][tile]) return;
     const int lane = threadIdx.x & 63;
     const int nx = P.nx, ny = P.ny, pitch = P.pitch;
     const int x0 = bx * SX, y0 = by * S;
@@ -1162,12 +1162,13 @@ __device__ __forceinline__ void lagrange_strip(const Inst &I, int par, int bx, i
 // Euler stage on a strip tile (K7 + limiter + K8) with the epilogue
 // reductions (Eq. 7 maxima and wet flag of the new state, boundary balances).
 // CS: some soil or source field is a per-cell plane (else all are scalars).
+// The caller has checked the error flag (one memory round trip per
+// wavefront saved: the step and the first rows load together).
 template <int S, bool CS>
 __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int by)
 {
     const KPar &P = I.P;
     Ctrl *ctrl = I.ctrl;
-    if (ctrl->err) return;
     const int ntx = I.ntx, tile = bx + by * ntx;
     const int lane = threadIdx.x & 63;
     const int nx = P.nx, ny = P.ny, pitch = P.pitch;
