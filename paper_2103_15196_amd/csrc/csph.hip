@@ -1005,6 +1005,10 @@ constexpr int SWAVES = NT / 64;  // strip tiles per workgroup (stacked along y)
 // a workgroup that finds no entry still costs time, so a mostly dry grid does
 // not launch one per tile.
 constexpr int kMaxStageGroups = 8192;
+// Wavefronts per listed tile in a single grid's Lagrangian stage (each marches
+// S / kLagHalves rows): more, shorter wavefronts hide the memory latency of the
+// few tiles a step lists better than they cost in extra halo rows.
+constexpr int kLagHalves = 2;
 
 // The value lane l-1 (lane_prev) or l+1 (lane_next) holds; 0 in the lane that
 // has no such neighbour.  Called only where all 64 lanes are active.
@@ -1659,8 +1663,12 @@ __device__ __forceinline__ void lagrange_listed(const Inst &I, int par, int w)
     uint4 v = lane < nb ? I.part[lane] : make_uint4(0u, 0u, 0u, 0u);
     int n = I.ntx * I.nty, seg = 0, start = 0;
     const int G4 = XP == 2 ? (int)gridDim.x * SWAVES : 0;
+    // XP = 1: LH wavefronts per listed tile, each on S / LH of its rows
+    constexpr int LH = XP == 1 ? kLagHalves : 1;
     if (XP && I.hgs) n = list_locate(I.cnt_l, cl0, nb, 0, seg, start, nullptr);
-    if (XP == 1) w = __builtin_amdgcn_readfirstlane(xcd_entry(w / SWAVES, w % SWAVES, n));
+    if (XP == 1) w = __builtin_amdgcn_readfirstlane(xcd_entry(w / SWAVES, w % SWAVES, LH * n));
+    const int part = w % LH;
+    w /= LH;
     if (XP != 2 && I.hgs) n = list_locate(I.cnt_l, cl0, nb, w, seg, start, nullptr);
     // XP = 2: workgroups past those the first (fullest) pass needs have no entry
     const bool idle = XP == 2 ? w / SWAVES >= (min(G4, n) + SWAVES - 1) / SWAVES : w >= n;
@@ -1686,7 +1694,7 @@ __device__ __forceinline__ void lagrange_listed(const Inst &I, int par, int w)
     if (XP != 2) {
         if (w >= n) return;
         const int t = __builtin_amdgcn_readfirstlane(I.hgs ? I.lag[seg * I.chunk + (w - start)] : w);
-        lagrange_strip<S, CS>(I, par, t % I.ntx, t / I.ntx, dt);
+        lagrange_strip<S / LH, CS>(I, par, t % I.ntx, (t / I.ntx) * LH + part, dt);
         return;
     }
     for (int base = 0; base < n; base += G4) {
@@ -2187,6 +2195,7 @@ void launch_strip_t(Stage st, hipStream_t s, const Inst &I, int par, hipEvent_t 
     const int need = (I.ntx * I.nty + SWAVES - 1) / SWAVES;
     const bool passes = need > kMaxStageGroups;
     const int gl = passes ? kMaxStageGroups : need;
+    const int gll = passes ? kMaxStageGroups : (kLagHalves * I.ntx * I.nty + SWAVES - 1) / SWAVES;
     const bool cs = cell_soil(I.P);
     auto lag = passes ? (cs ? k_lagrange_sl<S, true, 2> : k_lagrange_sl<S, false, 2>)
                       : (cs ? k_lagrange_sl<S, true, 1> : k_lagrange_sl<S, false, 1>);
@@ -2195,7 +2204,7 @@ void launch_strip_t(Stage st, hipStream_t s, const Inst &I, int par, hipEvent_t 
     if (st == kPrepare) hipLaunchKernelGGL((k_prepare_t<SX, S>), gt, dim3(NT), 0, s, I, par);
     else if (st == kDt) hipLaunchKernelGGL(k_dt_lists, dim3(I.nchunk), dim3(RT), 0, s, I, par);
     else if (st == kCount) hipLaunchKernelGGL(k_count_t, dim3(1), dim3(RT), 0, s, I, par, SX, S);
-    else if (st == kLagrange) launch_timed(lag, dim3(gl), s, e0, e1, I, par);
+    else if (st == kLagrange) launch_timed(lag, dim3(gll), s, e0, e1, I, par);
     else launch_timed(eul, dim3(gl), s, e0, e1, I, par);
 }
 
