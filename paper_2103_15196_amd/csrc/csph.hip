@@ -1462,18 +1462,21 @@ __device__ __forceinline__ int wave_scan(int v)
 // follows (the kernel boundary makes these writes visible): every wavefront
 // derives its entry and the Eq. 7 step from the segment lengths and maxima,
 // and wavefront 0 publishes the step and the Euler list's start positions.
+// A list workgroup has list_threads(chunk) threads, at most LT.
+constexpr int LT = 1024;
 __device__ void dt_lists(const Inst &I, int par, int b)
 {
-    __shared__ unsigned red[4][RT / 64];
-    __shared__ int wl[RT / 64], we[RT / 64];
+    __shared__ unsigned red[4][LT / 64];
+    __shared__ int wl[LT / 64], we[LT / 64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nthr = blockDim.x, nw = nthr >> 6;
     const int nt = I.ntx * I.nty;
     const int c0 = b * I.chunk, c1 = min(nt, c0 + I.chunk);
     const int ntx = I.ntx, nty = I.nty;
     const uint8_t *act = I.act[par];
     const uint8_t *synced = I.synced;
     const uint4 *tm = I.tmax[par];
-    const int per = (c1 - c0 + RT - 1) / RT;  // at most 32 (chunk <= 32 RT)
+    const int per = (c1 - c0 + nthr - 1) / nthr;  // at most 32 (chunk <= 32 threads)
     const int t0 = min(c1, c0 + tid * per), t1 = min(c1, t0 + per);
     // every load first: the tiles' maxima and (under skipping) the five wet
     // flags and the synced flag of each tile of this thread's run
@@ -1503,14 +1506,14 @@ __device__ void dt_lists(const Inst &I, int par, int b)
     if (lane == 0) { red[0][wv] = a; red[1][wv] = bb; red[2][wv] = c; red[3][wv] = bad; }
     __syncthreads();
     if (tid == 0) {
-        for (int w = 1; w < RT / 64; ++w) {
+        for (int w = 1; w < nw; ++w) {
             a = max(a, red[0][w]); bb = max(bb, red[1][w]); c = max(c, red[2][w]); bad = max(bad, red[3][w]);
         }
         I.part[b] = make_uint4(a, bb, c, bad);
     }
     if (!I.hgs) return;
     int ol = il - nl, oe = ie - ne, tl = 0, te = 0;
-    for (int k = 0; k < RT / 64; ++k) {
+    for (int k = 0; k < nw; ++k) {
         if (k < wv) { ol += wl[k]; oe += we[k]; }
         tl += wl[k]; te += we[k];
     }
@@ -1539,10 +1542,10 @@ __device__ void dt_lists(const Inst &I, int par, int b)
     }
 }
 
-__global__ void __launch_bounds__(RT) k_dt_lists(Inst I, int par) { dt_lists(I, par, blockIdx.x); }
+__global__ void __launch_bounds__(LT) k_dt_lists(Inst I, int par) { dt_lists(I, par, blockIdx.x); }
 
 // Ensemble: workgroup b runs segment table[2b+1] of member table[2b].
-__global__ void __launch_bounds__(RT) k_dt_lists_b(const Inst *__restrict__ insts,
+__global__ void __launch_bounds__(LT) k_dt_lists_b(const Inst *__restrict__ insts,
                                                    const int *__restrict__ table, int par)
 {
     dt_lists(insts[table[2 * blockIdx.x]], par, table[2 * blockIdx.x + 1]);
@@ -2021,9 +2024,13 @@ dim3 cell_grid(const sw_ctx *c) { return dim3((c->nx + BX - 1) / BX, (c->ny + BY
 
 size_t ntiles(const sw_ctx *c) { return (size_t)c->ntx * c->nty; }
 
-// Tiles per K3 workgroup (list segment) for nt tiles: at least RT, at most
-// 32 RT (one 32-bit mask per thread), and at most 64 segments where possible.
-int list_chunk(int nt) { return std::min(32 * RT, std::max(RT, (nt + 63) / 64)); }
+// Tiles per K3 workgroup (list segment) for nt tiles: at least 256, at most
+// 32 LT (one 32-bit mask per thread), and at most 64 segments where possible.
+int list_chunk(int nt) { return std::min(32 * LT, std::max(256, (nt + 63) / 64)); }
+// Threads of the workgroup that lists a segment of chunk tiles: one tile per
+// thread up to LT threads (small segments: short dependency chains in many
+// small workgroups; large ones: at most 32 tiles per thread).
+int list_threads(int chunk) { return std::min(LT, std::max(256, (chunk + 63) / 64 * 64)); }
 
 // Offsets (in ints) of the parts of the work-list buffer.
 struct SchedLayout {
@@ -2139,9 +2146,9 @@ void launch_batch_t(Stage st, hipStream_t s, const Inst *insts, int nmem, const 
 // kernels over the (member, local workgroup) table, both on work lists.
 template <int S, bool CS>
 void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, const int *table, int ntab,
-                    const int *dtab, int ndtab, int par)
+                    const int *dtab, int ndtab, int lthr, int par)
 {
-    if (st == kDt) hipLaunchKernelGGL(k_dt_lists_b, dim3(ndtab), dim3(RT), 0, s, insts, dtab, par);
+    if (st == kDt) hipLaunchKernelGGL(k_dt_lists_b, dim3(ndtab), dim3(lthr), 0, s, insts, dtab, par);
     else if (st == kLagrange)
         hipLaunchKernelGGL((k_lagrange_slb<S, CS>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
     else hipLaunchKernelGGL((k_euler_slb<S, CS>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
@@ -2149,25 +2156,26 @@ void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, const int *table
 
 template <int S>
 void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, const int *table, int ntab,
-                    const int *dtab, int ndtab, int par, bool cs)
+                    const int *dtab, int ndtab, int lthr, int par, bool cs)
 {
-    if (cs) launch_batch_s<S, true>(st, s, insts, table, ntab, dtab, ndtab, par);
-    else launch_batch_s<S, false>(st, s, insts, table, ntab, dtab, ndtab, par);
+    if (cs) launch_batch_s<S, true>(st, s, insts, table, ntab, dtab, ndtab, lthr, par);
+    else launch_batch_s<S, false>(st, s, insts, table, ntab, dtab, ndtab, lthr, par);
 }
 
 // cs: some member has a per-cell soil or source plane.  Tile shapes take the
 // (member, bx, by) table; strips the stage and K3a tables.
 void launch_batch(int shape, Stage st, hipStream_t s, const Inst *insts, int nmem,
-                  const int *table, int ntab, const int *dtab, int ndtab, int par, bool cs)
+                  const int *table, int ntab, const int *dtab, int ndtab, int lthr, int par,
+                  bool cs)
 {
     switch (shape) {
     case 0: launch_batch_t<64, 8>(st, s, insts, nmem, table, ntab, par); break;
     case 1: launch_batch_t<64, 4>(st, s, insts, nmem, table, ntab, par); break;
     case 2: launch_batch_t<64, 16>(st, s, insts, nmem, table, ntab, par); break;
     case 3: launch_batch_t<128, 4>(st, s, insts, nmem, table, ntab, par); break;
-    case 4: launch_batch_s<8>(st, s, insts, table, ntab, dtab, ndtab, par, cs); break;
-    case 5: launch_batch_s<16>(st, s, insts, table, ntab, dtab, ndtab, par, cs); break;
-    default: launch_batch_s<32>(st, s, insts, table, ntab, dtab, ndtab, par, cs); break;
+    case 4: launch_batch_s<8>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, cs); break;
+    case 5: launch_batch_s<16>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, cs); break;
+    default: launch_batch_s<32>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, cs); break;
     }
 }
 
@@ -2202,7 +2210,8 @@ void launch_strip_t(Stage st, hipStream_t s, const Inst &I, int par, hipEvent_t 
     auto eul = passes ? (cs ? k_euler_sl<S, true, 2> : k_euler_sl<S, false, 2>)
                       : (cs ? k_euler_sl<S, true, 1> : k_euler_sl<S, false, 1>);
     if (st == kPrepare) hipLaunchKernelGGL((k_prepare_t<SX, S>), gt, dim3(NT), 0, s, I, par);
-    else if (st == kDt) hipLaunchKernelGGL(k_dt_lists, dim3(I.nchunk), dim3(RT), 0, s, I, par);
+    else if (st == kDt)
+        hipLaunchKernelGGL(k_dt_lists, dim3(I.nchunk), dim3(list_threads(I.chunk)), 0, s, I, par);
     else if (st == kCount) hipLaunchKernelGGL(k_count_t, dim3(1), dim3(RT), 0, s, I, par, SX, S);
     else if (st == kLagrange) launch_timed(lag, dim3(gll), s, e0, e1, I, par);
     else launch_timed(eul, dim3(gl), s, e0, e1, I, par);
@@ -2970,6 +2979,7 @@ struct swb_ctx {
     Inst *d_insts = nullptr;
     int *d_table = nullptr;          // stage table, then (strips) the K3a table
     int ntab = 0, ndtab = 0;
+    int lthr = LT;  // threads of a K3a workgroup (the widest member segment's)
     int shape = kDefaultShape;
     bool cs = false;  // some member reads per-cell soil or source planes
     hipGraphExec_t gexec = nullptr;
@@ -2999,6 +3009,7 @@ int batch_build(swb_ctx *b)
     const int n = (int)b->mem.size();
     std::vector<Inst> insts(n);
     std::vector<int> table, dtable;
+    int lthr = 256;
     b->cs = false;
     for (int m = 0; m < n; ++m) {
         sw_ctx *c = b->mem[m];
@@ -3019,6 +3030,7 @@ int batch_build(swb_ctx *b)
                 dtable.push_back(m);
                 dtable.push_back(k);
             }
+            lthr = std::max(lthr, list_threads(insts[m].chunk));
         } else {  // one entry per tile
             for (int by = 0; by < c->nty; ++by)
                 for (int bx = 0; bx < c->ntx; ++bx) {
@@ -3031,6 +3043,7 @@ int batch_build(swb_ctx *b)
     const int per = is_strip(b->shape) ? 2 : 3;
     b->ntab = (int)(table.size() / per);
     b->ndtab = (int)(dtable.size() / 2);
+    b->lthr = lthr;
     table.insert(table.end(), dtable.begin(), dtable.end());
     (void)hipFree(b->d_insts);
     (void)hipFree(b->d_table);
@@ -3068,10 +3081,10 @@ void batch_step(swb_ctx *b, hipStream_t st, int par)
 {
     const int n = (int)b->mem.size();
     const int *dtab = b->d_table + 2 * b->ntab;
-    launch_batch(b->shape, kDt, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, par, b->cs);
-    launch_batch(b->shape, kLagrange, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, par,
+    launch_batch(b->shape, kDt, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, b->lthr, par, b->cs);
+    launch_batch(b->shape, kLagrange, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, b->lthr, par,
                  b->cs);
-    launch_batch(b->shape, kEuler, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, par,
+    launch_batch(b->shape, kEuler, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, b->lthr, par,
                  b->cs);
 }
 
