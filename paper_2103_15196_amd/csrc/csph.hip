@@ -1334,15 +1334,22 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
             }
         }
     };
-    const int rlo = y0 - 3, rhi = y0 + S + 2;  // S + 6 rows, an even count
+    // S + 6 rows, an even count, unrolled in full for S = 8: every row's
+    // offset from the tile is then a constant, so its part of the march
+    // (ring, tile or K8 row) is known at compile time, and the carried rows
+    // are renamed rather than moved (the code grows to about 10 K
+    // instructions, which the instruction cache still holds)
+    constexpr int kRows = S + 6;
+    const int rlo = y0 - 3;
     Row A, B;
     load_row(rlo, A);
     load_row(rlo + 1, B);
-    for (int r = rlo; r <= rhi; r += 2) {
-        step(r, A);
-        if (r + 2 <= rhi) load_row(r + 2, A);
-        step(r + 1, B);
-        if (r + 3 <= rhi) load_row(r + 3, B);
+#pragma unroll(S == 8 ? kRows / 2 : 1)
+    for (int k = 0; k < kRows; k += 2) {
+        step(rlo + k, A);
+        if (k + 2 < kRows) load_row(rlo + k + 2, A);
+        step(rlo + k + 1, B);
+        if (k + 3 < kRows) load_row(rlo + k + 3, B);
     }
     strip_maxima_store(I, par ^ 1, tile, mv, ms, mD, bad, wet);
 }
