@@ -1339,12 +1339,12 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
     // (ring, tile or K8 row) is known at compile time, and the carried rows
     // are renamed rather than moved (the code grows to about 10 K
     // instructions, which the instruction cache still holds)
-    constexpr int kRows = S + 6;
+    constexpr int kRows = S + 6, kUnroll = S == 8 ? kRows / 2 : 1;
     const int rlo = y0 - 3;
     Row A, B;
     load_row(rlo, A);
     load_row(rlo + 1, B);
-#pragma unroll(S == 8 ? kRows / 2 : 1)
+#pragma unroll kUnroll
     for (int k = 0; k < kRows; k += 2) {
         step(rlo + k, A);
         if (k + 2 < kRows) load_row(rlo + k + 2, A);
