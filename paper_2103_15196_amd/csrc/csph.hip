@@ -1337,8 +1337,8 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
     // S + 6 rows, an even count, unrolled in full for S = 8: every row's
     // offset from the tile is then a constant, so its part of the march
     // (ring, tile or K8 row) is known at compile time, and the carried rows
-    // are renamed rather than moved (the code grows to about 10 K
-    // instructions, which the instruction cache still holds)
+    // are renamed rather than moved (about 10 K instructions of code; taller
+    // strips keep the loop)
     constexpr int kRows = S + 6, kUnroll = S == 8 ? kRows / 2 : 1;
     const int rlo = y0 - 3;
     Row A, B;
