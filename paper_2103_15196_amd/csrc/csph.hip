@@ -1177,9 +1177,7 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
     const int lane = threadIdx.x & 63;
     const int nx = P.nx, ny = P.ny, pitch = P.pitch;
     const int x0 = bx * SX, y0 = by * S;
-    const int i = x0 - SHALO + lane;
-    const bool inx = (unsigned)i < (unsigned)nx;
-    const bool mine = lane >= SHALO && lane < SHALO + SX && inx;
+    const int i0 = x0 - SHALO + lane;  // this lane's column
     const int jend = min(y0 + S, ny);
     const float *SH = I.H[par], *Sqx = I.qx[par], *Sqy = I.qy[par], *Sb = I.b[par];
     float *OH = I.H[par ^ 1], *Oqx = I.qx[par ^ 1], *Oqy = I.qy[par ^ 1], *Ob = I.b[par ^ 1];
@@ -1189,9 +1187,7 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
     const float qmid = (float)ctrl->qmid[par];
     const double wdx = dtd * (double)P.dx;
     const bool wW = P.bcW == kWall, wE = P.bcE == kWall, wS = P.bcS == kWall, wN = P.bcN == kWall;
-    const bool xghost = i == -1 || i == nx;
-    const bool face_x = i >= 0 && i <= nx;  // this lane's west face is a grid face
-    const int ci = min(max(i, 0), nx - 1);
+    const int ci = min(max(i0, 0), nx - 1);
     const float *Jx = I.jx[par], *Jy = I.jy[par], *Jm = I.jm[par];
     // every plane is addressed as a uniform base plus one 32-bit byte offset
     auto at = [](const float *base, unsigned o) -> float {
@@ -1226,6 +1222,17 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
     unsigned mv = 0, ms = 0, mD = 0, bad = 0;
     bool wet = false;
     auto step = [&](int r, const Row &in) {
+        // the column and its lane predicates are derived again in every row
+        // from a copy the compiler cannot see through: kept across the march
+        // they were 64-bit lane masks in scalar registers, more than fit, and
+        // spilled to vector lanes to be read back row after row
+        int ic = i0;
+        asm volatile("" : "+v"(ic));
+        const int i = ic;
+        const bool inx = (unsigned)i < (unsigned)nx;
+        const bool mine = (unsigned)(i - x0) < (unsigned)SX && inx;
+        const bool xghost = i == -1 || i == nx;
+        const bool face_x = i >= 0 && i <= nx;  // this lane's west face is a grid face
         // the cells K8 updates in this step (row r-3), loaded again (cache
         // hits); loaded in every step, from the nearest row of the tile when
         // r-3 lies outside it (then unused), so no row outside the march is read
