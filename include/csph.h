@@ -105,6 +105,9 @@ typedef struct {
     int64_t cells_euler;       /* cells the Euler-stage kernel processed since set_state */
     int32_t binding_term;      /* Eq. 7 term that set last_dt: 0 h/(2vp), 1 h/vs, 2 h^2/(2D), 3 dt_max, 4 fixed */
     int32_t error;             /* sticky device error (SW_ERR_*), 0 if none */
+    int64_t graph_builds;      /* step graphs captured so far: a new state, bed or time
+                                  keeps them; soil, sources, tile shape or a new fixed dt
+                                  rebuild them at the next advance */
 } sw_sums;
 
 /* Fill *p with the defaults listed in sw_params. */
@@ -112,7 +115,10 @@ void sw_default_params(sw_params *p);
 
 /* Create a solver for `grid`.  hip_stream: a hipStream_t to order all work on
  * (for instance torch.cuda.current_stream().cuda_stream), or NULL to let the
- * library create its own.  The state is all zero until set. */
+ * library create its own.  The state is all zero until set.  Size limit: a
+ * row is padded to a multiple of 64 cells (the pitch), and pitch * ny must
+ * stay below 2^30 cells (each field plane under 4 GiB), e.g. up to 32768 x
+ * 32767; larger grids, nx or ny < 1 or dx <= 0 are SW_ERR_ARG. */
 int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw_ctx **out);
 int sw_destroy(sw_ctx *ctx);
 

@@ -100,6 +100,16 @@ int orc_threads(void)
 #endif
 }
 
+/* Set the thread count of the oracle's OpenMP loops (timing at one thread). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_NONFINITE = -3, ORC_ERR_DT = -4, ORC_ERR_CFL = -6 };
 
 /* ---------------------------------------------------------------------- */

@@ -27,11 +27,17 @@ BC_WALL, BC_OPEN = 0, 1
 BINDING_NAMES = ("h/(2vp)", "h/vs", "h^2/(2D)", "dt_max", "fixed")
 
 
+# -O3 for the generic x86-64 AVX2/FMA level rather than -march=native: the
+# library is built on one machine and may run on another host; contraction
+# into FMA stays off, so each operation is rounded as the source writes it.
+CFLAGS = ["-O3", "-march=x86-64-v3", "-ffp-contract=off", "-std=c11", "-fopenmp", "-fPIC",
+          "-shared", "-Wall", "-Wno-unknown-pragmas"]
+
+
 def compile_source(src: str, out: str) -> str:
-    """Compile one oracle source file with gcc (-O2, C11, OpenMP) into ``out``."""
+    """Compile one oracle source file with gcc (CFLAGS: -O3, C11, OpenMP) into ``out``."""
     tmp = out + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
-                           "-Wall", "-Wno-unknown-pragmas", src, "-o", tmp, "-lm"])
+    subprocess.check_call(["gcc"] + CFLAGS + [src, "-o", tmp, "-lm"])
     os.replace(tmp, out)
     return out
 
@@ -99,6 +105,8 @@ def _load():
                                  C.c_double, C.c_double, C.POINTER(_Info)]
         lib.orc_threads.restype = C.c_int
         lib.orc_threads.argtypes = []
+        lib.orc_set_threads.restype = None
+        lib.orc_set_threads.argtypes = [C.c_int]
         lib.orc_volumes.restype = None
         lib.orc_volumes.argtypes = [C.POINTER(_Params), C.POINTER(_Inputs), _dp, _dp, _dp, _dp]
         _lib = lib
@@ -302,3 +310,8 @@ def hydrograph(inp: Inputs, t: float) -> float:
 def threads() -> int:
     """OpenMP threads the oracle's loops use."""
     return int(_load().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the oracle's loops on n OpenMP threads from now on."""
+    _load().orc_set_threads(int(n))

@@ -54,7 +54,8 @@ class sw_sums(C.Structure):
                 ("sed_source_in", C.c_double), ("vp", C.c_double), ("vs", C.c_double),
                 ("D", C.c_double), ("step", C.c_int64), ("wet_cells", C.c_int64),
                 ("active_tiles", C.c_int64), ("cells_lagrange", C.c_int64),
-                ("cells_euler", C.c_int64), ("binding_term", C.c_int32), ("error", C.c_int32)]
+                ("cells_euler", C.c_int64), ("binding_term", C.c_int32), ("error", C.c_int32),
+                ("graph_builds", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -284,9 +285,12 @@ class Solver:
         return s.as_dict()
 
     def reset(self, w):
-        """Restart from workload ``w``'s initial bed and state (time back to 0)."""
+        """Restart from workload ``w``'s initial bed and state (time back to 0).
+        The library's set-up of the new state (its Eq. 7 maxima and wet-tile
+        flags) runs here too, so the next advance launches steps only."""
         self.set_bed(w.b)
         self.set_state(w.H, w.qx, w.qy)
+        self.advance(0)
 
     def load_workload(self, w):
         """Upload a paper_2103_15196_amd.workloads.Workload (bed, soil, state, sources)."""

@@ -1899,7 +1899,9 @@ struct sw_ctx {
     size_t stage_bytes = 0;
     hipGraphExec_t gexec = nullptr;  // two tiled steps (even k, then odd k)
     hipGraphExec_t gexec_long = nullptr;  // kLongPairs such pairs
-    bool graph_ok = false;
+    bool graph_ok = false;           // false once a kernel argument changed (soil, sources, shape)
+    int64_t graph_builds = 0;        // graph pairs captured and instantiated so far
+    uint64_t args_gen = 0;           // bumped whenever a kernel argument changes
     std::vector<int32_t> forced_in, forced_qb;  // inflow / bed-source cells (flat indices)
     int shape = kDefaultShape;       // index into kShapes
     size_t max_tiles = 0;            // tile count of the smallest shape (flag capacity)
@@ -2090,6 +2092,7 @@ void set_shape(sw_ctx *c, int shape)
     c->nty = (c->ny + kShapes[shape].ty - 1) / kShapes[shape].ty;
     c->dirty = true;
     c->graph_ok = false;
+    c->args_gen++;
 }
 
 Inst make_inst(const sw_ctx *c, const StepArgs &A)
@@ -2265,8 +2268,9 @@ int prepare(sw_ctx *c)
                            c->H[cur], c->qx[cur], c->qy[cur], c->b[cur]);
     }
     HIPCHK(c, hipGetLastError());
+    // the captured graphs stay valid: a new state, bed or time lands in the
+    // same planes and control block, so the kernel arguments are unchanged
     c->dirty = false;
-    c->graph_ok = false;
     return SW_OK;
 }
 
@@ -2339,6 +2343,7 @@ int ensure_graph(sw_ctx *c, const KPar &P, const StepArgs &A)
     if (!rc) rc = capture_pairs(c, P, A, kLongPairs, &c->gexec_long);
     if (rc) return rc;
     c->graph_ok = true;
+    c->graph_builds++;
     c->graph_fixed = A.mode_fixed;
     c->graph_dt = A.dt_fixed;
     return SW_OK;
@@ -2419,7 +2424,9 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
     if (!grid || !params || !out) return SW_ERR_ARG;
     *out = nullptr;
     if (grid->nx < 1 || grid->ny < 1 || !(grid->dx > 0.0)) return SW_ERR_ARG;
-    if ((int64_t)grid->nx * grid->ny > (int64_t)1 << 31) return SW_ERR_ARG;
+    // the strip kernels address a plane with one 32-bit byte offset from its
+    // base: a pitched plane must stay below 4 GiB (2^30 cells)
+    if ((int64_t)((grid->nx + 63) / 64 * 64) * grid->ny * 4 >= ((int64_t)1 << 32)) return SW_ERR_ARG;
     for (int s = 0; s < 4; ++s)
         if (grid->bc[s] != SW_BC_WALL && grid->bc[s] != SW_BC_OPEN) return SW_ERR_ARG;
     if (params->sed_law < SW_SED_NONE || params->sed_law > SW_SED_EQ4) return SW_ERR_ARG;
@@ -2571,6 +2578,8 @@ int sw_set_soil(sw_ctx *c, const float *manning, float manning_scalar, const flo
     c->d50_s = d50_scalar;
     c->psi_s = psi_scalar;
     c->dirty = true;
+    c->graph_ok = false;
+    c->args_gen++;  // soil pointers and scalars are kernel arguments
     return SW_OK;
 }
 
@@ -2636,6 +2645,8 @@ int sw_set_inflow(sw_ctx *c, const int32_t *cell_idx, const float *weight, int32
     if (!c) return SW_ERR_ARG;
     if (n < 0) return fail(c, SW_ERR_ARG, "n must be >= 0");
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->graph_ok = false;
+    c->args_gen++;  // the hydrograph and weight plane are kernel arguments
     if (n == 0) {
         c->has_inflow = 0;
         c->forced_in.clear();
@@ -2671,6 +2682,8 @@ int sw_set_sed_sources(sw_ctx *c, const float *qb_plus, const float *qb_minus, i
 {
     if (!c) return SW_ERR_ARG;
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->graph_ok = false;
+    c->args_gen++;  // the source plane and its total are kernel arguments
     if (!qb_plus && !qb_minus) {
         (void)hipFree(c->qb);
         c->qb = nullptr;
@@ -2975,6 +2988,7 @@ int sw_get_sums(sw_ctx *c, sw_sums *out)
     out->cells_euler = (int64_t)hc.work[1];
     out->binding_term = hc.binding;
     out->error = hc.err;
+    out->graph_builds = c->graph_builds;
     return SW_OK;
 }
 
@@ -2999,6 +3013,7 @@ struct swb_ctx {
     hipGraphExec_t gexec = nullptr;
     hipGraphExec_t gexec_long = nullptr;
     bool built = false;
+    std::vector<uint64_t> gen;  // each member's args_gen when the tables were built
     std::string err;
 };
 
@@ -3058,6 +3073,8 @@ int batch_build(swb_ctx *b)
     b->ntab = (int)(table.size() / per);
     b->ndtab = (int)(dtable.size() / 2);
     b->lthr = lthr;
+    b->gen.resize(n);
+    for (int m = 0; m < n; ++m) b->gen[m] = b->mem[m]->args_gen;
     table.insert(table.end(), dtable.begin(), dtable.end());
     (void)hipFree(b->d_insts);
     (void)hipFree(b->d_table);
@@ -3102,11 +3119,14 @@ void batch_step(swb_ctx *b, hipStream_t st, int par)
                  b->cs);
 }
 
+// The member tables and graphs hold every member's kernel arguments: they are
+// rebuilt when one of them changed (soil, sources, shape).  A member with a
+// new state, bed or time only needs its set-up pass.
 bool batch_needs_build(const swb_ctx *b)
 {
     if (!b->built) return true;
-    for (const sw_ctx *c : b->mem)
-        if (c->dirty || c->shape != b->shape) return true;
+    for (size_t m = 0; m < b->mem.size(); ++m)
+        if (b->mem[m]->args_gen != b->gen[m] || b->mem[m]->shape != b->shape) return true;
     return false;
 }
 
@@ -3173,6 +3193,11 @@ int swb_advance(swb_ctx *b, int32_t nsteps)
         int rc = batch_build(b);
         if (rc) return rc;
     }
+    for (size_t m = 0; m < b->mem.size(); ++m)
+        if (b->mem[m]->dirty) {
+            int rc = prepare(b->mem[m]);
+            if (rc) return bfail(b, rc, "member " + std::to_string(m) + ": " + b->mem[m]->err);
+        }
     int32_t left = nsteps;
     auto advance_members = [&](int s) {
         for (sw_ctx *c : b->mem) c->k += s;

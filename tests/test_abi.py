@@ -56,3 +56,18 @@ def test_product_path_does_not_touch_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.lower(), f"{f} mentions the oracle"
+
+
+def test_create_rejects_grids_beyond_the_32_bit_plane_offsets():
+    """sw_create checks the size limit of include/csph.h before any HIP call:
+    a pitched plane of 2^30 cells or more (the strip kernels' 32-bit byte
+    offsets) is SW_ERR_ARG, as are empty grids and a non-positive dx."""
+    from paper_2103_15196_amd import csph
+    p = csph.default_params()
+    h = ctypes.c_void_p()
+    for nx, ny, dx in ((32768, 32768, 1.0), (65536, 16384, 1.0), (32769, 32767, 1.0),
+                       (0, 10, 1.0), (10, 0, 1.0), (10, 10, 0.0), (10, 10, -1.0)):
+        g = csph.make_grid(nx, ny, dx)
+        rc = csph.lib.sw_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h))
+        assert rc == csph.SW_ERR_ARG, (nx, ny, dx, rc)
+        assert not h.value

@@ -51,6 +51,9 @@ MUTANTS = {
     "eq7_vp_term": ("h / (2.0 * vp)", "h / vp"),
     "eq7_D_term": ("h * h / (2.0 * D)", "h * h / D"),
     "shamov_exponent": ("cbrt(d50) * sqrt(cbrt(H))", "cbrt(d50) * cbrt(H)"),
+    "hydrograph_at_step_start": ("orc_hydrograph(in, t + 0.5 * dt)", "orc_hydrograph(in, t)"),
+    "hydrograph_at_step_end": ("orc_hydrograph(in, t + 0.5 * dt)", "orc_hydrograph(in, t + dt)"),
+    "hydrograph_sigma_factor": ("exp(-d * d / (2.0 * s * s))", "exp(-d * d / (s * s))"),
 }
 
 

@@ -487,3 +487,51 @@ def test_eq4_fractal_dam_break_is_ill_conditioned(oracle_mod):
     assert out[O.SED_EQ4] > 1e-4
     assert out[O.SED_GRASS] < 1e-5
     assert out[O.SED_EQ4] > 30 * out[O.SED_GRASS]
+
+
+# ---------------------------------------------------------------- inflow hydrograph
+
+def test_hydrograph_gaussian_pulse_values(oracle_mod):
+    """O0: Q(t) = Q_base + Q_peak exp(-(t - t_p)^2 / (2 s^2)) through properties
+    of the Gaussian pulse: Q_base + Q_peak at the peak, symmetric about it,
+    Q_base + Q_peak / sqrt(e) one standard deviation away, Q_base + Q_peak / 2
+    at the half-maximum points t_p +- s sqrt(2 ln 2), Q_base far away."""
+    O = oracle_mod
+    inp = O.Inputs(Q_base=100.0, Q_peak=2000.0, t_peak=120.0, t_sigma=40.0)
+    assert O.hydrograph(inp, 120.0) == 2100.0
+    for d in (3.0, 17.5, 40.0, 95.0):
+        assert O.hydrograph(inp, 120.0 + d) == pytest.approx(O.hydrograph(inp, 120.0 - d),
+                                                             rel=1e-15)
+    assert O.hydrograph(inp, 160.0) == pytest.approx(100.0 + 2000.0 / math.sqrt(math.e), rel=1e-14)
+    half = 40.0 * math.sqrt(2.0 * math.log(2.0))
+    assert O.hydrograph(inp, 120.0 + half) == pytest.approx(1100.0, rel=1e-14)
+    assert O.hydrograph(inp, 120.0 - half) == pytest.approx(1100.0, rel=1e-14)
+    assert O.hydrograph(inp, 120.0 + 40.0 * 40.0) == 100.0
+
+
+def test_inflow_volume_is_the_midpoint_rule_of_the_hydrograph(oracle_mod):
+    """O8 / R26: the source of a step is Q(t_n + dt/2) dt.  Over the rising half
+    of the pulse (t = 0 .. t_p in fixed steps) the accumulated inflow must
+    match the closed-form integral Q_base t_p + Q_peak s sqrt(pi/2)
+    erf(t_p / (s sqrt 2)) within the midpoint rule's error bound
+    t_p dt^2 max|Q''| / 24 (max|Q''| = Q_peak / s^2); evaluating Q at t_n or
+    t_n + dt would be off by about dt (Q(t_p) - Q(0)) / 2, 300 times that
+    bound.  The closed basin then holds exactly that volume."""
+    O = oracle_mod
+    n, dx = 16, 50.0
+    z = np.zeros((n, n))
+    w = W.Workload(name="pulse", nx=n, ny=n, dx=dx, bc=(0, 0, 0, 0), H=z, qx=z, qy=z, b=z,
+                   nM=0.0, d50=5e-4, psi=0.4, steps=240, cfl=0.3, sed_law=0,
+                   inflow_idx=np.array([5 * n + 5, 5 * n + 6, 9 * n + 2], dtype=np.int32),
+                   inflow_w=np.array([0.5, 0.3, 0.2]), Q_base=100.0, Q_peak=2000.0,
+                   t_peak=120.0, t_sigma=40.0)
+    p, inp, s = oracle_case(O, w)
+    dt, tp, sg = 0.5, 120.0, 40.0
+    O.run(p, inp, s, int(tp / dt), dt_fixed=dt)
+    assert s.t == pytest.approx(tp, rel=1e-15)
+    exact = 100.0 * tp + 2000.0 * sg * math.sqrt(math.pi / 2.0) * math.erf(tp / (sg * math.sqrt(2.0)))
+    bound = tp * dt * dt * (2000.0 / sg ** 2) / 24.0
+    assert abs(s.in_w - exact) <= bound
+    assert 0.5 * dt * (2100.0 - O.hydrograph(inp, 0.0)) > 300 * bound
+    V = O.volumes(p, inp, s)[0]
+    assert V == pytest.approx(s.in_w, rel=1e-13)
