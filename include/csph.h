@@ -208,6 +208,20 @@ int sw_get_fields(sw_ctx *ctx, float *h, float *hu, float *hv, float *b, int ptr
 /* FP64 global sums of the current state and the accumulated balances. */
 int sw_get_sums(sw_ctx *ctx, sw_sums *out);
 
+/* Checkpoint and resume (the Save block of Section 3, for restarts): the
+ * whole state a later step depends on -- h, hu, hv, the bed and its residual
+ * (the part of the accumulated Exner change the float32 bed has not absorbed
+ * yet), the model time and step counter, the accumulated inflow, bed-source
+ * and boundary balances -- in one host blob the caller owns.  A context
+ * created with the same grid, parameters, soil and sources that loads the
+ * blob continues bit for bit as the saved one would have.  Size from
+ * sw_checkpoint_size; save synchronises and refuses a context with a pending
+ * device error (SW_ERR_STATE); load checks the blob's header and grid
+ * (SW_ERR_ARG) and replaces the state, time and balances. */
+int sw_checkpoint_size(const sw_ctx *ctx, int64_t *bytes);
+int sw_checkpoint_save(sw_ctx *ctx, void *buf, int64_t bytes);
+int sw_checkpoint_load(sw_ctx *ctx, const void *buf, int64_t bytes);
+
 /* Text of the last error on ctx (never NULL; "" if none). */
 const char *sw_last_error(const sw_ctx *ctx);
 

@@ -86,6 +86,9 @@ SIGNATURES = [
     ("sw_get_fields", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     ("sw_get_sums", C.c_int, [_ctxp, C.POINTER(sw_sums)]),
     ("sw_last_error", C.c_char_p, [_ctxp]),
+    ("sw_checkpoint_size", C.c_int, [_ctxp, C.POINTER(C.c_int64)]),
+    ("sw_checkpoint_save", C.c_int, [_ctxp, C.c_void_p, C.c_int64]),
+    ("sw_checkpoint_load", C.c_int, [_ctxp, C.c_void_p, C.c_int64]),
     ("swb_create", C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     ("swb_destroy", C.c_int, [C.c_void_p]),
     ("swb_set_tile_shape", C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
@@ -283,6 +286,19 @@ class Solver:
         s = sw_sums()
         _check(self.ctx, lib.sw_get_sums(self.ctx, C.byref(s)))
         return s.as_dict()
+
+    def checkpoint(self) -> np.ndarray:
+        """The solver's whole state as a host blob (uint8 array) for a later restore."""
+        n = C.c_int64()
+        _check(self.ctx, lib.sw_checkpoint_size(self.ctx, C.byref(n)))
+        buf = np.empty(n.value, np.uint8)
+        _check(self.ctx, lib.sw_checkpoint_save(self.ctx, buf.ctypes.data, n.value))
+        return buf
+
+    def restore(self, blob) -> None:
+        """Continue from a blob written by checkpoint() (same grid and inputs)."""
+        a = np.ascontiguousarray(blob, dtype=np.uint8)
+        _check(self.ctx, lib.sw_checkpoint_load(self.ctx, a.ctypes.data, a.size))
 
     def reset(self, w):
         """Restart from workload ``w``'s initial bed and state (time back to 0).

@@ -417,8 +417,10 @@ __global__ void __launch_bounds__(BX * BY) k_update(KPar P, Ctrl *__restrict__ c
         float qxn = QLx - r * ((Fxe - Fxw) + (Gxn - Gxs));
         float qyn = QLy - r * ((Fye - Fyw) + (Gyn - Gys));
         float om = 1.0f - soil(P.psi, P.psi_s, c);
-        float bn = b - dt / (om * P.dx) * ((F.xJ[fe] - F.xJ[fw]) + (F.yJ[gn] - F.yJ[gs]));
-        if (P.qb) bn += dt * P.qb[c] / om;
+        float rb = P.rb ? P.rb[c] : 0.0f;
+        float bn = exner(P, dt, b, om, (F.xJ[fe] - F.xJ[fw]) + (F.yJ[gn] - F.yJ[gs]),
+                         P.qb ? P.qb[c] : 0.0f, rb);
+        if (P.rb) P.rb[c] = rb;
         if (Hn < 0.0f) Hn = 0.0f;
         if (Hn < P.eps) {
             float s = Hn * wdes(Hn, P);
@@ -721,7 +723,7 @@ struct CellNew {
 // of b (Eq. 1), negative depth clamped, momentum re-desingularised below eps.
 __device__ __forceinline__ CellNew cell_update(const KPar &P, float dt, const CellFaces &F, float h,
                                                float qx, float qy, float b, float QLx, float QLy,
-                                               float src, float psi, float qb)
+                                               float src, float psi, float qb, float &rb)
 {
     float sw = F.xHw > 0.0f ? F.thW : (F.xHw < 0.0f ? F.th : 1.0f);
     float se = F.xHe > 0.0f ? F.th : (F.xHe < 0.0f ? F.thE : 1.0f);
@@ -738,8 +740,7 @@ __device__ __forceinline__ CellNew cell_update(const KPar &P, float dt, const Ce
     float qxn = QLxc - r * ((Fxe - Fxw) + (Gxn - Gxs));
     float qyn = QLyc - r * ((Fye - Fyw) + (Gyn - Gys));
     float om = 1.0f - psi;
-    float bn = b - dt / (om * P.dx) * ((F.Je - F.Jw) + (F.Jn - F.Js));
-    if (P.qb) bn += dt * qb / om;
+    float bn = exner(P, dt, b, om, (F.Je - F.Jw) + (F.Jn - F.Js), qb, rb);
     if (Hn < 0.0f) Hn = 0.0f;
     if (Hn < P.eps) {
         float sc = Hn * wdes(Hn, P);
@@ -976,9 +977,11 @@ __device__ __forceinline__ void euler_tile(const Inst &I, int par, int bx, int b
         F.Jn = sed_flux(P, j + 1, ny, wS, wN, 1, rjx[cy][cx], rjy[cy][cx], rb[cy][cx],
                         rjx[cy + 1][cx], rjy[cy + 1][cx], rb[cy + 1][cx]);
         float src = P.srcw ? P.srcw[c] * (float)ctrl->qmid[par] : 0.0f;
+        float rbc = P.rb ? P.rb[c] : 0.0f;
         CellNew o = cell_update(P, dt, F, SH[c], Sqx[c], Sqy[c], Sb[c], QLx[c], QLy[c], src,
-                                soil(P.psi, P.psi_s, c), P.qb ? P.qb[c] : 0.0f);
+                                soil(P.psi, P.psi_s, c), P.qb ? P.qb[c] : 0.0f, rbc);
         OH[c] = o.H; Oqx[c] = o.qx; Oqy[c] = o.qy; Ob[c] = o.b;
+        if (P.rb) P.rb[c] = rbc;
         boundary_balances(P, bnd, dtd * (double)P.dx, i, j, o, F);
         cell_maxima(P, o.H, o.qx, o.qy, o.b, c, mv, ms, mD, bad);
         if (o.H > 0.0f) s_flag = 1;
@@ -1330,8 +1333,11 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
                 F.yHn = Y2.H; F.ynn = Y2.n; F.ytn = Y2.t;
                 F.Jw = xs3; F.Js = ys3; F.Jn = ys2;
                 const float src = P.srcw ? usrc * qmid : 0.0f;
-                const CellNew o = cell_update(P, dt, F, uh, uqx, uqy, ub, uLx, uLy, src, upsi, uqb);
+                float rbc = P.rb ? at(P.rb, uo) : 0.0f;
+                const CellNew o = cell_update(P, dt, F, uh, uqx, uqy, ub, uLx, uLy, src, upsi, uqb,
+                                              rbc);
                 put(OH, uo, o.H); put(Oqx, uo, o.qx); put(Oqy, uo, o.qy); put(Ob, uo, o.b);
+                if (P.rb) put(P.rb, uo, rbc);
                 boundary_balances(P, I.bnd, wdx, i, ju, o, F);
                 float njx, njy, njm;
                 cell_maxima_j(P, o.H, o.qx, o.qy, o.b, unM, ud50, upsi, mv, ms, mD, bad, njx, njy,
@@ -1821,7 +1827,9 @@ __global__ void __launch_bounds__(SUM_THREADS) k_sums1(KPar P, const float *__re
             int c = j * P.pitch + i;
             float h = H[c];
             sw += (double)h;
-            ss += (1.0 - (double)soil(P.psi, P.psi_s, c)) * (double)b[c];
+            // the accumulated bed: the stored float plus its residual
+            const double bc = (double)b[c] + (P.rb ? (double)P.rb[c] : 0.0);
+            ss += (1.0 - (double)soil(P.psi, P.psi_s, c)) * bc;
             wet += h > 0.0f ? 1.0 : 0.0;
         }
     sw = wave_sum(sw); ss = wave_sum(ss); wet = wave_sum(wet);
@@ -1874,6 +1882,7 @@ struct sw_ctx {
     float *H[2]{}, *qx[2]{}, *qy[2]{}, *b[2]{};
     float *QLx = nullptr, *QLy = nullptr;
     float *jx[2]{}, *jy[2]{}, *jm[2]{};  // J0 and |J0| per buffer level
+    float *rb = nullptr;             // bed residual of the compensated Exner update
     float *nM = nullptr, *d50 = nullptr, *psi = nullptr, *qb = nullptr, *srcw = nullptr;
     float nM_s = 0.0f, d50_s = 5e-4f, psi_s = 0.4f;
     float *faces = nullptr;          // unfused face arrays
@@ -1949,6 +1958,7 @@ KPar make_kpar(const sw_ctx *c)
     P.psi = c->psi; P.psi_s = c->psi_s;
     P.qb = c->qb;
     P.srcw = c->has_inflow ? c->srcw : nullptr;
+    P.rb = (c->par.sed_law != SW_SED_NONE || c->qb) ? c->rb : nullptr;
     return P;
 }
 
@@ -2452,8 +2462,8 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
             return bail(e, "hipStreamCreate");
         c->own_stream = true;
     }
-    // planes: 2 x (H, qx, qy, b), QLx, QLy
-    const int nplanes = 16;
+    // planes: 2 x (H, qx, qy, b), QLx, QLy, 2 x (J0x, J0y, |J0|), bed residual
+    const int nplanes = 17;
     if ((e = hipMalloc(&c->buf, nplanes * c->plane * sizeof(float))) != hipSuccess)
         return bail(e, "hipMalloc(state)");
     if ((e = hipMemsetAsync(c->buf, 0, nplanes * c->plane * sizeof(float), c->stream)) != hipSuccess)
@@ -2471,6 +2481,7 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
         c->jy[s] = c->buf + (11 + 3 * s) * c->plane;
         c->jm[s] = c->buf + (12 + 3 * s) * c->plane;
     }
+    c->rb = c->buf + 16 * c->plane;
     if (c->par.flags & SW_FLAG_UNFUSED) {  // face arrays of the unfused sequence only
         size_t nf = 4 * ((size_t)(c->nx + 1) * c->ny + (size_t)c->nx * (c->ny + 1));
         if ((e = hipMalloc(&c->faces, nf * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc(faces)");
@@ -2543,6 +2554,7 @@ int sw_set_bed(sw_ctx *c, const float *b, int ptr_kind)
     if (rc) return rc;
     HIPCHK(c, hipMemcpyAsync(c->b[cur ^ 1], c->b[cur], c->plane * sizeof(float),
                              hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->rb, 0, c->plane * sizeof(float), c->stream));
     c->dirty = true;
     return SW_OK;
 }
@@ -2754,6 +2766,7 @@ int sw_replace_state(sw_ctx *c, const float *h, const float *hu, const float *hv
     if ((rc = upload_plane(c, c->b[0], b, SW_PTR_DEVICE))) return rc;
     HIPCHK(c, hipMemcpyAsync(c->b[1], c->b[0], c->plane * sizeof(float), hipMemcpyDeviceToDevice,
                              c->stream));
+    HIPCHK(c, hipMemsetAsync(c->rb, 0, c->plane * sizeof(float), c->stream));
     HIPCHK(c, hipMemsetAsync(c->QLx, 0, 2 * c->plane * sizeof(float), c->stream));
     HIPCHK(c, hipMemsetAsync(c->bnd, 0, 4 * (size_t)(c->nx + c->ny) * sizeof(double), c->stream));
     Ctrl h0{};
@@ -2858,15 +2871,15 @@ int sw_autotune(sw_ctx *c, int32_t nsteps, int32_t *tile_x, int32_t *tile_y)
     const size_t nb = 4 * (size_t)(c->nx + c->ny);
     float *keep = nullptr;
     double *keepb = nullptr;
-    HIPCHK(c, hipMalloc(&keep, 4 * c->plane * sizeof(float)));
+    HIPCHK(c, hipMalloc(&keep, 5 * c->plane * sizeof(float)));
     hipError_t e = hipMalloc(&keepb, nb * sizeof(double));
     if (e != hipSuccess) {
         (void)hipFree(keep);
         return fail(c, SW_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
     }
-    float *src[4] = {c->H[cur], c->qx[cur], c->qy[cur], c->b[cur]};
+    float *src[5] = {c->H[cur], c->qx[cur], c->qy[cur], c->b[cur], c->rb};
     auto save_restore = [&](bool save) -> int {
-        for (int f = 0; f < 4; ++f) {
+        for (int f = 0; f < 5; ++f) {
             float *a = keep + f * c->plane, *b = src[f];
             HIPCHK(c, hipMemcpyAsync(save ? a : b, save ? b : a, c->plane * sizeof(float),
                                      hipMemcpyDeviceToDevice, c->stream));
@@ -2989,6 +3002,100 @@ int sw_get_sums(sw_ctx *c, sw_sums *out)
     out->binding_term = hc.binding;
     out->error = hc.err;
     out->graph_builds = c->graph_builds;
+    return SW_OK;
+}
+
+// Checkpoint blob: a fixed header, the dense planes h, hu, hv, b and the bed
+// residual of the current state, then the boundary accumulators.
+struct CkptHeader {
+    char magic[8];           // "CSPHCKP1"
+    int32_t nx, ny, ctrl_bytes, nb;
+    int64_t step;            // step counter of the saved state
+    double t;                // model time of the saved state
+    int32_t par, pad;        // buffer parity of the saved ring entries
+    Ctrl ctrl;               // device control block (time ring, source balances, maxima)
+};
+
+static size_t ckpt_bytes(const sw_ctx *c)
+{
+    const size_t n = (size_t)c->nx * c->ny, nb = 4 * (size_t)(c->nx + c->ny);
+    return sizeof(CkptHeader) + 5 * n * sizeof(float) + nb * sizeof(double);
+}
+
+int sw_checkpoint_size(const sw_ctx *c, int64_t *bytes)
+{
+    if (!c || !bytes) return SW_ERR_ARG;
+    *bytes = (int64_t)ckpt_bytes(c);
+    return SW_OK;
+}
+
+int sw_checkpoint_save(sw_ctx *c, void *buf, int64_t bytes)
+{
+    if (!c || !buf) return SW_ERR_ARG;
+    if (bytes < (int64_t)ckpt_bytes(c)) return fail(c, SW_ERR_ARG, "checkpoint buffer too small");
+    if (!c->have_state) return fail(c, SW_ERR_STATE, "checkpoint before sw_set_state");
+    CkptHeader h;
+    std::memset(&h, 0, sizeof(h));
+    int rc = read_ctrl(c, &h.ctrl);
+    if (rc) return rc;
+    if (h.ctrl.err) return fail(c, SW_ERR_STATE, "checkpoint with a pending device error");
+    std::memcpy(h.magic, "CSPHCKP1", 8);
+    h.nx = c->nx;
+    h.ny = c->ny;
+    h.ctrl_bytes = (int32_t)sizeof(Ctrl);
+    h.nb = 4 * (c->nx + c->ny);
+    h.par = (int32_t)(c->k & 1);
+    h.step = c->step0 + c->k;
+    h.t = h.ctrl.t[h.par];
+    char *out = (char *)buf;
+    std::memcpy(out, &h, sizeof(h));
+    out += sizeof(h);
+    const size_t n = (size_t)c->nx * c->ny;
+    const int cur = h.par;
+    const float *planes[5] = {c->H[cur], c->qx[cur], c->qy[cur], c->b[cur], c->rb};
+    for (int f = 0; f < 5; ++f, out += n * sizeof(float))
+        if ((rc = download_plane(c, (float *)out, planes[f], SW_PTR_HOST))) return rc;
+    return stage_to_host(c, out, c->bnd, (size_t)h.nb * sizeof(double));
+}
+
+int sw_checkpoint_load(sw_ctx *c, const void *buf, int64_t bytes)
+{
+    if (!c || !buf) return SW_ERR_ARG;
+    if (bytes < (int64_t)sizeof(CkptHeader)) return fail(c, SW_ERR_ARG, "checkpoint too short");
+    CkptHeader h;
+    std::memcpy(&h, buf, sizeof(h));
+    if (std::memcmp(h.magic, "CSPHCKP1", 8) != 0 || h.ctrl_bytes != (int32_t)sizeof(Ctrl))
+        return fail(c, SW_ERR_ARG, "not a checkpoint of this library");
+    if (h.nx != c->nx || h.ny != c->ny || h.nb != 4 * (c->nx + c->ny))
+        return fail(c, SW_ERR_ARG, "checkpoint of another grid");
+    if (bytes < (int64_t)ckpt_bytes(c)) return fail(c, SW_ERR_ARG, "checkpoint too short");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const char *in = (const char *)buf + sizeof(h);
+    const size_t n = (size_t)c->nx * c->ny;
+    c->k = 0;
+    float *planes[5] = {c->H[0], c->qx[0], c->qy[0], c->b[0], c->rb};
+    int rc;
+    for (int f = 0; f < 5; ++f, in += n * sizeof(float))
+        if ((rc = upload_plane(c, planes[f], (const float *)in, SW_PTR_HOST))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->b[1], c->b[0], c->plane * sizeof(float), hipMemcpyDeviceToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemsetAsync(c->QLx, 0, 2 * c->plane * sizeof(float), c->stream));
+    if ((rc = stage_to_device(c, c->bnd, in, (size_t)h.nb * sizeof(double)))) return rc;
+    // the saved control block with its ring entries moved to parity 0
+    Ctrl k0 = h.ctrl;
+    std::memset(k0.slot, 0, sizeof(k0.slot));
+    k0.t[0] = h.t;
+    k0.t[1] = h.t;
+    k0.dt[0] = h.ctrl.dt[h.par];
+    k0.qmid[0] = h.ctrl.qmid[h.par];
+    k0.kdev = 0;
+    k0.err = 0;
+    k0.err_k = 0;
+    if ((rc = stage_to_device(c, c->ctrl, &k0, sizeof(Ctrl)))) return rc;
+    c->t0 = h.t;
+    c->step0 = h.step;
+    c->have_state = true;
+    c->dirty = true;
     return SW_OK;
 }
 

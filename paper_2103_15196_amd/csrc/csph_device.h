@@ -34,6 +34,7 @@ struct KPar {
     const float *psi; float psi_s;  // porosity
     const float *qb;                // q_b^+ - q_b^- per cell, or null
     const float *srcw;              // inflow weight / dx^2 per cell, or null
+    float *rb;                      // bed residual per cell (null: the bed cannot change)
 };
 
 __device__ __forceinline__ float soil(const float *a, float s, int c) { return a ? a[c] : s; }
@@ -130,6 +131,25 @@ __device__ __forceinline__ void bedload(const KPar &P, float H, float u, float v
     }
     jx = f * u;
     jy = f * v;
+}
+
+// Exner update of Eq. 1 for one cell with the bedload divergence dJ (the sum
+// of the four face-flux differences) and the bed source qb = q_b^+ - q_b^-,
+// compensated: rb carries the part of the earlier updates the float32 bed
+// could not hold (the stored bed is the nearest float to the accumulated bed
+// b + rb), so bed changes smaller than half an ulp of the elevation add up
+// instead of rounding away.  The rounding error of b + d is recovered exactly
+// by Knuth's two-sum.
+__device__ __forceinline__ float exner(const KPar &P, float dt, float b, float om, float dJ,
+                                       float qb, float &rb)
+{
+    float d = -(dt / (om * P.dx)) * dJ;
+    if (P.qb) d += dt * qb / om;
+    d += rb;
+    const float bn = b + d;
+    const float bv = bn - b;
+    rb = (b - (bn - bv)) + (d - bv);
+    return bn;
 }
 
 // Hydrostatic-face force along one direction on cell C from its neighbours

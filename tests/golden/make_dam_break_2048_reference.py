@@ -1,17 +1,22 @@
-"""Write tests/golden/dam_break_2048_ref.npz: the FP64 oracle's state after
-1000 steps of the 2048 x 2048 fractal dam break (dx = 2 m, seed 2, 10 m relief,
-1 m dam line, 8 m reservoir, open boundaries, psi = 0.4, n = 0.03, Grass bedload
-with d50 = 0.5 mm for the critical speed, K = 0.3), started from the
-float32-rounded inputs.
+"""Write tests/golden/dam_break_2048_ref.npz: what the FP64 oracle fixes about the
+2048 x 2048 fractal dam break (dx = 2 m, seed 2, 10 m relief, 1 m dam line,
+8 m reservoir, open boundaries, psi = 0.4, n = 0.03, Grass bedload with
+d50 = 0.5 mm for the critical speed, K = 0.3) after 1000 steps, started from
+the float32-rounded inputs.
 
-Stored: every 16th cell in each direction of h, hu, hv, b (float64), the wet
-mask (h > 1e-4 m) of every cell (bit-packed), the water volume, boundary
-outflow and model time, and the run's step count.  A second oracle run from
-the same inputs with the initial depth multiplied by (1 + 1e-7 N(0,1))
-(seeded; float32 rounding level) stores its sampled depth as h_pert: the
-spread |h - h_pert| measures how strongly this flow amplifies rounding-level
-differences, cell by cell.  Only the oracle and the seeded input generator are
-called.  Takes ~20 minutes on 8 cores.
+Stored:
+* every 16th cell in each direction of h, hu, hv, b (float64), the wet mask
+  (h > 1e-4 m) of every cell (bit-packed), the water volume, boundary outflow,
+  model time and the Eq. 7 maximum of |v| + c of the final state;
+* the oracle's sensitivity to the float32 rounding of its inputs: a second
+  oracle run from the same scenario's float64 inputs (not rounded).  For each
+  field, every cell where the two runs differ by more than 5e-6 m (h, b) or
+  5e-6 m times max(|v| + c) (hu, hv) is listed with that spread (flat index,
+  float32 spread): the cells where this flow amplifies rounding-level
+  differences of the input.
+
+Only the oracle and the seeded input generator are called.  Takes about
+20 minutes on 8 cores.
 """
 import os
 import sys
@@ -29,6 +34,7 @@ from tests.helpers import oracle_case  # noqa: E402
 
 STEPS = 1000
 STRIDE = 16
+LIST_H = 5e-6   # m: spreads listed for h and b above this
 OUT = os.path.join(HERE, "dam_break_2048_ref.npz")
 
 
@@ -43,20 +49,30 @@ def run(w, label):
     return p, inp, s, V0
 
 
+def sparse(d, thr):
+    idx = np.flatnonzero(d.reshape(-1) > thr).astype(np.int32)
+    return idx, d.reshape(-1)[idx].astype(np.float32)
+
+
 def main():
     O.build(force=False)
     w = W.dam_break_fractal(n=2048, steps=STEPS).as_float32()
     p, inp, s, V0 = run(w, "reference")
     Vw, Vs = O.volumes(p, inp, s)
+    vs = O.cfl(p, inp, s)["vs"]
     sl = (slice(0, None, STRIDE), slice(0, None, STRIDE))
-    wp = W.dam_break_fractal(n=2048, steps=STEPS).as_float32()
-    rng = np.random.default_rng(1)
-    wp.H = wp.H * (1.0 + 1e-7 * rng.standard_normal(wp.H.shape))
-    _, _, sp, _ = run(wp, "perturbed")
+    wp = W.dam_break_fractal(n=2048, steps=STEPS)
+    _, _, sp, _ = run(wp, "float64 inputs")
+    lists = {}
+    for name, a, b, thr in (("h", s.H, sp.H, LIST_H), ("hu", s.qx, sp.qx, LIST_H * vs),
+                            ("hv", s.qy, sp.qy, LIST_H * vs), ("b", s.b, sp.b, LIST_H)):
+        idx, val = sparse(np.abs(a - b), thr)
+        lists[f"spread_{name}_idx"], lists[f"spread_{name}"] = idx, val
+        print(f"{name}: {idx.size} cells spread > {thr:.2e}, max {np.abs(a - b).max():.3e}")
     np.savez_compressed(
-        OUT, steps=STEPS, stride=STRIDE, t=s.t, V0=V0, Vw=Vw, Vs=Vs, out_w=s.out_w,
-        h=s.H[sl], hu=s.qx[sl], hv=s.qy[sl], b=s.b[sl], h_pert=sp.H[sl],
-        wet_bits=np.packbits((s.H > 1e-4).reshape(-1)))
+        OUT, steps=STEPS, stride=STRIDE, t=s.t, V0=V0, Vw=Vw, Vs=Vs, out_w=s.out_w, vs=vs,
+        list_h=LIST_H, h=s.H[sl], hu=s.qx[sl], hv=s.qy[sl], b=s.b[sl],
+        wet_bits=np.packbits((s.H > 1e-4).reshape(-1)), **lists)
     print(f"wrote {OUT} ({os.path.getsize(OUT) / 1e3:.0f} kB)")
 
 

@@ -41,33 +41,42 @@ def test_gpu_new_state_keeps_the_step_graphs():
     s.close()
 
 
-def test_gpu_resume_from_saved_fields_is_bitwise():
-    """Save mid-run (fields, time, step), restore them into a fresh solver and
-    continue: identical bits to the uninterrupted run, inflow hydrograph
-    included (the step depends only on the state, the bed and the time)."""
+def test_gpu_resume_from_a_checkpoint_is_bitwise():
+    """Checkpoint mid-run, load the blob into a fresh solver and continue:
+    identical fields, time, step and balances to the uninterrupted run
+    (inflow hydrograph, per-cell soil, bed sources, open boundary)."""
     from paper_2103_15196_amd import csph
     w = _small_valley()
+    w.qb = np.zeros((w.ny, w.nx))
+    w.qb[60:70, 100:110] = 2e-6
     st = torch_stream()
     ref = csph.solver_for(w, stream=st)
     ref.advance(300)
     f_ref, s_ref = ref.get_fields(), ref.get_sums()
     ref.close()
     a = csph.solver_for(w, stream=st)
-    a.advance(170)
-    h, hu, hv, b = a.get_fields()
+    a.advance(171)
+    blob = a.checkpoint()
     sa = a.get_sums()
     a.close()
-    say(f"saved at step {sa['step']}, t = {sa['t']:.6f} s")
+    say(f"checkpoint at step {sa['step']}, t = {sa['t']:.6f} s, {blob.size} bytes")
     r = csph.solver_for(w, stream=st)
-    r.set_bed(b)
-    r.set_state(h, hu, hv)
-    r.set_time(sa["t"], sa["step"])
-    r.advance(130)
+    r.advance(7)                   # whatever it held before is replaced
+    r.restore(blob)
+    assert r.get_sums()["step"] == 171
+    r.advance(129)
     f, s = r.get_fields(), r.get_sums()
-    r.close()
     for x, y in zip(f, f_ref):
         assert np.array_equal(x, y)
-    assert s["t"] == s_ref["t"] and s["step"] == s_ref["step"] == 300
+    for k in ("t", "step", "water_volume", "sediment_volume", "water_boundary_out",
+              "water_source_in", "sed_boundary_out", "sed_source_in"):
+        assert s[k] == s_ref[k], k
+    other = csph.Solver(w.nx + 1, w.ny, w.dx, w.bc, stream=st)
+    with pytest.raises(csph.SwError) as e:
+        other.restore(blob)
+    assert e.value.code == csph.SW_ERR_ARG
+    other.close()
+    r.close()
 
 
 def test_gpu_nonfinite_state_is_raised_by_the_device():

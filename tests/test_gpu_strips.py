@@ -109,3 +109,37 @@ def test_gpu_strips_long_lists_take_several_passes():
         for shape in ((58, 8), (58, 32)):
             say(f"strip {shape}, {name}, 8192x2048, 30 steps")
             _same(run_gpu(case, 30, flags=flags, shape=shape), ref, f"{name} {shape}")
+
+
+def test_gpu_strips_pass_kernels_with_per_cell_soil_vs_tiles_and_oracle():
+    """The kernels the 8192^2 river valley runs: 58 x 8 strips on more than
+    32 Ki tiles (here 8192 x 2048: 36352 tiles, two passes) with per-cell
+    soil planes (Manning n, d50, psi), bed sources and an inflow hydrograph.
+    Every tile listed (skipping off) and dry tiles skipped give the bits of
+    the 64 x 8 LDS tiles; after 20 steps of an all-wet start every cell of
+    h, hu, hv, b agrees with the FP64 oracle within the precision bounds."""
+    from paper_2103_15196_amd import csph
+    from oracle import oracle as O
+    from tests.gpu_common import field_check, run_oracle
+    O.build(force=False)
+    w = W.river_valley(n=8192, ny=2048, dx=5.0, wavelength=3000.0, amplitude=300.0)
+    rng = np.random.default_rng(17)
+    w.nM = rng.uniform(0.02, 0.04, size=(w.ny, w.nx))
+    w.qb = np.zeros((w.ny, w.nx))
+    w.qb[900:940, 3000:3100] = 5e-6
+    w.qb[100:110, 7000:7010] = -1e-6
+    w.H = np.full((w.ny, w.nx), 0.5)
+    w = w.as_float32()
+    steps = 20
+    say("river valley 8192x2048 per-cell soil: 64x8 tiles")
+    ref = run_gpu(w, steps, shape=(64, 8))
+    for flags in (csph.SW_FLAG_HGS, 0):
+        say(f"  58x8 strips (two passes), flags {flags}")
+        _same(run_gpu(w, steps, flags=flags), ref, f"flags {flags}")
+    say("  oracle")
+    p, inp, st = run_oracle(O, w, steps)
+    f = field_check(ref[0], st, None, O.cfl(p, inp, st)["vs"])
+    for name, r in f.items():
+        say(f"  {name}: err {r['err']:.3e} (bound {r['bound']:.3e}) at {r['worst']}")
+        assert r["err"] <= r["bound"], name
+    assert abs(ref[1]["t"] - st.t) <= 1e-5 * st.t
