@@ -225,6 +225,40 @@ int sw_checkpoint_load(sw_ctx *ctx, const void *buf, int64_t bytes);
 /* Text of the last error on ctx (never NULL; "" if none). */
 const char *sw_last_error(const sw_ctx *ctx);
 
+/* Allocation-free advance, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It runs the kernels of sw_advance (default 58x8 strip shape,
+ * skipping dry tiles if params->flags has SW_FLAG_HGS) on a state the caller
+ * owns, with every other buffer taken from one file-scope device array of
+ * SW_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends.  It calls no hipMalloc, hipFree, memset or memcpy:
+ * set-up, loading and readback are kernels, all ordered on hip_stream (NULL:
+ * the null stream), and nothing synchronises.
+ *  - h, hu, hv, b: device arrays [ny][nx] on the current GPU, read as the
+ *    state at time t0 and overwritten with the state after nsteps steps (or,
+ *    after a device error, the state at the start of the failing step).
+ *    Scalar soil manning, d50, psi; no inflow and no bed sources.
+ *  - dt_fixed = 0: the Eq. 7 step; dt_fixed > 0: that fixed step (a step
+ *    above its Eq. 7 bound raises SW_ERR_CFL on the device).
+ *  - t_out (device double, may be NULL): the model time of the returned state.
+ *  - err_out (device int32, may be NULL): 0, or the device error
+ *    (SW_ERR_NONFINITE, SW_ERR_DT_UNDERFLOW, SW_ERR_CFL, or SW_ERR_ARG for a
+ *    negative or non-finite input, in which case no step runs).
+ *  - errbuf (host, may be NULL): a message for a non-zero return.
+ * Returns SW_ERR_ARG without touching the GPU for bad arguments or a grid
+ * whose buffers do not fit the array (about 17 x 4 bytes per padded cell:
+ * rows padded to a multiple of 64, up to 1,048,576 padded cells, e.g.
+ * 1024 x 1024 or 2048 x 512); SW_ERR_HIP if a launch fails.  Every call on a
+ * GPU shares that GPU's array and leaves its contents behind: calls that
+ * overlap on one GPU (other streams, other host threads) race and must be
+ * serialised by the caller.  The results are bit-identical to sw_create +
+ * sw_set_bed/soil/state + sw_set_time(t0) + sw_advance on the same inputs. */
+#define SW_NOALLOC_SCRATCH_BYTES (72u << 20)
+int sw_advance_noalloc(const sw_grid *grid, const sw_params *params, float manning, float d50,
+                       float psi, float *h, float *hu, float *hv, float *b, int32_t nsteps,
+                       double dt_fixed, double t0, double *t_out, int32_t *err_out,
+                       void *hip_stream, char *errbuf, int32_t errbuf_len);
+
 /* ------------------------------------------------------------------------
  * Ensembles: many grids (uneven sizes, own terrain, soil, inflow and Eq. 7
  * step) advanced together.  Each step is one launch of the Eq. 7 reduction

@@ -98,6 +98,10 @@ SIGNATURES = [
     ("sw_replace_state", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_double, C.c_int64]),
     ("sw_get_grid", C.c_int, [_ctxp, C.POINTER(sw_grid)]),
+    ("sw_advance_noalloc", C.c_int, [C.POINTER(sw_grid), C.POINTER(sw_params), C.c_float, C.c_float,
+                                     C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_int32, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_char_p, C.c_int32]),
     ("sws_create", C.c_int, [C.POINTER(C.c_int32), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
     ("sws_destroy", C.c_int, [C.c_void_p]),
     ("sws_param_count", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
@@ -326,6 +330,31 @@ def solver_for(w, stream=None, **params) -> Solver:
     s = Solver(w.nx, w.ny, w.dx, w.bc, stream=stream, **kw)
     s.load_workload(w)
     return s
+
+
+SW_NOALLOC_SCRATCH_BYTES = 72 << 20
+
+
+def advance_noalloc(grid, params, manning, d50, psi, h, hu, hv, b, nsteps, dt_fixed=0.0, t0=0.0,
+                    t_out=None, err_out=None, stream=None):
+    """sw_advance_noalloc on device tensors h, hu, hv, b ([ny, nx] float32,
+    updated in place); t_out (float64) and err_out (int32) are optional
+    one-element device tensors.  Raises SwError on a non-zero return."""
+    ptrs = []
+    for a in (h, hu, hv, b):
+        if a is None:
+            ptrs.append(None)
+            continue
+        assert a.is_cuda and a.is_contiguous() and a.numel() == grid.nx * grid.ny
+        ptrs.append(C.c_void_p(a.data_ptr()))
+    tp = C.c_void_p(t_out.data_ptr()) if t_out is not None else None
+    ep = C.c_void_p(err_out.data_ptr()) if err_out is not None else None
+    msg = C.create_string_buffer(256)
+    rc = lib.sw_advance_noalloc(C.byref(grid), C.byref(params), float(manning), float(d50),
+                                float(psi), *ptrs, int(nsteps), float(dt_fixed), float(t0), tp, ep,
+                                C.c_void_p(stream) if stream is not None else None, msg, 256)
+    if rc != SW_OK:
+        raise SwError(rc, msg.value.decode())
 
 
 def _bcheck(b, rc):

@@ -12,9 +12,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdarg>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -3100,6 +3102,256 @@ int sw_checkpoint_load(sw_ctx *c, const void *buf, int64_t bytes)
 }
 
 const char *sw_last_error(const sw_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"
+
+// ===========================================================================
+// Allocation-free advance: the kernels of sw_advance on the default strip
+// shape, with every buffer they need (both state levels, the Lagrangian
+// momentum, the J0 planes, the bed residual, the boundary accumulators, tile
+// flags and maxima, work lists, control block) carved from one file-scope
+// device array.  Loading, set-up and readback are kernels too (no memset or
+// memcpy nodes), so the whole call can be captured into a HIP graph.
+// ===========================================================================
+
+static __device__ __align__(256) unsigned char scratch[SW_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+// Device address of `scratch` on each GPU (hipGetSymbolAddress, taken once
+// per device with that device current): host code never passes the array's
+// own name to a kernel or a runtime call.
+unsigned char *g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// Offsets (bytes, 256-aligned) of the parts of the array for one grid.
+struct NoallocLayout {
+    size_t planes, bnd, tflags, tmax, sched, ctrl, total;
+    int pitch, ntx, nty, chunks;
+    size_t plane, tiles;
+};
+
+size_t up256(size_t x) { return (x + 255) / 256 * 256; }
+
+NoallocLayout noalloc_layout(int nx, int ny)
+{
+    NoallocLayout L{};
+    L.pitch = (nx + 63) / 64 * 64;
+    L.plane = (size_t)L.pitch * ny;
+    L.ntx = (nx + kShapes[kDefaultShape].tx - 1) / kShapes[kDefaultShape].tx;
+    L.nty = (ny + kShapes[kDefaultShape].ty - 1) / kShapes[kDefaultShape].ty;
+    L.tiles = (size_t)L.ntx * L.nty;
+    const int ch = list_chunk((int)L.tiles);
+    L.chunks = ((int)L.tiles + ch - 1) / ch;
+    L.planes = 0;
+    L.bnd = up256(17 * L.plane * sizeof(float));
+    L.tflags = L.bnd + up256(4 * (size_t)(nx + ny) * sizeof(double));
+    L.tmax = L.tflags + up256(4 * L.tiles);
+    L.sched = L.tmax + up256(2 * L.tiles * sizeof(uint4));
+    L.ctrl = L.sched + up256(sched_layout(L.chunks, L.tiles).total * sizeof(int));
+    L.total = L.ctrl + up256(sizeof(Ctrl));
+    return L;
+}
+
+// Zero a 4-byte-word range of the array (grid-stride).
+__global__ void k_noalloc_zero(uint32_t *p, size_t n)
+{
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (size_t)gridDim.x * blockDim.x)
+        p[q] = 0u;
+}
+
+// Fresh control block with the model time t0.
+__global__ void k_noalloc_ctrl(Ctrl *ctrl, double t0)
+{
+    uint32_t *w = reinterpret_cast<uint32_t *>(ctrl);
+    for (size_t q = threadIdx.x; q < sizeof(Ctrl) / 4; q += blockDim.x) w[q] = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) ctrl->t[0] = t0;
+}
+
+// The caller's dense [ny][nx] state and bed into the pitched planes of level
+// 0 (the bed into both levels); a cell with zero depth gets zero discharge.
+// A negative or non-finite depth, or a non-finite discharge or bed, raises
+// SW_ERR_ARG in the control block before step 0, so no step runs.
+__global__ void k_noalloc_load(KPar P, Ctrl *ctrl, const float *__restrict__ h,
+                               const float *__restrict__ hu, const float *__restrict__ hv,
+                               const float *__restrict__ b, float *H, float *Qx, float *Qy,
+                               float *B0, float *B1)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= P.nx) return;
+    const size_t s = (size_t)j * P.nx + i, d = (size_t)j * P.pitch + i;
+    float hh = h[s], u = hu[s], v = hv[s];
+    const float bb = b[s];
+    if (!(hh >= 0.0f) || !isfinite(hh) || !isfinite(u) || !isfinite(v) || !isfinite(bb))
+        ctrl->err = SW_ERR_ARG;  // the same value from every failing lane; err_k stays 0
+    if (hh == 0.0f) { hh = 0.0f; u = 0.0f; v = 0.0f; }
+    H[d] = hh; Qx[d] = u; Qy[d] = v; B0[d] = bb; B1[d] = bb;
+}
+
+// The current state (level nsteps & 1, or the start of the failing step after
+// a device error) back into the caller's dense arrays; the model time and the
+// error code into the optional device outputs.
+__global__ void k_noalloc_store(KPar P, const Ctrl *__restrict__ ctrl, int nsteps, Inst I,
+                                float *h, float *hu, float *hv, float *b, double *t_out,
+                                int32_t *err_out)
+{
+    const int cur = ctrl->err ? (ctrl->err_k & 1) : (nsteps & 1);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i == 0 && j == 0) {
+        if (t_out) *t_out = ctrl->t[cur];
+        if (err_out) *err_out = ctrl->err;
+    }
+    if (i >= P.nx) return;
+    const size_t s = (size_t)j * P.nx + i, d = (size_t)j * P.pitch + i;
+    h[s] = I.H[cur][d]; hu[s] = I.qx[cur][d]; hv[s] = I.qy[cur][d]; b[s] = I.b[cur][d];
+}
+
+// Message for the caller's buffer (no heap allocation on any path).
+int noalloc_fail(char *errbuf, int32_t errbuf_len, int code, const char *fmt, ...)
+{
+    if (errbuf && errbuf_len > 0) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(errbuf, (size_t)errbuf_len, fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+// The array's address on the current device (looked up on the first call).
+int noalloc_scratch(unsigned char **out, char *errbuf, int32_t errbuf_len)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return noalloc_fail(errbuf, errbuf_len, SW_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return noalloc_fail(errbuf, errbuf_len, SW_ERR_ARG, "device %d beyond the library's table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return noalloc_fail(errbuf, errbuf_len, SW_ERR_HIP, "hipGetSymbolAddress(scratch): %s",
+                                hipGetErrorString(e));
+        g_scratch[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch[dev];
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sw_advance_noalloc(const sw_grid *grid, const sw_params *params, float manning, float d50,
+                       float psi, float *h, float *hu, float *hv, float *b, int32_t nsteps,
+                       double dt_fixed, double t0, double *t_out, int32_t *err_out,
+                       void *hip_stream, char *errbuf, int32_t errbuf_len)
+{
+    auto bad = [&](const char *m) { return noalloc_fail(errbuf, errbuf_len, SW_ERR_ARG, "%s", m); };
+    if (errbuf && errbuf_len > 0) errbuf[0] = '\0';
+    if (!grid || !params) return bad("grid or params is NULL");
+    if (!h || !hu || !hv || !b) return bad("a field pointer is NULL");
+    if (grid->nx < 1 || grid->ny < 1 || !(grid->dx > 0.0)) return bad("nx, ny must be >= 1 and dx > 0");
+    if (grid->nx > (1 << 24) || grid->ny > (1 << 24)) return bad("grid larger than the scratch array");
+    for (int s = 0; s < 4; ++s)
+        if (grid->bc[s] != SW_BC_WALL && grid->bc[s] != SW_BC_OPEN) return bad("unknown boundary kind");
+    if (params->sed_law < SW_SED_NONE || params->sed_law > SW_SED_EQ4) return bad("unknown sediment law");
+    if (!(params->cfl > 0.0) || !(params->g > 0.0) || !(params->eps_dry > 0.0))
+        return bad("cfl, g and eps_dry must be > 0");
+    if (params->flags & SW_FLAG_UNFUSED) return bad("the unfused sequence is not available here");
+    if (!(manning >= 0.0f) || !(d50 > 0.0f) || !(psi >= 0.0f && psi < 1.0f))
+        return bad("manning >= 0, d50 > 0 and 0 <= psi < 1 are required");
+    if (nsteps < 0) return bad("nsteps must be >= 0");
+    if (!(dt_fixed >= 0.0) || !std::isfinite(dt_fixed) || !std::isfinite(t0))
+        return bad("dt_fixed must be finite and >= 0, t0 finite");
+    const NoallocLayout L = noalloc_layout(grid->nx, grid->ny);
+    if (L.total > (size_t)SW_NOALLOC_SCRATCH_BYTES)
+        return noalloc_fail(errbuf, errbuf_len, SW_ERR_ARG,
+                            "a %d x %d grid needs %zu bytes of scratch, more than the %zu the "
+                            "library holds", grid->nx, grid->ny, L.total,
+                            (size_t)SW_NOALLOC_SCRATCH_BYTES);
+    unsigned char *base = nullptr;
+    int rc = noalloc_scratch(&base, errbuf, errbuf_len);
+    if (rc) return rc;
+
+    // a context on the stack whose buffers all lie in the array (nothing of
+    // it is allocated: its strings and vectors stay empty)
+    sw_ctx c;
+    c.grid = *grid;
+    c.par = *params;
+    c.stream = (hipStream_t)hip_stream;
+    c.nx = grid->nx;
+    c.ny = grid->ny;
+    c.pitch = L.pitch;
+    c.plane = L.plane;
+    c.buf = reinterpret_cast<float *>(base + L.planes);
+    for (int s = 0; s < 2; ++s) {
+        c.H[s] = c.buf + (4 * s + 0) * c.plane;
+        c.qx[s] = c.buf + (4 * s + 1) * c.plane;
+        c.qy[s] = c.buf + (4 * s + 2) * c.plane;
+        c.b[s] = c.buf + (4 * s + 3) * c.plane;
+    }
+    c.QLx = c.buf + 8 * c.plane;
+    c.QLy = c.buf + 9 * c.plane;
+    for (int s = 0; s < 2; ++s) {
+        c.jx[s] = c.buf + (10 + 3 * s) * c.plane;
+        c.jy[s] = c.buf + (11 + 3 * s) * c.plane;
+        c.jm[s] = c.buf + (12 + 3 * s) * c.plane;
+    }
+    c.rb = c.buf + 16 * c.plane;
+    c.nM_s = manning;
+    c.d50_s = d50;
+    c.psi_s = psi;
+    c.bnd = reinterpret_cast<double *>(base + L.bnd);
+    c.tflags = base + L.tflags;
+    c.tmax = reinterpret_cast<uint4 *>(base + L.tmax);
+    c.sched = reinterpret_cast<int *>(base + L.sched);
+    c.ctrl = reinterpret_cast<Ctrl *>(base + L.ctrl);
+    c.shape = kDefaultShape;
+    c.ntx = L.ntx;
+    c.nty = L.nty;
+    c.max_tiles = L.tiles;
+    c.max_chunks = L.chunks;
+    c.t0 = t0;
+
+    // set-up: clear the bed residual, balances, flags, maxima and lists; a
+    // fresh control block; the caller's state into level 0
+    hipStream_t st = c.stream;
+    struct Range {
+        void *p;
+        size_t bytes;
+    } clear[] = {{c.rb, c.plane * sizeof(float)},
+                 {c.bnd, 4 * (size_t)(c.nx + c.ny) * sizeof(double)},
+                 {c.tflags, 4 * L.tiles},
+                 {c.tmax, 2 * L.tiles * sizeof(uint4)},
+                 {c.sched, sched_layout(L.chunks, L.tiles).total * sizeof(int)}};
+    for (const Range &r : clear) {
+        const size_t words = (r.bytes + 3) / 4;
+        const int blocks = (int)std::min<size_t>(1024, (words + 255) / 256);
+        hipLaunchKernelGGL(k_noalloc_zero, dim3(std::max(blocks, 1)), dim3(256), 0, st,
+                           static_cast<uint32_t *>(r.p), words);
+    }
+    hipLaunchKernelGGL(k_noalloc_ctrl, dim3(1), dim3(256), 0, st, c.ctrl, t0);
+    const KPar P = make_kpar(&c);
+    const dim3 rows((c.nx + 255) / 256, c.ny);
+    hipLaunchKernelGGL(k_noalloc_load, rows, dim3(256), 0, st, P, c.ctrl, h, hu, hv, b, c.H[0],
+                       c.qx[0], c.qy[0], c.b[0], c.b[1]);
+    const StepArgs A = make_step_args(&c, dt_fixed > 0.0 ? 1 : 0, dt_fixed);
+    const Inst I = make_inst(&c, A);
+    launch_stage(c.shape, kPrepare, st, I, 0);
+    for (int32_t s = 0; s < nsteps; ++s) enqueue_tiled_step(&c, st, s & 1, P, A);
+    hipLaunchKernelGGL(k_noalloc_store, rows, dim3(256), 0, st, P, c.ctrl, nsteps, I, h, hu, hv,
+                       b, t_out, err_out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return noalloc_fail(errbuf, errbuf_len, SW_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
+    return SW_OK;
+}
 
 }  // extern "C"
 

@@ -71,3 +71,25 @@ def test_create_rejects_grids_beyond_the_32_bit_plane_offsets():
         rc = csph.lib.sw_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h))
         assert rc == csph.SW_ERR_ARG, (nx, ny, dx, rc)
         assert not h.value
+
+
+def test_noalloc_rejects_grids_beyond_its_scratch_array():
+    """sw_advance_noalloc checks its arguments and the size of the grid against
+    its fixed scratch array before any HIP call: SW_ERR_ARG and a message."""
+    from paper_2103_15196_amd import csph
+    p = csph.default_params()
+    buf = ctypes.create_string_buffer(256)
+    dummy = ctypes.c_void_p(16)  # never dereferenced: rejected before any device work
+    for nx, ny in ((2048, 1024), (1024, 1100), (4096, 4096), (0, 8)):
+        g = csph.make_grid(nx, ny, 1.0)
+        rc = csph.lib.sw_advance_noalloc(ctypes.byref(g), ctypes.byref(p), 0.02, 5e-4, 0.4,
+                                         dummy, dummy, dummy, dummy, 10, 0.0, 0.0, None, None,
+                                         None, buf, 256)
+        assert rc == csph.SW_ERR_ARG, (nx, ny, rc)
+        assert buf.value, (nx, ny)
+    assert b"scratch" in buf.value or b"nx, ny" in buf.value
+    g = csph.make_grid(1024, 1024, 1.0)
+    rc = csph.lib.sw_advance_noalloc(ctypes.byref(g), ctypes.byref(p), 0.02, 5e-4, 1.0,
+                                     dummy, dummy, dummy, dummy, 10, 0.0, 0.0, None, None, None,
+                                     buf, 256)
+    assert rc == csph.SW_ERR_ARG and b"psi" in buf.value
