@@ -18,6 +18,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "csph.h"
@@ -1226,7 +1227,24 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
     float pjy = 0, pmag = 0, pb = 0;           // J0_y, |J0| and bed of row r-1
     unsigned mv = 0, ms = 0, mD = 0, bad = 0;
     bool wet = false;
-    auto step = [&](int r, const Row &in) {
+    // The parts of the march a row takes, by its offset k = r - (y0 - 3) from
+    // the first row: bedload of row r (2 <= k <= S + 3; W faces 3 <= k <= S + 2,
+    // y faces from k = 3), y reconstruction of row r - 1 (k >= 2; its face
+    // from k = 3), x faces and limiter of row r - 2 (4 <= k <= S + 5), K8 of
+    // row r - 3 (k >= 6).  K >= 0: k is known at compile time (the first six
+    // and last four rows); K = -1: a row of the middle of the march
+    // (6 <= k <= S + 1), which takes every part.  Only the grid's own edges
+    // are left to run-time (uniform) tests.
+    auto step = [&](auto KC, int r, const Row &in) {
+        constexpr int K = decltype(KC)::value;
+        constexpr bool mid = K < 0;
+        constexpr bool part_j = mid || (K >= 2 && K <= S + 3);
+        constexpr bool part_jx = mid || (K >= 3 && K <= S + 2);
+        constexpr bool part_jy = mid || (K >= 3 && K <= S + 3);
+        constexpr bool part_y = mid || K >= 2;
+        constexpr bool part_yface = mid || K >= 3;
+        constexpr bool part_x = mid || (K >= 4 && K <= S + 5);
+        constexpr bool part_upd = mid || K >= 6;
         // the column and its lane predicates are derived again in every row
         // from a copy the compiler cannot see through: kept across the march
         // they were 64-bit lane masks in scalar registers, more than fit, and
@@ -1242,15 +1260,20 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
         // hits); loaded in every step, from the nearest row of the tile when
         // r-3 lies outside it (then unused), so no row outside the march is read
         const int ju = r - 3;
-        const bool upd = ju >= y0 && ju < jend;
-        const unsigned uo = (unsigned)(min(max(ju, y0), jend - 1) * pitch + ci) * 4u;
-        const float uh = at(SH, uo), uqx = at(Sqx, uo), uqy = at(Sqy, uo), ub = at(Sb, uo);
-        const float uLx = at(QLx, uo), uLy = at(QLy, uo);
-        const float upsi = soil_at(P.psi, P.psi_s, uo);
-        const float usrc = soil_at(P.srcw, 0.0f, uo);
-        const float uqb = soil_at(P.qb, 0.0f, uo);
-        const float unM = soil_at(P.nM, P.nM_s, uo);
-        const float ud50 = soil_at(P.d50, P.d50_s, uo);
+        const bool upd = part_upd && ju < jend;
+        unsigned uo = 0;
+        float uh = 0, uqx = 0, uqy = 0, ub = 0, uLx = 0, uLy = 0, upsi = 0, usrc = 0, uqb = 0,
+              unM = 0, ud50 = 0;
+        if constexpr (part_upd) {
+            uo = (unsigned)(min(ju, jend - 1) * pitch + ci) * 4u;
+            uh = at(SH, uo); uqx = at(Sqx, uo); uqy = at(Sqy, uo); ub = at(Sb, uo);
+            uLx = at(QLx, uo); uLy = at(QLy, uo);
+            upsi = soil_at(P.psi, P.psi_s, uo);
+            usrc = soil_at(P.srcw, 0.0f, uo);
+            uqb = soil_at(P.qb, 0.0f, uo);
+            unM = soil_at(P.nM, P.nM_s, uo);
+            ud50 = soil_at(P.d50, P.d50_s, uo);
+        }
         const bool iny = (unsigned)r < (unsigned)ny;
         {  // remap inputs of row r (ghost cells beyond the domain edge)
             const bool yghost = r == -1 || r == ny;
@@ -1270,16 +1293,16 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
         }
         xs3 = xs2; xs2 = xs1; xs1 = xs0;
         ys3 = ys2; ys2 = ys1; ys1 = ys0;
-        if (r >= y0 - 1 && r <= y0 + S) {  // J0 (Eqs. 3-5) of row r and its bedload faces
+        if constexpr (part_j) {  // J0 (Eqs. 3-5) of row r and its bedload faces
             // J0 and |J0| of the state were stored by the step that produced it
             const bool in_dom = inx && iny;
             const float jx = in_dom ? in.jx : 0.0f, jy = in_dom ? in.jy : 0.0f;
             const float mag = in_dom ? in.jm : 0.0f, b = in_dom ? in.b : 0.0f;
             const float jxW = lane_prev(jx), magW = lane_prev(mag), bW = lane_prev(b);
             float xs = 0.0f, ys = 0.0f;
-            if (r >= y0 && r < jend && face_x)  // W face of this lane in row r
+            if (part_jx && r < jend && face_x)  // W face of this lane in row r
                 xs = sed_face(P, i, nx, wW, wE, jxW, magW, bW, jx, mag, b);
-            if (r >= y0 && inx && r <= ny)  // y face r, between rows r-1 and r
+            if (part_jy && inx && r <= ny)  // y face r, between rows r-1 and r
                 ys = sed_face(P, r, ny, wS, wN, pjy, pmag, pb, jy, mag, b);
             xs0 = xs; ys0 = ys;
             pjy = jy; pmag = mag; pb = b;
@@ -1288,10 +1311,10 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
         {  // y reconstruction of row r-1 and y face r-1 (between rows r-2 and r-1)
             const int k = r - 1;
             Flux3 f{0.0f, 0.0f, 0.0f};
-            if (k >= y0 - 2 && k <= y0 + S + 1) {
+            if constexpr (part_y) {
                 SideQ ym, ypn;
                 reconstruct(along(v1, 1), along(v2, 1), along(v3, 1), ym, ypn);
-                if (k >= y0 - 1 && k >= 0 && k <= ny) {  // the face row (uniform); lanes inside the grid keep it
+                if (part_yface && k >= 0 && k <= ny) {  // the face row (uniform); lanes inside the grid keep it
                     side_flux(P, k, ny, wS, wN, yp, ym, f.H, f.n, f.t);
                     if (!inx) f = Flux3{0.0f, 0.0f, 0.0f};
                 }
@@ -1302,7 +1325,7 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
         const int jr = r - 2;  // ring/tile row whose x faces and limiter are due
         X3 = X2;
         th4 = th3; th3 = th2;
-        if (jr >= y0 - 1 && jr <= y0 + S) {
+        if constexpr (part_x) {
             const bool row_in = (unsigned)jr < (unsigned)ny;
             {  // x reconstruction of row r-2 and this lane's W face (west lane's plus side)
                 const CellQ c = along(v1, 0);
@@ -1349,23 +1372,32 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
             }
         }
     };
-    // S + 6 rows, an even count, unrolled in full for S = 8: every row's
-    // offset from the tile is then a constant, so its part of the march
-    // (ring, tile or K8 row) is known at compile time, and the carried rows
-    // are renamed rather than moved (about 10 K instructions of code; taller
-    // strips keep the loop)
-    constexpr int kRows = S + 6, kUnroll = S == 8 ? kRows / 2 : 1;
+    // S + 6 rows: the first six and the last four unrolled with their parts
+    // known at compile time, the middle S - 4 in pairs (unrolled for S = 8);
+    // the loads of the row two ahead are in flight while a row is computed
+    using std::integral_constant;
+    constexpr int kMidUnroll = S == 8 ? 2 : 1;
     const int rlo = y0 - 3;
     Row A, B;
     load_row(rlo, A);
     load_row(rlo + 1, B);
-#pragma unroll kUnroll
-    for (int k = 0; k < kRows; k += 2) {
-        step(rlo + k, A);
-        if (k + 2 < kRows) load_row(rlo + k + 2, A);
-        step(rlo + k + 1, B);
-        if (k + 3 < kRows) load_row(rlo + k + 3, B);
+    step(integral_constant<int, 0>{}, rlo + 0, A); load_row(rlo + 2, A);
+    step(integral_constant<int, 1>{}, rlo + 1, B); load_row(rlo + 3, B);
+    step(integral_constant<int, 2>{}, rlo + 2, A); load_row(rlo + 4, A);
+    step(integral_constant<int, 3>{}, rlo + 3, B); load_row(rlo + 5, B);
+    step(integral_constant<int, 4>{}, rlo + 4, A); load_row(rlo + 6, A);
+    step(integral_constant<int, 5>{}, rlo + 5, B); load_row(rlo + 7, B);
+#pragma unroll kMidUnroll
+    for (int k = 6; k < S + 2; k += 2) {
+        step(integral_constant<int, -1>{}, rlo + k, A);
+        load_row(rlo + k + 2, A);
+        step(integral_constant<int, -1>{}, rlo + k + 1, B);
+        load_row(rlo + k + 3, B);
     }
+    step(integral_constant<int, S + 2>{}, rlo + S + 2, A); load_row(rlo + S + 4, A);
+    step(integral_constant<int, S + 3>{}, rlo + S + 3, B); load_row(rlo + S + 5, B);
+    step(integral_constant<int, S + 4>{}, rlo + S + 4, A);
+    step(integral_constant<int, S + 5>{}, rlo + S + 5, B);
     strip_maxima_store(I, par ^ 1, tile, mv, ms, mD, bad, wet);
 }
 
