@@ -49,6 +49,13 @@
 #define ORC_SED_GRASS 1
 #define ORC_SED_EQ4 2
 
+#define ORC_LIM_MINMOD 0
+#define ORC_LIM_MC 1
+#define ORC_LIM_SUPERBEE 2
+
+#define ORC_SPEEDS_DAVIS 0
+#define ORC_SPEEDS_TWO_RAREFACTION 1
+
 typedef struct {
     int32_t nx, ny;
     double dx;        /* cell size (uniform, dx = dy); "h" in Eq. 7 */
@@ -63,6 +70,8 @@ typedef struct {
     double C_Sh;      /* Shamov coefficient of Eq. 5 */
     double A_G, m_exp;/* Grass law coefficient and exponent of Eq. 3 */
     int32_t sed_law;  /* 0 none, 1 Grass (A_G, m_exp), 2 Eq. 4 coefficient (m = 4) */
+    int32_t limiter;  /* TVD limiter of the Euler stage: 0 minmod, 1 MC, 2 superbee */
+    int32_t hll_speeds; /* HLL wave speeds: 0 Davis, 1 two-rarefaction (Toro) */
 } orc_params;
 
 typedef struct {
@@ -132,6 +141,27 @@ double orc_minmod(double a, double b)
     return a > b ? a : b;
 }
 
+/* The TVD limiters the Euler stage offers (Section 3 names TVD limiters      */
+/* without fixing one): the limited slope of a cell from its backward and   */
+/* forward differences a and b.  Zero unless a and b share a sign; else,    */
+/* with A = |a|, B = |b| and the sign of a:                                  */
+/*   minmod:   min(A, B)                                                    */
+/*   MC (monotonised central, van Leer 1977): min(2A, 2B, (A + B)/2)         */
+/*   superbee (Roe 1985): max(min(2A, B), min(A, 2B))                       */
+double orc_limiter(int kind, double a, double b)
+{
+    if (a * b <= 0.0) return 0.0;
+    double A = fabs(a), B = fabs(b), m;
+    if (kind == ORC_LIM_MC) {
+        m = fmin(fmin(2.0 * A, 2.0 * B), 0.5 * (A + B));
+    } else if (kind == ORC_LIM_SUPERBEE) {
+        m = fmax(fmin(2.0 * A, B), fmin(A, 2.0 * B));
+    } else {
+        m = fmin(A, B);
+    }
+    return a > 0.0 ? m : -m;
+}
+
 /* ---------------------------------------------------------------------- */
 /* O2  Zero-slope bedload J0 of one cell, Eqs. 3-5.  Bedload exists only    */
 /* where the depth exceeds h_sed and the speed exceeds the Shamov critical  */
@@ -162,14 +192,47 @@ void orc_j0(const orc_params *p, double H, double u, double v, double nM, double
     *jy = f * v;
 }
 
+/* Star state of the two-rarefaction approximation of the shallow-water    */
+/* Riemann problem (Toro, Shock-capturing methods for free-surface shallow  */
+/* flows, 2001): celerity c* = (cL + cR)/2 + (uL - uR)/4 and velocity       */
+/* u* = (uL + uR)/2 + cL - cR, exact when both waves are rarefactions.  A   */
+/* negative c* (the waves would open a dry middle) is taken as 0.           */
+void orc_trr_star(double g, double HsL, double unL, double HsR, double unR, double *ustar,
+                  double *cstar)
+{
+    double cL = sqrt(g * HsL), cR = sqrt(g * HsR);
+    *ustar = 0.5 * (unL + unR) + cL - cR;
+    *cstar = fmax(0.0, 0.5 * (cL + cR) + 0.25 * (unL - unR));
+}
+
+/* HLL wave-speed estimates from the side depths and transport velocities:  */
+/* Davis, SL = min(uL - cL, uR - cR), SR = max(uL + cL, uR + cR); or the    */
+/* two-rarefaction estimate, SL = min(uL - cL, u* - c*), SR = max(uR + cR,  */
+/* u* + c*), with the star state above (no separate dry-bed forms: the      */
+/* estimate stays continuous in the side states).                          */
+void orc_wave_speeds(int kind, double g, double HsL, double unL, double HsR, double unR,
+                     double *SL, double *SR)
+{
+    double cL = sqrt(g * HsL), cR = sqrt(g * HsR);
+    if (kind == ORC_SPEEDS_TWO_RAREFACTION) {
+        double us, cs;
+        orc_trr_star(g, HsL, unL, HsR, unR, &us, &cs);
+        *SL = fmin(unL - cL, us - cs);
+        *SR = fmax(unR + cR, us + cs);
+    } else {
+        *SL = fmin(unL - cL, unR - cR);
+        *SR = fmax(unL + cL, unR + cR);
+    }
+}
+
 /* HLL flux of the remap (Euler stage, Section 3).  Side states are the     */
 /* hydrostatic face depth Hs, the Lagrangian velocity (uLn normal, uLt      */
 /* tangential) and the transport velocity un.  Conserved U = (Hs, Hs uLn,   */
-/* Hs uLt), physical flux un * U, Davis wave speeds from un +- sqrt(g Hs).  */
+/* Hs uLt), physical flux un * U, wave speeds of the chosen estimate.       */
 /* Output f[0..2] = (mass, normal momentum, tangential momentum).           */
-void orc_hll(double g,
-             double HsL, double uLnL, double uLtL, double unL,
-             double HsR, double uLnR, double uLtR, double unR, double f[3])
+void orc_hll_v(int speeds, double g,
+               double HsL, double uLnL, double uLtL, double unL,
+               double HsR, double uLnR, double uLtR, double unR, double f[3])
 {
     double UL[3] = {HsL, HsL * uLnL, HsL * uLtL};
     double UR[3] = {HsR, HsR * uLnR, HsR * uLtR};
@@ -178,15 +241,22 @@ void orc_hll(double g,
         FL[k] = unL * UL[k];
         FR[k] = unR * UR[k];
     }
-    double cL = sqrt(g * HsL), cR = sqrt(g * HsR);
-    double SL = fmin(unL - cL, unR - cR);
-    double SR = fmax(unL + cL, unR + cR);
+    double SL, SR;
+    orc_wave_speeds(speeds, g, HsL, unL, HsR, unR, &SL, &SR);
     for (int k = 0; k < 3; ++k) {
         if (SL >= 0.0) f[k] = FL[k];
         else if (SR <= 0.0) f[k] = FR[k];
         else if (SR - SL <= 0.0) f[k] = 0.0;
         else f[k] = (SR * FL[k] - SL * FR[k] + SL * SR * (UR[k] - UL[k])) / (SR - SL);
     }
+}
+
+/* The same with Davis speeds. */
+void orc_hll(double g,
+             double HsL, double uLnL, double uLtL, double unL,
+             double HsR, double uLnR, double uLtR, double unR, double f[3])
+{
+    orc_hll_v(ORC_SPEEDS_DAVIS, g, HsL, uLnL, uLtL, unL, HsR, uLnR, uLtR, unR, f);
 }
 
 /* Hydrostatic face depths (Audusse et al. 2004) of a face between side     */
@@ -339,6 +409,26 @@ int orc_cfl(const orc_params *p, const orc_inputs *in, const double *H, const do
     return ORC_OK;
 }
 
+/* Normal-momentum flux through a wall face: the HLL flux against the      */
+/* mirrored ghost of the interior face state (depth Hs, Lagrangian velocity */
+/* normal n and tangential t, transport velocity u).  It carries no mass    */
+/* and no tangential momentum.  With Davis speeds this is                   */
+/* Hs n (u + |u| + c) for an interior cell on the minus side (E/N wall,     */
+/* side = +1) and Hs n (u - |u| - c) on the plus side (W/S wall).           */
+static double wall_flux_n(const orc_params *p, double Hs, double n, double t, double u, int side)
+{
+    if (p->hll_speeds == ORC_SPEEDS_DAVIS) {
+        double c = sqrt(p->g * Hs);
+        return side > 0 ? Hs * n * (u + fabs(u) + c) : Hs * n * (u - fabs(u) - c);
+    }
+    double f[3];
+    if (side > 0)
+        orc_hll_v(p->hll_speeds, p->g, Hs, n, t, u, Hs, -n, t, -u, f);
+    else
+        orc_hll_v(p->hll_speeds, p->g, Hs, -n, t, -u, Hs, n, t, u, f);
+    return f[1];
+}
+
 /* Ghost rule: value of a per-cell field at cell (i,j) when (i,j) may sit   */
 /* one cell outside the grid.  A wall mirrors (the normal velocity          */
 /* component flips sign, everything else is copied); an open side copies.   */
@@ -356,7 +446,8 @@ static double ghost(const orc_params *p, const double *a, int i, int j, int norm
     return sgn * a[(size_t)cj * nx + ci];
 }
 
-/* Limited slope of field a at cell (i,j) along x (dir 0) or y (dir 1). */
+/* Limited slope of field a at cell (i,j) along x (dir 0) or y (dir 1),    */
+/* with the run's TVD limiter.                                              */
 static double slope(const orc_params *p, const double *a, int i, int j, int dir, int nxf, int nyf)
 {
     double am, a0, ap;
@@ -368,7 +459,7 @@ static double slope(const orc_params *p, const double *a, int i, int j, int dir,
         am = ghost(p, a, i, j - 1, nxf, nyf);
         ap = ghost(p, a, i, j + 1, nxf, nyf);
     }
-    return orc_minmod(a0 - am, ap - a0);
+    return orc_limiter(p->limiter, a0 - am, ap - a0);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -524,7 +615,7 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
                 double sL = FACEV(uLy, sx[4], cL, +1), sR = FACEV(uLy, sx[4], cR, -1);
                 double HsL, HsR;
                 face_depths(zL, hL, zR, hR, &HsL, &HsR);
-                orc_hll(g, HsL, nL, sL, tL, HsR, nR, sR, tR, fl);
+                orc_hll_v(p->hll_speeds, g, HsL, nL, sL, tL, HsR, nR, sR, tR, fl);
                 double mag = 0.5 * (sqrt(J0x[cL] * J0x[cL] + J0y[cL] * J0y[cL]) +
                                     sqrt(J0x[cR] * J0x[cR] + J0y[cR] * J0y[cR]));
                 fj = fmax(J0x[cL], 0.0) + fmin(J0x[cR], 0.0) - CJ * mag * (b[cR] - b[cL]) / dx;
@@ -536,8 +627,7 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
                 double HsL, HsR;
                 face_depths(zL, hL, zL, hL, &HsL, &HsR);
                 if (p->bc[1] == ORC_BC_WALL) {
-                    double cL = sqrt(g * HsL);
-                    fl[1] = HsL * nL * (tL + fabs(tL) + cL);
+                    fl[1] = wall_flux_n(p, HsL, nL, sL, tL, +1);
                 } else {
                     fl[0] = tL * HsL;
                     fl[1] = tL * HsL * nL;
@@ -552,8 +642,7 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
                 double HsL, HsR;
                 face_depths(zR, hR, zR, hR, &HsL, &HsR);
                 if (p->bc[0] == ORC_BC_WALL) {
-                    double cR = sqrt(g * HsR);
-                    fl[1] = HsR * nR * (tR - fabs(tR) - cR);
+                    fl[1] = wall_flux_n(p, HsR, nR, sR, tR, -1);
                 } else {
                     fl[0] = tR * HsR;
                     fl[1] = tR * HsR * nR;
@@ -582,7 +671,7 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
                 double sL = FACEV(uLx, sy[4], cL, +1), sR = FACEV(uLx, sy[4], cR, -1);
                 double HsL, HsR;
                 face_depths(zL, hL, zR, hR, &HsL, &HsR);
-                orc_hll(g, HsL, nL, sL, tL, HsR, nR, sR, tR, fl);
+                orc_hll_v(p->hll_speeds, g, HsL, nL, sL, tL, HsR, nR, sR, tR, fl);
                 double mag = 0.5 * (sqrt(J0x[cL] * J0x[cL] + J0y[cL] * J0y[cL]) +
                                     sqrt(J0x[cR] * J0x[cR] + J0y[cR] * J0y[cR]));
                 fj = fmax(J0y[cL], 0.0) + fmin(J0y[cR], 0.0) - CJ * mag * (b[cR] - b[cL]) / dx;
@@ -594,8 +683,7 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
                 double HsL, HsR;
                 face_depths(zL, hL, zL, hL, &HsL, &HsR);
                 if (p->bc[3] == ORC_BC_WALL) {
-                    double cL = sqrt(g * HsL);
-                    fl[1] = HsL * nL * (tL + fabs(tL) + cL);
+                    fl[1] = wall_flux_n(p, HsL, nL, sL, tL, +1);
                 } else {
                     fl[0] = tL * HsL;
                     fl[1] = tL * HsL * nL;
@@ -610,8 +698,7 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
                 double HsL, HsR;
                 face_depths(zR, hR, zR, hR, &HsL, &HsR);
                 if (p->bc[2] == ORC_BC_WALL) {
-                    double cR = sqrt(g * HsR);
-                    fl[1] = HsR * nR * (tR - fabs(tR) - cR);
+                    fl[1] = wall_flux_n(p, HsR, nR, sR, tR, -1);
                 } else {
                     fl[0] = tR * HsR;
                     fl[1] = tR * HsR * nR;

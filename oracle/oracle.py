@@ -23,6 +23,8 @@ _SRC = os.path.join(_HERE, "csph_oracle.c")
 _LIB = os.environ.get("CSPH_ORACLE_LIB") or os.path.join(_HERE, "libcsph_oracle.so")
 
 SED_NONE, SED_GRASS, SED_EQ4 = 0, 1, 2
+LIM_MINMOD, LIM_MC, LIM_SUPERBEE = 0, 1, 2
+SPEEDS_DAVIS, SPEEDS_TWO_RAREFACTION = 0, 1
 BC_WALL, BC_OPEN = 0, 1
 BINDING_NAMES = ("h/(2vp)", "h/vs", "h^2/(2D)", "dt_max", "fixed")
 
@@ -42,6 +44,23 @@ def compile_source(src: str, out: str) -> str:
     return out
 
 
+_SRC_F32 = os.path.join(_HERE, "csph_oracle_f32.c")
+_LIB_F32 = os.path.join(_HERE, "libcsph_oracle_f32.so")
+
+
+def build_f32(force: bool = True) -> str:
+    """Compile the float32 evaluation of the oracle (csph_oracle_f32.c: the
+    same source, every literal and operation in float32).  It only measures
+    how far float32 rounding moves the FP64 answer; it is never a reference."""
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_F32))
+    if force or not os.path.exists(_LIB_F32) or os.path.getmtime(_LIB_F32) < newest:
+        tmp = _LIB_F32 + ".tmp"
+        subprocess.check_call(["gcc"] + CFLAGS + ["-fsingle-precision-constant", _SRC_F32, "-o", tmp,
+                                                  "-lm"])
+        os.replace(tmp, _LIB_F32)
+    return _LIB_F32
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle.  Returns the library path."""
     if os.environ.get("CSPH_ORACLE_LIB"):
@@ -57,7 +76,7 @@ class _Params(C.Structure):
                 ("eps", C.c_double), ("h_sed", C.c_double), ("dt_max", C.c_double),
                 ("dt_min", C.c_double), ("s_rel", C.c_double), ("C_J", C.c_double),
                 ("C_Sh", C.c_double), ("A_G", C.c_double), ("m_exp", C.c_double),
-                ("sed_law", C.c_int32)]
+                ("sed_law", C.c_int32), ("limiter", C.c_int32), ("hll_speeds", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -95,6 +114,14 @@ def _load():
                                C.c_double, C.c_double, _dp, _dp]
         lib.orc_hll.restype = None
         lib.orc_hll.argtypes = [C.c_double] + [C.c_double] * 8 + [_dp]
+        lib.orc_hll_v.restype = None
+        lib.orc_hll_v.argtypes = [C.c_int, C.c_double] + [C.c_double] * 8 + [_dp]
+        lib.orc_limiter.restype = C.c_double
+        lib.orc_limiter.argtypes = [C.c_int, C.c_double, C.c_double]
+        lib.orc_wave_speeds.restype = None
+        lib.orc_wave_speeds.argtypes = [C.c_int, C.c_double] + [C.c_double] * 4 + [_dp, _dp]
+        lib.orc_trr_star.restype = None
+        lib.orc_trr_star.argtypes = [C.c_double] + [C.c_double] * 4 + [_dp, _dp]
         lib.orc_hydrograph.restype = C.c_double
         lib.orc_hydrograph.argtypes = [C.POINTER(_Inputs), C.c_double]
         lib.orc_cfl.restype = C.c_int
@@ -139,6 +166,8 @@ class Params:
     A_G: float = 1e-3
     m_exp: float = 2.0
     sed_law: int = SED_EQ4
+    limiter: int = LIM_MINMOD
+    hll_speeds: int = SPEEDS_DAVIS
 
     def _c(self) -> _Params:
         p = _Params()
@@ -149,6 +178,8 @@ class Params:
                      "A_G", "m_exp"):
             setattr(p, name, float(getattr(self, name)))
         p.sed_law = int(self.sed_law)
+        p.limiter = int(self.limiter)
+        p.hll_speeds = int(self.hll_speeds)
         return p
 
 
@@ -247,6 +278,40 @@ def run(p: Params, inp: Inputs, s: State, nsteps: int, dt_fixed: float = 0.0) ->
     return s
 
 
+_lib_f32 = None
+
+
+def run_f32(p: Params, inp: Inputs, s: State, nsteps: int, dt_fixed: float = 0.0) -> State:
+    """``nsteps`` steps of the oracle evaluated in float32 arithmetic (see
+    build_f32): the state is rounded to float32 before each step.  For
+    measuring the conditioning of a problem only."""
+    global _lib_f32
+    if _lib_f32 is None:
+        lib = C.CDLL(build_f32(force=False))
+        lib.orcf_step.restype = C.c_int
+        lib.orcf_step.argtypes = [C.POINTER(_Params), C.POINTER(_Inputs), _dp, _dp, _dp, _dp,
+                                  C.c_double, C.c_double, C.POINTER(_Info)]
+        lib.orcf_set_threads.restype = None
+        lib.orcf_set_threads.argtypes = [C.c_int]
+        _lib_f32 = lib
+    _lib_f32.orcf_set_threads(threads())
+    n = p.nx * p.ny
+    for _ in range(nsteps):
+        cp, ci = p._c(), inp._c(n)
+        info = _Info()
+        for name in ("H", "qx", "qy", "b"):
+            setattr(s, name, _arr(getattr(s, name), n).reshape(p.ny, p.nx))
+        rc = _lib_f32.orcf_step(C.byref(cp), C.byref(ci), s.H.ctypes.data_as(_dp),
+                                s.qx.ctypes.data_as(_dp), s.qy.ctypes.data_as(_dp),
+                                s.b.ctypes.data_as(_dp), s.t, float(dt_fixed), C.byref(info))
+        inp._keep.clear()
+        if rc != 0:
+            raise OracleError(rc)
+        s.t += info.dt
+        s.step += 1
+    return s
+
+
 def cfl(p: Params, inp: Inputs, s: State) -> dict:
     """Eq. 7 time step and its three maxima for the state ``s``."""
     lib = _load()
@@ -298,6 +363,31 @@ def hll(g, HsL, uLnL, uLtL, unL, HsR, uLnR, uLtR, unR):
     _load().orc_hll(float(g), float(HsL), float(uLnL), float(uLtL), float(unL), float(HsR),
                     float(uLnR), float(uLtR), float(unR), f)
     return tuple(f)
+
+
+def limiter(kind: int, a: float, b: float) -> float:
+    return _load().orc_limiter(int(kind), float(a), float(b))
+
+
+def hll_v(speeds, g, HsL, uLnL, uLtL, unL, HsR, uLnR, uLtR, unR):
+    f = (C.c_double * 3)()
+    _load().orc_hll_v(int(speeds), float(g), float(HsL), float(uLnL), float(uLtL), float(unL),
+                      float(HsR), float(uLnR), float(uLtR), float(unR), f)
+    return tuple(f)
+
+
+def wave_speeds(kind, g, HsL, unL, HsR, unR):
+    a, b = C.c_double(), C.c_double()
+    _load().orc_wave_speeds(int(kind), float(g), float(HsL), float(unL), float(HsR), float(unR),
+                            C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def trr_star(g, HsL, unL, HsR, unR):
+    u, c = C.c_double(), C.c_double()
+    _load().orc_trr_star(float(g), float(HsL), float(unL), float(HsR), float(unR), C.byref(u),
+                         C.byref(c))
+    return u.value, c.value
 
 
 def hydrograph(inp: Inputs, t: float) -> float:

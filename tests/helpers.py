@@ -62,3 +62,22 @@ def ritter(h0, x, t, x0, g=9.81):
     c0 = math.sqrt(g * h0)
     xi = (x - x0) / t
     return np.where(xi < -c0, h0, np.where(xi < 2 * c0, (2 * c0 - xi) ** 2 / (9 * g), 0.0))
+
+
+def exact_riemann_star(hl, ul, hr, ur, g=9.81):
+    """Star state (h*, u*) of the shallow-water Riemann problem with wet sides,
+    from the exact wave relations (textbook: each side a rarefaction if h* <= h_K,
+    else a shock; root of f_L(h) + f_R(h) + u_R - u_L)."""
+    from scipy.optimize import brentq
+
+    def f(h, hk):
+        if h <= hk:
+            return 2.0 * (math.sqrt(g * h) - math.sqrt(g * hk))
+        return (h - hk) * math.sqrt(0.5 * g * (h + hk) / (h * hk))
+
+    def phi(h):
+        return f(h, hl) + f(h, hr) + ur - ul
+
+    hs = brentq(phi, 1e-12, 100.0 * max(hl, hr) + 10.0, xtol=1e-15, rtol=1e-15, maxiter=500)
+    us = 0.5 * (ul + ur) + 0.5 * (f(hs, hr) - f(hs, hl))
+    return hs, us

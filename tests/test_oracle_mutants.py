@@ -3,7 +3,7 @@
 Each mutant below plants one typical error (a dropped term, a flipped sign, a
 wrong neighbour, an x/y mix-up, a wrong donor) into a temporary copy of the
 oracle's C source, compiles it on the CPU, and runs the pin suite
-(test_oracle_pins.py) against it in a subprocess.  Every mutant must make at
+(test_oracle_pins.py, test_oracle_variants.py) against it in a subprocess.  Every mutant must make at
 least one pin fail; the unmodified source must pass.
 """
 import os
@@ -35,8 +35,19 @@ MUTANTS = {
     "y_face_transposed_operand": ("double tL = FACEV(uty, sy[2], cL, +1), tR = FACEV(uty, sy[2], cR, -1);",
                                   "double tL = FACEV(utx, sy[2], cL, +1), tR = FACEV(uty, sy[2], cR, -1);"),
     "slope_ghost_normal_flag": ("const int fx_nx[5] = {0, 0, 1, 1, 0}", "const int fx_nx[5] = {0, 0, 1, 0, 0}"),
-    "wall_flux_sign_east": ("fl[1] = HsL * nL * (tL + fabs(tL) + cL);",
-                            "fl[1] = HsL * nL * (tL - fabs(tL) + cL);"),
+    "wall_flux_sign_east": ("side > 0 ? Hs * n * (u + fabs(u) + c)",
+                            "side > 0 ? Hs * n * (u - fabs(u) + c)"),
+    "limiter_minmod_is_maxmod": ("        m = fmin(A, B);", "        m = fmax(A, B);"),
+    "limiter_mc_drops_half": ("0.5 * (A + B)", "(A + B)"),
+    "limiter_superbee_is_min": ("m = fmax(fmin(2.0 * A, B), fmin(A, 2.0 * B));",
+                                "m = fmin(fmin(2.0 * A, B), fmin(A, 2.0 * B));"),
+    "slope_ignores_limiter_choice": ("orc_limiter(p->limiter, a0 - am, ap - a0)",
+                                     "orc_limiter(ORC_LIM_MINMOD, a0 - am, ap - a0)"),
+    "trr_celerity_sign": ("0.25 * (unL - unR)", "0.25 * (unR - unL)"),
+    "trr_velocity_sign": ("*ustar = 0.5 * (unL + unR) + cL - cR;", "*ustar = 0.5 * (unL + unR) + cR - cL;"),
+    "trr_speed_uses_left_head_twice": ("*SR = fmax(unR + cR, us + cs);", "*SR = fmax(unL + cL, us + cs);"),
+    "trr_wall_ghost_not_mirrored": ("orc_hll_v(p->hll_speeds, p->g, Hs, n, t, u, Hs, -n, t, -u, f);",
+                                    "orc_hll_v(p->hll_speeds, p->g, Hs, n, t, u, Hs, n, t, u, f);"),
     "open_boundary_blocks_mass": ("fl[0] = tL * HsL;\n                    fl[1] = tL * HsL * nL;\n                    fl[2] = tL * HsL * sL;\n                    fj = fmax(J0x[c], 0.0);",
                                   "fl[1] = tL * HsL * nL;\n                    fl[2] = tL * HsL * sL;\n                    fj = fmax(J0x[c], 0.0);"),
     "theta_wrong_donor": ("if (FH[f] > 0.0 && k - 1 >= 0) th = theta[(size_t)j * nx + k - 1];",
@@ -60,7 +71,8 @@ MUTANTS = {
 def _run_pins(lib):
     env = dict(os.environ, CSPH_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_variants.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return r.returncode, r.stdout[-2000:]
 
