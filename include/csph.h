@@ -56,6 +56,20 @@ extern "C" {
 #define SW_PTR_HOST 0
 #define SW_PTR_DEVICE 1
 
+/* TVD limiter of the Euler stage (Section 3 names TVD limiters without fixing
+ * one): minmod (default), MC (monotonised central, van Leer 1977), superbee
+ * (Roe 1985). */
+#define SW_LIM_MINMOD 0
+#define SW_LIM_MC 1
+#define SW_LIM_SUPERBEE 2
+
+/* HLL wave-speed estimate of the Euler stage: Davis (default), or the
+ * two-rarefaction estimate of Toro (star celerity (cL + cR)/2 + (uL - uR)/4,
+ * star velocity (uL + uR)/2 + cL - cR; SL = min(uL - cL, u* - c*), SR =
+ * max(uR + cR, u* + c*)). */
+#define SW_HLL_DAVIS 0
+#define SW_HLL_TWO_RAREFACTION 1
+
 /* sw_params.flags */
 #define SW_FLAG_HGS 1u        /* skip dry tiles (the hierarchical grid system, Section 3) */
 #define SW_FLAG_UNFUSED 2u    /* run the unfused kernel sequence (faces, then update) */
@@ -85,6 +99,8 @@ typedef struct {
     double m_exp;   /* Grass exponent of Eq. 3, 2 */
     int32_t sed_law;/* SW_SED_*, default SW_SED_EQ4 */
     uint32_t flags; /* SW_FLAG_*, default SW_FLAG_HGS */
+    int32_t limiter;    /* SW_LIM_*, default SW_LIM_MINMOD */
+    int32_t hll_speeds; /* SW_HLL_*, default SW_HLL_DAVIS */
 } sw_params;
 
 /* Global diagnostics, all accumulated in FP64 on the device. */

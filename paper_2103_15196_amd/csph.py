@@ -33,6 +33,8 @@ SW_BC_WALL, SW_BC_OPEN = 0, 1
 SW_SED_NONE, SW_SED_GRASS, SW_SED_EQ4 = 0, 1, 2
 SW_PTR_HOST, SW_PTR_DEVICE = 0, 1
 SW_FLAG_HGS, SW_FLAG_UNFUSED, SW_FLAG_NO_GRAPH = 1, 2, 4
+SW_LIM_MINMOD, SW_LIM_MC, SW_LIM_SUPERBEE = 0, 1, 2
+SW_HLL_DAVIS, SW_HLL_TWO_RAREFACTION = 0, 1
 
 
 class sw_grid(C.Structure):
@@ -44,7 +46,7 @@ class sw_params(C.Structure):
                 ("h_sed", C.c_double), ("dt_max", C.c_double), ("dt_min", C.c_double),
                 ("s_rel", C.c_double), ("C_J", C.c_double), ("C_Sh", C.c_double),
                 ("A_G", C.c_double), ("m_exp", C.c_double), ("sed_law", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("limiter", C.c_int32), ("hll_speeds", C.c_int32)]
 
 
 class sw_sums(C.Structure):

@@ -1174,7 +1174,7 @@ __device__ __forceinline__ void lagrange_strip(const Inst &I, int par, int bx, i
 // CS: some soil or source field is a per-cell plane (else all are scalars).
 // The caller has checked the error flag (one memory round trip per
 // wavefront saved: the step and the first rows load together).
-template <int S, bool CS>
+template <int S, bool CS, bool V>
 __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int by)
 {
     const KPar &P = I.P;
@@ -1313,9 +1313,9 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
             Flux3 f{0.0f, 0.0f, 0.0f};
             if constexpr (part_y) {
                 SideQ ym, ypn;
-                reconstruct(along(v1, 1), along(v2, 1), along(v3, 1), ym, ypn);
+                reconstruct<V>(P, along(v1, 1), along(v2, 1), along(v3, 1), ym, ypn);
                 if (part_yface && k >= 0 && k <= ny) {  // the face row (uniform); lanes inside the grid keep it
-                    side_flux(P, k, ny, wS, wN, yp, ym, f.H, f.n, f.t);
+                    side_flux<V>(P, k, ny, wS, wN, yp, ym, f.H, f.n, f.t);
                     if (!inx) f = Flux3{0.0f, 0.0f, 0.0f};
                 }
                 yp = ypn;
@@ -1330,11 +1330,11 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
             {  // x reconstruction of row r-2 and this lane's W face (west lane's plus side)
                 const CellQ c = along(v1, 0);
                 SideQ xm, xp;
-                reconstruct(q_prev(c), c, q_next(c), xm, xp);
+                reconstruct<V>(P, q_prev(c), c, q_next(c), xm, xp);
                 const SideQ xl{lane_prev(xp.z), lane_prev(xp.h), lane_prev(xp.ut),
                                lane_prev(xp.uLn), lane_prev(xp.uLt), lane_prev(xp.b)};
                 Flux3 f;
-                side_flux(P, i, nx, wW, wE, xl, xm, f.H, f.n, f.t);
+                side_flux<V>(P, i, nx, wW, wE, xl, xm, f.H, f.n, f.t);
                 const bool on = row_in && face_x;
                 X2 = Flux3{on ? f.H : 0.0f, on ? f.n : 0.0f, on ? f.t : 0.0f};
             }
@@ -1763,16 +1763,16 @@ __device__ __forceinline__ void lagrange_listed(const Inst &I, int par, int w)
         lagrange_strip<S, CS>(I, par, t % I.ntx, t / I.ntx, dt);
     }
 }
-template <int S, bool CS>
+template <int S, bool CS, bool V>
 __device__ __forceinline__ void euler_entry(const Inst &I, int par, int p0, int w)
 {
     const int e = __builtin_amdgcn_readfirstlane(
         I.hgs ? list_entry(I.eul, I.pre_e, p0, I.nchunk, I.chunk, w) : w);
     const int t = e < 0 ? -1 - e : e;
     if (e < 0) strip_copy<S>(I, par, t % I.ntx, t / I.ntx);
-    else euler_strip<S, CS>(I, par, t % I.ntx, t / I.ntx);
+    else euler_strip<S, CS, V>(I, par, t % I.ntx, t / I.ntx);
 }
-template <int S, bool CS, int XP>
+template <int S, bool CS, int XP, bool V>
 __device__ __forceinline__ void euler_listed(const Inst &I, int par, int w)
 {
     // error flag, list length and the first 64 start positions in one round trip
@@ -1784,7 +1784,7 @@ __device__ __forceinline__ void euler_listed(const Inst &I, int par, int w)
     if (XP != 2) {
         if (XP == 1) w = __builtin_amdgcn_readfirstlane(xcd_entry(w / SWAVES, w % SWAVES, n));
         if (err || w >= n) return;
-        euler_entry<S, CS>(I, par, p0, w);
+        euler_entry<S, CS, V>(I, par, p0, w);
         return;
     }
     if (err) return;
@@ -1796,7 +1796,7 @@ __device__ __forceinline__ void euler_listed(const Inst &I, int par, int w)
             if (base == 0) return;  // no entry in the first (fullest) pass: none later
             continue;
         }
-        euler_entry<S, CS>(I, par, p0, we);
+        euler_entry<S, CS, V>(I, par, p0, we);
     }
 }
 
@@ -1805,10 +1805,12 @@ __global__ void __launch_bounds__(NT) k_lagrange_sl(Inst I, int par)
 {
     lagrange_listed<S, CS, XP>(I, par, blockIdx.x * SWAVES + (threadIdx.x >> 6));
 }
-template <int S, bool CS, int XP>
+// V: the limiter or the wave-speed estimate is not minmod + Davis (read from
+// the run's constants); V = false keeps the default arithmetic branch-free.
+template <int S, bool CS, int XP, bool V>
 __global__ void __launch_bounds__(NT) k_euler_sl(Inst I, int par)
 {
-    euler_listed<S, CS, XP>(I, par, blockIdx.x * SWAVES + (threadIdx.x >> 6));
+    euler_listed<S, CS, XP, V>(I, par, blockIdx.x * SWAVES + (threadIdx.x >> 6));
 }
 
 // Ensemble: workgroup b runs waves SWAVES table[2b+1] + w of member table[2b].
@@ -1819,12 +1821,12 @@ __global__ void __launch_bounds__(NT) k_lagrange_slb(const Inst *__restrict__ in
     const int *t = table + 2 * blockIdx.x;
     lagrange_listed<S, CS, 0>(insts[t[0]], par, t[1] * SWAVES + (threadIdx.x >> 6));
 }
-template <int S, bool CS>
+template <int S, bool CS, bool V>
 __global__ void __launch_bounds__(NT) k_euler_slb(const Inst *__restrict__ insts,
                                                   const int *__restrict__ table, int par)
 {
     const int *t = table + 2 * blockIdx.x;
-    euler_listed<S, CS, 0>(insts[t[0]], par, t[1] * SWAVES + (threadIdx.x >> 6));
+    euler_listed<S, CS, 0, V>(insts[t[0]], par, t[1] * SWAVES + (threadIdx.x >> 6));
 }
 
 // Tile shapes the autotuner chooses from: TX x TY cells per 256-thread
@@ -1993,6 +1995,12 @@ KPar make_kpar(const sw_ctx *c)
     P.qb = c->qb;
     P.srcw = c->has_inflow ? c->srcw : nullptr;
     P.rb = (c->par.sed_law != SW_SED_NONE || c->qb) ? c->rb : nullptr;
+    // limiter as the bounds of its slope ratio (beta, theta, gamma)
+    P.lim_b = P.lim_t = P.lim_g = 1.0f;
+    if (c->par.limiter == SW_LIM_MC) { P.lim_b = 2.0f; P.lim_t = 2.0f; P.lim_g = 0.5f; }
+    if (c->par.limiter == SW_LIM_SUPERBEE) { P.lim_b = 2.0f; P.lim_t = 2.0f; P.lim_g = 1.0f; }
+    P.speeds = c->par.hll_speeds;
+    P.variant = (c->par.limiter != SW_LIM_MINMOD || c->par.hll_speeds != SW_HLL_DAVIS) ? 1 : 0;
     return P;
 }
 
@@ -2207,36 +2215,40 @@ void launch_batch_t(Stage st, hipStream_t s, const Inst *insts, int nmem, const 
 // kernels over the (member, local workgroup) table, both on work lists.
 template <int S, bool CS>
 void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, const int *table, int ntab,
-                    const int *dtab, int ndtab, int lthr, int par)
+                    const int *dtab, int ndtab, int lthr, int par, bool var)
 {
     if (st == kDt) hipLaunchKernelGGL(k_dt_lists_b, dim3(ndtab), dim3(lthr), 0, s, insts, dtab, par);
     else if (st == kLagrange)
         hipLaunchKernelGGL((k_lagrange_slb<S, CS>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
-    else hipLaunchKernelGGL((k_euler_slb<S, CS>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
+    else if (var)
+        hipLaunchKernelGGL((k_euler_slb<S, CS, true>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
+    else hipLaunchKernelGGL((k_euler_slb<S, CS, false>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
 }
 
 template <int S>
 void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, const int *table, int ntab,
-                    const int *dtab, int ndtab, int lthr, int par, bool cs)
+                    const int *dtab, int ndtab, int lthr, int par, bool cs, bool var)
 {
-    if (cs) launch_batch_s<S, true>(st, s, insts, table, ntab, dtab, ndtab, lthr, par);
-    else launch_batch_s<S, false>(st, s, insts, table, ntab, dtab, ndtab, lthr, par);
+    if (cs) launch_batch_s<S, true>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, var);
+    else launch_batch_s<S, false>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, var);
 }
 
-// cs: some member has a per-cell soil or source plane.  Tile shapes take the
+// cs: some member has a per-cell soil or source plane; var: some member runs
+// another limiter or wave-speed estimate than minmod + Davis (the general
+// kernel gives those members the default's bits).  Tile shapes take the
 // (member, bx, by) table; strips the stage and K3a tables.
 void launch_batch(int shape, Stage st, hipStream_t s, const Inst *insts, int nmem,
                   const int *table, int ntab, const int *dtab, int ndtab, int lthr, int par,
-                  bool cs)
+                  bool cs, bool var)
 {
     switch (shape) {
     case 0: launch_batch_t<64, 8>(st, s, insts, nmem, table, ntab, par); break;
     case 1: launch_batch_t<64, 4>(st, s, insts, nmem, table, ntab, par); break;
     case 2: launch_batch_t<64, 16>(st, s, insts, nmem, table, ntab, par); break;
     case 3: launch_batch_t<128, 4>(st, s, insts, nmem, table, ntab, par); break;
-    case 4: launch_batch_s<8>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, cs); break;
-    case 5: launch_batch_s<16>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, cs); break;
-    default: launch_batch_s<32>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, cs); break;
+    case 4: launch_batch_s<8>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, cs, var); break;
+    case 5: launch_batch_s<16>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, cs, var); break;
+    default: launch_batch_s<32>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, cs, var); break;
     }
 }
 
@@ -2268,8 +2280,11 @@ void launch_strip_t(Stage st, hipStream_t s, const Inst &I, int par, hipEvent_t 
     const bool cs = cell_soil(I.P);
     auto lag = passes ? (cs ? k_lagrange_sl<S, true, 2> : k_lagrange_sl<S, false, 2>)
                       : (cs ? k_lagrange_sl<S, true, 1> : k_lagrange_sl<S, false, 1>);
-    auto eul = passes ? (cs ? k_euler_sl<S, true, 2> : k_euler_sl<S, false, 2>)
-                      : (cs ? k_euler_sl<S, true, 1> : k_euler_sl<S, false, 1>);
+    auto eul = I.P.variant
+                   ? (passes ? (cs ? k_euler_sl<S, true, 2, true> : k_euler_sl<S, false, 2, true>)
+                             : (cs ? k_euler_sl<S, true, 1, true> : k_euler_sl<S, false, 1, true>))
+                   : (passes ? (cs ? k_euler_sl<S, true, 2, false> : k_euler_sl<S, false, 2, false>)
+                             : (cs ? k_euler_sl<S, true, 1, false> : k_euler_sl<S, false, 1, false>));
     if (st == kPrepare) hipLaunchKernelGGL((k_prepare_t<SX, S>), gt, dim3(NT), 0, s, I, par);
     else if (st == kDt)
         hipLaunchKernelGGL(k_dt_lists, dim3(I.nchunk), dim3(list_threads(I.chunk)), 0, s, I, par);
@@ -2461,6 +2476,8 @@ void sw_default_params(sw_params *p)
     p->m_exp = 2.0;
     p->sed_law = SW_SED_EQ4;
     p->flags = SW_FLAG_HGS;
+    p->limiter = SW_LIM_MINMOD;
+    p->hll_speeds = SW_HLL_DAVIS;
 }
 
 int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw_ctx **out)
@@ -2475,6 +2492,9 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
         if (grid->bc[s] != SW_BC_WALL && grid->bc[s] != SW_BC_OPEN) return SW_ERR_ARG;
     if (params->sed_law < SW_SED_NONE || params->sed_law > SW_SED_EQ4) return SW_ERR_ARG;
     if (!(params->cfl > 0.0) || !(params->g > 0.0) || !(params->eps_dry > 0.0)) return SW_ERR_ARG;
+    if (params->limiter < SW_LIM_MINMOD || params->limiter > SW_LIM_SUPERBEE) return SW_ERR_ARG;
+    if (params->hll_speeds != SW_HLL_DAVIS && params->hll_speeds != SW_HLL_TWO_RAREFACTION)
+        return SW_ERR_ARG;
     sw_ctx *c = new sw_ctx();
     c->grid = *grid;
     c->par = *params;
@@ -3293,6 +3313,9 @@ int sw_advance_noalloc(const sw_grid *grid, const sw_params *params, float manni
     for (int s = 0; s < 4; ++s)
         if (grid->bc[s] != SW_BC_WALL && grid->bc[s] != SW_BC_OPEN) return bad("unknown boundary kind");
     if (params->sed_law < SW_SED_NONE || params->sed_law > SW_SED_EQ4) return bad("unknown sediment law");
+    if (params->limiter < SW_LIM_MINMOD || params->limiter > SW_LIM_SUPERBEE) return bad("unknown limiter");
+    if (params->hll_speeds != SW_HLL_DAVIS && params->hll_speeds != SW_HLL_TWO_RAREFACTION)
+        return bad("unknown wave-speed estimate");
     if (!(params->cfl > 0.0) || !(params->g > 0.0) || !(params->eps_dry > 0.0))
         return bad("cfl, g and eps_dry must be > 0");
     if (params->flags & SW_FLAG_UNFUSED) return bad("the unfused sequence is not available here");
@@ -3401,6 +3424,7 @@ struct swb_ctx {
     int lthr = LT;  // threads of a K3a workgroup (the widest member segment's)
     int shape = kDefaultShape;
     bool cs = false;  // some member reads per-cell soil or source planes
+    bool var = false; // some member runs a limiter or wave-speed estimate other than minmod + Davis
     hipGraphExec_t gexec = nullptr;
     hipGraphExec_t gexec_long = nullptr;
     bool built = false;
@@ -3431,6 +3455,7 @@ int batch_build(swb_ctx *b)
     std::vector<int> table, dtable;
     int lthr = 256;
     b->cs = false;
+    b->var = false;
     for (int m = 0; m < n; ++m) {
         sw_ctx *c = b->mem[m];
         if (c->shape != b->shape) set_shape(c, b->shape);
@@ -3440,6 +3465,7 @@ int batch_build(swb_ctx *b)
         }
         insts[m] = make_inst(c, make_step_args(c, 0, 0.0));
         b->cs = b->cs || cell_soil(insts[m].P);
+        b->var = b->var || insts[m].P.variant;
         if (is_strip(b->shape)) {  // one entry per workgroup of SWAVES list entries
             const int blocks = (c->ntx * c->nty + SWAVES - 1) / SWAVES;
             for (int w = 0; w < blocks; ++w) {
@@ -3503,11 +3529,12 @@ void batch_step(swb_ctx *b, hipStream_t st, int par)
 {
     const int n = (int)b->mem.size();
     const int *dtab = b->d_table + 2 * b->ntab;
-    launch_batch(b->shape, kDt, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, b->lthr, par, b->cs);
+    launch_batch(b->shape, kDt, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, b->lthr, par,
+                 b->cs, b->var);
     launch_batch(b->shape, kLagrange, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, b->lthr, par,
-                 b->cs);
+                 b->cs, b->var);
     launch_batch(b->shape, kEuler, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, b->lthr, par,
-                 b->cs);
+                 b->cs, b->var);
 }
 
 // The member tables and graphs hold every member's kernel arguments: they are

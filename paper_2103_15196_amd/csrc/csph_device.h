@@ -35,6 +35,11 @@ struct KPar {
     const float *qb;                // q_b^+ - q_b^- per cell, or null
     const float *srcw;              // inflow weight / dx^2 per cell, or null
     float *rb;                      // bed residual per cell (null: the bed cannot change)
+    // TVD limiter of the Euler stage as the bounds of its slope ratio (see
+    // `limited`): minmod (1, 1, 1), MC (2, 2, 1/2), superbee (2, 2, 1)
+    float lim_b, lim_t, lim_g;
+    int speeds;                     // HLL wave speeds: 0 Davis, 1 two-rarefaction
+    int variant;                    // 1 when the limiter or the speeds differ from minmod + Davis
 };
 
 __device__ __forceinline__ float soil(const float *a, float s, int c) { return a ? a[c] : s; }
@@ -91,6 +96,28 @@ __device__ __forceinline__ float minmod(float a, float b)
 {
     const float m = copysignf(fminf(fabsf(a), fabsf(b)), a);
     return a * b <= 0.0f ? 0.0f : m;
+}
+
+// The TVD limiter of the run, from the backward and forward differences a,
+// b (V = false: minmod).  Zero unless a and b share a sign; else, with A =
+// |a|, B = |b|, the sign of a and the magnitude
+//   min( max(min(beta A, B), min(A, beta B)), theta min(A, B), gamma (A + B) ),
+// which is min(A, B) for minmod (beta = theta = gamma = 1), min(2A, 2B,
+// (A + B)/2) for MC (2, 2, 1/2) and max(min(2A, B), min(A, 2B)) for
+// superbee (2, 2, 1): every min and max and the doublings are exact, so each
+// is the limiter's own value, minmod bit for bit.
+template <bool V>
+__device__ __forceinline__ float limited(const KPar &P, float a, float b)
+{
+    if constexpr (!V) {
+        return minmod(a, b);
+    } else {
+        const float A = fabsf(a), B = fabsf(b);
+        float m = fmaxf(fminf(P.lim_b * A, B), fminf(A, P.lim_b * B));
+        m = fminf(m, P.lim_t * fminf(A, B));
+        m = fminf(m, P.lim_g * (A + B));
+        return a * b <= 0.0f ? 0.0f : copysignf(m, a);
+    }
 }
 
 // Powers through the hardware base-2 logarithm and exponential (v_log_f32,
@@ -253,19 +280,20 @@ struct FaceState {
 // Reconstructed face states on both sides of the face between cells L and R,
 // given the outer neighbours A (beyond L) and B (beyond R): minmod slopes,
 // side values L + slope/2 and R - slope/2, hydrostatic face depths.
-__device__ __forceinline__ void face_states(const CellQ &A, const CellQ &L, const CellQ &R,
-                                            const CellQ &B, FaceState &fl, FaceState &fr)
+__device__ __forceinline__ void face_states(const KPar &P, const CellQ &A, const CellQ &L,
+                                            const CellQ &R, const CellQ &B, FaceState &fl,
+                                            FaceState &fr)
 {
-    float zL = L.z + 0.5f * minmod(L.z - A.z, R.z - L.z);
-    float hL = L.h + 0.5f * minmod(L.h - A.h, R.h - L.h);
-    float tL = L.ut + 0.5f * minmod(L.ut - A.ut, R.ut - L.ut);
-    float nL = L.uLn + 0.5f * minmod(L.uLn - A.uLn, R.uLn - L.uLn);
-    float sL = L.uLt + 0.5f * minmod(L.uLt - A.uLt, R.uLt - L.uLt);
-    float zR = R.z - 0.5f * minmod(R.z - L.z, B.z - R.z);
-    float hR = R.h - 0.5f * minmod(R.h - L.h, B.h - R.h);
-    float tR = R.ut - 0.5f * minmod(R.ut - L.ut, B.ut - R.ut);
-    float nR = R.uLn - 0.5f * minmod(R.uLn - L.uLn, B.uLn - R.uLn);
-    float sR = R.uLt - 0.5f * minmod(R.uLt - L.uLt, B.uLt - R.uLt);
+    float zL = L.z + 0.5f * limited<true>(P, L.z - A.z, R.z - L.z);
+    float hL = L.h + 0.5f * limited<true>(P, L.h - A.h, R.h - L.h);
+    float tL = L.ut + 0.5f * limited<true>(P, L.ut - A.ut, R.ut - L.ut);
+    float nL = L.uLn + 0.5f * limited<true>(P, L.uLn - A.uLn, R.uLn - L.uLn);
+    float sL = L.uLt + 0.5f * limited<true>(P, L.uLt - A.uLt, R.uLt - L.uLt);
+    float zR = R.z - 0.5f * limited<true>(P, R.z - L.z, B.z - R.z);
+    float hR = R.h - 0.5f * limited<true>(P, R.h - L.h, B.h - R.h);
+    float tR = R.ut - 0.5f * limited<true>(P, R.ut - L.ut, B.ut - R.ut);
+    float nR = R.uLn - 0.5f * limited<true>(P, R.uLn - L.uLn, B.uLn - R.uLn);
+    float sR = R.uLt - 0.5f * limited<true>(P, R.uLt - L.uLt, B.uLt - R.uLt);
     float bL = zL - hL, bR = zR - hR;
     float bf = fmaxf(bL, bR);
     fl.Hs = fmaxf(0.0f, zL - bf);
@@ -276,27 +304,33 @@ __device__ __forceinline__ void face_states(const CellQ &A, const CellQ &L, cons
 
 // One-sided face state of a boundary cell: its neighbour inside (A) and its
 // ghost outside (G); side = +1 for the E/N face, -1 for the W/S face.
-__device__ __forceinline__ FaceState boundary_state(const CellQ &A, const CellQ &C,
-                                                    const CellQ &G, float side)
+__device__ __forceinline__ FaceState boundary_state(const KPar &P, const CellQ &A,
+                                                    const CellQ &C, const CellQ &G, float side)
 {
     // slope of C from its two neighbours in increasing coordinate order
     const CellQ &lo = side > 0.0f ? A : G;
     const CellQ &hi = side > 0.0f ? G : A;
-    float z = C.z + side * 0.5f * minmod(C.z - lo.z, hi.z - C.z);
-    float h = C.h + side * 0.5f * minmod(C.h - lo.h, hi.h - C.h);
+    float z = C.z + side * 0.5f * limited<true>(P, C.z - lo.z, hi.z - C.z);
+    float h = C.h + side * 0.5f * limited<true>(P, C.h - lo.h, hi.h - C.h);
     FaceState s;
-    s.ut = C.ut + side * 0.5f * minmod(C.ut - lo.ut, hi.ut - C.ut);
-    s.uLn = C.uLn + side * 0.5f * minmod(C.uLn - lo.uLn, hi.uLn - C.uLn);
-    s.uLt = C.uLt + side * 0.5f * minmod(C.uLt - lo.uLt, hi.uLt - C.uLt);
+    s.ut = C.ut + side * 0.5f * limited<true>(P, C.ut - lo.ut, hi.ut - C.ut);
+    s.uLn = C.uLn + side * 0.5f * limited<true>(P, C.uLn - lo.uLn, hi.uLn - C.uLn);
+    s.uLt = C.uLt + side * 0.5f * limited<true>(P, C.uLt - lo.uLt, hi.uLt - C.uLt);
     float bb = z - h;
     s.Hs = fmaxf(0.0f, z - bb);
     return s;
 }
 
-// HLL flux of the remap: U = (Hs, Hs uLn, Hs uLt), F = ut U, Davis speeds.
-__device__ __forceinline__ void hll(float g, const FaceState &l, const FaceState &r, float &fH,
-                                    float &fn, float &ft)
+// HLL flux of the remap: U = (Hs, Hs uLn, Hs uLt), F = ut U.  Wave speeds:
+// Davis, SL = min(uL - cL, uR - cR), SR = max(uL + cL, uR + cR); or (V and
+// P.speeds = 1) the two-rarefaction estimate SL = min(uL - cL, u* - c*),
+// SR = max(uR + cR, u* + c*) with u* = (uL + uR)/2 + cL - cR and
+// c* = max(0, (cL + cR)/2 + (uL - uR)/4) (Toro).
+template <bool V>
+__device__ __forceinline__ void hll(const KPar &P, const FaceState &l, const FaceState &r,
+                                    float &fH, float &fn, float &ft)
 {
+    const float g = P.g;
     float UL0 = l.Hs, UL1 = l.Hs * l.uLn, UL2 = l.Hs * l.uLt;
     float UR0 = r.Hs, UR1 = r.Hs * r.uLn, UR2 = r.Hs * r.uLt;
     float FL0 = l.ut * UL0, FL1 = l.ut * UL1, FL2 = l.ut * UL2;
@@ -304,6 +338,12 @@ __device__ __forceinline__ void hll(float g, const FaceState &l, const FaceState
     float cL = nsqrt(g * l.Hs), cR = nsqrt(g * r.Hs);
     float SL = fminf(l.ut - cL, r.ut - cR);
     float SR = fmaxf(l.ut + cL, r.ut + cR);
+    if (V && P.speeds == 1) {
+        const float us = 0.5f * (l.ut + r.ut) + cL - cR;
+        const float cs = fmaxf(0.0f, 0.5f * (cL + cR) + 0.25f * (l.ut - r.ut));
+        SL = fminf(l.ut - cL, us - cs);
+        SR = fmaxf(r.ut + cR, us + cs);
+    }
     // the four cases are selected, not branched: every lane evaluates the
     // HLL average and keeps the upwind flux when both speeds share a sign
     const bool left = SL >= 0.0f, right = SR <= 0.0f, fan = SR - SL > 0.0f;
@@ -318,12 +358,17 @@ __device__ __forceinline__ void hll(float g, const FaceState &l, const FaceState
 }
 
 // Wall face fluxes (HLL against the mirrored ghost): no mass, no tangential
-// momentum; normal momentum Hs uLn (ut +- |ut| +- c) with the upper signs for
-// the interior cell on the minus side (E/N wall).
-__device__ __forceinline__ float wall_flux_n(float g, const FaceState &s, float side)
+// momentum; normal momentum Hs uLn (ut + side S), side = +1 for the interior
+// cell on the minus side (E/N wall), -1 on the plus side (W/S wall).  The
+// mirrored pair has symmetric speeds -S, S: Davis S = |ut| + c; the
+// two-rarefaction estimate S = max(c - side ut, max(0, c + side ut / 2)).
+template <bool V>
+__device__ __forceinline__ float wall_flux_n(const KPar &P, const FaceState &s, float side)
 {
-    float c = nsqrt(g * s.Hs);
-    return s.Hs * s.uLn * (s.ut + side * (fabsf(s.ut) + c));
+    float c = nsqrt(P.g * s.Hs);
+    float S = fabsf(s.ut) + c;
+    if (V && P.speeds == 1) S = fmaxf(c - side * s.ut, fmaxf(0.0f, c + side * 0.5f * s.ut));
+    return s.Hs * s.uLn * (s.ut + side * S);
 }
 
 // Bedload face flux: donor split of J0 plus the slope term of Eq. 2 with the
@@ -347,21 +392,21 @@ __device__ __forceinline__ void water_flux(const KPar &P, int k, int n, bool wal
     fH = fn = ft = 0.0f;
     if (k > 0 && k < n) {
         FaceState fl, fr;
-        face_states(c0, c1, c2, c3, fl, fr);
-        hll(P.g, fl, fr, fH, fn, ft);
+        face_states(P, c0, c1, c2, c3, fl, fr);
+        hll<true>(P, fl, fr, fH, fn, ft);
     } else if (k == n) {  // high boundary: interior cell c1, its inner neighbour c0, ghost c2
-        FaceState s = boundary_state(c0, c1, c2, 1.0f);
+        FaceState s = boundary_state(P, c0, c1, c2, 1.0f);
         if (wallHi) {
-            fn = wall_flux_n(P.g, s, 1.0f);
+            fn = wall_flux_n<true>(P, s, 1.0f);
         } else {
             fH = s.ut * s.Hs;
             fn = s.ut * s.Hs * s.uLn;
             ft = s.ut * s.Hs * s.uLt;
         }
     } else {  // k == 0: interior cell c2, its inner neighbour c3, ghost c1
-        FaceState s = boundary_state(c3, c2, c1, -1.0f);
+        FaceState s = boundary_state(P, c3, c2, c1, -1.0f);
         if (wallLo) {
-            fn = wall_flux_n(P.g, s, -1.0f);
+            fn = wall_flux_n<true>(P, s, -1.0f);
         } else {
             fH = s.ut * s.Hs;
             fn = s.ut * s.Hs * s.uLn;
@@ -371,7 +416,7 @@ __device__ __forceinline__ void water_flux(const KPar &P, int k, int n, bool wal
 }
 
 // Reconstructed values of one cell on its two faces along a direction: the
-// minmod slope of each quantity from the neighbours M (minus side) and Q
+// limited slope of each quantity from the neighbours M (minus side) and Q
 // (plus side), value -/+ slope/2, and the bed under each face value.  The
 // face between cells k-1 and k takes the plus side of k-1 and the minus side
 // of k; this gives the bits of face_states / boundary_state (same slopes,
@@ -380,14 +425,15 @@ struct SideQ {
     float z, h, ut, uLn, uLt, b;
 };
 
-__device__ __forceinline__ void reconstruct(const CellQ &M, const CellQ &C, const CellQ &Q,
-                                            SideQ &minus, SideQ &plus)
+template <bool V>
+__device__ __forceinline__ void reconstruct(const KPar &P, const CellQ &M, const CellQ &C,
+                                            const CellQ &Q, SideQ &minus, SideQ &plus)
 {
-    const float sz = minmod(C.z - M.z, Q.z - C.z);
-    const float sh = minmod(C.h - M.h, Q.h - C.h);
-    const float st = minmod(C.ut - M.ut, Q.ut - C.ut);
-    const float sn = minmod(C.uLn - M.uLn, Q.uLn - C.uLn);
-    const float ss = minmod(C.uLt - M.uLt, Q.uLt - C.uLt);
+    const float sz = limited<V>(P, C.z - M.z, Q.z - C.z);
+    const float sh = limited<V>(P, C.h - M.h, Q.h - C.h);
+    const float st = limited<V>(P, C.ut - M.ut, Q.ut - C.ut);
+    const float sn = limited<V>(P, C.uLn - M.uLn, Q.uLn - C.uLn);
+    const float ss = limited<V>(P, C.uLt - M.uLt, Q.uLt - C.uLt);
     plus.z = C.z + 0.5f * sz;
     plus.h = C.h + 0.5f * sh;
     plus.ut = C.ut + 0.5f * st;
@@ -406,6 +452,7 @@ __device__ __forceinline__ void reconstruct(const CellQ &M, const CellQ &C, cons
 // the minus side R of cell k (the result of water_flux): interior faces take
 // hydrostatic face depths and HLL; a boundary face uses the interior cell's
 // side only (wall flux, or the physical flux on an open side).
+template <bool V>
 __device__ __forceinline__ void side_flux(const KPar &P, int k, int n, bool wallLo, bool wallHi,
                                           const SideQ &L, const SideQ &R, float &fH, float &fn,
                                           float &ft)
@@ -416,7 +463,7 @@ __device__ __forceinline__ void side_flux(const KPar &P, int k, int n, bool wall
     FaceState fl, fr;
     fl.Hs = fmaxf(0.0f, L.z - bf); fl.uLn = L.uLn; fl.uLt = L.uLt; fl.ut = L.ut;
     fr.Hs = fmaxf(0.0f, R.z - bf); fr.uLn = R.uLn; fr.uLt = R.uLt; fr.ut = R.ut;
-    hll(P.g, fl, fr, fH, fn, ft);
+    hll<V>(P, fl, fr, fH, fn, ft);
     if (k > 0 && k < n) return;
     fH = fn = ft = 0.0f;
     const SideQ &C = k == n ? L : R;
@@ -424,7 +471,7 @@ __device__ __forceinline__ void side_flux(const KPar &P, int k, int n, bool wall
     FaceState s;
     s.Hs = fmaxf(0.0f, C.z - C.b); s.uLn = C.uLn; s.uLt = C.uLt; s.ut = C.ut;
     if (k == n ? wallHi : wallLo) {
-        fn = wall_flux_n(P.g, s, side);
+        fn = wall_flux_n<V>(P, s, side);
     } else {
         fH = s.ut * s.Hs;
         fn = s.ut * s.Hs * s.uLn;
