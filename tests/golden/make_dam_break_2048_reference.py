@@ -8,15 +8,16 @@ Stored:
 * every 16th cell in each direction of h, hu, hv, b (float64), the wet mask
   (h > 1e-4 m) of every cell (bit-packed), the water volume, boundary outflow,
   model time and the Eq. 7 maximum of |v| + c of the final state;
-* the oracle's sensitivity to the float32 rounding of its inputs: a second
-  oracle run from the same scenario's float64 inputs (not rounded).  For each
-  field, every cell where the two runs differ by more than 5e-6 m (h, b) or
-  5e-6 m times max(|v| + c) (hu, hv) is listed with that spread (flat index,
-  float32 spread): the cells where this flow amplifies rounding-level
-  differences of the input.
+* the problem's sensitivity to float32 rounding: a second run of the same
+  algorithm evaluated in float32 arithmetic (oracle.run_f32, the oracle's own
+  source compiled with every literal and operation in float32), from the
+  same inputs.  For each field, every cell where the two runs differ by more
+  than 5e-6 m (h, b) or 5e-6 m times max(|v| + c) (hu, hv) is listed with that
+  spread (flat index, float32 spread): the cells where this flow amplifies
+  rounding at float32 precision.
 
-Only the oracle and the seeded input generator are called.  Takes about
-20 minutes on 8 cores.
+Only the oracle (FP64, and its float32 evaluation) and the seeded input
+generator are called.  Takes about 20 minutes on 8 cores.
 """
 import os
 import sys
@@ -38,12 +39,15 @@ LIST_H = 5e-6   # m: spreads listed for h and b above this
 OUT = os.path.join(HERE, "dam_break_2048_ref.npz")
 
 
-def run(w, label):
+def run(w, label, f32=False):
     p, inp, s = oracle_case(O, w)
     V0 = O.volumes(p, inp, s)[0]
     t0 = time.time()
     for k in range(STEPS):
-        O.step(p, inp, s)
+        if f32:
+            O.run_f32(p, inp, s, 1)
+        else:
+            O.step(p, inp, s)
         if (k + 1) % 50 == 0:
             print(f"{label}: step {k + 1}/{STEPS}  t={s.t:.3f}  {time.time() - t0:.0f} s", flush=True)
     return p, inp, s, V0
@@ -61,8 +65,7 @@ def main():
     Vw, Vs = O.volumes(p, inp, s)
     vs = O.cfl(p, inp, s)["vs"]
     sl = (slice(0, None, STRIDE), slice(0, None, STRIDE))
-    wp = W.dam_break_fractal(n=2048, steps=STEPS)
-    _, _, sp, _ = run(wp, "float64 inputs")
+    _, _, sp, _ = run(w, "float32 evaluation", f32=True)
     lists = {}
     for name, a, b, thr in (("h", s.H, sp.H, LIST_H), ("hu", s.qx, sp.qx, LIST_H * vs),
                             ("hv", s.qy, sp.qy, LIST_H * vs), ("b", s.b, sp.b, LIST_H)):

@@ -50,13 +50,16 @@ def run_oracle(O, w, steps, dt=None, **over):
 # the largest wave speed max(|v| + c) of the oracle's final state (a depth
 # error dh carried by a wave moves the discharge by (u +- c) dh).
 LINF_H = 1e-4
-# A cell counts as ill-conditioned when the oracle's own answer moves by more
-# than COND times the field's bound when its inputs move by their float32
-# rounding (oracle on the float64 inputs vs on the float32-rounded ones): no
-# float32 path can be held to the bound there.  Such cells are counted and
-# reported, and may make up at most ILL_MAX of the grid.
+# A cell counts as ill-conditioned when the same algorithm evaluated in
+# float32 arithmetic (the oracle's source compiled in float32, oracle.run_f32)
+# already ends more than COND times the field's bound away from the FP64
+# answer there: rounding at float32 precision alone moves the result by that
+# much, so no float32 implementation can be held to the bound at that cell.
+# Such cells are counted and reported instead of asserted; as a guard against
+# a criterion that excuses too much they may make up at most ILL_MAX of the
+# grid (a small minority: fronts and shocks, not the flow).
 COND = 0.1
-ILL_MAX = 1e-3
+ILL_MAX = 5e-3
 
 
 def field_check(fields, st, spread, vs):
@@ -76,17 +79,20 @@ def field_check(fields, st, spread, vs):
     return out
 
 
-def oracle_spread(O, w64, st, steps, dt=None, **over):
-    """|oracle(float64 inputs) - oracle(float32 inputs)| per field: how far
-    the FP64 answer itself moves under the float32 rounding of the inputs."""
-    _, _, s64 = run_oracle(O, w64, steps, dt, **over)
-    return {"h": np.abs(s64.H - st.H), "hu": np.abs(s64.qx - st.qx),
-            "hv": np.abs(s64.qy - st.qy), "b": np.abs(s64.b - st.b)}
+def oracle_spread(O, w, st, steps, dt=None, **over):
+    """|oracle in float32 arithmetic - FP64 oracle state st| per field, both from
+    workload w's inputs: how far float32 rounding alone moves the answer."""
+    p, inp, s32 = oracle_case(O, w, **over)
+    O.run_f32(p, inp, s32, steps, dt_fixed=dt or 0.0)
+    return {"h": np.abs(s32.H - st.H), "hu": np.abs(s32.qx - st.qx),
+            "hv": np.abs(s32.qy - st.qy), "b": np.abs(s32.b - st.b)}
 
 
-def compare(O, w, gpu, orc, wet_h=1e-4, w64=None, steps=None, dt=None):
+def compare(O, w, gpu, orc, wet_h=1e-4, spread=False, steps=None, dt=None, over=None):
     """Per-field errors of the FP32 GPU result against the FP64 oracle; with
-    w64 (the scenario before float32 rounding) also the oracle's own spread."""
+    spread, cells the float32 evaluation of the oracle marks ill-conditioned
+    are counted apart (oracle_spread over the same steps; `over`: the oracle
+    parameters that differ from the defaults, such as a limiter)."""
     (h, hu, hv, b), sums = gpu
     p, inp, st = orc
     dx2 = w.dx * w.dx
@@ -108,7 +114,7 @@ def compare(O, w, gpu, orc, wet_h=1e-4, w64=None, steps=None, dt=None):
         "t_oracle": st.t,
     }
     vs = O.cfl(p, inp, st)["vs"]
-    spread = oracle_spread(O, w64, st, steps, dt) if w64 is not None else None
-    res["fields"] = field_check((h, hu, hv, b), st, spread, vs)
+    sp = oracle_spread(O, w, st, steps, dt, **(over or {})) if spread else None
+    res["fields"] = field_check((h, hu, hv, b), st, sp, vs)
     res["cells"] = int(h.size)
     return res
