@@ -290,9 +290,11 @@ def surrogate_rates(csph, torch, train_steps=1500):
 def ensemble_rates(csph, W, torch, count=64, steps=1000):
     """64 dam-break members of uneven size (sides U{256..1536}, own terrain,
     depth, Manning n and Eq. 7 step), 1000 steps each: one batch (one launch
-    per stage over all members' tiles, graph replay) against the members
-    advanced one after another; both rates are all members' cell-steps over
-    the wall time, from the same initial states."""
+    per stage over all members' tiles, graph replay, tile shape from the
+    batch autotuner) against the members advanced one after another (each
+    with its set-up pass and step graphs done before the timing); both rates
+    are all members' cell-steps over the wall time, from the same initial
+    states."""
     log(f"[bench] ensemble of {count} x {steps} steps")
     ms = [m.as_float32() for m in W.ensemble(count=count, seed0=1000, n_min=256, n_max=1536,
                                              steps=steps)]
@@ -300,6 +302,7 @@ def ensemble_rates(csph, W, torch, count=64, steps=1000):
     stream = torch.cuda.current_stream()
     solvers = [csph.solver_for(m, stream=stream.cuda_stream) for m in ms]
     b = csph.Batch(solvers)
+    shape = b.autotune(10)  # the batch's tile shape, chosen from the initial states
     b.advance(2)
     b.sync()
     for s, m in zip(solvers, ms):
@@ -322,7 +325,7 @@ def ensemble_rates(csph, W, torch, count=64, steps=1000):
         t_seq += time.perf_counter() - t0
     for s in solvers:
         s.close()
-    res = {"members": count, "cells": cells, "steps": steps,
+    res = {"members": count, "cells": cells, "steps": steps, "batch_tile_shape": list(shape),
            "batched_gcell_steps_s": round(cells * steps / t_batch / 1e9, 3),
            "sequential_gcell_steps_s": round(cells * steps / t_seq / 1e9, 3),
            "speedup": round(t_seq / t_batch, 3)}

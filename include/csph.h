@@ -200,14 +200,16 @@ int sw_advance_fixed_dt(sw_ctx *ctx, int32_t nsteps, double dt);
  * unfused path. */
 int sw_advance_profiled(sw_ctx *ctx, int32_t nsteps, double *avg_ms);
 
-/* Use tile shape tile_x x tile_y for later steps: 64x8, 64x4, 64x16 or 128x4
+/* Tile shape of the hierarchical grid of Section 3 (the blocks whose dry
+ * members the HGS skips).  Use tile shape tile_x x tile_y for later steps: 64x8, 64x4, 64x16 or 128x4
  * cells per 256-thread workgroup staged through LDS, or 58x8 (the default),
  * 58x16 or 58x32 cells per wavefront (strips: one lane per column plus a
  * 3-column halo, rows marched in registers).  SW_ERR_ARG for any other shape.
  * Results do not depend on the shape (bit-identical). */
 int sw_set_tile_shape(sw_ctx *ctx, int32_t tile_x, int32_t tile_y);
 
-/* Tile-shape autotuner: from the current state, time nsteps of each tile
+/* Tile-shape autotuner for the tiles of the hierarchical grid of Section 3:
+ * from the current state, time nsteps of each tile
  * shape the library has (the seven of sw_set_tile_shape), put
  * the state, time and balances back, and keep the fastest shape for every
  * later step.  All shapes give bit-identical results.  Allocates and frees a
@@ -215,13 +217,19 @@ int sw_set_tile_shape(sw_ctx *ctx, int32_t tile_x, int32_t tile_y);
  * the chosen shape. */
 int sw_autotune(sw_ctx *ctx, int32_t nsteps, int32_t *tile_x, int32_t *tile_y);
 
-/* Wait for queued work; returns the sticky device error, if any. */
+/* Wait for queued work; returns the sticky device error, if any (the CPU
+ * side of the Solver loop of Section 3 waits for the GPU only here and in
+ * the two readbacks below). */
 int sw_sync(sw_ctx *ctx);
 
-/* Read the current fields (any pointer may be NULL to skip that field). */
+/* Read the current fields h, hu, hv, b (the state the Save and Screen blocks
+ * of Section 3 record; any pointer may be NULL to skip that field).
+ * Synchronises the context's stream. */
 int sw_get_fields(sw_ctx *ctx, float *h, float *hu, float *hv, float *b, int ptr_kind);
 
-/* FP64 global sums of the current state and the accumulated balances. */
+/* FP64 global sums of the current state and the accumulated balances (the
+ * water volume and the sediment volume of Eq. 1, the Eq. 7 maxima and the
+ * boundary and source balances).  Synchronises the context's stream. */
 int sw_get_sums(sw_ctx *ctx, sw_sums *out);
 
 /* Checkpoint and resume (the Save block of Section 3, for restarts): the
@@ -303,6 +311,35 @@ int swb_advance(swb_ctx *batch, int32_t nsteps);
 
 /* Wait for the batch; returns the first member's sticky device error. */
 int swb_sync(swb_ctx *batch);
+
+/* Batch tile-shape autotuner (the hierarchical tiling of Section 3 sized for
+ * an ensemble): from the members' current states, time nsteps batch steps of
+ * each tile shape, put every member's state, time and balances back, and keep
+ * the fastest shape for later swb_advance calls (results are bit-identical for
+ * every shape).  Members must hold states at steps of one parity
+ * (SW_ERR_STATE).  Allocates and frees a copy of each member's state;
+ * synchronises.  *tile_x, *tile_y (may be NULL) receive the chosen shape. */
+int swb_autotune(swb_ctx *batch, int32_t nsteps, int32_t *tile_x, int32_t *tile_y);
+
+/* Member m (0 <= m < n) of the batch, read or set through the batch: each
+ * call is the member's own sw_get_fields / sw_get_sums / sw_set_* (the Main
+ * block's inputs and the Save block's outputs of Section 3, per scenario),
+ * with the same arguments, ordering and errors; SW_ERR_ARG for an index out of
+ * range.  A new state restarts the member's step counter, so the batch then
+ * advances only once all members stand at steps of one parity again. */
+int swb_get_fields(swb_ctx *batch, int32_t m, float *h, float *hu, float *hv, float *b,
+                   int ptr_kind);
+int swb_get_sums(swb_ctx *batch, int32_t m, sw_sums *out);
+int swb_set_state(swb_ctx *batch, int32_t m, const float *h, const float *hu, const float *hv,
+                  int ptr_kind);
+int swb_set_bed(swb_ctx *batch, int32_t m, const float *b, int ptr_kind);
+int swb_set_soil(swb_ctx *batch, int32_t m, const float *manning, float manning_scalar,
+                 const float *d50, float d50_scalar, const float *psi, float psi_scalar,
+                 int ptr_kind);
+int swb_set_inflow(swb_ctx *batch, int32_t m, const int32_t *cell_idx, const float *weight,
+                   int32_t n, double q_base, double q_peak, double t_peak, double t_sigma);
+int swb_set_sed_sources(swb_ctx *batch, int32_t m, const float *qb_plus, const float *qb_minus,
+                        int ptr_kind);
 
 const char *swb_last_error(const swb_ctx *batch);
 

@@ -97,6 +97,18 @@ SIGNATURES = [
     ("swb_advance", C.c_int, [C.c_void_p, C.c_int32]),
     ("swb_sync", C.c_int, [C.c_void_p]),
     ("swb_last_error", C.c_char_p, [C.c_void_p]),
+    ("swb_autotune", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    ("swb_get_fields", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_int]),
+    ("swb_get_sums", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(sw_sums)]),
+    ("swb_set_state", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_int]),
+    ("swb_set_bed", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int]),
+    ("swb_set_soil", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_float, C.c_void_p,
+                               C.c_float, C.c_void_p, C.c_float, C.c_int]),
+    ("swb_set_inflow", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                 C.c_double, C.c_double, C.c_double, C.c_double]),
+    ("swb_set_sed_sources", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int]),
     ("sw_replace_state", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_double, C.c_int64]),
     ("sw_get_grid", C.c_int, [_ctxp, C.POINTER(sw_grid)]),
@@ -394,6 +406,35 @@ class Batch:
 
     def sync(self):
         _bcheck(self.ctx, lib.swb_sync(self.ctx))
+
+    def autotune(self, nsteps=10):
+        """Pick the fastest tile shape for the batch from the current states."""
+        tx, ty = C.c_int32(), C.c_int32()
+        _bcheck(self.ctx, lib.swb_autotune(self.ctx, int(nsteps), C.byref(tx), C.byref(ty)))
+        return tx.value, ty.value
+
+    def get_fields(self, m):
+        """Member m's (h, hu, hv, b) as float32 numpy arrays [ny, nx]."""
+        s = self.members[m]
+        arrs = [np.empty((s.ny, s.nx), dtype=np.float32) for _ in range(4)]
+        _bcheck(self.ctx, lib.swb_get_fields(self.ctx, int(m),
+                                             *[a.ctypes.data_as(C.c_void_p) for a in arrs],
+                                             SW_PTR_HOST))
+        return tuple(arrs)
+
+    def get_sums(self, m) -> dict:
+        out = sw_sums()
+        _bcheck(self.ctx, lib.swb_get_sums(self.ctx, int(m), C.byref(out)))
+        return out.as_dict()
+
+    def set_state(self, m, h, hu, hv):
+        n = self.members[m].n
+        (ph, kind, k1), (pu, _, k2), (pv, _, k3) = (_ptr(x, n) for x in (h, hu, hv))
+        _bcheck(self.ctx, lib.swb_set_state(self.ctx, int(m), ph, pu, pv, kind))
+
+    def set_bed(self, m, b):
+        p, kind, keep = _ptr(b, self.members[m].n)
+        _bcheck(self.ctx, lib.swb_set_bed(self.ctx, int(m), p, kind))
 
 
 def _scheck(h, rc):

@@ -2456,6 +2456,61 @@ int launch_steps(sw_ctx *c, int32_t nsteps, int fixed, double dt)
     return SW_OK;
 }
 
+// A copy of a context's current state (fields, bed residual, boundary
+// accumulators, control block and step index) on the device, to put back
+// after trial steps (the autotuners).
+struct StateKeep {
+    float *planes = nullptr;
+    double *bnd = nullptr;
+    Ctrl ctrl{};
+    int64_t k0 = 0;
+};
+
+int keep_save(sw_ctx *c, StateKeep &kp)
+{
+    int rc = read_ctrl(c, &kp.ctrl);
+    if (rc) return rc;
+    if (kp.ctrl.err) return fail(c, kp.ctrl.err, "trial steps with a pending device error");
+    kp.k0 = c->k;
+    const int cur = (int)(kp.k0 & 1);
+    const size_t nb = 4 * (size_t)(c->nx + c->ny);
+    HIPCHK(c, hipMalloc(&kp.planes, 5 * c->plane * sizeof(float)));
+    HIPCHK(c, hipMalloc(&kp.bnd, nb * sizeof(double)));
+    const float *src[5] = {c->H[cur], c->qx[cur], c->qy[cur], c->b[cur], c->rb};
+    for (int f = 0; f < 5; ++f)
+        HIPCHK(c, hipMemcpyAsync(kp.planes + f * c->plane, src[f], c->plane * sizeof(float),
+                                 hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(kp.bnd, c->bnd, nb * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SW_OK;
+}
+
+// Put the kept state back (the next advance runs the set-up pass).
+int keep_restore(sw_ctx *c, const StateKeep &kp)
+{
+    const int cur = (int)(kp.k0 & 1);
+    const size_t nb = 4 * (size_t)(c->nx + c->ny);
+    float *dst[5] = {c->H[cur], c->qx[cur], c->qy[cur], c->b[cur], c->rb};
+    for (int f = 0; f < 5; ++f)
+        HIPCHK(c, hipMemcpyAsync(dst[f], kp.planes + f * c->plane, c->plane * sizeof(float),
+                                 hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->bnd, kp.bnd, nb * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    int rc = stage_to_device(c, c->ctrl, &kp.ctrl, sizeof(Ctrl));
+    if (rc) return rc;
+    c->k = kp.k0;
+    c->dirty = true;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SW_OK;
+}
+
+void keep_free(StateKeep &kp)
+{
+    (void)hipFree(kp.planes);
+    (void)hipFree(kp.bnd);
+    kp.planes = nullptr;
+    kp.bnd = nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2916,47 +2971,17 @@ int sw_autotune(sw_ctx *c, int32_t nsteps, int32_t *tile_x, int32_t *tile_y)
     if (nsteps < 1) return fail(c, SW_ERR_ARG, "nsteps must be >= 1");
     if (!c->have_state) return fail(c, SW_ERR_STATE, "autotune before sw_set_state");
     if (c->par.flags & SW_FLAG_UNFUSED) return fail(c, SW_ERR_ARG, "the unfused path has no tiles");
-    Ctrl saved;
-    int rc = read_ctrl(c, &saved);
-    if (rc) return rc;
-    if (saved.err) return fail(c, saved.err, "autotune with a pending device error");
-    const int64_t k0 = c->k;
-    const int cur = (int)(k0 & 1);
-    const size_t nb = 4 * (size_t)(c->nx + c->ny);
-    float *keep = nullptr;
-    double *keepb = nullptr;
-    HIPCHK(c, hipMalloc(&keep, 5 * c->plane * sizeof(float)));
-    hipError_t e = hipMalloc(&keepb, nb * sizeof(double));
-    if (e != hipSuccess) {
-        (void)hipFree(keep);
-        return fail(c, SW_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+    StateKeep kp;
+    int rc = keep_save(c, kp);
+    if (rc) {
+        keep_free(kp);
+        return rc;
     }
-    float *src[5] = {c->H[cur], c->qx[cur], c->qy[cur], c->b[cur], c->rb};
-    auto save_restore = [&](bool save) -> int {
-        for (int f = 0; f < 5; ++f) {
-            float *a = keep + f * c->plane, *b = src[f];
-            HIPCHK(c, hipMemcpyAsync(save ? a : b, save ? b : a, c->plane * sizeof(float),
-                                     hipMemcpyDeviceToDevice, c->stream));
-        }
-        HIPCHK(c, hipMemcpyAsync(save ? keepb : c->bnd, save ? c->bnd : keepb, nb * sizeof(double),
-                                 hipMemcpyDeviceToDevice, c->stream));
-        if (!save) {
-            {
-                const int rc_ = stage_to_device(c, c->ctrl, &saved, sizeof(Ctrl));
-                if (rc_) return rc_;
-            }
-            c->k = k0;
-            c->dirty = true;
-        }
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        return SW_OK;
-    };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int best = c->shape;
     float best_ms = 0.0f;
-    rc = save_restore(true);
-    if (!rc && hipEventCreate(&e0) != hipSuccess) rc = fail(c, SW_ERR_HIP, "hipEventCreate");
-    if (!rc && hipEventCreate(&e1) != hipSuccess) rc = fail(c, SW_ERR_HIP, "hipEventCreate");
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rc = fail(c, SW_ERR_HIP, "hipEventCreate");
     for (int sh = 0; sh < kNumShapes && !rc; ++sh) {
         set_shape(c, sh);
         if ((rc = prepare(c))) break;
@@ -2976,13 +3001,12 @@ int sw_autotune(sw_ctx *c, int32_t nsteps, int32_t *tile_x, int32_t *tile_y)
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (sh == 0 || ms < best_ms) { best_ms = ms; best = sh; }
-        if ((rc = save_restore(false))) break;
+        if ((rc = keep_restore(c, kp))) break;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (!rc) rc = save_restore(false);
-    (void)hipFree(keep);
-    (void)hipFree(keepb);
+    if (!rc) rc = keep_restore(c, kp);
+    keep_free(kp);
     if (rc) return rc;
     set_shape(c, best);
     if (tile_x) *tile_x = kShapes[best].tx;
@@ -3673,5 +3697,139 @@ int swb_sync(swb_ctx *b)
 }
 
 const char *swb_last_error(const swb_ctx *b) { return b ? b->err.c_str() : "null batch"; }
+
+int swb_autotune(swb_ctx *b, int32_t nsteps, int32_t *tile_x, int32_t *tile_y)
+{
+    if (!b) return SW_ERR_ARG;
+    if (nsteps < 1) return bfail(b, SW_ERR_ARG, "nsteps must be >= 1");
+    const int n = (int)b->mem.size();
+    const int par0 = (int)(b->mem[0]->k & 1);
+    for (int m = 0; m < n; ++m) {
+        if (!b->mem[m]->have_state)
+            return bfail(b, SW_ERR_STATE, "member " + std::to_string(m) + " has no state");
+        if ((int)(b->mem[m]->k & 1) != par0)
+            return bfail(b, SW_ERR_STATE, "members are at steps of different parity");
+    }
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    std::vector<StateKeep> keep(n);
+    int rc = SW_OK;
+    for (int m = 0; m < n && !rc; ++m)
+        if ((rc = keep_save(b->mem[m], keep[m]))) rc = bfail(b, rc, "member " + std::to_string(m) + ": " + b->mem[m]->err);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = bfail(b, SW_ERR_HIP, "hipEventCreate");
+    const int shape0 = b->shape;
+    int best = shape0;
+    float best_ms = 0.0f;
+    for (int sh = 0; sh < kNumShapes && !rc; ++sh) {
+        b->shape = sh;
+        b->built = false;
+        if ((rc = batch_build(b))) break;
+        for (int m = 0; m < n && !rc; ++m)
+            if (b->mem[m]->dirty && (rc = prepare(b->mem[m])))
+                rc = bfail(b, rc, "member " + std::to_string(m) + ": " + b->mem[m]->err);
+        if (rc) break;
+        if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = bfail(b, SW_ERR_HIP, "hipEventRecord"); break; }
+        for (int32_t s = 0; s < nsteps; ++s) {
+            batch_step(b, b->stream, (int)(b->mem[0]->k & 1));
+            for (sw_ctx *c : b->mem) c->k++;
+        }
+        if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = bfail(b, SW_ERR_HIP, "kernel timing failed");
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (sh == 0 || ms < best_ms) { best_ms = ms; best = sh; }
+        for (int m = 0; m < n && !rc; ++m)
+            if ((rc = keep_restore(b->mem[m], keep[m])))
+                rc = bfail(b, rc, "member " + std::to_string(m) + ": " + b->mem[m]->err);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (int m = 0; m < n; ++m) {
+        if (!rc && keep[m].planes && (rc = keep_restore(b->mem[m], keep[m])))
+            rc = bfail(b, rc, "member " + std::to_string(m) + ": " + b->mem[m]->err);
+        keep_free(keep[m]);
+    }
+    b->shape = rc ? shape0 : best;
+    b->built = false;
+    if (rc) return rc;
+    if (tile_x) *tile_x = kShapes[best].tx;
+    if (tile_y) *tile_y = kShapes[best].ty;
+    return SW_OK;
+}
+
+// Per-member access through the batch: the members are ordinary contexts, so
+// each call forwards to the member's own entry point (and its error text is
+// copied into the batch's).
+static int bmember(swb_ctx *b, int32_t m, sw_ctx **c)
+{
+    if (!b) return SW_ERR_ARG;
+    if (m < 0 || m >= (int32_t)b->mem.size()) return bfail(b, SW_ERR_ARG, "member index out of range");
+    *c = b->mem[m];
+    return SW_OK;
+}
+static int bforward(swb_ctx *b, sw_ctx *c, int rc)
+{
+    if (rc) b->err = c->err;
+    return rc;
+}
+
+int swb_get_fields(swb_ctx *b, int32_t m, float *h, float *hu, float *hv, float *bed, int ptr_kind)
+{
+    sw_ctx *c = nullptr;
+    int rc = bmember(b, m, &c);
+    return rc ? rc : bforward(b, c, sw_get_fields(c, h, hu, hv, bed, ptr_kind));
+}
+
+int swb_get_sums(swb_ctx *b, int32_t m, sw_sums *out)
+{
+    sw_ctx *c = nullptr;
+    int rc = bmember(b, m, &c);
+    return rc ? rc : bforward(b, c, sw_get_sums(c, out));
+}
+
+int swb_set_state(swb_ctx *b, int32_t m, const float *h, const float *hu, const float *hv,
+                  int ptr_kind)
+{
+    sw_ctx *c = nullptr;
+    int rc = bmember(b, m, &c);
+    return rc ? rc : bforward(b, c, sw_set_state(c, h, hu, hv, ptr_kind));
+}
+
+int swb_set_bed(swb_ctx *b, int32_t m, const float *bed, int ptr_kind)
+{
+    sw_ctx *c = nullptr;
+    int rc = bmember(b, m, &c);
+    return rc ? rc : bforward(b, c, sw_set_bed(c, bed, ptr_kind));
+}
+
+int swb_set_soil(swb_ctx *b, int32_t m, const float *manning, float manning_scalar, const float *d50,
+                 float d50_scalar, const float *psi, float psi_scalar, int ptr_kind)
+{
+    sw_ctx *c = nullptr;
+    int rc = bmember(b, m, &c);
+    return rc ? rc
+              : bforward(b, c, sw_set_soil(c, manning, manning_scalar, d50, d50_scalar, psi,
+                                           psi_scalar, ptr_kind));
+}
+
+int swb_set_inflow(swb_ctx *b, int32_t m, const int32_t *cell_idx, const float *weight, int32_t n,
+                   double q_base, double q_peak, double t_peak, double t_sigma)
+{
+    sw_ctx *c = nullptr;
+    int rc = bmember(b, m, &c);
+    return rc ? rc
+              : bforward(b, c, sw_set_inflow(c, cell_idx, weight, n, q_base, q_peak, t_peak, t_sigma));
+}
+
+int swb_set_sed_sources(swb_ctx *b, int32_t m, const float *qb_plus, const float *qb_minus,
+                        int ptr_kind)
+{
+    sw_ctx *c = nullptr;
+    int rc = bmember(b, m, &c);
+    return rc ? rc : bforward(b, c, sw_set_sed_sources(c, qb_plus, qb_minus, ptr_kind));
+}
 
 }  // extern "C"

@@ -95,3 +95,66 @@ def test_gpu_batch_rejects_mixed_parity():
     b.close()
     for s in solvers:
         s.close()
+
+
+def test_gpu_batch_full_size_member_matches_oracle():
+    """A member of the ensemble's full size (1024 x 1024, within the 256..1536
+    range of the 64-member workload: own fractal bed, reservoir depth, Manning
+    n) advanced in a batch beside small members, read through swb_get_fields
+    / swb_get_sums, against the FP64 oracle on every cell (cells
+    ill-conditioned at float32 precision counted apart)."""
+    import torch
+    from oracle import oracle as O
+    from paper_2103_15196_amd import csph
+    from tests.test_gpu_parity import _check
+    O.build(force=False)
+    stream = torch.cuda.Stream()
+    big = W.dam_break_fractal(n=1024, dx=2.0, seed=1017, relief=10.0, dam_height=1.0, depth=6.5,
+                              manning=0.027).as_float32()
+    ms = [big] + _members()[:3]
+    solvers = [csph.solver_for(w, stream=stream.cuda_stream) for w in ms]
+    b = csph.Batch(solvers)
+    steps = 160
+    say(f"case batch member 1024x1024, {steps} steps")
+    b.advance(steps)
+    b.sync()
+    f, sums = b.get_fields(0), b.get_sums(0)
+    assert sums["step"] == steps
+    res = compare(O, big, (f, sums), run_oracle(O, big, steps), spread=True, steps=steps)
+    _check(res)
+    b.close()
+    for s in solvers:
+        s.close()
+
+
+def test_gpu_batch_autotune_keeps_states_and_bits():
+    """swb_autotune times every tile shape from the members' states, puts the
+    states back and keeps the fastest shape; the batch then still gives each
+    member's bits alone."""
+    import torch
+    from paper_2103_15196_amd import csph
+    stream = torch.cuda.Stream()
+    ms = _members()[:4]
+    solvers = [csph.solver_for(w, stream=stream.cuda_stream) for w in ms]
+    b = csph.Batch(solvers)
+    b.advance(10)
+    b.sync()
+    before = [b.get_fields(m) for m in range(len(ms))]
+    shape = b.autotune(5)
+    say(f"batch autotune chose {shape}")
+    for m in range(len(ms)):
+        for a, r in zip(b.get_fields(m), before[m]):
+            assert np.array_equal(a, r)
+        assert b.get_sums(m)["step"] == 10
+    b.advance(60)
+    b.sync()
+    for k, (w, s) in enumerate(zip(ms, solvers)):
+        rf, rsums = _solo(w, 70, stream.cuda_stream)
+        for a, r in zip(b.get_fields(k), rf):
+            assert np.array_equal(a, r), k
+    with pytest.raises(csph.SwError) as e:
+        b.get_sums(len(ms))  # member index out of range: checked in the library
+    assert e.value.code == csph.SW_ERR_ARG
+    b.close()
+    for s in solvers:
+        s.close()
