@@ -72,6 +72,11 @@ typedef struct {
     int32_t sed_law;  /* 0 none, 1 Grass (A_G, m_exp), 2 Eq. 4 coefficient (m = 4) */
     int32_t limiter;  /* TVD limiter of the Euler stage: 0 minmod, 1 MC, 2 superbee */
     int32_t hll_speeds; /* HLL wave speeds: 0 Davis, 1 two-rarefaction (Toro) */
+    /* Forcing named by Eq. 6's sigma and f without a formula (readings):    */
+    double rain;      /* rainfall rate, m/s, on every cell (mass only)       */
+    double coriolis;  /* Coriolis parameter f_c = 2 Omega sin(latitude), 1/s */
+    double wind_x, wind_y; /* wind velocity W at 10 m, m/s                   */
+    double wind_coef; /* C_w = (rho_air / rho_water) C_D, dimensionless      */
 } orc_params;
 
 typedef struct {
@@ -83,6 +88,7 @@ typedef struct {
     const int32_t *inflow_idx;   /* flat cell index of each inflow cell */
     const double *inflow_w;      /* weight of each inflow cell (sum 1) */
     double Q_base, Q_peak, t_peak, t_sigma;  /* hydrograph, m^3/s */
+    const double *beta; /* absorption (infiltration) coefficient, 1/s, or NULL [ny*nx] */
 } orc_inputs;
 
 typedef struct {
@@ -93,6 +99,8 @@ typedef struct {
     double in_w;        /* water volume added by inflow this step */
     double out_s;       /* sediment volume (1-psi) b dx^2 leaving this step */
     double in_s;        /* sediment volume added by q_b this step */
+    double rain_in;     /* water volume added by rainfall this step */
+    double absorbed;    /* water volume absorbed (infiltrated) this step */
 } orc_step_info;
 
 #ifdef _OPENMP
@@ -354,6 +362,20 @@ static void forces(const orc_params *p, const double *Hd, const double *b, doubl
     }
 }
 
+/* External forces per unit area on the momentum q of a column of depth    */
+/* Hd (the Earth-rotation and wind parts of f in Eq. 6, readings):          */
+/*   Coriolis  f_c (q_y, -q_x), turning the flow to the right for f_c > 0;  */
+/*   wind      C_w |W| W chi(Hd), chi = min(1, Hd / h_sed): the stress acts */
+/*             on water at least h_sed deep and fades to zero on a drying   */
+/*             cell (continuous at Hd = 0).                                  */
+static void forcing(const orc_params *p, double Hd, double qxc, double qyc, double *Fx, double *Fy)
+{
+    double Wm = sqrt(p->wind_x * p->wind_x + p->wind_y * p->wind_y);
+    double chi = fmin(1.0, Hd / p->h_sed);
+    *Fx = p->coriolis * qyc + p->wind_coef * Wm * p->wind_x * chi;
+    *Fy = -p->coriolis * qxc + p->wind_coef * Wm * p->wind_y * chi;
+}
+
 /* Manning friction rate gamma = g nM^2 |v| / max(H, eps)^(4/3), applied    */
 /* semi-implicitly (the bottom-friction part of f in Eq. 6).                */
 static double friction_rate(const orc_params *p, double nM, double speed, double H)
@@ -498,6 +520,7 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
     double *Sx = malloc(n * sizeof(double)), *Sy = malloc(n * sizeof(double));
     double *up = malloc(n * sizeof(double)), *vpv = malloc(n * sizeof(double));
     double *Hh = malloc(n * sizeof(double));
+    double *QPx = malloc(n * sizeof(double)), *QPy = malloc(n * sizeof(double));
     double *QLx = malloc(n * sizeof(double)), *QLy = malloc(n * sizeof(double));
     double *uLx = malloc(n * sizeof(double)), *uLy = malloc(n * sizeof(double));
     double *utx = malloc(n * sizeof(double)), *uty = malloc(n * sizeof(double));
@@ -531,8 +554,12 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
             double sp = sqrt(u[c] * u[c] + v[c] * v[c]);
             double gam = friction_rate(p, in->nM[c], sp, H[c]);
             double w = orc_w(H[c], eps);
-            double qpx = (qx[c] + 0.5 * dt * Sx[c]) / (1.0 + 0.5 * dt * gam);
-            double qpy = (qy[c] + 0.5 * dt * Sy[c]) / (1.0 + 0.5 * dt * gam);
+            double Fx, Fy;
+            forcing(p, H[c], qx[c], qy[c], &Fx, &Fy);
+            double qpx = (qx[c] + 0.5 * dt * (Sx[c] + Fx)) / (1.0 + 0.5 * dt * gam);
+            double qpy = (qy[c] + 0.5 * dt * (Sy[c] + Fy)) / (1.0 + 0.5 * dt * gam);
+            QPx[c] = qpx;
+            QPy[c] = qpy;
             up[c] = qpx * w;
             vpv[c] = qpy * w;
             /* face-mean velocities: interior mean; wall 0; open = the cell's own */
@@ -559,8 +586,10 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
     for (size_t c = 0; c < n; ++c) {
         double spp = sqrt(up[c] * up[c] + vpv[c] * vpv[c]);
         double gam = friction_rate(p, in->nM[c], spp, Hh[c]);
-        QLx[c] = (qx[c] + dt * Sx[c]) / (1.0 + dt * gam);
-        QLy[c] = (qy[c] + dt * Sy[c]) / (1.0 + dt * gam);
+        double Fx, Fy;  /* forcing at t_{n+1/2}: half-step depth, predictor momentum */
+        forcing(p, Hh[c], QPx[c], QPy[c], &Fx, &Fy);
+        QLx[c] = (qx[c] + dt * (Sx[c] + Fx)) / (1.0 + dt * gam);
+        QLy[c] = (qy[c] + dt * (Sy[c] + Fy)) / (1.0 + dt * gam);
         double w = orc_w(H[c], eps);
         uLx[c] = QLx[c] * w;
         uLy[c] = QLy[c] * w;
@@ -759,28 +788,40 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
     }
 
     /* O8 (K8): conservative update from the face fluxes, the inflow source */
-    /* at t_n + dt/2 (mass only) and the Exner update (Eq. 1) with the      */
-    /* cell's porosity.  A tiny negative depth left by rounding is set to   */
-    /* zero; a thin film's momentum is re-desingularised, q <- H w(H) q.    */
+    /* at t_n + dt/2 and the rainfall (mass only), and the Exner update     */
+    /* (Eq. 1) with the cell's porosity.  A tiny negative depth left by     */
+    /* rounding is set to zero.  Absorption (the infiltration part of sigma, */
+    /* reading: dH/dt = -beta H, implicit) divides depth and momentum by    */
+    /* 1 + beta dt, so the water it removes leaves with its velocity.  A    */
+    /* thin film's momentum is re-desingularised, q <- H w(H) q.            */
     double Qmid = orc_hydrograph(in, t + 0.5 * dt);
     double *src = calloc(n, sizeof(double));
     for (int k = 0; k < in->n_inflow; ++k)
         src[in->inflow_idx[k]] += Qmid * in->inflow_w[k] / (dx * dx);
     int nonfinite = 0;
-#pragma omp parallel for schedule(static) reduction(| : nonfinite)
+    double absorbed = 0.0;
+#pragma omp parallel for schedule(static) reduction(| : nonfinite) reduction(+ : absorbed)
     for (int j = 0; j < ny; ++j) {
         for (int i = 0; i < nx; ++i) {
             size_t c = (size_t)j * nx + i;
             size_t fw = (size_t)j * (nx + 1) + i, fe = fw + 1;
             size_t gs = (size_t)j * nx + i, gn = gs + nx;
             double r = dt / dx;
-            double Hn = H[c] - r * ((FH[fe] - FH[fw]) + (GH[gn] - GH[gs])) + dt * src[c];
+            double Hn = H[c] - r * ((FH[fe] - FH[fw]) + (GH[gn] - GH[gs])) + dt * src[c] + dt * p->rain;
             double qxn = QLx[c] - r * ((Fqx[fe] - Fqx[fw]) + (Gqx[gn] - Gqx[gs]));
             double qyn = QLy[c] - r * ((Fqy[fe] - Fqy[fw]) + (Gqy[gn] - Gqy[gs]));
             double om = 1.0 - in->psi[c];
             double bn = b[c] - dt / (om * dx) * ((FJ[fe] - FJ[fw]) + (GJ[gn] - GJ[gs]));
             if (in->qb) bn += dt * in->qb[c] / om;
             if (Hn < 0.0) Hn = 0.0;
+            if (in->beta && in->beta[c] > 0.0) {
+                double a = 1.0 + in->beta[c] * dt;
+                double Ha = Hn / a;
+                absorbed += Hn - Ha;
+                Hn = Ha;
+                qxn /= a;
+                qyn /= a;
+            }
             if (Hn < eps) {
                 double s = Hn * orc_w(Hn, eps);
                 qxn *= s;
@@ -811,8 +852,10 @@ int orc_step(const orc_params *p, const orc_inputs *in, double *H, double *qx, d
     if (in->qb)
         for (size_t c = 0; c < n; ++c) qbs += in->qb[c];
     info->in_s = dt * qbs * dx * dx;
+    info->rain_in = dt * p->rain * (double)n * dx * dx;
+    info->absorbed = absorbed * dx * dx;
 
-    free(u); free(v); free(Sx); free(Sy); free(up); free(vpv); free(Hh);
+    free(u); free(v); free(Sx); free(Sy); free(up); free(vpv); free(Hh); free(QPx); free(QPy);
     free(QLx); free(QLy); free(uLx); free(uLy); free(utx); free(uty); free(zeta);
     free(J0x); free(J0y); free(theta);
     free(FH); free(Fqx); free(Fqy); free(FJ); free(GH); free(Gqx); free(Gqy); free(GJ);

@@ -28,6 +28,7 @@ typedef struct {
     int32_t bc[4];
     double g, cfl, eps, h_sed, dt_max, dt_min, s_rel, C_J, C_Sh, A_G, m_exp;
     int32_t sed_law, limiter, hll_speeds;
+    double rain, coriolis, wind_x, wind_y, wind_coef;
 } f32_params_d;
 typedef struct {
     const double *nM, *d50, *psi, *qb;
@@ -35,11 +36,12 @@ typedef struct {
     const int32_t *inflow_idx;
     const double *inflow_w;
     double Q_base, Q_peak, t_peak, t_sigma;
+    const double *beta;
 } f32_inputs_d;
 typedef struct {
     double dt, vp, vs, D;
     int32_t binding;
-    double out_w, in_w, out_s, in_s;
+    double out_w, in_w, out_s, in_s, rain_in, absorbed;
 } f32_info_d;
 
 /* every name the oracle exports gets an _f32 suffix inside this unit */
@@ -84,6 +86,8 @@ int orcf_step(const f32_params_d *pd, const f32_inputs_d *id, double *H, double 
     p.C_J = (float)pd->C_J; p.C_Sh = (float)pd->C_Sh; p.A_G = (float)pd->A_G;
     p.m_exp = (float)pd->m_exp; p.sed_law = pd->sed_law; p.limiter = pd->limiter;
     p.hll_speeds = pd->hll_speeds;
+    p.rain = (float)pd->rain; p.coriolis = (float)pd->coriolis; p.wind_x = (float)pd->wind_x;
+    p.wind_y = (float)pd->wind_y; p.wind_coef = (float)pd->wind_coef;
     const size_t n = (size_t)p.nx * p.ny;
     orc_inputs in;
     in.nM = to_f32(id->nM, n); in.d50 = to_f32(id->d50, n); in.psi = to_f32(id->psi, n);
@@ -92,6 +96,7 @@ int orcf_step(const f32_params_d *pd, const f32_inputs_d *id, double *H, double 
     in.inflow_w = to_f32(id->inflow_w, (size_t)(id->n_inflow > 0 ? id->n_inflow : 0));
     in.Q_base = (float)id->Q_base; in.Q_peak = (float)id->Q_peak;
     in.t_peak = (float)id->t_peak; in.t_sigma = (float)id->t_sigma;
+    in.beta = to_f32(id->beta, n);
     float *Hf = to_f32(H, n), *uf = to_f32(qx, n), *vf = to_f32(qy, n), *bf = to_f32(b, n);
     orc_step_info si;
     int rc = orc_step_f32(&p, &in, Hf, uf, vf, bf, (float)t, (float)dt_fixed, &si);
@@ -101,8 +106,9 @@ int orcf_step(const f32_params_d *pd, const f32_inputs_d *id, double *H, double 
     info->dt = si.dt; info->vp = si.vp; info->vs = si.vs; info->D = si.D;
     info->binding = si.binding; info->out_w = si.out_w; info->in_w = si.in_w;
     info->out_s = si.out_s; info->in_s = si.in_s;
+    info->rain_in = si.rain_in; info->absorbed = si.absorbed;
     free(Hf); free(uf); free(vf); free(bf);
     free((void *)in.nM); free((void *)in.d50); free((void *)in.psi); free((void *)in.qb);
-    free((void *)in.inflow_w);
+    free((void *)in.inflow_w); free((void *)in.beta);
     return rc;
 }

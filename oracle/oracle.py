@@ -76,7 +76,9 @@ class _Params(C.Structure):
                 ("eps", C.c_double), ("h_sed", C.c_double), ("dt_max", C.c_double),
                 ("dt_min", C.c_double), ("s_rel", C.c_double), ("C_J", C.c_double),
                 ("C_Sh", C.c_double), ("A_G", C.c_double), ("m_exp", C.c_double),
-                ("sed_law", C.c_int32), ("limiter", C.c_int32), ("hll_speeds", C.c_int32)]
+                ("sed_law", C.c_int32), ("limiter", C.c_int32), ("hll_speeds", C.c_int32),
+                ("rain", C.c_double), ("coriolis", C.c_double), ("wind_x", C.c_double),
+                ("wind_y", C.c_double), ("wind_coef", C.c_double)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -87,13 +89,14 @@ class _Inputs(C.Structure):
     _fields_ = [("nM", _dp), ("d50", _dp), ("psi", _dp), ("qb", _dp),
                 ("n_inflow", C.c_int32), ("inflow_idx", _ip), ("inflow_w", _dp),
                 ("Q_base", C.c_double), ("Q_peak", C.c_double), ("t_peak", C.c_double),
-                ("t_sigma", C.c_double)]
+                ("t_sigma", C.c_double), ("beta", _dp)]
 
 
 class _Info(C.Structure):
     _fields_ = [("dt", C.c_double), ("vp", C.c_double), ("vs", C.c_double), ("D", C.c_double),
                 ("binding", C.c_int32), ("out_w", C.c_double), ("in_w", C.c_double),
-                ("out_s", C.c_double), ("in_s", C.c_double)]
+                ("out_s", C.c_double), ("in_s", C.c_double), ("rain_in", C.c_double),
+                ("absorbed", C.c_double)]
 
 
 _lib = None
@@ -168,6 +171,11 @@ class Params:
     sed_law: int = SED_EQ4
     limiter: int = LIM_MINMOD
     hll_speeds: int = SPEEDS_DAVIS
+    rain: float = 0.0        # m/s
+    coriolis: float = 0.0    # 1/s
+    wind_x: float = 0.0      # m/s
+    wind_y: float = 0.0
+    wind_coef: float = 0.0   # (rho_air / rho_water) C_D
 
     def _c(self) -> _Params:
         p = _Params()
@@ -175,7 +183,7 @@ class Params:
         for k in range(4):
             p.bc[k] = int(self.bc[k])
         for name in ("g", "cfl", "eps", "h_sed", "dt_max", "dt_min", "s_rel", "C_J", "C_Sh",
-                     "A_G", "m_exp"):
+                     "A_G", "m_exp", "rain", "coriolis", "wind_x", "wind_y", "wind_coef"):
             setattr(p, name, float(getattr(self, name)))
         p.sed_law = int(self.sed_law)
         p.limiter = int(self.limiter)
@@ -196,6 +204,7 @@ class Inputs:
     Q_peak: float = 0.0
     t_peak: float = 0.0
     t_sigma: float = 1.0
+    beta: object = None            # absorption coefficient per cell (1/s), scalar, or None
     _keep: list = field(default_factory=list, repr=False)
 
     def _c(self, n: int) -> _Inputs:
@@ -207,6 +216,7 @@ class Inputs:
         ci = _Inputs()
         ci.nM, ci.d50, ci.psi = full(self.nM), full(self.d50), full(self.psi)
         ci.qb = full(self.qb) if self.qb is not None else _dp()
+        ci.beta = full(self.beta) if self.beta is not None else _dp()
         if self.inflow_idx is not None and len(self.inflow_idx) > 0:
             idx = np.ascontiguousarray(self.inflow_idx, dtype=np.int32).reshape(-1)
             w = np.ascontiguousarray(self.inflow_w, dtype=np.float64).reshape(-1)
@@ -238,12 +248,14 @@ class State:
         self.t = float(t)
         self.step = 0
         self.out_w = self.in_w = self.out_s = self.in_s = 0.0
+        self.rain_in = self.absorbed = 0.0
         self.last = None
 
     def copy(self) -> "State":
         s = State(self.H, self.qx, self.qy, self.b, self.t)
         s.step = self.step
         s.out_w, s.in_w, s.out_s, s.in_s = self.out_w, self.in_w, self.out_s, self.in_s
+        s.rain_in, s.absorbed = self.rain_in, self.absorbed
         return s
 
 
@@ -267,6 +279,8 @@ def step(p: Params, inp: Inputs, s: State, dt_fixed: float = 0.0) -> dict:
     s.in_w += info.in_w
     s.out_s += info.out_s
     s.in_s += info.in_s
+    s.rain_in += info.rain_in
+    s.absorbed += info.absorbed
     rec = {k: getattr(info, k) for k, _ in _Info._fields_}
     s.last = rec
     return rec

@@ -17,7 +17,7 @@ def oracle_case(O, w, **over):
     p = O.Params(**kw)
     inp = O.Inputs(nM=w.nM, d50=w.d50, psi=w.psi, qb=w.qb, inflow_idx=w.inflow_idx,
                    inflow_w=w.inflow_w, Q_base=w.Q_base, Q_peak=w.Q_peak, t_peak=w.t_peak,
-                   t_sigma=w.t_sigma)
+                   t_sigma=w.t_sigma, beta=over.get("beta"))
     s = O.State(w.H, w.qx, w.qy, w.b)
     return p, inp, s
 

@@ -3,7 +3,7 @@
 Each mutant below plants one typical error (a dropped term, a flipped sign, a
 wrong neighbour, an x/y mix-up, a wrong donor) into a temporary copy of the
 oracle's C source, compiles it on the CPU, and runs the pin suite
-(test_oracle_pins.py, test_oracle_variants.py) against it in a subprocess.  Every mutant must make at
+(test_oracle_pins.py, test_oracle_variants.py, test_oracle_forcing.py) against it in a subprocess.  Every mutant must make at
 least one pin fail; the unmodified source must pass.
 """
 import os
@@ -29,7 +29,7 @@ MUTANTS = {
                              "(g / (2.0 * dx)) * (HsLe * HsLe - HsRw * HsRw)"),
     "force_y_wrong_neighbour": ("size_t n = c + nx;", "size_t n = c + 1;"),
     "manning_exponent": ("(Hf * cbrt(Hf))", "(Hf * sqrt(Hf))"),
-    "predictor_full_step": ("(qx[c] + 0.5 * dt * Sx[c])", "(qx[c] + dt * Sx[c])"),
+    "predictor_full_step": ("(qx[c] + 0.5 * dt * (Sx[c] + Fx))", "(qx[c] + dt * (Sx[c] + Fx))"),
     "half_depth_multiplies": ("Hh[c] = H[c] / (Jx * Jy);", "Hh[c] = H[c] * (Jx * Jy);"),
     "transport_velocity_drops_vn": ("utx[c] = 0.5 * (u[c] + uLx[c]);", "utx[c] = uLx[c];"),
     "y_face_transposed_operand": ("double tL = FACEV(uty, sy[2], cL, +1), tR = FACEV(uty, sy[2], cR, -1);",
@@ -48,11 +48,19 @@ MUTANTS = {
     "trr_speed_uses_left_head_twice": ("*SR = fmax(unR + cR, us + cs);", "*SR = fmax(unL + cL, us + cs);"),
     "trr_wall_ghost_not_mirrored": ("orc_hll_v(p->hll_speeds, p->g, Hs, n, t, u, Hs, -n, t, -u, f);",
                                     "orc_hll_v(p->hll_speeds, p->g, Hs, n, t, u, Hs, n, t, u, f);"),
+    "coriolis_sign": ("*Fy = -p->coriolis * qxc", "*Fy = p->coriolis * qxc"),
+    "coriolis_corrector_uses_qn": ("forcing(p, Hh[c], QPx[c], QPy[c], &Fx, &Fy);",
+                                   "forcing(p, Hh[c], qx[c], qy[c], &Fx, &Fy);"),
+    "wind_drops_depth_ramp": ("double chi = fmin(1.0, Hd / p->h_sed);", "double chi = 1.0;"),
+    "wind_drops_speed_factor": ("p->wind_coef * Wm * p->wind_x * chi", "p->wind_coef * p->wind_x * chi"),
+    "rain_dropped": (" + dt * src[c] + dt * p->rain;", " + dt * src[c];"),
+    "absorption_explicit": ("double Ha = Hn / a;", "double Ha = Hn * (2.0 - a);"),
+    "absorption_keeps_momentum": ("                qxn /= a;\n                qyn /= a;\n", ""),
     "open_boundary_blocks_mass": ("fl[0] = tL * HsL;\n                    fl[1] = tL * HsL * nL;\n                    fl[2] = tL * HsL * sL;\n                    fj = fmax(J0x[c], 0.0);",
                                   "fl[1] = tL * HsL * nL;\n                    fl[2] = tL * HsL * sL;\n                    fj = fmax(J0x[c], 0.0);"),
     "theta_wrong_donor": ("if (FH[f] > 0.0 && k - 1 >= 0) th = theta[(size_t)j * nx + k - 1];",
                           "if (FH[f] > 0.0 && k < nx) th = theta[(size_t)j * nx + k];"),
-    "inflow_source_dropped": ("+ dt * src[c];", ";"),
+    "inflow_source_dropped": ("+ dt * src[c] + dt * p->rain;", "+ dt * p->rain;"),
     "exner_drops_porosity": ("double bn = b[c] - dt / (om * dx) *", "double bn = b[c] - dt / dx *"),
     "bed_slope_diffusion_sign": ("fj = fmax(J0x[cL], 0.0) + fmin(J0x[cR], 0.0) - CJ * mag",
                                  "fj = fmax(J0x[cL], 0.0) + fmin(J0x[cR], 0.0) + CJ * mag"),
@@ -72,7 +80,8 @@ def _run_pins(lib):
     env = dict(os.environ, CSPH_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_variants.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_variants.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_forcing.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return r.returncode, r.stdout[-2000:]
 
