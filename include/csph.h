@@ -122,8 +122,10 @@ typedef struct {
     int32_t binding_term;      /* Eq. 7 term that set last_dt: 0 h/(2vp), 1 h/vs, 2 h^2/(2D), 3 dt_max, 4 fixed */
     int32_t error;             /* sticky device error (SW_ERR_*), 0 if none */
     int64_t graph_builds;      /* step graphs captured so far: a new state, bed or time
-                                  keeps them; soil, sources, tile shape or a new fixed dt
-                                  rebuild them at the next advance */
+                                  keeps them; soil, sources, forcing, tile shape or a new
+                                  fixed dt rebuild them at the next advance */
+    double water_rain_in;      /* accumulated rainfall volume */
+    double water_absorbed;     /* accumulated volume absorbed (infiltrated) */
 } sw_sums;
 
 /* Fill *p with the defaults listed in sw_params. */
@@ -163,6 +165,23 @@ int sw_set_inflow(sw_ctx *ctx, const int32_t *cell_idx, const float *weight, int
 /* Bed sources q_b^+ (deposition) and q_b^- (erosion drain) of Eq. 1, m/s,
  * per cell; either may be NULL (zero). */
 int sw_set_sed_sources(sw_ctx *ctx, const float *qb_plus, const float *qb_minus, int ptr_kind);
+
+/* Forcing named by Eq. 6 without a formula (the water sources sigma and the
+ * force f; the Main block's absorption map beta(x, y), Section 3):
+ *  - rain: rainfall rate (m/s) on every cell, adding depth without momentum
+ *    (with rain > 0 no tile is skipped);
+ *  - beta (per-cell array, or NULL for beta_scalar): absorption coefficient
+ *    (1/s); dH/dt = -beta H taken implicitly each step (depth and momentum
+ *    divided by 1 + beta dt, so the absorbed water leaves with its velocity);
+ *  - coriolis: f_c = 2 Omega sin(latitude) (1/s), force f_c (hv, -hu);
+ *  - wind_x, wind_y (m/s) and wind_coef C_w = (rho_air / rho_water) C_D:
+ *    stress C_w |W| W on water, scaled by min(1, h / h_sed) on thinner layers.
+ * Forces enter the predictor at t_n and the corrector at t_{n+1/2}.  All zero
+ * (the default) is the plain model.  sw_sums reports water_rain_in and
+ * water_absorbed.  Negative or non-finite rain, beta or wind_coef, or
+ * non-finite Coriolis and wind values are SW_ERR_ARG. */
+int sw_set_forcing(sw_ctx *ctx, double rain, const float *beta, float beta_scalar, double coriolis,
+                   double wind_x, double wind_y, double wind_coef, int ptr_kind);
 
 /* Model time and step counter reported by sw_get_sums (does not touch fields). */
 int sw_set_time(sw_ctx *ctx, double t, int64_t step);

@@ -57,7 +57,8 @@ class sw_sums(C.Structure):
                 ("D", C.c_double), ("step", C.c_int64), ("wet_cells", C.c_int64),
                 ("active_tiles", C.c_int64), ("cells_lagrange", C.c_int64),
                 ("cells_euler", C.c_int64), ("binding_term", C.c_int32), ("error", C.c_int32),
-                ("graph_builds", C.c_int64)]
+                ("graph_builds", C.c_int64), ("water_rain_in", C.c_double),
+                ("water_absorbed", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -79,6 +80,8 @@ SIGNATURES = [
                                 C.c_double, C.c_double]),
     ("sw_set_sed_sources", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_int]),
     ("sw_set_time", C.c_int, [_ctxp, C.c_double, C.c_int64]),
+    ("sw_set_forcing", C.c_int, [_ctxp, C.c_double, C.c_void_p, C.c_float, C.c_double, C.c_double,
+                                 C.c_double, C.c_double, C.c_int]),
     ("sw_advance", C.c_int, [_ctxp, C.c_int32]),
     ("sw_advance_fixed_dt", C.c_int, [_ctxp, C.c_int32, C.c_double]),
     ("sw_advance_profiled", C.c_int, [_ctxp, C.c_int32, C.POINTER(C.c_double)]),
@@ -261,6 +264,18 @@ class Solver:
         (pp, k1, a), (pm, k2, b) = _ptr(qb_plus, self.n), _ptr(qb_minus, self.n)
         kind = k1 if qb_plus is not None else k2
         _check(self.ctx, lib.sw_set_sed_sources(self.ctx, pp, pm, kind))
+
+    def set_forcing(self, rain=0.0, beta=0.0, coriolis=0.0, wind_x=0.0, wind_y=0.0, wind_coef=0.0):
+        """Rainfall (m/s), absorption coefficient beta (1/s, scalar or per-cell
+        array), Coriolis parameter (1/s), wind (m/s) and its stress coefficient."""
+        if np.isscalar(beta):
+            pb, kind, keep = None, SW_PTR_HOST, None
+            bs = float(beta)
+        else:
+            pb, kind, keep = _ptr(beta, self.n)
+            bs = 0.0
+        _check(self.ctx, lib.sw_set_forcing(self.ctx, float(rain), pb, bs, float(coriolis),
+                                            float(wind_x), float(wind_y), float(wind_coef), kind))
 
     def set_time(self, t, step=0):
         _check(self.ctx, lib.sw_set_time(self.ctx, float(t), int(step)))

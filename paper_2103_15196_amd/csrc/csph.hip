@@ -39,6 +39,7 @@ struct Ctrl {
     double dt[2];                // step size of step k
     double qmid[2];              // inflow discharge at t_k + dt_k/2
     double in_w, in_s;           // accumulated source volumes
+    double in_rain;              // accumulated rainfall volume
     double vp, vs, D;            // Eq. 7 maxima at the start of the last step
     double last_dt;
     int err, err_k, binding, kdev;  // kdev: steps taken since the state was set
@@ -52,6 +53,7 @@ struct StepArgs {
     int has_inflow;
     double q_base, q_peak, t_peak, t_sigma;
     double qb_total;             // sum over cells of (q_b^+ - q_b^-) dx^2
+    double rain_area;            // rainfall rate x grid area, m^3/s
 };
 
 __device__ __forceinline__ unsigned fbits_nonneg(float x) { return __float_as_uint(x + 0.0f); }
@@ -208,6 +210,7 @@ __global__ void k_dt(Ctrl *ctrl, int k, StepArgs A)
         ctrl->in_w += dt * q;
     }
     ctrl->in_s += dt * A.qb_total;
+    ctrl->in_rain += dt * A.rain_area;
     ctrl->qmid[k & 1] = q;
     ctrl->dt[k & 1] = dt;
     ctrl->t[(k + 1) & 1] = tn + dt;
@@ -253,47 +256,6 @@ __device__ float half_depth(const KPar &P, const StateView &S, int i, int j, flo
     return ndiv(S.H[c], Jx * Jy);
 }
 
-__global__ void __launch_bounds__(BX * BY) k_lagrange(KPar P, const Ctrl *__restrict__ ctrl, int k,
-                                                      StateView S, float *__restrict__ QLx,
-                                                      float *__restrict__ QLy)
-{
-    if (ctrl->err) return;
-    int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
-    if (i >= P.nx || j >= P.ny) return;
-    float dt = (float)ctrl->dt[k & 1];
-    int c = j * P.pitch + i;
-    bool hasW = i > 0, hasE = i + 1 < P.nx, hasS = j > 0, hasN = j + 1 < P.ny;
-    int cW = hasW ? c - 1 : c, cE = hasE ? c + 1 : c;
-    int cS = hasS ? c - P.pitch : c, cN = hasN ? c + P.pitch : c;
-    float Hc = S.H[c], bc = S.b[c];
-    float bW = S.b[cW], bE = S.b[cE], bS = S.b[cS], bN = S.b[cN];
-    // K2: forces at t_n
-    float Snx = face_force(P, S.H[cW], bW, Hc, bc, S.H[cE], bE, hasW, hasE);
-    float Sny = face_force(P, S.H[cS], bS, Hc, bc, S.H[cN], bN, hasS, hasN);
-    float wc = wdes(Hc, P);
-    float qxc = S.qx[c], qyc = S.qy[c];
-    float uc = qxc * wc, vc = qyc * wc;
-    float nM = soil(P.nM, P.nM_s, c);
-    float gam = friction_rate(P, nM, nsqrt(sumsq(uc, vc)), Hc);
-    // K4: predictor momentum and half-step depths
-    float hdt = 0.5f * dt;
-    float qpx = ndiv(qxc + hdt * Snx, 1.0f + hdt * gam);
-    float qpy = ndiv(qyc + hdt * Sny, 1.0f + hdt * gam);
-    float upx = qpx * wc, upy = qpy * wc;
-    float hdt_dx = dt / (2.0f * P.dx);
-    float Hh = half_depth(P, S, i, j, hdt_dx);
-    float HhW = hasW ? half_depth(P, S, i - 1, j, hdt_dx) : Hh;
-    float HhE = hasE ? half_depth(P, S, i + 1, j, hdt_dx) : Hh;
-    float HhS = hasS ? half_depth(P, S, i, j - 1, hdt_dx) : Hh;
-    float HhN = hasN ? half_depth(P, S, i, j + 1, hdt_dx) : Hh;
-    // K5: forces at t_{n+1/2}
-    float Shx = face_force(P, HhW, bW, Hh, bc, HhE, bE, hasW, hasE);
-    float Shy = face_force(P, HhS, bS, Hh, bc, HhN, bN, hasS, hasN);
-    float gamh = friction_rate(P, nM, nsqrt(sumsq(upx, upy)), Hh);
-    // K6: corrector (Lagrangian momentum)
-    QLx[c] = ndiv(qxc + dt * Shx, 1.0f + dt * gamh);
-    QLy[c] = ndiv(qyc + dt * Shy, 1.0f + dt * gamh);
-}
 
 // ---------------------------------------------------------------------------
 // Euler stage, unfused: K7 raw face fluxes, then K8 limiter + update.
@@ -387,60 +349,6 @@ __device__ __forceinline__ float theta_of(const KPar &P, const StateView &S, con
     return out > 0.0f ? fminf(1.0f, S.H[j * P.pitch + i] * P.dx / (dt * out)) : 1.0f;
 }
 
-__global__ void __launch_bounds__(BX * BY) k_update(KPar P, Ctrl *__restrict__ ctrl, int k,
-                                                    StateView S, LagView L, FaceView F, OutView O,
-                                                    double *__restrict__ bnd)
-{
-    unsigned mv = 0, ms = 0, mD = 0, bad = 0;
-    bool live = !ctrl->err;
-    int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
-    if (live && i < P.nx && j < P.ny) {
-        double dtd = ctrl->dt[k & 1];
-        float dt = (float)dtd;
-        int c = j * P.pitch + i;
-        float th = theta_of(P, S, F, i, j, dt);
-        float thW = theta_of(P, S, F, i - 1, j, dt), thE = theta_of(P, S, F, i + 1, j, dt);
-        float thS = theta_of(P, S, F, i, j - 1, dt), thN = theta_of(P, S, F, i, j + 1, dt);
-        int fw = j * (P.nx + 1) + i, fe = fw + 1;
-        int gs = j * P.nx + i, gn = gs + P.nx;
-        // each face's water fluxes take the theta of the cell the mass leaves
-        float sw = F.xH[fw] > 0.0f ? thW : (F.xH[fw] < 0.0f ? th : 1.0f);
-        float se = F.xH[fe] > 0.0f ? th : (F.xH[fe] < 0.0f ? thE : 1.0f);
-        float ss = F.yH[gs] > 0.0f ? thS : (F.yH[gs] < 0.0f ? th : 1.0f);
-        float sn = F.yH[gn] > 0.0f ? th : (F.yH[gn] < 0.0f ? thN : 1.0f);
-        float FHw = F.xH[fw] * sw, FHe = F.xH[fe] * se, GHs = F.yH[gs] * ss, GHn = F.yH[gn] * sn;
-        float Fxw = F.xn[fw] * sw, Fxe = F.xn[fe] * se, Gxs = F.yt[gs] * ss, Gxn = F.yt[gn] * sn;
-        float Fyw = F.xt[fw] * sw, Fye = F.xt[fe] * se, Gys = F.yn[gs] * ss, Gyn = F.yn[gn] * sn;
-        float H = S.H[c], qx = S.qx[c], qy = S.qy[c], b = S.b[c];
-        float QLx = H > 0.0f ? L.QLx[c] : qx;
-        float QLy = H > 0.0f ? L.QLy[c] : qy;
-        float r = dt * P.inv_dx;
-        float src = P.srcw ? P.srcw[c] * (float)ctrl->qmid[k & 1] : 0.0f;
-        float Hn = H - r * ((FHe - FHw) + (GHn - GHs)) + dt * src;
-        float qxn = QLx - r * ((Fxe - Fxw) + (Gxn - Gxs));
-        float qyn = QLy - r * ((Fye - Fyw) + (Gyn - Gys));
-        float om = 1.0f - soil(P.psi, P.psi_s, c);
-        float rb = P.rb ? P.rb[c] : 0.0f;
-        float bn = exner(P, dt, b, om, (F.xJ[fe] - F.xJ[fw]) + (F.yJ[gn] - F.yJ[gs]),
-                         P.qb ? P.qb[c] : 0.0f, rb);
-        if (P.rb) P.rb[c] = rb;
-        if (Hn < 0.0f) Hn = 0.0f;
-        if (Hn < P.eps) {
-            float s = Hn * wdes(Hn, P);
-            qxn *= s;
-            qyn *= s;
-        }
-        O.H[c] = Hn; O.qx[c] = qxn; O.qy[c] = qyn; O.b[c] = bn;
-        // boundary balances (FP64, one accumulator per boundary face)
-        double wdx = dtd * (double)P.dx;
-        if (i == 0) { bnd[j] += wdx * (double)(-FHw); bnd[2 * (P.nx + P.ny) + j] += wdx * (double)(-F.xJ[fw]); }
-        if (i == P.nx - 1) { bnd[P.ny + j] += wdx * (double)FHe; bnd[2 * (P.nx + P.ny) + P.ny + j] += wdx * (double)F.xJ[fe]; }
-        if (j == 0) { bnd[2 * P.ny + i] += wdx * (double)(-GHs); bnd[2 * (P.nx + P.ny) + 2 * P.ny + i] += wdx * (double)(-F.yJ[gs]); }
-        if (j == P.ny - 1) { bnd[2 * P.ny + P.nx + i] += wdx * (double)GHn; bnd[2 * (P.nx + P.ny) + 2 * P.ny + P.nx + i] += wdx * (double)F.yJ[gn]; }
-        cell_maxima(P, Hn, qxn, qyn, bn, c, mv, ms, mD, bad);
-    }
-    block_maxima(mv, ms, mD, bad, ctrl->slot[(k + 1) & 1], blockIdx.x + blockIdx.y * gridDim.x);
-}
 
 
 // ---------------------------------------------------------------------------
@@ -601,6 +509,7 @@ __device__ void publish_dt(Ctrl *ctrl, int par, const StepArgs &A, uint4 m)
         ctrl->in_w += dt * q;
     }
     ctrl->in_s += dt * A.qb_total;
+    ctrl->in_rain += dt * A.rain_area;
     ctrl->qmid[par] = q;
     ctrl->dt[par] = dt;
     ctrl->t[par ^ 1] = tn + dt;
@@ -689,16 +598,29 @@ __device__ __forceinline__ void lagrange_cell(const KPar &P, float dt, const Nbr
     float uc = qxc * wc, vc = qyc * wc;
     float gam = friction_rate(P, nM, nsqrt(sumsq(uc, vc)), Hd.C);
     float hdt = 0.5f * dt;
-    float qpx = ndiv(qxc + hdt * Snx, 1.0f + hdt * gam);
-    float qpy = ndiv(qyc + hdt * Sny, 1.0f + hdt * gam);
+    float qpx, qpy;
+    if (P.force) {  // Coriolis and wind at t_n
+        const float chi = fminf(1.0f, Hd.C * P.inv_hsed);
+        qpx = ndiv(qxc + hdt * (Snx + (P.cor * qyc + chi * P.wsx)), 1.0f + hdt * gam);
+        qpy = ndiv(qyc + hdt * (Sny + (-P.cor * qxc + chi * P.wsy)), 1.0f + hdt * gam);
+    } else {
+        qpx = ndiv(qxc + hdt * Snx, 1.0f + hdt * gam);
+        qpy = ndiv(qyc + hdt * Sny, 1.0f + hdt * gam);
+    }
     float upx = qpx * wc, upy = qpy * wc;
     float HhW = hasW ? Hh.W : Hh.C, HhE = hasE ? Hh.E : Hh.C;
     float HhS = hasS ? Hh.S : Hh.C, HhN = hasN ? Hh.N : Hh.C;
     float Shx = face_force(P, HhW, bd.W, Hh.C, bd.C, HhE, bd.E, hasW, hasE);
     float Shy = face_force(P, HhS, bd.S, Hh.C, bd.C, HhN, bd.N, hasS, hasN);
     float gamh = friction_rate(P, nM, nsqrt(sumsq(upx, upy)), Hh.C);
-    QLx = ndiv(qxc + dt * Shx, 1.0f + dt * gamh);
-    QLy = ndiv(qyc + dt * Shy, 1.0f + dt * gamh);
+    if (P.force) {  // at t_{n+1/2}: half-step depth, predictor momentum
+        const float chi = fminf(1.0f, Hh.C * P.inv_hsed);
+        QLx = ndiv(qxc + dt * (Shx + (P.cor * qpy + chi * P.wsx)), 1.0f + dt * gamh);
+        QLy = ndiv(qyc + dt * (Shy + (-P.cor * qpx + chi * P.wsy)), 1.0f + dt * gamh);
+    } else {
+        QLx = ndiv(qxc + dt * Shx, 1.0f + dt * gamh);
+        QLy = ndiv(qyc + dt * Shy, 1.0f + dt * gamh);
+    }
 }
 
 // Draining limiter of a cell of depth h from its four raw mass fluxes.
@@ -719,14 +641,23 @@ struct CellFaces {
 struct CellNew {
     float H, qx, qy, b;
     float FHw, FHe, GHs, GHn;  // limited mass fluxes (boundary balances)
+    float ab;                  // depth absorbed this step
 };
 
 // K8 of one cell: each face's water fluxes take the limiter of the cell the
 // mass leaves; conservative update of H and momentum from Q^L, Exner update
 // of b (Eq. 1), negative depth clamped, momentum re-desingularised below eps.
+// Rainfall adds depth only; absorption (dH/dt = -beta H, implicit) divides
+// depth and momentum by 1 + beta dt, so the absorbed water leaves with its
+// velocity.
+// The rainfall is added compensated: rh carries the part of the earlier
+// additions the float32 depth could not hold (as the bed's residual does for
+// the Exner update), so a rain increment far below an ulp of the depth is
+// not rounded away step after step.
 __device__ __forceinline__ CellNew cell_update(const KPar &P, float dt, const CellFaces &F, float h,
                                                float qx, float qy, float b, float QLx, float QLy,
-                                               float src, float psi, float qb, float &rb)
+                                               float src, float psi, float qb, float beta, float &rb,
+                                               float &rh)
 {
     float sw = F.xHw > 0.0f ? F.thW : (F.xHw < 0.0f ? F.th : 1.0f);
     float se = F.xHe > 0.0f ? F.th : (F.xHe < 0.0f ? F.thE : 1.0f);
@@ -744,7 +675,24 @@ __device__ __forceinline__ CellNew cell_update(const KPar &P, float dt, const Ce
     float qyn = QLyc - r * ((Fye - Fyw) + (Gyn - Gys));
     float om = 1.0f - psi;
     float bn = exner(P, dt, b, om, (F.Je - F.Jw) + (F.Jn - F.Js), qb, rb);
+    if (P.rain > 0.0f) {
+        const float d = dt * P.rain + rh;
+        const float hn = Hn + d;
+        const float dv = hn - Hn;
+        rh = (Hn - (hn - dv)) + (d - dv);
+        Hn = hn;
+    }
     if (Hn < 0.0f) Hn = 0.0f;
+    o.ab = 0.0f;
+    if (beta > 0.0f) {
+        const float a = 1.0f + beta * dt;
+        const float Ha = ndiv(Hn, a);
+        o.ab = Hn - Ha;
+        Hn = Ha;
+        qxn = ndiv(qxn, a);
+        qyn = ndiv(qyn, a);
+        rh = ndiv(rh, a);
+    }
     if (Hn < P.eps) {
         float sc = Hn * wdes(Hn, P);
         qxn *= sc;
@@ -764,6 +712,73 @@ __device__ __forceinline__ void boundary_balances(const KPar &P, double *bnd, do
     if (i == nx - 1) { bnd[ny + j] += wdx * (double)o.FHe; bnd[nb + ny + j] += wdx * (double)F.Je; }
     if (j == 0) { bnd[2 * ny + i] += wdx * (double)(-o.GHs); bnd[nb + 2 * ny + i] += wdx * (double)(-F.Js); }
     if (j == ny - 1) { bnd[2 * ny + nx + i] += wdx * (double)o.GHn; bnd[nb + 2 * ny + nx + i] += wdx * (double)F.Jn; }
+}
+
+// Unfused sequence: K2..K6 per cell, then (after the face kernel) K8 per
+// cell, through the same per-cell functions as the tiled kernels.
+__global__ void __launch_bounds__(BX * BY) k_lagrange(KPar P, const Ctrl *__restrict__ ctrl, int k,
+                                                      StateView S, float *__restrict__ QLx,
+                                                      float *__restrict__ QLy)
+{
+    if (ctrl->err) return;
+    int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (i >= P.nx || j >= P.ny) return;
+    float dt = (float)ctrl->dt[k & 1];
+    int c = j * P.pitch + i;
+    bool hasW = i > 0, hasE = i + 1 < P.nx, hasS = j > 0, hasN = j + 1 < P.ny;
+    int cW = hasW ? c - 1 : c, cE = hasE ? c + 1 : c;
+    int cS = hasS ? c - P.pitch : c, cN = hasN ? c + P.pitch : c;
+    float hdt_dx = dt / (2.0f * P.dx);
+    float Hh = half_depth(P, S, i, j, hdt_dx);
+    NbrDepths Hd{S.H[c], S.H[cW], S.H[cE], S.H[cS], S.H[cN]};
+    NbrDepths bd{S.b[c], S.b[cW], S.b[cE], S.b[cS], S.b[cN]};
+    NbrDepths Hhd{Hh, hasW ? half_depth(P, S, i - 1, j, hdt_dx) : Hh,
+                  hasE ? half_depth(P, S, i + 1, j, hdt_dx) : Hh,
+                  hasS ? half_depth(P, S, i, j - 1, hdt_dx) : Hh,
+                  hasN ? half_depth(P, S, i, j + 1, hdt_dx) : Hh};
+    float qlx, qly;
+    lagrange_cell(P, dt, Hd, bd, Hhd, hasW, hasE, hasS, hasN, S.qx[c], S.qy[c],
+                  soil(P.nM, P.nM_s, c), qlx, qly);
+    QLx[c] = qlx;
+    QLy[c] = qly;
+}
+
+__global__ void __launch_bounds__(BX * BY) k_update(KPar P, Ctrl *__restrict__ ctrl, int k,
+                                                    StateView S, LagView L, FaceView F, OutView O,
+                                                    double *__restrict__ bnd)
+{
+    unsigned mv = 0, ms = 0, mD = 0, bad = 0;
+    bool live = !ctrl->err;
+    int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    if (live && i < P.nx && j < P.ny) {
+        double dtd = ctrl->dt[k & 1];
+        float dt = (float)dtd;
+        int c = j * P.pitch + i;
+        int fw = j * (P.nx + 1) + i, fe = fw + 1;
+        int gs = j * P.nx + i, gn = gs + P.nx;
+        CellFaces Fc;
+        Fc.th = theta_of(P, S, F, i, j, dt);
+        Fc.thW = theta_of(P, S, F, i - 1, j, dt); Fc.thE = theta_of(P, S, F, i + 1, j, dt);
+        Fc.thS = theta_of(P, S, F, i, j - 1, dt); Fc.thN = theta_of(P, S, F, i, j + 1, dt);
+        Fc.xHw = F.xH[fw]; Fc.xnw = F.xn[fw]; Fc.xtw = F.xt[fw];
+        Fc.xHe = F.xH[fe]; Fc.xne = F.xn[fe]; Fc.xte = F.xt[fe];
+        Fc.yHs = F.yH[gs]; Fc.yns = F.yn[gs]; Fc.yts = F.yt[gs];
+        Fc.yHn = F.yH[gn]; Fc.ynn = F.yn[gn]; Fc.ytn = F.yt[gn];
+        Fc.Jw = F.xJ[fw]; Fc.Je = F.xJ[fe]; Fc.Js = F.yJ[gs]; Fc.Jn = F.yJ[gn];
+        float src = P.srcw ? P.srcw[c] * (float)ctrl->qmid[k & 1] : 0.0f;
+        float rb = P.rb ? P.rb[c] : 0.0f;
+        float rh = P.rh ? P.rh[c] : 0.0f;
+        CellNew o = cell_update(P, dt, Fc, S.H[c], S.qx[c], S.qy[c], S.b[c], L.QLx[c], L.QLy[c], src,
+                                soil(P.psi, P.psi_s, c), P.qb ? P.qb[c] : 0.0f,
+                                soil(P.beta, P.beta_s, c), rb, rh);
+        if (P.rb) P.rb[c] = rb;
+        if (P.rh) P.rh[c] = rh;
+        if (P.ab) P.ab[c] += (double)o.ab;
+        O.H[c] = o.H; O.qx[c] = o.qx; O.qy[c] = o.qy; O.b[c] = o.b;
+        boundary_balances(P, bnd, dtd * (double)P.dx, i, j, o, Fc);
+        cell_maxima(P, o.H, o.qx, o.qy, o.b, c, mv, ms, mD, bad);
+    }
+    block_maxima(mv, ms, mD, bad, ctrl->slot[(k + 1) & 1], blockIdx.x + blockIdx.y * gridDim.x);
 }
 
 // Lagrangian stage on a tile (K2, K4, K5, K6) with the Eq. 7 step (K3).
@@ -981,10 +996,14 @@ __device__ __forceinline__ void euler_tile(const Inst &I, int par, int bx, int b
                         rjx[cy + 1][cx], rjy[cy + 1][cx], rb[cy + 1][cx]);
         float src = P.srcw ? P.srcw[c] * (float)ctrl->qmid[par] : 0.0f;
         float rbc = P.rb ? P.rb[c] : 0.0f;
+        float rhc = P.rh ? P.rh[c] : 0.0f;
         CellNew o = cell_update(P, dt, F, SH[c], Sqx[c], Sqy[c], Sb[c], QLx[c], QLy[c], src,
-                                soil(P.psi, P.psi_s, c), P.qb ? P.qb[c] : 0.0f, rbc);
+                                soil(P.psi, P.psi_s, c), P.qb ? P.qb[c] : 0.0f,
+                                soil(P.beta, P.beta_s, c), rbc, rhc);
         OH[c] = o.H; Oqx[c] = o.qx; Oqy[c] = o.qy; Ob[c] = o.b;
         if (P.rb) P.rb[c] = rbc;
+        if (P.rh) P.rh[c] = rhc;
+        if (P.ab) P.ab[c] += (double)o.ab;
         boundary_balances(P, bnd, dtd * (double)P.dx, i, j, o, F);
         cell_maxima(P, o.H, o.qx, o.qy, o.b, c, mv, ms, mD, bad);
         if (o.H > 0.0f) s_flag = 1;
@@ -1359,10 +1378,16 @@ __device__ __forceinline__ void euler_strip(const Inst &I, int par, int bx, int 
                 F.Jw = xs3; F.Js = ys3; F.Jn = ys2;
                 const float src = P.srcw ? usrc * qmid : 0.0f;
                 float rbc = P.rb ? at(P.rb, uo) : 0.0f;
+                float rhc = P.rh ? at(P.rh, uo) : 0.0f;
+                const float ubeta = soil_at(P.beta, P.beta_s, uo);
                 const CellNew o = cell_update(P, dt, F, uh, uqx, uqy, ub, uLx, uLy, src, upsi, uqb,
-                                              rbc);
+                                              ubeta, rbc, rhc);
                 put(OH, uo, o.H); put(Oqx, uo, o.qx); put(Oqy, uo, o.qy); put(Ob, uo, o.b);
                 if (P.rb) put(P.rb, uo, rbc);
+                if (P.rh) put(P.rh, uo, rhc);
+                if (P.ab)  // FP64 plane: twice the float plane's byte offset
+                    *reinterpret_cast<double *>(reinterpret_cast<char *>(P.ab) + 2 * (size_t)uo) +=
+                        (double)o.ab;
                 boundary_balances(P, I.bnd, wdx, i, ju, o, F);
                 float njx, njy, njm;
                 cell_maxima_j(P, o.H, o.qx, o.qy, o.b, unM, ud50, upsi, mv, ms, mD, bad, njx, njy,
@@ -1855,49 +1880,58 @@ __global__ void __launch_bounds__(SUM_THREADS) k_sums1(KPar P, const float *__re
                                                        const float *__restrict__ b,
                                                        double *__restrict__ part, int rows_per_block)
 {
-    __shared__ double sh[3][SUM_THREADS / 64];
-    double sw = 0.0, ss = 0.0, wet = 0.0;
+    __shared__ double sh[4][SUM_THREADS / 64];
+    double sw = 0.0, ss = 0.0, wet = 0.0, ab = 0.0;
     int j0 = blockIdx.x * rows_per_block, j1 = min(P.ny, j0 + rows_per_block);
     for (int j = j0; j < j1; ++j)
         for (int i = threadIdx.x; i < P.nx; i += SUM_THREADS) {
             int c = j * P.pitch + i;
             float h = H[c];
-            sw += (double)h;
+            // the accumulated depth: the stored float plus its rainfall residual
+            sw += (double)h + (P.rh ? (double)P.rh[c] : 0.0);
             // the accumulated bed: the stored float plus its residual
             const double bc = (double)b[c] + (P.rb ? (double)P.rb[c] : 0.0);
             ss += (1.0 - (double)soil(P.psi, P.psi_s, c)) * bc;
             wet += h > 0.0f ? 1.0 : 0.0;
+            if (P.ab) ab += P.ab[c];
         }
-    sw = wave_sum(sw); ss = wave_sum(ss); wet = wave_sum(wet);
+    sw = wave_sum(sw); ss = wave_sum(ss); wet = wave_sum(wet); ab = wave_sum(ab);
     int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { sh[0][w] = sw; sh[1][w] = ss; sh[2][w] = wet; }
+    if ((threadIdx.x & 63) == 0) { sh[0][w] = sw; sh[1][w] = ss; sh[2][w] = wet; sh[3][w] = ab; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 1; k < SUM_THREADS / 64; ++k) { sw += sh[0][k]; ss += sh[1][k]; wet += sh[2][k]; }
-        part[3 * blockIdx.x + 0] = sw;
-        part[3 * blockIdx.x + 1] = ss;
-        part[3 * blockIdx.x + 2] = wet;
+        for (int k = 1; k < SUM_THREADS / 64; ++k) {
+            sw += sh[0][k]; ss += sh[1][k]; wet += sh[2][k]; ab += sh[3][k];
+        }
+        part[4 * blockIdx.x + 0] = sw;
+        part[4 * blockIdx.x + 1] = ss;
+        part[4 * blockIdx.x + 2] = wet;
+        part[4 * blockIdx.x + 3] = ab;
     }
 }
 
-// Sum of npart partial triples and of the boundary accumulators, in a fixed order.
+// Sum of npart partial quadruples and of the boundary accumulators, in a fixed order.
 __global__ void __launch_bounds__(SUM_THREADS) k_sums2(const double *__restrict__ part, int npart,
                                                        const double *__restrict__ bnd, int nb,
                                                        double *__restrict__ out)
 {
-    __shared__ double sh[5][SUM_THREADS / 64];
-    double a = 0, b = 0, c = 0, d = 0, e = 0;
+    __shared__ double sh[6][SUM_THREADS / 64];
+    double a = 0, b = 0, c = 0, d = 0, e = 0, f = 0;
     for (int k = threadIdx.x; k < npart; k += SUM_THREADS) {
-        a += part[3 * k]; b += part[3 * k + 1]; c += part[3 * k + 2];
+        a += part[4 * k]; b += part[4 * k + 1]; c += part[4 * k + 2]; f += part[4 * k + 3];
     }
     for (int k = threadIdx.x; k < nb; k += SUM_THREADS) { d += bnd[k]; e += bnd[nb + k]; }
-    a = wave_sum(a); b = wave_sum(b); c = wave_sum(c); d = wave_sum(d); e = wave_sum(e);
+    a = wave_sum(a); b = wave_sum(b); c = wave_sum(c); d = wave_sum(d); e = wave_sum(e); f = wave_sum(f);
     int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { sh[0][w] = a; sh[1][w] = b; sh[2][w] = c; sh[3][w] = d; sh[4][w] = e; }
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][w] = a; sh[1][w] = b; sh[2][w] = c; sh[3][w] = d; sh[4][w] = e; sh[5][w] = f;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 1; k < SUM_THREADS / 64; ++k) { a += sh[0][k]; b += sh[1][k]; c += sh[2][k]; d += sh[3][k]; e += sh[4][k]; }
-        out[0] = a; out[1] = b; out[2] = c; out[3] = d; out[4] = e;
+        for (int k = 1; k < SUM_THREADS / 64; ++k) {
+            a += sh[0][k]; b += sh[1][k]; c += sh[2][k]; d += sh[3][k]; e += sh[4][k]; f += sh[5][k];
+        }
+        out[0] = a; out[1] = b; out[2] = c; out[3] = d; out[4] = e; out[5] = f;
     }
 }
 
@@ -1921,6 +1955,12 @@ struct sw_ctx {
     float *rb = nullptr;             // bed residual of the compensated Exner update
     float *nM = nullptr, *d50 = nullptr, *psi = nullptr, *qb = nullptr, *srcw = nullptr;
     float nM_s = 0.0f, d50_s = 5e-4f, psi_s = 0.4f;
+    // forcing: rainfall, absorption (per-cell plane or scalar), Coriolis, wind
+    double rain = 0.0, coriolis = 0.0, wind_x = 0.0, wind_y = 0.0, wind_coef = 0.0;
+    float *beta = nullptr;
+    float beta_s = 0.0f;
+    double *ab = nullptr;            // absorbed depth per cell (FP64, pitched), with absorption
+    float *rh = nullptr;             // depth residual of the compensated rainfall, with rain
     float *faces = nullptr;          // unfused face arrays
     double *bnd = nullptr;           // boundary accumulators: water [2(nx+ny)], sediment [2(nx+ny)]
     double *part = nullptr;          // sum partials
@@ -2000,6 +2040,17 @@ KPar make_kpar(const sw_ctx *c)
     if (c->par.limiter == SW_LIM_MC) { P.lim_b = 2.0f; P.lim_t = 2.0f; P.lim_g = 0.5f; }
     if (c->par.limiter == SW_LIM_SUPERBEE) { P.lim_b = 2.0f; P.lim_t = 2.0f; P.lim_g = 1.0f; }
     P.speeds = c->par.hll_speeds;
+    P.rain = (float)c->rain;
+    P.beta = c->beta;
+    P.beta_s = c->beta_s;
+    P.ab = c->ab;
+    P.rh = c->rh;
+    P.cor = (float)c->coriolis;
+    const double wm = std::sqrt(c->wind_x * c->wind_x + c->wind_y * c->wind_y);
+    P.wsx = (float)(c->wind_coef * wm * c->wind_x);
+    P.wsy = (float)(c->wind_coef * wm * c->wind_y);
+    P.inv_hsed = (float)(1.0 / c->par.h_sed);
+    P.force = (c->coriolis != 0.0 || P.wsx != 0.0f || P.wsy != 0.0f) ? 1 : 0;
     P.variant = (c->par.limiter != SW_LIM_MINMOD || c->par.hll_speeds != SW_HLL_DAVIS) ? 1 : 0;
     return P;
 }
@@ -2013,6 +2064,7 @@ StepArgs make_step_args(const sw_ctx *c, int fixed, double dt)
     A.has_inflow = c->has_inflow;
     A.q_base = c->q_base; A.q_peak = c->q_peak; A.t_peak = c->t_peak; A.t_sigma = c->t_sigma;
     A.qb_total = c->qb_total;
+    A.rain_area = c->rain * (double)c->nx * (double)c->ny * c->grid.dx * c->grid.dx;
     return A;
 }
 
@@ -2171,7 +2223,8 @@ Inst make_inst(const sw_ctx *c, const StepArgs &A)
     I.tmax[1] = c->tmax + c->max_tiles;
     I.ntx = c->ntx;
     I.nty = c->nty;
-    I.hgs = (c->par.flags & SW_FLAG_HGS) ? 1 : 0;
+    // rain wets every tile: no tile may be skipped
+    I.hgs = ((c->par.flags & SW_FLAG_HGS) && !(c->rain > 0.0)) ? 1 : 0;
     const int nt = c->ntx * c->nty;
     I.chunk = list_chunk(nt);
     I.nchunk = (nt + I.chunk - 1) / I.chunk;
@@ -2253,7 +2306,7 @@ void launch_batch(int shape, Stage st, hipStream_t s, const Inst *insts, int nme
 }
 
 // Whether a grid's kernels must read per-cell soil or source planes.
-bool cell_soil(const KPar &P) { return P.nM || P.d50 || P.psi || P.srcw || P.qb; }
+bool cell_soil(const KPar &P) { return P.nM || P.d50 || P.psi || P.srcw || P.qb || P.beta; }
 
 // Strip shapes: the prepare pass runs one workgroup per tile; K3 builds the
 // work lists; the stage kernels run one wavefront per list entry.
@@ -2601,9 +2654,9 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
     if ((e = hipMemsetAsync(c->bnd, 0, nb * sizeof(double), c->stream)) != hipSuccess) return bail(e, "hipMemset(bnd)");
     c->sum_rows = std::max(1, (int)((c->ny + 1023) / 1024));
     c->nsum_blocks = (c->ny + c->sum_rows - 1) / c->sum_rows;
-    if ((e = hipMalloc(&c->part, (3 * (size_t)c->nsum_blocks + 8) * sizeof(double))) != hipSuccess)
+    if ((e = hipMalloc(&c->part, (4 * (size_t)c->nsum_blocks + 8) * sizeof(double))) != hipSuccess)
         return bail(e, "hipMalloc(part)");
-    c->sums = c->part + 3 * (size_t)c->nsum_blocks;
+    c->sums = c->part + 4 * (size_t)c->nsum_blocks;
     for (int sh = 0; sh < kNumShapes; ++sh) {
         set_shape(c, sh);
         c->max_tiles = std::max(c->max_tiles, ntiles(c));
@@ -2642,6 +2695,9 @@ int sw_destroy(sw_ctx *c)
     (void)hipFree(c->psi);
     (void)hipFree(c->qb);
     (void)hipFree(c->srcw);
+    (void)hipFree(c->beta);
+    (void)hipFree(c->ab);
+    (void)hipFree(c->rh);
     (void)hipFree(c->tflags);
     (void)hipFree(c->tmax);
     (void)hipFree(c->sched);
@@ -2749,6 +2805,8 @@ int sw_set_state(sw_ctx *c, const float *h, const float *hu, const float *hv, in
     if ((rc = upload_plane(c, c->qy[0], V.data(), SW_PTR_HOST))) return rc;
     HIPCHK(c, hipMemsetAsync(c->QLx, 0, 2 * c->plane * sizeof(float), c->stream));
     HIPCHK(c, hipMemsetAsync(c->bnd, 0, 4 * (size_t)(c->nx + c->ny) * sizeof(double), c->stream));
+    if (c->ab) HIPCHK(c, hipMemsetAsync(c->ab, 0, c->plane * sizeof(double), c->stream));
+    if (c->rh) HIPCHK(c, hipMemsetAsync(c->rh, 0, c->plane * sizeof(float), c->stream));
     Ctrl h0{};
     h0.t[0] = c->t0;
     {
@@ -2846,6 +2904,52 @@ int sw_set_sed_sources(sw_ctx *c, const float *qb_plus, const float *qb_minus, i
     return upload_force(c);
 }
 
+int sw_set_forcing(sw_ctx *c, double rain, const float *beta, float beta_scalar, double coriolis,
+                   double wind_x, double wind_y, double wind_coef, int ptr_kind)
+{
+    if (!c) return SW_ERR_ARG;
+    if (!(rain >= 0.0) || !std::isfinite(rain)) return fail(c, SW_ERR_ARG, "rain must be finite and >= 0");
+    if (!beta && !(beta_scalar >= 0.0f && std::isfinite(beta_scalar)))
+        return fail(c, SW_ERR_ARG, "absorption coefficient must be finite and >= 0");
+    if (!std::isfinite(coriolis) || !std::isfinite(wind_x) || !std::isfinite(wind_y) ||
+        !(wind_coef >= 0.0) || !std::isfinite(wind_coef))
+        return fail(c, SW_ERR_ARG, "Coriolis and wind parameters must be finite, wind_coef >= 0");
+    if (beta && ptr_kind == SW_PTR_HOST)
+        for (size_t q = 0; q < (size_t)c->nx * c->ny; ++q)
+            if (!(beta[q] >= 0.0f) || !std::isfinite(beta[q]))
+                return fail(c, SW_ERR_ARG, "absorption coefficients must be finite and >= 0");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int rc = set_soil_field(c, &c->beta, beta, ptr_kind);
+    if (rc) return rc;
+    c->beta_s = beta ? 0.0f : beta_scalar;
+    const bool absorbs = beta != nullptr || beta_scalar > 0.0f;
+    if (absorbs && !c->ab) {
+        HIPCHK(c, hipMalloc(&c->ab, c->plane * sizeof(double)));
+        HIPCHK(c, hipMemsetAsync(c->ab, 0, c->plane * sizeof(double), c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else if (!absorbs && c->ab) {
+        (void)hipFree(c->ab);
+        c->ab = nullptr;
+    }
+    if (rain > 0.0 && !c->rh) {
+        HIPCHK(c, hipMalloc(&c->rh, c->plane * sizeof(float)));
+        HIPCHK(c, hipMemsetAsync(c->rh, 0, c->plane * sizeof(float), c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else if (!(rain > 0.0) && c->rh) {
+        (void)hipFree(c->rh);
+        c->rh = nullptr;
+    }
+    c->rain = rain;
+    c->coriolis = coriolis;
+    c->wind_x = wind_x;
+    c->wind_y = wind_y;
+    c->wind_coef = wind_coef;
+    c->dirty = true;
+    c->graph_ok = false;
+    c->args_gen++;  // the forcing constants and planes are kernel arguments
+    return SW_OK;
+}
+
 int sw_set_time(sw_ctx *c, double t, int64_t step)
 {
     if (!c) return SW_ERR_ARG;
@@ -2878,6 +2982,8 @@ int sw_replace_state(sw_ctx *c, const float *h, const float *hu, const float *hv
     HIPCHK(c, hipMemsetAsync(c->rb, 0, c->plane * sizeof(float), c->stream));
     HIPCHK(c, hipMemsetAsync(c->QLx, 0, 2 * c->plane * sizeof(float), c->stream));
     HIPCHK(c, hipMemsetAsync(c->bnd, 0, 4 * (size_t)(c->nx + c->ny) * sizeof(double), c->stream));
+    if (c->ab) HIPCHK(c, hipMemsetAsync(c->ab, 0, c->plane * sizeof(double), c->stream));
+    if (c->rh) HIPCHK(c, hipMemsetAsync(c->rh, 0, c->plane * sizeof(float), c->stream));
     Ctrl h0{};
     h0.t[0] = t;
     {
@@ -3054,7 +3160,7 @@ int sw_get_sums(sw_ctx *c, sw_sums *out)
     hipLaunchKernelGGL(k_sums2, dim3(1), dim3(SUM_THREADS), 0, c->stream, c->part, c->nsum_blocks,
                        c->bnd, nb, c->sums);
     HIPCHK(c, hipGetLastError());
-    double s[5];
+    double s[6];
     std::vector<uint8_t> act(ntiles(c));
     if ((rc = stage_to_host(c, s, c->sums, sizeof(s)))) return rc;
     if ((rc = stage_to_host(c, act.data(), act_flags(c, cur), act.size()))) return rc;
@@ -3080,6 +3186,8 @@ int sw_get_sums(sw_ctx *c, sw_sums *out)
     out->binding_term = hc.binding;
     out->error = hc.err;
     out->graph_builds = c->graph_builds;
+    out->water_rain_in = hc.in_rain;
+    out->water_absorbed = s[5] * dx2;
     return SW_OK;
 }
 
@@ -3090,14 +3198,16 @@ struct CkptHeader {
     int32_t nx, ny, ctrl_bytes, nb;
     int64_t step;            // step counter of the saved state
     double t;                // model time of the saved state
-    int32_t par, pad;        // buffer parity of the saved ring entries
+    int32_t par;             // buffer parity of the saved ring entries
+    int32_t extra;           // bit 0: absorbed depths (FP64 plane), bit 1: rainfall residual plane follow
     Ctrl ctrl;               // device control block (time ring, source balances, maxima)
 };
 
 static size_t ckpt_bytes(const sw_ctx *c)
 {
     const size_t n = (size_t)c->nx * c->ny, nb = 4 * (size_t)(c->nx + c->ny);
-    return sizeof(CkptHeader) + 5 * n * sizeof(float) + nb * sizeof(double);
+    return sizeof(CkptHeader) + 5 * n * sizeof(float) + nb * sizeof(double) +
+           (c->ab ? c->plane * sizeof(double) : 0) + (c->rh ? c->plane * sizeof(float) : 0);
 }
 
 int sw_checkpoint_size(const sw_ctx *c, int64_t *bytes)
@@ -3123,6 +3233,7 @@ int sw_checkpoint_save(sw_ctx *c, void *buf, int64_t bytes)
     h.ctrl_bytes = (int32_t)sizeof(Ctrl);
     h.nb = 4 * (c->nx + c->ny);
     h.par = (int32_t)(c->k & 1);
+    h.extra = (c->ab ? 1 : 0) | (c->rh ? 2 : 0);
     h.step = c->step0 + c->k;
     h.t = h.ctrl.t[h.par];
     char *out = (char *)buf;
@@ -3133,7 +3244,12 @@ int sw_checkpoint_save(sw_ctx *c, void *buf, int64_t bytes)
     const float *planes[5] = {c->H[cur], c->qx[cur], c->qy[cur], c->b[cur], c->rb};
     for (int f = 0; f < 5; ++f, out += n * sizeof(float))
         if ((rc = download_plane(c, (float *)out, planes[f], SW_PTR_HOST))) return rc;
-    return stage_to_host(c, out, c->bnd, (size_t)h.nb * sizeof(double));
+    if ((rc = stage_to_host(c, out, c->bnd, (size_t)h.nb * sizeof(double)))) return rc;
+    out += (size_t)h.nb * sizeof(double);
+    if (c->ab && (rc = stage_to_host(c, out, c->ab, c->plane * sizeof(double)))) return rc;
+    if (c->ab) out += c->plane * sizeof(double);
+    if (c->rh) rc = stage_to_host(c, out, c->rh, c->plane * sizeof(float));
+    return rc;
 }
 
 int sw_checkpoint_load(sw_ctx *c, const void *buf, int64_t bytes)
@@ -3147,6 +3263,8 @@ int sw_checkpoint_load(sw_ctx *c, const void *buf, int64_t bytes)
     if (h.nx != c->nx || h.ny != c->ny || h.nb != 4 * (c->nx + c->ny))
         return fail(c, SW_ERR_ARG, "checkpoint of another grid");
     if (bytes < (int64_t)ckpt_bytes(c)) return fail(c, SW_ERR_ARG, "checkpoint too short");
+    if (h.extra != ((c->ab ? 1 : 0) | (c->rh ? 2 : 0)))
+        return fail(c, SW_ERR_ARG, "checkpoint of a context with other rain or absorption settings");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const char *in = (const char *)buf + sizeof(h);
     const size_t n = (size_t)c->nx * c->ny;
@@ -3159,6 +3277,10 @@ int sw_checkpoint_load(sw_ctx *c, const void *buf, int64_t bytes)
                              c->stream));
     HIPCHK(c, hipMemsetAsync(c->QLx, 0, 2 * c->plane * sizeof(float), c->stream));
     if ((rc = stage_to_device(c, c->bnd, in, (size_t)h.nb * sizeof(double)))) return rc;
+    in += (size_t)h.nb * sizeof(double);
+    if (c->ab && (rc = stage_to_device(c, c->ab, in, c->plane * sizeof(double)))) return rc;
+    if (c->ab) in += c->plane * sizeof(double);
+    if (c->rh && (rc = stage_to_device(c, c->rh, in, c->plane * sizeof(float)))) return rc;
     // the saved control block with its ring entries moved to parity 0
     Ctrl k0 = h.ctrl;
     std::memset(k0.slot, 0, sizeof(k0.slot));

@@ -40,6 +40,15 @@ struct KPar {
     float lim_b, lim_t, lim_g;
     int speeds;                     // HLL wave speeds: 0 Davis, 1 two-rarefaction
     int variant;                    // 1 when the limiter or the speeds differ from minmod + Davis
+    // forcing (sigma and f of Eq. 6)
+    float rain;                     // rainfall rate, m/s, on every cell (mass only)
+    const float *beta; float beta_s;  // absorption coefficient, 1/s: per cell or scalar
+    double *ab;                     // absorbed depth per cell, FP64 (null: no absorption)
+    float *rh;                      // depth residual of the compensated rainfall (null: no rain)
+    float cor;                      // Coriolis parameter f_c, 1/s
+    float wsx, wsy;                 // wind stress per unit density C_w |W| W, m^2/s^2
+    float inv_hsed;                 // 1 / h_sed (the wind's depth ramp)
+    int force;                      // 1 when the Coriolis or the wind term acts
 };
 
 __device__ __forceinline__ float soil(const float *a, float s, int c) { return a ? a[c] : s; }
