@@ -210,6 +210,8 @@ def main():
     if not args.no_hgs:
         out["hgs"] = hgs_rate(csph, w, torch, stream, args.steps, value)
     if not args.no_extras:
+        out["save_overlap"] = save_overlap(csph, w, torch, stream)
+    if not args.no_extras:
         out["dam_break_2048"] = dam_break_rate(csph, W, torch, stream)
         out["surrogate"] = surrogate_rates(csph, torch)
         out["ensemble"] = ensemble_rates(csph, W, torch)
@@ -236,6 +238,46 @@ def hgs_rate(csph, w, torch, stream, steps, full_rate):
            "cells_euler_per_step": round(sums["cells_euler"] / steps),
            "gain_vs_every_tile": round(rate / full_rate, 2)}
     log(f"[bench]   hgs: {res}")
+    return res
+
+
+def save_overlap(csph, w, torch, stream, steps=400, every=100):
+    """The state read back every `every` steps (the Save block of Section 3):
+    synchronously (sw_get_fields between the advances) and asynchronously
+    (sw_save_begin, then sw_save_wait one interval later, the copy running on a
+    second stream), against the same steps without readback."""
+    log(f"[bench] readback every {every} steps on {w.nx}^2, {steps} steps")
+    s = csph.solver_for(w, stream=stream.cuda_stream, flags=0)
+    s.advance(2)
+    s.save_begin()
+    s.save_wait()
+
+    def run(mode):
+        s.reset(w)
+        s.sync()
+        t0 = time.perf_counter()
+        pending = False
+        for _ in range(steps // every):
+            s.advance(every)
+            if mode == "sync":
+                s.get_fields()
+            elif mode == "async":
+                if pending:
+                    s.save_wait()
+                s.save_begin()
+                pending = True
+        if pending:
+            s.save_wait()
+        s.sync()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    plain, sync, asyn = run("none"), run("sync"), run("async")
+    s.close()
+    res = {"grid": [w.nx, w.ny], "steps": steps, "every": every,
+           "ms_per_step_no_readback": round(plain, 4), "ms_per_step_sync": round(sync, 4),
+           "ms_per_step_async": round(asyn, 4),
+           "async_gain_vs_sync": round(sync / asyn - 1.0, 4)}
+    log(f"[bench]   readback: {res}")
     return res
 
 

@@ -251,6 +251,22 @@ int sw_get_fields(sw_ctx *ctx, float *h, float *hu, float *hv, float *b, int ptr
  * boundary and source balances).  Synchronises the context's stream. */
 int sw_get_sums(sw_ctx *ctx, sw_sums *out);
 
+/* Asynchronous Save (the Save and Screen blocks of Section 3 record the state
+ * every 100-1000 steps; the paper overlaps that exchange with the computation
+ * on CUDA streams).  sw_save_begin queues, on the context's stream after the
+ * work already queued, a device copy of the current h, hu, hv, b and control
+ * block, and on a second stream of its own the copy of that snapshot into
+ * pinned host memory the library owns; it returns at once, so later
+ * sw_advance calls run while the copy travels.  sw_save_wait blocks until
+ * that copy has arrived and writes it into the caller's host arrays
+ * [ny][nx] (any may be NULL), with the model time and step of the snapshot
+ * (t, step may be NULL); it returns a device error the snapshot carries.  One
+ * save may be in flight at a time (SW_ERR_STATE otherwise, and for a wait
+ * without a save).  The first call allocates a device snapshot (4 planes)
+ * and a pinned host buffer of the same size. */
+int sw_save_begin(sw_ctx *ctx);
+int sw_save_wait(sw_ctx *ctx, float *h, float *hu, float *hv, float *b, double *t, int64_t *step);
+
 /* Checkpoint and resume (the Save block of Section 3, for restarts): the
  * whole state a later step depends on -- h, hu, hv, the bed and its residual
  * (the part of the accumulated Exner change the float32 bed has not absorbed

@@ -91,6 +91,9 @@ SIGNATURES = [
     ("sw_get_fields", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     ("sw_get_sums", C.c_int, [_ctxp, C.POINTER(sw_sums)]),
     ("sw_last_error", C.c_char_p, [_ctxp]),
+    ("sw_save_begin", C.c_int, [_ctxp]),
+    ("sw_save_wait", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("sw_checkpoint_size", C.c_int, [_ctxp, C.POINTER(C.c_int64)]),
     ("sw_checkpoint_save", C.c_int, [_ctxp, C.c_void_p, C.c_int64]),
     ("sw_checkpoint_load", C.c_int, [_ctxp, C.c_void_p, C.c_int64]),
@@ -319,6 +322,18 @@ class Solver:
         s = sw_sums()
         _check(self.ctx, lib.sw_get_sums(self.ctx, C.byref(s)))
         return s.as_dict()
+
+    def save_begin(self):
+        """Start copying the current state to the host on a second stream."""
+        _check(self.ctx, lib.sw_save_begin(self.ctx))
+
+    def save_wait(self):
+        """(h, hu, hv, b, t, step) of the snapshot sw_save_begin took."""
+        arrs = [np.empty((self.ny, self.nx), dtype=np.float32) for _ in range(4)]
+        t, step = C.c_double(), C.c_int64()
+        _check(self.ctx, lib.sw_save_wait(self.ctx, *[a.ctypes.data_as(C.c_void_p) for a in arrs],
+                                          C.byref(t), C.byref(step)))
+        return (*arrs, t.value, step.value)
 
     def checkpoint(self) -> np.ndarray:
         """The solver's whole state as a host blob (uint8 array) for a later restore."""

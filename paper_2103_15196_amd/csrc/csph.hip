@@ -1982,6 +1982,15 @@ struct sw_ctx {
     // so the runtime never has to pin pageable user memory on the fly
     float *stage = nullptr;
     size_t stage_bytes = 0;
+    // asynchronous Save: a device snapshot of the state, copied to pinned host
+    // memory on a second stream while the steps go on
+    float *snap = nullptr;           // 4 pitched planes h, hu, hv, b
+    Ctrl *snap_ctrl = nullptr;       // the control block at the snapshot (device)
+    float *snap_host = nullptr;      // pinned: 4 dense planes, then the control block
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t ev_snap = nullptr, ev_copied = nullptr;
+    bool save_pending = false;
+    int64_t save_k = 0;
     hipGraphExec_t gexec = nullptr;  // two tiled steps (even k, then odd k)
     hipGraphExec_t gexec_long = nullptr;  // kLongPairs such pairs
     bool graph_ok = false;           // false once a kernel argument changed (soil, sources, shape)
@@ -2074,6 +2083,13 @@ int ensure_stage(sw_ctx *c, size_t bytes)
     bytes = std::max(bytes, c->plane * sizeof(float));
     if (c->stage_bytes >= bytes) return SW_OK;
     if (c->stage) (void)hipHostFree(c->stage);
+    if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
+    (void)hipFree(c->snap);
+    (void)hipFree(c->snap_ctrl);
+    if (c->snap_host) (void)hipHostFree(c->snap_host);
+    if (c->ev_snap) (void)hipEventDestroy(c->ev_snap);
+    if (c->ev_copied) (void)hipEventDestroy(c->ev_copied);
+    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
     c->stage = nullptr;
     c->stage_bytes = 0;
     HIPCHK(c, hipHostMalloc((void **)&c->stage, bytes, hipHostMallocDefault));
@@ -2702,6 +2718,13 @@ int sw_destroy(sw_ctx *c)
     (void)hipFree(c->tmax);
     (void)hipFree(c->sched);
     if (c->stage) (void)hipHostFree(c->stage);
+    if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
+    (void)hipFree(c->snap);
+    (void)hipFree(c->snap_ctrl);
+    if (c->snap_host) (void)hipHostFree(c->snap_host);
+    if (c->ev_snap) (void)hipEventDestroy(c->ev_snap);
+    if (c->ev_copied) (void)hipEventDestroy(c->ev_copied);
+    if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->gexec_long) (void)hipGraphExecDestroy(c->gexec_long);
     if (c->cap) (void)hipStreamDestroy(c->cap);
@@ -3188,6 +3211,63 @@ int sw_get_sums(sw_ctx *c, sw_sums *out)
     out->graph_builds = c->graph_builds;
     out->water_rain_in = hc.in_rain;
     out->water_absorbed = s[5] * dx2;
+    return SW_OK;
+}
+
+int sw_save_begin(sw_ctx *c)
+{
+    if (!c) return SW_ERR_ARG;
+    if (!c->have_state) return fail(c, SW_ERR_STATE, "save before sw_set_state");
+    if (c->save_pending) return fail(c, SW_ERR_STATE, "the previous save was not collected");
+    const size_t dense = (size_t)c->nx * c->ny;
+    if (!c->snap) {
+        HIPCHK(c, hipMalloc(&c->snap, 4 * c->plane * sizeof(float)));
+        HIPCHK(c, hipMalloc(&c->snap_ctrl, sizeof(Ctrl)));
+        HIPCHK(c, hipHostMalloc((void **)&c->snap_host, 4 * dense * sizeof(float) + sizeof(Ctrl),
+                                hipHostMallocDefault));
+        HIPCHK(c, hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_snap, hipEventDisableTiming));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_copied, hipEventDisableTiming));
+    }
+    // on the solver's stream, after the queued steps: a device copy of the
+    // current level (the steps after it may overwrite that level)
+    const int cur = (int)(c->k & 1);
+    const float *src[4] = {c->H[cur], c->qx[cur], c->qy[cur], c->b[cur]};
+    for (int f = 0; f < 4; ++f)
+        HIPCHK(c, hipMemcpyAsync(c->snap + f * c->plane, src[f], c->plane * sizeof(float),
+                                 hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->snap_ctrl, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev_snap, c->stream));
+    // on the copy stream: the snapshot to pinned host memory
+    HIPCHK(c, hipStreamWaitEvent(c->copy_stream, c->ev_snap, 0));
+    for (int f = 0; f < 4; ++f)
+        HIPCHK(c, hipMemcpy2DAsync(c->snap_host + f * dense, c->nx * sizeof(float),
+                                   c->snap + f * c->plane, c->pitch * sizeof(float),
+                                   c->nx * sizeof(float), c->ny, hipMemcpyDeviceToHost,
+                                   c->copy_stream));
+    HIPCHK(c, hipMemcpyAsync(c->snap_host + 4 * dense, c->snap_ctrl, sizeof(Ctrl),
+                             hipMemcpyDeviceToHost, c->copy_stream));
+    HIPCHK(c, hipEventRecord(c->ev_copied, c->copy_stream));
+    c->save_pending = true;
+    c->save_k = c->k;
+    return SW_OK;
+}
+
+int sw_save_wait(sw_ctx *c, float *h, float *hu, float *hv, float *b, double *t, int64_t *step)
+{
+    if (!c) return SW_ERR_ARG;
+    if (!c->save_pending) return fail(c, SW_ERR_STATE, "no save in flight");
+    HIPCHK(c, hipEventSynchronize(c->ev_copied));
+    c->save_pending = false;
+    const size_t dense = (size_t)c->nx * c->ny;
+    float *dst[4] = {h, hu, hv, b};
+    for (int f = 0; f < 4; ++f)
+        if (dst[f]) std::memcpy(dst[f], c->snap_host + f * dense, dense * sizeof(float));
+    Ctrl hc;
+    std::memcpy(&hc, c->snap_host + 4 * dense, sizeof(Ctrl));
+    if (t) *t = hc.t[c->save_k & 1];
+    if (step) *step = c->step0 + c->save_k;
+    if (hc.err) return fail(c, hc.err, "device error raised at step " + std::to_string(hc.err_k));
     return SW_OK;
 }
 

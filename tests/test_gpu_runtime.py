@@ -128,3 +128,38 @@ def test_gpu_dt_underflow_is_raised_by_the_device():
     ok.sync()
     assert ok.get_sums()["last_dt"] == pytest.approx(0.3 / np.sqrt(9.81 * 2.0), rel=1e-6)
     ok.close()
+
+
+def test_gpu_async_save_snapshots_the_state_while_steps_go_on():
+    """sw_save_begin takes the state after the queued steps and copies it on
+    a second stream while later steps run: the snapshot equals the state a
+    plain run reads at that step, the run itself is unchanged, and out-of-order
+    calls are SW_ERR_STATE."""
+    from paper_2103_15196_amd import csph
+    import torch
+    w = W.dam_break_fractal(n=200, ny=150, dx=2.0, seed=21, relief=8.0, depth=5.0).as_float32()
+    stream = torch.cuda.Stream().cuda_stream
+    a = csph.solver_for(w, stream=stream)
+    with pytest.raises(csph.SwError) as e:
+        a.save_wait()
+    assert e.value.code == csph.SW_ERR_STATE
+    a.advance(30)
+    a.save_begin()
+    with pytest.raises(csph.SwError) as e:
+        a.save_begin()
+    assert e.value.code == csph.SW_ERR_STATE
+    a.advance(30)
+    h, hu, hv, b, t, step = a.save_wait()
+    end = a.get_fields()
+    ref = csph.solver_for(w, stream=stream)
+    ref.advance(30)
+    r30, s30 = ref.get_fields(), ref.get_sums()
+    ref.advance(30)
+    r60 = ref.get_fields()
+    for x, y in zip((h, hu, hv, b), r30):
+        assert np.array_equal(x, y)
+    assert t == s30["t"] and step == 30
+    for x, y in zip(end, r60):
+        assert np.array_equal(x, y)
+    a.close()
+    ref.close()
