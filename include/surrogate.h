@@ -73,13 +73,62 @@ int sws_train_step(sws_net *net, const float *x, const float *target, int32_t ni
 
 /* Advance a solver by k steps with the surrogate: the predicted change is
  * added to the solver's state (depth clamped at 0, momentum zeroed where the
- * depth is 0) unless the relative change of the water volume exceeds
- * max_drift (closed domains: the volume must not change), in which case the
- * solver takes the k steps itself with fixed step dt.  Either way the model
- * time advances by k dt.  *used (may be NULL) receives 1 if the surrogate's
- * prediction was kept.  Synchronises. */
+ * depth is 0) unless the relative change of the water volume or of the bed
+ * sum exceeds max_drift (closed domains: neither may change), in which case
+ * the solver takes the k steps itself with fixed step dt.  Either way the
+ * model time advances by k dt.  *used (may be NULL) receives 1 if the
+ * surrogate's prediction was kept.  One call of sws_advance_K without
+ * residual checks.  Synchronises. */
 int sws_advance(sws_net *net, sw_ctx *solver, int32_t k, double dt, double max_drift,
                 int32_t *used);
+
+/* Training run on the GPU (the loop the paper's solver-generated data feeds;
+ * the learning part of the method is this project's, as the paper has none):
+ * npairs pairs of already scaled inputs x [npairs][5][ny][nx] and scaled
+ * targets [npairs][4][ny][nx] (host or device, per ptr_kind) are copied to the
+ * device once; each of cfg->steps Adam steps (sws_train_step) takes cfg->batch
+ * distinct pairs drawn with SplitMix64 from cfg->seed, with the learning rate
+ * cfg->lr 0.5 (1 + cos(pi step / steps)).  *report (may be NULL): the first
+ * step's loss and the mean of the last min(50, steps); losses (host, may be
+ * NULL): every step's loss (reading them synchronises every step).
+ * Allocates and frees a device copy of the set; synchronises. */
+typedef struct {
+    int32_t steps;
+    int32_t batch;
+    float lr;
+    uint64_t seed;
+} sws_train_cfg;
+typedef struct {
+    double first_loss, final_loss;
+    int32_t steps;
+} sws_train_report;
+int sws_train(sws_net *net, const float *x, const float *target, int32_t npairs, int32_t nx,
+              int32_t ny, const sws_train_cfg *cfg, sws_train_report *report, float *losses,
+              int ptr_kind);
+
+/* n_calls surrogate calls of k steps each on a solver (sws_advance's step,
+ * called again and again), with the checks that decide whether a prediction
+ * is kept:
+ *  - conservation: the relative change of the water volume, and of the bed
+ *    volume sum b, must stay within max_drift (a closed domain without
+ *    sources); else the solver takes the k plain steps (fixed dt);
+ *  - residual (every check_every-th call, 0 = never): the plain solver takes
+ *    the same k steps from the same state and judges the prediction: if the
+ *    largest depth difference exceeds max_err (m), the plain result is kept.
+ * The model time advances by k dt per call either way.  *stats (may be NULL)
+ * receives the counts and the largest drift and residual seen.
+ * Synchronises. */
+typedef struct {
+    int32_t calls;               /* surrogate calls made */
+    int32_t kept;                /* predictions installed */
+    int32_t fallbacks_volume;    /* calls the conservation check sent to the plain step */
+    int32_t fallbacks_residual;  /* checked calls whose depth residual exceeded max_err */
+    int32_t checks;              /* calls the plain step judged */
+    double max_volume_drift;     /* largest relative water or bed volume change predicted */
+    double max_residual;         /* largest depth difference (m) at a check */
+} sws_stats;
+int sws_advance_K(sws_net *net, sw_ctx *solver, int32_t n_calls, int32_t k, double dt,
+                  double max_drift, int32_t check_every, double max_err, sws_stats *stats);
 
 /* Text of the last error on net (never NULL). */
 const char *sws_last_error(const sws_net *net);

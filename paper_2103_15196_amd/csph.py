@@ -136,6 +136,10 @@ SIGNATURES = [
                            C.c_void_p, C.POINTER(C.c_double), C.c_int]),
     ("sws_advance", C.c_int, [C.c_void_p, _ctxp, C.c_int32, C.c_double, C.c_double,
                               C.POINTER(C.c_int32)]),
+    ("sws_train", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    ("sws_advance_K", C.c_int, [C.c_void_p, _ctxp, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                C.c_int32, C.c_double, C.c_void_p]),
     ("sws_last_error", C.c_char_p, [C.c_void_p]),
 ]
 
@@ -473,6 +477,23 @@ def _scheck(h, rc):
         raise SwError(rc, msg)
 
 
+class sws_train_cfg(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("seed", C.c_uint64)]
+
+
+class sws_train_report(C.Structure):
+    _fields_ = [("first_loss", C.c_double), ("final_loss", C.c_double), ("steps", C.c_int32)]
+
+
+class sws_stats(C.Structure):
+    _fields_ = [("calls", C.c_int32), ("kept", C.c_int32), ("fallbacks_volume", C.c_int32),
+                ("fallbacks_residual", C.c_int32), ("checks", C.c_int32),
+                ("max_volume_drift", C.c_double), ("max_residual", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Surrogate:
     """The convolutional surrogate (BF16 matrix-core convolutions): widths
     `channels` (5 inputs ... 4 outputs); parameters as one FP32 vector (per
@@ -543,6 +564,30 @@ class Surrogate:
         _scheck(self.ctx, lib.sws_train_step(self.ctx, x.ctypes.data, t.ctypes.data, nimg, nx, ny,
                                              float(lr), C.byref(loss), SW_PTR_HOST))
         return loss.value
+
+    def train(self, x, target, steps, batch, lr, seed=0, keep_losses=False):
+        """sws_train on scaled pairs x [n, 5, ny, nx], target [n, 4, ny, nx]:
+        returns (report dict, per-step losses or None)."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(target, dtype=np.float32)
+        npairs, _, ny, nx = x.shape
+        cfg = sws_train_cfg(int(steps), int(batch), float(lr), int(seed))
+        rep = sws_train_report()
+        losses = np.empty(int(steps), np.float32) if keep_losses else None
+        _scheck(self.ctx, lib.sws_train(self.ctx, x.ctypes.data, t.ctypes.data, npairs, nx, ny,
+                                        C.byref(cfg), C.byref(rep),
+                                        losses.ctypes.data if losses is not None else None,
+                                        SW_PTR_HOST))
+        return {"first_loss": rep.first_loss, "final_loss": rep.final_loss, "steps": rep.steps}, losses
+
+    def advance_k(self, solver, n_calls, k, dt, max_drift=1e-5, check_every=0, max_err=5e-3):
+        """sws_advance_K: n_calls surrogate calls with the conservation and
+        residual checks; returns the stats dict."""
+        st = sws_stats()
+        _scheck(self.ctx, lib.sws_advance_K(self.ctx, solver.ctx, int(n_calls), int(k), float(dt),
+                                            float(max_drift), int(check_every), float(max_err),
+                                            C.byref(st)))
+        return st.as_dict()
 
     def advance(self, solver, k, dt, max_drift=1e-5):
         """k steps of `solver` by the surrogate (or by the solver if the water

@@ -1,8 +1,8 @@
 // surrogate.hip -- the learned surrogate of the CSPH-TVD step on gfx950: 3x3
 // convolutions on the matrix cores (v_mfma_f32_16x16x32_bf16: BF16 operands,
-// FP32 accumulation), training kernels (input gradients on the matrix cores,
-// weight gradients and Adam in FP32) and the surrogate step with its mass
-// check and plain-solver fall back.
+// FP32 accumulation), training kernels (input and weight gradients on the
+// matrix cores, Adam in FP32) and the surrogate step with its mass check and
+// plain-solver fall back.
 //
 // Layouts.  Activations are BF16, channels last ("NHWC"): [img][y][x][C] with
 // C = 8 for the 5-channel input (channels 5..7 zero) and C = 48 for the
@@ -305,26 +305,41 @@ __global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, 
     }
 }
 
-// Weight and bias gradients of one layer, FP32: dW[n][c][ky][kx] =
-// sum_pixels dz[p][n] x[p + (ky-1, kx-1)][c], db[n] = sum_pixels dz[p][n].
-// Workgroup job = 64 pixels of one row; x rows y-1..y+1 and dz staged in LDS;
-// thread t accumulates the (n, c) pairs t, t + 256, ... over all 9 taps and
-// all its jobs, then writes its partials (one slice per workgroup).
-constexpr int DWX = 64;
-__global__ void __launch_bounds__(NT) k_dw(const unsigned short *__restrict__ x, int cs, int cin,
-                                           const unsigned short *__restrict__ dz, int dcs, int cout,
-                                           int nimg, int nx, int ny, float *__restrict__ part)
+// Weight and bias gradients of one layer on the matrix cores:
+//   dW[n][c][ky][kx] = sum over pixels p of dz[p][n] x[p + (ky-1, kx-1)][c],
+//   db[n] = sum over p of dz[p][n],
+// a GEMM D[n][j] = sum_p A[n][p] B[p][j] with j = 9 c + 3 ky + kx (so D is
+// W's gradient in parameter order), M = cout, N = 9 cin, and the pixels as
+// the reduction (BF16 products, FP32 accumulation, split over workgroups).
+// A job is 64 pixels of one row: dz is staged transposed, sdz[n][i], and the
+// three input rows once per horizontal shift, sxt[kx][c][ky][i] = x at
+// (y + ky - 1, x0 + i + kx - 1), so every A and B fragment (8 consecutive
+// pixels of one channel) is one aligned 16-byte LDS read.  Wavefront w owns
+// the output blocks w, w + DWW, ...; each workgroup writes its partials (one
+// slice per workgroup, summed in a fixed order by k_dw_sum).
+constexpr int DWX = 64;            // pixels per job
+constexpr int DWP = DWX + 8;       // padded LDS row (bf16)
+constexpr int DWW = 8;             // wavefronts of a weight-gradient workgroup
+constexpr int DWT = 64 * DWW;
+constexpr int DW_MAXB = ((MAXW / 16) * ((9 * MAXW + 15) / 16) + DWW - 1) / DWW;
+__global__ void __launch_bounds__(DWT) k_dw(const unsigned short *__restrict__ x, int cs, int cin,
+                                            const unsigned short *__restrict__ dz, int dcs,
+                                            int cout, int nimg, int nx, int ny,
+                                            float *__restrict__ part)
 {
-    __shared__ unsigned short sx[3][DWX + 2][MAXW];
-    __shared__ unsigned short sd[DWX][MAXW];
-    const int npair = cout * cin;
-    constexpr int PP = (MAXW * MAXW + NT - 1) / NT;  // pairs per thread
-    float acc[PP][9];
+    __shared__ __attribute__((aligned(16))) unsigned short sdz[MAXW][DWP];
+    __shared__ __attribute__((aligned(16))) unsigned short sxt[3][MAXW][3][DWP];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, kg = lane >> 4;
+    const int jcols = 9 * cin, nbj = (jcols + 15) / 16, nbm = (cout + 15) / 16;
+    const int nblk = nbm * nbj;
+    // rows n >= cout of sdz and channels c >= cin of sxt are never staged: zero
+    for (int q = threadIdx.x; q < MAXW * DWP; q += DWT) (&sdz[0][0])[q] = 0;
+    for (int q = threadIdx.x; q < 3 * MAXW * 3 * DWP; q += DWT) (&sxt[0][0][0][0])[q] = 0;
+    floatx4 acc[DW_MAXB];
+#pragma unroll
+    for (int t = 0; t < DW_MAXB; ++t) acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     float accb = 0.0f;
-#pragma unroll
-    for (int q = 0; q < PP; ++q)
-#pragma unroll
-        for (int t = 0; t < 9; ++t) acc[q][t] = 0.0f;
     const int xblocks = (nx + DWX - 1) / DWX;
     const long jobs = (long)nimg * ny * xblocks;
     for (long job = blockIdx.x; job < jobs; job += gridDim.x) {
@@ -332,47 +347,61 @@ __global__ void __launch_bounds__(NT) k_dw(const unsigned short *__restrict__ x,
         const long rowi = job / xblocks;
         const int y = (int)(rowi % ny), img = (int)(rowi / ny);
         const int x0 = xb * DWX;
-        __syncthreads();
-        for (int q = threadIdx.x; q < 3 * (DWX + 2) * cin; q += NT) {
+        __syncthreads();  // the previous job is done with the staged rows
+        for (int q = threadIdx.x; q < DWX * cout; q += DWT) {
+            const int n = q % cout, i = q / cout, gx = x0 + i;
+            sdz[n][i] = gx < nx ? dz[(((long)img * ny + y) * nx + gx) * dcs + n] : 0;
+        }
+        for (int q = threadIdx.x; q < 3 * (DWX + 2) * cin; q += DWT) {
             const int c = q % cin, xx = (q / cin) % (DWX + 2), r = q / (cin * (DWX + 2));
             const int gy = y + r - 1, gx = x0 + xx - 1;
             unsigned short v = 0;
             if ((unsigned)gy < (unsigned)ny && (unsigned)gx < (unsigned)nx)
                 v = x[(((long)img * ny + gy) * nx + gx) * cs + c];
-            sx[r][xx][c] = v;
-        }
-        for (int q = threadIdx.x; q < DWX * cout; q += NT) {
-            const int n = q % cout, xx = q / cout;
-            const int gx = x0 + xx;
-            sd[xx][n] = gx < nx ? dz[(((long)img * ny + y) * nx + gx) * dcs + n] : 0;
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {  // pixel i sees column xx = i + kx
+                const int i = xx - kx;
+                if (i >= 0 && i < DWX) sxt[kx][c][r][i] = v;
+            }
         }
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < PP; ++q) {
-            const int pr = threadIdx.x + q * NT;
-            if (pr >= npair) continue;
-            const int n = pr / cin, c = pr % cin;
-            for (int xx = 0; xx < DWX; ++xx) {
-                const float d = bf16_float(sd[xx][n]);
-                if (d == 0.0f) continue;
+        for (int t = 0; t < DW_MAXB; ++t) {
+            const int bi = wv + DWW * t;
+            if (bi >= nblk) break;
+            const int nb = bi / nbj, jb = bi - nb * nbj;
+            const int n = 16 * nb + m, j = 16 * jb + m;
+            const int jj = min(j, jcols - 1);
+            const int c = jj / 9, tap = jj - 9 * c, ky = tap / 3, kx = tap - 3 * ky;
 #pragma unroll
-                for (int t = 0; t < 9; ++t)
-                    acc[q][t] += d * bf16_float(sx[t / 3][xx + t % 3][c]);
+            for (int k0 = 0; k0 < DWX; k0 += 32) {
+                bf16x8 av, bv;
+                const uint4 a4 = *reinterpret_cast<const uint4 *>(&sdz[n][k0 + 8 * kg]);
+                uint4 b4 = *reinterpret_cast<const uint4 *>(&sxt[kx][c][ky][k0 + 8 * kg]);
+                if (j >= jcols) b4 = make_uint4(0u, 0u, 0u, 0u);
+                __builtin_memcpy(&av, &a4, 16);
+                __builtin_memcpy(&bv, &b4, 16);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
             }
         }
         if ((int)threadIdx.x < cout)
-            for (int xx = 0; xx < DWX; ++xx) accb += bf16_float(sd[xx][threadIdx.x]);
+            for (int i = 0; i < DWX; ++i) accb += bf16_float(sdz[threadIdx.x][i]);
     }
-    float *mine = part + (long)blockIdx.x * (npair * 9 + cout);
+    // lane holds D[16 nb + 4 kg + i][16 jb + m], i = 0..3
+    float *mine = part + (long)blockIdx.x * (cout * jcols + cout);
 #pragma unroll
-    for (int q = 0; q < PP; ++q) {
-        const int pr = threadIdx.x + q * NT;
-        if (pr >= npair) continue;
-        const int n = pr / cin, c = pr % cin;
+    for (int t = 0; t < DW_MAXB; ++t) {
+        const int bi = wv + DWW * t;
+        if (bi >= nblk) break;
+        const int nb = bi / nbj, jb = bi - nb * nbj;
+        const int j = 16 * jb + m;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) mine[(n * cin + c) * 9 + t] = acc[q][t];
+        for (int i = 0; i < 4; ++i) {
+            const int n = 16 * nb + 4 * kg + i;
+            if (n < cout && j < jcols) mine[n * jcols + j] = acc[t][i];
+        }
     }
-    if ((int)threadIdx.x < cout) mine[npair * 9 + threadIdx.x] = accb;
+    if ((int)threadIdx.x < cout) mine[cout * jcols + threadIdx.x] = accb;
 }
 
 // Sum of the per-workgroup partial gradients (fixed order) into grad.
@@ -419,13 +448,13 @@ __global__ void k_inputs(const float *__restrict__ f, long n, float s0, float s1
 }
 
 // New state = old + out_scale * prediction (depth clamped at 0, momentum 0 on
-// dry cells); FP64 partial sums of the old and new depth.
+// dry cells); FP64 partial sums of the old and new depth and bed.
 __global__ void k_apply(const float *__restrict__ f, const float *__restrict__ o, long n, float s0,
                         float s1, float s2, float s3, float *__restrict__ nf,
                         double *__restrict__ part)
 {
-    __shared__ double r0[NWAVE], r1[NWAVE];
-    double a = 0.0, b = 0.0;
+    __shared__ double r[4][NWAVE];
+    double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
     for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < n;
          p += (long)gridDim.x * blockDim.x) {
         const float h = f[p];
@@ -433,23 +462,63 @@ __global__ void k_apply(const float *__restrict__ f, const float *__restrict__ o
         if (!(hn > 0.0f)) hn = 0.0f;
         const float qx = hn > 0.0f ? f[n + p] + s1 * o[n + p] : 0.0f;
         const float qy = hn > 0.0f ? f[2 * n + p] + s2 * o[2 * n + p] : 0.0f;
+        const float bn = f[3 * n + p] + s3 * o[3 * n + p];
         nf[p] = hn;
         nf[n + p] = qx;
         nf[2 * n + p] = qy;
-        nf[3 * n + p] = f[3 * n + p] + s3 * o[3 * n + p];
+        nf[3 * n + p] = bn;
         a += (double)h;
         b += (double)hn;
+        c += (double)f[3 * n + p];
+        d += (double)bn;
     }
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_down(a, off);
         b += __shfl_down(b, off);
+        c += __shfl_down(c, off);
+        d += __shfl_down(d, off);
     }
-    if ((threadIdx.x & 63) == 0) { r0[threadIdx.x >> 6] = a; r1[threadIdx.x >> 6] = b; }
+    if ((threadIdx.x & 63) == 0) {
+        r[0][threadIdx.x >> 6] = a; r[1][threadIdx.x >> 6] = b;
+        r[2][threadIdx.x >> 6] = c; r[3][threadIdx.x >> 6] = d;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < NWAVE; ++w) { a += r0[w]; b += r1[w]; }
-        part[2 * blockIdx.x] = a;
-        part[2 * blockIdx.x + 1] = b;
+        for (int w = 1; w < NWAVE; ++w) { a += r[0][w]; b += r[1][w]; c += r[2][w]; d += r[3][w]; }
+        part[4 * blockIdx.x] = a;
+        part[4 * blockIdx.x + 1] = b;
+        part[4 * blockIdx.x + 2] = c;
+        part[4 * blockIdx.x + 3] = d;
+    }
+}
+
+// Largest |u[p] - v[p]| over n values (per workgroup; exact in FP32).
+__global__ void k_maxdiff(const float *__restrict__ u, const float *__restrict__ v, long n,
+                          float *__restrict__ part)
+{
+    __shared__ float r[NWAVE];
+    float m = 0.0f;
+    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < n;
+         p += (long)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(u[p] - v[p]));
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_down(m, off));
+    if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < NWAVE; ++w) m = fmaxf(m, r[w]);
+        part[blockIdx.x] = m;
+    }
+}
+
+// Gather of images idx[0..nb) of a planar set [npairs][c][npix] into [nb][c][npix].
+__global__ void k_gather(const float *__restrict__ src, const int *__restrict__ idx, int nb, int c,
+                         long npix, float *__restrict__ dst)
+{
+    const long per = (long)c * npix, total = per * nb;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < total;
+         q += (long)gridDim.x * blockDim.x) {
+        const long i = q / per, r = q - i * per;
+        dst[q] = src[(long)idx[i] * per + r];
     }
 }
 
@@ -613,7 +682,7 @@ Scratch layout(const sws_net *n, long npix, char *base)
     s.ga = (unsigned short *)take((size_t)npix * MAXW * 2);
     s.gb = (unsigned short *)take((size_t)npix * MAXW * 2);
     s.dwpart = (float *)take((size_t)DW_GRID * (MAXW * MAXW * 9 + MAXW) * sizeof(float));
-    s.red = (double *)take((size_t)2 * RED_GRID * sizeof(double));
+    s.red = (double *)take((size_t)4 * RED_GRID * sizeof(double));
     s.bytes = off;
     return s;
 }
@@ -841,7 +910,7 @@ int compute_grads(sws_net *n, const float *x, const float *target, int32_t nimg,
     for (int l = L - 1; l >= 0; --l) {
         // weight and bias gradients of layer l from dz_l (gcur) and its input act[l]
         const int cin = n->ch[l], cout = n->ch[l + 1];
-        hipLaunchKernelGGL(k_dw, dim3(DW_GRID), dim3(NT), 0, n->stream, s.act[l], stored(cin), cin,
+        hipLaunchKernelGGL(k_dw, dim3(DW_GRID), dim3(DWT), 0, n->stream, s.act[l], stored(cin), cin,
                            gcur, cs_out, cout, nimg, nx, ny, s.dwpart);
         const int len = cout * cin * 9 + cout;
         hipLaunchKernelGGL(k_dw_sum, dim3(grid_for(len)), dim3(NT), 0, n->stream, s.dwpart, DW_GRID,
@@ -897,53 +966,185 @@ int sws_advance(sws_net *n, sw_ctx *solver, int32_t k, double dt, double max_dri
 {
     if (!n || !solver || k < 1 || !(dt > 0.0) || !(max_drift >= 0.0)) return SW_ERR_ARG;
     if (used) *used = 0;
+    sws_stats st{};
+    int rc = sws_advance_K(n, solver, 1, k, dt, max_drift, 0, 0.0, &st);
+    if (!rc && used) *used = st.kept;
+    return rc;
+}
+
+int sws_advance_K(sws_net *n, sw_ctx *solver, int32_t n_calls, int32_t k, double dt,
+                  double max_drift, int32_t check_every, double max_err, sws_stats *stats)
+{
+    if (!n || !solver || n_calls < 0 || k < 1 || !(dt > 0.0) || !(max_drift >= 0.0) ||
+        check_every < 0 || !(max_err >= 0.0))
+        return SW_ERR_ARG;
+    sws_stats st{};
     if (!n->packed) {
         int rc = pack_all(n);
         if (rc) return rc;
     }
     sw_grid gr;
-    sw_sums sums;
     int rc = sw_get_grid(solver, &gr);
-    if (!rc) rc = sw_get_sums(solver, &sums);
     if (rc) return sfail(n, rc, std::string("solver: ") + sw_last_error(solver));
     const int nx = gr.nx, ny = gr.ny;
     const long npix = (long)nx * ny;
     const size_t fbytes = (size_t)npix * 4 * sizeof(float);
-    const size_t need = layout(n, npix, nullptr).bytes + 2 * fbytes;
+    const size_t need = layout(n, npix, nullptr).bytes + 3 * fbytes;
     if ((rc = ensure_scratch(n, need))) return rc;
     Scratch s = layout(n, npix, (char *)n->scratch);
-    float *f0 = (float *)((char *)n->scratch + s.bytes);
-    float *f1 = (float *)((char *)f0 + fbytes);
-    // the solver's fields (on its stream), then the network on ours
-    rc = sw_get_fields(solver, f0, f0 + npix, f0 + 2 * npix, f0 + 3 * npix, SW_PTR_DEVICE);
-    if (!rc) rc = sw_sync(solver);
-    if (rc) return sfail(n, rc, std::string("solver: ") + sw_last_error(solver));
+    float *f0 = (float *)((char *)n->scratch + s.bytes);   // the solver's state
+    float *f1 = (float *)((char *)f0 + fbytes);            // the prediction
+    float *f2 = (float *)((char *)f1 + fbytes);            // the plain steps (checks)
     const float *is = n->in_scale, *os = n->out_scale;
-    hipLaunchKernelGGL(k_inputs, dim3(grid_for(npix)), dim3(NT), 0, n->stream, f0, npix, is[0],
-                       is[1], is[2], is[3], is[4], s.act[0]);
-    if ((rc = forward_into(n, s, 1, nx, ny))) return rc;
-    hipLaunchKernelGGL(k_apply, dim3(RED_GRID), dim3(NT), 0, n->stream, f0, s.out, npix, os[0], os[1],
-                       os[2], os[3], f1, s.red);
-    SHIP(n, hipGetLastError());
-    std::vector<double> part(2 * RED_GRID);
-    if ((rc = copy_out(n, part.data(), s.red, part.size() * sizeof(double), SW_PTR_HOST))) return rc;
-    double v0 = 0.0, v1 = 0.0;
-    for (int b = 0; b < RED_GRID; ++b) {
-        v0 += part[2 * b];
-        v1 += part[2 * b + 1];
-    }
-    const double drift = v0 > 0.0 ? std::fabs(v1 - v0) / v0 : (v1 > 0.0 ? INFINITY : 0.0);
-    if (drift <= max_drift) {
-        rc = sw_replace_state(solver, f1, f1 + npix, f1 + 2 * npix, f1 + 3 * npix, sums.t + k * dt,
-                              sums.step + k);
+    for (int32_t call = 0; call < n_calls; ++call) {
+        sw_sums sums;
+        rc = sw_get_sums(solver, &sums);
+        if (!rc) rc = sw_get_fields(solver, f0, f0 + npix, f0 + 2 * npix, f0 + 3 * npix, SW_PTR_DEVICE);
+        if (!rc) rc = sw_sync(solver);
         if (rc) return sfail(n, rc, std::string("solver: ") + sw_last_error(solver));
-        if (used) *used = 1;
-        return SW_OK;
+        hipLaunchKernelGGL(k_inputs, dim3(grid_for(npix)), dim3(NT), 0, n->stream, f0, npix, is[0],
+                           is[1], is[2], is[3], is[4], s.act[0]);
+        if ((rc = forward_into(n, s, 1, nx, ny))) return rc;
+        hipLaunchKernelGGL(k_apply, dim3(RED_GRID), dim3(NT), 0, n->stream, f0, s.out, npix, os[0],
+                           os[1], os[2], os[3], f1, s.red);
+        SHIP(n, hipGetLastError());
+        std::vector<double> part(4 * RED_GRID);
+        if ((rc = copy_out(n, part.data(), s.red, part.size() * sizeof(double), SW_PTR_HOST))) return rc;
+        double v0 = 0.0, v1 = 0.0, b0 = 0.0, b1 = 0.0;
+        for (int q = 0; q < RED_GRID; ++q) {  // fixed order
+            v0 += part[4 * q];
+            v1 += part[4 * q + 1];
+            b0 += part[4 * q + 2];
+            b1 += part[4 * q + 3];
+        }
+        // conservation: water volume, and the bed (sediment) volume, of a
+        // closed domain without sources must not change
+        const double drift = v0 > 0.0 ? std::fabs(v1 - v0) / v0 : (v1 > 0.0 ? INFINITY : 0.0);
+        const double bdrift = std::fabs(b1 - b0) / std::max(std::fabs(b0), 1e-30);
+        st.calls++;
+        st.max_volume_drift = std::max(st.max_volume_drift, std::max(drift, bdrift));
+        const double t1 = sums.t + k * dt;
+        const int64_t step1 = sums.step + k;
+        if (drift > max_drift || bdrift > max_drift) {
+            st.fallbacks_volume++;
+            rc = sw_advance_fixed_dt(solver, k, dt);
+            if (!rc) rc = sw_sync(solver);
+            if (rc) return sfail(n, rc, std::string("solver: ") + sw_last_error(solver));
+            continue;
+        }
+        if (check_every > 0 && call % check_every == 0) {
+            // the plain step judges the prediction: the same k steps from the
+            // same state, compared in depth
+            st.checks++;
+            rc = sw_advance_fixed_dt(solver, k, dt);
+            if (!rc) rc = sw_get_fields(solver, f2, nullptr, nullptr, nullptr, SW_PTR_DEVICE);
+            if (rc) return sfail(n, rc, std::string("solver: ") + sw_last_error(solver));
+            hipLaunchKernelGGL(k_maxdiff, dim3(RED_GRID), dim3(NT), 0, n->stream, f1, f2, npix,
+                               (float *)s.red);
+            SHIP(n, hipGetLastError());
+            std::vector<float> mx(RED_GRID);
+            if ((rc = copy_out(n, mx.data(), s.red, RED_GRID * sizeof(float), SW_PTR_HOST))) return rc;
+            float e = 0.0f;
+            for (float v : mx) e = std::max(e, v);
+            st.max_residual = std::max(st.max_residual, (double)e);
+            if (!(e <= max_err)) {  // keep the plain result the solver already holds
+                st.fallbacks_residual++;
+                continue;
+            }
+        }
+        rc = sw_replace_state(solver, f1, f1 + npix, f1 + 2 * npix, f1 + 3 * npix, t1, step1);
+        if (rc) return sfail(n, rc, std::string("solver: ") + sw_last_error(solver));
+        st.kept++;
     }
-    rc = sw_advance_fixed_dt(solver, k, dt);
-    if (!rc) rc = sw_sync(solver);
-    if (rc) return sfail(n, rc, std::string("solver: ") + sw_last_error(solver));
+    if (stats) *stats = st;
     return SW_OK;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): the minibatch draws of sws_train.
+static uint64_t splitmix64(uint64_t &state)
+{
+    uint64_t z = (state += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+int sws_train(sws_net *n, const float *x, const float *target, int32_t npairs, int32_t nx,
+              int32_t ny, const sws_train_cfg *cfg, sws_train_report *report, float *losses,
+              int ptr_kind)
+{
+    if (!n || !x || !target || !cfg || npairs < 1 || nx < 1 || ny < 1) return SW_ERR_ARG;
+    if (cfg->steps < 1 || cfg->batch < 1 || cfg->batch > npairs || !(cfg->lr > 0.0f))
+        return sfail(n, SW_ERR_ARG, "steps >= 1, 1 <= batch <= npairs and lr > 0 are required");
+    const long npix = (long)nx * ny;
+    const size_t xb = (size_t)npairs * 5 * npix * sizeof(float);
+    const size_t tb = (size_t)npairs * 4 * npix * sizeof(float);
+    const size_t bx = (size_t)cfg->batch * 5 * npix * sizeof(float);
+    const size_t bt = (size_t)cfg->batch * 4 * npix * sizeof(float);
+    // the whole set resides on the device; each step gathers its minibatch
+    char *set = nullptr;
+    int *didx = nullptr;
+    SHIP(n, hipMalloc(&set, xb + tb + bx + bt));
+    if (hipMalloc(&didx, cfg->batch * sizeof(int)) != hipSuccess) {
+        (void)hipFree(set);
+        return sfail(n, SW_ERR_HIP, "hipMalloc(minibatch indices)");
+    }
+    float *dx = (float *)set, *dt = (float *)(set + xb);
+    float *gx = (float *)(set + xb + tb), *gt = (float *)(set + xb + tb + bx);
+    auto done = [&](int rc) {
+        (void)hipStreamSynchronize(n->stream);
+        (void)hipFree(set);
+        (void)hipFree(didx);
+        return rc;
+    };
+    int rc = copy_in(n, dx, x, xb, ptr_kind);
+    if (!rc) rc = copy_in(n, dt, target, tb, ptr_kind);
+    if (rc) return done(rc);
+    uint64_t state = cfg->seed;
+    std::vector<int> perm(npairs), pick(cfg->batch);
+    double first = 0.0, tail = 0.0;
+    const int ntail = std::min(50, (int)cfg->steps);
+    int *hidx = nullptr;
+    if (hipHostMalloc((void **)&hidx, cfg->batch * sizeof(int), hipHostMallocDefault) != hipSuccess)
+        return done(sfail(n, SW_ERR_HIP, "hipHostMalloc(minibatch indices)"));
+    for (int32_t it = 0; it < cfg->steps && !rc; ++it) {
+        // batch distinct pairs: a partial Fisher-Yates shuffle
+        for (int i = 0; i < npairs; ++i) perm[i] = i;
+        for (int i = 0; i < cfg->batch; ++i) {
+            const int j = i + (int)(splitmix64(state) % (uint64_t)(npairs - i));
+            std::swap(perm[i], perm[j]);
+            hidx[i] = perm[i];
+        }
+        if (hipMemcpyAsync(didx, hidx, cfg->batch * sizeof(int), hipMemcpyHostToDevice, n->stream) !=
+            hipSuccess) {
+            rc = sfail(n, SW_ERR_HIP, "index upload");
+            break;
+        }
+        hipLaunchKernelGGL(k_gather, dim3(grid_for((long)cfg->batch * 5 * npix)), dim3(NT), 0,
+                           n->stream, dx, didx, cfg->batch, 5, npix, gx);
+        hipLaunchKernelGGL(k_gather, dim3(grid_for((long)cfg->batch * 4 * npix)), dim3(NT), 0,
+                           n->stream, dt, didx, cfg->batch, 4, npix, gt);
+        // cosine decay of the learning rate to 0 over the steps
+        const float lr = (float)(cfg->lr * 0.5 * (1.0 + std::cos(M_PI * it / cfg->steps)));
+        const bool want = losses || it == 0 || it >= cfg->steps - ntail;
+        double loss = 0.0;
+        rc = sws_train_step(n, gx, gt, cfg->batch, nx, ny, lr, want ? &loss : nullptr, SW_PTR_DEVICE);
+        // the indices buffer is rewritten next step: wait for its use
+        if (!rc && !want && hipStreamSynchronize(n->stream) != hipSuccess)
+            rc = sfail(n, SW_ERR_HIP, "hipStreamSynchronize");
+        if (rc) break;
+        if (losses) losses[it] = (float)loss;
+        if (it == 0) first = loss;
+        if (it >= cfg->steps - ntail) tail += loss;
+    }
+    (void)hipStreamSynchronize(n->stream);
+    (void)hipHostFree(hidx);
+    if (!rc && report) {
+        report->first_loss = first;
+        report->final_loss = tail / ntail;
+        report->steps = cfg->steps;
+    }
+    return done(rc);
 }
 
 const char *sws_last_error(const sws_net *n) { return n ? n->err.c_str() : "null net"; }

@@ -1,9 +1,9 @@
 """Training and evaluation of the convolutional surrogate on solver trajectories.
 
-Everything numerical runs in the library's kernels: the trajectories come
-from the solver (fixed step), the network's forward, backward and Adam steps
-from `sws_train_step`, the surrogate step from `sws_advance`.  This module
-only assembles arrays (sampling pairs, per-channel scales) and loops.
+Everything numerical runs in the library: the trajectories come from the
+solver (fixed step), training from `sws_train` (forward, backward and Adam
+kernels), the surrogate step with its checks from `sws_advance_K`.  This
+module only assembles arrays (sampling pairs, per-channel scales).
 
 A training pair is (state at step n, change of (h, hu, hv, b) over the next k
 steps).  Network inputs are x = in_scale * (h, hu, hv, b, wet mask); its
@@ -94,19 +94,16 @@ def he_init(channels, seed):
 
 
 def train(net, p: Pairs, in_s, out_s, steps, batch, lr, seed=0, log=None):
+    """Scale the pairs and run the library's training loop (sws_train: Adam,
+    cosine learning-rate decay, minibatches drawn on the host side of the
+    library).  Returns the per-step losses."""
     net.set_scales(in_s, out_s)
     x = p.x * in_s[None, :, None, None]
     t = p.d / out_s[None, :, None, None]
-    rng = np.random.default_rng(seed)
-    losses = []
-    for it in range(steps):
-        idx = rng.choice(len(x), size=min(batch, len(x)), replace=False)
-        # cosine decay of the learning rate
-        lr_t = lr * 0.5 * (1.0 + math.cos(math.pi * it / steps))
-        losses.append(net.train_step(x[idx], t[idx], lr_t))
-        if log and (it % 100 == 0 or it == steps - 1):
-            log(f"train step {it}: loss {losses[-1]:.4e}")
-    return losses
+    rep, losses = net.train(x, t, steps, batch, lr, seed=seed, keep_losses=True)
+    if log:
+        log(f"trained {steps} steps: loss {rep['first_loss']:.4e} -> {rep['final_loss']:.4e}")
+    return list(losses)
 
 
 def evaluate(net, p: Pairs, in_s, out_s):
@@ -121,32 +118,36 @@ def evaluate(net, p: Pairs, in_s, out_s):
     return err, drift
 
 
-def measure_gain(net, w, dt, calls, k=8, max_drift=1e-5, stream=None):
-    """Effective rate of the surrogate step (k steps per call, fall backs
-    included) against the plain solver's k fixed steps, both in grid cells x
-    steps per second.  Every call starts from the same initial state (the
-    reset is not timed), so one bad prediction cannot spoil the next call."""
+def measure_gain(net, w, dt, calls, k=8, max_drift=1e-5, check_every=4, max_err=5e-3,
+                 stream=None):
+    """Effective rate of the surrogate step (sws_advance_K: k steps per call,
+    the conservation check every call and the plain step judging every
+    check_every-th call, fall backs included) against the plain solver's k
+    fixed steps over the same model time, both in grid cells x steps per
+    second, from the same initial state; graphs and set-up are done before
+    either timing."""
     import torch
     s = csph.solver_for(w, stream=stream)
-    used, t_sur, t_plain = 0, 0.0, 0.0
-    for _ in range(calls):
-        s.reset(w)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        used += int(net.advance(s, k, dt, max_drift))
-        torch.cuda.synchronize()
-        t_sur += time.perf_counter() - t0
-    for it in range(calls + 1):
-        s.reset(w)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.advance(k, dt=dt)
-        s.sync()
-        if it:  # the first run builds the step graph
-            t_plain += time.perf_counter() - t0
+    s.advance(k, dt=dt)  # the step graphs are built here
+    s.reset(w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = net.advance_k(s, calls, k, dt, max_drift, check_every, max_err)
+    torch.cuda.synchronize()
+    t_sur = time.perf_counter() - t0
+    s.reset(w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.advance(calls * k, dt=dt)
+    s.sync()
+    t_plain = time.perf_counter() - t0
     s.close()
     cells = w.nx * w.ny * k * calls
     return {"grid": [w.nx, w.ny], "k": k, "calls": calls, "max_drift": max_drift,
+            "check_every": check_every, "max_err_m": max_err,
             "surrogate_gcell_steps_s": round(cells / t_sur / 1e9, 3),
             "plain_gcell_steps_s": round(cells / t_plain / 1e9, 3),
-            "kept": used, "fallback_rate": round(1.0 - used / calls, 4)}
+            "kept": stats["kept"], "fallbacks_volume": stats["fallbacks_volume"],
+            "fallbacks_residual": stats["fallbacks_residual"], "checks": stats["checks"],
+            "max_residual_m": round(stats["max_residual"], 6),
+            "fallback_rate": round(1.0 - stats["kept"] / calls, 4)}

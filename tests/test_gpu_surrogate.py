@@ -1,6 +1,7 @@
-"""The surrogate's kernels (BF16 matrix-core convolutions, FP32 weight
-gradients and Adam) against the FP64 oracle of the network, and its solver
-step (mass check, plain fall back) against the solver itself."""
+"""The surrogate's kernels (BF16 matrix-core convolutions and weight
+gradients, FP32 Adam) against the FP64 oracle of the network, its training
+loop, and its solver step (conservation and residual checks, plain fall
+back) against the solver itself."""
 import numpy as np
 import pytest
 
@@ -181,7 +182,8 @@ def test_gpu_surrogate_step_keeps_or_falls_back():
 
 def test_gpu_surrogate_training_driver_end_to_end():
     """Trajectories from the solver, a short training run, held-out error and
-    volume change, and the gain measurement (every call restarted)."""
+    volume change, and the gain measurement (conservation and residual
+    checks, fall backs included)."""
     import torch
     from paper_2103_15196_amd import csph, surrogate as SG
     st = torch.cuda.current_stream().cuda_stream
@@ -205,3 +207,59 @@ def test_gpu_surrogate_training_driver_end_to_end():
     say(f"end to end: training-set loss {before:.3f} -> {after:.3f}; held-out max err {err.max():.3e}; {res}")
     assert res["calls"] == 2 and 0.0 <= res["fallback_rate"] <= 1.0
     net.close()
+
+
+def test_gpu_surrogate_plain_step_judges_the_prediction():
+    """sws_advance_K with the residual check on every call: a network that
+    predicts no change keeps a still lake (residual 0) but is overruled on a
+    dam break, where the solver's own k steps are kept (the final state is the
+    plain run's, bit for bit)."""
+    from paper_2103_15196_amd import csph
+    import torch
+    st = torch.cuda.current_stream().cuda_stream
+    net = csph.Surrogate((5, 16, 4), stream=st)
+    net.set_params(np.zeros(net.nparam, np.float32))
+    lake = W.lake_at_rest(64, 48, bc=(0, 0, 0, 0)).as_float32()
+    s = csph.solver_for(lake, stream=st)
+    stats = net.advance_k(s, 3, 8, 0.05, check_every=1, max_err=5e-3)
+    say(f"lake: {stats}")
+    assert stats["kept"] == 3 and stats["checks"] == 3 and stats["max_residual"] == 0.0
+    assert np.array_equal(s.get_fields()[0], np.asarray(lake.H, np.float32))
+    s.close()
+    w = _closed_basin()
+    dt = 0.02
+    s = csph.solver_for(w, stream=st)
+    stats = net.advance_k(s, 3, 8, dt, check_every=1, max_err=5e-3)
+    say(f"dam break: {stats}")
+    assert stats["kept"] == 0 and stats["fallbacks_residual"] == 3 and stats["max_residual"] > 5e-3
+    r = csph.solver_for(w, stream=st)
+    r.advance(24, dt=dt)
+    for a, c in zip(s.get_fields(), r.get_fields()):
+        assert np.array_equal(a, c)
+    assert s.get_sums()["t"] == pytest.approx(24 * dt, rel=1e-12)
+    s.close()
+    r.close()
+    net.close()
+
+
+def test_gpu_surrogate_training_loop_is_deterministic_and_learns():
+    """sws_train (minibatches from a seed, cosine learning rate) lowers the
+    loss, reports it, and repeats bit for bit from the same seed."""
+    from paper_2103_15196_amd import csph, surrogate as SG
+    import torch
+    st = torch.cuda.current_stream().cuda_stream
+    tr = SG.collect([5000, 5001, 5002], n=48, steps=32, k=8, stream=st)
+    ins, outs = SG.scales(tr)
+    x = tr.x * ins[None, :, None, None]
+    t = tr.d / outs[None, :, None, None]
+    params = []
+    for _ in range(2):
+        net = csph.Surrogate((5, 16, 16, 4), stream=st)
+        net.set_params(SG.he_init((5, 16, 16, 4), 3))
+        net.set_scales(ins, outs)
+        rep, losses = net.train(x, t, 150, 4, 3e-3, seed=11, keep_losses=True)
+        assert rep["final_loss"] < 0.8 * rep["first_loss"]
+        assert rep["first_loss"] == pytest.approx(float(losses[0]), rel=1e-6)
+        params.append(net.get_params())
+        net.close()
+    assert np.array_equal(params[0], params[1])
