@@ -685,13 +685,18 @@ __device__ __forceinline__ CellNew cell_update(const KPar &P, float dt, const Ce
     if (Hn < 0.0f) Hn = 0.0f;
     o.ab = 0.0f;
     if (beta > 0.0f) {
-        const float a = 1.0f + beta * dt;
-        const float Ha = ndiv(Hn, a);
+        // 1 / (1 + beta dt) = 1 - f with the absorbed fraction f formed
+        // directly, so the quotient's rounding does not sit in the small
+        // difference H - H / (1 + beta dt); the absorbed depth is then that
+        // difference taken exactly (the two depths are within a factor 2)
+        const float bd = beta * dt;
+        const float f = ndiv(bd, 1.0f + bd);
+        const float Ha = fmaf(-Hn, f, Hn);
         o.ab = Hn - Ha;
         Hn = Ha;
-        qxn = ndiv(qxn, a);
-        qyn = ndiv(qyn, a);
-        rh = ndiv(rh, a);
+        qxn = fmaf(-qxn, f, qxn);
+        qyn = fmaf(-qyn, f, qyn);
+        rh = fmaf(-rh, f, rh);
     }
     if (Hn < P.eps) {
         float sc = Hn * wdes(Hn, P);
@@ -1724,9 +1729,13 @@ __device__ __forceinline__ int xcd_entry(int b, int wave, int n)
 //   XP = 1: w = blockIdx.x * SWAVES + wave of a single grid whose stage grid
 //           has a wavefront per possible entry; spread over the XCDs once the
 //           list length is known;
-//   XP = 2: as 1, for grids with more tiles than kMaxStageGroups workgroups
-//           hold: the grid's G4 = gridDim.x * SWAVES wavefronts take the list
-//           in passes of at most G4 entries, each pass spread over the XCDs.
+//   XP = 2: as 1, for grids with dry tiles skipped and more tiles than
+//           kMaxStageGroups workgroups hold: the grid's G4 = gridDim.x * SWAVES
+//           wavefronts take the list in passes of at most G4 entries, each
+//           pass spread over the XCDs;
+//   XP = 3: (Lagrangian stage) as 1 with one wavefront per tile, for grids of
+//           more tiles than that with every tile listed: they fill the chip
+//           without the halves' extra halo rows.
 // (XP = 2 is a kernel of its own: the pass loop costs the Euler kernel
 // registers, and with them a wavefront per SIMD, that XP = 1 keeps.)
 template <int S, bool CS, int XP>
@@ -1748,7 +1757,8 @@ __device__ __forceinline__ void lagrange_listed(const Inst &I, int par, int w)
     // XP = 1: LH wavefronts per listed tile, each on S / LH of its rows
     constexpr int LH = XP == 1 ? kLagHalves : 1;
     if (XP && I.hgs) n = list_locate(I.cnt_l, cl0, nb, 0, seg, start, nullptr);
-    if (XP == 1) w = __builtin_amdgcn_readfirstlane(xcd_entry(w / SWAVES, w % SWAVES, LH * n));
+    if (XP == 1 || XP == 3)
+        w = __builtin_amdgcn_readfirstlane(xcd_entry(w / SWAVES, w % SWAVES, LH * n));
     const int part = w % LH;
     w /= LH;
     if (XP != 2 && I.hgs) n = list_locate(I.cnt_l, cl0, nb, w, seg, start, nullptr);
@@ -2340,14 +2350,19 @@ template <int S>
 void launch_strip_t(Stage st, hipStream_t s, const Inst &I, int par, hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 gt(I.ntx, I.nty);
-    // one wavefront per possible entry, up to kMaxStageGroups workgroups (the
-    // stage kernels then take longer lists in passes)
+    // one wavefront per possible entry; with dry tiles skipped, at most
+    // kMaxStageGroups workgroups (the stage kernels then take longer lists in
+    // passes).  Without skipping every tile is listed, no workgroup idles and
+    // the single-pass kernels (fewer registers held across the pass loop)
+    // take the whole grid.
     const int need = (I.ntx * I.nty + SWAVES - 1) / SWAVES;
-    const bool passes = need > kMaxStageGroups;
+    const bool big = need > kMaxStageGroups;
+    const bool passes = I.hgs && big;
     const int gl = passes ? kMaxStageGroups : need;
-    const int gll = passes ? kMaxStageGroups : (kLagHalves * I.ntx * I.nty + SWAVES - 1) / SWAVES;
+    const int gll = passes || big ? gl : (kLagHalves * I.ntx * I.nty + SWAVES - 1) / SWAVES;
     const bool cs = cell_soil(I.P);
     auto lag = passes ? (cs ? k_lagrange_sl<S, true, 2> : k_lagrange_sl<S, false, 2>)
+               : big  ? (cs ? k_lagrange_sl<S, true, 3> : k_lagrange_sl<S, false, 3>)
                       : (cs ? k_lagrange_sl<S, true, 1> : k_lagrange_sl<S, false, 1>);
     auto eul = I.P.variant
                    ? (passes ? (cs ? k_euler_sl<S, true, 2, true> : k_euler_sl<S, false, 2, true>)

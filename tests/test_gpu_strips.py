@@ -95,11 +95,12 @@ def test_gpu_strips_tiny_grids():
 
 
 def test_gpu_strips_long_lists_take_several_passes():
-    """8192 x 2048 cells: 58 x 8 strips make 36352 tiles, more than the stage
-    grid's 8192 workgroups of 4 wavefronts hold, so the Lagrangian and Euler
-    kernels take their lists in two passes; 58 x 32 strips (4544 tiles) take
-    one.  Both give the bits of the 64 x 8 tiles, with every tile listed (no
-    dry-tile skipping) and with the lists of an all-wet grid."""
+    """8192 x 2048 cells: 58 x 8 strips make 36352 tiles.  With dry tiles
+    skipped that is more than the stage grid's 8192 workgroups of 4
+    wavefronts hold, so the Lagrangian and Euler kernels take their lists in
+    two passes; with every tile listed (no skipping) one grid covers them all;
+    58 x 32 strips (4544 tiles) take one pass either way.  All give the bits
+    of the 64 x 8 tiles."""
     from paper_2103_15196_amd import csph
     w = W.dam_break_fractal(n=8192, ny=2048, dx=2.0, seed=5, relief=10.0, depth=6.0).as_float32()
     wet = copy.deepcopy(w)
@@ -113,11 +114,12 @@ def test_gpu_strips_long_lists_take_several_passes():
 
 def test_gpu_strips_pass_kernels_with_per_cell_soil_vs_tiles_and_oracle():
     """The kernels the 8192^2 river valley runs: 58 x 8 strips on more than
-    32 Ki tiles (here 8192 x 2048: 36352 tiles, two passes) with per-cell
-    soil planes (Manning n, d50, psi), bed sources and an inflow hydrograph.
-    Every tile listed (skipping off) and dry tiles skipped give the bits of
-    the 64 x 8 LDS tiles; after 20 steps of an all-wet start every cell of
-    h, hu, hv, b agrees with the FP64 oracle within the precision bounds."""
+    32 Ki tiles (here 8192 x 2048: 36352 tiles; one grid of them with every
+    tile listed, two passes with dry tiles skipped) with per-cell soil planes
+    (Manning n, d50, psi), bed sources and an inflow hydrograph.  Both give
+    the bits of the 64 x 8 LDS tiles; after 20 steps of an all-wet start
+    every cell of h, hu, hv, b agrees with the FP64 oracle within the
+    precision bounds."""
     from paper_2103_15196_amd import csph
     from oracle import oracle as O
     from tests.gpu_common import field_check, run_oracle
@@ -134,7 +136,7 @@ def test_gpu_strips_pass_kernels_with_per_cell_soil_vs_tiles_and_oracle():
     say("river valley 8192x2048 per-cell soil: 64x8 tiles")
     ref = run_gpu(w, steps, shape=(64, 8))
     for flags in (csph.SW_FLAG_HGS, 0):
-        say(f"  58x8 strips (two passes), flags {flags}")
+        say(f"  58x8 strips, flags {flags}")
         _same(run_gpu(w, steps, flags=flags), ref, f"flags {flags}")
     say("  oracle")
     p, inp, st = run_oracle(O, w, steps)
