@@ -113,7 +113,8 @@ typedef struct {
     double water_source_in;    /* accumulated inflow volume */
     double sed_boundary_out;   /* accumulated outward boundary sediment volume */
     double sed_source_in;      /* accumulated (q_b^+ - q_b^-) dx^2 dt */
-    double vp, vs, D;          /* Eq. 7 maxima of the current state */
+    double vp, vs, D;          /* Eq. 7 maxima at the start of the last step (sw_step_bound
+                                  takes them over the current fields) */
     int64_t step;              /* step counter */
     int64_t wet_cells;         /* cells with h > 0 */
     int64_t active_tiles;      /* tiles the next step will not skip */
@@ -197,6 +198,14 @@ int sw_replace_state(sw_ctx *ctx, const float *h, const float *hu, const float *
 
 /* The grid the context was created with. */
 int sw_get_grid(const sw_ctx *ctx, sw_grid *out);
+
+/* The Eq. 7 step bound of the current fields: K min(h / (2 vp), h / vs,
+ * h^2 / (2 D)) with the cell size h = dx and the maxima vp, vs, D taken over
+ * the fields as the next step's K3 takes them, capped at dt_max.  A fixed step
+ * above it raises SW_ERR_CFL.  Synchronises; SW_ERR_STATE before
+ * sw_set_state, SW_ERR_NONFINITE if a field is not finite, a pending device
+ * error is returned as by sw_get_fields. */
+int sw_step_bound(sw_ctx *ctx, double *dt);
 
 /* Advance nsteps CSPH-TVD steps (Section 3 kernels K1..K8) with the Eq. 7
  * time step.  Asynchronous: errors raised on the device (SW_ERR_NONFINITE,

@@ -114,7 +114,10 @@ int sws_train(sws_net *net, const float *x, const float *target, int32_t npairs,
  *    sources); else the solver takes the k plain steps (fixed dt);
  *  - residual (every check_every-th call, 0 = never): the plain solver takes
  *    the same k steps from the same state and judges the prediction: if the
- *    largest depth difference exceeds max_err (m), the plain result is kept.
+ *    largest depth difference exceeds max_err (m), the plain result is kept;
+ *  - stability: the prediction must admit the step dt by Eq. 7
+ *    (sw_step_bound), so the solver can go on from it; else the state of the
+ *    call's start is restored and the solver takes the k plain steps.
  * The model time advances by k dt per call either way.  *stats (may be NULL)
  * receives the counts and the largest drift and residual seen.
  * Synchronises. */
@@ -126,6 +129,7 @@ typedef struct {
     int32_t checks;              /* calls the plain step judged */
     double max_volume_drift;     /* largest relative water or bed volume change predicted */
     double max_residual;         /* largest depth difference (m) at a check */
+    int32_t fallbacks_stability; /* predictions whose Eq. 7 step bound was below dt */
 } sws_stats;
 int sws_advance_K(sws_net *net, sw_ctx *solver, int32_t n_calls, int32_t k, double dt,
                   double max_drift, int32_t check_every, double max_err, sws_stats *stats);

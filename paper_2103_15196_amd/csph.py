@@ -90,6 +90,7 @@ SIGNATURES = [
     ("sw_sync", C.c_int, [_ctxp]),
     ("sw_get_fields", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     ("sw_get_sums", C.c_int, [_ctxp, C.POINTER(sw_sums)]),
+    ("sw_step_bound", C.c_int, [_ctxp, C.POINTER(C.c_double)]),
     ("sw_last_error", C.c_char_p, [_ctxp]),
     ("sw_save_begin", C.c_int, [_ctxp]),
     ("sw_save_wait", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -327,6 +328,12 @@ class Solver:
         _check(self.ctx, lib.sw_get_sums(self.ctx, C.byref(s)))
         return s.as_dict()
 
+    def step_bound(self) -> float:
+        """The Eq. 7 step bound of the current fields (sw_step_bound)."""
+        dt = C.c_double()
+        _check(self.ctx, lib.sw_step_bound(self.ctx, C.byref(dt)))
+        return dt.value
+
     def save_begin(self):
         """Start copying the current state to the host on a second stream."""
         _check(self.ctx, lib.sw_save_begin(self.ctx))
@@ -488,7 +495,8 @@ class sws_train_report(C.Structure):
 class sws_stats(C.Structure):
     _fields_ = [("calls", C.c_int32), ("kept", C.c_int32), ("fallbacks_volume", C.c_int32),
                 ("fallbacks_residual", C.c_int32), ("checks", C.c_int32),
-                ("max_volume_drift", C.c_double), ("max_residual", C.c_double)]
+                ("max_volume_drift", C.c_double), ("max_residual", C.c_double),
+                ("fallbacks_stability", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -147,6 +147,21 @@ __global__ void k_prepare(KPar P, Ctrl *ctrl, int k, const float *__restrict__ H
     block_maxima(mv, ms, mD, bad, ctrl->slot[k & 1], blockIdx.x + blockIdx.y * gridDim.x);
 }
 
+// Maxima of the current fields into the given slots (sw_step_bound): the
+// arithmetic of the set-up pass, without touching the step's own slots.
+__global__ void k_bound(KPar P, unsigned (*slot)[4], const float *__restrict__ H,
+                        const float *__restrict__ qx, const float *__restrict__ qy,
+                        const float *__restrict__ b)
+{
+    int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    unsigned mv = 0, ms = 0, mD = 0, bad = 0;
+    if (i < P.nx && j < P.ny) {
+        int c = j * P.pitch + i;
+        cell_maxima(P, H[c], qx[c], qy[c], b[c], c, mv, ms, mD, bad);
+    }
+    block_maxima(mv, ms, mD, bad, slot, blockIdx.x + blockIdx.y * gridDim.x);
+}
+
 // K3: time step of Eq. 7 from the maxima of step k's state; clears the slots
 // that step k's update fills for step k+1; advances the time ring.
 __global__ void k_dt(Ctrl *ctrl, int k, StepArgs A)
@@ -1980,6 +1995,7 @@ struct sw_ctx {
     int64_t step0 = 0;               // step counter offset (sw_set_time)
     double t0 = 0.0;                 // time at k = 0
     bool have_state = false, dirty = true;
+    unsigned *bound_slot = nullptr;  // NSLOT x 4 maxima of sw_step_bound
     int has_inflow = 0;
     double q_base = 0, q_peak = 0, t_peak = 0, t_sigma = 1;
     double qb_total = 0.0;
@@ -2721,6 +2737,7 @@ int sw_destroy(sw_ctx *c)
     (void)hipFree(c->bnd);
     (void)hipFree(c->part);
     (void)hipFree(c->ctrl);
+    (void)hipFree(c->bound_slot);
     (void)hipFree(c->nM);
     (void)hipFree(c->d50);
     (void)hipFree(c->psi);
@@ -3181,6 +3198,42 @@ int sw_get_fields(sw_ctx *c, float *h, float *hu, float *hv, float *b, int ptr_k
     if (b && (rc = download_plane(c, b, c->b[cur], ptr_kind))) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (hc.err) return fail(c, hc.err, "device error raised at step " + std::to_string(hc.err_k));
+    return SW_OK;
+}
+
+int sw_step_bound(sw_ctx *c, double *dt)
+{
+    if (!c || !dt) return SW_ERR_ARG;
+    if (!c->have_state) return fail(c, SW_ERR_STATE, "sw_step_bound before sw_set_state");
+    Ctrl hc;
+    int rc = read_ctrl(c, &hc);
+    if (rc) return rc;
+    if (hc.err) return fail(c, hc.err, "device error raised at step " + std::to_string(hc.err_k));
+    const int cur = current_buffer(c, hc);
+    const size_t bytes = NSLOT * 4 * sizeof(unsigned);
+    if (!c->bound_slot) HIPCHK(c, hipMalloc(&c->bound_slot, bytes));
+    HIPCHK(c, hipMemsetAsync(c->bound_slot, 0, bytes, c->stream));
+    KPar P = make_kpar(c);
+    hipLaunchKernelGGL(k_bound, cell_grid(c), dim3(BX, BY), 0, c->stream, P,
+                       (unsigned(*)[4])c->bound_slot, c->H[cur], c->qx[cur], c->qy[cur], c->b[cur]);
+    HIPCHK(c, hipGetLastError());
+    unsigned m[NSLOT][4];
+    if ((rc = stage_to_host(c, m, c->bound_slot, bytes))) return rc;
+    unsigned a = 0, b = 0, d = 0, bad = 0;
+    for (int q = 0; q < NSLOT; ++q) {
+        a = std::max(a, m[q][0]); b = std::max(b, m[q][1]); d = std::max(d, m[q][2]);
+        bad = std::max(bad, m[q][3]);
+    }
+    if (bad) return fail(c, SW_ERR_NONFINITE, "sw_step_bound: a field is not finite");
+    float fa, fb, fd;
+    std::memcpy(&fa, &a, 4); std::memcpy(&fb, &b, 4); std::memcpy(&fd, &d, 4);
+    // the K3 reading of Eq. 7 (cell size h = dx), capped at dt_max
+    const double h = c->grid.dx, vp = fa, vs = fb, D = fd;
+    const double t0 = vp > 0.0 ? h / (2.0 * vp) : INFINITY;
+    const double t1 = vs > 0.0 ? h / vs : INFINITY;
+    const double t2 = D > 0.0 ? h * h / (2.0 * D) : INFINITY;
+    const double bound = c->par.cfl * std::min(t0, std::min(t1, t2));
+    *dt = bound < c->par.dt_max ? bound : c->par.dt_max;
     return SW_OK;
 }
 

@@ -1053,7 +1053,20 @@ int sws_advance_K(sws_net *n, sw_ctx *solver, int32_t n_calls, int32_t k, double
             }
         }
         rc = sw_replace_state(solver, f1, f1 + npix, f1 + 2 * npix, f1 + 3 * npix, t1, step1);
-        if (rc) return sfail(n, rc, std::string("solver: ") + sw_last_error(solver));
+        double bound = 0.0;
+        if (!rc) rc = sw_step_bound(solver, &bound);
+        if (rc && rc != SW_ERR_NONFINITE) return sfail(n, rc, std::string("solver: ") + sw_last_error(solver));
+        if (rc || !(dt <= bound)) {
+            // the solver could not take its step from the prediction: back
+            // to the call's start, and the k plain steps
+            st.fallbacks_stability++;
+            rc = sw_replace_state(solver, f0, f0 + npix, f0 + 2 * npix, f0 + 3 * npix, sums.t,
+                                  sums.step);
+            if (!rc) rc = sw_advance_fixed_dt(solver, k, dt);
+            if (!rc) rc = sw_sync(solver);
+            if (rc) return sfail(n, rc, std::string("solver: ") + sw_last_error(solver));
+            continue;
+        }
         st.kept++;
     }
     if (stats) *stats = st;

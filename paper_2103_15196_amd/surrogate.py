@@ -121,8 +121,8 @@ def evaluate(net, p: Pairs, in_s, out_s):
 def measure_gain(net, w, dt, calls, k=8, max_drift=1e-5, check_every=4, max_err=5e-3,
                  stream=None):
     """Effective rate of the surrogate step (sws_advance_K: k steps per call,
-    the conservation check every call and the plain step judging every
-    check_every-th call, fall backs included) against the plain solver's k
+    the conservation and stability checks every call and the plain step
+    judging every check_every-th call, fall backs included) against the plain solver's k
     fixed steps over the same model time, both in grid cells x steps per
     second, from the same initial state; graphs and set-up are done before
     either timing."""
@@ -148,6 +148,7 @@ def measure_gain(net, w, dt, calls, k=8, max_drift=1e-5, check_every=4, max_err=
             "surrogate_gcell_steps_s": round(cells / t_sur / 1e9, 3),
             "plain_gcell_steps_s": round(cells / t_plain / 1e9, 3),
             "kept": stats["kept"], "fallbacks_volume": stats["fallbacks_volume"],
-            "fallbacks_residual": stats["fallbacks_residual"], "checks": stats["checks"],
+            "fallbacks_residual": stats["fallbacks_residual"],
+            "fallbacks_stability": stats["fallbacks_stability"], "checks": stats["checks"],
             "max_residual_m": round(stats["max_residual"], 6),
             "fallback_rate": round(1.0 - stats["kept"] / calls, 4)}

@@ -163,3 +163,43 @@ def test_gpu_async_save_snapshots_the_state_while_steps_go_on():
         assert np.array_equal(x, y)
     a.close()
     ref.close()
+
+
+def test_gpu_step_bound_is_the_next_steps_eq7_step():
+    """sw_step_bound takes the Eq. 7 maxima over the current fields as the
+    next step's K3 takes them: on a fresh all-wet river valley and again 60
+    steps later it equals the step the solver then takes; a fixed step equal
+    to it runs, one a millionth above it raises SW_ERR_CFL on the device; a
+    NaN in the fields is SW_ERR_NONFINITE."""
+    import torch
+    from paper_2103_15196_amd import csph
+    w = _small_valley()
+    w.H = np.full((w.ny, w.nx), 0.5)
+    w = w.as_float32()
+    s = csph.solver_for(w, stream=torch_stream())
+    for n in (0, 60):
+        if n:
+            s.advance(n)
+        bound = s.step_bound()
+        s.advance(1)
+        last = s.get_sums()["last_dt"]
+        say(f"after {n} steps: bound {bound!r}, step taken {last!r}")
+        assert last == bound
+    bound = s.step_bound()
+    s.advance(1, dt=bound)
+    s.sync()
+    bound = s.step_bound()
+    s.advance(1, dt=bound * (1.0 + 1e-6))
+    with pytest.raises(csph.SwError) as e:
+        s.sync()
+    assert e.value.code == csph.SW_ERR_CFL
+    s.reset(w)
+    dev = torch.device("cuda:0")
+    t = [torch.tensor(x, dtype=torch.float32, device=dev).contiguous() for x in s.get_fields()]
+    t[2][10, 12] = float("nan")
+    assert csph.lib.sw_replace_state(s.ctx, t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr(),
+                                     t[3].data_ptr(), 0.0, 0) == csph.SW_OK
+    with pytest.raises(csph.SwError) as e:
+        s.step_bound()
+    assert e.value.code == csph.SW_ERR_NONFINITE
+    s.close()

@@ -242,6 +242,36 @@ def test_gpu_surrogate_plain_step_judges_the_prediction():
     net.close()
 
 
+def test_gpu_surrogate_unstable_prediction_falls_back():
+    """A prediction that keeps the water and bed volumes but carries momentum
+    the solver's Eq. 7 step cannot take (+1000 m^2/s of hu on every cell) is
+    not kept: the call's start is restored and the plain steps are taken, so
+    the final state is the plain run's, bit for bit."""
+    from paper_2103_15196_amd import csph
+    import torch
+    st = torch.cuda.current_stream().cuda_stream
+    net = csph.Surrogate((5, 16, 4), stream=st)
+    p = np.zeros(net.nparam, np.float32)
+    p[16 * 5 * 9 + 16 + 4 * 16 * 9 + 1] = 1.0  # bias of the hu output
+    net.set_params(p)
+    net.set_scales(np.ones(5, np.float32), np.array([0.0, 1000.0, 0.0, 0.0], np.float32))
+    lake = W.lake_at_rest(64, 48, bc=(0, 0, 0, 0)).as_float32()
+    dt = 0.05
+    s = csph.solver_for(lake, stream=st)
+    stats = net.advance_k(s, 3, 8, dt, check_every=0)
+    say(f"unstable: {stats}")
+    assert stats["kept"] == 0 and stats["fallbacks_stability"] == 3
+    assert stats["fallbacks_volume"] == 0 and stats["max_volume_drift"] == 0.0
+    r = csph.solver_for(lake, stream=st)
+    r.advance(24, dt=dt)
+    for a, c in zip(s.get_fields(), r.get_fields()):
+        assert np.array_equal(a, c)
+    assert s.get_sums()["t"] == pytest.approx(24 * dt, rel=1e-12)
+    s.close()
+    r.close()
+    net.close()
+
+
 def test_gpu_surrogate_training_loop_is_deterministic_and_learns():
     """sws_train (minibatches from a seed, cosine learning rate) lowers the
     loss, reports it, and repeats bit for bit from the same seed."""
