@@ -40,6 +40,57 @@ def basin(n, seed, depth, relief=10.0, dx=2.0):
     return w
 
 
+def valley_basin(n, seed, depth, dx=5.0):
+    """A closed basin on the terrain of the large river valley (fractal relief
+    on a regional slope, a meandering carved channel, per-cell d50 and psi,
+    Eq. 4 bedload; meander amplitude min(600 m, a quarter of the side)),
+    walls on every side and no inflow: the upstream quarter holds a reservoir
+    whose flat surface lies `depth` above the lowest twentieth of its bed (the
+    channel), released at t = 0 down the channel and over its banks.  The
+    water volume cannot change."""
+    side = n * dx
+    w = W.river_valley(n=n, dx=dx, seed=seed, amplitude=min(600.0, 0.25 * side))
+    w.bc = (W.WALL, W.WALL, W.WALL, W.WALL)
+    w.inflow_idx, w.inflow_w, w.Q_base, w.Q_peak = None, None, 0.0, 0.0
+    q = n // 4
+    level = float(np.quantile(w.b[:, :q], 0.05)) + depth
+    H = np.zeros_like(w.b)
+    H[:, :q] = np.maximum(0.0, level - w.b[:, :q])
+    w.H = H
+    w.name = f"valley_basin_{n}_{seed}"
+    return w.as_float32()
+
+
+# fixed step of the valley basins (dx = 5 m, reservoir depths up to about
+# 8 m): below their Eq. 7 bound (K = 0.3) while |v| < 2 sqrt(g H_max)
+VALLEY_DT = 0.03
+
+
+def collect_valley(seeds, n, steps, k, stream=None, depth_range=(1.5, 4.0), spinup=(0, 600)):
+    """Pairs from valley basins: each seed draws its reservoir depth and a
+    spin-up of fixed steps (so the pairs cover the flood wave at different
+    stages), then records steps // k consecutive pairs."""
+    xs, ds, dts = [], [], []
+    for sd in seeds:
+        rng = np.random.default_rng(sd)
+        w = valley_basin(n, sd, float(rng.uniform(*depth_range)))
+        s = csph.solver_for(w, stream=stream)
+        n0 = int(rng.integers(spinup[0], spinup[1] + 1))
+        if n0:
+            s.advance(n0, dt=VALLEY_DT)
+        f0 = s.get_fields()
+        for _ in range(steps // k):
+            s.advance(k, dt=VALLEY_DT)
+            f1 = s.get_fields()
+            h, hu, hv, b = f0
+            xs.append(np.stack([h, hu, hv, b, (h > 0).astype(np.float32)]))
+            ds.append(np.stack([a1 - a0 for a1, a0 in zip(f1, f0)]))
+            f0 = f1
+        s.close()
+        dts += [VALLEY_DT] * (steps // k)
+    return Pairs(np.stack(xs), np.stack(ds), k, np.array(dts))
+
+
 def fixed_dt(w, factor=0.08):
     """dt = factor dx / sqrt(g H_max) of the trajectory's initial state; 0.08
     keeps it under the Eq. 7 step (K = 0.3) while |v| + c stays below about
