@@ -38,8 +38,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-# FP32 VALU issue peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# FP32 FMA issue rate without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (a wave64 FMA every 4 cycles per SIMD; independent FMA chains reach 0.94-0.97
+# of it).  Some other vector instruction kinds issue faster, so it bounds the
+# FP32 arithmetic of a kernel, not every instruction it counts.
 VALU_PEAK_TLANE = 256 * 4 * 16 * 2.4e9 / 1e12
+# the Euler kernel the river valley's launch selects: 58 x 8 strips, per-cell
+# soil, every tile listed in one grid, minmod limiter and Davis speeds
+EULER_KERNEL = "k_euler_sl<8,true,1,false>"
 KERNEL_SOURCES = ("paper_2103_15196_amd/csrc/csph.hip", "paper_2103_15196_amd/csrc/csph_device.h")
 PROFILE = "profiles/k_euler_sl_river_valley_8192_counters.md"
 # algorithmic bytes per cell-step of the river valley: h, hu, hv, b read and
@@ -188,7 +194,7 @@ def main():
                    "parallelism": "single-gpu"},
         "hbm_frac_step": round(value * STEP_BYTES / HBM_PEAK_GBS, 4),
         # the dominant kernel against the HBM roof with the method's own bytes
-        "roofline": {"kernel": "k_euler_sl<8,true,2>", "bound": "hbm", "achieved": round(achieved, 1),
+        "roofline": {"kernel": EULER_KERNEL, "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": (int(float(prof["traffic_bytes"])) if prof else None),
                      "bytes_per_cell": STEP_BYTES, "cells_per_launch": round(eul_cells),
@@ -198,14 +204,17 @@ def main():
         "wet_fraction_end": round(sums["wet_cells"] / cells, 6),
     }
     if prof:
-        # executed VALU work of the same kernel (counters on these sources):
-        # every issued lane-operation against the non-packed FP32 issue rate
+        # executed vector work of the same kernel (counters on these sources):
+        # every issued lane-instruction against the non-packed FP32 FMA rate
         lane_ops = float(prof["valu_insts"]) * 64
         ach = lane_ops / (eul_ms * 1e-3) / 1e12
         out["roofline"]["valu"] = {"achieved": round(ach, 2), "unit": "Tlane-op/s",
-                                   "peak": round(VALU_PEAK_TLANE, 2),
-                                   "frac": round(ach / VALU_PEAK_TLANE, 4),
+                                   "fp32_fma_rate": round(VALU_PEAK_TLANE, 2),
+                                   "frac_of_fma_rate": round(ach / VALU_PEAK_TLANE, 4),
                                    "lane_ops_per_cell": round(lane_ops / eul_cells, 1)}
+        # HBM bytes the counters saw per launch, at the launch time measured here
+        out["roofline"]["traffic_gbs"] = round(float(prof["traffic_bytes"]) / (eul_ms * 1e-3) / 1e9, 1)
+        out["roofline"]["traffic_frac"] = round(out["roofline"]["traffic_gbs"] / HBM_PEAK_GBS, 4)
 
     if not args.no_hgs:
         out["hgs"] = hgs_rate(csph, w, torch, stream, args.steps, value)
