@@ -405,14 +405,26 @@ __global__ void __launch_bounds__(DWT) k_dw(const unsigned short *__restrict__ x
 }
 
 // Sum of the per-workgroup partial gradients (fixed order) into grad.
-__global__ void k_dw_sum(const float *__restrict__ part, int nparts, int len,
-                         float *__restrict__ grad)
+// The weight gradient as the sum of the workgroups' partial slices, in a
+// fixed order (the same bits every run): a 256-thread workgroup takes 64
+// consecutive entries; its four wavefronts sum the partials p = q, q + 4,
+// q + 8, ... (q the wavefront) with coalesced loads, and the four sums are
+// added in wavefront order.
+constexpr int DWS_COLS = 64;
+__global__ void __launch_bounds__(256) k_dw_sum(const float *__restrict__ part, int nparts, int len,
+                                                float *__restrict__ grad)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
-        float s = 0.0f;
-        for (int p = 0; p < nparts; ++p) s += part[(long)p * len + i];
-        grad[i] = s;
+    __shared__ float red[4][DWS_COLS];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int i = blockIdx.x * DWS_COLS + lane;
+    float s = 0.0f;
+    if (i < len) {
+#pragma unroll 8
+        for (int p = q; p < nparts; p += 4) s += part[(long)p * len + i];
     }
+    red[q][lane] = s;
+    __syncthreads();
+    if (q == 0 && i < len) grad[i] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 // Adam with bias correction (Kingma & Ba 2015), FP32.
@@ -913,8 +925,8 @@ int compute_grads(sws_net *n, const float *x, const float *target, int32_t nimg,
         hipLaunchKernelGGL(k_dw, dim3(DW_GRID), dim3(DWT), 0, n->stream, s.act[l], stored(cin), cin,
                            gcur, cs_out, cout, nimg, nx, ny, s.dwpart);
         const int len = cout * cin * 9 + cout;
-        hipLaunchKernelGGL(k_dw_sum, dim3(grid_for(len)), dim3(NT), 0, n->stream, s.dwpart, DW_GRID,
-                           len, n->g + n->woff[l]);
+        hipLaunchKernelGGL(k_dw_sum, dim3((len + DWS_COLS - 1) / DWS_COLS), dim3(256), 0, n->stream,
+                           s.dwpart, DW_GRID, len, n->g + n->woff[l]);
         if (l > 0) {  // dz_{l-1} = (W_l^T * dz_l) where act[l] > 0
             rc = conv(n, gcur, n->bwd[l], n->wpk_t[l], nullptr, 2, s.act[l], stored(n->ch[l]),
                       gnext, cs_out, nimg, nx, ny);
