@@ -77,6 +77,8 @@ typedef struct {
     double coriolis;  /* Coriolis parameter f_c = 2 Omega sin(latitude), 1/s */
     double wind_x, wind_y; /* wind velocity W at 10 m, m/s                   */
     double wind_coef; /* C_w = (rho_air / rho_water) C_D, dimensionless      */
+    int32_t force_order; /* Lagrangian force: 1 on cell values, 2 on states  */
+                         /* reconstructed with the TVD limiter (O4)          */
 } orc_params;
 
 typedef struct {
@@ -303,7 +305,8 @@ double orc_hydrograph(const orc_inputs *in, double t)
 /* At rest over any bed (constant Hd + b where wet, dry banks               */
 /* above it) every face has HsL = HsR and S = 0.                            */
 /* ---------------------------------------------------------------------- */
-static void forces(const orc_params *p, const double *Hd, const double *b, double *Sx, double *Sy)
+static void forces_first(const orc_params *p, const double *Hd, const double *b, double *Sx,
+                         double *Sy)
 {
     const int nx = p->nx, ny = p->ny;
     const double g = p->g, dx = p->dx;
@@ -360,6 +363,143 @@ static void forces(const orc_params *p, const double *Hd, const double *b, doubl
             Sy[c] = -(Pn - Ps) / dx + (g / (2.0 * dx)) * (HsLn * HsLn - HsRs * HsRs);
         }
     }
+}
+
+/* ---------------------------------------------------------------------- */
+/* O4, second-order form (force_order = 2; a reading: the paper names TVD   */
+/* reconstruction only for the Euler stage).  The same hydrostatic-face     */
+/* force, on side states reconstructed with the run's TVD limiter: a cell   */
+/* with surface zeta = Hd + b and limited slopes s_zeta, s_H (per direction,*/
+/* ghost cells copy their neighbour, so boundary cells have zero slope)     */
+/* offers the face on its east (north) side zeta + s_zeta/2, Hd + s_H/2,    */
+/* and on its west (south) side zeta - s_zeta/2, Hd - s_H/2, with the bed   */
+/* side b_s = zeta_s - H_s.  At a face: b_face = max of the two side beds,  */
+/* each side depth Hs = max(0, zeta_s - b_face), P = (g/2) HsL HsR.  On     */
+/* cell i (x direction), with Audusse et al. (2004)'s centred term for the  */
+/* bed slope inside the cell:                                               */
+/*   Sx_i = -(P_{i+1/2} - P_{i-1/2})/dx                                     */
+/*          + (g/(2 dx)) [ (HsL_{i+1/2})^2 - (HsR_{i-1/2})^2 ]              */
+/*          - g Hd_i s_zeta_i / dx.                                         */
+/* (The last term is what remains of Audusse's corrections                  */
+/* g/2 (h_side^2 - Hs^2) and -g (h_w + h_e)/2 (b_e - b_w) once the side    */
+/* depths h_e + h_w = 2 Hd_i and surfaces zeta_e - zeta_w = s_zeta_i are    */
+/* used.)  With s = 0 it is the first-order form; at rest (zeta constant    */
+/* where wet) every wet cell has s_zeta = 0 and every face balances.        */
+/* ---------------------------------------------------------------------- */
+static void forces_second(const orc_params *p, const double *Hd, const double *b, double *Sx,
+                          double *Sy)
+{
+    const int nx = p->nx, ny = p->ny;
+    const double g = p->g, dx = p->dx;
+    const size_t n = (size_t)nx * ny;
+    double *Z = (double *)malloc(n * sizeof(double));
+    double *sZx = (double *)malloc(n * sizeof(double)), *sHx = (double *)malloc(n * sizeof(double));
+    double *sZy = (double *)malloc(n * sizeof(double)), *sHy = (double *)malloc(n * sizeof(double));
+    for (size_t c = 0; c < n; ++c) Z[c] = Hd[c] + b[c];
+    /* limited slopes; the ghost of a boundary cell is the cell itself */
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            size_t c = (size_t)j * nx + i;
+            size_t w = i > 0 ? c - 1 : c, e = i + 1 < nx ? c + 1 : c;
+            size_t s = j > 0 ? c - nx : c, nn = j + 1 < ny ? c + nx : c;
+            sZx[c] = orc_limiter(p->limiter, Z[c] - Z[w], Z[e] - Z[c]);
+            sHx[c] = orc_limiter(p->limiter, Hd[c] - Hd[w], Hd[e] - Hd[c]);
+            sZy[c] = orc_limiter(p->limiter, Z[c] - Z[s], Z[nn] - Z[c]);
+            sHy[c] = orc_limiter(p->limiter, Hd[c] - Hd[s], Hd[nn] - Hd[c]);
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            size_t c = (size_t)j * nx + i;
+            double zL, hL, zR, hR, bf, HsL, HsR, Pe, Pw, Pn, Ps, HsLe, HsRw, HsLn, HsRs;
+            /* east face: this cell's east side against the east cell's west side */
+            zL = Z[c] + 0.5 * sZx[c];
+            hL = Hd[c] + 0.5 * sHx[c];
+            if (i + 1 < nx) {
+                size_t e = c + 1;
+                zR = Z[e] - 0.5 * sZx[e];
+                hR = Hd[e] - 0.5 * sHx[e];
+            } else {
+                zR = zL;
+                hR = hL;
+            }
+            bf = fmax(zL - hL, zR - hR);
+            HsL = fmax(0.0, zL - bf);
+            HsR = fmax(0.0, zR - bf);
+            Pe = 0.5 * g * HsL * HsR;
+            HsLe = HsL;
+            /* west face: the west cell's east side against this cell's west side */
+            zR = Z[c] - 0.5 * sZx[c];
+            hR = Hd[c] - 0.5 * sHx[c];
+            if (i > 0) {
+                size_t w = c - 1;
+                zL = Z[w] + 0.5 * sZx[w];
+                hL = Hd[w] + 0.5 * sHx[w];
+            } else {
+                zL = zR;
+                hL = hR;
+            }
+            bf = fmax(zL - hL, zR - hR);
+            HsL = fmax(0.0, zL - bf);
+            HsR = fmax(0.0, zR - bf);
+            Pw = 0.5 * g * HsL * HsR;
+            HsRw = HsR;
+            Sx[c] = -(Pe - Pw) / dx + (g / (2.0 * dx)) * (HsLe * HsLe - HsRw * HsRw)
+                    - g * Hd[c] * sZx[c] / dx;
+            /* north face */
+            zL = Z[c] + 0.5 * sZy[c];
+            hL = Hd[c] + 0.5 * sHy[c];
+            if (j + 1 < ny) {
+                size_t nn = c + nx;
+                zR = Z[nn] - 0.5 * sZy[nn];
+                hR = Hd[nn] - 0.5 * sHy[nn];
+            } else {
+                zR = zL;
+                hR = hL;
+            }
+            bf = fmax(zL - hL, zR - hR);
+            HsL = fmax(0.0, zL - bf);
+            HsR = fmax(0.0, zR - bf);
+            Pn = 0.5 * g * HsL * HsR;
+            HsLn = HsL;
+            /* south face */
+            zR = Z[c] - 0.5 * sZy[c];
+            hR = Hd[c] - 0.5 * sHy[c];
+            if (j > 0) {
+                size_t s = c - nx;
+                zL = Z[s] + 0.5 * sZy[s];
+                hL = Hd[s] + 0.5 * sHy[s];
+            } else {
+                zL = zR;
+                hL = hR;
+            }
+            bf = fmax(zL - hL, zR - hR);
+            HsL = fmax(0.0, zL - bf);
+            HsR = fmax(0.0, zR - bf);
+            Ps = 0.5 * g * HsL * HsR;
+            HsRs = HsR;
+            Sy[c] = -(Pn - Ps) / dx + (g / (2.0 * dx)) * (HsLn * HsLn - HsRs * HsRs)
+                    - g * Hd[c] * sZy[c] / dx;
+        }
+    }
+    free(Z); free(sZx); free(sHx); free(sZy); free(sHy);
+}
+
+static void forces(const orc_params *p, const double *Hd, const double *b, double *Sx, double *Sy)
+{
+    if (p->force_order == 2) forces_second(p, Hd, b, Sx, Sy);
+    else forces_first(p, Hd, b, Sx, Sy);
+}
+
+/* The O4 force alone on a state (the first- or second-order form of the    */
+/* run's parameters), for pins of its consistency.                          */
+int orc_force(const orc_params *p, const double *Hd, const double *b, double *Sx, double *Sy)
+{
+    if (!p || !Hd || !b || !Sx || !Sy || p->nx < 1 || p->ny < 1) return ORC_ERR_ARG;
+    forces(p, Hd, b, Sx, Sy);
+    return ORC_OK;
 }
 
 /* External forces per unit area on the momentum q of a column of depth    */

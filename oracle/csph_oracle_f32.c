@@ -29,6 +29,7 @@ typedef struct {
     double g, cfl, eps, h_sed, dt_max, dt_min, s_rel, C_J, C_Sh, A_G, m_exp;
     int32_t sed_law, limiter, hll_speeds;
     double rain, coriolis, wind_x, wind_y, wind_coef;
+    int32_t force_order;
 } f32_params_d;
 typedef struct {
     const double *nM, *d50, *psi, *qb;
@@ -60,6 +61,7 @@ typedef struct {
 #define orc_hydrograph orc_hydrograph_f32
 #define orc_threads orc_threads_f32
 #define orc_set_threads orc_set_threads_f32
+#define orc_force orc_force_f32
 #include "csph_oracle.c"
 #undef double
 
@@ -88,6 +90,7 @@ int orcf_step(const f32_params_d *pd, const f32_inputs_d *id, double *H, double 
     p.hll_speeds = pd->hll_speeds;
     p.rain = (float)pd->rain; p.coriolis = (float)pd->coriolis; p.wind_x = (float)pd->wind_x;
     p.wind_y = (float)pd->wind_y; p.wind_coef = (float)pd->wind_coef;
+    p.force_order = pd->force_order;
     const size_t n = (size_t)p.nx * p.ny;
     orc_inputs in;
     in.nM = to_f32(id->nM, n); in.d50 = to_f32(id->d50, n); in.psi = to_f32(id->psi, n);

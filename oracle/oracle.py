@@ -78,7 +78,7 @@ class _Params(C.Structure):
                 ("C_Sh", C.c_double), ("A_G", C.c_double), ("m_exp", C.c_double),
                 ("sed_law", C.c_int32), ("limiter", C.c_int32), ("hll_speeds", C.c_int32),
                 ("rain", C.c_double), ("coriolis", C.c_double), ("wind_x", C.c_double),
-                ("wind_y", C.c_double), ("wind_coef", C.c_double)]
+                ("wind_y", C.c_double), ("wind_coef", C.c_double), ("force_order", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -125,6 +125,8 @@ def _load():
         lib.orc_wave_speeds.argtypes = [C.c_int, C.c_double] + [C.c_double] * 4 + [_dp, _dp]
         lib.orc_trr_star.restype = None
         lib.orc_trr_star.argtypes = [C.c_double] + [C.c_double] * 4 + [_dp, _dp]
+        lib.orc_force.restype = C.c_int
+        lib.orc_force.argtypes = [C.POINTER(_Params), _dp, _dp, _dp, _dp]
         lib.orc_hydrograph.restype = C.c_double
         lib.orc_hydrograph.argtypes = [C.POINTER(_Inputs), C.c_double]
         lib.orc_cfl.restype = C.c_int
@@ -176,6 +178,7 @@ class Params:
     wind_x: float = 0.0      # m/s
     wind_y: float = 0.0
     wind_coef: float = 0.0   # (rho_air / rho_water) C_D
+    force_order: int = 1     # Lagrangian force on cell values (1) or reconstructed states (2)
 
     def _c(self) -> _Params:
         p = _Params()
@@ -188,6 +191,7 @@ class Params:
         p.sed_law = int(self.sed_law)
         p.limiter = int(self.limiter)
         p.hll_speeds = int(self.hll_speeds)
+        p.force_order = int(self.force_order)
         return p
 
 
@@ -377,6 +381,22 @@ def hll(g, HsL, uLnL, uLtL, unL, HsR, uLnR, uLtR, unR):
     _load().orc_hll(float(g), float(HsL), float(uLnL), float(uLtL), float(unL), float(HsR),
                     float(uLnR), float(uLtR), float(unR), f)
     return tuple(f)
+
+
+def force(p: Params, Hd, b):
+    """The Lagrangian force per unit area (Sx, Sy) of depth Hd over bed b
+    ([ny, nx] arrays), in the first- or second-order form of p."""
+    Hd = np.ascontiguousarray(Hd, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    assert Hd.shape == (p.ny, p.nx) and b.shape == Hd.shape
+    Sx = np.empty_like(Hd)
+    Sy = np.empty_like(Hd)
+    pc = p._c()
+    rc = _load().orc_force(C.byref(pc), Hd.ctypes.data_as(_dp), b.ctypes.data_as(_dp),
+                           Sx.ctypes.data_as(_dp), Sy.ctypes.data_as(_dp))
+    if rc != 0:
+        raise OracleError(rc)
+    return Sx, Sy
 
 
 def limiter(kind: int, a: float, b: float) -> float:

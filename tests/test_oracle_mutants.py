@@ -3,7 +3,8 @@
 Each mutant below plants one typical error (a dropped term, a flipped sign, a
 wrong neighbour, an x/y mix-up, a wrong donor) into a temporary copy of the
 oracle's C source, compiles it on the CPU, and runs the pin suite
-(test_oracle_pins.py, test_oracle_variants.py, test_oracle_forcing.py) against it in a subprocess.  Every mutant must make at
+(test_oracle_pins.py, test_oracle_variants.py, test_oracle_forcing.py) against
+it in a subprocess.  Every mutant must make at
 least one pin fail; the unmodified source must pass.
 """
 import os
@@ -73,6 +74,16 @@ MUTANTS = {
     "hydrograph_at_step_start": ("orc_hydrograph(in, t + 0.5 * dt)", "orc_hydrograph(in, t)"),
     "hydrograph_at_step_end": ("orc_hydrograph(in, t + 0.5 * dt)", "orc_hydrograph(in, t + dt)"),
     "hydrograph_sigma_factor": ("exp(-d * d / (2.0 * s * s))", "exp(-d * d / (s * s))"),
+    "force2_ignored": ("if (p->force_order == 2) forces_second", "if (p->force_order == 3) forces_second"),
+    "force2_central_term_sign": ("- g * Hd[c] * sZx[c] / dx;", "+ g * Hd[c] * sZx[c] / dx;"),
+    "force2_drops_central_term_y": ("(HsLn * HsLn - HsRs * HsRs)\n                    - g * Hd[c] * sZy[c] / dx;",
+                                    "(HsLn * HsLn - HsRs * HsRs);"),
+    "force2_own_side_wrong_half": ("zL = Z[c] + 0.5 * sZx[c];", "zL = Z[c] - 0.5 * sZx[c];"),
+    "force2_neighbour_side_wrong_half": ("zR = Z[e] - 0.5 * sZx[e];", "zR = Z[e] + 0.5 * sZx[e];"),
+    "force2_face_bed_from_cell_bed": ("bf = fmax(zL - hL, zR - hR);\n            HsL = fmax(0.0, zL - bf);\n            HsR = fmax(0.0, zR - bf);\n            Pe",
+                                      "bf = fmax(b[c], zR - hR);\n            HsL = fmax(0.0, zL - bf);\n            HsR = fmax(0.0, zR - bf);\n            Pe"),
+    "force2_depth_slope_is_surface_slope": ("sHx[c] = orc_limiter(p->limiter, Hd[c] - Hd[w], Hd[e] - Hd[c]);",
+                                            "sHx[c] = sZx[c];"),
 }
 
 

@@ -1,6 +1,7 @@
 """Pins of the oracle's limiter and wave-speed variants of the Euler stage
 (Section 3 names TVD limiters and HLL without fixing either): MC and superbee
-slopes, the two-rarefaction (Toro) HLL speeds.
+slopes, the two-rarefaction (Toro) HLL speeds; and of the second-order form of
+the Lagrangian force (hydrostatic faces on reconstructed states).
 
 As in test_oracle_pins.py, each check is against a hand-worked value, an exact
 solution or an invariant, never the oracle against itself."""
@@ -123,6 +124,8 @@ def test_stoker_with_every_limiter_and_speed_estimate(oracle_mod):
     assert e["mc"][0] < e["minmod"][0] and e["superbee"][0] < e["minmod"][0]
     _stoker_errors(O, hll_speeds=1)
     _stoker_errors(O, limiter=2, hll_speeds=1)
+    _stoker_errors(O, force_order=2)
+    _stoker_errors(O, limiter=1, force_order=2)
 
 
 def test_ritter_with_two_rarefaction_speeds(oracle_mod):
@@ -142,15 +145,18 @@ def test_ritter_with_two_rarefaction_speeds(oracle_mod):
     assert errs[1] < 0.6 * errs[0]
 
 
-@pytest.mark.parametrize("limiter,speeds", [(1, 0), (2, 0), (0, 1), (2, 1)])
-def test_variants_keep_the_lake_at_rest_and_conserve(oracle_mod, limiter, speeds):
+@pytest.mark.parametrize("limiter,speeds,force_order",
+                         [(1, 0, 1), (2, 0, 1), (0, 1, 1), (2, 1, 1), (0, 0, 2), (1, 0, 2),
+                          (2, 1, 2)])
+def test_variants_keep_the_lake_at_rest_and_conserve(oracle_mod, limiter, speeds, force_order):
     """Well-balanced and conservative with every variant: a lake over a seeded
     bed with emerged islands stays still (walls, then open sides), and a
     walled fractal dam break keeps its water and sediment volume."""
     O = oracle_mod
     for bc in ((0, 0, 0, 0), (1, 1, 1, 1)):
         w = W.lake_at_rest(48, 36, bc=bc)
-        p, inp, s = oracle_case(O, w, limiter=limiter, hll_speeds=speeds)
+        p, inp, s = oracle_case(O, w, limiter=limiter, hll_speeds=speeds,
+                                force_order=force_order)
         z0 = s.H + s.b
         O.run(p, inp, s, 200)
         wet = s.H > 0
@@ -160,7 +166,7 @@ def test_variants_keep_the_lake_at_rest_and_conserve(oracle_mod, limiter, speeds
     w.bc = (0, 0, 0, 0)
     w.psi = np.random.default_rng(1).uniform(0.3, 0.45, (w.ny, w.nx))
     w.sed_law = W.SED_EQ4
-    p, inp, s = oracle_case(O, w, limiter=limiter, hll_speeds=speeds)
+    p, inp, s = oracle_case(O, w, limiter=limiter, hll_speeds=speeds, force_order=force_order)
     V0 = O.volumes(p, inp, s)
     O.run(p, inp, s, 300)
     V1 = O.volumes(p, inp, s)
@@ -168,21 +174,93 @@ def test_variants_keep_the_lake_at_rest_and_conserve(oracle_mod, limiter, speeds
     assert abs(V1[1] - V0[1]) / V0[1] < 1e-13
 
 
-@pytest.mark.parametrize("limiter,speeds", [(1, 1), (2, 0)])
-def test_variants_keep_mirror_symmetry(oracle_mod, limiter, speeds):
+@pytest.mark.parametrize("limiter,speeds,force_order", [(1, 1, 1), (2, 0, 1), (1, 0, 2)])
+def test_variants_keep_mirror_symmetry(oracle_mod, limiter, speeds, force_order):
     """A problem mirrored in x gives the mirrored answer (walls on both x
     sides exercise the mirrored-ghost wall flux of each estimate)."""
     O = oracle_mod
     w = W.dam_break_fractal(n=36, ny=20, dx=2.0, seed=9, relief=5.0, depth=4.0)
     w.bc = (0, 0, 1, 1)
-    p, inp, s = oracle_case(O, w, limiter=limiter, hll_speeds=speeds)
+    p, inp, s = oracle_case(O, w, limiter=limiter, hll_speeds=speeds, force_order=force_order)
     O.run(p, inp, s, 120)
     wm = W.dam_break_fractal(n=36, ny=20, dx=2.0, seed=9, relief=5.0, depth=4.0)
     wm.bc = (0, 0, 1, 1)
     wm.H, wm.b = wm.H[:, ::-1].copy(), wm.b[:, ::-1].copy()
     wm.qx, wm.qy = -wm.qx[:, ::-1].copy(), wm.qy[:, ::-1].copy()
-    pm, im, sm = oracle_case(O, wm, limiter=limiter, hll_speeds=speeds)
+    pm, im, sm = oracle_case(O, wm, limiter=limiter, hll_speeds=speeds, force_order=force_order)
     O.run(pm, im, sm, 120)
     np.testing.assert_allclose(sm.H[:, ::-1], s.H, atol=1e-11)
     np.testing.assert_allclose(-sm.qx[:, ::-1], s.qx, atol=1e-10)
     np.testing.assert_allclose(sm.qy[:, ::-1], s.qy, atol=1e-10)
+
+
+def _smooth_force_errors(O, limiter, force_order, sizes=(32, 64, 128, 256)):
+    """L1 (mean) and L-inf error of the Lagrangian force against the exact
+    -g H dzeta/dx at the cell centres, for a smooth surface
+    zeta = 3 + 0.3 cos(pi x / L) (level at both walls) over a sloping, waving
+    bed, uniform along y."""
+    out = []
+    for n in sizes:
+        L = 100.0
+        dx = L / n
+        x = (np.arange(n) + 0.5) * dx
+        zeta = 3.0 + 0.3 * np.cos(np.pi * x / L)
+        b = 0.8 * np.sin(2 * np.pi * x / L) + 0.3 * x / L
+        H = zeta - b
+        p = O.Params(nx=n, ny=3, dx=dx, limiter=limiter, force_order=force_order)
+        Sx, Sy = O.force(p, np.tile(H, (3, 1)), np.tile(b, (3, 1)))
+        assert np.all(Sy == 0.0)
+        exact = -G * H * (-0.3 * np.pi / L) * np.sin(np.pi * x / L)
+        e = np.abs(Sx[1] - exact)
+        out.append((e.mean(), e.max()))
+    return np.array(out)
+
+
+def test_second_order_force_converges_at_second_order(oracle_mod):
+    """On a smooth state the hydrostatic-face force on cell values is a
+    first-order approximation of -g H grad(zeta) (the face bed max(b_L, b_R)
+    departs from the bed by O(dx) where it slopes); on limited reconstructed
+    states with the centred term it is second order in L1 for every limiter
+    (the limiters clip the slopes at the surface's extrema, so L-inf stays
+    first order)."""
+    O = oracle_mod
+    e1 = _smooth_force_errors(O, 0, 1)
+    o1 = np.log2(e1[:-1, 0] / e1[1:, 0])
+    assert np.all((o1 > 0.95) & (o1 < 1.15)), o1
+    for lim in (0, 1, 2):
+        e2 = _smooth_force_errors(O, lim, 2)
+        o2 = np.log2(e2[:-1, 0] / e2[1:, 0])
+        assert np.all((o2 > 1.9) & (o2 < 2.1)), (lim, o2)
+        assert e2[-1, 0] < e1[-1, 0] / 10
+        oi = np.log2(e2[:-1, 1] / e2[1:, 1])
+        assert np.all(oi > 0.9), (lim, oi)
+
+
+def test_second_order_force_is_exact_at_rest_and_symmetric(oracle_mod):
+    """At rest over a seeded bed with islands the second-order force vanishes
+    on every wet cell up to FP64 rounding of g H^2 / (2 dx) (as the
+    first-order one does), while a 1 mm bump of the surface is felt; the
+    force of the transposed state is the transposed y force bit for bit, and
+    the mirrored state's x force is the negated mirror (up to the order of a
+    product's factors)."""
+    O = oracle_mod
+    w = W.lake_at_rest(40, 30, seed=12, relief=3.0, level=2.0)
+    wet = w.H > 0
+    for lim in (0, 1, 2):
+        p = O.Params(nx=w.nx, ny=w.ny, dx=1.0, limiter=lim, force_order=2)
+        Sx, Sy = O.force(p, w.H, w.b)
+        assert np.abs(Sx[wet]).max() <= 1e-13 and np.abs(Sy[wet]).max() <= 1e-13, lim
+        Hb = w.H.copy()
+        Hb[wet & (np.arange(w.nx)[None, :] == 20)] += 1e-3
+        Bx, _ = O.force(p, Hb, w.b)
+        assert np.abs(Bx[wet]).max() > 1e-3, lim
+    d = W.dam_break_fractal(n=30, ny=22, dx=2.0, seed=4, relief=5.0, depth=3.0)
+    p = O.Params(nx=30, ny=22, dx=2.0, limiter=1, force_order=2)
+    Sx, Sy = O.force(p, d.H, d.b)
+    pt = O.Params(nx=22, ny=30, dx=2.0, limiter=1, force_order=2)
+    Tx, Ty = O.force(pt, d.H.T, d.b.T)
+    assert np.array_equal(Ty, Sx.T) and np.array_equal(Tx, Sy.T)
+    Mx, My = O.force(p, d.H[:, ::-1], d.b[:, ::-1])
+    np.testing.assert_allclose(Mx[:, ::-1], -Sx, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(My[:, ::-1], Sy, rtol=0, atol=1e-12)
+    assert np.abs(Sx).max() > 0.1
