@@ -74,6 +74,14 @@ extern "C" {
 #define SW_FLAG_HGS 1u        /* skip dry tiles (the hierarchical grid system, Section 3) */
 #define SW_FLAG_UNFUSED 2u    /* run the unfused kernel sequence (faces, then update) */
 #define SW_FLAG_NO_GRAPH 4u   /* launch kernels one by one instead of replaying a HIP graph */
+/* Second-order Lagrangian force (the K2/K5 pressure and bed-slope force of
+ * Eq. 6 on hydrostatic faces of states reconstructed with the TVD limiter,
+ * plus Audusse et al.'s centred bed-slope term; a reading: the paper names
+ * TVD reconstruction for the Euler stage only).  Built into the strip
+ * kernels: with it, LDS tile shapes (sw_set_tile_shape) and SW_FLAG_UNFUSED
+ * are SW_ERR_ARG, the autotuners try strip shapes only, and an ensemble's
+ * members must all have it or all lack it. */
+#define SW_FLAG_FORCE2 8u
 
 typedef struct sw_ctx sw_ctx;
 

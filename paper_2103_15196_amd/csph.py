@@ -32,7 +32,7 @@ ERROR_NAMES = {-1: "SW_ERR_ARG", -2: "SW_ERR_HIP", -3: "SW_ERR_NONFINITE",
 SW_BC_WALL, SW_BC_OPEN = 0, 1
 SW_SED_NONE, SW_SED_GRASS, SW_SED_EQ4 = 0, 1, 2
 SW_PTR_HOST, SW_PTR_DEVICE = 0, 1
-SW_FLAG_HGS, SW_FLAG_UNFUSED, SW_FLAG_NO_GRAPH = 1, 2, 4
+SW_FLAG_HGS, SW_FLAG_UNFUSED, SW_FLAG_NO_GRAPH, SW_FLAG_FORCE2 = 1, 2, 4, 8
 SW_LIM_MINMOD, SW_LIM_MC, SW_LIM_SUPERBEE = 0, 1, 2
 SW_HLL_DAVIS, SW_HLL_TWO_RAREFACTION = 0, 1
 

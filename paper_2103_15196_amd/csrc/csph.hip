@@ -602,20 +602,20 @@ __device__ __forceinline__ float half_depth_cell(const KPar &P, float H, float u
 struct NbrDepths {
     float C, W, E, S, N;
 };
-__device__ __forceinline__ void lagrange_cell(const KPar &P, float dt, const NbrDepths &Hd,
-                                              const NbrDepths &bd, const NbrDepths &Hh, bool hasW,
-                                              bool hasE, bool hasS, bool hasN, float qxc, float qyc,
-                                              float nM, float &QLx, float &QLy)
+// Predictor and corrector of one cell from its forces at t_n (Snx, Sny, on
+// depth HdC) and at t_{n+1/2} (Shx, Shy, on the half-step depth HhC).
+__device__ __forceinline__ void lagrange_momentum(const KPar &P, float dt, float HdC, float HhC,
+                                                  float Snx, float Sny, float Shx, float Shy,
+                                                  float qxc, float qyc, float nM, float &QLx,
+                                                  float &QLy)
 {
-    float Snx = face_force(P, Hd.W, bd.W, Hd.C, bd.C, Hd.E, bd.E, hasW, hasE);
-    float Sny = face_force(P, Hd.S, bd.S, Hd.C, bd.C, Hd.N, bd.N, hasS, hasN);
-    float wc = wdes(Hd.C, P);
+    float wc = wdes(HdC, P);
     float uc = qxc * wc, vc = qyc * wc;
-    float gam = friction_rate(P, nM, nsqrt(sumsq(uc, vc)), Hd.C);
+    float gam = friction_rate(P, nM, nsqrt(sumsq(uc, vc)), HdC);
     float hdt = 0.5f * dt;
     float qpx, qpy;
     if (P.force) {  // Coriolis and wind at t_n
-        const float chi = fminf(1.0f, Hd.C * P.inv_hsed);
+        const float chi = fminf(1.0f, HdC * P.inv_hsed);
         qpx = ndiv(qxc + hdt * (Snx + (P.cor * qyc + chi * P.wsx)), 1.0f + hdt * gam);
         qpy = ndiv(qyc + hdt * (Sny + (-P.cor * qxc + chi * P.wsy)), 1.0f + hdt * gam);
     } else {
@@ -623,19 +623,31 @@ __device__ __forceinline__ void lagrange_cell(const KPar &P, float dt, const Nbr
         qpy = ndiv(qyc + hdt * Sny, 1.0f + hdt * gam);
     }
     float upx = qpx * wc, upy = qpy * wc;
-    float HhW = hasW ? Hh.W : Hh.C, HhE = hasE ? Hh.E : Hh.C;
-    float HhS = hasS ? Hh.S : Hh.C, HhN = hasN ? Hh.N : Hh.C;
-    float Shx = face_force(P, HhW, bd.W, Hh.C, bd.C, HhE, bd.E, hasW, hasE);
-    float Shy = face_force(P, HhS, bd.S, Hh.C, bd.C, HhN, bd.N, hasS, hasN);
-    float gamh = friction_rate(P, nM, nsqrt(sumsq(upx, upy)), Hh.C);
+    float gamh = friction_rate(P, nM, nsqrt(sumsq(upx, upy)), HhC);
     if (P.force) {  // at t_{n+1/2}: half-step depth, predictor momentum
-        const float chi = fminf(1.0f, Hh.C * P.inv_hsed);
+        const float chi = fminf(1.0f, HhC * P.inv_hsed);
         QLx = ndiv(qxc + dt * (Shx + (P.cor * qpy + chi * P.wsx)), 1.0f + dt * gamh);
         QLy = ndiv(qyc + dt * (Shy + (-P.cor * qpx + chi * P.wsy)), 1.0f + dt * gamh);
     } else {
         QLx = ndiv(qxc + dt * Shx, 1.0f + dt * gamh);
         QLy = ndiv(qyc + dt * Shy, 1.0f + dt * gamh);
     }
+}
+
+// The same with the first-order forces from the depths and beds of the cell
+// (C) and its W/E/S/N neighbours.
+__device__ __forceinline__ void lagrange_cell(const KPar &P, float dt, const NbrDepths &Hd,
+                                              const NbrDepths &bd, const NbrDepths &Hh, bool hasW,
+                                              bool hasE, bool hasS, bool hasN, float qxc, float qyc,
+                                              float nM, float &QLx, float &QLy)
+{
+    float Snx = face_force(P, Hd.W, bd.W, Hd.C, bd.C, Hd.E, bd.E, hasW, hasE);
+    float Sny = face_force(P, Hd.S, bd.S, Hd.C, bd.C, Hd.N, bd.N, hasS, hasN);
+    float HhW = hasW ? Hh.W : Hh.C, HhE = hasE ? Hh.E : Hh.C;
+    float HhS = hasS ? Hh.S : Hh.C, HhN = hasN ? Hh.N : Hh.C;
+    float Shx = face_force(P, HhW, bd.W, Hh.C, bd.C, HhE, bd.E, hasW, hasE);
+    float Shy = face_force(P, HhS, bd.S, Hh.C, bd.C, HhN, bd.N, hasS, hasN);
+    lagrange_momentum(P, dt, Hd.C, Hh.C, Snx, Sny, Shx, Shy, qxc, qyc, nM, QLx, QLy);
 }
 
 // Draining limiter of a cell of depth h from its four raw mass fluxes.
@@ -1208,6 +1220,119 @@ __device__ __forceinline__ void lagrange_strip(const Inst &I, int par, int bx, i
     }
 }
 
+// Lagrangian stage on a strip tile with the second-order force (hydrostatic
+// faces on limited reconstructions of surface and depth, face_force2).  Its
+// stencil reaches two cells past the cell, and the half-step depths it uses
+// need the velocities one more row out, so the march covers rows y0-3 ..
+// y0+S+2 and computes K2..K6 of row r-3 at row r (the first-order march:
+// y0-2 .. y0+S+1, row r-2).  x neighbours: three halo lanes suffice.
+template <int S, bool CS>
+__device__ __forceinline__ void lagrange_strip2(const Inst &I, int par, int bx, int by, float dt)
+{
+    const KPar &P = I.P;
+    const int lane = threadIdx.x & 63;
+    const int nx = P.nx, ny = P.ny, pitch = P.pitch;
+    const int x0 = bx * SX, y0 = by * S;
+    const int i = x0 - SHALO + lane;
+    const bool inx = (unsigned)i < (unsigned)nx;
+    const bool mine = lane >= SHALO && lane < SHALO + SX && inx;
+    const bool hasW = i > 0, hasE = i + 1 < nx;
+    const int ci = min(max(i, 0), nx - 1);
+    const int jend = min(y0 + S, ny);
+    const float *H = I.H[par], *Qx = I.qx[par], *Qy = I.qy[par], *B = I.b[par];
+    const float hdt_dx = dt / (2.0f * P.dx);
+    struct LRow {
+        float h, qx, qy, b, nM;
+    };
+    auto load_row = [&](int r, LRow &w) {
+        const int c = min(max(r, 0), ny - 1) * pitch + ci;
+        w.h = H[c]; w.qx = Qx[c]; w.qy = Qy[c]; w.b = B[c];
+        w.nM = CS && P.nM ? P.nM[c] : P.nM_s;
+    };
+    // for the current row r: depth and bed of rows r-5 .. r (H5 .. H0),
+    // momentum and Manning n of rows r-3 .. r, u of rows r-1 .. r, v of rows
+    // r-2 .. r, half-step depths of rows r-5 .. r-1 (Hh5 .. Hh1)
+    float H5 = 0, H4 = 0, H3 = 0, H2 = 0, H1 = 0, H0 = 0;
+    float b5 = 0, b4 = 0, b3 = 0, b2 = 0, b1 = 0, b0 = 0;
+    float qx3 = 0, qx2 = 0, qx1 = 0, qx0 = 0, qy3 = 0, qy2 = 0, qy1 = 0, qy0 = 0;
+    float n3 = 0, n2 = 0, n1 = 0, n0 = 0;
+    float u1 = 0, u0 = 0, v2 = 0, v1 = 0, v0 = 0;
+    float Hh5 = 0, Hh4 = 0, Hh3 = 0, Hh2 = 0, Hh1 = 0;
+    // limited slopes (a boundary cell's ghost is the cell itself)
+    auto xslope = [&](float a, float aW, float aE) {
+        return limited<true>(P, hasW ? a - aW : 0.0f, hasE ? aE - a : 0.0f);
+    };
+    auto yslope = [&](int j, float am, float a, float ap) {
+        return limited<true>(P, j > 0 ? a - am : 0.0f, j + 1 < ny ? ap - a : 0.0f);
+    };
+    // both force components on row j of depth rows d[j-2 .. j+2] over bed
+    // rows e[j-2 .. j+2]; the lane shifts run with every lane active
+    auto forces2 = [&](int j, float dm2, float dm1, float d, float dp1, float dp2, float em2,
+                       float em1, float e, float ep1, float ep2, float &Sx, float &Sy) {
+        const float z = d + e;
+        const float zW = lane_prev(z), zE = lane_next(z);
+        const float dW = lane_prev(d), dE = lane_next(d);
+        const float sz = xslope(z, zW, zE), sh = xslope(d, dW, dE);
+        const ReconQ Wx{zW, dW, lane_prev(sz), lane_prev(sh)};
+        const ReconQ Cx{z, d, sz, sh};
+        const ReconQ Ex{zE, dE, lane_next(sz), lane_next(sh)};
+        Sx = face_force2(P, Wx, Cx, Ex, hasW, hasE);
+        const float zm2 = dm2 + em2, zm1 = dm1 + em1, zp1 = dp1 + ep1, zp2 = dp2 + ep2;
+        const ReconQ Sq{zm1, dm1, yslope(j - 1, zm2, zm1, z), yslope(j - 1, dm2, dm1, d)};
+        const ReconQ Cy{z, d, yslope(j, zm1, z, zp1), yslope(j, dm1, d, dp1)};
+        const ReconQ Nq{zp1, dp1, yslope(j + 1, z, zp1, zp2), yslope(j + 1, d, dp1, dp2)};
+        Sy = face_force2(P, Sq, Cy, Nq, j > 0, j + 1 < ny);
+    };
+    auto step = [&](int r, const LRow &in) {
+        H5 = H4; H4 = H3; H3 = H2; H2 = H1; H1 = H0;
+        b5 = b4; b4 = b3; b3 = b2; b2 = b1; b1 = b0;
+        qx3 = qx2; qx2 = qx1; qx1 = qx0; qy3 = qy2; qy2 = qy1; qy1 = qy0;
+        n3 = n2; n2 = n1; n1 = n0;
+        u1 = u0; v2 = v1; v1 = v0;
+        Hh5 = Hh4; Hh4 = Hh3; Hh3 = Hh2; Hh2 = Hh1;
+        const bool ok = inx && (unsigned)r < (unsigned)ny;
+        H0 = ok ? in.h : 0.0f;
+        b0 = ok ? in.b : 0.0f;
+        qx0 = ok ? in.qx : 0.0f;
+        qy0 = ok ? in.qy : 0.0f;
+        n0 = in.nM;
+        const float w = wdes(H0, P);
+        u0 = ok ? qx0 * w : 0.0f;
+        v0 = ok ? qy0 * w : 0.0f;
+        {  // K4 half-step depth of row r-1 (the tile's rows and two-row rings)
+            const int j = r - 1;
+            const float uW = lane_prev(u1), uE = lane_next(u1);
+            float hh = 0.0f;
+            if (j >= y0 - 2 && j <= y0 + S + 1 && inx && (unsigned)j < (unsigned)ny)
+                hh = half_depth_cell(P, H1, u1, uW, uE, v1, v2, v0, i, j, hdt_dx);
+            Hh1 = hh;
+        }
+        const int j = r - 3;  // K2, K4, K5, K6 of row r-3
+        if (j >= y0 && j < jend) {
+            float Snx, Sny, Shx, Shy;
+            forces2(j, H5, H4, H3, H2, H1, b5, b4, b3, b2, b1, Snx, Sny);
+            forces2(j, Hh5, Hh4, Hh3, Hh2, Hh1, b5, b4, b3, b2, b1, Shx, Shy);
+            if (mine) {
+                float QLx, QLy;
+                lagrange_momentum(P, dt, H3, Hh3, Snx, Sny, Shx, Shy, qx3, qy3, n3, QLx, QLy);
+                const int c = j * pitch + i;
+                I.QLx[c] = QLx;
+                I.QLy[c] = QLy;
+            }
+        }
+    };
+    const int rlo = y0 - 3, rhi = y0 + S + 2;  // S + 6 rows, an even count
+    LRow A, Bq;
+    load_row(rlo, A);
+    load_row(rlo + 1, Bq);
+    for (int r = rlo; r <= rhi; r += 2) {
+        step(r, A);
+        if (r + 2 <= rhi) load_row(r + 2, A);
+        step(r + 1, Bq);
+        if (r + 3 <= rhi) load_row(r + 3, Bq);
+    }
+}
+
 // Euler stage on a strip tile (K7 + limiter + K8) with the epilogue
 // reductions (Eq. 7 maxima and wet flag of the new state, boundary balances).
 // CS: some soil or source field is a per-cell plane (else all are scalars).
@@ -1753,7 +1878,7 @@ __device__ __forceinline__ int xcd_entry(int b, int wave, int n)
 //           without the halves' extra halo rows.
 // (XP = 2 is a kernel of its own: the pass loop costs the Euler kernel
 // registers, and with them a wavefront per SIMD, that XP = 1 keeps.)
-template <int S, bool CS, int XP>
+template <int S, bool CS, int XP, bool F2>
 __device__ __forceinline__ void lagrange_listed(const Inst &I, int par, int w)
 {
     w = __builtin_amdgcn_readfirstlane(w);
@@ -1801,7 +1926,8 @@ __device__ __forceinline__ void lagrange_listed(const Inst &I, int par, int w)
     if (XP != 2) {
         if (w >= n) return;
         const int t = __builtin_amdgcn_readfirstlane(I.hgs ? I.lag[seg * I.chunk + (w - start)] : w);
-        lagrange_strip<S / LH, CS>(I, par, t % I.ntx, (t / I.ntx) * LH + part, dt);
+        if constexpr (F2) lagrange_strip2<S / LH, CS>(I, par, t % I.ntx, (t / I.ntx) * LH + part, dt);
+        else lagrange_strip<S / LH, CS>(I, par, t % I.ntx, (t / I.ntx) * LH + part, dt);
         return;
     }
     for (int base = 0; base < n; base += G4) {
@@ -1810,7 +1936,8 @@ __device__ __forceinline__ void lagrange_listed(const Inst &I, int par, int w)
         if (we >= base + cnt) continue;
         if (I.hgs) list_locate(I.cnt_l, cl0, nb, we, seg, start, nullptr);
         const int t = __builtin_amdgcn_readfirstlane(I.hgs ? I.lag[seg * I.chunk + (we - start)] : we);
-        lagrange_strip<S, CS>(I, par, t % I.ntx, t / I.ntx, dt);
+        if constexpr (F2) lagrange_strip2<S, CS>(I, par, t % I.ntx, t / I.ntx, dt);
+        else lagrange_strip<S, CS>(I, par, t % I.ntx, t / I.ntx, dt);
     }
 }
 template <int S, bool CS, bool V>
@@ -1850,10 +1977,11 @@ __device__ __forceinline__ void euler_listed(const Inst &I, int par, int w)
     }
 }
 
-template <int S, bool CS, int XP>
+// F2: the second-order force (lagrange_strip2).
+template <int S, bool CS, int XP, bool F2>
 __global__ void __launch_bounds__(NT) k_lagrange_sl(Inst I, int par)
 {
-    lagrange_listed<S, CS, XP>(I, par, blockIdx.x * SWAVES + (threadIdx.x >> 6));
+    lagrange_listed<S, CS, XP, F2>(I, par, blockIdx.x * SWAVES + (threadIdx.x >> 6));
 }
 // V: the limiter or the wave-speed estimate is not minmod + Davis (read from
 // the run's constants); V = false keeps the default arithmetic branch-free.
@@ -1864,12 +1992,12 @@ __global__ void __launch_bounds__(NT) k_euler_sl(Inst I, int par)
 }
 
 // Ensemble: workgroup b runs waves SWAVES table[2b+1] + w of member table[2b].
-template <int S, bool CS>
+template <int S, bool CS, bool F2>
 __global__ void __launch_bounds__(NT) k_lagrange_slb(const Inst *__restrict__ insts,
                                                      const int *__restrict__ table, int par)
 {
     const int *t = table + 2 * blockIdx.x;
-    lagrange_listed<S, CS, 0>(insts[t[0]], par, t[1] * SWAVES + (threadIdx.x >> 6));
+    lagrange_listed<S, CS, 0, F2>(insts[t[0]], par, t[1] * SWAVES + (threadIdx.x >> 6));
 }
 template <int S, bool CS, bool V>
 __global__ void __launch_bounds__(NT) k_euler_slb(const Inst *__restrict__ insts,
@@ -2087,6 +2215,7 @@ KPar make_kpar(const sw_ctx *c)
     P.inv_hsed = (float)(1.0 / c->par.h_sed);
     P.force = (c->coriolis != 0.0 || P.wsx != 0.0f || P.wsy != 0.0f) ? 1 : 0;
     P.variant = (c->par.limiter != SW_LIM_MINMOD || c->par.hll_speeds != SW_HLL_DAVIS) ? 1 : 0;
+    P.force2 = (c->par.flags & SW_FLAG_FORCE2) ? 1 : 0;
     return P;
 }
 
@@ -2310,11 +2439,13 @@ void launch_batch_t(Stage st, hipStream_t s, const Inst *insts, int nmem, const 
 // kernels over the (member, local workgroup) table, both on work lists.
 template <int S, bool CS>
 void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, const int *table, int ntab,
-                    const int *dtab, int ndtab, int lthr, int par, bool var)
+                    const int *dtab, int ndtab, int lthr, int par, bool var, bool f2)
 {
     if (st == kDt) hipLaunchKernelGGL(k_dt_lists_b, dim3(ndtab), dim3(lthr), 0, s, insts, dtab, par);
+    else if (st == kLagrange && f2)
+        hipLaunchKernelGGL((k_lagrange_slb<S, CS, true>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
     else if (st == kLagrange)
-        hipLaunchKernelGGL((k_lagrange_slb<S, CS>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
+        hipLaunchKernelGGL((k_lagrange_slb<S, CS, false>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
     else if (var)
         hipLaunchKernelGGL((k_euler_slb<S, CS, true>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
     else hipLaunchKernelGGL((k_euler_slb<S, CS, false>), dim3(ntab), dim3(NT), 0, s, insts, table, par);
@@ -2322,10 +2453,10 @@ void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, const int *table
 
 template <int S>
 void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, const int *table, int ntab,
-                    const int *dtab, int ndtab, int lthr, int par, bool cs, bool var)
+                    const int *dtab, int ndtab, int lthr, int par, bool cs, bool var, bool f2)
 {
-    if (cs) launch_batch_s<S, true>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, var);
-    else launch_batch_s<S, false>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, var);
+    if (cs) launch_batch_s<S, true>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, var, f2);
+    else launch_batch_s<S, false>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, var, f2);
 }
 
 // cs: some member has a per-cell soil or source plane; var: some member runs
@@ -2334,16 +2465,16 @@ void launch_batch_s(Stage st, hipStream_t s, const Inst *insts, const int *table
 // (member, bx, by) table; strips the stage and K3a tables.
 void launch_batch(int shape, Stage st, hipStream_t s, const Inst *insts, int nmem,
                   const int *table, int ntab, const int *dtab, int ndtab, int lthr, int par,
-                  bool cs, bool var)
+                  bool cs, bool var, bool f2)
 {
     switch (shape) {
     case 0: launch_batch_t<64, 8>(st, s, insts, nmem, table, ntab, par); break;
     case 1: launch_batch_t<64, 4>(st, s, insts, nmem, table, ntab, par); break;
     case 2: launch_batch_t<64, 16>(st, s, insts, nmem, table, ntab, par); break;
     case 3: launch_batch_t<128, 4>(st, s, insts, nmem, table, ntab, par); break;
-    case 4: launch_batch_s<8>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, cs, var); break;
-    case 5: launch_batch_s<16>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, cs, var); break;
-    default: launch_batch_s<32>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, cs, var); break;
+    case 4: launch_batch_s<8>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, cs, var, f2); break;
+    case 5: launch_batch_s<16>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, cs, var, f2); break;
+    default: launch_batch_s<32>(st, s, insts, table, ntab, dtab, ndtab, lthr, par, cs, var, f2); break;
     }
 }
 
@@ -2377,9 +2508,13 @@ void launch_strip_t(Stage st, hipStream_t s, const Inst &I, int par, hipEvent_t 
     const int gl = passes ? kMaxStageGroups : need;
     const int gll = passes || big ? gl : (kLagHalves * I.ntx * I.nty + SWAVES - 1) / SWAVES;
     const bool cs = cell_soil(I.P);
-    auto lag = passes ? (cs ? k_lagrange_sl<S, true, 2> : k_lagrange_sl<S, false, 2>)
-               : big  ? (cs ? k_lagrange_sl<S, true, 3> : k_lagrange_sl<S, false, 3>)
-                      : (cs ? k_lagrange_sl<S, true, 1> : k_lagrange_sl<S, false, 1>);
+    auto lag1 = passes ? (cs ? k_lagrange_sl<S, true, 2, false> : k_lagrange_sl<S, false, 2, false>)
+                : big  ? (cs ? k_lagrange_sl<S, true, 3, false> : k_lagrange_sl<S, false, 3, false>)
+                       : (cs ? k_lagrange_sl<S, true, 1, false> : k_lagrange_sl<S, false, 1, false>);
+    auto lag2 = passes ? (cs ? k_lagrange_sl<S, true, 2, true> : k_lagrange_sl<S, false, 2, true>)
+                : big  ? (cs ? k_lagrange_sl<S, true, 3, true> : k_lagrange_sl<S, false, 3, true>)
+                       : (cs ? k_lagrange_sl<S, true, 1, true> : k_lagrange_sl<S, false, 1, true>);
+    auto lag = I.P.force2 ? lag2 : lag1;
     auto eul = I.P.variant
                    ? (passes ? (cs ? k_euler_sl<S, true, 2, true> : k_euler_sl<S, false, 2, true>)
                              : (cs ? k_euler_sl<S, true, 1, true> : k_euler_sl<S, false, 1, true>))
@@ -2650,6 +2785,8 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
     if (params->limiter < SW_LIM_MINMOD || params->limiter > SW_LIM_SUPERBEE) return SW_ERR_ARG;
     if (params->hll_speeds != SW_HLL_DAVIS && params->hll_speeds != SW_HLL_TWO_RAREFACTION)
         return SW_ERR_ARG;
+    // the second-order force is built into the strip kernels only
+    if ((params->flags & SW_FLAG_FORCE2) && (params->flags & SW_FLAG_UNFUSED)) return SW_ERR_ARG;
     sw_ctx *c = new sw_ctx();
     c->grid = *grid;
     c->par = *params;
@@ -3119,6 +3256,8 @@ int sw_set_tile_shape(sw_ctx *c, int32_t tile_x, int32_t tile_y)
     if (!c) return SW_ERR_ARG;
     for (int sh = 0; sh < kNumShapes; ++sh)
         if (kShapes[sh].tx == tile_x && kShapes[sh].ty == tile_y) {
+            if ((c->par.flags & SW_FLAG_FORCE2) && !is_strip(sh))
+                return fail(c, SW_ERR_ARG, "the second-order force runs on strip shapes only");
             HIPCHK(c, hipStreamSynchronize(c->stream));
             set_shape(c, sh);
             return SW_OK;
@@ -3141,9 +3280,11 @@ int sw_autotune(sw_ctx *c, int32_t nsteps, int32_t *tile_x, int32_t *tile_y)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int best = c->shape;
     float best_ms = 0.0f;
+    bool timed = false;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         rc = fail(c, SW_ERR_HIP, "hipEventCreate");
     for (int sh = 0; sh < kNumShapes && !rc; ++sh) {
+        if ((c->par.flags & SW_FLAG_FORCE2) && !is_strip(sh)) continue;
         set_shape(c, sh);
         if ((rc = prepare(c))) break;
         Inst I = make_inst(c, make_step_args(c, 0, 0.0));
@@ -3161,7 +3302,7 @@ int sw_autotune(sw_ctx *c, int32_t nsteps, int32_t *tile_x, int32_t *tile_y)
         }
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        if (sh == 0 || ms < best_ms) { best_ms = ms; best = sh; }
+        if (!timed || ms < best_ms) { best_ms = ms; best = sh; timed = true; }
         if ((rc = keep_restore(c, kp))) break;
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -3719,6 +3860,7 @@ struct swb_ctx {
     int shape = kDefaultShape;
     bool cs = false;  // some member reads per-cell soil or source planes
     bool var = false; // some member runs a limiter or wave-speed estimate other than minmod + Davis
+    bool f2 = false;  // the members run the second-order Lagrangian force
     hipGraphExec_t gexec = nullptr;
     hipGraphExec_t gexec_long = nullptr;
     bool built = false;
@@ -3750,6 +3892,7 @@ int batch_build(swb_ctx *b)
     int lthr = 256;
     b->cs = false;
     b->var = false;
+    b->f2 = (b->mem[0]->par.flags & SW_FLAG_FORCE2) != 0;
     for (int m = 0; m < n; ++m) {
         sw_ctx *c = b->mem[m];
         if (c->shape != b->shape) set_shape(c, b->shape);
@@ -3824,11 +3967,11 @@ void batch_step(swb_ctx *b, hipStream_t st, int par)
     const int n = (int)b->mem.size();
     const int *dtab = b->d_table + 2 * b->ntab;
     launch_batch(b->shape, kDt, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, b->lthr, par,
-                 b->cs, b->var);
+                 b->cs, b->var, b->f2);
     launch_batch(b->shape, kLagrange, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, b->lthr, par,
-                 b->cs, b->var);
+                 b->cs, b->var, b->f2);
     launch_batch(b->shape, kEuler, st, b->d_insts, n, b->d_table, b->ntab, dtab, b->ndtab, b->lthr, par,
-                 b->cs, b->var);
+                 b->cs, b->var, b->f2);
 }
 
 // The member tables and graphs hold every member's kernel arguments: they are
@@ -3854,6 +3997,8 @@ int swb_create(int32_t n, sw_ctx *const *members, swb_ctx **out)
         if (!members[m]) return SW_ERR_ARG;
         if (members[m]->stream != members[0]->stream) return SW_ERR_ARG;
         if (members[m]->par.flags & SW_FLAG_UNFUSED) return SW_ERR_ARG;
+        // one Lagrangian kernel serves every member: one force order
+        if ((members[m]->par.flags ^ members[0]->par.flags) & SW_FLAG_FORCE2) return SW_ERR_ARG;
         for (int32_t q = 0; q < m; ++q)
             if (members[q] == members[m]) return SW_ERR_ARG;
     }
@@ -3882,6 +4027,8 @@ int swb_set_tile_shape(swb_ctx *b, int32_t tile_x, int32_t tile_y)
     if (!b) return SW_ERR_ARG;
     for (int sh = 0; sh < kNumShapes; ++sh)
         if (kShapes[sh].tx == tile_x && kShapes[sh].ty == tile_y) {
+            if ((b->mem[0]->par.flags & SW_FLAG_FORCE2) && !is_strip(sh))
+                return bfail(b, SW_ERR_ARG, "the second-order force runs on strip shapes only");
             BHIPCHK(b, hipStreamSynchronize(b->stream));
             b->shape = sh;
             b->built = false;
@@ -3991,7 +4138,9 @@ int swb_autotune(swb_ctx *b, int32_t nsteps, int32_t *tile_x, int32_t *tile_y)
     const int shape0 = b->shape;
     int best = shape0;
     float best_ms = 0.0f;
+    bool timed = false;
     for (int sh = 0; sh < kNumShapes && !rc; ++sh) {
+        if ((b->mem[0]->par.flags & SW_FLAG_FORCE2) && !is_strip(sh)) continue;
         b->shape = sh;
         b->built = false;
         if ((rc = batch_build(b))) break;
@@ -4010,7 +4159,7 @@ int swb_autotune(swb_ctx *b, int32_t nsteps, int32_t *tile_x, int32_t *tile_y)
         }
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        if (sh == 0 || ms < best_ms) { best_ms = ms; best = sh; }
+        if (!timed || ms < best_ms) { best_ms = ms; best = sh; timed = true; }
         for (int m = 0; m < n && !rc; ++m)
             if ((rc = keep_restore(b->mem[m], keep[m])))
                 rc = bfail(b, rc, "member " + std::to_string(m) + ": " + b->mem[m]->err);

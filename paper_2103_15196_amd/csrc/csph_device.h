@@ -49,6 +49,7 @@ struct KPar {
     float wsx, wsy;                 // wind stress per unit density C_w |W| W, m^2/s^2
     float inv_hsed;                 // 1 / h_sed (the wind's depth ramp)
     int force;                      // 1 when the Coriolis or the wind term acts
+    int force2;                     // 1: second-order Lagrangian force (strip kernels)
 };
 
 __device__ __forceinline__ float soil(const float *a, float s, int c) { return a ? a[c] : s; }
@@ -213,6 +214,39 @@ __device__ __forceinline__ float face_force(const KPar &P, float HdM, float bM, 
         HsLm = HsRm = fmaxf(0.0f, HdC + bC - bC);
     }
     return P.half_g_inv_dx * (HsLp * (HsLp - HsRp) - HsRm * (HsRm - HsLm));
+}
+
+// Second-order form of the same force (a reading; the paper names TVD
+// reconstruction for the Euler stage only): the hydrostatic faces take side
+// states reconstructed with the run's TVD limiter, from a cell's surface
+// z = Hd + b, depth Hd and their limited slopes sz, sh along the direction
+// (a boundary cell's slopes are zero): the plus side offers z + sz/2,
+// Hd + sh/2, the minus side z - sz/2, Hd - sh/2, each with the bed side
+// z_s - Hd_s; the face bed is the higher bed side.  Audusse et al. (2004)'s
+// centred term for the bed slope inside the cell adds -g Hd sz / dx.  At rest
+// (z constant where wet) every wet cell has sz = 0 and every face balances.
+struct ReconQ {
+    float z, h, sz, sh;
+};
+__device__ __forceinline__ float face_force2(const KPar &P, const ReconQ &M, const ReconQ &C,
+                                             const ReconQ &Q, bool hasM, bool hasQ)
+{
+    float HsLp, HsRp, HsLm, HsRm;
+    {
+        const float zL = C.z + 0.5f * C.sz, hL = C.h + 0.5f * C.sh;
+        const float zR = hasQ ? Q.z - 0.5f * Q.sz : zL, hR = hasQ ? Q.h - 0.5f * Q.sh : hL;
+        const float bf = fmaxf(zL - hL, zR - hR);
+        HsLp = fmaxf(0.0f, zL - bf);
+        HsRp = fmaxf(0.0f, zR - bf);
+    }
+    {
+        const float zR = C.z - 0.5f * C.sz, hR = C.h - 0.5f * C.sh;
+        const float zL = hasM ? M.z + 0.5f * M.sz : zR, hL = hasM ? M.h + 0.5f * M.sh : hR;
+        const float bf = fmaxf(zL - hL, zR - hR);
+        HsLm = fmaxf(0.0f, zL - bf);
+        HsRm = fmaxf(0.0f, zR - bf);
+    }
+    return P.half_g_inv_dx * ((HsLp * (HsLp - HsRp) - HsRm * (HsRm - HsLm)) - 2.0f * C.h * C.sz);
 }
 
 // Per-cell quantities the remap reconstructs along one direction:

@@ -75,6 +75,18 @@ def test_create_rejects_grids_beyond_the_32_bit_plane_offsets():
         assert not h.value
 
 
+def test_create_refuses_the_second_order_force_on_the_unfused_path():
+    """The second-order force is built into the strip kernels only: sw_create
+    refuses it with the unfused sequence before any HIP call."""
+    from paper_2103_15196_amd import csph
+    p = csph.default_params()
+    p.flags = csph.SW_FLAG_FORCE2 | csph.SW_FLAG_UNFUSED
+    h = ctypes.c_void_p()
+    g = csph.make_grid(64, 32, 1.0)
+    assert csph.lib.sw_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == csph.SW_ERR_ARG
+    assert not h.value
+
+
 def test_noalloc_rejects_grids_beyond_its_scratch_array():
     """sw_advance_noalloc checks its arguments and the size of the grid against
     its fixed scratch array before any HIP call: SW_ERR_ARG and a message."""
