@@ -308,24 +308,27 @@ def dam_break_rate(csph, W, torch, stream, n=2048, steps=1000):
     return res
 
 
-def surrogate_rates(csph, torch, train_steps=8000, trajectories=200):
+def surrogate_rates(csph, torch, train_steps=8000, trajectories=200, heldout=20):
     """The learned surrogate (6 BF16 matrix-core 3x3 convolutions, widths 5,
-    48 x 5, 4; k = 8 fixed steps of 0.03 s per call) trained here with the
-    library's training loop on 200 trajectories of 256^2 closed basins on the
+    48 x 5, 4; k = 8 fixed steps of 0.02 s per call) trained here with the
+    library's training loop on 200 trajectories of 1024^2 closed basins on the
     river valley's terrain (a reservoir released down the meandering channel,
-    per-cell soil, a random spin-up each, 12 consecutive pairs per
-    trajectory); held out: 4 basins of 1024^2 (32 pairs).  Reported: the
-    held-out depth error of one call against the 5e-3 m gate, beside the error
-    of predicting no change, and the effective rate of the surrogate step on a
+    per-cell soil, a random spin-up each; 12 consecutive pairs per trajectory,
+    each kept as a 256^2 window around a wet cell; a seed whose flow outruns
+    the fixed step is replaced by the next); held out: 20 basins of 1024^2
+    (seeds from 6000, 4 pairs each, whole grids).  Reported: the held-out
+    depth error of one call against the 5e-3 m gate, beside the error of
+    predicting no change, and the effective rate of the surrogate step on a
     1024^2 basin (conservation, stability and residual checks, fall backs
     included) next to the plain solver's 8 fixed steps."""
     import numpy as np
     from paper_2103_15196_amd import surrogate as SG
     st = torch.cuda.current_stream().cuda_stream
     t0 = time.perf_counter()
-    tr = SG.collect_valley(range(5000, 5000 + trajectories), 256, 96, 8, stream=st,
-                           depth_range=(1.5, 3.0))
-    ho = SG.collect_valley(range(7000, 7004), 1024, 64, 8, stream=st, depth_range=(1.5, 3.0))
+    tr, drop_tr = SG.collect_valley(range(5000, 5000 + 2 * trajectories), 1024, 96, 8, stream=st,
+                                    depth_range=(1.5, 3.0), crop=256, count=trajectories)
+    ho, drop_ho = SG.collect_valley(range(6000, 6000 + 5 * heldout), 1024, 32, 8, stream=st,
+                                    depth_range=(1.5, 3.0), count=heldout)
     t_data = time.perf_counter() - t0
     ins, outs = SG.scales(tr)
     net = csph.Surrogate(SG.DESIGN_CHANNELS, stream=st)
@@ -340,11 +343,12 @@ def surrogate_rates(csph, torch, train_steps=8000, trajectories=200):
     gain = SG.measure_gain(net, w, SG.VALLEY_DT, calls=20, k=8, stream=st)
     net.close()
     enabled = bool(err.max() <= 5e-3)
-    res = {"train_trajectories": trajectories, "train_grid": [256, 256],
+    res = {"train_trajectories": trajectories, "trajectory_grid": [1024, 1024],
+           "train_window": [256, 256], "dropped_seeds": drop_tr + drop_ho,
            "train_pairs": int(len(tr.x)), "train_steps": train_steps, "batch": 8,
            "first_loss": round(float(losses[0]), 5),
            "final_loss": round(float(np.mean(losses[-50:])), 5),
-           "heldout_grid": [1024, 1024], "heldout_pairs": int(len(ho.x)),
+           "heldout_seeds": heldout, "heldout_pairs": int(len(ho.x)),
            "heldout_linf_dh_m": round(float(err.max()), 5),
            "heldout_median_linf_dh_m": round(float(np.median(err)), 5),
            "no_change_linf_dh_m": round(float(zero.max()), 5),

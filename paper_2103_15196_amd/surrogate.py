@@ -61,34 +61,65 @@ def valley_basin(n, seed, depth, dx=5.0):
     return w.as_float32()
 
 
-# fixed step of the valley basins (dx = 5 m, reservoir depths up to about
-# 8 m): below their Eq. 7 bound (K = 0.3) while |v| < 2 sqrt(g H_max)
-VALLEY_DT = 0.03
+# fixed step of the valley basins (dx = 5 m, depths up to about 11 m): below
+# their Eq. 7 bound (K = 0.3) while |v| < 3 sqrt(g H_max), which the flood
+# waves running down the 1024^2 valleys' slopes approach
+VALLEY_DT = 0.02
 
 
-def collect_valley(seeds, n, steps, k, stream=None, depth_range=(1.5, 4.0), spinup=(0, 600)):
-    """Pairs from valley basins: each seed draws its reservoir depth and a
-    spin-up of fixed steps (so the pairs cover the flood wave at different
-    stages), then records steps // k consecutive pairs."""
-    xs, ds, dts = [], [], []
+def collect_valley(seeds, n, steps, k, stream=None, depth_range=(1.5, 4.0), spinup=(0, 600),
+                   crop=None, count=None):
+    """Pairs from valley basins of side n: each seed draws its reservoir depth
+    and a spin-up of fixed steps (so the pairs cover the flood wave at
+    different stages), then records steps // k consecutive pairs.  With crop,
+    each pair keeps a crop x crop window around a wet cell drawn from the
+    seed's generator (the basin is mostly dry).  A trajectory whose flow
+    outruns the fixed step (SW_ERR_CFL from the solver) is dropped; with
+    count, seeds are taken until that many trajectories are complete.
+    Returns the pairs and the list of dropped seeds."""
+    xs, ds, dts, dropped, done = [], [], [], [], 0
     for sd in seeds:
+        if count is not None and done >= count:
+            break
         rng = np.random.default_rng(sd)
         w = valley_basin(n, sd, float(rng.uniform(*depth_range)))
         s = csph.solver_for(w, stream=stream)
-        n0 = int(rng.integers(spinup[0], spinup[1] + 1))
-        if n0:
-            s.advance(n0, dt=VALLEY_DT)
-        f0 = s.get_fields()
-        for _ in range(steps // k):
-            s.advance(k, dt=VALLEY_DT)
-            f1 = s.get_fields()
-            h, hu, hv, b = f0
-            xs.append(np.stack([h, hu, hv, b, (h > 0).astype(np.float32)]))
-            ds.append(np.stack([a1 - a0 for a1, a0 in zip(f1, f0)]))
-            f0 = f1
-        s.close()
-        dts += [VALLEY_DT] * (steps // k)
-    return Pairs(np.stack(xs), np.stack(ds), k, np.array(dts))
+        tx, td = [], []
+        try:
+            n0 = int(rng.integers(spinup[0], spinup[1] + 1))
+            if n0:
+                s.advance(n0, dt=VALLEY_DT)
+            f0 = s.get_fields()
+            for _ in range(steps // k):
+                s.advance(k, dt=VALLEY_DT)
+                f1 = s.get_fields()
+                h, hu, hv, b = f0
+                x = np.stack([h, hu, hv, b, (h > 0).astype(np.float32)])
+                d = np.stack([a1 - a0 for a1, a0 in zip(f1, f0)])
+                if crop:
+                    wet = np.flatnonzero(h > 0)
+                    c = int(wet[rng.integers(len(wet))]) if len(wet) else int(rng.integers(h.size))
+                    y0 = min(max(c // w.nx - crop // 2, 0), w.ny - crop)
+                    x0 = min(max(c % w.nx - crop // 2, 0), w.nx - crop)
+                    x = x[:, y0:y0 + crop, x0:x0 + crop].copy()
+                    d = d[:, y0:y0 + crop, x0:x0 + crop].copy()
+                tx.append(x)
+                td.append(d)
+                f0 = f1
+        except csph.SwError as e:
+            if e.code != csph.SW_ERR_CFL:
+                raise
+            dropped.append(sd)
+            continue
+        finally:
+            s.close()
+        xs += tx
+        ds += td
+        dts += [VALLEY_DT] * len(tx)
+        done += 1
+    if not xs:
+        raise RuntimeError(f"no valley trajectory completed (dropped seeds {dropped})")
+    return Pairs(np.stack(xs), np.stack(ds), k, np.array(dts)), dropped
 
 
 def fixed_dt(w, factor=0.08):

@@ -293,3 +293,29 @@ def test_gpu_surrogate_training_loop_is_deterministic_and_learns():
         params.append(net.get_params())
         net.close()
     assert np.array_equal(params[0], params[1])
+
+
+def test_gpu_valley_trajectories_windows_and_drops():
+    """collect_valley on 1024^2-style valley basins (small here): consecutive
+    pairs, windows around a wet cell, the change equal to the difference of
+    the solver's states; a seed whose flow outruns the fixed step is dropped
+    and the next taken (forced here with a step far above Eq. 7's)."""
+    from paper_2103_15196_amd import csph, surrogate as SG
+    import torch
+    st = torch.cuda.current_stream().cuda_stream
+    p, dropped = SG.collect_valley(range(5000, 5004), 128, 16, 8, stream=st, crop=64, count=2,
+                                   spinup=(0, 50))
+    assert dropped == [] and p.x.shape == (4, 5, 64, 64) and p.d.shape == (4, 4, 64, 64)
+    assert all((x[0] > 0).any() for x in p.x)
+    assert np.array_equal(p.x[:, 4], (p.x[:, 0] > 0).astype(np.float32))
+    # pairs of one trajectory are consecutive: whole grids (no window) chain exactly
+    q, _ = SG.collect_valley([5000], 128, 16, 8, stream=st, spinup=(0, 50))
+    np.testing.assert_allclose(q.x[0, 0] + q.d[0, 0], q.x[1, 0], rtol=0, atol=1e-6)
+    old = SG.VALLEY_DT
+    try:
+        SG.VALLEY_DT = 5.0
+        with pytest.raises(RuntimeError) as e:
+            SG.collect_valley(range(5000, 5003), 96, 8, 8, stream=st, count=1)
+        assert "5000, 5001, 5002" in str(e.value)
+    finally:
+        SG.VALLEY_DT = old
