@@ -14,8 +14,8 @@ import numpy as np
 import pytest
 
 from paper_2103_15196_amd import workloads as W
-from tests.gpu_common import ILL_MAX, compare, run_gpu, run_oracle, say
-from tests.helpers import read_golden
+from tests.gpu_common import ILL_MAX, compare, run_gpu, run_oracle, say, torch_stream
+from tests.helpers import oracle_case, read_golden
 
 pytestmark = pytest.mark.gpu
 
@@ -327,3 +327,42 @@ def test_gpu_dam_break_2048_full_size_every_cell(O):
         f"; 99.9% of cells within {np.quantile(eh, 0.999):.2e} m")
     _check(res)
     assert res["volume_vs_oracle"] <= 1e-6
+
+
+@pytest.mark.timeout(600)
+def test_gpu_river_valley_8192_full_size_one_step_every_cell(O):
+    """The 8192 x 8192 river valley (the benchmark's workload, its launch
+    configuration: 58 x 8 strips, every tile processed, one grid of
+    per-cell-soil kernels) after 1000 steps from its initial state, inflow
+    running: one more GPU step against one FP64 oracle step from the same
+    float32 state and time, every cell of h, hu, hv and b, the step length and
+    the inflow volume of the step.  (The oracle takes about 2 s a step on the
+    grid: the full 2000-step run is out of its reach, one step from the GPU's
+    state is not.)"""
+    import time
+    from paper_2103_15196_amd import csph
+    from tests.gpu_common import field_check
+    w = W.river_valley(n=8192, steps=2000).as_float32()
+    say("case river valley 8192^2: 1000 GPU steps, then one step on both sides")
+    s = csph.solver_for(w, stream=torch_stream(), flags=0)
+    s.advance(1000)
+    h, hu, hv, b = s.get_fields()
+    s0 = s.get_sums()
+    s.advance(1)
+    g = s.get_fields()
+    s1 = s.get_sums()
+    s.close()
+    say(f"  GPU at t = {s0['t']:.4f} s, wet cells {s0['wet_cells']}; oracle step")
+    p, inp, st = oracle_case(O, w)
+    st = O.State(h, hu, hv, b, t=s0["t"])
+    t0 = time.time()
+    rec = O.step(p, inp, st)
+    say(f"  oracle step in {time.time() - t0:.1f} s, dt {rec['dt']!r} (GPU {s1['last_dt']!r})")
+    assert abs(s1["last_dt"] - rec["dt"]) <= 1e-6 * rec["dt"]
+    assert abs((s1["water_source_in"] - s0["water_source_in"]) - rec["in_w"]) <= 1e-6 * rec["in_w"]
+    vs = O.cfl(p, inp, st)["vs"]
+    f = field_check(g, st, None, vs)
+    for name, r in f.items():
+        say(f"  {name}: err {r['err']:.3e} (bound {r['bound']:.3e}) at {r['worst']}")
+        assert r["err"] <= r["bound"], name
+    assert s0["wet_cells"] > 100
