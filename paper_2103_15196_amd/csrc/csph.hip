@@ -686,10 +686,15 @@ __device__ __forceinline__ CellNew cell_update(const KPar &P, float dt, const Ce
                                                float src, float psi, float qb, float beta, float &rb,
                                                float &rh)
 {
-    float sw = F.xHw > 0.0f ? F.thW : (F.xHw < 0.0f ? F.th : 1.0f);
-    float se = F.xHe > 0.0f ? F.th : (F.xHe < 0.0f ? F.thE : 1.0f);
-    float ss = F.yHs > 0.0f ? F.thS : (F.yHs < 0.0f ? F.th : 1.0f);
-    float sn = F.yHn > 0.0f ? F.th : (F.yHn < 0.0f ? F.thN : 1.0f);
+    // the limiter of the cell the mass leaves (1 for no flux), as selects
+    float sw = F.xHw < 0.0f ? F.th : 1.0f;
+    sw = F.xHw > 0.0f ? F.thW : sw;
+    float se = F.xHe < 0.0f ? F.thE : 1.0f;
+    se = F.xHe > 0.0f ? F.th : se;
+    float ss = F.yHs < 0.0f ? F.th : 1.0f;
+    ss = F.yHs > 0.0f ? F.thS : ss;
+    float sn = F.yHn < 0.0f ? F.thN : 1.0f;
+    sn = F.yHn > 0.0f ? F.th : sn;
     CellNew o;
     o.FHw = F.xHw * sw; o.FHe = F.xHe * se; o.GHs = F.yHs * ss; o.GHn = F.yHn * sn;
     float Fxw = F.xnw * sw, Fxe = F.xne * se, Gxs = F.yts * ss, Gxn = F.ytn * sn;

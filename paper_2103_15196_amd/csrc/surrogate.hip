@@ -1037,7 +1037,7 @@ int sws_advance_K(sws_net *n, sw_ctx *solver, int32_t n_calls, int32_t k, double
         st.max_volume_drift = std::max(st.max_volume_drift, std::max(drift, bdrift));
         const double t1 = sums.t + k * dt;
         const int64_t step1 = sums.step + k;
-        if (drift > max_drift || bdrift > max_drift) {
+        if (!(drift <= max_drift) || !(bdrift <= max_drift)) {  // NaN fails too
             st.fallbacks_volume++;
             rc = sw_advance_fixed_dt(solver, k, dt);
             if (!rc) rc = sw_sync(solver);

@@ -272,6 +272,29 @@ def test_gpu_surrogate_unstable_prediction_falls_back():
     net.close()
 
 
+def test_gpu_surrogate_corrupt_weights_fall_back_to_the_plain_steps():
+    """Weights that make every prediction NaN: every call falls back on the
+    conservation check, and the final state is the plain run's, bit for bit."""
+    from paper_2103_15196_amd import csph
+    import torch
+    st = torch.cuda.current_stream().cuda_stream
+    net = csph.Surrogate((5, 16, 4), stream=st)
+    net.set_params(np.full(net.nparam, np.nan, np.float32))
+    w = _closed_basin()
+    dt = 0.02
+    s = csph.solver_for(w, stream=st)
+    stats = net.advance_k(s, 3, 8, dt, check_every=0)
+    say(f"corrupt: {stats}")
+    assert stats["kept"] == 0 and stats["fallbacks_volume"] == 3
+    r = csph.solver_for(w, stream=st)
+    r.advance(24, dt=dt)
+    for a, c in zip(s.get_fields(), r.get_fields()):
+        assert np.array_equal(a, c)
+    s.close()
+    r.close()
+    net.close()
+
+
 def test_gpu_surrogate_training_loop_is_deterministic_and_learns():
     """sws_train (minibatches from a seed, cosine learning rate) lowers the
     loss, reports it, and repeats bit for bit from the same seed."""
