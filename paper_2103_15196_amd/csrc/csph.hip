@@ -1071,6 +1071,11 @@ constexpr int kMaxStageGroups = 8192;
 // S / kLagHalves rows): more, shorter wavefronts hide the memory latency of the
 // few tiles a step lists better than they cost in extra halo rows.
 constexpr int kLagHalves = 2;
+// Tiles per wavefront in a single grid's Lagrangian stage when every tile of a
+// large grid is listed: one wavefront marches kLagGroup vertically stacked
+// tiles as one strip, so their shared halo rows are loaded and computed once
+// (the wavefronts are plentiful there).
+constexpr int kLagGroup = 4;
 
 // The value lane l-1 (lane_prev) or l+1 (lane_next) holds; 0 in the lane that
 // has no such neighbour.  Called only where all 64 lanes are active.
@@ -1878,9 +1883,10 @@ __device__ __forceinline__ int xcd_entry(int b, int wave, int n)
 //           kMaxStageGroups workgroups hold: the grid's G4 = gridDim.x * SWAVES
 //           wavefronts take the list in passes of at most G4 entries, each
 //           pass spread over the XCDs;
-//   XP = 3: (Lagrangian stage) as 1 with one wavefront per tile, for grids of
-//           more tiles than that with every tile listed: they fill the chip
-//           without the halves' extra halo rows.
+//   XP = 3: (Lagrangian stage) as 1 with one wavefront per kLagGroup
+//           vertically stacked tiles, for grids of more tiles than that with
+//           every tile listed: they fill the chip, and the taller strips
+//           spare the halo rows the halves and single tiles add.
 // (XP = 2 is a kernel of its own: the pass loop costs the Euler kernel
 // registers, and with them a wavefront per SIMD, that XP = 1 keeps.)
 template <int S, bool CS, int XP, bool F2>
@@ -1897,7 +1903,9 @@ __device__ __forceinline__ void lagrange_listed(const Inst &I, int par, int w)
     const int cl0 = I.hgs && lane < nb ? I.cnt_l[lane] : 0;
     const int ce0 = I.hgs && publisher && lane < nb ? I.cnt_e[lane] : 0;
     uint4 v = lane < nb ? I.part[lane] : make_uint4(0u, 0u, 0u, 0u);
-    int n = I.ntx * I.nty, seg = 0, start = 0;
+    // XP = 3: entries are groups of kLagGroup stacked tiles (every tile listed)
+    int n = XP == 3 ? I.ntx * ((I.nty + kLagGroup - 1) / kLagGroup) : I.ntx * I.nty;
+    int seg = 0, start = 0;
     const int G4 = XP == 2 ? (int)gridDim.x * SWAVES : 0;
     // XP = 1: LH wavefronts per listed tile, each on S / LH of its rows
     constexpr int LH = XP == 1 ? kLagHalves : 1;
@@ -1931,8 +1939,13 @@ __device__ __forceinline__ void lagrange_listed(const Inst &I, int par, int w)
     if (XP != 2) {
         if (w >= n) return;
         const int t = __builtin_amdgcn_readfirstlane(I.hgs ? I.lag[seg * I.chunk + (w - start)] : w);
-        if constexpr (F2) lagrange_strip2<S / LH, CS>(I, par, t % I.ntx, (t / I.ntx) * LH + part, dt);
-        else lagrange_strip<S / LH, CS>(I, par, t % I.ntx, (t / I.ntx) * LH + part, dt);
+        if constexpr (XP == 3) {  // a group of stacked tiles as one strip
+            if constexpr (F2) lagrange_strip2<S * kLagGroup, CS>(I, par, t % I.ntx, t / I.ntx, dt);
+            else lagrange_strip<S * kLagGroup, CS>(I, par, t % I.ntx, t / I.ntx, dt);
+        } else {
+            if constexpr (F2) lagrange_strip2<S / LH, CS>(I, par, t % I.ntx, (t / I.ntx) * LH + part, dt);
+            else lagrange_strip<S / LH, CS>(I, par, t % I.ntx, (t / I.ntx) * LH + part, dt);
+        }
         return;
     }
     for (int base = 0; base < n; base += G4) {
@@ -2511,7 +2524,9 @@ void launch_strip_t(Stage st, hipStream_t s, const Inst &I, int par, hipEvent_t 
     const bool big = need > kMaxStageGroups;
     const bool passes = I.hgs && big;
     const int gl = passes ? kMaxStageGroups : need;
-    const int gll = passes || big ? gl : (kLagHalves * I.ntx * I.nty + SWAVES - 1) / SWAVES;
+    const int gll = passes ? gl
+                    : big  ? (I.ntx * ((I.nty + kLagGroup - 1) / kLagGroup) + SWAVES - 1) / SWAVES
+                           : (kLagHalves * I.ntx * I.nty + SWAVES - 1) / SWAVES;
     const bool cs = cell_soil(I.P);
     auto lag1 = passes ? (cs ? k_lagrange_sl<S, true, 2, false> : k_lagrange_sl<S, false, 2, false>)
                 : big  ? (cs ? k_lagrange_sl<S, true, 3, false> : k_lagrange_sl<S, false, 3, false>)
