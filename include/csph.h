@@ -215,6 +215,29 @@ int sw_get_grid(const sw_ctx *ctx, sw_grid *out);
  * error is returned as by sw_get_fields. */
 int sw_step_bound(sw_ctx *ctx, double *dt);
 
+/* Step log, the record the Screen block of Section 3 shows while a run goes
+ * on: each step's time, step length, Eq. 7 maxima and binding term, and the
+ * inflow discharge, written by the device when the step's time step is
+ * published, into a ring of the last SW_STEP_LOG steps per context (cleared
+ * by a new state: sw_set_state, sw_replace_state, sw_checkpoint_load).
+ * sw_get_step_log copies the records of the last min(n, steps since the
+ * state was set, SW_STEP_LOG) steps, oldest first, into out[] (host memory,
+ * n records) and their number into *count (may be NULL).  Synchronises.  A
+ * pending device error does not stop it: the records of the steps before the
+ * failing one are returned (the failing step has none); SW_ERR_ARG for n < 0
+ * or a NULL out with n > 0. */
+#define SW_STEP_LOG 1024
+typedef struct {
+    int64_t step;     /* the step's index (the step counter before it) */
+    double t;         /* model time at its start */
+    double dt;        /* its length */
+    double vp, vs, D; /* Eq. 7 maxima of the state at its start */
+    double inflow;    /* hydrograph discharge Q(t + dt/2), m^3/s (0 without inflow) */
+    int32_t binding;  /* Eq. 7 term that set dt, as sw_sums.binding_term */
+    int32_t reserved;
+} sw_step_record;
+int sw_get_step_log(sw_ctx *ctx, int32_t n, sw_step_record *out, int32_t *count);
+
 /* Advance nsteps CSPH-TVD steps (Section 3 kernels K1..K8) with the Eq. 7
  * time step.  Asynchronous: errors raised on the device (SW_ERR_NONFINITE,
  * SW_ERR_DT_UNDERFLOW) stop all later steps and are returned by the next

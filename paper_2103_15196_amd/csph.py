@@ -49,6 +49,15 @@ class sw_params(C.Structure):
                 ("flags", C.c_uint32), ("limiter", C.c_int32), ("hll_speeds", C.c_int32)]
 
 
+SW_STEP_LOG = 1024
+
+
+class sw_step_record(C.Structure):
+    _fields_ = [("step", C.c_int64), ("t", C.c_double), ("dt", C.c_double), ("vp", C.c_double),
+                ("vs", C.c_double), ("D", C.c_double), ("inflow", C.c_double),
+                ("binding", C.c_int32), ("reserved", C.c_int32)]
+
+
 class sw_sums(C.Structure):
     _fields_ = [("t", C.c_double), ("last_dt", C.c_double), ("water_volume", C.c_double),
                 ("sediment_volume", C.c_double), ("water_boundary_out", C.c_double),
@@ -91,6 +100,7 @@ SIGNATURES = [
     ("sw_get_fields", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     ("sw_get_sums", C.c_int, [_ctxp, C.POINTER(sw_sums)]),
     ("sw_step_bound", C.c_int, [_ctxp, C.POINTER(C.c_double)]),
+    ("sw_get_step_log", C.c_int, [_ctxp, C.c_int32, C.POINTER(sw_step_record), C.POINTER(C.c_int32)]),
     ("sw_last_error", C.c_char_p, [_ctxp]),
     ("sw_save_begin", C.c_int, [_ctxp]),
     ("sw_save_wait", C.c_int, [_ctxp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -327,6 +337,15 @@ class Solver:
         s = sw_sums()
         _check(self.ctx, lib.sw_get_sums(self.ctx, C.byref(s)))
         return s.as_dict()
+
+    def step_log(self, n=SW_STEP_LOG) -> list:
+        """The records of the last min(n, steps since the state was set,
+        SW_STEP_LOG) steps, oldest first (sw_get_step_log), as dicts."""
+        buf = (sw_step_record * max(int(n), 1))()
+        cnt = C.c_int32()
+        _check(self.ctx, lib.sw_get_step_log(self.ctx, int(n), buf, C.byref(cnt)))
+        return [{k: getattr(buf[q], k) for k, _ in sw_step_record._fields_ if k != "reserved"}
+                for q in range(cnt.value)]
 
     def step_bound(self) -> float:
         """The Eq. 7 step bound of the current fields (sw_step_bound)."""

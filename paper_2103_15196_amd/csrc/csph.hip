@@ -46,6 +46,15 @@ struct Ctrl {
     unsigned long long work[2];     // cells processed by the Lagrangian / Euler stage
 };
 
+// One step's record in the step log (the layout of sw_step_record).
+struct StepRec {
+    long long step;              // steps since the state was set (the host adds its step0)
+    double t, dt, vp, vs, D, q;
+    int binding, reserved;
+};
+constexpr int kStepLog = SW_STEP_LOG;  // records in the ring (a power of two)
+static_assert((kStepLog & (kStepLog - 1)) == 0, "the step log ring is a power of two");
+
 struct StepArgs {
     int mode_fixed;              // 1: fixed dt
     double dt_fixed;
@@ -54,7 +63,18 @@ struct StepArgs {
     double q_base, q_peak, t_peak, t_sigma;
     double qb_total;             // sum over cells of (q_b^+ - q_b^-) dx^2
     double rain_area;            // rainfall rate x grid area, m^3/s
+    StepRec *log;                // step log ring (kStepLog records), or null
 };
+
+// The step's record into the log ring (the thread that publishes the step).
+__device__ __forceinline__ void log_step(const StepArgs &A, int kd, double tn, double dt,
+                                         double vp, double vs, double D, double q, int which)
+{
+    if (!A.log) return;
+    StepRec &r = A.log[kd & (kStepLog - 1)];
+    r.step = kd; r.t = tn; r.dt = dt; r.vp = vp; r.vs = vs; r.D = D; r.q = q;
+    r.binding = which; r.reserved = 0;
+}
 
 __device__ __forceinline__ unsigned fbits_nonneg(float x) { return __float_as_uint(x + 0.0f); }
 
@@ -232,6 +252,7 @@ __global__ void k_dt(Ctrl *ctrl, int k, StepArgs A)
     ctrl->last_dt = dt;
     ctrl->binding = which;
     ctrl->kdev = kd + 1;
+    log_step(A, kd, tn, dt, vp, vs, D, q, which);
 }
 
 // ---------------------------------------------------------------------------
@@ -531,6 +552,7 @@ __device__ void publish_dt(Ctrl *ctrl, int par, const StepArgs &A, uint4 m)
     ctrl->last_dt = dt;
     ctrl->binding = which;
     ctrl->kdev = kd + 1;
+    log_step(A, kd, tn, dt, ctrl->vp, ctrl->vs, ctrl->D, q, which);
 }
 
 // K3 of one grid in one 1024-thread workgroup (the maximum does not depend
@@ -2142,6 +2164,7 @@ struct sw_ctx {
     double t0 = 0.0;                 // time at k = 0
     bool have_state = false, dirty = true;
     unsigned *bound_slot = nullptr;  // NSLOT x 4 maxima of sw_step_bound
+    StepRec *steplog = nullptr;      // the step log ring (kStepLog records)
     int has_inflow = 0;
     double q_base = 0, q_peak = 0, t_peak = 0, t_sigma = 1;
     double qb_total = 0.0;
@@ -2247,6 +2270,7 @@ StepArgs make_step_args(const sw_ctx *c, int fixed, double dt)
     A.q_base = c->q_base; A.q_peak = c->q_peak; A.t_peak = c->t_peak; A.t_sigma = c->t_sigma;
     A.qb_total = c->qb_total;
     A.rain_area = c->rain * (double)c->nx * (double)c->ny * c->grid.dx * c->grid.dx;
+    A.log = c->steplog;
     return A;
 }
 
@@ -2855,6 +2879,8 @@ int sw_create(const sw_grid *grid, const sw_params *params, void *hip_stream, sw
     }
     size_t nb = 4 * (size_t)(c->nx + c->ny);
     if ((e = hipMalloc(&c->bnd, nb * sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(bnd)");
+    if ((e = hipMalloc(&c->steplog, kStepLog * sizeof(StepRec))) != hipSuccess)
+        return bail(e, "hipMalloc(step log)");
     if ((e = hipMemsetAsync(c->bnd, 0, nb * sizeof(double), c->stream)) != hipSuccess) return bail(e, "hipMemset(bnd)");
     c->sum_rows = std::max(1, (int)((c->ny + 1023) / 1024));
     c->nsum_blocks = (c->ny + c->sum_rows - 1) / c->sum_rows;
@@ -2895,6 +2921,7 @@ int sw_destroy(sw_ctx *c)
     (void)hipFree(c->part);
     (void)hipFree(c->ctrl);
     (void)hipFree(c->bound_slot);
+    (void)hipFree(c->steplog);
     (void)hipFree(c->nM);
     (void)hipFree(c->d50);
     (void)hipFree(c->psi);
@@ -3395,6 +3422,28 @@ int sw_step_bound(sw_ctx *c, double *dt)
     const double t2 = D > 0.0 ? h * h / (2.0 * D) : INFINITY;
     const double bound = c->par.cfl * std::min(t0, std::min(t1, t2));
     *dt = bound < c->par.dt_max ? bound : c->par.dt_max;
+    return SW_OK;
+}
+
+int sw_get_step_log(sw_ctx *c, int32_t n, sw_step_record *out, int32_t *count)
+{
+    if (!c || n < 0 || (n > 0 && !out)) return SW_ERR_ARG;
+    Ctrl hc;
+    int rc = read_ctrl(c, &hc);
+    if (rc) return rc;
+    const int taken = hc.kdev;  // steps published since the state was set
+    const int m = std::min(std::min(n, taken), kStepLog);
+    if (count) *count = m;
+    if (m == 0) return SW_OK;
+    std::vector<StepRec> ring(kStepLog);
+    if ((rc = stage_to_host(c, ring.data(), c->steplog, kStepLog * sizeof(StepRec)))) return rc;
+    for (int q = 0; q < m; ++q) {  // oldest first
+        const StepRec &r = ring[(taken - m + q) & (kStepLog - 1)];
+        sw_step_record &o = out[q];
+        o.step = c->step0 + r.step;
+        o.t = r.t; o.dt = r.dt; o.vp = r.vp; o.vs = r.vs; o.D = r.D; o.inflow = r.q;
+        o.binding = r.binding; o.reserved = 0;
+    }
     return SW_OK;
 }
 

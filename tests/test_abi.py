@@ -45,6 +45,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(csph.sw_grid) == 4 + 4 + 8 + 16
     assert ctypes.sizeof(csph.sw_params) == 11 * 8 + 4 + 4 + 4 + 4
     assert ctypes.sizeof(csph.sws_stats) == 5 * 4 + 4 + 8 + 8 + 4 + 4
+    assert ctypes.sizeof(csph.sw_step_record) == 8 + 6 * 8 + 4 + 4
     p = csph.default_params()
     assert p.cfl == 0.3 and p.eps_dry == 1e-5 and p.sed_law == csph.SW_SED_EQ4
     assert p.limiter == csph.SW_LIM_MINMOD and p.hll_speeds == csph.SW_HLL_DAVIS

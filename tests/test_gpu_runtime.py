@@ -203,3 +203,39 @@ def test_gpu_step_bound_is_the_next_steps_eq7_step():
         s.step_bound()
     assert e.value.code == csph.SW_ERR_NONFINITE
     s.close()
+
+
+def test_gpu_step_log_records_each_step():
+    """The step log (the Screen block's record) holds one record per step:
+    the times chain exactly (t + dt is the next record's t), the last record
+    is what sw_get_sums reports (step length, Eq. 7 maxima, binding term),
+    the inflow is the hydrograph at t + dt/2; fixed steps record binding 4;
+    past SW_STEP_LOG steps only the last ones remain, consecutive; a new
+    state clears it."""
+    import math
+    from paper_2103_15196_amd import csph
+    w = _small_valley()
+    s = csph.solver_for(w, stream=torch_stream())
+    s.advance(50)
+    log = s.step_log()
+    assert [r["step"] for r in log] == list(range(50))
+    for a, b in zip(log, log[1:]):
+        assert b["t"] == a["t"] + a["dt"]
+    sums = s.get_sums()
+    last = log[-1]
+    assert last["dt"] == sums["last_dt"] and last["binding"] == sums["binding_term"]
+    assert (last["vp"], last["vs"], last["D"]) == (sums["vp"], sums["vs"], sums["D"])
+    assert sums["t"] == last["t"] + last["dt"]
+    for r in log:
+        d = r["t"] + 0.5 * r["dt"] - w.t_peak
+        q = w.Q_base + w.Q_peak * math.exp(-d * d / (2.0 * w.t_sigma ** 2))
+        assert abs(r["inflow"] - q) <= 1e-12 * q
+    s.advance(1100, dt=0.05)
+    log = s.step_log()
+    assert len(log) == csph.SW_STEP_LOG
+    assert [r["step"] for r in log] == list(range(1150 - csph.SW_STEP_LOG, 1150))
+    assert all(r["binding"] == 4 and r["dt"] == 0.05 for r in log)
+    assert len(s.step_log(10)) == 10 and s.step_log(10)[-1]["step"] == 1149
+    s.reset(w)
+    assert s.step_log() == []
+    s.close()
