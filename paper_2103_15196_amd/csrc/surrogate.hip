@@ -284,16 +284,27 @@ __global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, 
     const long total = npix_img * nimg;
     for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < total;
          p += (long)gridDim.x * blockDim.x) {
-        const long img = p / npix_img, q = p % npix_img;
-        for (int c = 0; c < cs; ++c) {
-            float gv = 0.0f;
-            if (c < cout) {
-                const long i = (img * cout + c) * npix_img + q;
-                const float d = y[i] - t[i];
-                s += (double)d * (double)d;
-                gv = (float)(2.0 * inv_n * (double)d);
+        const long img = p / npix_img, q = p - img * npix_img;
+        // the pixel's cs BF16 values (cout gradients, zeros after them) leave
+        // as 16-byte chunks (cs is a stored width: a multiple of 8)
+        uint4 *gp = reinterpret_cast<uint4 *>(g + p * cs);
+        for (int c8 = 0; c8 < cs; c8 += 8) {
+            unsigned short v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int c = c8 + k;
+                float gv = 0.0f;
+                if (c < cout) {
+                    const long i = (img * cout + c) * npix_img + q;
+                    const float d = y[i] - t[i];
+                    s += (double)d * (double)d;
+                    gv = (float)(2.0 * inv_n * (double)d);
+                }
+                v[k] = bf16_bits(gv);
             }
-            g[p * cs + c] = bf16_bits(gv);
+            uint4 u;
+            __builtin_memcpy(&u, v, 16);
+            gp[c8 / 8] = u;
         }
     }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
