@@ -63,7 +63,9 @@ __device__ __forceinline__ float soil(const float *a, float s, int c) { return a
 // reciprocal and two residual steps q + r (a - b q) the quotient.  In this
 // range both are the correctly rounded results (what sqrtf and a / b give),
 // without the scaling and special-value handling that only operands outside
-// it need.  (A numerator of -0 gives +0.)
+// it need.  (A numerator of -0 gives +0.)  The square root's correction is
+// Tuckerman's rounding test; the quotient's, Markstein's Newton-Raphson
+// refinement with a final residual correction.
 __device__ __forceinline__ float nsqrt(float x)
 {
     const float s = __builtin_amdgcn_sqrtf(x);
