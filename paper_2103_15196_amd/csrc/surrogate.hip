@@ -322,97 +322,249 @@ __global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, 
 // a GEMM D[n][j] = sum_p A[n][p] B[p][j] with j = 9 c + 3 ky + kx (so D is
 // W's gradient in parameter order), M = cout, N = 9 cin, and the pixels as
 // the reduction (BF16 products, FP32 accumulation, split over workgroups).
-// A job is 64 pixels of one row: dz is staged transposed, sdz[n][i], and the
-// three input rows once per horizontal shift, sxt[kx][c][ky][i] = x at
-// (y + ky - 1, x0 + i + kx - 1), so every A and B fragment (8 consecutive
-// pixels of one channel) is one aligned 16-byte LDS read.  Wavefront w owns
-// the output blocks w, w + DWW, ...; each workgroup writes its partials (one
-// slice per workgroup, summed in a fixed order by k_dw_sum).
-constexpr int DWX = 64;            // pixels per job
-constexpr int DWP = DWX + 8;       // padded LDS row (bf16)
-constexpr int DWW = 8;             // wavefronts of a weight-gradient workgroup
+//
+// Work item: R consecutive rows of one 64-pixel column strip of one image.
+// Its steps s = 0, 1 stage the input rows ya - 1 and ya; step s >= 2 stages
+// input row y + 1 and the dz row y = ya + s - 2, then adds the products of
+// row y.  The input rows sit in a ring of three LDS slots (image row gy in
+// slot (gy + 1) mod 3), so every input row is loaded and staged once per
+// item.  Both operands are staged transposed, pixels contiguous, so an A or
+// B fragment (8 consecutive pixels of one row n or column j) is one aligned
+// 16-byte LDS read:
+//   sdz[n][i]                 = dz at (y, x0 + i),
+//   sx[9 c + 3 slot + kx][i]  = x at (gy, x0 + i + kx - 1)
+// (consecutive columns j read rows 4 banks apart: no bank conflicts).  The
+// bias gradient is one more GEMM column, j = 9 cin, whose B rows are ones
+// (three LDS rows of ones, one per slot, staged once).  A staging task is
+// 8 pixels x 4 channels: 8-byte channels-last buffer loads from a resource
+// spanning one image row (10 pixels for the input, whose three horizontal
+// shifts need the neighbours; a pixel outside the image takes an offset
+// beyond the resource, which the hardware answers with zeros), a transpose
+// of BF16 pairs in registers and 16-byte LDS stores.  Two loader
+// groups of threads (tid < 256, tid >= 256) take the steps alternately, each
+// loading the step after next while the products run, so two steps of loads
+// are in flight.  Wavefront w owns the column blocks w, w + DWW, ... and all
+// row blocks, with the A fragments of a 32-pixel chunk in registers (each
+// B fragment read feeds NBM MFMAs).  Each workgroup writes its partials (one slice per
+// workgroup, summed in a fixed order by k_dw_sum).
+constexpr int DWX = 64;                                  // pixels per strip
+constexpr int DWP = DWX + 8;                             // padded LDS row (bf16): 144 bytes
+constexpr int DWW = 8;                                   // wavefronts of a workgroup
 constexpr int DWT = 64 * DWW;
-constexpr int DW_MAXB = ((MAXW / 16) * ((9 * MAXW + 15) / 16) + DWW - 1) / DWW;
-__global__ void __launch_bounds__(DWT) k_dw(const unsigned short *__restrict__ x, int cs, int cin,
-                                            const unsigned short *__restrict__ dz, int dcs,
-                                            int cout, int nimg, int nx, int ny,
-                                            float *__restrict__ part)
+constexpr int DWJ = ((9 * MAXW + 16) / 16 + DWW - 1) / DWW;  // column blocks per wavefront (+ bias)
+constexpr int DW_ONES = 9 * MAXW;                        // first of the three rows of ones
+constexpr unsigned DW_OOB = 0x80000000u;                 // an offset beyond every resource
+constexpr int DW_ZT = 96;                                // first dz task within a loader group
+
+// BF16 pairs (low half of a with low half of b), (high half of a with high
+// of b): one byte permute each (selector bytes 0-3 pick bytes of a, 4-7 bytes of b)
+__device__ __forceinline__ unsigned pair_lo(unsigned a, unsigned b) { return __builtin_amdgcn_perm(b, a, 0x05040100u); }
+__device__ __forceinline__ unsigned pair_hi(unsigned a, unsigned b) { return __builtin_amdgcn_perm(b, a, 0x07060302u); }
+// channel e (0..3) of a 4-channel chunk, pixels a (low half) and b (high half)
+__device__ __forceinline__ unsigned pair_ch(const uint2 &a, const uint2 &b, int e)
+{
+    const unsigned wa = e < 2 ? a.x : a.y, wb = e < 2 ? b.x : b.y;
+    return (e & 1) ? pair_hi(wa, wb) : pair_lo(wa, wb);
+}
+
+// One step of a work item (uniform across the workgroup).
+struct DwStep {
+    long it;                  // item index
+    int s, nrow;              // step, rows of the item
+    int img, x0, ya;          // image, first pixel of the strip, first row
+};
+
+template <int NBM>  // row blocks: ceil(cout / 16)
+__global__ void __launch_bounds__(DWT) __attribute__((amdgpu_waves_per_eu(4))) k_dw(
+    const unsigned short *__restrict__ x, int cs, int cin, const unsigned short *__restrict__ dz, int dcs,
+    int cout, int nimg, int nx, int ny, float *__restrict__ part)
 {
     __shared__ __attribute__((aligned(16))) unsigned short sdz[MAXW][DWP];
-    __shared__ __attribute__((aligned(16))) unsigned short sxt[3][MAXW][3][DWP];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ __attribute__((aligned(16))) unsigned short sx[9 * MAXW + 9][DWP];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = lane & 15, kg = lane >> 4;
-    const int jcols = 9 * cin, nbj = (jcols + 15) / 16, nbm = (cout + 15) / 16;
-    const int nblk = nbm * nbj;
-    // rows n >= cout of sdz and channels c >= cin of sxt are never staged: zero
-    for (int q = threadIdx.x; q < MAXW * DWP; q += DWT) (&sdz[0][0])[q] = 0;
-    for (int q = threadIdx.x; q < 3 * MAXW * 3 * DWP; q += DWT) (&sxt[0][0][0][0])[q] = 0;
-    floatx4 acc[DW_MAXB];
+    const int jcols = 9 * cin, nbj = (jcols + 16) / 16;  // + the bias column
+    const int ncx = (cin + 3) / 4, ncz = (cout + 3) / 4;  // 4-channel groups
+    // loader role: group grp stages the steps of its parity; within it,
+    // l < 8 ncx is the input task (g, cg), DW_ZT <= l < DW_ZT + 8 ncz the
+    // dz task (g, cg); g = group of 8 pixels, cg = group of 4 channels
+    const int grp = tid >> 8, l = tid & 255;
+    const bool tx = l < 8 * ncx, tz = l >= DW_ZT && l < DW_ZT + 8 * ncz;
+    const int tl = tz ? l - DW_ZT : l;
+    const int tg = tl & 7, tcg = tl >> 3;
+    // this lane's GEMM columns: sx row 9 c + kx + 3 slot(ky), kept as
+    // 4 (9 c + kx) + ky; the bias column reads the rows of ones
+    int col[DWJ];
 #pragma unroll
-    for (int t = 0; t < DW_MAXB; ++t) acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    float accb = 0.0f;
+    for (int t = 0; t < DWJ; ++t) {
+        const int j = 16 * (wv + DWW * t) + m;
+        const int jj = min(j, jcols - 1);
+        const int c = jj / 9, tap = jj - 9 * c, ky = tap / 3, kx = tap - 3 * ky;
+        col[t] = j == jcols ? 4 * DW_ONES : 4 * (9 * c + kx) + ky;
+    }
+    // rows of sdz and sx that are read but never staged hold zeros (their
+    // products land only in D entries that are not written)
+    for (int q = tid; q < MAXW * DWP / 8; q += DWT) reinterpret_cast<uint4 *>(&sdz[0][0])[q] = make_uint4(0u, 0u, 0u, 0u);
+    for (int q = tid; q < (9 * MAXW + 9) * DWP / 8; q += DWT) {
+        const unsigned one = q >= DW_ONES * DWP / 8 ? 0x3f803f80u : 0u;  // BF16 1.0 pairs
+        reinterpret_cast<uint4 *>(&sx[0][0])[q] = make_uint4(one, one, one, one);
+    }
+    floatx4 acc[DWJ][NBM];
+#pragma unroll
+    for (int t = 0; t < DWJ; ++t)
+#pragma unroll
+        for (int b = 0; b < NBM; ++b) acc[t][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    // work items: R rows of a strip, about one item per workgroup
     const int xblocks = (nx + DWX - 1) / DWX;
-    const long jobs = (long)nimg * ny * xblocks;
-    for (long job = blockIdx.x; job < jobs; job += gridDim.x) {
-        const int xb = (int)(job % xblocks);
-        const long rowi = job / xblocks;
-        const int y = (int)(rowi % ny), img = (int)(rowi / ny);
-        const int x0 = xb * DWX;
-        __syncthreads();  // the previous job is done with the staged rows
-        for (int q = threadIdx.x; q < DWX * cout; q += DWT) {
-            const int n = q % cout, i = q / cout, gx = x0 + i;
-            sdz[n][i] = gx < nx ? dz[(((long)img * ny + y) * nx + gx) * dcs + n] : 0;
-        }
-        for (int q = threadIdx.x; q < 3 * (DWX + 2) * cin; q += DWT) {
-            const int c = q % cin, xx = (q / cin) % (DWX + 2), r = q / (cin * (DWX + 2));
-            const int gy = y + r - 1, gx = x0 + xx - 1;
-            unsigned short v = 0;
-            if ((unsigned)gy < (unsigned)ny && (unsigned)gx < (unsigned)nx)
-                v = x[(((long)img * ny + gy) * nx + gx) * cs + c];
+    const long strips = (long)nimg * xblocks;
+    const long G = gridDim.x;
+    const int R = (int)max(1L, (strips * ny + G - 1) / G);
+    const int cps = (ny + R - 1) / R;
+    const long items = strips * cps;
+    auto first = [&](long it, DwStep &st) -> bool {
+        if (it >= items) return false;
+        const int q = (int)(it % cps);
+        const long sp = it / cps;
+        st.it = it;
+        st.s = 0;
+        st.ya = q * R;
+        st.nrow = min(R, ny - st.ya);
+        st.x0 = (int)(sp % xblocks) * DWX;
+        st.img = (int)(sp / xblocks);
+        return true;
+    };
+    auto next = [&](DwStep &st) -> bool {
+        if (++st.s < st.nrow + 2) return true;
+        return first(st.it + G, st);
+    };
+
+    // the loads of one step, into registers
+    uint2 v[10];
+    auto fetch = [&](const DwStep &st) {
+        if (tx) {  // pixels x0 + 8 g - 1 .. x0 + 8 g + 8 of input row ya + s - 1 (zeros outside)
+            const int gy = st.ya + st.s - 1;
+            const bool rowok = (unsigned)gy < (unsigned)ny;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(x + ((long)st.img * ny + (rowok ? gy : 0)) * nx * cs), (short)0,
+                rowok ? nx * cs * 2 : 0, 0x00020000);
+            const int p0 = st.x0 + 8 * tg - 1;
 #pragma unroll
-            for (int kx = 0; kx < 3; ++kx) {  // pixel i sees column xx = i + kx
-                const int i = xx - kx;
-                if (i >= 0 && i < DWX) sxt[kx][c][r][i] = v;
+            for (int e = 0; e < 10; ++e) {
+                const int px = p0 + e;
+                const unsigned off = (unsigned)px < (unsigned)nx ? (unsigned)(px * cs + 4 * tcg) * 2u : DW_OOB;
+                const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+                v[e] = make_uint2(w[0], w[1]);
+            }
+        } else if (tz && st.s >= 2) {  // pixels x0 + 8 g .. x0 + 8 g + 7 of dz row ya + s - 2
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(dz + ((long)st.img * ny + st.ya + st.s - 2) * nx * dcs), (short)0, nx * dcs * 2,
+                0x00020000);
+            const int p0 = st.x0 + 8 * tg;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int px = p0 + e;
+                const unsigned off = px < nx ? (unsigned)(px * dcs + 4 * tcg) * 2u : DW_OOB;
+                const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+                v[e] = make_uint2(w[0], w[1]);
+            }
+        }
+    };
+
+    DwStep cur, ahead;  // the step being computed; the last step whose loads were issued
+    bool has = first(blockIdx.x, cur);
+    ahead = cur;
+    bool hasa = has && next(ahead);
+    if (grp == 0 && has) fetch(cur);
+    if (grp == 1 && hasa) fetch(ahead);
+    for (int k = 0; has; ++k) {
+        const bool mine = grp == (k & 1);
+        __syncthreads();  // the previous step is done with the slots it read
+        if (mine) {
+            if (tx) {
+                // sx[9 c + 3 slot + kx][8 g + i] = pixel x0 + 8 g + i + kx - 1 = v[i + kx]
+                const int slot = (cur.ya + cur.s) % 3;  // (gy + 1) mod 3
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int c = 4 * tcg + e;
+                    uint4 *row = reinterpret_cast<uint4 *>(&sx[9 * c + 3 * slot][8 * tg]);
+                    const unsigned p0 = pair_ch(v[0], v[1], e), p2 = pair_ch(v[2], v[3], e),
+                                   p4 = pair_ch(v[4], v[5], e), p6 = pair_ch(v[6], v[7], e),
+                                   p8 = pair_ch(v[8], v[9], e);
+                    row[0] = make_uint4(p0, p2, p4, p6);  // kx = 0
+                    row[DWP / 8] = make_uint4(pair_ch(v[1], v[2], e), pair_ch(v[3], v[4], e),
+                                              pair_ch(v[5], v[6], e), pair_ch(v[7], v[8], e));
+                    row[2 * DWP / 8] = make_uint4(p2, p4, p6, p8);  // kx = 2
+                }
+            } else if (tz && cur.s >= 2) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    *reinterpret_cast<uint4 *>(&sdz[4 * tcg + e][8 * tg]) =
+                        make_uint4(pair_ch(v[0], v[1], e), pair_ch(v[2], v[3], e),
+                                   pair_ch(v[4], v[5], e), pair_ch(v[6], v[7], e));
             }
         }
         __syncthreads();
+        {  // this group loads the step after next
+            DwStep n2 = ahead;
+            const bool h2 = hasa && next(n2);
+            if (mine && h2) fetch(n2);
+            ahead = n2;
+            hasa = h2;
+        }
+        if (cur.s >= 2) {  // products of row y = ya + s - 2 (input rows y - 1 .. y + 1)
+            const int ym = (cur.ya + cur.s - 2) % 3;  // tap ky reads slot (y + ky) mod 3
+            // byte offsets of this lane's fragments; the A fragments of both
+            // 32-pixel chunks stay in registers, each column block reads its
+            // two B fragments before its MFMAs
+            const char *sxb = reinterpret_cast<const char *>(&sx[0][0]);
+            const char *szb = reinterpret_cast<const char *>(&sdz[0][0]);
+            const unsigned aoff = (unsigned)m * (2u * DWP) + 16u * kg;
+            bf16x8 a[NBM][2];
 #pragma unroll
-        for (int t = 0; t < DW_MAXB; ++t) {
-            const int bi = wv + DWW * t;
-            if (bi >= nblk) break;
-            const int nb = bi / nbj, jb = bi - nb * nbj;
-            const int n = 16 * nb + m, j = 16 * jb + m;
-            const int jj = min(j, jcols - 1);
-            const int c = jj / 9, tap = jj - 9 * c, ky = tap / 3, kx = tap - 3 * ky;
+            for (int b = 0; b < NBM; ++b)
 #pragma unroll
-            for (int k0 = 0; k0 < DWX; k0 += 32) {
-                bf16x8 av, bv;
-                const uint4 a4 = *reinterpret_cast<const uint4 *>(&sdz[n][k0 + 8 * kg]);
-                uint4 b4 = *reinterpret_cast<const uint4 *>(&sxt[kx][c][ky][k0 + 8 * kg]);
-                if (j >= jcols) b4 = make_uint4(0u, 0u, 0u, 0u);
-                __builtin_memcpy(&av, &a4, 16);
-                __builtin_memcpy(&bv, &b4, 16);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+                for (int ks = 0; ks < 2; ++ks) {
+                    const uint4 w = *reinterpret_cast<const uint4 *>(szb + aoff + b * 16 * (2 * DWP) + 64 * ks);
+                    __builtin_memcpy(&a[b][ks], &w, 16);
+                }
+#pragma unroll
+            for (int t = 0; t < DWJ; ++t) {
+                if (wv + DWW * t >= nbj) break;
+                int slot = ym + (col[t] & 3);
+                slot = slot >= 3 ? slot - 3 : slot;
+                const unsigned boff = (unsigned)((col[t] >> 2) + 3 * slot) * (2u * DWP) + 16u * kg;
+                const uint4 w0 = *reinterpret_cast<const uint4 *>(sxb + boff);
+                const uint4 w1 = *reinterpret_cast<const uint4 *>(sxb + boff + 64);
+                bf16x8 b0, b1;
+                __builtin_memcpy(&b0, &w0, 16);
+                __builtin_memcpy(&b1, &w1, 16);
+#pragma unroll
+                for (int b = 0; b < NBM; ++b)
+                    acc[t][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[b][0], b0, acc[t][b], 0, 0, 0);
+#pragma unroll
+                for (int b = 0; b < NBM; ++b)
+                    acc[t][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[b][1], b1, acc[t][b], 0, 0, 0);
             }
         }
-        if ((int)threadIdx.x < cout)
-            for (int i = 0; i < DWX; ++i) accb += bf16_float(sdz[threadIdx.x][i]);
+        has = next(cur);
     }
-    // lane holds D[16 nb + 4 kg + i][16 jb + m], i = 0..3
+    // lane holds D[16 b + 4 kg + i][16 jb + m], i = 0..3; column jcols is the bias
     float *mine = part + (long)blockIdx.x * (cout * jcols + cout);
 #pragma unroll
-    for (int t = 0; t < DW_MAXB; ++t) {
-        const int bi = wv + DWW * t;
-        if (bi >= nblk) break;
-        const int nb = bi / nbj, jb = bi - nb * nbj;
+    for (int t = 0; t < DWJ; ++t) {
+        const int jb = wv + DWW * t;
+        if (jb >= nbj) break;
         const int j = 16 * jb + m;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int n = 16 * nb + 4 * kg + i;
-            if (n < cout && j < jcols) mine[n * jcols + j] = acc[t][i];
-        }
+        for (int b = 0; b < NBM; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int n = 16 * b + 4 * kg + i;
+                if (n < cout && j < jcols) mine[n * jcols + j] = acc[t][b][i];
+                if (n < cout && j == jcols) mine[cout * jcols + n] = acc[t][b][i];
+            }
     }
-    if ((int)threadIdx.x < cout) mine[cout * jcols + threadIdx.x] = accb;
 }
 
 // Sum of the per-workgroup partial gradients (fixed order) into grad.
@@ -933,7 +1085,8 @@ int compute_grads(sws_net *n, const float *x, const float *target, int32_t nimg,
     for (int l = L - 1; l >= 0; --l) {
         // weight and bias gradients of layer l from dz_l (gcur) and its input act[l]
         const int cin = n->ch[l], cout = n->ch[l + 1];
-        hipLaunchKernelGGL(k_dw, dim3(DW_GRID), dim3(DWT), 0, n->stream, s.act[l], stored(cin), cin,
+        auto dw = cout > 32 ? k_dw<3> : cout > 16 ? k_dw<2> : k_dw<1>;
+        hipLaunchKernelGGL(dw, dim3(DW_GRID), dim3(DWT), 0, n->stream, s.act[l], stored(cin), cin,
                            gcur, cs_out, cout, nimg, nx, ny, s.dwpart);
         const int len = cout * cin * 9 + cout;
         hipLaunchKernelGGL(k_dw_sum, dim3((len + DWS_COLS - 1) / DWS_COLS), dim3(256), 0, n->stream,

@@ -70,8 +70,13 @@ def test_gpu_surrogate_forward_spans_several_tiles():
     net.close()
 
 
+# (1101, 70): the weight-gradient kernel's work items span several rows (its
+# ring of staged input rows is reused) and the last item of a strip is
+# shorter; (3, 16640): more 64-pixel strips than workgroups, so workgroups
+# take several items
 @pytest.mark.parametrize("chans,hw", [((5, 16, 11, 4), (19, 41)), (DESIGN, (19, 41)),
-                                     (DESIGN, (45, 133))])
+                                     (DESIGN, (45, 133)), (DESIGN, (1101, 70)),
+                                     (DESIGN, (3, 16640))])
 def test_gpu_surrogate_gradients_match_oracle(chans, hw):
     net, Ws, bs = _net(chans, seed=20)
     rng = np.random.default_rng(4)
