@@ -97,14 +97,14 @@ constexpr int TW = 64;     // output pixels per tile row
 constexpr int CW = 8;      // wavefronts (output rows per step) of a convolution workgroup
 constexpr int CT = 64 * CW;
 
-// LDS of one convolution workgroup: packed weights, then the staged input
-// rows (reused for the waves' output tiles)
+// LDS of one convolution workgroup: packed weights, the staged input rows
+// and the waves' output tiles
 template <int NB, int KC>
 constexpr int conv_lds_bytes()
 {
     constexpr int PXU = (KC == 3 ? CIN0 : MAXW) * 2 / 16;
     constexpr int SU = (CW + 2) * (TW + 2) * PXU, OU = TW * NB * 2;
-    return 16 * (NB * KC * 64 + (SU > CW * OU ? SU : CW * OU));
+    return 16 * (NB * KC * 64 + SU + CW * OU);
 }
 
 template <int NB, int KC>
@@ -122,9 +122,9 @@ __global__ void __launch_bounds__(CT) k_conv(const unsigned short *__restrict__ 
     constexpr int SU = SROWS * ROWU;            // staged uint4 per step
     constexpr int PER = (SU + CT - 1) / CT;     // staged uint4 per thread
     constexpr int OU = TW * NB * 2;             // uint4 of one wave's BF16 output tile
-    constexpr int XU = SU > CW * OU ? SU : CW * OU;
     __shared__ uint4 sw[NB * KC * 64];
-    __shared__ uint4 sx[XU];  // staged input rows; then the waves' output tiles
+    __shared__ uint4 sx[SU];       // staged input rows
+    __shared__ uint4 st[CW * OU];  // the waves' output tiles (one region per wave)
     const uint4 *w4 = reinterpret_cast<const uint4 *>(wpk);
     for (int q = threadIdx.x; q < NB * KC * 64; q += CT) sw[q] = w4[q];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -148,8 +148,36 @@ __global__ void __launch_bounds__(CT) k_conv(const unsigned short *__restrict__ 
         }
     };
     // BF16 NHWC outputs of exactly NB * 16 channels leave through LDS as
-    // whole 16-byte pixel chunks
+    // whole 16-byte pixel chunks: a wave writes its tile into its own region
+    // of st after its MFMAs and stores it to memory in the next step, before
+    // that step's input loads are issued (a wait for the loads then finds the
+    // stores, which the same counter tracks, long done)
     const bool tile_out = mode != 1 && out_c == NB * 16 && (mode == 0 || mask_c == out_c);
+    auto flush = [&](int y) {
+        if (y >= ye) return;
+        unsigned short *ob = static_cast<unsigned short *>(out);
+        for (int q = lane; q < OU; q += 64) {
+            const int px = q / (NB * 2), part = q - px * (NB * 2);
+            const int xx = x0 + px;
+            if (xx >= nx) continue;
+            const long pix = ((long)img * ny + y) * nx + xx;
+            uint4 v = st[wv * OU + q];
+            if (mode == 2) {  // the gradient flows only where the activation is > 0
+                const uint4 mk = *reinterpret_cast<const uint4 *>(mask + pix * mask_c + part * 8);
+                unsigned vv[4] = {v.x, v.y, v.z, v.w};
+                const unsigned mm[4] = {mk.x, mk.y, mk.z, mk.w};
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const bool lo = bf16_float((unsigned short)(mm[h] & 0xffffu)) > 0.0f;
+                    const bool hi = bf16_float((unsigned short)(mm[h] >> 16)) > 0.0f;
+                    vv[h] &= (lo ? 0x0000ffffu : 0u) | (hi ? 0xffff0000u : 0u);
+                }
+                v = make_uint4(vv[0], vv[1], vv[2], vv[3]);
+            }
+            *reinterpret_cast<uint4 *>(ob + pix * out_c + part * 8) = v;
+        }
+    };
+    int pending = -1;  // row of the tile waiting in st (tile_out), or -1
     fetch(ys);
     for (int y0 = ys; y0 < ye; y0 += CW) {
         __syncthreads();  // the previous step is done with sx
@@ -159,6 +187,7 @@ __global__ void __launch_bounds__(CT) k_conv(const unsigned short *__restrict__ 
             if (q < SU) sx[q] = pre[j];
         }
         __syncthreads();
+        if (pending >= 0) flush(pending);
         if (y0 + CW < ye) fetch(y0 + CW);
         floatx4 acc[4][NB];
 #pragma unroll
@@ -193,8 +222,7 @@ __global__ void __launch_bounds__(CT) k_conv(const unsigned short *__restrict__ 
         // (i = 0..3) of row y, channel 16 b + m
         const int y = y0 + wv;
         if (tile_out) {
-            __syncthreads();  // every wave is done reading the staged rows
-            unsigned short *so = reinterpret_cast<unsigned short *>(sx + wv * OU);
+            unsigned short *so = reinterpret_cast<unsigned short *>(st + wv * OU);
 #pragma unroll
             for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
@@ -207,30 +235,7 @@ __global__ void __launch_bounds__(CT) k_conv(const unsigned short *__restrict__ 
                         so[(16 * mb + 4 * kg + i) * (NB * 16) + n] = bf16_bits(v);
                     }
                 }
-            __syncthreads();
-            if (y < ye) {
-                unsigned short *ob = static_cast<unsigned short *>(out);
-                for (int q = lane; q < OU; q += 64) {
-                    const int px = q / (NB * 2), part = q - px * (NB * 2);
-                    const int xx = x0 + px;
-                    if (xx >= nx) continue;
-                    const long pix = ((long)img * ny + y) * nx + xx;
-                    uint4 v = sx[wv * OU + q];
-                    if (mode == 2) {  // the gradient flows only where the activation is > 0
-                        const uint4 mk = *reinterpret_cast<const uint4 *>(mask + pix * mask_c + part * 8);
-                        unsigned vv[4] = {v.x, v.y, v.z, v.w};
-                        const unsigned mm[4] = {mk.x, mk.y, mk.z, mk.w};
-#pragma unroll
-                        for (int h = 0; h < 4; ++h) {
-                            const bool lo = bf16_float((unsigned short)(mm[h] & 0xffffu)) > 0.0f;
-                            const bool hi = bf16_float((unsigned short)(mm[h] >> 16)) > 0.0f;
-                            vv[h] &= (lo ? 0x0000ffffu : 0u) | (hi ? 0xffff0000u : 0u);
-                        }
-                        v = make_uint4(vv[0], vv[1], vv[2], vv[3]);
-                    }
-                    *reinterpret_cast<uint4 *>(ob + pix * out_c + part * 8) = v;
-                }
-            }
+            pending = y;
             continue;
         }
         if (y >= ye) continue;
@@ -258,6 +263,7 @@ __global__ void __launch_bounds__(CT) k_conv(const unsigned short *__restrict__ 
                 }
             }
     }
+    if (pending >= 0) flush(pending);
 }
 
 // Planar FP32 [img][cin][ny][nx] -> BF16 NHWC with cs stored channels.
