@@ -350,9 +350,10 @@ __global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, 
 // groups of threads (tid < 256, tid >= 256) take the steps alternately, each
 // loading the step after next while the products run, so two steps of loads
 // are in flight.  Wavefront w owns the column blocks w, w + DWW, ... and all
-// row blocks, with the A fragments of a 32-pixel chunk in registers (each
-// B fragment read feeds NBM MFMAs).  Each workgroup writes its partials (one slice per
-// workgroup, summed in a fixed order by k_dw_sum).
+// row blocks; it holds the step's A fragments in registers and reads the
+// two B fragments of a column block before its MFMAs (each B fragment feeds
+// NBM MFMAs).  Each workgroup writes its partials (one slice per workgroup,
+// summed in a fixed order by k_dw_sum).
 constexpr int DWX = 64;                                  // pixels per strip
 constexpr int DWP = DWX + 8;                             // padded LDS row (bf16): 144 bytes
 constexpr int DWW = 8;                                   // wavefronts of a workgroup
