@@ -60,7 +60,9 @@ int sws_forward(sws_net *net, const float *x, float *y, int32_t nimg, int32_t nx
 /* Gradient of the loss (as in sws_train_step) with respect to every
  * parameter, without an update: grad receives the FP32 vector in parameter
  * order (ptr_kind as for the inputs); *loss (may be NULL) the loss.
- * Synchronises. */
+ * Synchronises.  Training calls (sws_grad, sws_train_step, sws_train) take
+ * images of nx * 96 < 2^31 (one row of 48 BF16 channels must fit a 31-bit
+ * byte count); wider images are SW_ERR_ARG before any device work. */
 int sws_grad(sws_net *net, const float *x, const float *target, int32_t nimg, int32_t nx,
              int32_t ny, float *grad, double *loss, int ptr_kind);
 

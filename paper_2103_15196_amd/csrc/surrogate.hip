@@ -1058,6 +1058,15 @@ int sws_forward(sws_net *n, const float *x, float *y, int32_t nimg, int32_t nx, 
 
 namespace {
 
+// The weight-gradient kernel reads each image row through a buffer resource
+// whose size (48 BF16 channels per pixel) is a 31-bit byte count.
+bool train_width_ok(sws_net *n, int32_t nx)
+{
+    if ((long)nx * MAXW * 2 <= 0x7fffffffL) return true;
+    sfail(n, SW_ERR_ARG, "nx too large for training (nx * 96 bytes must be below 2^31)");
+    return false;
+}
+
 // Forward, loss and backward: the gradient lands in n->g; the FP64 loss
 // partials in the scratch (returned through *loss when asked, synchronising).
 int compute_grads(sws_net *n, const float *x, const float *target, int32_t nimg, int32_t nx,
@@ -1066,6 +1075,7 @@ int compute_grads(sws_net *n, const float *x, const float *target, int32_t nimg,
     if (!n || !x || !target || nimg < 1 || nx < 1 || ny < 1) return SW_ERR_ARG;
     if (ptr_kind != SW_PTR_HOST && ptr_kind != SW_PTR_DEVICE)
         return sfail(n, SW_ERR_ARG, "ptr_kind must be SW_PTR_HOST or SW_PTR_DEVICE");
+    if (!train_width_ok(n, nx)) return SW_ERR_ARG;
     if (!n->packed) {
         int rc = pack_all(n);
         if (rc) return rc;
@@ -1123,7 +1133,7 @@ extern "C" {
 int sws_grad(sws_net *n, const float *x, const float *target, int32_t nimg, int32_t nx,
              int32_t ny, float *grad, double *loss, int ptr_kind)
 {
-    if (!grad) return SW_ERR_ARG;
+    if (!grad) return sfail(n, SW_ERR_ARG, "grad is NULL");
     int rc = compute_grads(n, x, target, nimg, nx, ny, loss, ptr_kind);
     if (rc) return rc;
     return copy_out(n, grad, n->g, n->nparam * sizeof(float), ptr_kind);
@@ -1272,6 +1282,7 @@ int sws_train(sws_net *n, const float *x, const float *target, int32_t npairs, i
     if (!n || !x || !target || !cfg || npairs < 1 || nx < 1 || ny < 1) return SW_ERR_ARG;
     if (cfg->steps < 1 || cfg->batch < 1 || cfg->batch > npairs || !(cfg->lr > 0.0f))
         return sfail(n, SW_ERR_ARG, "steps >= 1, 1 <= batch <= npairs and lr > 0 are required");
+    if (!train_width_ok(n, nx)) return SW_ERR_ARG;
     const long npix = (long)nx * ny;
     const size_t xb = (size_t)npairs * 5 * npix * sizeof(float);
     const size_t tb = (size_t)npairs * 4 * npix * sizeof(float);

@@ -347,3 +347,31 @@ def test_gpu_valley_trajectories_windows_and_drops():
         assert "5000, 5001, 5002" in str(e.value)
     finally:
         SG.VALLEY_DT = old
+
+
+def test_gpu_surrogate_training_rejects_rows_beyond_the_kernel_limit():
+    """Training calls refuse images whose row of 48 BF16 channels would
+    exceed a 31-bit byte count (the weight-gradient kernel's buffer
+    resource spans one row) with SW_ERR_ARG and a message, before reading
+    the inputs; the net keeps training at ordinary sizes afterwards."""
+    import ctypes as C
+    from paper_2103_15196_amd import csph
+    net, _, _ = _net(DESIGN, seed=3)
+    buf = np.zeros(16, np.float32)  # never read: the call is refused first
+    nx = 2**31 // 96 + 1
+    rc = csph.lib.sws_grad(net.ctx, buf.ctypes.data, buf.ctypes.data, 1, nx, 1, buf.ctypes.data,
+                           None, csph.SW_PTR_HOST)
+    assert rc == csph.SW_ERR_ARG
+    assert b"nx" in csph.lib.sws_last_error(net.ctx)
+    cfg = csph.sws_train_cfg(1, 1, 1e-3, 0)
+    rep = csph.sws_train_report()
+    rc = csph.lib.sws_train(net.ctx, buf.ctypes.data, buf.ctypes.data, 1, nx, 1, C.byref(cfg),
+                            C.byref(rep), None, csph.SW_PTR_HOST)
+    assert rc == csph.SW_ERR_ARG
+    assert b"nx" in csph.lib.sws_last_error(net.ctx)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((1, 5, 9, 70)).astype(np.float32)
+    t = rng.standard_normal((1, 4, 9, 70)).astype(np.float32)
+    g, loss = net.grad(x, t)
+    assert np.isfinite(loss) and np.all(np.isfinite(g))
+    net.close()
