@@ -1089,9 +1089,10 @@ constexpr int SWAVES = NT / 64;  // strip tiles per workgroup (stacked along y)
 // a workgroup that finds no entry still costs time, so a mostly dry grid does
 // not launch one per tile.
 constexpr int kMaxStageGroups = 8192;
-// Wavefronts per listed tile in a single grid's Lagrangian stage (each marches
-// S / kLagHalves rows): more, shorter wavefronts hide the memory latency of the
-// few tiles a step lists better than they cost in extra halo rows.
+// Wavefronts per listed tile in a single grid's Lagrangian stage when tiles
+// are skipped or the grid is small (each marches S / kLagHalves rows): more,
+// shorter wavefronts hide the latency of the few tiles a step lists better
+// than they cost in extra halo rows.
 constexpr int kLagHalves = 2;
 // Tiles per wavefront in a single grid's Lagrangian stage when every tile of a
 // large grid is listed: one wavefront marches kLagGroup vertically stacked
@@ -1929,16 +1930,19 @@ __device__ __forceinline__ void lagrange_listed(const Inst &I, int par, int w)
     int n = XP == 3 ? I.ntx * ((I.nty + kLagGroup - 1) / kLagGroup) : I.ntx * I.nty;
     int seg = 0, start = 0;
     const int G4 = XP == 2 ? (int)gridDim.x * SWAVES : 0;
-    // XP = 1: LH wavefronts per listed tile, each on S / LH of its rows
-    constexpr int LH = XP == 1 ? kLagHalves : 1;
+    // XP = 1, 2: LH wavefronts per listed tile, each on S / LH of its rows
+    constexpr int LH = XP == 1 || XP == 2 ? kLagHalves : 1;
     if (XP && I.hgs) n = list_locate(I.cnt_l, cl0, nb, 0, seg, start, nullptr);
     if (XP == 1 || XP == 3)
         w = __builtin_amdgcn_readfirstlane(xcd_entry(w / SWAVES, w % SWAVES, LH * n));
     const int part = w % LH;
-    w /= LH;
+    if (XP != 2) w /= LH;
     if (XP != 2 && I.hgs) n = list_locate(I.cnt_l, cl0, nb, w, seg, start, nullptr);
-    // XP = 2: workgroups past those the first (fullest) pass needs have no entry
-    const bool idle = XP == 2 ? w / SWAVES >= (min(G4, n) + SWAVES - 1) / SWAVES : w >= n;
+    // XP = 2: LH wavefronts per entry when the list is short enough for one
+    // pass of them (the launch's idle wavefronts take the halves), else one;
+    // workgroups past those the first (fullest) pass needs have no entry
+    const int lh = XP == 2 && LH * n <= G4 ? LH : 1;
+    const bool idle = XP == 2 ? w / SWAVES >= (min(G4, lh * n) + SWAVES - 1) / SWAVES : w >= n;
     if (idle && !publisher) return;
     // the Eq. 7 step from the segment maxima (K3 proper)
     unsigned a = v.x, b = v.y, c = v.z, bad = v.w;
@@ -1968,6 +1972,16 @@ __device__ __forceinline__ void lagrange_listed(const Inst &I, int par, int w)
             if constexpr (F2) lagrange_strip2<S / LH, CS>(I, par, t % I.ntx, (t / I.ntx) * LH + part, dt);
             else lagrange_strip<S / LH, CS>(I, par, t % I.ntx, (t / I.ntx) * LH + part, dt);
         }
+        return;
+    }
+    if (lh > 1) {  // one pass: wavefront w takes part w % LH of entry w / LH
+        const int wi = __builtin_amdgcn_readfirstlane(xcd_entry(w / SWAVES, w % SWAVES, LH * n));
+        if (wi >= LH * n) return;
+        const int we = wi / LH, pt = wi % LH;
+        if (I.hgs) list_locate(I.cnt_l, cl0, nb, we, seg, start, nullptr);
+        const int t = __builtin_amdgcn_readfirstlane(I.hgs ? I.lag[seg * I.chunk + (we - start)] : we);
+        if constexpr (F2) lagrange_strip2<S / LH, CS>(I, par, t % I.ntx, (t / I.ntx) * LH + pt, dt);
+        else lagrange_strip<S / LH, CS>(I, par, t % I.ntx, (t / I.ntx) * LH + pt, dt);
         return;
     }
     for (int base = 0; base < n; base += G4) {

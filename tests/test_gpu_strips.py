@@ -96,17 +96,25 @@ def test_gpu_strips_tiny_grids():
 
 def test_gpu_strips_long_lists_take_several_passes():
     """8192 x 2048 cells: 58 x 8 strips make 36352 tiles.  With dry tiles
-    skipped that is more than the stage grid's 8192 workgroups of 4
-    wavefronts hold, so the Lagrangian and Euler kernels take their lists in
-    two passes; with every tile listed (no skipping) one grid covers them all;
-    58 x 32 strips (4544 tiles) take one pass either way.  All give the bits
-    of the 64 x 8 tiles."""
+    skipped and every tile wet that is more than the stage grid's 8192
+    workgroups of 4 wavefronts hold, so the Lagrangian and Euler kernels take
+    their lists in two passes; a shorter list (the dam break's own dry
+    regions, or one small wet block) fits one pass, and the Lagrangian stage
+    then puts two wavefronts on each listed tile; with every tile listed (no
+    skipping) one grid covers them all; 58 x 32 strips (4544 tiles) take one
+    pass either way.  All give the bits of the 64 x 8 tiles."""
     from paper_2103_15196_amd import csph
     w = W.dam_break_fractal(n=8192, ny=2048, dx=2.0, seed=5, relief=10.0, depth=6.0).as_float32()
     wet = copy.deepcopy(w)
     wet.H = (w.H + 0.5).astype(np.float32).astype(np.float64)
-    for name, case, flags in (("all tiles", w, 0), ("all wet", wet, csph.SW_FLAG_HGS)):
-        ref = run_gpu(case, 30, flags=flags)
+    block = copy.deepcopy(w)
+    block.H = np.zeros_like(w.H)
+    block.H[1000:1100, 4000:4200] = w.H[1000:1100, 4000:4200] + 1.0
+    block.H = block.H.astype(np.float32).astype(np.float64)
+    for name, case, flags in (("all tiles", w, 0), ("all wet", wet, csph.SW_FLAG_HGS),
+                              ("dry tiles skipped", w, csph.SW_FLAG_HGS),
+                              ("one wet block", block, csph.SW_FLAG_HGS)):
+        ref = run_gpu(case, 30, flags=flags, shape=(64, 8))
         for shape in ((58, 8), (58, 32)):
             say(f"strip {shape}, {name}, 8192x2048, 30 steps")
             _same(run_gpu(case, 30, flags=flags, shape=shape), ref, f"{name} {shape}")
