@@ -361,6 +361,9 @@ constexpr int DWT = 64 * DWW;
 constexpr int DWJ = ((9 * MAXW + 16) / 16 + DWW - 1) / DWW;  // column blocks per wavefront (+ bias)
 constexpr int DW_ONES = 9 * MAXW;                        // first of the three rows of ones
 constexpr unsigned DW_OOB = 0x80000000u;                 // an offset beyond every resource
+// fourth word of a raw buffer resource: data format 32 bits (4 in bits 15..18),
+// stride 0, so an offset at or past the resource's byte count reads zero
+constexpr int DW_RSRC_W3 = 4 << 15;
 constexpr int DW_ZT = 96;                                // first dz task within a loader group
 
 // BF16 pairs (low half of a with low half of b), (high half of a with high
@@ -454,7 +457,7 @@ __global__ void __launch_bounds__(DWT) __attribute__((amdgpu_waves_per_eu(4))) k
             const bool rowok = (unsigned)gy < (unsigned)ny;
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 (void *)(x + ((long)st.img * ny + (rowok ? gy : 0)) * nx * cs), (short)0,
-                rowok ? nx * cs * 2 : 0, 0x00020000);
+                rowok ? nx * cs * 2 : 0, DW_RSRC_W3);
             const int p0 = st.x0 + 8 * tg - 1;
 #pragma unroll
             for (int e = 0; e < 10; ++e) {
@@ -466,7 +469,7 @@ __global__ void __launch_bounds__(DWT) __attribute__((amdgpu_waves_per_eu(4))) k
         } else if (tz && st.s >= 2) {  // pixels x0 + 8 g .. x0 + 8 g + 7 of dz row ya + s - 2
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 (void *)(dz + ((long)st.img * ny + st.ya + st.s - 2) * nx * dcs), (short)0, nx * dcs * 2,
-                0x00020000);
+                DW_RSRC_W3);
             const int p0 = st.x0 + 8 * tg;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
