@@ -365,6 +365,9 @@ constexpr unsigned DW_OOB = 0x80000000u;                 // an offset beyond eve
 // stride 0, so an offset at or past the resource's byte count reads zero
 constexpr int DW_RSRC_W3 = 4 << 15;
 constexpr int DW_ZT = 96;                                // first dz task within a loader group
+static_assert(DWT == 2 * 256, "two loader groups of 256 threads");
+static_assert(8 * (MAXW / 4) <= DW_ZT && DW_ZT + 8 * (MAXW / 4) <= 256,
+              "a group holds the input tasks of 48 channels, then the dz tasks of 48 channels");
 
 // BF16 pairs (low half of a with low half of b), (high half of a with high
 // of b): one byte permute each (selector bytes 0-3 pick bytes of a, 4-7 bytes of b)
