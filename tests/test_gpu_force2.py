@@ -104,6 +104,23 @@ def test_gpu_force2_one_grid_and_passes():
             assert np.array_equal(a, b), (shape, hgs)
 
 
+def test_gpu_force2_short_list_two_wavefronts_per_tile():
+    """The same grid dry but for one wet block: with skipping the list fits
+    one pass and the Lagrangian stage puts two wavefronts on each listed
+    tile (each marching half its rows); without skipping one wavefront
+    marches four stacked tiles.  Same bits."""
+    w = W.dam_break_fractal(n=8192, ny=2048, dx=2.0, seed=5, relief=10.0, depth=6.0).as_float32()
+    H = np.zeros_like(w.H)
+    H[1000:1100, 4000:4200] = w.H[1000:1100, 4000:4200] + 1.0
+    w.H = H.astype(np.float32).astype(np.float64)
+    say("case force2: 8192x2048 one wet block 30 steps, skipping on and off")
+    ref, rs = run_gpu(w, 30, flags=_f2(False))
+    f, fs = run_gpu(w, 30, flags=_f2(True))
+    for a, b in zip(f, ref):
+        assert np.array_equal(a, b)
+    assert fs["t"] == rs["t"] and fs["water_volume"] == rs["water_volume"]
+
+
 def test_gpu_force2_batch_and_refusals():
     """A batch of two members with the flag: each equals its run alone; a
     batch mixing force orders, an LDS tile shape and the unfused sequence are
