@@ -952,10 +952,14 @@ int sws_create(const int32_t *channels, int32_t nlayers, void *hip_stream, sws_n
     long off = 0;
     for (int l = 0; l < nlayers; ++l) {
         n->fwd.push_back(make_geo(n->ch[l], n->ch[l + 1]));
-        // the transposed convolution reads gradient buffers of MAXW channels per pixel
+        // the transposed convolution reads gradient buffers of MAXW channels per
+        // pixel, except the loss gradient of the last layer's outputs, which
+        // keeps their stored width (8 channels: 3 reduction chunks, not 14)
         Geo t = make_geo(n->ch[l + 1], n->ch[l]);
-        t.cs = MAXW;
-        t.kc = (9 * MAXW + 31) / 32;
+        if (l + 1 < nlayers) {
+            t.cs = MAXW;
+            t.kc = (9 * MAXW + 31) / 32;
+        }
         n->bwd.push_back(t);
         n->woff.push_back(off);
         off += (long)n->ch[l + 1] * n->ch[l] * 9;
@@ -1099,10 +1103,11 @@ int compute_grads(sws_net *n, const float *x, const float *target, int32_t nimg,
     hipLaunchKernelGGL(k_to_nhwc, dim3(grid_for(npix)), dim3(NT), 0, n->stream, xd, 5, CIN0,
                        (long)nx * ny, nimg, s.act[0]);
     if ((rc = forward_into(n, s, nimg, nx, ny))) return rc;
-    // loss and dL/dy (BF16, stored channels of the last layer's output = 16-block)
+    // loss and dL/dy (BF16, the stored width of the last layer's outputs)
     const int L = n->L;
-    const int cs_out = MAXW;  // gradient buffers always hold MAXW channels per pixel
-    hipLaunchKernelGGL(k_mse, dim3(RED_GRID), dim3(NT), 0, n->stream, s.out, td, 4, cs_out,
+    const int cs_out = MAXW;  // the other gradient buffers hold MAXW channels per pixel
+    const int cs_last = stored(n->ch[L]);
+    hipLaunchKernelGGL(k_mse, dim3(RED_GRID), dim3(NT), 0, n->stream, s.out, td, 4, cs_last,
                        (long)nx * ny, nimg, 1.0 / ((double)npix * 4), s.ga, s.red);
     unsigned short *gcur = s.ga, *gnext = s.gb;
     for (int l = L - 1; l >= 0; --l) {
@@ -1110,7 +1115,7 @@ int compute_grads(sws_net *n, const float *x, const float *target, int32_t nimg,
         const int cin = n->ch[l], cout = n->ch[l + 1];
         auto dw = cout > 32 ? k_dw<3> : cout > 16 ? k_dw<2> : k_dw<1>;
         hipLaunchKernelGGL(dw, dim3(DW_GRID), dim3(DWT), 0, n->stream, s.act[l], stored(cin), cin,
-                           gcur, cs_out, cout, nimg, nx, ny, s.dwpart);
+                           gcur, l == L - 1 ? cs_last : cs_out, cout, nimg, nx, ny, s.dwpart);
         const int len = cout * cin * 9 + cout;
         hipLaunchKernelGGL(k_dw_sum, dim3((len + DWS_COLS - 1) / DWS_COLS), dim3(256), 0, n->stream,
                            s.dwpart, DW_GRID, len, n->g + n->woff[l]);
