@@ -56,9 +56,22 @@ struct Geo {
 // per-lane fragment order [nb][kc][lane][8].  flip: the weights of the
 // transposed convolution (input gradient), Wf[n][c][ky][kx] = W[c][n][2-ky][2-kx].
 // ---------------------------------------------------------------------------
-__global__ void k_pack(const float *__restrict__ W, Geo g, int flip, int wcin,
-                       unsigned short *__restrict__ out)
+// One packing job: a layer's weights into the forward or transposed fragment
+// order; the launch takes up to kPackJobs of them, one per row of its grid.
+struct PackJob {
+    const float *W;
+    unsigned short *out;
+    Geo g;
+    int flip, wcin;
+};
+constexpr int kPackJobs = 16;
+struct PackTable {
+    PackJob j[kPackJobs];
+};
+__global__ void k_pack(PackTable t)
 {
+    const PackJob &J = t.j[blockIdx.y];
+    const Geo g = J.g;
     const int total = g.nb * g.kc * 64 * 8;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
         const int j = q & 7, lane = (q >> 3) & 63, f = q >> 9;
@@ -69,10 +82,10 @@ __global__ void k_pack(const float *__restrict__ W, Geo g, int flip, int wcin,
         if (tap < 9 && c < g.cin && n < g.cout) {
             const int ky = tap / 3, kx = tap % 3;
             // W is [wcout][wcin][3][3]
-            v = flip ? W[((c * wcin + n) * 3 + (2 - ky)) * 3 + (2 - kx)]
-                     : W[((n * wcin + c) * 3 + ky) * 3 + kx];
+            v = J.flip ? J.W[((c * J.wcin + n) * 3 + (2 - ky)) * 3 + (2 - kx)]
+                       : J.W[((n * J.wcin + c) * 3 + ky) * 3 + kx];
         }
-        out[q] = bf16_bits(v);
+        J.out[q] = bf16_bits(v);
     }
 }
 
@@ -812,15 +825,21 @@ int conv(sws_net *n, const unsigned short *in, const Geo &g, const unsigned shor
 
 int pack_all(sws_net *n)
 {
+    std::vector<PackJob> jobs;
     for (int l = 0; l < n->L; ++l) {
-        const Geo &g = n->fwd[l];
-        hipLaunchKernelGGL(k_pack, dim3(grid_for((long)packed_len(g))), dim3(NT), 0, n->stream,
-                           n->p + n->woff[l], g, 0, n->ch[l], n->wpk[l]);
-        if (l > 0) {  // the input gradient of layer 0 is never needed
-            const Geo &t = n->bwd[l];
-            hipLaunchKernelGGL(k_pack, dim3(grid_for((long)packed_len(t))), dim3(NT), 0,
-                               n->stream, n->p + n->woff[l], t, 1, n->ch[l], n->wpk_t[l]);
+        jobs.push_back(PackJob{n->p + n->woff[l], n->wpk[l], n->fwd[l], 0, n->ch[l]});
+        if (l > 0)  // the input gradient of layer 0 is never needed
+            jobs.push_back(PackJob{n->p + n->woff[l], n->wpk_t[l], n->bwd[l], 1, n->ch[l]});
+    }
+    for (size_t j0 = 0; j0 < jobs.size(); j0 += kPackJobs) {
+        PackTable t{};
+        const int nj = (int)std::min<size_t>(kPackJobs, jobs.size() - j0);
+        long most = 1;
+        for (int j = 0; j < nj; ++j) {
+            t.j[j] = jobs[j0 + j];
+            most = std::max<long>(most, (long)packed_len(jobs[j0 + j].g));
         }
+        hipLaunchKernelGGL(k_pack, dim3(grid_for(most), nj), dim3(NT), 0, n->stream, t);
     }
     SHIP(n, hipGetLastError());
     n->packed = true;
