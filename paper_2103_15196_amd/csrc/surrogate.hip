@@ -1111,14 +1111,21 @@ int compute_grads(sws_net *n, const float *x, const float *target, int32_t nimg,
     }
     const long npix = (long)nimg * nx * ny;
     const size_t xin = (size_t)npix * 5 * sizeof(float), tin = (size_t)npix * 4 * sizeof(float);
-    const size_t need = layout(n, npix, nullptr).bytes + xin + tin;
+    // device inputs are read where they are; host inputs are staged in the scratch
+    const bool host = ptr_kind == SW_PTR_HOST;
+    const size_t need = layout(n, npix, nullptr).bytes + (host ? xin + tin : 0);
     int rc = ensure_scratch(n, need);
     if (rc) return rc;
     Scratch s = layout(n, npix, (char *)n->scratch);
-    float *xd = (float *)((char *)n->scratch + s.bytes);
-    float *td = (float *)((char *)xd + xin);
-    if ((rc = copy_in(n, xd, x, xin, ptr_kind))) return rc;
-    if ((rc = copy_in(n, td, target, tin, ptr_kind))) return rc;
+    const float *xd = x, *td = target;
+    if (host) {
+        float *xs = (float *)((char *)n->scratch + s.bytes);
+        float *ts = (float *)((char *)xs + xin);
+        if ((rc = copy_in(n, xs, x, xin, ptr_kind))) return rc;
+        if ((rc = copy_in(n, ts, target, tin, ptr_kind))) return rc;
+        xd = xs;
+        td = ts;
+    }
     hipLaunchKernelGGL(k_to_nhwc, dim3(grid_for(npix)), dim3(NT), 0, n->stream, xd, 5, CIN0,
                        (long)nx * ny, nimg, s.act[0]);
     if ((rc = forward_into(n, s, nimg, nx, ny))) return rc;
